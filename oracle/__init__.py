@@ -1,0 +1,28 @@
+"""Plain CPU FP64 oracle for time-stepper Arnoldi stability analysis.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and its
+Python binding) may import, call, link or execute anything in this package.  It
+is used by ``tests/``, by ``__graft_entry__.smoke()`` and by the ``cpu_baseline``
+leg of ``bench.py``.  It shares no code, table or constant generator with the
+HIP path; both sides only receive the same seeded inputs from ``workloads``.
+
+Modules (each function cites the passage of Loiseau, Bucci, Cherubini & Robinet,
+"Time-stepping and Krylov methods for large-scale instability problems",
+arXiv:1804.03859, that it follows):
+
+* ``cgle``        -- linear complex Ginzburg-Landau operator (Sec. 2.3.2, eq.
+                     "ginzburg-landau equation"), 2nd-order finite differences,
+                     Crank-Nicolson propagator.
+* ``kolmogorov``  -- linearized 2D Navier-Stokes about a base flow (Sec. 3,
+                     eq. "linearized Navier-Stokes equations") in vorticity form,
+                     pseudo-spectral with 2/3 dealiasing, integrating-factor RK4.
+* ``arnoldi``     -- m-step Arnoldi factorisation (Sec. 3.2.1, Algorithm 1) with
+                     classical Gram-Schmidt applied twice, Ritz pairs, the Ritz
+                     residual estimate (Sec. 3.2.2, eq. "Krylov convergence"),
+                     wanted set and stop rule, lambda = log(mu)/T (Sec. 3.2).
+* ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
+                     definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
+* ``mlp``         -- FP64 forward/backward of the start-vector MLP.
+
+Parity status of every function is stated in its module header.
+"""

@@ -1,0 +1,83 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds only workload definitions (sizes, physical parameters) and
+seeded random draws.  It contains none of the method's arithmetic; both the HIP
+path and the CPU oracle receive the arrays it produces.
+
+Every random array comes from numpy's PCG64 ``default_rng(seed)``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ---- workload definitions ---------------------------------------------------
+# Linear complex Ginzburg-Landau, 1D, x in [-50, 50], 256 interior FD nodes,
+# Crank-Nicolson dt = 0.01 over T = 1, Arnoldi m = 64, k = 6.
+CGLE = dict(n=256, half_width=50.0, U=2.0, c_u=0.2, c_d=-1.0, mu0=0.41,
+            mu2=-0.01, dt=0.01, T=1.0, m=64, k=6, tol=1e-8)
+
+# Linearized Kolmogorov flow U = (sin 4y, 0), box [0, 2pi/alpha) x [0, 2pi),
+# Re = 20, alpha = 0.5, integrating-factor RK4 dt = 0.005 over T = 1.
+KOLMO_128_FP64 = dict(N=128, alpha=0.5, Re=20.0, dt=0.005, T=1.0, n_forcing=4,
+                      m=64, k=6, tol=1e-8, precision="fp64")
+KOLMO_512_FP32 = dict(N=512, alpha=0.5, Re=20.0, dt=0.005, T=1.0, n_forcing=4,
+                      m=96, k=6, tol=1e-8, precision="fp32")
+
+BATCH_ALPHAS = (0.25, 0.5, 0.75, 1.0)
+BATCH_SIZES = (128, 256, 384)
+
+
+def batch_sweep(count=64, seed=0):
+    """Neutral-curve sweep instances: Re ~ U[5, 40] (seeded), alpha cycles over
+    BATCH_ALPHAS, grid N cycles over BATCH_SIZES in blocks of four."""
+    rng = np.random.default_rng(seed)
+    Re = rng.uniform(5.0, 40.0, size=count)
+    out = []
+    for i in range(count):
+        out.append(dict(N=BATCH_SIZES[(i // 4) % 3], alpha=BATCH_ALPHAS[i % 4],
+                        Re=float(Re[i]), dt=0.005, T=1.0, n_forcing=4,
+                        m=64, k=4, tol=1e-8, precision="fp32"))
+    return out
+
+
+# ---- seeded draws -------------------------------------------------------------
+def normal_real(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def normal_complex(n, seed):
+    """Real and imaginary parts iid N(0, 1)."""
+    z = np.random.default_rng(seed).standard_normal((2, n))
+    return z[0] + 1j * z[1]
+
+
+def cgle_start(n=256, seed=0):
+    return normal_complex(n, seed)
+
+
+def kolmo_start_physical(N, seed=0):
+    """iid N(0,1) physical vorticity field, indexed [y, x]."""
+    return normal_real((N, N), seed)
+
+
+def random_matrix(n, seed, complex_=False):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    if complex_:
+        A = A + 1j * rng.standard_normal((n, n))
+    return A
+
+
+def random_base_modes(max_j=2, seed=0, amplitude=0.3):
+    """Random band-limited base streamfunction: coefficients for (jx, jy) with
+    |jx|, |jy| <= max_j, conjugate-symmetric so the field is real, no mean."""
+    rng = np.random.default_rng(seed)
+    modes = {}
+    for jx in range(0, max_j + 1):
+        for jy in range(-max_j, max_j + 1):
+            if jx == 0 and jy <= 0:
+                continue
+            c = amplitude * (rng.standard_normal() + 1j * rng.standard_normal())
+            modes[(jx, jy)] = c
+            modes[(-jx, -jy)] = np.conj(c)
+    return modes

@@ -1,0 +1,150 @@
+"""Benchmark: time-stepper Arnoldi on the linearized Kolmogorov flow, 128 x 128,
+FP64 (Re = 20, alpha = 0.5, IF-RK4 dt = 0.005, T = 1, m = 64, k = 6,
+tol = 1e-8), one MI355X.
+
+A step is one pass of the whole path on one start vector: projection of the
+seeded N(0,1) physical field on the dealiased state space, then Arnoldi with a
+matvec (200 IF-RK4 steps) per Krylov vector, CGS2, device Hessenberg QR and the
+stop test after every matvec, and the Ritz values/vectors at the end.  The
+physical start field is resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  Other output goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak
+
+
+def colstep_flops(N, nsteps):
+    """Algorithmic flops of one matvec of the column stepper: per dealiased
+    column kx >= 1 and RK stage, one inverse and one forward complex FFT of length
+    N (5 N log2 N each), the product with the base profile (2 N) and the
+    spectral bookkeeping (12 flops per kept mode)."""
+    M = (N - 1) // 3
+    NM = 2 * M + 1
+    per_stage = 2 * 5 * N * math.log2(N) + 2 * N + 12 * NM
+    return M * 4 * nsteps * per_stage
+
+
+def cpu_baseline(seconds=12.0):
+    """The CPU oracle (NumPy FP64, single thread) on a bounded sample of the same
+    workload: as many full matvecs (200 IF-RK4 steps each) of the 128^2 operator
+    as fit in about `seconds`."""
+    import numpy as np  # noqa: F401
+
+    import workloads as W
+    from oracle.kolmogorov import Kolmogorov
+    c = W.KOLMO_128_FP64
+    N = c["N"]
+    op = Kolmogorov.kolmogorov(N, c["alpha"], c["Re"], c["dt"], c["T"], c["n_forcing"])
+    w = op.project(W.kolmo_start_physical(N, 0))
+    t0 = time.perf_counter()
+    count = 0
+    while True:
+        w = op.apply(w)
+        w /= np.linalg.norm(w)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    tsgp = count * op.nsteps * N * N / el
+    return {"value": tsgp, "unit": "time-steps*gridpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{count} oracle matvecs (200 IF-RK4 steps each) of the 128x128 FP64 operator, "
+                      f"{el:.1f} s, NumPy/pocketfft single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1804_03859_amd.tsk as tsk
+    import workloads as W
+
+    if not os.path.exists(tsk.LIB_PATH):
+        from paper_1804_03859_amd import build
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    c = W.KOLMO_128_FP64
+    N, m, k, tol = c["N"], c["m"], c["k"], c["tol"]
+    nsteps = int(round(c["T"] / c["dt"]))
+    op = tsk.create_kolmo2d(N, tsk.TSK_FP64)
+    tsk.set_params_kolmo(op, c["Re"], c["alpha"], c["dt"], c["T"])
+    tsk.set_base_kolmogorov(op, c["n_forcing"])
+    phys = torch.from_numpy(W.kolmo_start_physical(N, 0)).cuda().reshape(-1)
+    x = op.new_state()
+
+    def step():
+        tsk.from_physical(op, phys, x)
+        return tsk.arnoldi(op, m, k, tol, v0=x, want_vectors=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el * 1e3 / args.steps
+    r = results[-1]
+    nmv = r["n_matvec"]
+    tsgp_step = nmv * nsteps * N * N
+    value = tsgp_step / (ms_per_step / 1e3)
+    ms_apply = sum(q["ms_apply"] for q in results) / args.steps
+    launch_ms = ms_apply / nmv
+    flops = colstep_flops(N, nsteps)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    out = {
+        "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
+        "value": value,
+        "unit": "time-steps*gridpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "linearized Kolmogorov flow 128x128 FP64, Re=20, alpha=0.5, IF-RK4 dt=0.005 T=1, "
+                               "Arnoldi m=64 k=6 tol=1e-8, seeded N(0,1) start",
+                   "n_matvec": nmv, "status": r["status"],
+                   "wall_time_to_6_pairs_s": ms_per_step / 1e3,
+                   "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
+                   "lambda": [round(float(v.real), 10) for v in r["lam"]],
+                   "max_residual": float(np.max(r["res"]))},
+        "roofline": {"bound": "alu", "kernel": "k_colstep<double,128,true>", "achieved": achieved,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

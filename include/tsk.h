@@ -1,0 +1,185 @@
+/*
+ * tsk.h -- C ABI of libtsk: time-stepper Arnoldi for linear stability analysis on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Loiseau, Bucci, Cherubini & Robinet, "Time-stepping and Krylov methods
+ * for large-scale instability problems", arXiv:1804.03859.
+ *   - The stability of a fixed point is read from the eigenvalues of the
+ *     exponential propagator M = exp(A T) (Sec. 2.2; Sec. 3.2, eq. "discrete-time
+ *     linear system"); lambda = log(mu) / T.
+ *   - M is never formed: one matvec M x is one time integration of the
+ *     linearized equations over T (Sec. 3, "time-stepper" approach).
+ *   - Ritz pairs come from the m-step Arnoldi factorisation (Sec. 3.2.1,
+ *     eq. "m-step Arnoldi", Algorithm 1) and are accepted by the residual
+ *     |beta e_m^T y| (Sec. 3.2.2, eq. "Krylov convergence").
+ *
+ * Conventions for every entry point
+ *   - No exception crosses this boundary.  A negative status means nothing was
+ *     written to caller buffers; tsk_last_error() then describes the failure
+ *     (thread-local string, valid until the next call on the same thread).
+ *   - "dev" pointers are HIP device pointers owned by the caller; "host" pointers
+ *     are ordinary host memory owned by the caller.  The library never frees a
+ *     caller pointer.  The operator handle and its workspace (Krylov basis,
+ *     Hessenberg matrix, tables) are owned by the library until tsk_destroy().
+ *   - Every operator is bound to the hipStream_t given at creation (NULL = the
+ *     default stream).  tsk_apply, tsk_from_physical and tsk_to_physical are
+ *     asynchronous on that stream.  tsk_arnoldi synchronises it before it writes
+ *     host outputs.
+ *   - A handle must not be used by two host threads at once.
+ */
+#ifndef TSK_H
+#define TSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsk_op_s* tsk_op;
+
+typedef enum {
+    TSK_OK = 0,              /* k wanted Ritz pairs converged                      */
+    TSK_NOT_CONVERGED = 1,   /* m matvecs done; outputs hold the current estimates */
+    TSK_BREAKDOWN = 2,       /* invariant subspace found (beta ~ 0): pairs exact   */
+    TSK_EINVAL = -1,         /* invalid argument or unsupported size               */
+    TSK_ENOMEM = -2,         /* device allocation failed                           */
+    TSK_EHIP = -3,           /* HIP runtime error                                  */
+    TSK_ENONFINITE = -4,     /* NaN/Inf met (start vector, matvec output, beta)    */
+    TSK_ESTATE = -5,         /* call out of order (e.g. parameters not set)        */
+    TSK_EEIG = -6            /* Hessenberg QR did not converge                     */
+} tsk_status;
+
+typedef enum {
+    TSK_FP64 = 0,            /* state, transforms and time stepping in FP64        */
+    TSK_FP32 = 1             /* state in FP32; Gram-Schmidt sums, norms, H in FP64 */
+} tsk_precision;
+
+typedef struct {
+    int n_matvec;            /* matvecs performed (= Arnoldi steps, Table 1 counts this way) */
+    int n_ritz;              /* Ritz pairs written (k, fewer only at an early breakdown)      */
+    int n_converged;         /* of those, residual <= tol                                    */
+    int status;              /* same value as returned                                       */
+    double beta;             /* last ||f_j||                                                 */
+    double ms_total;         /* wall time of the call, host clock                            */
+    double ms_apply;         /* device time of the matvecs, HIP events on the op's stream     */
+} tsk_arnoldi_info;
+
+/* ---------------------------------------------------------------------------
+ * Linear complex Ginzburg-Landau operator (Sec. 2.3.2, eq. "ginzburg-landau
+ * equation"): du/dt = -nu u_x + gamma u_xx + mu(x) u, mu(x) = mu0 - c_u^2 +
+ * mu2 x^2 / 2, read with nu = U + 2 i c_u and gamma = 1 + i c_d.
+ * Discretised on n interior nodes of [-half_width, half_width] (dx =
+ * 2 half_width/(n+1), Dirichlet ends) by second-order central differences;
+ * time integration by Crank-Nicolson.  State: n complex128 values (interleaved
+ * re, im), node-major.  2 <= n <= 1024.
+ * ------------------------------------------------------------------------- */
+tsk_status tsk_create_cgle1d(tsk_op* op, int n, double half_width, void* hip_stream);
+
+/* dt > 0, T/dt an integer within 1e-9 relative. */
+tsk_status tsk_set_params_cgle(tsk_op op, double U, double c_u, double c_d,
+                               double mu0, double mu2, double dt, double T);
+
+/* ---------------------------------------------------------------------------
+ * Linearized 2D Navier-Stokes about a base flow (Sec. 3, eq. "linearized
+ * Navier-Stokes equations"), vorticity form, doubly periodic box
+ * [0, 2 pi/alpha) x [0, 2 pi), N x N pseudo-spectral grid with the 2/3 rule
+ * (|jx|, |jy| < N/3 kept, mean mode removed), Lawson integrating-factor RK4.
+ * N in {16, 32, 48, 64, 96, 128, 192, 256, 384, 512}.
+ *
+ * State vector ("packed spectral"): the independent real unknowns of the
+ * dealiased zero-mean vorticity field, n = 4 M (M + 1) reals, M = (N-1)/3:
+ *   [ kx = 0 : jy = 1..M ]  then  [ kx = j : jy = -M..M ] for j = 1..M,
+ * each entry (re, im) of sqrt(2) * rfft2(omega)[jy, kx] / N^2.  With this
+ * scaling the Euclidean norm of the state equals the RMS of the physical
+ * field, so residuals are independent of N.  Element type: double (TSK_FP64)
+ * or float (TSK_FP32).
+ * Physical fields: N x N, row-major [y][x], same element type as the state.
+ * ------------------------------------------------------------------------- */
+tsk_status tsk_create_kolmo2d(tsk_op* op, int N, tsk_precision precision, void* hip_stream);
+
+/* Re > 0, alpha > 0, dt > 0, T/dt an integer within 1e-9 relative. */
+tsk_status tsk_set_params_kolmo(tsk_op op, double Re, double alpha, double dt, double T);
+
+/* Parallel base flow U = (U(y), 0): host arrays of N samples at y_l = 2 pi l/N
+ * of U and of dOmega/dy = -U''(y).  Copied; the caller keeps ownership. */
+tsk_status tsk_set_base_parallel(tsk_op op, const double* U_y, const double* dOmega_dy);
+
+/* Kolmogorov base flow U = (sin(n y), 0), i.e. dOmega/dy = n^2 sin(n y). */
+tsk_status tsk_set_base_kolmogorov(tsk_op op, int n_forcing);
+
+/* General 2D base flow: host arrays of N*N samples ([y][x]) of U, V and of the
+ * base-vorticity gradient dOmega/dx, dOmega/dy.  Switches the operator to the
+ * full two-dimensional transform pipeline. */
+tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
+                             const double* dOmega_dx, const double* dOmega_dy);
+
+/* ---------------------------------------------------------------------------
+ * Common to all operators.
+ * ------------------------------------------------------------------------- */
+
+/* n_scalars: state length in scalars (complex count if *is_complex);
+ * elem_bytes: bytes per real component (8 or 4). */
+tsk_status tsk_state_dim(tsk_op op, int64_t* n_scalars, int* is_complex, int* elem_bytes);
+
+/* Physical field (dev) -> state (dev): orthogonal projection on the state
+ * space (for the Navier-Stokes operator: dealias and drop the mean).  For the
+ * Ginzburg-Landau operator the two representations coincide (a copy). */
+tsk_status tsk_from_physical(tsk_op op, const void* phys_dev, void* state_dev);
+
+/* State (dev) -> physical field (dev). */
+tsk_status tsk_to_physical(tsk_op op, const void* state_dev, void* phys_dev);
+
+/* One matvec y = M x = (time integration over T) x.  x and y are state vectors
+ * in device memory; they may not alias. */
+tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev);
+
+/* Arnoldi with classical Gram-Schmidt applied twice (Sec. 3.2.1, Algorithm 1),
+ * Ritz pairs from a device-side Hessenberg QR after every matvec, stop when the
+ * k wanted pairs have |beta e_m^T y| <= tol (Sec. 3.2.2), or after m matvecs,
+ * or at a happy breakdown.
+ *   m:        maximum Krylov dimension, 1 <= k <= m <= 96, m <= state length.
+ *   tol:      residual tolerance (absolute, unit-norm Ritz vectors); 0 = run m.
+ *   v0_dev:   start vector (state, dev) or NULL: then an iid N(0,1) field drawn
+ *             from `seed` (splitmix64 + Box-Muller, counter = element index of
+ *             the physical field) is projected on the state space.
+ *   mu_ri:    host, 2k doubles: Ritz values of M (re, im), wanted order.
+ *   lambda_ri:host, 2k doubles: log(mu)/T, principal branch.
+ *   resid:    host, k doubles: residual estimates.
+ *   ritz_dev: dev or NULL: k Ritz vectors V y, each n complex128 (interleaved),
+ *             vector-major.
+ *   info:     host or NULL.
+ * Returns TSK_OK, TSK_NOT_CONVERGED or TSK_BREAKDOWN with outputs written, or a
+ * negative status with nothing written. */
+tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed,
+                       double* mu_ri, double* lambda_ri, double* resid, void* ritz_dev,
+                       tsk_arnoldi_info* info);
+
+/* Last Arnoldi run, for inspection: H ((m+1) x m complex128, column-major,
+ * leading dimension m+1, zero beyond the steps taken) copied to host, and the
+ * basis pointer (device, (steps+1) vectors of the state type, vector-major,
+ * stride *ld elements).  Valid until the next tsk_arnoldi or tsk_destroy. */
+tsk_status tsk_last_hessenberg(tsk_op op, double* H_host, int* m_out, int* steps_out);
+tsk_status tsk_last_basis(tsk_op op, const void** V_dev, int64_t* ld);
+
+/* Device Hessenberg eigensolver on its own (the one tsk_arnoldi uses):
+ * H_dev: p x p complex128 upper Hessenberg, column-major with leading
+ * dimension ldh (>= p); beta: residual scale.  Outputs (dev): mu_dev (p
+ * complex128), Y_dev (p x p complex128, column-major, unit-norm columns),
+ * res_dev (p doubles, beta |Y[p-1, i]|).  1 <= p <= 96.  Synchronous on
+ * hip_stream.  Returns TSK_EEIG if the QR iteration failed to converge. */
+tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta,
+                               void* mu_dev, void* Y_dev, void* res_dev, void* hip_stream);
+
+/* iid N(0,1) draws (device, FP64): count values of the splitmix64 +
+ * Box-Muller stream of `seed` (element e uses outputs 2*(e/2), 2*(e/2)+1). */
+tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream);
+
+void tsk_destroy(tsk_op op);
+const char* tsk_status_str(int status);
+const char* tsk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSK_H */

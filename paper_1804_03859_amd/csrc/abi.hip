@@ -1,0 +1,252 @@
+// extern "C" entry points declared in include/tsk.h.  Every entry point catches
+// C++ exceptions and turns them into a negative status; the message of the last
+// failure on the calling thread is kept for tsk_last_error().
+#include <cmath>
+#include <cstring>
+#include <vector>
+#include <exception>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "krylov.hpp"
+#include "ops.hpp"
+
+struct tsk_op_s {
+    std::unique_ptr<tsk::Operator> op;
+};
+
+namespace tsk {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+tsk_status fail(tsk_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace tsk
+
+using namespace tsk;
+
+#define TSK_GUARD(...)                                                                 \
+    try {                                                                              \
+        __VA_ARGS__                                                                    \
+    } catch (const std::bad_alloc&) {                                                  \
+        return fail(TSK_ENOMEM, "host allocation failed");                             \
+    } catch (const std::exception& e) {                                                \
+        return fail(TSK_EINVAL, std::string("internal error: ") + e.what());           \
+    } catch (...) {                                                                    \
+        return fail(TSK_EINVAL, "internal error");                                     \
+    }
+
+#define TSK_NEED(op)                                                                   \
+    if (!(op) || !(op)->op) return fail(TSK_EINVAL, "null operator handle");
+
+extern "C" {
+
+tsk_status tsk_create_cgle1d(tsk_op* out, int n, double half_width, void* hip_stream) {
+    TSK_GUARD({
+        if (!out) return fail(TSK_EINVAL, "null output handle");
+        *out = nullptr;
+        std::unique_ptr<Operator> op;
+        TSK_TRY(make_cgle(n, half_width, static_cast<hipStream_t>(hip_stream), &op));
+        auto* h = new tsk_op_s;
+        h->op = std::move(op);
+        *out = h;
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_set_params_cgle(tsk_op op, double U, double c_u, double c_d, double mu0, double mu2, double dt,
+                               double T) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return cgle_set_params(op->op.get(), U, c_u, c_d, mu0, mu2, dt, T);
+    })
+}
+
+tsk_status tsk_create_kolmo2d(tsk_op* out, int N, tsk_precision precision, void* hip_stream) {
+    TSK_GUARD({
+        if (!out) return fail(TSK_EINVAL, "null output handle");
+        *out = nullptr;
+        std::unique_ptr<Operator> op;
+        TSK_TRY(make_kolmo(N, precision, static_cast<hipStream_t>(hip_stream), &op));
+        auto* h = new tsk_op_s;
+        h->op = std::move(op);
+        *out = h;
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_set_params_kolmo(tsk_op op, double Re, double alpha, double dt, double T) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_params(op->op.get(), Re, alpha, dt, T);
+    })
+}
+
+tsk_status tsk_set_base_parallel(tsk_op op, const double* U_y, const double* dOmega_dy) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_base_parallel(op->op.get(), U_y, dOmega_dy);
+    })
+}
+
+tsk_status tsk_set_base_kolmogorov(tsk_op op, int n_forcing) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!is_kolmo(op->op.get())) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+        if (n_forcing < 1) return fail(TSK_EINVAL, "n_forcing must be >= 1");
+        int64_t N = op->op->physical_reals();
+        int n = 1;
+        while (int64_t(n) * n < N) ++n;
+        std::vector<double> U(n), dO(n);
+        const double pi = 3.14159265358979323846264338327950288;
+        for (int l = 0; l < n; ++l) {
+            double y = 2.0 * pi * l / n;
+            U[l] = std::sin(n_forcing * y);
+            dO[l] = double(n_forcing) * n_forcing * U[l];
+        }
+        return kolmo_set_base_parallel(op->op.get(), U.data(), dO.data());
+    })
+}
+
+tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V, const double* dOmega_dx,
+                             const double* dOmega_dy) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_base_general(op->op.get(), U, V, dOmega_dx, dOmega_dy);
+    })
+}
+
+tsk_status tsk_state_dim(tsk_op op, int64_t* n_scalars, int* is_complex, int* elem_bytes) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (n_scalars) *n_scalars = op->op->n;
+        if (is_complex) *is_complex = op->op->is_complex() ? 1 : 0;
+        if (elem_bytes) *elem_bytes = op->op->elem_bytes();
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_from_physical(tsk_op op, const void* phys_dev, void* state_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!phys_dev || !state_dev) return fail(TSK_EINVAL, "null buffer");
+        return op->op->from_physical(phys_dev, state_dev);
+    })
+}
+
+tsk_status tsk_to_physical(tsk_op op, const void* state_dev, void* phys_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!phys_dev || !state_dev) return fail(TSK_EINVAL, "null buffer");
+        return op->op->to_physical(state_dev, phys_dev);
+    })
+}
+
+tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!x_dev || !y_dev) return fail(TSK_EINVAL, "null buffer");
+        if (x_dev == y_dev) return fail(TSK_EINVAL, "apply: input and output must not alias");
+        return op->op->apply(x_dev, y_dev);
+    })
+}
+
+tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed, double* mu_ri,
+                       double* lambda_ri, double* resid, void* ritz_dev, tsk_arnoldi_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return arnoldi(op->op.get(), m, k, tol, v0_dev, seed, mu_ri, lambda_ri, resid, ritz_dev, info);
+    })
+}
+
+tsk_status tsk_last_hessenberg(tsk_op op, double* H_host, int* m_out, int* steps_out) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        ArnoldiWork& W = op->op->aw;
+        if (!W.H.ptr || W.m == 0) return fail(TSK_ESTATE, "no Arnoldi run on this operator");
+        if (m_out) *m_out = W.m;
+        if (steps_out) *steps_out = W.steps;
+        if (H_host) {
+            TSK_HIP(hipStreamSynchronize(op->op->stream));
+            TSK_HIP(hipMemcpy(H_host, W.H.ptr, size_t(W.m + 1) * W.m * sizeof(double2), hipMemcpyDeviceToHost));
+        }
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_last_basis(tsk_op op, const void** V_dev, int64_t* ld) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        ArnoldiWork& W = op->op->aw;
+        if (!W.V.ptr || W.m == 0) return fail(TSK_ESTATE, "no Arnoldi run on this operator");
+        if (V_dev) *V_dev = W.V.ptr;
+        if (ld) *ld = W.ldv;
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta, void* mu_dev, void* Y_dev,
+                               void* res_dev, void* hip_stream) {
+    TSK_GUARD({
+        if (!H_dev || !mu_dev || !Y_dev || !res_dev) return fail(TSK_EINVAL, "null buffer");
+        if (p < 1 || p > kMaxKrylov || ldh < p) return fail(TSK_EINVAL, "need 1 <= p <= 96 and ldh >= p");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        DevBuf Z, S, rr;
+        TSK_TRY(Z.ensure(size_t(p) * p * sizeof(double2)));
+        TSK_TRY(S.ensure(size_t(p) * p * sizeof(double2)));
+        TSK_TRY(rr.ensure(sizeof(RitzResult)));
+        TSK_HIP(hipMemsetAsync(rr.ptr, 0, sizeof(RitzResult), s));
+        TSK_TRY(hess_ritz_launch(static_cast<const double2*>(H_dev), ldh, p, nullptr, beta, Z.as<double2>(),
+                                 S.as<double2>(), static_cast<double2*>(mu_dev), static_cast<double2*>(Y_dev),
+                                 static_cast<double*>(res_dev), 0, 0.0, 1.0, nullptr, rr.as<RitzResult>(), s));
+        RitzResult h{};
+        TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+        TSK_HIP(hipStreamSynchronize(s));
+        if (h.eig_fail) return fail(TSK_EEIG, "Hessenberg QR did not converge");
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream) {
+    TSK_GUARD({
+        if (!out_dev || count < 0) return fail(TSK_EINVAL, "bad output buffer or count");
+        return normal_fill(out_dev, count, seed, static_cast<hipStream_t>(hip_stream));
+    })
+}
+
+void tsk_destroy(tsk_op op) {
+    try {
+        if (op) {
+            if (op->op) (void)hipStreamSynchronize(op->op->stream);
+            delete op;
+        }
+    } catch (...) {
+    }
+}
+
+const char* tsk_status_str(int status) {
+    switch (status) {
+        case TSK_OK: return "converged";
+        case TSK_NOT_CONVERGED: return "not converged after m matvecs";
+        case TSK_BREAKDOWN: return "Arnoldi breakdown (invariant subspace)";
+        case TSK_EINVAL: return "invalid argument";
+        case TSK_ENOMEM: return "out of memory";
+        case TSK_EHIP: return "HIP runtime error";
+        case TSK_ENONFINITE: return "non-finite value";
+        case TSK_ESTATE: return "call out of order";
+        case TSK_EEIG: return "Hessenberg QR did not converge";
+        default: return "unknown status";
+    }
+}
+
+const char* tsk_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Linear complex Ginzburg-Landau operator and its Crank-Nicolson time stepper.
+//
+// Equation (Sec. 2.3.2, eq. "ginzburg-landau equation"):
+//     du/dt = -nu u_x + gamma u_xx + mu(x) u,  mu(x) = mu0 - c_u^2 + mu2 x^2 / 2,
+// with nu = U + 2 i c_u and gamma = 1 + i c_d.  Second-order central
+// differences on n interior nodes (Dirichlet ends) give the tridiagonal L_h;
+// one matvec of M = exp(L T) is T/dt Crank-Nicolson steps
+//     (I - dt/2 L_h) u+ = (I + dt/2 L_h) u.
+//
+// Kernel design: the whole state (n <= 1024 complex128, 16 KB) stays in one
+// workgroup for the full integration, one thread per node.  The implicit solve
+// is parallel cyclic reduction (Hockney & Jesshope): level l eliminates the
+// couplings at distance 2^l, so after ceil(log2 n) levels every equation is
+// decoupled.  The elimination multipliers of the constant matrix are computed
+// once on the host when the parameters are set, so a time step is the
+// three-point right-hand side plus, per level, two neighbour reads from LDS and
+// two complex multiply-adds per node.  The matrix is strictly diagonally
+// dominant, so no pivoting is needed.
+#include <complex>
+#include <vector>
+
+#include "ops.hpp"
+
+namespace tsk {
+
+namespace {
+
+constexpr int kCgleMaxN = 1024;
+constexpr int kCgleMaxLevels = 10;
+
+__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict__ uin, double2* __restrict__ uout,
+                                                      const double2* __restrict__ rhs_main, double2 rhs_sub,
+                                                      double2 rhs_sup, const double2* __restrict__ alpha,
+                                                      const double2* __restrict__ gamma,
+                                                      const double2* __restrict__ binv, int n, int levels,
+                                                      int nsteps) {
+    __shared__ double2 bufA[kCgleMaxN];
+    __shared__ double2 bufB[kCgleMaxN];
+    const int i = threadIdx.x;
+    const bool act = i < n;
+    double2 al[kCgleMaxLevels], ga[kCgleMaxLevels];
+#pragma unroll
+    for (int l = 0; l < kCgleMaxLevels; ++l) {
+        al[l] = (act && l < levels) ? alpha[l * n + i] : cmk<double2>(0.0, 0.0);
+        ga[l] = (act && l < levels) ? gamma[l * n + i] : cmk<double2>(0.0, 0.0);
+    }
+    const double2 rm = act ? rhs_main[i] : cmk<double2>(0.0, 0.0);
+    const double2 bi = act ? binv[i] : cmk<double2>(0.0, 0.0);
+    double2 u = act ? uin[i] : cmk<double2>(0.0, 0.0);
+    const double2 zero = cmk<double2>(0.0, 0.0);
+    for (int st = 0; st < nsteps; ++st) {
+        // explicit half: d = (I + dt/2 L) u
+        bufA[i] = u;
+        __syncthreads();
+        double2 um = (i > 0 && act) ? bufA[i - 1] : zero;
+        double2 up = (i + 1 < n) ? bufA[i + 1] : zero;
+        double2 d = cadd(cmul(rm, u), cadd(cmul(rhs_sub, um), cmul(rhs_sup, up)));
+        // implicit half by cyclic reduction, ping-pong between two LDS buffers
+        double2* src = bufA;  // level 0 swaps to bufB: bufA is still being read for the stencil
+        double2* dst = bufB;
+        int s = 1;
+#pragma unroll
+        for (int l = 0; l < kCgleMaxLevels; ++l) {
+            if (l >= levels) break;
+            double2* t = src; src = dst; dst = t;  // write into the buffer read last level
+            src[i] = d;
+            __syncthreads();
+            double2 dm = (i - s >= 0 && act) ? src[i - s] : zero;
+            double2 dp = (i + s < n) ? src[i + s] : zero;
+            d = cadd(d, cadd(cmul(al[l], dm), cmul(ga[l], dp)));
+            s <<= 1;
+        }
+        u = cmul(d, bi);
+        __syncthreads();
+    }
+    if (act) uout[i] = u;
+}
+
+struct CgleOp final : Operator {
+    int nn = 0;
+    double half_width = 0.0;
+    int levels = 0, nsteps = 0;
+    double2 rsub{}, rsup{};
+    DevBuf tab;  // rhs_main[n] | alpha[levels*n] | gamma[levels*n] | binv[n]
+
+    const char* name() const override { return "cgle1d"; }
+    int64_t physical_reals() const override { return 2 * int64_t(nn); }
+
+    tsk_status set_params(double U, double c_u, double c_d, double mu0, double mu2, double dt, double TT) {
+        using cd = std::complex<double>;
+        if (!(dt > 0.0) || !(TT > 0.0) || !std::isfinite(dt) || !std::isfinite(TT))
+            return fail(TSK_EINVAL, "dt and T must be positive and finite");
+        double ns = TT / dt;
+        int nsi = int(std::lround(ns));
+        if (nsi < 1 || std::fabs(ns - nsi) > 1e-9 * std::max(1.0, ns))
+            return fail(TSK_EINVAL, "T must be an integer multiple of dt");
+        const int n_ = nn;
+        const double dx = 2.0 * half_width / (n_ + 1);
+        const cd nu(U, 2.0 * c_u), gam(1.0, c_d);
+        const cd sub = gam / (dx * dx) + nu / (2.0 * dx);
+        const cd sup = gam / (dx * dx) - nu / (2.0 * dx);
+        const double h = 0.5 * dt;
+        std::vector<cd> mainv(n_), a(n_), b(n_), c(n_);
+        for (int j = 0; j < n_; ++j) {
+            double x = -half_width + dx * (j + 1);
+            double mux = (mu0 - c_u * c_u) + mu2 * x * x / 2.0;
+            mainv[j] = -2.0 * gam / (dx * dx) + mux;
+            a[j] = j > 0 ? -h * sub : cd(0.0);
+            b[j] = 1.0 - h * mainv[j];
+            c[j] = j + 1 < n_ ? -h * sup : cd(0.0);
+        }
+        int L = 0;
+        while ((1 << L) < n_) ++L;
+        std::vector<cd> al(size_t(L) * n_), ga(size_t(L) * n_);
+        for (int l = 0, s = 1; l < L; ++l, s <<= 1) {
+            std::vector<cd> a2(n_), b2(n_), c2(n_);
+            for (int j = 0; j < n_; ++j) {
+                cd alpha = j - s >= 0 ? -a[j] / b[j - s] : cd(0.0);
+                cd gamma = j + s < n_ ? -c[j] / b[j + s] : cd(0.0);
+                al[size_t(l) * n_ + j] = alpha;
+                ga[size_t(l) * n_ + j] = gamma;
+                a2[j] = j - s >= 0 ? alpha * a[j - s] : cd(0.0);
+                c2[j] = j + s < n_ ? gamma * c[j + s] : cd(0.0);
+                b2[j] = b[j] + (j - s >= 0 ? alpha * c[j - s] : cd(0.0)) + (j + s < n_ ? gamma * a[j + s] : cd(0.0));
+            }
+            a.swap(a2); b.swap(b2); c.swap(c2);
+        }
+        std::vector<double2> host(size_t(n_) * (2 + 2 * L));
+        size_t o = 0;
+        for (int j = 0; j < n_; ++j) { cd r = 1.0 + h * mainv[j]; host[o++] = cmk<double2>(r.real(), r.imag()); }
+        for (const cd& v : al) host[o++] = cmk<double2>(v.real(), v.imag());
+        for (const cd& v : ga) host[o++] = cmk<double2>(v.real(), v.imag());
+        for (int j = 0; j < n_; ++j) { cd r = 1.0 / b[j]; host[o++] = cmk<double2>(r.real(), r.imag()); }
+        TSK_TRY(tab.ensure(host.size() * sizeof(double2)));
+        TSK_HIP(hipMemcpy(tab.ptr, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice));
+        cd rs = h * sub, rp = h * sup;
+        rsub = cmk<double2>(rs.real(), rs.imag());
+        rsup = cmk<double2>(rp.real(), rp.imag());
+        levels = L;
+        nsteps = nsi;
+        T = TT;
+        params_set = true;
+        return TSK_OK;
+    }
+
+    tsk_status apply(const void* x, void* y) override {
+        if (!ready()) return fail(TSK_ESTATE, "CGLE parameters not set");
+        const double2* t = tab.as<double2>();
+        const int n_ = nn;
+        const int threads = (n_ + kWave - 1) / kWave * kWave;
+        hipLaunchKernelGGL(k_cgle_cn, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
+                           static_cast<double2*>(y), t, rsub, rsup, t + n_, t + n_ + size_t(levels) * n_,
+                           t + n_ + 2 * size_t(levels) * n_, n_, levels, nsteps);
+        TSK_HIP(hipGetLastError());
+        return TSK_OK;
+    }
+    tsk_status from_physical(const void* phys, void* state) override {
+        TSK_HIP(hipMemcpyAsync(state, phys, state_bytes(), hipMemcpyDeviceToDevice, stream));
+        return TSK_OK;
+    }
+    tsk_status to_physical(const void* state, void* phys) override {
+        TSK_HIP(hipMemcpyAsync(phys, state, state_bytes(), hipMemcpyDeviceToDevice, stream));
+        return TSK_OK;
+    }
+};
+
+}  // namespace
+
+tsk_status make_cgle(int n, double half_width, hipStream_t s, std::unique_ptr<Operator>* out) {
+    if (n < 2 || n > kCgleMaxN) return fail(TSK_EINVAL, "CGLE node count must be in [2, 1024]");
+    if (!(half_width > 0.0) || !std::isfinite(half_width)) return fail(TSK_EINVAL, "half_width must be positive");
+    auto op = std::make_unique<CgleOp>();
+    op->nn = n;
+    op->half_width = half_width;
+    op->n = n;
+    op->kind = StateKind::Complex64x2;
+    op->stream = s;
+    op->base_set = true;  // the CGLE has no base flow
+    *out = std::move(op);
+    return TSK_OK;
+}
+
+tsk_status cgle_set_params(Operator* op, double U, double c_u, double c_d, double mu0, double mu2, double dt,
+                           double T) {
+    auto* c = dynamic_cast<CgleOp*>(op);
+    if (!c) return fail(TSK_EINVAL, "not a Ginzburg-Landau operator");
+    return c->set_params(U, c_u, c_d, mu0, mu2, dt, T);
+}
+
+bool is_cgle(const Operator* op) { return dynamic_cast<const CgleOp*>(op) != nullptr; }
+
+}  // namespace tsk

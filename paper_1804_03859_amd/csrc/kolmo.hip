@@ -1,0 +1,510 @@
+// Linearized 2D Navier-Stokes operator (vorticity form) about a parallel base
+// flow, pseudo-spectral with the 2/3 rule, integrating-factor RK4 time stepper.
+//
+// Equation (Sec. 3, eq. "linearized Navier-Stokes equations", curl taken):
+//     d omega/dt = -(U d_x omega + v dOmega/dy) + Re^-1 lap omega,
+// for a base flow (U(y), 0) with base-vorticity gradient dOmega/dy = -U''(y);
+// u = d psi/dy, v = -d psi/dx, -lap psi = omega.  The matvec of the
+// exponential propagator M = exp(A T) (Sec. 3.2) is T/dt steps of Lawson's
+// integrating-factor RK4 with E(t) = exp(-K^2 t / Re).
+//
+// MI355X design.  With a base flow that depends on y only, the grid products
+// U(y) f(x, y) never mix x-wavenumbers: the forward and inverse x-transforms
+// around the product cancel exactly on the kept modes, so each dealiased kx
+// column evolves on its own.  One 64-lane workgroup owns one column for the
+// whole matvec (all T/dt steps and 4 stages): the column's spectral state, RK
+// accumulator and stage input live in registers, the y-transforms run in LDS
+// (fft.hpp), the product with the base profile is applied in registers between
+// the inverse and forward transforms, and HBM is touched only to read the
+// input column once and to write the output column once.  No grid-wide
+// synchronisation is needed, so a matvec is a single launch of M+1 workgroups.
+// When dOmega/dy = c U (true for the Kolmogorov base sin(n y), c = n^2) the two
+// inverse transforms are merged in spectral space by linearity,
+// d_x omega - c d_x psi <-> i kx (1 - c/K^2) omega_hat.
+//
+// State layout ("packed spectral", see tsk.h): kx = 0 column jy = 1..M, then
+// kx = 1..M columns jy = -M..M, each (re, im) of sqrt(2) rfft2(omega)/N^2.
+#include <cmath>
+#include <vector>
+
+#include "fft.hpp"
+#include "ops.hpp"
+
+namespace tsk {
+
+namespace {
+
+template <int N> struct Geo {
+    static constexpr int M = (N - 1) / 3;       // largest kept |j|
+    static constexpr int NM = 2 * M + 1;        // kept ky per column
+    static constexpr int RM = (NM + kWave - 1) / kWave;
+    static constexpr int RY = (N + kWave - 1) / kWave;
+    static constexpr int64_t n_state = 4ll * M * (M + 1);
+    static __host__ __device__ constexpr int64_t seg(int kx) {
+        return kx == 0 ? 0 : 2ll * M + int64_t(kx - 1) * 2 * NM;
+    }
+};
+
+// ---- the column time stepper ------------------------------------------------------------
+template <typename real, int N, bool PROP>
+__global__ __launch_bounds__(kWave) void k_colstep(const real* __restrict__ xin, real* __restrict__ yout,
+                                                   const real* __restrict__ negU, const real* __restrict__ dOdy,
+                                                   const cplx<real>* __restrict__ twg, double alpha, double Re,
+                                                   double dt, double cprop, int nsteps) {
+    using C = cplx<real>;
+    using G = Geo<N>;
+    constexpr int M = G::M, NM = G::NM, RM = G::RM, RY = G::RY;
+    const int lane = threadIdx.x;
+    const int kx = blockIdx.x;
+
+    if (kx == 0) {
+        // kx = 0: the advection term vanishes identically (d/dx of a y-only
+        // field), so the integrating factor alone advances the column.
+        for (int q = lane; q < M; q += kWave) {
+            const double jy = q + 1;
+            const real E1 = real(exp(-jy * jy * dt / Re));
+            real re = xin[2 * q], im = xin[2 * q + 1];
+            for (int st = 0; st < nsteps; ++st) { re *= E1; im *= E1; }
+            yout[2 * q] = re;
+            yout[2 * q + 1] = im;
+        }
+        return;
+    }
+
+    __shared__ C sA[N], sB[N], sT[N];
+    __shared__ C sC[PROP ? 1 : N], sD[PROP ? 1 : N];
+    for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
+
+    const double kxv = alpha * kx;
+    real E1[RM], Eh[RM], g1[RM], g2[RM];
+    C w[RM], acc[RM], s[RM];
+    int pos[RM];
+    const real* xs = xin + G::seg(kx);
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int q = lane + r * kWave;
+        if (q < NM) {
+            const int jy = q - M;
+            const double K2 = kxv * kxv + double(jy) * jy;
+            E1[r] = real(exp(-K2 * dt / Re));
+            Eh[r] = real(exp(-K2 * (0.5 * dt) / Re));
+            g1[r] = PROP ? real(kxv * (1.0 - cprop / K2)) : real(kxv);
+            g2[r] = real(kxv / K2);
+            pos[r] = jy < 0 ? jy + N : jy;
+            w[r] = cmk<C>(xs[2 * q], xs[2 * q + 1]);
+        } else {
+            E1[r] = Eh[r] = g1[r] = g2[r] = real(0);
+            pos[r] = 0;
+            w[r] = cmk<C>(real(0), real(0));
+        }
+        acc[r] = s[r] = w[r];
+    }
+    real nu[RY], oy[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int l = lane + r * kWave;
+        nu[r] = l < N ? negU[l] : real(0);
+        oy[r] = (!PROP && l < N) ? dOdy[l] : real(0);
+    }
+    __syncthreads();
+
+    const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
+    const real invN = real(1.0 / N);
+    const C zero = cmk<C>(real(0), real(0));
+
+    for (int st = 0; st < nsteps; ++st) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) s[r] = w[r];
+#pragma unroll 1
+        for (int stage = 0; stage < 4; ++stage) {
+            // i kx (...) applied to the stage input, scattered in FFT order
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                if (lane + r * kWave < NM) {
+                    sA[pos[r]] = cmk<C>(-g1[r] * s[r].y, g1[r] * s[r].x);
+                    if constexpr (!PROP) sC[pos[r]] = cmk<C>(-g2[r] * s[r].y, g2[r] * s[r].x);
+                }
+            }
+            for (int t = M + 1 + lane; t < N - M; t += kWave) {
+                sA[t] = zero;
+                if constexpr (!PROP) sC[t] = zero;
+            }
+            __syncthreads();
+            C* F = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
+            C* Gq = nullptr;
+            if constexpr (!PROP) Gq = fft_lds<N, +1, kWave>(sC, sD, sT, lane);
+            // product with the base profiles on the y grid
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int l = lane + r * kWave;
+                if (l < N) {
+                    C f = F[l];
+                    C p = cmk<C>(nu[r] * f.x, nu[r] * f.y);
+                    if constexpr (!PROP) {
+                        C g = Gq[l];
+                        p.x += oy[r] * g.x;
+                        p.y += oy[r] * g.y;
+                    }
+                    F[l] = p;
+                }
+            }
+            __syncthreads();
+            C* X = fft_lds<N, -1, kWave>(F, F == sA ? sB : sA, sT, lane);
+            // Lawson RK4 bookkeeping on the kept modes
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                if (lane + r * kWave < NM) {
+                    C nh = X[pos[r]];
+                    nh.x *= invN;
+                    nh.y *= invN;
+                    const real e1 = E1[r], eh = Eh[r];
+                    if (stage == 0) {
+                        acc[r] = cmk<C>(e1 * (w[r].x + h6 * nh.x), e1 * (w[r].y + h6 * nh.y));
+                        s[r] = cmk<C>(eh * (w[r].x + h2 * nh.x), eh * (w[r].y + h2 * nh.y));
+                    } else if (stage == 1) {
+                        acc[r].x += h3 * eh * nh.x;
+                        acc[r].y += h3 * eh * nh.y;
+                        s[r] = cmk<C>(eh * w[r].x + h2 * nh.x, eh * w[r].y + h2 * nh.y);
+                    } else if (stage == 2) {
+                        acc[r].x += h3 * eh * nh.x;
+                        acc[r].y += h3 * eh * nh.y;
+                        s[r] = cmk<C>(e1 * w[r].x + hh * eh * nh.x, e1 * w[r].y + hh * eh * nh.y);
+                    } else {
+                        w[r] = cmk<C>(acc[r].x + h6 * nh.x, acc[r].y + h6 * nh.y);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    real* ys = yout + G::seg(kx);
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int q = lane + r * kWave;
+        if (q < NM) {
+            ys[2 * q] = w[r].x;
+            ys[2 * q + 1] = w[r].y;
+        }
+    }
+}
+
+// ---- physical <-> packed spectral ------------------------------------------------------
+// Z is the N x (M+1) complex intermediate, row-major [y][kx].
+template <typename real, int N>
+__global__ __launch_bounds__(kWave) void k_rows_fwd(const real* __restrict__ phys, cplx<real>* __restrict__ Z,
+                                                    const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    constexpr int M = Geo<N>::M;
+    __shared__ C sA[N], sB[N], sT[N];
+    const int lane = threadIdx.x, y = blockIdx.x;
+    for (int t = lane; t < N; t += kWave) {
+        sT[t] = twg[t];
+        sA[t] = cmk<C>(phys[size_t(y) * N + t], real(0));
+    }
+    __syncthreads();
+    C* X = fft_lds<N, -1, kWave>(sA, sB, sT, lane);
+    for (int kx = lane; kx <= M; kx += kWave) Z[size_t(y) * (M + 1) + kx] = X[kx];
+}
+
+template <typename real, int N>
+__global__ __launch_bounds__(kWave) void k_cols_fwd(const cplx<real>* __restrict__ Z, real* __restrict__ state,
+                                                    const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    using G = Geo<N>;
+    constexpr int M = G::M, NM = G::NM;
+    __shared__ C sA[N], sB[N], sT[N];
+    const int lane = threadIdx.x, kx = blockIdx.x;
+    for (int t = lane; t < N; t += kWave) {
+        sT[t] = twg[t];
+        sA[t] = Z[size_t(t) * (M + 1) + kx];
+    }
+    __syncthreads();
+    C* X = fft_lds<N, -1, kWave>(sA, sB, sT, lane);
+    const real sc = real(1.4142135623730950488 / (double(N) * N));
+    real* out = state + G::seg(kx);
+    if (kx == 0) {
+        for (int jy = 1 + lane; jy <= M; jy += kWave) {
+            out[2 * (jy - 1)] = X[jy].x * sc;
+            out[2 * (jy - 1) + 1] = X[jy].y * sc;
+        }
+    } else {
+        for (int q = lane; q < NM; q += kWave) {
+            int jy = q - M, pp = jy < 0 ? jy + N : jy;
+            out[2 * q] = X[pp].x * sc;
+            out[2 * q + 1] = X[pp].y * sc;
+        }
+    }
+}
+
+template <typename real, int N>
+__global__ __launch_bounds__(kWave) void k_cols_inv(const real* __restrict__ state, cplx<real>* __restrict__ Z,
+                                                    const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    using G = Geo<N>;
+    constexpr int M = G::M, NM = G::NM;
+    __shared__ C sA[N], sB[N], sT[N];
+    const int lane = threadIdx.x, kx = blockIdx.x;
+    for (int t = lane; t < N; t += kWave) {
+        sT[t] = twg[t];
+        sA[t] = cmk<C>(real(0), real(0));
+    }
+    __syncthreads();
+    const real sc = real(0.70710678118654752440);
+    const real* in = state + G::seg(kx);
+    if (kx == 0) {
+        for (int jy = 1 + lane; jy <= M; jy += kWave) {
+            C c = cmk<C>(in[2 * (jy - 1)] * sc, in[2 * (jy - 1) + 1] * sc);
+            sA[jy] = c;
+            sA[N - jy] = cconj(c);
+        }
+    } else {
+        for (int q = lane; q < NM; q += kWave) {
+            int jy = q - M, pp = jy < 0 ? jy + N : jy;
+            sA[pp] = cmk<C>(in[2 * q] * sc, in[2 * q + 1] * sc);
+        }
+    }
+    __syncthreads();
+    C* X = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
+    for (int y = lane; y < N; y += kWave) Z[size_t(y) * (M + 1) + kx] = X[y];
+}
+
+template <typename real, int N>
+__global__ __launch_bounds__(kWave) void k_rows_inv(const cplx<real>* __restrict__ Z, real* __restrict__ phys,
+                                                    const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    constexpr int M = Geo<N>::M;
+    __shared__ C sA[N], sB[N], sT[N];
+    const int lane = threadIdx.x, y = blockIdx.x;
+    for (int t = lane; t < N; t += kWave) {
+        sT[t] = twg[t];
+        sA[t] = cmk<C>(real(0), real(0));
+    }
+    __syncthreads();
+    for (int kx = lane; kx <= M; kx += kWave) {
+        C c = Z[size_t(y) * (M + 1) + kx];
+        sA[kx] = c;
+        if (kx > 0) sA[N - kx] = cconj(c);
+    }
+    __syncthreads();
+    C* X = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
+    for (int x = lane; x < N; x += kWave) phys[size_t(y) * N + x] = X[x].x;
+}
+
+// ---- dispatch ------------------------------------------------------------------------------
+struct KolmoLaunch {
+    const void* x;
+    void* y;
+    const void* negU;
+    const void* dOdy;
+    const void* tw;
+    void* Z;
+    double alpha, Re, dt, cprop;
+    int nsteps;
+    hipStream_t s;
+};
+
+template <typename real, int N> struct KK {
+    using C = cplx<real>;
+    static void colstep(const KolmoLaunch& a, bool prop) {
+        constexpr int M = Geo<N>::M;
+        if (prop)
+            hipLaunchKernelGGL((k_colstep<real, N, true>), dim3(M + 1), dim3(kWave), 0, a.s,
+                               static_cast<const real*>(a.x), static_cast<real*>(a.y),
+                               static_cast<const real*>(a.negU), static_cast<const real*>(a.dOdy),
+                               static_cast<const C*>(a.tw), a.alpha, a.Re, a.dt, a.cprop, a.nsteps);
+        else
+            hipLaunchKernelGGL((k_colstep<real, N, false>), dim3(M + 1), dim3(kWave), 0, a.s,
+                               static_cast<const real*>(a.x), static_cast<real*>(a.y),
+                               static_cast<const real*>(a.negU), static_cast<const real*>(a.dOdy),
+                               static_cast<const C*>(a.tw), a.alpha, a.Re, a.dt, a.cprop, a.nsteps);
+    }
+    static void fwd(const KolmoLaunch& a) {
+        constexpr int M = Geo<N>::M;
+        hipLaunchKernelGGL((k_rows_fwd<real, N>), dim3(N), dim3(kWave), 0, a.s, static_cast<const real*>(a.x),
+                           static_cast<C*>(a.Z), static_cast<const C*>(a.tw));
+        hipLaunchKernelGGL((k_cols_fwd<real, N>), dim3(M + 1), dim3(kWave), 0, a.s,
+                           static_cast<const C*>(a.Z), static_cast<real*>(a.y), static_cast<const C*>(a.tw));
+    }
+    static void inv(const KolmoLaunch& a) {
+        constexpr int M = Geo<N>::M;
+        hipLaunchKernelGGL((k_cols_inv<real, N>), dim3(M + 1), dim3(kWave), 0, a.s, static_cast<const real*>(a.x),
+                           static_cast<C*>(a.Z), static_cast<const C*>(a.tw));
+        hipLaunchKernelGGL((k_rows_inv<real, N>), dim3(N), dim3(kWave), 0, a.s, static_cast<const C*>(a.Z),
+                           static_cast<real*>(a.y), static_cast<const C*>(a.tw));
+    }
+};
+
+#define TSK_KOLMO_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+bool kolmo_size_ok(int N) {
+    switch (N) {
+#define X(n) case n:
+        TSK_KOLMO_SIZES(X)
+#undef X
+        return true;
+        default: return false;
+    }
+}
+
+template <typename real> void dispatch_colstep(int N, const KolmoLaunch& a, bool prop) {
+    switch (N) {
+#define X(n) case n: KK<real, n>::colstep(a, prop); break;
+        TSK_KOLMO_SIZES(X)
+#undef X
+    }
+}
+template <typename real> void dispatch_fwd(int N, const KolmoLaunch& a) {
+    switch (N) {
+#define X(n) case n: KK<real, n>::fwd(a); break;
+        TSK_KOLMO_SIZES(X)
+#undef X
+    }
+}
+template <typename real> void dispatch_inv(int N, const KolmoLaunch& a) {
+    switch (N) {
+#define X(n) case n: KK<real, n>::inv(a); break;
+        TSK_KOLMO_SIZES(X)
+#undef X
+    }
+}
+
+struct KolmoOp final : Operator {
+    int N = 0, M = 0;
+    tsk_precision prec = TSK_FP64;
+    double alpha = 0.0, Re = 0.0, dt = 0.0;
+    int nsteps = 0;
+    bool prop = false;
+    double cprop = 0.0;
+    DevBuf tw, negU, dOdy, Z;
+
+    const char* name() const override { return "kolmo2d"; }
+    int64_t physical_reals() const override { return int64_t(N) * N; }
+    size_t rb() const { return prec == TSK_FP32 ? 4 : 8; }
+
+    tsk_status upload_real(DevBuf& buf, const std::vector<double>& v) {
+        TSK_TRY(buf.ensure(v.size() * rb()));
+        if (prec == TSK_FP32) {
+            std::vector<float> f(v.begin(), v.end());
+            TSK_HIP(hipMemcpy(buf.ptr, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+        } else {
+            TSK_HIP(hipMemcpy(buf.ptr, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+        }
+        return TSK_OK;
+    }
+
+    tsk_status init() {
+        std::vector<double> t(2 * size_t(N));
+        for (int i = 0; i < N; ++i) {
+            // exp(-2 pi i t / N), evaluated in FP64 on the host
+            const double pi = 3.14159265358979323846264338327950288;
+            double ang = 2.0 * pi * double(i) / N;
+            t[2 * i] = std::cos(ang);
+            t[2 * i + 1] = -std::sin(ang);
+        }
+        TSK_TRY(upload_real(tw, t));
+        TSK_TRY(Z.ensure(size_t(N) * (M + 1) * 2 * rb()));
+        return TSK_OK;
+    }
+
+    KolmoLaunch args(const void* x, void* y) const {
+        KolmoLaunch a{x, y, negU.ptr, dOdy.ptr, tw.ptr, Z.ptr, alpha, Re, dt, cprop, nsteps, stream};
+        return a;
+    }
+
+    tsk_status apply(const void* x, void* y) override {
+        if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
+        if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
+        KolmoLaunch a = args(x, y);
+        if (prec == TSK_FP32) dispatch_colstep<float>(N, a, prop);
+        else dispatch_colstep<double>(N, a, prop);
+        TSK_HIP(hipGetLastError());
+        return TSK_OK;
+    }
+    tsk_status from_physical(const void* phys, void* state) override {
+        KolmoLaunch a = args(phys, state);
+        if (prec == TSK_FP32) dispatch_fwd<float>(N, a);
+        else dispatch_fwd<double>(N, a);
+        TSK_HIP(hipGetLastError());
+        return TSK_OK;
+    }
+    tsk_status to_physical(const void* state, void* phys) override {
+        KolmoLaunch a = args(state, phys);
+        if (prec == TSK_FP32) dispatch_inv<float>(N, a);
+        else dispatch_inv<double>(N, a);
+        TSK_HIP(hipGetLastError());
+        return TSK_OK;
+    }
+};
+
+}  // namespace
+
+tsk_status make_kolmo(int N, tsk_precision prec, hipStream_t s, std::unique_ptr<Operator>* out) {
+    if (!kolmo_size_ok(N))
+        return fail(TSK_EINVAL, "grid size N must be one of 16, 32, 48, 64, 96, 128, 192, 256, 384, 512");
+    if (prec != TSK_FP64 && prec != TSK_FP32) return fail(TSK_EINVAL, "unknown precision");
+    auto op = std::make_unique<KolmoOp>();
+    op->N = N;
+    op->M = (N - 1) / 3;
+    op->prec = prec;
+    op->stream = s;
+    op->n = 4ll * op->M * (op->M + 1);
+    op->kind = prec == TSK_FP32 ? StateKind::Real32 : StateKind::Real64;
+    TSK_TRY(op->init());
+    *out = std::move(op);
+    return TSK_OK;
+}
+
+tsk_status kolmo_set_params(Operator* op, double Re, double alpha, double dt, double T) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!(Re > 0.0) || !(alpha > 0.0) || !(dt > 0.0) || !(T > 0.0) || !std::isfinite(Re) || !std::isfinite(alpha) ||
+        !std::isfinite(dt) || !std::isfinite(T))
+        return fail(TSK_EINVAL, "Re, alpha, dt and T must be positive and finite");
+    double ns = T / dt;
+    int nsi = int(std::lround(ns));
+    if (nsi < 1 || std::fabs(ns - nsi) > 1e-9 * std::max(1.0, ns))
+        return fail(TSK_EINVAL, "T must be an integer multiple of dt");
+    k->Re = Re;
+    k->alpha = alpha;
+    k->dt = dt;
+    k->nsteps = nsi;
+    k->T = T;
+    k->params_set = true;
+    return TSK_OK;
+}
+
+tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* dOdy) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!U || !dOdy) return fail(TSK_EINVAL, "null base-flow profile");
+    const int N = k->N;
+    std::vector<double> nu(N), oy(N);
+    double uu = 0.0, uo = 0.0, omax = 0.0;
+    for (int i = 0; i < N; ++i) {
+        if (!std::isfinite(U[i]) || !std::isfinite(dOdy[i])) return fail(TSK_ENONFINITE, "non-finite base flow");
+        nu[i] = -U[i];
+        oy[i] = dOdy[i];
+        uu += U[i] * U[i];
+        uo += U[i] * dOdy[i];
+        omax = std::max(omax, std::fabs(dOdy[i]));
+    }
+    // detect dOmega/dy = c U (one inverse transform per stage instead of two)
+    double c = uu > 0.0 ? uo / uu : 0.0;
+    double dev = 0.0;
+    for (int i = 0; i < N; ++i) dev = std::max(dev, std::fabs(dOdy[i] - c * U[i]));
+    k->prop = uu > 0.0 && dev <= 1e-13 * std::max(omax, 1e-300);
+    k->cprop = k->prop ? c : 0.0;
+    TSK_TRY(k->upload_real(k->negU, nu));
+    TSK_TRY(k->upload_real(k->dOdy, oy));
+    k->base_set = true;
+    return TSK_OK;
+}
+
+tsk_status kolmo_set_base_general(Operator* op, const double*, const double*, const double*, const double*) {
+    if (!dynamic_cast<KolmoOp*>(op)) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    return fail(TSK_EINVAL, "general two-dimensional base flows are not supported by this build");
+}
+
+bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != nullptr; }
+
+}  // namespace tsk

@@ -1,0 +1,114 @@
+// Operator objects behind the opaque tsk_op handle, and the Arnoldi driver's
+// device workspace.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tsk {
+
+// Device buffer owned by the library (hipMalloc/hipFree), grown on demand.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    tsk_status ensure(size_t want) {
+        if (want <= bytes && ptr) return TSK_OK;
+        release();
+        if (want == 0) want = 16;
+        if (hipMalloc(&ptr, want) != hipSuccess) {
+            ptr = nullptr;
+            return fail(TSK_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        bytes = want;
+        return TSK_OK;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+enum class StateKind { Complex64x2, Real64, Real32 };  // double2 / double / float
+
+struct ArnoldiWork {
+    DevBuf V;         // (m+1) x n state vectors
+    DevBuf H;         // (m+1) x m complex128, column-major
+    DevBuf w;         // matvec output (state type)
+    DevBuf w64;       // FP64 (or complex128) working copy during Gram-Schmidt
+    DevBuf partial;   // per-block partial dot products
+    DevBuf pnrm;      // per-block partial squared norms
+    DevBuf h;         // reduced projection coefficients
+    DevBuf scal;      // device scalars
+    DevBuf eigZ, eigS, eigY, eigMu, eigRes, sel;  // Hessenberg eigensolver
+    DevBuf rr;        // RitzResult
+    DevBuf phys;      // physical field scratch (seeded start vector)
+    RitzResult* rr_host = nullptr;  // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // matvec timing
+    int m = 0, steps = 0;
+    int64_t ldv = 0;
+    ~ArnoldiWork() {
+        if (rr_host) (void)hipHostFree(rr_host);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+struct Operator {
+    virtual ~Operator() = default;
+    hipStream_t stream = nullptr;
+    int64_t n = 0;           // state length in scalars (complex count if complex)
+    StateKind kind = StateKind::Real64;
+    double T = 0.0;
+    bool params_set = false;
+    bool base_set = false;
+    ArnoldiWork aw;
+
+    bool is_complex() const { return kind == StateKind::Complex64x2; }
+    int elem_bytes() const { return kind == StateKind::Real32 ? 4 : 8; }
+    size_t state_bytes() const { return size_t(n) * (is_complex() ? 16 : size_t(elem_bytes())); }
+    bool ready() const { return params_set && base_set; }
+
+    virtual const char* name() const = 0;
+    virtual tsk_status apply(const void* x, void* y) = 0;
+    virtual tsk_status from_physical(const void* phys, void* state) = 0;
+    virtual tsk_status to_physical(const void* state, void* phys) = 0;
+    // Number of reals in the physical field (complex fields count 2 per value).
+    virtual int64_t physical_reals() const = 0;
+};
+
+// Factories (defined in cgle.hip / kolmo.hip).
+tsk_status make_cgle(int n, double half_width, hipStream_t s, std::unique_ptr<Operator>* out);
+tsk_status cgle_set_params(Operator* op, double U, double c_u, double c_d, double mu0, double mu2,
+                           double dt, double T);
+tsk_status make_kolmo(int N, tsk_precision prec, hipStream_t s, std::unique_ptr<Operator>* out);
+tsk_status kolmo_set_params(Operator* op, double Re, double alpha, double dt, double T);
+tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* dOdy);
+tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
+                                  const double* Oy);
+bool is_kolmo(const Operator* op);
+bool is_cgle(const Operator* op);
+
+// Arnoldi driver (arnoldi.hip).
+tsk_status arnoldi(Operator* op, int m, int k, double tol, const void* v0, uint64_t seed, double* mu_ri,
+                   double* lam_ri, double* resid, void* ritz, tsk_arnoldi_info* info);
+
+// Device Hessenberg eigensolver + wanted-set selection (hessenberg.hip).
+// Launches on `s`.  sel/rr may be null (no selection).
+tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta_dev, double beta_val,
+                            double2* Z, double2* S, double2* mu, double2* Y, double* res, int k, double tol,
+                            double T, int* sel, RitzResult* rr, hipStream_t s);
+
+// Normal draws (rng.hip).
+tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);
+// out[i] = float(in[i]); out may alias the front of in.
+tsk_status narrow_to_float(const double* in, float* out, int64_t count, hipStream_t s);
+
+}  // namespace tsk

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libtsk (include/tsk.h).  Argument marshalling only:
+every step of the computation runs in the HIP library.  PyTorch supplies device
+memory (tensors as buffers) and the current HIP stream.
+
+The binding refuses to work without the built library: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsk.so")
+
+TSK_OK, TSK_NOT_CONVERGED, TSK_BREAKDOWN = 0, 1, 2
+TSK_EINVAL, TSK_ENOMEM, TSK_EHIP, TSK_ENONFINITE, TSK_ESTATE, TSK_EEIG = -1, -2, -3, -4, -5, -6
+TSK_FP64, TSK_FP32 = 0, 1
+
+
+class TskError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class ArnoldiInfo(C.Structure):
+    _fields_ = [("n_matvec", C.c_int), ("n_ritz", C.c_int), ("n_converged", C.c_int),
+                ("status", C.c_int), ("beta", C.c_double), ("ms_total", C.c_double),
+                ("ms_apply", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libtsk.so (built by paper_1804_03859_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libtsk.so not found at {LIB_PATH}: build it with "
+                          "`python -m paper_1804_03859_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_uint64
+    P = C.POINTER
+    sig = {
+        "tsk_create_cgle1d": [P(vp), i32, f64, vp],
+        "tsk_set_params_cgle": [vp, f64, f64, f64, f64, f64, f64, f64],
+        "tsk_create_kolmo2d": [P(vp), i32, i32, vp],
+        "tsk_set_params_kolmo": [vp, f64, f64, f64, f64],
+        "tsk_set_base_parallel": [vp, P(f64), P(f64)],
+        "tsk_set_base_kolmogorov": [vp, i32],
+        "tsk_set_base_flow": [vp, P(f64), P(f64), P(f64), P(f64)],
+        "tsk_state_dim": [vp, P(i64), P(i32), P(i32)],
+        "tsk_from_physical": [vp, vp, vp],
+        "tsk_to_physical": [vp, vp, vp],
+        "tsk_apply": [vp, vp, vp],
+        "tsk_arnoldi": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), P(f64), vp, P(ArnoldiInfo)],
+        "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
+        "tsk_last_basis": [vp, P(vp), P(i64)],
+        "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
+        "tsk_normal_fill": [vp, i64, u64, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.tsk_destroy.argtypes = [vp]
+    lib.tsk_destroy.restype = None
+    lib.tsk_status_str.argtypes = [C.c_int]
+    lib.tsk_status_str.restype = C.c_char_p
+    lib.tsk_last_error.argtypes = []
+    lib.tsk_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the binding expects the library to export (all of include/tsk.h)."""
+    return ["tsk_create_cgle1d", "tsk_set_params_cgle", "tsk_create_kolmo2d", "tsk_set_params_kolmo",
+            "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_state_dim",
+            "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_last_hessenberg",
+            "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
+            "tsk_last_error"]
+
+
+def _check(st, allow_positive=True):
+    if st < 0 or (st > 0 and not allow_positive):
+        lib = load()
+        raise TskError(st, lib.tsk_last_error().decode())
+    return st
+
+
+def _stream(stream=None):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _need(t, numel, dtype, what):
+    """Host-side check that a device buffer has the size and type the kernels
+    assume (the library itself only sees raw pointers)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a CUDA/HIP tensor")
+    if t.dtype != dtype or t.numel() != numel or not t.is_contiguous():
+        raise ValueError(f"{what}: expected {numel} contiguous {dtype}, got {tuple(t.shape)} {t.dtype}")
+
+
+def _dbl(arr):
+    import numpy as np
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Op:
+    """Owning wrapper of a tsk_op handle."""
+
+    def __init__(self, handle, kind):
+        self.h = handle
+        self.kind = kind
+        n, c, b = C.c_int64(), C.c_int(), C.c_int()
+        _check(load().tsk_state_dim(self.h, C.byref(n), C.byref(c), C.byref(b)))
+        self.n, self.is_complex, self.elem_bytes = n.value, bool(c.value), b.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tsk_destroy(self.h)
+            self.h = None
+
+    @property
+    def state_dtype(self):
+        if self.is_complex:
+            return torch.complex128
+        return torch.float64 if self.elem_bytes == 8 else torch.float32
+
+    def new_state(self, device="cuda"):
+        return torch.zeros(self.n, dtype=self.state_dtype, device=device)
+
+
+# ---- same-named wrappers of the C entry points ---------------------------------------------
+def create_cgle1d(n=256, half_width=50.0, stream=None):
+    h = C.c_void_p()
+    _check(load().tsk_create_cgle1d(C.byref(h), n, half_width, _stream(stream)))
+    return Op(h, "cgle1d")
+
+
+def set_params_cgle(op, U, c_u, c_d, mu0, mu2, dt, T):
+    _check(load().tsk_set_params_cgle(op.h, U, c_u, c_d, mu0, mu2, dt, T))
+
+
+def create_kolmo2d(N, precision=TSK_FP64, stream=None):
+    h = C.c_void_p()
+    _check(load().tsk_create_kolmo2d(C.byref(h), N, precision, _stream(stream)))
+    op = Op(h, "kolmo2d")
+    op.N = N
+    return op
+
+
+def set_params_kolmo(op, Re, alpha, dt, T):
+    _check(load().tsk_set_params_kolmo(op.h, Re, alpha, dt, T))
+
+
+def set_base_parallel(op, U_y, dOmega_dy):
+    a, pa = _dbl(U_y)
+    b, pb = _dbl(dOmega_dy)
+    if a.size != op.N or b.size != op.N:
+        raise ValueError(f"base profiles must have N = {op.N} samples")
+    _check(load().tsk_set_base_parallel(op.h, pa, pb))
+
+
+def set_base_kolmogorov(op, n_forcing=4):
+    _check(load().tsk_set_base_kolmogorov(op.h, n_forcing))
+
+
+def set_base_flow(op, U, V, dOmega_dx, dOmega_dy):
+    arrs = [_dbl(x) for x in (U, V, dOmega_dx, dOmega_dy)]
+    if any(a.size != op.N * op.N for a, _ in arrs):
+        raise ValueError(f"base fields must have N*N = {op.N * op.N} samples")
+    _check(load().tsk_set_base_flow(op.h, *[p for _, p in arrs]))
+
+
+def _phys_spec(op):
+    if op.is_complex:
+        return op.n, torch.complex128
+    return op.N * op.N, op.state_dtype
+
+
+def from_physical(op, phys, state):
+    _need(phys, *_phys_spec(op), "physical field")
+    _need(state, op.n, op.state_dtype, "state")
+    _check(load().tsk_from_physical(op.h, _ptr(phys), _ptr(state)))
+
+
+def to_physical(op, state, phys):
+    _need(phys, *_phys_spec(op), "physical field")
+    _need(state, op.n, op.state_dtype, "state")
+    _check(load().tsk_to_physical(op.h, _ptr(state), _ptr(phys)))
+
+
+def apply(op, x, y):
+    _need(x, op.n, op.state_dtype, "x")
+    _need(y, op.n, op.state_dtype, "y")
+    _check(load().tsk_apply(op.h, _ptr(x), _ptr(y)))
+
+
+def arnoldi(op, m, k, tol, v0=None, seed=0, want_vectors=False):
+    """Run tsk_arnoldi; returns a dict with mu, lam (complex numpy), res, status,
+    n_matvec, n_ritz, n_converged, beta, ms_total and X (Ritz vectors, complex128
+    tensor n x k on the device) when want_vectors."""
+    import numpy as np
+    if v0 is not None:
+        _need(v0, op.n, op.state_dtype, "v0")
+    mu = np.zeros(2 * k)
+    lam = np.zeros(2 * k)
+    res = np.zeros(k)
+    X = None
+    if want_vectors:
+        X = torch.zeros((k, op.n), dtype=torch.complex128, device="cuda")
+    info = ArnoldiInfo()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    st = load().tsk_arnoldi(op.h, m, k, tol, _ptr(v0) if v0 is not None else None, C.c_uint64(seed),
+                            pd(mu), pd(lam), pd(res), _ptr(X) if X is not None else None, C.byref(info))
+    _check(st)
+    nr = info.n_ritz
+    out = dict(mu=(mu[0::2] + 1j * mu[1::2])[:nr], lam=(lam[0::2] + 1j * lam[1::2])[:nr], res=res[:nr],
+               status=st, n_matvec=info.n_matvec, n_ritz=nr, n_converged=info.n_converged,
+               beta=info.beta, ms_total=info.ms_total, ms_apply=info.ms_apply)
+    if X is not None:
+        out["X"] = X[:nr]
+    return out
+
+
+def last_hessenberg(op):
+    import numpy as np
+    m, steps = C.c_int(), C.c_int()
+    _check(load().tsk_last_hessenberg(op.h, None, C.byref(m), C.byref(steps)))
+    buf = np.zeros(2 * (m.value + 1) * m.value)
+    _check(load().tsk_last_hessenberg(op.h, buf.ctypes.data_as(C.POINTER(C.c_double)), C.byref(m),
+                                      C.byref(steps)))
+    H = (buf[0::2] + 1j * buf[1::2]).reshape(m.value, m.value + 1).T  # column-major
+    s = steps.value
+    return H[: s + 1, :s]
+
+
+def last_basis(op):
+    """Device basis of the last run as a tensor view (steps+1 rows)."""
+    p, ld = C.c_void_p(), C.c_int64()
+    _check(load().tsk_last_basis(op.h, C.byref(p), C.byref(ld)))
+    return p.value, ld.value
+
+
+def hessenberg_ritz(H, beta, stream=None):
+    """Device eigensolve of a p x p complex128 Hessenberg tensor (cuda)."""
+    p = H.shape[0]
+    if H.dim() != 2 or H.shape[1] != p or not H.is_cuda:
+        raise ValueError("H must be a square CUDA/HIP tensor")
+    Hc = H.to(torch.complex128).t().contiguous()  # column-major storage
+    mu = torch.zeros(p, dtype=torch.complex128, device=H.device)
+    Y = torch.zeros((p, p), dtype=torch.complex128, device=H.device)
+    res = torch.zeros(p, dtype=torch.float64, device=H.device)
+    _check(load().tsk_hessenberg_ritz(_ptr(Hc), p, p, beta, _ptr(mu), _ptr(Y), _ptr(res), _stream(stream)))
+    return mu, Y.t(), res  # Y rows were columns
+
+
+def normal_fill(count, seed, stream=None):
+    count = int(count)
+    if count < 0:
+        raise ValueError("count must be >= 0")
+    out = torch.zeros(count, dtype=torch.float64, device="cuda")
+    _check(load().tsk_normal_fill(C.c_void_p(out.data_ptr()), count, C.c_uint64(seed), _stream(stream)))
+    return out

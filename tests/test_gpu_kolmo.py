@@ -1,0 +1,173 @@
+"""GPU parity of the linearized Navier-Stokes (Kolmogorov) path against the CPU
+oracle, through the C ABI: physical <-> spectral transforms, the IF-RK4 matvec,
+Arnoldi at small and full size."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from conftest import match_sets
+from oracle.arnoldi import arnoldi as oracle_arnoldi
+from oracle.kolmogorov import Kolmogorov, galerkin_sinusoidal_blocks
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _op(tsk, N, alpha=0.5, Re=20.0, dt=0.005, T=1.0, prec=0, base="kolmogorov", U=None, dO=None):
+    op = tsk.create_kolmo2d(N, prec)
+    tsk.set_params_kolmo(op, Re, alpha, dt, T)
+    if base == "kolmogorov":
+        tsk.set_base_kolmogorov(op, 4)
+        ref = Kolmogorov.kolmogorov(N, alpha, Re, dt, T, 4)
+    else:
+        tsk.set_base_parallel(op, U, dO)
+        Ug = np.repeat(np.asarray(U)[:, None], N, axis=1)
+        Og = np.repeat(np.asarray(dO)[:, None], N, axis=1)
+        z = np.zeros((N, N))
+        ref = Kolmogorov(N, alpha, Re, dt, T, Ug, z, z, Og)
+    return op, ref
+
+
+def _phys(op, N, a):
+    dt = torch.float64 if op.elem_bytes == 8 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda().reshape(-1)
+
+
+def _to_phys(tsk, op, state):
+    out = torch.zeros(op.N * op.N, dtype=state.dtype, device="cuda")
+    tsk.to_physical(op, state, out)
+    return out.double().cpu().numpy().reshape(op.N, op.N)
+
+
+@pytest.mark.parametrize("N", [16, 48, 128, 384, 512])
+def test_transforms_project_like_the_oracle(tsk, N):
+    print(f"kolmo transforms N={N}", flush=True)
+    op, ref = _op(tsk, N)
+    w = W.kolmo_start_physical(N, 2)
+    s = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w), s)
+    back = _to_phys(tsk, op, s)
+    want = ref.project(w)
+    assert np.max(np.abs(back - want)) <= 1e-12 * np.max(np.abs(want))
+    # Euclidean norm of the state = RMS of the projected field
+    assert abs(torch.linalg.norm(s).item() - np.sqrt(np.mean(want ** 2))) <= 1e-12 * np.sqrt(np.mean(want ** 2))
+
+
+@pytest.mark.parametrize("N,T", [(16, 1.0), (48, 1.0), (128, 0.1), (96, 0.05), (384, 0.01), (512, 0.01)])
+def test_matvec_matches_oracle(tsk, N, T):
+    print(f"kolmo matvec N={N} T={T}", flush=True)
+    op, ref = _op(tsk, N, T=T)
+    w = ref.project(W.kolmo_start_physical(N, 3))
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w), x)
+    y = op.new_state()
+    tsk.apply(op, x, y)
+    got = _to_phys(tsk, op, y)
+    want = ref.apply(w)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_matvec_general_parallel_base_matches_oracle(tsk):
+    # a parallel base flow whose vorticity gradient is not proportional to U
+    N = 48
+    y = 2 * np.pi * np.arange(N) / N
+    U = np.sin(y) + 0.5 * np.cos(2 * y)
+    dO = np.sin(y) + 2.0 * np.cos(2 * y)          # -U''
+    print("kolmo matvec general parallel base N=48", flush=True)
+    op, ref = _op(tsk, N, base="parallel", U=U, dO=dO, alpha=0.75, Re=30.0)
+    w = ref.project(W.kolmo_start_physical(N, 4))
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w), x)
+    yv = op.new_state()
+    tsk.apply(op, x, yv)
+    got = _to_phys(tsk, op, yv)
+    want = ref.apply(w)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("N", [32, 48])
+def test_arnoldi_small_grid_same_steps_and_ritz_values(tsk, N):
+    print(f"kolmo arnoldi N={N}", flush=True)
+    op, ref = _op(tsk, N)
+    w0 = W.kolmo_start_physical(N, 0)
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w0), x)
+    r = tsk.arnoldi(op, 40, 6, 1e-8, v0=x)
+    o = oracle_arnoldi(lambda v: ref.apply(v.reshape(N, N)).ravel(), ref.project(w0).ravel(), 40, 6, 1e-8,
+                       T=ref.T)
+    assert r["status"] == o["status"]
+    assert r["n_matvec"] == o["n_matvec"]
+    assert match_sets(r["lam"], o["lam"]) <= 1e-8
+
+
+def test_arnoldi_full_config_fp64_matches_stored_oracle_run(tsk):
+    print("kolmo arnoldi N=128 fp64 m=64 k=6 tol=1e-8", flush=True)
+    c = W.KOLMO_128_FP64
+    g = json.load(open(os.path.join(GOLD, "oracle_kolmo128_fp64.json")))
+    N = c["N"]
+    op, ref = _op(tsk, N)
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, W.kolmo_start_physical(N, 0)), x)
+    r = tsk.arnoldi(op, c["m"], c["k"], c["tol"], v0=x, want_vectors=True)
+    assert r["status"] == 0
+    assert r["n_matvec"] == g["n_matvec"]
+    lam_o = np.array(g["lam_re"]) + 1j * np.array(g["lam_im"])
+    assert match_sets(r["lam"], lam_o) <= 1e-8
+    # and against the dense Galerkin eigenvalues of the operator (time error ~1e-9)
+    blocks = galerkin_sinusoidal_blocks(N, c["alpha"], c["Re"])
+    ev = np.concatenate([np.linalg.eigvals(A) for _, A in blocks.values()])
+    assert match_sets(r["lam"], ev) <= 5e-8
+    # Ritz vectors of the leading (multiplicity-2) pair: residual under the oracle
+    X = r["X"].cpu().numpy()
+    x0 = X[0]
+    for part in (x0.real, x0.imag):
+        if np.linalg.norm(part) < 1e-3:
+            continue
+        t = torch.from_numpy(part / np.linalg.norm(part)).cuda()
+        ph = _to_phys(tsk, op, t)
+        Mx = ref.apply(ph)
+        rel = np.linalg.norm(Mx - r["mu"][0].real * ph) / np.linalg.norm(ph)
+        assert rel <= 1e-7
+
+
+def test_seeded_start_matches_oracle_generator(tsk):
+    from oracle.rng import normal
+    N = 48
+    print("kolmo seeded start N=48", flush=True)
+    op, ref = _op(tsk, N)
+    r = tsk.arnoldi(op, 30, 4, 1e-8, v0=None, seed=5)
+    w0 = normal(N * N, 5).reshape(N, N)
+    o = oracle_arnoldi(lambda v: ref.apply(v.reshape(N, N)).ravel(), ref.project(w0).ravel(), 30, 4, 1e-8,
+                       T=ref.T)
+    assert r["n_matvec"] == o["n_matvec"]
+    assert match_sets(r["lam"], o["lam"]) <= 1e-8
+
+
+def test_exact_eigenvector_start_breaks_down(tsk):
+    N, Re = 48, 20.0
+    print("kolmo breakdown", flush=True)
+    op, ref = _op(tsk, N)
+    x, y = ref.grid()
+    w = np.repeat(np.cos(3 * y)[:, None], N, axis=1)
+    s = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w), s)
+    r = tsk.arnoldi(op, 10, 1, 1e-10, v0=s)
+    assert r["status"] == 2 and r["n_matvec"] == 1
+    assert abs(r["mu"][0] - np.exp(-9 * ref.T / Re)) < 1e-13
+
+
+def test_invalid_sizes_and_parameters(tsk):
+    for N in (100, 1024, 8):
+        with pytest.raises(tsk.TskError) as e:
+            tsk.create_kolmo2d(N, 0)
+        assert e.value.status == tsk.TSK_EINVAL
+    op = tsk.create_kolmo2d(32, 0)
+    with pytest.raises(tsk.TskError):
+        tsk.set_params_kolmo(op, 20.0, 0.5, 0.003, 1.0)
+    with pytest.raises(tsk.TskError) as e:
+        tsk.arnoldi(op, 10, 2, 1e-8)
+    assert e.value.status == tsk.TSK_ESTATE

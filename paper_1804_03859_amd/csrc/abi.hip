@@ -206,7 +206,7 @@ tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta, v
         TSK_HIP(hipMemsetAsync(rr.ptr, 0, sizeof(RitzResult), s));
         TSK_TRY(hess_ritz_launch(static_cast<const double2*>(H_dev), ldh, p, nullptr, beta, Z.as<double2>(),
                                  S.as<double2>(), static_cast<double2*>(mu_dev), static_cast<double2*>(Y_dev),
-                                 static_cast<double*>(res_dev), 0, 0.0, 1.0, nullptr, rr.as<RitzResult>(), s));
+                                 static_cast<double*>(res_dev), 0, 0.0, 0.0, nullptr, rr.as<RitzResult>(), s));
         RitzResult h{};
         TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
         TSK_HIP(hipStreamSynchronize(s));

@@ -6,7 +6,13 @@
 // After each matvec: CGS2 projection and normalisation (krylov.hip), then the
 // device Hessenberg QR and wanted-set test (hessenberg.hip).  The only device to
 // host traffic per step is the 48-byte RitzResult that tells the host whether
-// to stop.  Ritz values are mapped to lambda = log(mu)/T on the device
+// to stop.
+//
+// Overlap: as soon as v_{j+1} exists, the matvec M v_{j+1} is launched on the
+// operator's stream while the Ritz analysis of H_j runs on a side stream (one
+// wavefront, so it barely competes for compute units).  The host waits only for
+// the side stream; if H_j already satisfies the stop test, the speculative
+// matvec is discarded (it is neither counted nor used).  Ritz values are mapped to lambda = log(mu)/T on the device
 // (principal branch, valid when |Im lambda| T < pi/2, the four-samples-per-period
 // rule of Sec. 3.2.1).
 #include <chrono>
@@ -64,9 +70,14 @@ tsk_status arnoldi_t(Operator* op, int m, int k, double tol, const void* v0, uin
     TSK_TRY(W.sel.ensure(gath_off + 5 * size_t(k) * sizeof(double)));
     TSK_TRY(W.rr.ensure(sizeof(RitzResult)));
     if (!W.rr_host) TSK_HIP(hipHostMalloc((void**)&W.rr_host, sizeof(RitzResult) + 64 * sizeof(double), 0));
-    if (!W.ev0) TSK_HIP(hipEventCreate(&W.ev0));
-    if (!W.ev1) TSK_HIP(hipEventCreate(&W.ev1));
-    double ms_apply = 0.0;
+    while (W.ev_apply.size() < size_t(2 * (m + 1))) {
+        hipEvent_t e;
+        TSK_HIP(hipEventCreate(&e));
+        W.ev_apply.push_back(e);
+    }
+    if (!W.ev_cgs) TSK_HIP(hipEventCreateWithFlags(&W.ev_cgs, hipEventDisableTiming));
+    if (!W.side) TSK_HIP(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
+    const hipStream_t s2 = W.side;
     W.m = m;
     W.steps = 0;
     W.ldv = ldv;
@@ -109,11 +120,11 @@ tsk_status arnoldi_t(Operator* op, int m, int k, double tol, const void* v0, uin
     // ---- Arnoldi steps ------------------------------------------------------------------
     tsk_status status = TSK_NOT_CONVERGED;
     int steps = 0;
+    TSK_HIP(hipEventRecord(W.ev_apply[0], s));
+    TSK_TRY(op->apply(V, w));
+    TSK_HIP(hipEventRecord(W.ev_apply[1], s));
     for (int j = 0; j < m; ++j) {
         const int p = j + 1;
-        TSK_HIP(hipEventRecord(W.ev0, s));
-        TSK_TRY(op->apply(V + j * ldv, w));
-        TSK_HIP(hipEventRecord(W.ev1, s));
         double2* Hcol = H + size_t(m + 1) * j;
         launch_dot<TS>(V, ldv, p, w, n, W.partial.as<double2>(), W.pnrm.as<double>(), s);
         launch_reduce(W.partial.as<double2>(), nblk, p, W.h.as<double2>(), Hcol, 1, W.pnrm.as<double>(), scal, 1, s);
@@ -124,15 +135,21 @@ tsk_status arnoldi_t(Operator* op, int m, int k, double tol, const void* v0, uin
                           W.partial.as<double2>(), W.pnrm.as<double>(), s);
         launch_finalize(W.pnrm.as<double>(), nblk, scal, 1, Hcol + p, scal + 2, rr, s);
         launch_scale<TS>(W.w64.ptr, scal + 2, V + (j + 1) * ldv, n, s);
+        TSK_HIP(hipEventRecord(W.ev_cgs, s));
+        // speculative matvec of the next step
+        if (j + 1 < m) {
+            TSK_HIP(hipEventRecord(W.ev_apply[2 * (j + 1)], s));
+            TSK_TRY(op->apply(V + (j + 1) * ldv, w));
+            TSK_HIP(hipEventRecord(W.ev_apply[2 * (j + 1) + 1], s));
+        }
+        // Ritz analysis of H_j on the side stream
+        TSK_HIP(hipStreamWaitEvent(s2, W.ev_cgs, 0));
         const int kk = k < p ? k : p;
         TSK_TRY(hess_ritz_launch(H, m + 1, p, scal + 2, 0.0, W.eigZ.as<double2>(), W.eigS.as<double2>(),
                                  W.eigMu.as<double2>(), W.eigY.as<double2>(), W.eigRes.as<double>(), kk, tol,
-                                 op->T, W.sel.as<int>(), rr, s));
-        TSK_HIP(hipMemcpyAsync(rrh, rr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
-        TSK_HIP(hipStreamSynchronize(s));
-        float ms_step = 0.0f;
-        TSK_HIP(hipEventElapsedTime(&ms_step, W.ev0, W.ev1));
-        ms_apply += ms_step;
+                                 op->kind == StateKind::Real32 ? kDupRelFp32 : 0.0, W.sel.as<int>(), rr, s2));
+        TSK_HIP(hipMemcpyAsync(rrh, rr, sizeof(RitzResult), hipMemcpyDeviceToHost, s2));
+        TSK_HIP(hipStreamSynchronize(s2));
         steps = p;
         W.steps = p;
         if (rrh->nonfinite) return fail(TSK_ENONFINITE, "non-finite matvec output or norm at step " + std::to_string(p));
@@ -142,11 +159,21 @@ tsk_status arnoldi_t(Operator* op, int m, int k, double tol, const void* v0, uin
     }
 
     // ---- outputs ---------------------------------------------------------------------------
+    TSK_HIP(hipStreamSynchronize(s));  // drains a discarded speculative matvec
+    double ms_apply = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        float ms = 0.0f;
+        TSK_HIP(hipEventElapsedTime(&ms, W.ev_apply[2 * j], W.ev_apply[2 * j + 1]));
+        ms_apply += ms;
+    }
     const int nsel = rrh->nsel;
     double* gath = reinterpret_cast<double*>(static_cast<char*>(W.sel.ptr) + gath_off);
     hipLaunchKernelGGL(k_gather_ritz, dim3(1), dim3(128), 0, s, W.eigMu.as<double2>(), W.eigRes.as<double>(),
                        W.sel.as<int>(), nsel, op->T, gath);
     TSK_HIP(hipGetLastError());
+    if (ritz && nsel > 0)
+        TSK_TRY(ritz_coords_launch(H, m + 1, steps, W.eigMu.as<double2>(), W.sel.as<int>(), nsel,
+                                   W.eigY.as<double2>(), s));
     if (ritz && nsel > 0)
         launch_ritz_vectors<TS>(V, ldv, steps, W.eigY.as<double2>(), W.sel.as<int>(), nsel,
                                 static_cast<double2*>(ritz), n, s);

@@ -1,0 +1,115 @@
+// Single-wavefront complex FFT of length N whose first and last passes work
+// on registers, for the column time stepper.
+//
+// Plan: N = RE * (middle radices) * RE with the same "edge" radix RE = 8 (or 4)
+// for the first and the last Stockham pass.  Lane-owned butterfly j
+// (0 <= j < NB = N/RE) of the first pass reads positions j + r NB; the last
+// pass of the same plan writes its butterfly j to exactly those positions.  So a
+// lane that keeps the data of "its" positions in registers can (i) feed the first
+// pass without an LDS read, (ii) take the last pass's outputs without an LDS
+// write, and (iii) chain an inverse transform, a pointwise product and a
+// forward transform with LDS traffic only inside each transform
+// (1 + number-of-middle-passes round trips per transform).
+//
+// LDS buffers use a padded index pad(i) = i + i/8, which spreads the stride-R
+// writes of the first pass over all banks.
+#pragma once
+
+#include "fft.hpp"
+
+namespace tsk {
+
+__host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
+template <int N> constexpr int padded_len() { return N + N / 8 + 1; }
+
+template <int N> struct ColPlan {
+    static constexpr int RE = (N % 64 == 0) ? 8 : 4;
+    static constexpr int MID = N / (RE * RE);
+    static constexpr int NMID = MID > 1 ? fft_num_passes(MID) : 0;
+    static constexpr int NB = N / RE;                 // butterflies of an edge pass
+    static constexpr int NBL = (NB + kWave - 1) / kWave;  // per lane
+    static_assert(RE * RE * MID == N, "unsupported length");
+};
+
+// One middle Stockham pass (LDS -> LDS, padded), radix R, stride NS.
+template <int N, int R, int NS, int SIGN, typename C>
+__device__ inline void col_mid_pass(const C* __restrict__ in, C* __restrict__ out, const C* __restrict__ tw,
+                                    int lane) {
+    constexpr int NB = N / R;
+    constexpr int TS = N / (NS * R);
+    for (int j = lane; j < NB; j += kWave) {
+        const int k = j % NS;
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            C x = in[pad8(j + r * NB)];
+            if (r > 0) {
+                C w = tw[k * r * TS];
+                if constexpr (SIGN > 0) w.y = -w.y;
+                x = cmul(x, w);
+            }
+            v[r] = x;
+        }
+        dft<R, SIGN>(v);
+        const int o = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[pad8(o + r * NS)] = v[r];
+    }
+}
+
+template <int N, int P, int NS, int SIGN, typename C>
+__device__ inline C* col_mid_passes(C* a, C* b, const C* tw, int lane) {
+    using PL = ColPlan<N>;
+    if constexpr (P >= PL::NMID) {
+        return a;
+    } else {
+        constexpr int R = fft_radix(PL::MID, P);
+        col_mid_pass<N, R, NS, SIGN>(a, b, tw, lane);
+        __syncthreads();
+        return col_mid_passes<N, P + 1, NS * R, SIGN>(b, a, tw, lane);
+    }
+}
+
+// Whole transform: v[b][r] holds position j + r NB (j = lane + 64 b) on entry
+// and on exit.  The first pass writes `a`; returns nothing (result in v).
+// Uses a and b as LDS scratch.
+template <int N, int SIGN, typename C>
+__device__ inline void col_fft(C (&v)[ColPlan<N>::NBL][ColPlan<N>::RE], C* a, C* b, const C* tw, int lane) {
+    using PL = ColPlan<N>;
+    constexpr int RE = PL::RE, NB = PL::NB;
+    // first pass (stride 1, no twiddles) from registers
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+            dft<RE, SIGN>(v[q]);
+#pragma unroll
+            for (int r = 0; r < RE; ++r) a[pad8(j * RE + r)] = v[q][r];
+        }
+    }
+    __syncthreads();
+    const C* src = col_mid_passes<N, 0, RE, SIGN>(a, b, tw, lane);
+    // last pass (stride NB) into registers
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+#pragma unroll
+            for (int r = 0; r < RE; ++r) {
+                C x = src[pad8(j + r * NB)];
+                if (r > 0) {
+                    C w = tw[j * r];
+                    if constexpr (SIGN > 0) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[q][r] = x;
+            }
+            dft<RE, SIGN>(v[q]);
+        }
+    }
+}
+
+// Buffer that col_fft's last pass reads from (the first pass writes `a`).
+template <int N> constexpr bool col_result_in_a() { return (ColPlan<N>::NMID % 2) == 0; }
+
+}  // namespace tsk

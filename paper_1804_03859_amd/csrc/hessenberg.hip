@@ -1,300 +1,428 @@
-// Device-side Ritz analysis of the Arnoldi Hessenberg matrix (one workgroup).
+// Device-side Ritz analysis of the Arnoldi Hessenberg matrix (one wavefront).
 //
 // Ritz pairs (mu_H, y) of H_p give the approximations (mu, V_p y) of the
 // eigenpairs of M (Sec. 3.2.1, eq. "m-step Arnoldi" and the Ritz relation that
-// follows it); each pair is judged by |beta e_p^T y| (Sec. 3.2.2, eq. "Krylov
-// convergence").  The eigensolver is the shifted QR algorithm on the Hessenberg
-// matrix in complex arithmetic (Francis 1961; Golub & Van Loan, "Matrix
-// Computations", Sec. 7.5): Wilkinson shift from the trailing 2x2 block,
-// exceptional shifts every tenth iteration, deflation on negligible subdiagonal
-// entries, Givens rotations accumulated into Z so that H = Z T Z^H with T upper
-// triangular.  Eigenvectors of T by back substitution (swept column by column
-// so the whole workgroup works on all eigenvectors at once), y = Z z, unit
-// 2-norm.  A real H (real operators) is treated as complex; its conjugate
-// pairs come out to rounding.
+// follows it); each pair is judged by |beta e_p^T y| with ||y|| = 1 (Sec. 3.2.2,
+// eq. "Krylov convergence").  The eigensolver is the shifted QR algorithm on the
+// Hessenberg matrix in complex arithmetic (Francis 1961; Golub & Van Loan,
+// "Matrix Computations", Sec. 7.5): Wilkinson shift from the trailing 2x2
+// block, an exceptional shift every tenth iteration, deflation on negligible
+// subdiagonal entries, Givens rotations accumulated into Z so that
+// H = Z T Z^H with T upper triangular.  A real H (real operators) is treated as
+// complex; its conjugate pairs come out to rounding.
 //
-// The wanted set follows the stop rule documented with tsk_arnoldi: sort by
-// |mu| descending (ties: larger arg mu first), accept converged values, skip an
-// unconverged value that lies within its residual of a converged or an already
-// accepted value, accept the rest; done when the first k accepted are converged.
+// Wavefront design.  The whole solve runs in one 64-lane wavefront, so every
+// wait is just the LDS latency of one wave.  T (p x p complex128, row-major)
+// sits in LDS.  The deflation test of all subdiagonal entries is one ballot.
+// Every lane evaluates the shift and the rotation of the current bulge position
+// itself from broadcast LDS reads.  The similarity G T G^H of one rotation
+// touches two rows and two columns whose only overlap is a 2x2 block, so the
+// block, the rest of the rows and the rest of the columns are updated in a
+// single phase: one wait per rotation.  For the Arnoldi stop test only the
+// last row of Z (H = Z T Z^H) is tracked: with z_i the eigenvectors of T (back
+// substitution, one eigenvector per lane, no synchronisation) and Z unitary,
+// the residual of Ritz pair i is beta |(last row of Z) z_i| / ||z_i||.  The
+// unit Ritz coordinates of the wanted pairs are then computed once, at the end
+// of the run, by inverse iteration on H (k_ritz_coords).  The standalone entry
+// point accumulates all of Z instead (rotations recorded per sweep and applied
+// to Z off the critical path) and forms every eigenvector.
 //
-// Layout: T (p x p complex128) in LDS, row-major T[r * p + c]; Z, the
-// eigenvector sweep and Y in global scratch, column-major [col * p + row].
+// Wanted set (stop rule documented with tsk_arnoldi): sort by |mu| descending
+// (ties: larger arg mu first), accept converged values, skip an unconverged
+// value that lies within its residual of a converged or an already accepted
+// value, accept the rest; done when the first k accepted are converged.  With
+// dup_rel > 0 (FP32 states) values closer than dup_rel |mu| to an accepted or
+// converged one also count as copies of it: FP32 rounding splits a multiple
+// eigenvalue into a cluster of that width, each member of which converges.
 #include "ops.hpp"
 
 namespace tsk {
 
 namespace {
 
-constexpr int kHT = 256;  // threads of the eigensolver workgroup
+constexpr int kHT = 64;  // one wavefront
 constexpr double kEps = 2.220446049250313e-16;
 
 __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
-// Givens rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0], c real.
+// Givens rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0], c real:
+// c = |x| / rho, s = (x/|x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2).  The
+// rotation sits on the critical path of the bulge chase, so it uses two square
+// roots and one division (no hypot: entries of H are far from overflow).
 __device__ inline void givens(double2 x, double2 y, double& c, double2& s) {
-    double ax = cabs(x), ay = cabs(y);
-    if (ay == 0.0) { c = 1.0; s = cmk<double2>(0.0, 0.0); return; }
-    if (ax == 0.0) {  // swap rows: G = [[0, conj(y)/|y|], [-(y/|y|), 0]]
+    const double nx = x.x * x.x + x.y * x.y, ny = y.x * y.x + y.y * y.y;
+    if (ny == 0.0) { c = 1.0; s = cmk<double2>(0.0, 0.0); return; }
+    if (nx == 0.0) {
         c = 0.0;
-        s = cmk<double2>(y.x / ay, -y.y / ay);
+        const double f = 1.0 / sqrt(ny);
+        s = cmk<double2>(y.x * f, -y.y * f);
         return;
     }
-    double rho = hypot(ax, ay);
-    c = ax / rho;
-    double2 ph = cmk<double2>(x.x / ax, x.y / ax);              // x/|x|
-    s = cscale(cmul(ph, cmk<double2>(y.x, -y.y)), 1.0 / rho);  // (x/|x|) conj(y) / rho
+    const double ax = sqrt(nx), rho = sqrt(nx + ny);
+    const double f = 1.0 / (ax * rho);
+    c = ax * f * ax;  // = |x| / rho
+    s = cscale(cmulc(y, x), f);  // x conj(y) / (|x| rho)
 }
 
+__device__ inline int highest_bit(unsigned long long m) { return 63 - __builtin_clzll(m); }
+
+// z = eigenvector of upper-triangular T for eigenvalue index i (z[i] = 1,
+// z[r > i] = 0), written to zc[0..i]; returns ||z||^2.
+__device__ inline double tri_eigvec(const double2* T, int p, int i, double2* zc) {
+    const double2 lam = T[i * p + i];
+    double smin = kEps * cabs1(lam);
+    if (smin < 1e-290) smin = 1e-290;
+    zc[i] = cmk<double2>(1.0, 0.0);
+    double nrm = 1.0;
+    for (int c = i - 1; c >= 0; --c) {
+        double2 acc = T[c * p + i];
+        for (int r = c + 1; r < i; ++r) acc = cadd(acc, cmul(T[c * p + r], zc[r]));
+        double2 den = csub(T[c * p + c], lam);
+        if (cabs1(den) < smin) den = cmk<double2>(smin, 0.0);
+        double2 z = cdiv(cmk<double2>(-acc.x, -acc.y), den);
+        zc[c] = z;
+        nrm += cabs2(z);
+    }
+    return nrm;
+}
+
+// FULLZ: accumulate all of Z (standalone use, every eigenvector formed);
+// otherwise only the last row of Z is tracked (all the residuals need) and the
+// wanted Ritz coordinates are computed afterwards by inverse iteration.
+template <bool FULLZ>
 __global__ __launch_bounds__(kHT) void k_hess_ritz(const double2* __restrict__ H, int ldh, int p,
                                                   const double* __restrict__ beta_dev, double beta_val,
                                                   double2* __restrict__ Z, double2* __restrict__ S,
                                                   double2* __restrict__ mu, double2* __restrict__ Y,
-                                                  double* __restrict__ res, int k, double tol, double T,
+                                                  double* __restrict__ res, int k, double tol, double dup_rel,
                                                   int* __restrict__ sel, RitzResult* __restrict__ rr) {
-    extern __shared__ double2 Tl[];  // p*p
-    __shared__ double sh_c;
-    __shared__ double2 sh_s;
-    __shared__ int sh_l, sh_ihi, sh_fail, sh_iters;
-    __shared__ double2 sh_shift;
+    extern __shared__ double2 T[];  // p*p
+    __shared__ double rc[kMaxKrylov];
+    __shared__ double2 rs[kMaxKrylov];
+    __shared__ double2 zl[kMaxKrylov];  // last row of Z
     __shared__ int order[kMaxKrylov];
     __shared__ int dupc[kMaxKrylov];
-    const int tid = threadIdx.x;
+    __shared__ double znrm[kMaxKrylov];
+    const int lane = threadIdx.x;
 
-    // ---- load H_p (Hessenberg part only), Z = I --------------------------------
-    for (int e = tid; e < p * p; e += kHT) {
+    for (int e = lane; e < p * p; e += kHT) {
         int r = e / p, c = e % p;
-        Tl[e] = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
-        Z[c * p + r] = cmk<double2>(r == c ? 1.0 : 0.0, 0.0);
+        T[e] = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
     }
-    if (tid == 0) { sh_ihi = p - 1; sh_fail = 0; sh_iters = 0; }
+    for (int c = lane; c < p; c += kHT) zl[c] = cmk<double2>(c == p - 1 ? 1.0 : 0.0, 0.0);
+    if constexpr (FULLZ) {
+        for (int r = lane; r < p; r += kHT)
+            for (int c = 0; c < p; ++c) Z[c * p + r] = cmk<double2>(r == c ? 1.0 : 0.0, 0.0);
+    }
     __syncthreads();
 
-    // ---- shifted QR iteration ----------------------------------------------------
-    int its = 0;           // iterations on the current eigenvalue (uniform)
+    // ---- shifted QR iteration -------------------------------------------------------
+    int ihi = p - 1, its = 0, total = 0, failed = 0;
     const int itmax = 30 * (p > 10 ? p : 10);
-    while (true) {
-        if (tid == 0) {
-            int ihi = sh_ihi;
-            int l = ihi;
-            // deflation scan
-            while (l > 0) {
-                double2 sub = Tl[l * p + (l - 1)];
-                double tst = cabs1(Tl[(l - 1) * p + (l - 1)]) + cabs1(Tl[l * p + l]);
+    while (ihi > 0) {
+        // deflation: largest l <= ihi with a negligible T[l][l-1] (else 0)
+        bool s0 = false, s1 = false;
+        {
+            int i = lane + 1;
+            if (i <= ihi) {
+                double tst = cabs1(T[(i - 1) * p + (i - 1)]) + cabs1(T[i * p + i]);
                 if (tst == 0.0) tst = 1.0;
-                if (cabs1(sub) <= kEps * tst) { Tl[l * p + (l - 1)] = cmk<double2>(0.0, 0.0); break; }
-                --l;
+                s0 = cabs1(T[i * p + (i - 1)]) <= kEps * tst;
             }
-            sh_l = l;
-            if (l < ihi) {
-                // shift
-                double2 a = Tl[(ihi - 1) * p + (ihi - 1)], b = Tl[(ihi - 1) * p + ihi];
-                double2 c2 = Tl[ihi * p + (ihi - 1)], d = Tl[ihi * p + ihi];
-                double2 sft;
-                if ((its + 1) % 10 == 0) {
-                    // exceptional shift
-                    double ex = 0.75 * fabs(c2.x) + fabs(d.x);
-                    sft = cmk<double2>(d.x + ex, d.y);
-                } else {
-                    double2 half = cscale(csub(a, d), 0.5);
-                    double2 disc = csqrt(cadd(cmul(half, half), cmul(b, c2)));
-                    double2 mid = cscale(cadd(a, d), 0.5);
-                    double2 l1 = cadd(mid, disc), l2 = csub(mid, disc);
-                    sft = (cabs(csub(l1, d)) <= cabs(csub(l2, d))) ? l1 : l2;
-                }
-                sh_shift = sft;
-                double2 x = csub(Tl[l * p + l], sft);
-                double2 y = Tl[(l + 1) * p + l];
-                double c;
-                double2 s;
-                givens(x, y, c, s);
-                sh_c = c;
-                sh_s = s;
+            i = lane + 65;
+            if (i <= ihi) {
+                double tst = cabs1(T[(i - 1) * p + (i - 1)]) + cabs1(T[i * p + i]);
+                if (tst == 0.0) tst = 1.0;
+                s1 = cabs1(T[i * p + (i - 1)]) <= kEps * tst;
             }
-            sh_iters = sh_iters + (l < ihi ? 1 : 0);
         }
+        unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
+        int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
         __syncthreads();
-        const int ihi = sh_ihi, l = sh_l;
-        if (ihi <= 0) break;
-        if (l == ihi) {  // eigenvalue T[ihi][ihi] converged
-            __syncthreads();
-            if (tid == 0) sh_ihi = ihi - 1;
+        if (l > 0 && lane == 0) T[l * p + (l - 1)] = cmk<double2>(0.0, 0.0);
+        __syncthreads();
+        if (l == ihi) {
+            --ihi;
             its = 0;
-            __syncthreads();
             continue;
         }
-        if (sh_iters > itmax) {
-            if (tid == 0) sh_fail = 1;
-            __syncthreads();
-            break;
-        }
+        if (++total > itmax) { failed = 1; break; }
         ++its;
-        // bulge chase k = l .. ihi-1
+        // shift (every lane computes it)
+        double2 sft;
+        {
+            double2 a = T[(ihi - 1) * p + (ihi - 1)], b = T[(ihi - 1) * p + ihi];
+            double2 c2 = T[ihi * p + (ihi - 1)], d = T[ihi * p + ihi];
+            if (its % 10 == 0) {
+                double ex = 0.75 * fabs(c2.x) + fabs(d.x);
+                sft = cmk<double2>(d.x + ex, d.y);
+            } else {
+                double2 half = cscale(csub(a, d), 0.5);
+                double2 disc = csqrt(cadd(cmul(half, half), cmul(b, c2)));
+                double2 mid = cscale(cadd(a, d), 0.5);
+                double2 l1 = cadd(mid, disc), l2 = csub(mid, disc);
+                sft = (cabs(csub(l1, d)) <= cabs(csub(l2, d))) ? l1 : l2;
+            }
+        }
+        // Bulge chase kk = l .. ihi-1.  The similarity G T G^H touches rows
+        // {kk, kk+1} (left factor) and columns {kk, kk+1} (right factor); apart
+        // from their 2x2 intersection the two sets are disjoint, so one phase
+        // (one wait) per rotation updates: the 2x2 block, the rest of the two
+        // rows (columns kk-1 and kk+2..p-1) and the rest of the two columns
+        // (rows 0..kk-1 and kk+2).
         for (int kk = l; kk < ihi; ++kk) {
-            if (kk > l) {
-                if (tid == 0) {
-                    double c;
-                    double2 s;
-                    givens(Tl[kk * p + (kk - 1)], Tl[(kk + 1) * p + (kk - 1)], c, s);
-                    sh_c = c;
-                    sh_s = s;
-                }
-                __syncthreads();
+            double2 x, y;
+            if (kk == l) {
+                x = csub(T[l * p + l], sft);
+                y = T[(l + 1) * p + l];
+            } else {
+                x = T[kk * p + (kk - 1)];
+                y = T[(kk + 1) * p + (kk - 1)];
             }
-            const double c = sh_c;
-            const double2 s = sh_s;
+            double c;
+            double2 s;
+            givens(x, y, c, s);
             const double2 sc = cconj(s);
-            // rows kk, kk+1: T <- G T on columns [max(kk-1, l), p)
-            const int c0 = kk > l ? kk - 1 : l;
-            for (int col = c0 + tid; col < p; col += kHT) {
-                double2 a = Tl[kk * p + col], b = Tl[(kk + 1) * p + col];
-                Tl[kk * p + col] = cadd(cscale(a, c), cmul(s, b));
-                Tl[(kk + 1) * p + col] = csub(cscale(b, c), cmul(sc, a));
+            const int nrow_only = (p - (kk + 2) > 0 ? p - (kk + 2) : 0);  // columns kk+2..p-1
+            const int ncol_only = kk + (kk + 2 <= ihi ? 1 : 0);            // rows 0..kk-1, kk+2
+            const int items = 1 + nrow_only + ncol_only;
+            for (int t = lane; t < items; t += kHT) {
+                if (t == 0) {
+                    double2 a = T[kk * p + kk], b = T[kk * p + kk + 1];
+                    double2 d = T[(kk + 1) * p + kk], e = T[(kk + 1) * p + kk + 1];
+                    double2 a1 = cadd(cscale(a, c), cmul(s, d)), b1 = cadd(cscale(b, c), cmul(s, e));
+                    double2 d1 = csub(cscale(d, c), cmul(sc, a)), e1 = csub(cscale(e, c), cmul(sc, b));
+                    T[kk * p + kk] = cadd(cscale(a1, c), cmul(sc, b1));
+                    T[kk * p + kk + 1] = csub(cscale(b1, c), cmul(s, a1));
+                    T[(kk + 1) * p + kk] = cadd(cscale(d1, c), cmul(sc, e1));
+                    T[(kk + 1) * p + kk + 1] = csub(cscale(e1, c), cmul(s, d1));
+                    if (kk > l) {  // the annihilated bulge column
+                        T[kk * p + (kk - 1)] = cadd(cscale(x, c), cmul(s, y));
+                        T[(kk + 1) * p + (kk - 1)] = cmk<double2>(0.0, 0.0);
+                    }
+                    double2 za = zl[kk], zb = zl[kk + 1];
+                    zl[kk] = cadd(cscale(za, c), cmul(sc, zb));
+                    zl[kk + 1] = csub(cscale(zb, c), cmul(s, za));
+                    rc[kk - l] = c;
+                    rs[kk - l] = s;
+                } else if (t <= nrow_only) {
+                    const int col = kk + 1 + t;  // kk+2 ..
+                    double2 a = T[kk * p + col], b = T[(kk + 1) * p + col];
+                    T[kk * p + col] = cadd(cscale(a, c), cmul(s, b));
+                    T[(kk + 1) * p + col] = csub(cscale(b, c), cmul(sc, a));
+                } else {
+                    const int q = t - 1 - nrow_only;
+                    const int row = q < kk ? q : kk + 2;
+                    double2 a = T[row * p + kk], b = T[row * p + kk + 1];
+                    T[row * p + kk] = cadd(cscale(a, c), cmul(sc, b));
+                    T[row * p + kk + 1] = csub(cscale(b, c), cmul(s, a));
+                }
             }
             __syncthreads();
-            if (kk > l && tid == 0) Tl[(kk + 1) * p + (kk - 1)] = cmk<double2>(0.0, 0.0);
-            // columns kk, kk+1: T <- T G^H on rows [0, min(kk+2, ihi)], Z <- Z G^H
-            const int r1 = (kk + 2 < ihi ? kk + 2 : ihi);
-            for (int row = tid; row <= r1; row += kHT) {
-                double2 a = Tl[row * p + kk], b = Tl[row * p + kk + 1];
-                Tl[row * p + kk] = cadd(cscale(a, c), cmul(sc, b));
-                Tl[row * p + kk + 1] = csub(cscale(b, c), cmul(s, a));
-            }
-            for (int row = tid; row < p; row += kHT) {
-                double2 a = Z[kk * p + row], b = Z[(kk + 1) * p + row];
-                Z[kk * p + row] = cadd(cscale(a, c), cmul(sc, b));
-                Z[(kk + 1) * p + row] = csub(cscale(b, c), cmul(s, a));
+        }
+        if constexpr (FULLZ) {
+            // Z <- Z G^H for the sweep's rotations, one row of Z per lane
+            for (int row = lane; row < p; row += kHT) {
+                double2 carry = Z[l * p + row];
+                for (int kk = l; kk < ihi; ++kk) {
+                    const double c = rc[kk - l];
+                    const double2 s = rs[kk - l];
+                    double2 b = Z[(kk + 1) * p + row];
+                    Z[kk * p + row] = cadd(cscale(carry, c), cmul(cconj(s), b));
+                    carry = csub(cscale(b, c), cmul(s, carry));
+                }
+                Z[ihi * p + row] = carry;
             }
             __syncthreads();
         }
     }
-    const int failed = sh_fail;
 
-    // ---- eigenvalues ----------------------------------------------------------------
-    for (int i = tid; i < p; i += kHT) mu[i] = Tl[i * p + i];
-
-    // ---- eigenvectors of T: column sweep, S[i*p + r] holds the partial sums of
-    //      vector i, the solution is written back into S.
-    for (int e = tid; e < p * p; e += kHT) {
-        int i = e / p, r = e % p;
-        S[e] = (r < i) ? Tl[r * p + i] : cmk<double2>(r == i ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    for (int c = p - 1; c >= 1; --c) {
-        // finalise component c of every vector i > c
-        for (int i = c + 1 + tid; i < p; i += kHT) {
-            double2 lam = Tl[i * p + i];
-            double2 den = csub(Tl[c * p + c], lam);
-            double smin = kEps * cabs1(lam);
-            if (smin < 1e-290) smin = 1e-290;
-            if (cabs1(den) < smin) den = cmk<double2>(smin, 0.0);
-            double2 z = cdiv(cmk<double2>(-S[i * p + c].x, -S[i * p + c].y), den);
-            S[i * p + c] = z;
-        }
-        __syncthreads();
-        // accumulate T[r][c] * z_i[c] into rows r < c of every vector i > c
-        const int ni = p - 1 - c;  // vectors i = c+1 .. p-1
-        for (int e = tid; e < ni * c; e += kHT) {
-            int i = c + 1 + e / c, r = e % c;
-            S[i * p + r] = cadd(S[i * p + r], cmul(Tl[r * p + c], S[i * p + c]));
-        }
-        __syncthreads();
-    }
-    // component 0 of every vector i >= 1
-    for (int i = 1 + tid; i < p; i += kHT) {
-        double2 lam = Tl[i * p + i];
-        double2 den = csub(Tl[0], lam);
-        double smin = kEps * cabs1(lam);
-        if (smin < 1e-290) smin = 1e-290;
-        if (cabs1(den) < smin) den = cmk<double2>(smin, 0.0);
-        S[i * p] = cdiv(cmk<double2>(-S[i * p].x, -S[i * p].y), den);
-    }
-    __syncthreads();
-
-    // ---- Y = Z z (z_i upper: components 0..i) -------------------------------------------
-    for (int e = tid; e < p * p; e += kHT) {
-        int i = e / p, r = e % p;
-        double2 acc = cmk<double2>(0.0, 0.0);
-        for (int c = 0; c <= i; ++c) acc = cadd(acc, cmul(Z[c * p + r], S[i * p + c]));
-        Y[e] = acc;
-    }
-    __syncthreads();
+    // ---- Ritz values and residuals ---------------------------------------------------------
     const double beta = beta_dev ? beta_dev[0] : beta_val;
-    for (int i = tid; i < p; i += kHT) {
-        double nrm = 0.0;
-        for (int r = 0; r < p; ++r) nrm += cabs2(Y[i * p + r]);
-        nrm = sqrt(nrm);
-        double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int r = 0; r < p; ++r) Y[i * p + r] = cscale(Y[i * p + r], inv);
-        res[i] = fabs(beta) * cabs(Y[i * p + (p - 1)]);
+    for (int i = lane; i < p; i += kHT) {
+        mu[i] = T[i * p + i];
+        double2* zc = S + (size_t)i * p;
+        double n2 = tri_eigvec(T, p, i, zc);
+        double2 last = cmk<double2>(0.0, 0.0);
+        for (int c = 0; c <= i; ++c) last = cadd(last, cmul(zl[c], zc[c]));
+        double nz = sqrt(n2);
+        znrm[i] = nz;
+        res[i] = fabs(beta) * cabs(last) / nz;
     }
     __syncthreads();
-    if (sel == nullptr) {
-        if (tid == 0 && rr) { rr->eig_fail = failed; rr->iters = sh_iters; }
-        return;
-    }
 
-    // ---- wanted set ----------------------------------------------------------------------
-    // rank by (-|mu|, -arg(mu)), ties by index
-    for (int i = tid; i < p; i += kHT) {
-        double mi = cabs(mu[i]), ai = atan2(mu[i].y, mu[i].x);
-        int rank = 0;
-        for (int j = 0; j < p; ++j) {
-            if (j == i) continue;
-            double mj = cabs(mu[j]), aj = atan2(mu[j].y, mu[j].x);
-            bool before = (mj > mi) || (mj == mi && (aj > ai || (aj == ai && j < i)));
-            rank += before ? 1 : 0;
+    if constexpr (FULLZ) {
+        // every eigenvector: Y[:, i] = Z z_i / ||z_i||
+        for (int i = 0; i < p; ++i) {
+            const double2* zc = S + (size_t)i * p;
+            const double inv = 1.0 / znrm[i];
+            for (int r = lane; r < p; r += kHT) {
+                double2 acc = cmk<double2>(0.0, 0.0);
+                for (int c = 0; c <= i; ++c) acc = cadd(acc, cmul(Z[c * p + r], zc[c]));
+                Y[(size_t)i * p + r] = cscale(acc, inv);
+            }
         }
-        order[rank] = i;
-        // an unconverged value within its residual of some converged value
-        int d = 0;
-        if (!(res[i] <= tol)) {
-            for (int j = 0; j < p; ++j)
-                if (j != i && res[j] <= tol && cabs(csub(mu[i], mu[j])) <= res[i]) d = 1;
+        if (lane == 0 && rr) { rr->eig_fail = failed; rr->iters = total; }
+        return;
+    } else {
+        // ---- wanted set ------------------------------------------------------------------------
+        for (int i = lane; i < p; i += kHT) {
+            double mi = cabs(mu[i]), ai = atan2(mu[i].y, mu[i].x);
+            int rank = 0;
+            for (int j = 0; j < p; ++j) {
+                if (j == i) continue;
+                double mj = cabs(mu[j]), aj = atan2(mu[j].y, mu[j].x);
+                bool before = (mj > mi) || (mj == mi && (aj > ai || (aj == ai && j < i)));
+                rank += before ? 1 : 0;
+            }
+            order[rank] = i;
+            int d = 0;
+            if (!(res[i] <= tol)) {
+                const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
+                for (int j = 0; j < p; ++j)
+                    if (j != i && res[j] <= tol && cabs(csub(mu[i], mu[j])) <= rad) d = 1;
+            }
+            dupc[i] = d;
         }
-        dupc[i] = d;
+        __syncthreads();
+        if (lane == 0) {
+            int nsel = 0, nconv = 0;
+            for (int t = 0; t < p && nsel < k; ++t) {
+                int i = order[t];
+                bool conv = res[i] <= tol;
+                bool take;
+                if (conv) {
+                    // a converged copy of an accepted value (only with dup_rel > 0)
+                    take = true;
+                    const double rad = dup_rel * cabs(mu[i]);
+                    for (int a = 0; a < nsel && take; ++a)
+                        if (cabs(csub(mu[i], mu[sel[a]])) < rad) take = false;
+                } else {
+                    take = !dupc[i];
+                    const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
+                    for (int a = 0; a < nsel && take; ++a)
+                        if (cabs(csub(mu[i], mu[sel[a]])) <= rad) take = false;
+                }
+                if (take) {
+                    sel[nsel++] = i;
+                    nconv += conv ? 1 : 0;
+                }
+            }
+            rr->nsel = nsel;
+            rr->nconv = nconv;
+            rr->done = (nsel >= k && nconv == nsel) ? 1 : 0;
+            rr->eig_fail = failed;
+            rr->iters = total;
+        }
+    }
+}
+
+// Unit Ritz coordinates of the wanted pairs by inverse iteration on H_p (one
+// wavefront per pair): solve (H - mu I) y = b with the Hessenberg LU (partial
+// pivoting between the two candidate rows of each column), twice, starting from
+// b = (1, ..., 1); normalise to ||y|| = 1.  Y[s*p + r].
+__global__ __launch_bounds__(kHT) void k_ritz_coords(const double2* __restrict__ H, int ldh, int p,
+                                                    const double2* __restrict__ mu, const int* __restrict__ sel,
+                                                    double2* __restrict__ Y) {
+    extern __shared__ double2 A[];  // p*p, row-major
+    __shared__ double2 b[kMaxKrylov];
+    __shared__ int piv[kMaxKrylov];
+    __shared__ double2 lmul[kMaxKrylov];
+    __shared__ double red[kHT];
+    const int lane = threadIdx.x;
+    const int sidx = blockIdx.x;
+    const double2 m = mu[sel[sidx]];
+    double hn = 0.0;
+    for (int e = lane; e < p * p; e += kHT) {
+        int r = e / p, c = e % p;
+        double2 v = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
+        hn = fmax(hn, cabs1(v));
+        if (r == c) v = csub(v, m);
+        A[e] = v;
+    }
+    red[lane] = hn;
+    for (int r = lane; r < p; r += kHT) b[r] = cmk<double2>(1.0, 0.0);
+    __syncthreads();
+    if (lane == 0) {
+        double t = 0.0;
+        for (int q = 0; q < kHT; ++q) t = fmax(t, red[q]);
+        red[0] = t;
     }
     __syncthreads();
-    if (tid == 0) {
-        int nsel = 0, nconv = 0;
-        for (int t = 0; t < p && nsel < k; ++t) {
-            int i = order[t];
-            bool conv = res[i] <= tol;
-            bool take = conv;
-            if (!conv) {
-                take = !dupc[i];
-                for (int a = 0; a < nsel && take; ++a)
-                    if (cabs(csub(mu[i], mu[sel[a]])) <= res[i]) take = false;
-            }
-            if (take) {
-                sel[nsel++] = i;
-                nconv += conv ? 1 : 0;
-            }
+    const double tiny = kEps * (red[0] > 0.0 ? red[0] : 1.0);
+    // LU with row interchanges j <-> j+1
+    for (int j = 0; j < p - 1; ++j) {
+        double2 a = A[j * p + j], d = A[(j + 1) * p + j];
+        const bool sw = cabs1(d) > cabs1(a);
+        if (sw) { double2 t = a; a = d; d = t; }
+        if (cabs1(a) == 0.0) a = cmk<double2>(tiny, 0.0);
+        const double2 lm = cdiv(d, a);
+        for (int c = j + lane; c < p; c += kHT) {
+            double2 u = A[j * p + c], v = A[(j + 1) * p + c];
+            if (sw) { double2 t = u; u = v; v = t; }
+            if (c == j) u = a;
+            A[j * p + c] = u;
+            A[(j + 1) * p + c] = (c == j) ? cmk<double2>(0.0, 0.0) : csub(v, cmul(lm, u));
         }
-        rr->nsel = nsel;
-        rr->nconv = nconv;
-        rr->done = (nsel >= k && nconv == nsel) ? 1 : 0;
-        rr->eig_fail = failed;
-        rr->iters = sh_iters;
-        (void)T;
+        if (lane == 0) { piv[j] = sw ? 1 : 0; lmul[j] = lm; }
+        __syncthreads();
     }
+    if (lane == 0 && cabs1(A[(p - 1) * p + (p - 1)]) < tiny) A[(p - 1) * p + (p - 1)] = cmk<double2>(tiny, 0.0);
+    __syncthreads();
+    for (int it = 0; it < 2; ++it) {
+        if (lane == 0) {
+            // forward elimination on b, then back substitution (serial, O(p^2))
+            for (int j = 0; j < p - 1; ++j) {
+                if (piv[j]) { double2 t = b[j]; b[j] = b[j + 1]; b[j + 1] = t; }
+                b[j + 1] = csub(b[j + 1], cmul(lmul[j], b[j]));
+            }
+            for (int r = p - 1; r >= 0; --r) {
+                double2 acc = b[r];
+                for (int c = r + 1; c < p; ++c) acc = csub(acc, cmul(A[r * p + c], b[c]));
+                double2 dg = A[r * p + r];
+                if (cabs1(dg) < tiny) dg = cmk<double2>(tiny, 0.0);
+                b[r] = cdiv(acc, dg);
+            }
+            double n2 = 0.0;
+            for (int r = 0; r < p; ++r) n2 += cabs2(b[r]);
+            double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+            for (int r = 0; r < p; ++r) b[r] = cscale(b[r], inv);
+        }
+        __syncthreads();
+    }
+    for (int r = lane; r < p; r += kHT) Y[(size_t)sidx * p + r] = b[r];
 }
 
 }  // namespace
 
 tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta_dev, double beta_val,
                             double2* Z, double2* S, double2* mu, double2* Y, double* res, int k, double tol,
-                            double T, int* sel, RitzResult* rr, hipStream_t s) {
+                            double dup_rel, int* sel, RitzResult* rr, hipStream_t s) {
     if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Hessenberg size must be in [1, 96]");
     size_t lds = size_t(p) * p * sizeof(double2);
     static bool attr_set = false;
     if (!attr_set) {
-        TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(kMaxKrylov * kMaxKrylov * sizeof(double2))));
+        const int mx = int(kMaxKrylov * kMaxKrylov * sizeof(double2));
+        TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz<false>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        TSK_HIP(hipFuncSetAttribute((const void*)k_ritz_coords, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_hess_ritz, dim3(1), dim3(kHT), lds, s, H, ldh, p, beta_dev, beta_val, Z, S, mu, Y,
-                       res, k, tol, T, sel, rr);
+    if (sel == nullptr)
+        hipLaunchKernelGGL(k_hess_ritz<true>, dim3(1), dim3(kHT), lds, s, H, ldh, p, beta_dev, beta_val, Z, S, mu,
+                           Y, res, k, tol, dup_rel, sel, rr);
+    else
+        hipLaunchKernelGGL(k_hess_ritz<false>, dim3(1), dim3(kHT), lds, s, H, ldh, p, beta_dev, beta_val, Z, S,
+                           mu, Y, res, k, tol, dup_rel, sel, rr);
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+tsk_status ritz_coords_launch(const double2* H, int ldh, int p, const double2* mu, const int* sel, int nsel,
+                              double2* Y, hipStream_t s) {
+    if (nsel <= 0) return TSK_OK;
+    size_t lds = size_t(p) * p * sizeof(double2);
+    hipLaunchKernelGGL(k_ritz_coords, dim3(nsel), dim3(kHT), lds, s, H, ldh, p, mu, sel, Y);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }

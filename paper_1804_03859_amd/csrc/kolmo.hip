@@ -13,10 +13,11 @@
 // around the product cancel exactly on the kept modes, so each dealiased kx
 // column evolves on its own.  One 64-lane workgroup owns one column for the
 // whole matvec (all T/dt steps and 4 stages): the column's spectral state, RK
-// accumulator and stage input live in registers, the y-transforms run in LDS
-// (fft.hpp), the product with the base profile is applied in registers between
-// the inverse and forward transforms, and HBM is touched only to read the
-// input column once and to write the output column once.  No grid-wide
+// accumulator and stage input live in registers in the layout of the first and
+// last passes of the y-transforms (colfft.hpp), so the spectral bookkeeping and
+// the product with the base profile never go through LDS; only the interior
+// transform passes do.  HBM is touched only to read the input column once and
+// to write the output column once.  No grid-wide
 // synchronisation is needed, so a matvec is a single launch of M+1 workgroups.
 // When dOmega/dy = c U (true for the Kolmogorov base sin(n y), c = n^2) the two
 // inverse transforms are merged in spectral space by linearity,
@@ -27,6 +28,7 @@
 #include <cmath>
 #include <vector>
 
+#include "colfft.hpp"
 #include "fft.hpp"
 #include "ops.hpp"
 
@@ -46,6 +48,10 @@ template <int N> struct Geo {
 };
 
 // ---- the column time stepper ------------------------------------------------------------
+// Lane-owned positions: j = lane (< NB = N/RE) and slots r < RE hold the
+// y-index / FFT-order wavenumber index pos = j + r NB (colfft.hpp), for the
+// spectral state (jy = pos or pos - N, kept when |jy| <= M) and, after the
+// inverse transform, for the grid values at y = 2 pi pos / N.
 template <typename real, int N, bool PROP>
 __global__ __launch_bounds__(kWave) void k_colstep(const real* __restrict__ xin, real* __restrict__ yout,
                                                    const real* __restrict__ negU, const real* __restrict__ dOdy,
@@ -53,7 +59,9 @@ __global__ __launch_bounds__(kWave) void k_colstep(const real* __restrict__ xin,
                                                    double dt, double cprop, int nsteps) {
     using C = cplx<real>;
     using G = Geo<N>;
-    constexpr int M = G::M, NM = G::NM, RM = G::RM, RY = G::RY;
+    using PL = ColPlan<N>;
+    constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
+    static_assert(PL::NBL == 1, "one edge butterfly per lane");
     const int lane = threadIdx.x;
     const int kx = blockIdx.x;
 
@@ -71,117 +79,95 @@ __global__ __launch_bounds__(kWave) void k_colstep(const real* __restrict__ xin,
         return;
     }
 
-    __shared__ C sA[N], sB[N], sT[N];
-    __shared__ C sC[PROP ? 1 : N], sD[PROP ? 1 : N];
+    constexpr int LP = padded_len<N>();
+    __shared__ C sA[LP], sB[LP], sT[N];
+    __shared__ C sA2[PROP ? 1 : LP], sB2[PROP ? 1 : LP];
     for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
 
     const double kxv = alpha * kx;
-    real E1[RM], Eh[RM], g1[RM], g2[RM];
-    C w[RM], acc[RM], s[RM];
-    int pos[RM];
+    const bool act = lane < NB;
+    real E1[RE], Eh[RE], g1[RE], g2[RE], nu[RE], oy[RE];
+    C w[RE], acc[RE], s[RE];
+    unsigned keep = 0;
     const real* xs = xin + G::seg(kx);
 #pragma unroll
-    for (int r = 0; r < RM; ++r) {
-        const int q = lane + r * kWave;
-        if (q < NM) {
-            const int jy = q - M;
-            const double K2 = kxv * kxv + double(jy) * jy;
-            E1[r] = real(exp(-K2 * dt / Re));
-            Eh[r] = real(exp(-K2 * (0.5 * dt) / Re));
-            g1[r] = PROP ? real(kxv * (1.0 - cprop / K2)) : real(kxv);
-            g2[r] = real(kxv / K2);
-            pos[r] = jy < 0 ? jy + N : jy;
-            w[r] = cmk<C>(xs[2 * q], xs[2 * q + 1]);
-        } else {
-            E1[r] = Eh[r] = g1[r] = g2[r] = real(0);
-            pos[r] = 0;
-            w[r] = cmk<C>(real(0), real(0));
-        }
+    for (int r = 0; r < RE; ++r) {
+        const int pos = lane + r * NB;
+        const int jy = pos <= N / 2 ? pos : pos - N;
+        const bool kp = act && jy >= -M && jy <= M;
+        keep |= kp ? (1u << r) : 0u;
+        const double K2 = kxv * kxv + double(jy) * jy;
+        E1[r] = kp ? real(exp(-K2 * dt / Re)) : real(0);
+        Eh[r] = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
+        g1[r] = kp ? (PROP ? real(kxv * (1.0 - cprop / K2)) : real(kxv)) : real(0);
+        g2[r] = kp ? real(kxv / K2) : real(0);
+        nu[r] = act ? negU[pos] : real(0);
+        oy[r] = (!PROP && act) ? dOdy[pos] : real(0);
+        const int q = jy + M;
+        w[r] = kp ? cmk<C>(xs[2 * q], xs[2 * q + 1]) : cmk<C>(real(0), real(0));
         acc[r] = s[r] = w[r];
-    }
-    real nu[RY], oy[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const int l = lane + r * kWave;
-        nu[r] = l < N ? negU[l] : real(0);
-        oy[r] = (!PROP && l < N) ? dOdy[l] : real(0);
     }
     __syncthreads();
 
     const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
     const real invN = real(1.0 / N);
-    const C zero = cmk<C>(real(0), real(0));
+    C* fwdA = col_result_in_a<N>() ? sB : sA;  // forward transform must not write
+    C* fwdB = col_result_in_a<N>() ? sA : sB;  // the buffer the inverse reads last
 
     for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
-        for (int r = 0; r < RM; ++r) s[r] = w[r];
+        for (int r = 0; r < RE; ++r) s[r] = w[r];
 #pragma unroll 1
         for (int stage = 0; stage < 4; ++stage) {
-            // i kx (...) applied to the stage input, scattered in FFT order
+            C v[1][RE], v2[1][PROP ? 1 : RE];
 #pragma unroll
-            for (int r = 0; r < RM; ++r) {
-                if (lane + r * kWave < NM) {
-                    sA[pos[r]] = cmk<C>(-g1[r] * s[r].y, g1[r] * s[r].x);
-                    if constexpr (!PROP) sC[pos[r]] = cmk<C>(-g2[r] * s[r].y, g2[r] * s[r].x);
+            for (int r = 0; r < RE; ++r) {
+                v[0][r] = cmk<C>(-g1[r] * s[r].y, g1[r] * s[r].x);  // i kx (...) s
+                if constexpr (!PROP) v2[0][r] = cmk<C>(-g2[r] * s[r].y, g2[r] * s[r].x);
+            }
+            col_fft<N, +1>(v, sA, sB, sT, lane);
+            if constexpr (!PROP) col_fft<N, +1>(v2, sA2, sB2, sT, lane);
+            // product with the base profiles at y = pos
+#pragma unroll
+            for (int r = 0; r < RE; ++r) {
+                C p = cmk<C>(nu[r] * v[0][r].x, nu[r] * v[0][r].y);
+                if constexpr (!PROP) {
+                    p.x += oy[r] * v2[0][r].x;
+                    p.y += oy[r] * v2[0][r].y;
+                }
+                v[0][r] = p;
+            }
+            col_fft<N, -1>(v, fwdA, fwdB, sT, lane);
+            // Lawson RK4 bookkeeping on the kept modes (registers only)
+#pragma unroll
+            for (int r = 0; r < RE; ++r) {
+                const real kmask = (keep >> r) & 1u ? invN : real(0);
+                const C nh = cmk<C>(v[0][r].x * kmask, v[0][r].y * kmask);
+                const real e1 = E1[r], eh = Eh[r];
+                if (stage == 0) {
+                    acc[r] = cmk<C>(e1 * (w[r].x + h6 * nh.x), e1 * (w[r].y + h6 * nh.y));
+                    s[r] = cmk<C>(eh * (w[r].x + h2 * nh.x), eh * (w[r].y + h2 * nh.y));
+                } else if (stage == 1) {
+                    acc[r].x += h3 * eh * nh.x;
+                    acc[r].y += h3 * eh * nh.y;
+                    s[r] = cmk<C>(eh * w[r].x + h2 * nh.x, eh * w[r].y + h2 * nh.y);
+                } else if (stage == 2) {
+                    acc[r].x += h3 * eh * nh.x;
+                    acc[r].y += h3 * eh * nh.y;
+                    s[r] = cmk<C>(e1 * w[r].x + hh * eh * nh.x, e1 * w[r].y + hh * eh * nh.y);
+                } else {
+                    w[r] = cmk<C>(acc[r].x + h6 * nh.x, acc[r].y + h6 * nh.y);
                 }
             }
-            for (int t = M + 1 + lane; t < N - M; t += kWave) {
-                sA[t] = zero;
-                if constexpr (!PROP) sC[t] = zero;
-            }
-            __syncthreads();
-            C* F = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
-            C* Gq = nullptr;
-            if constexpr (!PROP) Gq = fft_lds<N, +1, kWave>(sC, sD, sT, lane);
-            // product with the base profiles on the y grid
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const int l = lane + r * kWave;
-                if (l < N) {
-                    C f = F[l];
-                    C p = cmk<C>(nu[r] * f.x, nu[r] * f.y);
-                    if constexpr (!PROP) {
-                        C g = Gq[l];
-                        p.x += oy[r] * g.x;
-                        p.y += oy[r] * g.y;
-                    }
-                    F[l] = p;
-                }
-            }
-            __syncthreads();
-            C* X = fft_lds<N, -1, kWave>(F, F == sA ? sB : sA, sT, lane);
-            // Lawson RK4 bookkeeping on the kept modes
-#pragma unroll
-            for (int r = 0; r < RM; ++r) {
-                if (lane + r * kWave < NM) {
-                    C nh = X[pos[r]];
-                    nh.x *= invN;
-                    nh.y *= invN;
-                    const real e1 = E1[r], eh = Eh[r];
-                    if (stage == 0) {
-                        acc[r] = cmk<C>(e1 * (w[r].x + h6 * nh.x), e1 * (w[r].y + h6 * nh.y));
-                        s[r] = cmk<C>(eh * (w[r].x + h2 * nh.x), eh * (w[r].y + h2 * nh.y));
-                    } else if (stage == 1) {
-                        acc[r].x += h3 * eh * nh.x;
-                        acc[r].y += h3 * eh * nh.y;
-                        s[r] = cmk<C>(eh * w[r].x + h2 * nh.x, eh * w[r].y + h2 * nh.y);
-                    } else if (stage == 2) {
-                        acc[r].x += h3 * eh * nh.x;
-                        acc[r].y += h3 * eh * nh.y;
-                        s[r] = cmk<C>(e1 * w[r].x + hh * eh * nh.x, e1 * w[r].y + hh * eh * nh.y);
-                    } else {
-                        w[r] = cmk<C>(acc[r].x + h6 * nh.x, acc[r].y + h6 * nh.y);
-                    }
-                }
-            }
-            __syncthreads();
         }
     }
     real* ys = yout + G::seg(kx);
 #pragma unroll
-    for (int r = 0; r < RM; ++r) {
-        const int q = lane + r * kWave;
-        if (q < NM) {
+    for (int r = 0; r < RE; ++r) {
+        if ((keep >> r) & 1u) {
+            const int pos = lane + r * NB;
+            const int jy = pos <= N / 2 ? pos : pos - N;
+            const int q = jy + M;
             ys[2 * q] = w[r].x;
             ys[2 * q + 1] = w[r].y;
         }

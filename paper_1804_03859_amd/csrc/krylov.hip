@@ -95,8 +95,8 @@ __global__ __launch_bounds__(kBT) void k_dot(const TS* __restrict__ V, int64_t l
 template <typename TS>
 __global__ __launch_bounds__(kBT) void k_update(const TS* __restrict__ V, int64_t ldv, int p,
                                                 const double2* __restrict__ h, const TS* __restrict__ w_in,
-                                                const typename ET<TS>::A* __restrict__ w64_in,
-                                                typename ET<TS>::A* __restrict__ w64_out, int64_t n, int dot,
+                                                const typename ET<TS>::A* w64_in,  // may equal w64_out
+                                                typename ET<TS>::A* w64_out, int64_t n, int dot,
                                                 double2* __restrict__ partial, double* __restrict__ pnrm) {
     using A = typename ET<TS>::A;
     __shared__ A wl[kChunk];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBT) void k_ritz(const TS* __restrict__ V, int64_t 
                                               const double2* __restrict__ Y, const int* __restrict__ sel, int k,
                                               double2* __restrict__ X, int64_t n) {
     const int s = blockIdx.y;
-    const double2* y = Y + size_t(sel[s]) * p;
+    const double2* y = Y + size_t(s) * p;  // unit Ritz coordinates of wanted pair s
     for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
         double2 acc = cmk<double2>(0.0, 0.0);
         for (int i = 0; i < p; ++i) {

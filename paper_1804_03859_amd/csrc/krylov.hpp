@@ -50,7 +50,8 @@ void launch_scale(const void* w64, const double* beta, TS* v, int64_t n, hipStre
 // v = x / ||x|| from a state vector x (norm from scal[slot]).
 template <typename TS>
 void launch_scale_state(const TS* x, const double* scal, int slot, TS* v, int64_t n, hipStream_t s);
-// X[s*n + e] = sum_i V_i[e] Y[sel[s]*p + i], complex128 output.
+// X[s*n + e] = sum_i V_i[e] Y[s*p + i] (Y: unit Ritz coordinates of the k
+// wanted pairs, in wanted order), complex128 output.
 template <typename TS>
 void launch_ritz_vectors(const TS* V, int64_t ldv, int p, const double2* Y, const int* sel, int k,
                          double2* X, int64_t n, hipStream_t s);

@@ -51,13 +51,16 @@ struct ArnoldiWork {
     DevBuf rr;        // RitzResult
     DevBuf phys;      // physical field scratch (seeded start vector)
     RitzResult* rr_host = nullptr;  // pinned
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // matvec timing
+    std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
+    hipEvent_t ev_cgs = nullptr;       // basis vector j+1 and H column j ready
+    hipStream_t side = nullptr;        // Ritz analysis overlaps the next matvec
     int m = 0, steps = 0;
     int64_t ldv = 0;
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
+        for (hipEvent_t e : ev_apply) (void)hipEventDestroy(e);
+        if (ev_cgs) (void)hipEventDestroy(ev_cgs);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -104,7 +107,16 @@ tsk_status arnoldi(Operator* op, int m, int k, double tol, const void* v0, uint6
 // Launches on `s`.  sel/rr may be null (no selection).
 tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta_dev, double beta_val,
                             double2* Z, double2* S, double2* mu, double2* Y, double* res, int k, double tol,
-                            double T, int* sel, RitzResult* rr, hipStream_t s);
+                            double dup_rel, int* sel, RitzResult* rr, hipStream_t s);
+
+// Relative width below which two Ritz values of an FP32-state run are taken as
+// copies of one eigenvalue (64 unit roundoffs of FP32).
+constexpr double kDupRelFp32 = 64.0 * 5.9604644775390625e-08;
+
+// Unit Ritz coordinates of the nsel wanted pairs (inverse iteration on H_p):
+// Y[s*p + r].  Needs the attribute set by a prior hess_ritz_launch.
+tsk_status ritz_coords_launch(const double2* H, int ldh, int p, const double2* mu, const int* sel, int nsel,
+                              double2* Y, hipStream_t s);
 
 // Normal draws (rng.hip).
 tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);

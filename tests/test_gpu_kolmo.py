@@ -114,7 +114,11 @@ def test_arnoldi_full_config_fp64_matches_stored_oracle_run(tsk):
     tsk.from_physical(op, _phys(op, N, W.kolmo_start_physical(N, 0)), x)
     r = tsk.arnoldi(op, c["m"], c["k"], c["tol"], v0=x, want_vectors=True)
     assert r["status"] == 0
-    assert r["n_matvec"] == g["n_matvec"]
+    # The leading eigenvalues are double (+-kx); their second copies only enter
+    # the Krylov space through rounding, so late Hessenberg columns depend on
+    # rounding order and the stop step may differ by a few matvecs.
+    assert abs(r["n_matvec"] - g["n_matvec"]) <= 3
+    assert np.all(r["res"] <= c["tol"])
     lam_o = np.array(g["lam_re"]) + 1j * np.array(g["lam_im"])
     assert match_sets(r["lam"], lam_o) <= 1e-8
     # and against the dense Galerkin eigenvalues of the operator (time error ~1e-9)
@@ -171,3 +175,41 @@ def test_invalid_sizes_and_parameters(tsk):
     with pytest.raises(tsk.TskError) as e:
         tsk.arnoldi(op, 10, 2, 1e-8)
     assert e.value.status == tsk.TSK_ESTATE
+
+
+def test_hessenberg_columns_match_oracle_before_rounding_amplification(tsk):
+    # Same start, fixed m: the first 20 columns of H agree elementwise.
+    N, m = 128, 20
+    print("kolmo N=128 H columns m=20", flush=True)
+    op, ref = _op(tsk, N)
+    w0 = W.kolmo_start_physical(N, 0)
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, w0), x)
+    r = tsk.arnoldi(op, m, 4, 0.0, v0=x)
+    assert r["status"] == 1 and r["n_matvec"] == m
+    H = tsk.last_hessenberg(op)
+    o = oracle_arnoldi(lambda v: ref.apply(v.reshape(N, N)).ravel(), ref.project(w0).ravel(), m, 4, 0.0,
+                       T=ref.T, keep_basis=False)
+    assert np.max(np.abs(H - o["H"])) <= 1e-11
+
+
+# Precision form: FP32 state, FFTs and IF-RK4; FP64 Gram-Schmidt sums, norms and
+# Hessenberg QR.  Stated bound on |lambda_FP32 - lambda_oracle|: 2e-5 (about
+# 100 FP32 unit roundoffs of the leading growth rates), measured ~5e-6.
+FP32_LAMBDA_BOUND = 2e-5
+
+
+@pytest.mark.parametrize("N,m", [(128, 64), (512, 96)])
+def test_fp32_precision_form_within_stated_bound(tsk, N, m):
+    print(f"kolmo fp32 N={N} m={m}", flush=True)
+    g = json.load(open(os.path.join(GOLD, "oracle_kolmo128_fp64.json")))
+    lam_o = np.array(g["lam_re"]) + 1j * np.array(g["lam_im"])
+    op, _ = _op(tsk, N, prec=1)
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, W.kolmo_start_physical(N, 0)), x)
+    r = tsk.arnoldi(op, m, 6, 1e-8, v0=x)
+    # six distinct eigenvalues (FP32 copies of the double ones are merged)
+    assert r["n_ritz"] == 6
+    lam = np.sort(r["lam"].real)[::-1]
+    assert np.all(np.diff(lam) < -1e-3)
+    assert match_sets(r["lam"], lam_o) <= FP32_LAMBDA_BOUND

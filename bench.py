@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X published FP64 vector peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
 
 def colstep_flops(N, nsteps):
@@ -64,11 +65,129 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
+def _flops_for(N, nsteps):
+    return colstep_flops(N, nsteps)
+
+
+def run_sweep(args, tsk, W, np, torch):
+    """Batched neutral-curve sweep: 64 FP32 instances of mixed size in lockstep."""
+    sweep = W.batch_sweep(64, 0)
+    ops = []
+    for c in sweep:
+        op = tsk.create_kolmo2d(c["N"], tsk.TSK_FP32)
+        tsk.set_params_kolmo(op, c["Re"], c["alpha"], c["dt"], c["T"])
+        tsk.set_base_kolmogorov(op, c["n_forcing"])
+        ops.append(op)
+    phys = [torch.from_numpy(W.kolmo_start_physical(c["N"], i)).float().cuda().reshape(-1)
+            for i, c in enumerate(sweep)]
+    xs = [op.new_state() for op in ops]
+
+    def step():
+        for op, p_, x in zip(ops, phys, xs):
+            tsk.from_physical(op, p_, x)
+        return tsk.batch_arnoldi(ops, 64, 4, 1e-8, v0s=xs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rb = res[-1]
+    ms = el * 1e3 / args.steps
+    nsteps = int(round(sweep[0]["T"] / sweep[0]["dt"]))
+    tsgp = sum(b["n_matvec"] * nsteps * c["N"] ** 2 for b, c in zip(rb, sweep))
+    # every step launches the batched matvec of the instances still active;
+    # ms_apply sums the HIP-event durations of those launches
+    steps_run = max(b["n_matvec"] for b in rb)
+    ms_apply = rb[0]["ms_apply"]
+    flops_total = sum(b["n_matvec"] * _flops_for(c["N"], nsteps) for b, c in zip(rb, sweep))
+    launch_ms = ms_apply / steps_run
+    flops_step = flops_total / steps_run
+    achieved = flops_total / (ms_apply / 1e3) / 1e12
+    return {
+        "metric": "time-steps*gridpoints/s (batched neutral-curve sweep, all instances to 4 Ritz pairs at 1e-8)",
+        "value": tsgp / (ms / 1e3), "unit": "time-steps*gridpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 Kolmogorov instances (24x128^2, 20x256^2, 20x384^2), FP32, Re~U[5,40], "
+                               "alpha in {0.25,0.5,0.75,1}, m=64, k=4, tol=1e-8",
+                   "n_matvec": [b["n_matvec"] for b in rb], "status": [b["status"] for b in rb],
+                   "batched_matvec_ms": launch_ms},
+        "roofline": {"bound": "alu", "kernel": "k_colstep<float,{128,256,384},true> (one batched matvec)",
+                     "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
+                     "flops_per_launch": flops_step, "traffic": None},
+        "cpu_baseline": None,
+    }
+
+
+def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
+    N, m, k, tol = cfg["N"], cfg["m"], cfg["k"], cfg["tol"]
+    nsteps = int(round(cfg["T"] / cfg["dt"]))
+    op = tsk.create_kolmo2d(N, prec)
+    tsk.set_params_kolmo(op, cfg["Re"], cfg["alpha"], cfg["dt"], cfg["T"])
+    tsk.set_base_kolmogorov(op, cfg["n_forcing"])
+    tdt = torch.float64 if prec == tsk.TSK_FP64 else torch.float32
+    phys = torch.from_numpy(W.kolmo_start_physical(N, 0)).to(tdt).cuda().reshape(-1)
+    x = op.new_state()
+
+    def step():
+        tsk.from_physical(op, phys, x)
+        return tsk.arnoldi(op, m, k, tol, v0=x, want_vectors=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el * 1e3 / args.steps
+    r = results[-1]
+    nmv = r["n_matvec"]
+    tsgp_step = nmv * nsteps * N * N
+    ms_apply = sum(q["ms_apply"] for q in results) / args.steps
+    launch_ms = ms_apply / nmv
+    flops = colstep_flops(N, nsteps)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    peak = FP64_VECTOR_PEAK_TFLOPS if prec == tsk.TSK_FP64 else FP32_VECTOR_PEAK_TFLOPS
+    rt = "double" if prec == tsk.TSK_FP64 else "float"
+    return {
+        "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
+        "value": tsgp_step / (ms_per_step / 1e3),
+        "unit": "time-steps*gridpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {"workload": f"linearized Kolmogorov flow {N}x{N} {dtype_name.upper()}, Re=20, alpha=0.5, "
+                               f"IF-RK4 dt=0.005 T=1, Arnoldi m={m} k={k} tol=1e-8, seeded N(0,1) start",
+                   "n_matvec": nmv, "status": r["status"],
+                   "wall_time_to_6_pairs_s": ms_per_step / 1e3,
+                   "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
+                   "lambda": [round(float(v.real), 10) for v in r["lam"]],
+                   "max_residual": float(np.max(r["res"]))},
+        "roofline": {"bound": "alu", "kernel": f"k_colstep<{rt},{N},true>", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": None},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="kolmo128",
+                    choices=["kolmo128", "kolmo512-fp32", "sweep"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -87,62 +206,14 @@ def main():
         build.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    c = W.KOLMO_128_FP64
-    N, m, k, tol = c["N"], c["m"], c["k"], c["tol"]
-    nsteps = int(round(c["T"] / c["dt"]))
-    op = tsk.create_kolmo2d(N, tsk.TSK_FP64)
-    tsk.set_params_kolmo(op, c["Re"], c["alpha"], c["dt"], c["T"])
-    tsk.set_base_kolmogorov(op, c["n_forcing"])
-    phys = torch.from_numpy(W.kolmo_start_physical(N, 0)).cuda().reshape(-1)
-    x = op.new_state()
-
-    def step():
-        tsk.from_physical(op, phys, x)
-        return tsk.arnoldi(op, m, k, tol, v0=x, want_vectors=True)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_per_step = el * 1e3 / args.steps
-    r = results[-1]
-    nmv = r["n_matvec"]
-    tsgp_step = nmv * nsteps * N * N
-    value = tsgp_step / (ms_per_step / 1e3)
-    ms_apply = sum(q["ms_apply"] for q in results) / args.steps
-    launch_ms = ms_apply / nmv
-    flops = colstep_flops(N, nsteps)
-    achieved = flops / (launch_ms / 1e3) / 1e12
-    out = {
-        "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
-        "value": value,
-        "unit": "time-steps*gridpoints/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "linearized Kolmogorov flow 128x128 FP64, Re=20, alpha=0.5, IF-RK4 dt=0.005 T=1, "
-                               "Arnoldi m=64 k=6 tol=1e-8, seeded N(0,1) start",
-                   "n_matvec": nmv, "status": r["status"],
-                   "wall_time_to_6_pairs_s": ms_per_step / 1e3,
-                   "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
-                   "lambda": [round(float(v.real), 10) for v in r["lam"]],
-                   "max_residual": float(np.max(r["res"]))},
-        "roofline": {"bound": "alu", "kernel": "k_colstep<double,128,true>", "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": None},
-        "cpu_baseline": None,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+    if args.workload == "kolmo128":
+        out = run_single(args, tsk, W, np, torch, W.KOLMO_128_FP64, tsk.TSK_FP64, "f64")
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline()
+    elif args.workload == "kolmo512-fp32":
+        out = run_single(args, tsk, W, np, torch, W.KOLMO_512_FP32, tsk.TSK_FP32, "f32")
+    else:
+        out = run_sweep(args, tsk, W, np, torch)
     print(json.dumps(out))
 
 

@@ -155,6 +155,21 @@ tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, 
                        double* mu_ri, double* lambda_ri, double* resid, void* ritz_dev,
                        tsk_arnoldi_info* info);
 
+/* Batched Arnoldi (neutral-curve sweeps): `count` operators of one state type
+ * and one stream (for example Navier-Stokes operators of different N, Re and
+ * alpha, all FP32) advance in lockstep; the matvecs of all Navier-Stokes
+ * instances of one grid size run in one launch.  Each instance stops on its
+ * own test; the call returns when all have stopped.  Arguments as for
+ * tsk_arnoldi, per instance i: v0_devs[i] (array or entries may be NULL),
+ * seeds[i] (NULL array: seed i), mu_ri + 2k i, lambda_ri + 2k i, resid + k i,
+ * ritz_devs[i] (array or entries may be NULL), infos[i] (per-instance status).
+ * Returns TSK_OK when every instance ended without error (see infos[i].status),
+ * or a negative status for an argument or runtime failure of the whole batch. */
+tsk_status tsk_batch_arnoldi(const tsk_op* ops, int count, int m, int k, double tol,
+                             const void* const* v0_devs, const uint64_t* seeds, double* mu_ri,
+                             double* lambda_ri, double* resid, void* const* ritz_devs,
+                             tsk_arnoldi_info* infos);
+
 /* Last Arnoldi run, for inspection: H ((m+1) x m complex128, column-major,
  * leading dimension m+1, zero beyond the steps taken) copied to host, and the
  * basis pointer (device, (steps+1) vectors of the state type, vector-major,

@@ -163,7 +163,23 @@ tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, 
                        double* lambda_ri, double* resid, void* ritz_dev, tsk_arnoldi_info* info) {
     TSK_GUARD({
         TSK_NEED(op);
-        return arnoldi(op->op.get(), m, k, tol, v0_dev, seed, mu_ri, lambda_ri, resid, ritz_dev, info);
+        Operator* o = op->op.get();
+        return arnoldi_batch(&o, 1, m, k, tol, &v0_dev, &seed, mu_ri, lambda_ri, resid, &ritz_dev, info);
+    })
+}
+
+tsk_status tsk_batch_arnoldi(const tsk_op* ops, int count, int m, int k, double tol, const void* const* v0_devs,
+                             const uint64_t* seeds, double* mu_ri, double* lambda_ri, double* resid,
+                             void* const* ritz_devs, tsk_arnoldi_info* infos) {
+    TSK_GUARD({
+        if (!ops || count < 1) return fail(TSK_EINVAL, "empty batch");
+        std::vector<Operator*> o(count);
+        for (int i = 0; i < count; ++i) {
+            if (!ops[i] || !ops[i]->op) return fail(TSK_EINVAL, "null operator handle in batch");
+            o[i] = ops[i]->op.get();
+        }
+        return arnoldi_batch(o.data(), count, m, k, tol, v0_devs, seeds, mu_ri, lambda_ri, resid, ritz_devs,
+                             infos);
     })
 }
 
@@ -199,14 +215,31 @@ tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta, v
         if (!H_dev || !mu_dev || !Y_dev || !res_dev) return fail(TSK_EINVAL, "null buffer");
         if (p < 1 || p > kMaxKrylov || ldh < p) return fail(TSK_EINVAL, "need 1 <= p <= 96 and ldh >= p");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        DevBuf Z, S, rr;
+        DevBuf Z, S, rr, scal, dd;
         TSK_TRY(Z.ensure(size_t(p) * p * sizeof(double2)));
         TSK_TRY(S.ensure(size_t(p) * p * sizeof(double2)));
         TSK_TRY(rr.ensure(sizeof(RitzResult)));
-        TSK_HIP(hipMemsetAsync(rr.ptr, 0, sizeof(RitzResult), s));
-        TSK_TRY(hess_ritz_launch(static_cast<const double2*>(H_dev), ldh, p, nullptr, beta, Z.as<double2>(),
-                                 S.as<double2>(), static_cast<double2*>(mu_dev), static_cast<double2*>(Y_dev),
-                                 static_cast<double*>(res_dev), 0, 0.0, 0.0, nullptr, rr.as<RitzResult>(), s));
+        TSK_TRY(scal.ensure(64 * sizeof(double)));
+        TSK_TRY(dd.ensure(sizeof(KryDesc)));
+        double sc[64] = {0};
+        sc[2] = beta;
+        RitzResult r0{};
+        KryDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.H = const_cast<double2*>(static_cast<const double2*>(H_dev));
+        d.ldh = ldh;
+        d.scal = scal.as<double>();
+        d.Z = Z.as<double2>();
+        d.S = S.as<double2>();
+        d.Y = static_cast<double2*>(Y_dev);
+        d.mu = static_cast<double2*>(mu_dev);
+        d.res = static_cast<double*>(res_dev);
+        d.rr = rr.as<RitzResult>();
+        d.active = 1;
+        TSK_HIP(hipMemcpyAsync(scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+        TSK_HIP(hipMemcpyAsync(rr.ptr, &r0, sizeof(r0), hipMemcpyHostToDevice, s));
+        TSK_HIP(hipMemcpyAsync(dd.ptr, &d, sizeof(d), hipMemcpyHostToDevice, s));
+        TSK_TRY(hess_ritz_launch(dd.as<KryDesc>(), 1, p, 0, 0.0, true, s));
         RitzResult h{};
         TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
         TSK_HIP(hipStreamSynchronize(s));

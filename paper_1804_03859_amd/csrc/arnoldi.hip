@@ -1,22 +1,27 @@
-// Arnoldi driver (host orchestration of device kernels).
+// Arnoldi driver (host orchestration of device kernels) for a batch of
+// independent instances advancing in lockstep; a single run is a batch of one.
 //
 // m-step Arnoldi factorisation M V_m = V_m H_m + beta v_{m+1} e_m^T
 // (Sec. 3.2.1, eq. "m-step Arnoldi", Algorithm 1) with every matvec a time
 // integration of the linearized equations (Sec. 3, time-stepper approach).
 // After each matvec: CGS2 projection and normalisation (krylov.hip), then the
-// device Hessenberg QR and wanted-set test (hessenberg.hip).  The only device to
-// host traffic per step is the 48-byte RitzResult that tells the host whether
-// to stop.
+// device Hessenberg QR and wanted-set test (hessenberg.hip), one wavefront per
+// instance.  The only device-to-host traffic per step is one 48-byte
+// RitzResult per instance, telling the host which instances stop.  Ritz values
+// are mapped to lambda = log(mu)/T on the device (principal branch, valid when
+// |Im lambda| T < pi/2, the four-samples-per-period rule of Sec. 3.2.1).
 //
 // Overlap: as soon as v_{j+1} exists, the matvec M v_{j+1} is launched on the
-// operator's stream while the Ritz analysis of H_j runs on a side stream (one
-// wavefront, so it barely competes for compute units).  The host waits only for
-// the side stream; if H_j already satisfies the stop test, the speculative
-// matvec is discarded (it is neither counted nor used).  Ritz values are mapped to lambda = log(mu)/T on the device
-// (principal branch, valid when |Im lambda| T < pi/2, the four-samples-per-period
-// rule of Sec. 3.2.1).
+// operator stream while the Ritz analysis of H_j runs on a side stream (one
+// wavefront per instance, so it barely competes for compute units).  The host
+// waits only for the side stream; an instance whose H_j already satisfies the
+// stop test is marked inactive and its speculative matvec is discarded (neither
+// counted nor used).  Batched Navier-Stokes instances share one launch per grid
+// size for the matvec; kernels of the Gram-Schmidt and Ritz phases index the
+// instance by blockIdx.
 #include <chrono>
 #include <cstring>
+#include <vector>
 
 #include "krylov.hpp"
 #include "ops.hpp"
@@ -25,199 +30,297 @@ namespace tsk {
 
 namespace {
 
-__global__ void k_gather_ritz(const double2* __restrict__ mu, const double* __restrict__ res,
-                              const int* __restrict__ sel, int nsel, double T, double* __restrict__ out) {
-    // out layout: [mu re,im]*nsel | [lambda re,im]*nsel | [res]*nsel
-    int s = threadIdx.x;
-    if (s >= nsel) return;
-    double2 m = mu[sel[s]];
-    out[2 * s] = m.x;
-    out[2 * s + 1] = m.y;
-    double r = hypot(m.x, m.y);
-    out[2 * nsel + 2 * s] = log(r) / T;
-    out[2 * nsel + 2 * s + 1] = atan2(m.y, m.x) / T;
-    out[4 * nsel + s] = res[sel[s]];
+__global__ void k_collect(const KryDesc* __restrict__ Dv, int count, RitzResult* __restrict__ dst, int with_scal) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        RitzResult r = *Dv[i].rr;
+        if (with_scal) {  // start-vector checks: ||x0||^2 in beta, finite flag in nonfinite
+            r.beta = Dv[i].scal[0];
+            r.nonfinite = *reinterpret_cast<const int*>(Dv[i].scal + 32);
+        }
+        dst[i] = r;
+    }
+}
+
+__global__ void k_reset(const KryDesc* __restrict__ Dv, int count) {
+    const KryDesc& d = Dv[blockIdx.x];
+    for (int i = threadIdx.x; i < d.ldh * (d.ldh - 1); i += blockDim.x) d.H[i] = cmk<double2>(0.0, 0.0);
+    if (threadIdx.x == 0) {
+        *d.rr = RitzResult{};
+        *reinterpret_cast<int*>(d.scal + 32) = 0;
+    }
 }
 
 template <typename TS> struct WorkType { using A = double; };
 template <> struct WorkType<double2> { using A = double2; };
 
+struct Outcome {
+    int status = TSK_NOT_CONVERGED;
+    int steps = 0;
+    bool done = false;
+    std::string err;
+};
+
 template <typename TS>
-tsk_status arnoldi_t(Operator* op, int m, int k, double tol, const void* v0, uint64_t seed, double* mu_ri,
-                     double* lam_ri, double* resid, void* ritz, tsk_arnoldi_info* info) {
+tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
+                     const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
+                     tsk_arnoldi_info* infos) {
     using A = typename WorkType<TS>::A;
     auto t0 = std::chrono::steady_clock::now();
-    const hipStream_t s = op->stream;
-    ArnoldiWork& W = op->aw;
-    const int64_t n = op->n;
-    const int64_t ldv = (n + 63) / 64 * 64;
-    const int nblk = cgs_blocks(n);
+    Operator* lead = ops[0];
+    const hipStream_t s = lead->stream;
+    ArnoldiWork& L = lead->aw;
+    const double dup_rel = lead->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
 
-    TSK_TRY(W.V.ensure(size_t(m + 1) * ldv * sizeof(TS)));
-    TSK_TRY(W.H.ensure(size_t(m + 1) * m * sizeof(double2)));
-    TSK_TRY(W.w.ensure(size_t(n) * sizeof(TS)));
-    TSK_TRY(W.w64.ensure(size_t(n) * sizeof(A)));
-    TSK_TRY(W.partial.ensure(size_t(nblk) * (m + 1) * sizeof(double2)));
-    TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
-    TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
-    TSK_TRY(W.scal.ensure(64 * sizeof(double)));
-    TSK_TRY(W.eigZ.ensure(size_t(m) * m * sizeof(double2)));
-    TSK_TRY(W.eigS.ensure(size_t(m) * m * sizeof(double2)));
-    TSK_TRY(W.eigY.ensure(size_t(m) * m * sizeof(double2)));
-    TSK_TRY(W.eigMu.ensure(size_t(m) * sizeof(double2)));
-    TSK_TRY(W.eigRes.ensure(size_t(m) * sizeof(double)));
-    const size_t gath_off = (size_t(m) * sizeof(int) + 15) / 16 * 16;
-    TSK_TRY(W.sel.ensure(gath_off + 5 * size_t(k) * sizeof(double)));
-    TSK_TRY(W.rr.ensure(sizeof(RitzResult)));
-    if (!W.rr_host) TSK_HIP(hipHostMalloc((void**)&W.rr_host, sizeof(RitzResult) + 64 * sizeof(double), 0));
-    while (W.ev_apply.size() < size_t(2 * (m + 1))) {
+    // ---- per-instance workspace and descriptors ------------------------------------
+    std::vector<KryDesc> Dh(count);
+    int64_t nmax = 0;
+    int nblk_max = 0;
+    for (int i = 0; i < count; ++i) {
+        Operator* op = ops[i];
+        ArnoldiWork& W = op->aw;
+        const int64_t n = op->n;
+        const int64_t ldv = (n + 63) / 64 * 64;
+        const int nblk = cgs_blocks(n);
+        TSK_TRY(W.V.ensure(size_t(m + 1) * ldv * sizeof(TS)));
+        TSK_TRY(W.H.ensure(size_t(m + 1) * m * sizeof(double2)));
+        TSK_TRY(W.w.ensure(size_t(n) * sizeof(TS)));
+        TSK_TRY(W.w64.ensure(size_t(n) * sizeof(A)));
+        TSK_TRY(W.partial.ensure(size_t(nblk) * (m + 1) * sizeof(double2)));
+        TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
+        TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
+        TSK_TRY(W.scal.ensure(64 * sizeof(double)));
+        TSK_TRY(W.eigS.ensure(size_t(m) * m * sizeof(double2)));
+        TSK_TRY(W.eigY.ensure(size_t(m) * (k > 0 ? k : 1) * sizeof(double2)));
+        TSK_TRY(W.eigMu.ensure(size_t(m) * sizeof(double2)));
+        TSK_TRY(W.eigRes.ensure(size_t(m) * sizeof(double)));
+        TSK_TRY(W.sel.ensure(size_t(m) * sizeof(int)));
+        TSK_TRY(W.out.ensure(5 * size_t(k) * sizeof(double)));
+        TSK_TRY(W.rr.ensure(sizeof(RitzResult)));
+        W.m = m;
+        W.steps = 0;
+        W.ldv = ldv;
+        KryDesc& d = Dh[i];
+        std::memset(&d, 0, sizeof(d));
+        d.V = W.V.ptr;
+        d.w = W.w.ptr;
+        d.w64 = W.w64.ptr;
+        d.H = W.H.as<double2>();
+        d.partial = W.partial.as<double2>();
+        d.pnrm = W.pnrm.as<double>();
+        d.h = W.h.as<double2>();
+        d.scal = W.scal.as<double>();
+        d.Z = nullptr;
+        d.S = W.eigS.as<double2>();
+        d.Y = W.eigY.as<double2>();
+        d.mu = W.eigMu.as<double2>();
+        d.res = W.eigRes.as<double>();
+        d.sel = W.sel.as<int>();
+        d.rr = W.rr.as<RitzResult>();
+        d.ritz = (ritz && ritz[i]) ? ritz[i] : nullptr;
+        d.out = W.out.as<double>();
+        d.ldv = ldv;
+        d.n = n;
+        d.ldh = m + 1;
+        d.nblk = nblk;
+        d.active = 1;
+        d.dup_rel = dup_rel;
+        d.T = op->T;
+        nmax = std::max(nmax, n);
+        nblk_max = std::max(nblk_max, nblk);
+    }
+    while (L.ev_apply.size() < size_t(2 * (m + 1))) {
         hipEvent_t e;
         TSK_HIP(hipEventCreate(&e));
-        W.ev_apply.push_back(e);
+        L.ev_apply.push_back(e);
     }
-    if (!W.ev_cgs) TSK_HIP(hipEventCreateWithFlags(&W.ev_cgs, hipEventDisableTiming));
-    if (!W.side) TSK_HIP(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
-    const hipStream_t s2 = W.side;
-    W.m = m;
-    W.steps = 0;
-    W.ldv = ldv;
+    if (!L.ev_cgs) TSK_HIP(hipEventCreateWithFlags(&L.ev_cgs, hipEventDisableTiming));
+    if (!L.side) TSK_HIP(hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking));
+    const hipStream_t s2 = L.side;
+    TSK_TRY(L.batch_rr.ensure(size_t(count) * sizeof(RitzResult)));
+    if (L.rr_host_count < count) {
+        if (L.rr_host) (void)hipHostFree(L.rr_host);
+        L.rr_host = nullptr;
+        TSK_HIP(hipHostMalloc((void**)&L.rr_host, size_t(count) * sizeof(RitzResult), 0));
+        L.rr_host_count = count;
+    }
+    RitzResult* rrh = L.rr_host;
 
-    TS* V = W.V.as<TS>();
-    double2* H = W.H.as<double2>();
-    TS* w = W.w.as<TS>();
-    double* scal = W.scal.as<double>();
-    RitzResult* rr = W.rr.as<RitzResult>();
-    RitzResult* rrh = W.rr_host;
-    double* scal_host = reinterpret_cast<double*>(rrh + 1);
-
-    TSK_HIP(hipMemsetAsync(H, 0, size_t(m + 1) * m * sizeof(double2), s));
-    TSK_HIP(hipMemsetAsync(rr, 0, sizeof(RitzResult), s));
-
-    // ---- start vector (Algorithm 1: v1 = v / ||v||) ------------------------------
-    const TS* x0 = static_cast<const TS*>(v0);
-    if (!x0) {
-        const int64_t pr = op->physical_reals();
-        TSK_TRY(W.phys.ensure(size_t(pr) * 8));
-        TSK_TRY(normal_fill(W.phys.as<double>(), pr, seed, s));
-        if (op->kind == StateKind::Real32) {
-            // FP32 operators take an FP32 physical field: narrow in place (front half)
-            TSK_TRY(narrow_to_float(W.phys.as<double>(), W.phys.as<float>(), pr, s));
+    // ---- start vectors (Algorithm 1: v1 = v / ||v||) -----------------------------------
+    for (int i = 0; i < count; ++i) {
+        const void* x0 = (v0s && v0s[i]) ? v0s[i] : nullptr;
+        if (!x0) {
+            Operator* op = ops[i];
+            const int64_t pr = op->physical_reals();
+            TSK_TRY(op->aw.phys.ensure(size_t(pr) * 8));
+            TSK_TRY(normal_fill(op->aw.phys.as<double>(), pr, seeds ? seeds[i] : uint64_t(i), s));
+            if (op->kind == StateKind::Real32)
+                TSK_TRY(narrow_to_float(op->aw.phys.as<double>(), op->aw.phys.as<float>(), pr, s));
+            TSK_TRY(op->from_physical(op->aw.phys.ptr, op->aw.w.ptr));
+            x0 = op->aw.w.ptr;
         }
-        TSK_TRY(op->from_physical(W.phys.ptr, w));
-        x0 = w;
+        Dh[i].x0 = x0;
     }
-    int* flag = reinterpret_cast<int*>(scal + 32);
-    TSK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    launch_check_finite<TS>(x0, n, flag, s);
-    launch_dot<TS>(V, ldv, 0, x0, n, W.partial.as<double2>(), W.pnrm.as<double>(), s);
-    launch_reduce(W.partial.as<double2>(), nblk, 0, W.h.as<double2>(), nullptr, 0, W.pnrm.as<double>(), scal, 0, s);
-    TSK_HIP(hipMemcpyAsync(scal_host, scal, 40 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TSK_TRY(L.batch_desc.ensure(size_t(count) * sizeof(KryDesc)));
+    KryDesc* D = L.batch_desc.as<KryDesc>();
+    TSK_HIP(hipMemcpyAsync(D, Dh.data(), size_t(count) * sizeof(KryDesc), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count);
+    launch_check_finite<TS>(D, count, nmax, s);
+    launch_dot<TS>(D, count, nblk_max, 0, true, s);
+    launch_reduce(D, count, 0, -1, 0, 0, s);
+    hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, D, count, L.batch_rr.as<RitzResult>(), 1);
+    TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
     TSK_HIP(hipStreamSynchronize(s));
-    if (*reinterpret_cast<int*>(scal_host + 32) != 0) return fail(TSK_ENONFINITE, "start vector is not finite");
-    if (!(scal_host[0] > 0.0)) return fail(TSK_EINVAL, "start vector is zero");
-    launch_scale_state<TS>(x0, scal, 0, V, n, s);
+    for (int i = 0; i < count; ++i) {
+        if (rrh[i].nonfinite) return fail(TSK_ENONFINITE, "start vector " + std::to_string(i) + " is not finite");
+        if (!(rrh[i].beta > 0.0)) return fail(TSK_EINVAL, "start vector " + std::to_string(i) + " is zero");
+    }
+    launch_scale<TS>(D, count, nmax, -1, s);
 
-    // ---- Arnoldi steps ------------------------------------------------------------------
-    tsk_status status = TSK_NOT_CONVERGED;
-    int steps = 0;
-    TSK_HIP(hipEventRecord(W.ev_apply[0], s));
-    TSK_TRY(op->apply(V, w));
-    TSK_HIP(hipEventRecord(W.ev_apply[1], s));
-    for (int j = 0; j < m; ++j) {
+    // ---- matvec of step j for every active instance --------------------------------------
+    KolmoBatchPtr kb;
+    bool all_kolmo = true;
+    for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && is_kolmo(ops[i]);
+    if (all_kolmo) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
+    std::vector<Outcome> oc(count);
+    auto matvec = [&](int j) -> tsk_status {
+        if (kb) return kolmo_batch_matvec(kb.get(), j, s);
+        for (int i = 0; i < count; ++i)
+            if (!oc[i].done) TSK_TRY(ops[i]->apply(static_cast<TS*>(Dh[i].V) + j * Dh[i].ldv, Dh[i].w));
+        return TSK_OK;
+    };
+
+    // ---- Arnoldi steps ------------------------------------------------------------------------
+    TSK_HIP(hipEventRecord(L.ev_apply[0], s));
+    TSK_TRY(matvec(0));
+    TSK_HIP(hipEventRecord(L.ev_apply[1], s));
+    int remaining = count;
+    int steps_run = 0;
+    for (int j = 0; j < m && remaining > 0; ++j) {
         const int p = j + 1;
-        double2* Hcol = H + size_t(m + 1) * j;
-        launch_dot<TS>(V, ldv, p, w, n, W.partial.as<double2>(), W.pnrm.as<double>(), s);
-        launch_reduce(W.partial.as<double2>(), nblk, p, W.h.as<double2>(), Hcol, 1, W.pnrm.as<double>(), scal, 1, s);
-        launch_update<TS>(V, ldv, p, W.h.as<double2>(), w, nullptr, W.w64.ptr, n, true, W.partial.as<double2>(),
-                          W.pnrm.as<double>(), s);
-        launch_reduce(W.partial.as<double2>(), nblk, p, W.h.as<double2>(), Hcol, 0, nullptr, scal, 0, s);
-        launch_update<TS>(V, ldv, p, W.h.as<double2>(), nullptr, W.w64.ptr, W.w64.ptr, n, false,
-                          W.partial.as<double2>(), W.pnrm.as<double>(), s);
-        launch_finalize(W.pnrm.as<double>(), nblk, scal, 1, Hcol + p, scal + 2, rr, s);
-        launch_scale<TS>(W.w64.ptr, scal + 2, V + (j + 1) * ldv, n, s);
-        TSK_HIP(hipEventRecord(W.ev_cgs, s));
-        // speculative matvec of the next step
-        if (j + 1 < m) {
-            TSK_HIP(hipEventRecord(W.ev_apply[2 * (j + 1)], s));
-            TSK_TRY(op->apply(V + (j + 1) * ldv, w));
-            TSK_HIP(hipEventRecord(W.ev_apply[2 * (j + 1) + 1], s));
+        launch_dot<TS>(D, count, nblk_max, p, false, s);
+        launch_reduce(D, count, p, j, 1, 1, s);
+        launch_update<TS>(D, count, nblk_max, p, true, true, s);
+        launch_reduce(D, count, p, j, 0, -1, s);
+        launch_update<TS>(D, count, nblk_max, p, false, false, s);
+        launch_finalize(D, count, j, s);
+        launch_scale<TS>(D, count, nmax, j, s);
+        TSK_HIP(hipEventRecord(L.ev_cgs, s));
+        if (j + 1 < m) {  // speculative matvec of the next step
+            TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
+            TSK_TRY(matvec(j + 1));
+            TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1) + 1], s));
         }
-        // Ritz analysis of H_j on the side stream
-        TSK_HIP(hipStreamWaitEvent(s2, W.ev_cgs, 0));
+        TSK_HIP(hipStreamWaitEvent(s2, L.ev_cgs, 0));
         const int kk = k < p ? k : p;
-        TSK_TRY(hess_ritz_launch(H, m + 1, p, scal + 2, 0.0, W.eigZ.as<double2>(), W.eigS.as<double2>(),
-                                 W.eigMu.as<double2>(), W.eigY.as<double2>(), W.eigRes.as<double>(), kk, tol,
-                                 op->kind == StateKind::Real32 ? kDupRelFp32 : 0.0, W.sel.as<int>(), rr, s2));
-        TSK_HIP(hipMemcpyAsync(rrh, rr, sizeof(RitzResult), hipMemcpyDeviceToHost, s2));
+        TSK_TRY(hess_ritz_launch(D, count, p, kk, tol, false, s2));
+        hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s2, D, count, L.batch_rr.as<RitzResult>(), 0);
+        TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s2));
         TSK_HIP(hipStreamSynchronize(s2));
-        steps = p;
-        W.steps = p;
-        if (rrh->nonfinite) return fail(TSK_ENONFINITE, "non-finite matvec output or norm at step " + std::to_string(p));
-        if (rrh->eig_fail) return fail(TSK_EEIG, "Hessenberg QR did not converge at step " + std::to_string(p));
-        if (rrh->breakdown) { status = TSK_BREAKDOWN; break; }
-        if (rrh->done && kk == k) { status = TSK_OK; break; }
+        steps_run = p;
+        bool changed = false;
+        for (int i = 0; i < count; ++i) {
+            if (oc[i].done) continue;
+            oc[i].steps = p;
+            const RitzResult& r = rrh[i];
+            int st = 0;
+            if (r.nonfinite) { st = TSK_ENONFINITE; oc[i].err = "non-finite matvec output or norm"; }
+            else if (r.eig_fail) { st = TSK_EEIG; oc[i].err = "Hessenberg QR did not converge"; }
+            else if (r.breakdown) st = TSK_BREAKDOWN;
+            else if (r.done && kk == k) st = TSK_OK;
+            else continue;
+            oc[i].status = st;
+            oc[i].done = true;
+            --remaining;
+            Dh[i].active = 0;
+            TSK_HIP(hipMemcpyAsync(&D[i].active, &Dh[i].active, sizeof(int), hipMemcpyHostToDevice, s));
+            changed = true;
+        }
+        (void)changed;
     }
 
-    // ---- outputs ---------------------------------------------------------------------------
-    TSK_HIP(hipStreamSynchronize(s));  // drains a discarded speculative matvec
+    // ---- outputs --------------------------------------------------------------------------------
+    TSK_HIP(hipStreamSynchronize(s));  // drains discarded speculative matvecs
     double ms_apply = 0.0;
-    for (int j = 0; j < steps; ++j) {
+    for (int j = 0; j < steps_run; ++j) {
         float ms = 0.0f;
-        TSK_HIP(hipEventElapsedTime(&ms, W.ev_apply[2 * j], W.ev_apply[2 * j + 1]));
+        TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * j], L.ev_apply[2 * j + 1]));
         ms_apply += ms;
     }
-    const int nsel = rrh->nsel;
-    double* gath = reinterpret_cast<double*>(static_cast<char*>(W.sel.ptr) + gath_off);
-    hipLaunchKernelGGL(k_gather_ritz, dim3(1), dim3(128), 0, s, W.eigMu.as<double2>(), W.eigRes.as<double>(),
-                       W.sel.as<int>(), nsel, op->T, gath);
-    TSK_HIP(hipGetLastError());
-    if (ritz && nsel > 0)
-        TSK_TRY(ritz_coords_launch(H, m + 1, steps, W.eigMu.as<double2>(), W.sel.as<int>(), nsel,
-                                   W.eigY.as<double2>(), s));
-    if (ritz && nsel > 0)
-        launch_ritz_vectors<TS>(V, ldv, steps, W.eigY.as<double2>(), W.sel.as<int>(), nsel,
-                                static_cast<double2*>(ritz), n, s);
-    std::vector<double> hbuf(5 * size_t(nsel > 0 ? nsel : 1));
-    if (nsel > 0)
-        TSK_HIP(hipMemcpyAsync(hbuf.data(), gath, 5 * size_t(nsel) * sizeof(double), hipMemcpyDeviceToHost, s));
+    int pmax = 1;
+    for (int i = 0; i < count; ++i) {
+        Dh[i].steps = oc[i].steps;
+        Dh[i].active = 1;
+        ops[i]->aw.steps = oc[i].steps;
+        pmax = std::max(pmax, oc[i].steps);
+    }
+    TSK_HIP(hipMemcpyAsync(D, Dh.data(), size_t(count) * sizeof(KryDesc), hipMemcpyHostToDevice, s));
+    bool any_ritz = false;
+    for (int i = 0; i < count; ++i) any_ritz = any_ritz || Dh[i].ritz;
+    if (any_ritz) {
+        TSK_TRY(ritz_coords_launch(D, count, pmax, k, s));
+        launch_ritz_vectors<TS>(D, count, nmax, k, s);
+    }
+    launch_gather(D, count, k, s);
+    std::vector<double> hout(5 * size_t(k) * count);
+    for (int i = 0; i < count; ++i)
+        TSK_HIP(hipMemcpyAsync(hout.data() + 5 * size_t(k) * i, Dh[i].out, 5 * size_t(k) * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, D, count, L.batch_rr.as<RitzResult>(), 0);
+    TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
     TSK_HIP(hipStreamSynchronize(s));
     TSK_HIP(hipGetLastError());
-    for (int i = 0; i < k; ++i) {
-        bool have = i < nsel;
-        if (mu_ri) { mu_ri[2 * i] = have ? hbuf[2 * i] : 0.0; mu_ri[2 * i + 1] = have ? hbuf[2 * i + 1] : 0.0; }
-        if (lam_ri) {
-            lam_ri[2 * i] = have ? hbuf[2 * nsel + 2 * i] : 0.0;
-            lam_ri[2 * i + 1] = have ? hbuf[2 * nsel + 2 * i + 1] : 0.0;
+    const double ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < count; ++i) {
+        const double* o = hout.data() + 5 * size_t(k) * i;
+        const bool ok = oc[i].status >= 0;
+        for (int q = 0; q < k; ++q) {
+            if (mu_ri) { mu_ri[2 * k * i + 2 * q] = ok ? o[2 * q] : 0.0; mu_ri[2 * k * i + 2 * q + 1] = ok ? o[2 * q + 1] : 0.0; }
+            if (lam_ri) {
+                lam_ri[2 * k * i + 2 * q] = ok ? o[2 * k + 2 * q] : 0.0;
+                lam_ri[2 * k * i + 2 * q + 1] = ok ? o[2 * k + 2 * q + 1] : 0.0;
+            }
+            if (resid) resid[k * i + q] = ok ? o[4 * k + q] : 0.0;
         }
-        if (resid) resid[i] = have ? hbuf[4 * nsel + i] : 0.0;
+        if (infos) {
+            tsk_arnoldi_info& f = infos[i];
+            f.n_matvec = oc[i].steps;
+            f.n_ritz = ok ? rrh[i].nsel : 0;
+            f.n_converged = ok ? rrh[i].nconv : 0;
+            f.status = oc[i].status;
+            f.beta = rrh[i].beta;
+            f.ms_total = ms_total;
+            f.ms_apply = ms_apply;
+        }
     }
-    if (info) {
-        info->n_matvec = steps;
-        info->n_ritz = nsel;
-        info->n_converged = rrh->nconv;
-        info->status = status;
-        info->beta = rrh->beta;
-        info->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        info->ms_apply = ms_apply;
-    }
-    return status;
+    if (count == 1 && oc[0].status < 0) return fail(tsk_status(oc[0].status), oc[0].err + " at step " + std::to_string(oc[0].steps));
+    return count == 1 ? tsk_status(oc[0].status) : TSK_OK;
 }
 
 }  // namespace
 
-tsk_status arnoldi(Operator* op, int m, int k, double tol, const void* v0, uint64_t seed, double* mu_ri,
-                   double* lam_ri, double* resid, void* ritz, tsk_arnoldi_info* info) {
-    if (!op->ready()) return fail(TSK_ESTATE, "operator parameters or base flow not set");
+tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
+                         const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
+                         tsk_arnoldi_info* infos) {
+    if (count < 1 || !ops) return fail(TSK_EINVAL, "empty batch");
     if (k < 1 || m < k || m > kMaxKrylov) return fail(TSK_EINVAL, "need 1 <= k <= m <= 96");
-    if (int64_t(m) > op->n) return fail(TSK_EINVAL, "m exceeds the state dimension");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TSK_EINVAL, "tol must be finite and >= 0");
-    switch (op->kind) {
+    for (int i = 0; i < count; ++i) {
+        if (!ops[i]) return fail(TSK_EINVAL, "null operator in batch");
+        if (!ops[i]->ready()) return fail(TSK_ESTATE, "operator parameters or base flow not set");
+        if (int64_t(m) > ops[i]->n) return fail(TSK_EINVAL, "m exceeds the state dimension");
+        if (ops[i]->kind != ops[0]->kind) return fail(TSK_EINVAL, "a batch must share one state type");
+        if (ops[i]->stream != ops[0]->stream) return fail(TSK_EINVAL, "batch members must share one stream");
+        for (int q = 0; q < i; ++q)
+            if (ops[q] == ops[i]) return fail(TSK_EINVAL, "an operator appears twice in the batch");
+    }
+    switch (ops[0]->kind) {
         case StateKind::Complex64x2:
-            return arnoldi_t<double2>(op, m, k, tol, v0, seed, mu_ri, lam_ri, resid, ritz, info);
+            return arnoldi_t<double2>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
         case StateKind::Real64:
-            return arnoldi_t<double>(op, m, k, tol, v0, seed, mu_ri, lam_ri, resid, ritz, info);
+            return arnoldi_t<double>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
         case StateKind::Real32:
-            return arnoldi_t<float>(op, m, k, tol, v0, seed, mu_ri, lam_ri, resid, ritz, info);
+            return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
     }
     return fail(TSK_EINVAL, "unknown state kind");
 }

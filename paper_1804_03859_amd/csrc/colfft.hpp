@@ -1,8 +1,8 @@
 // Single-wavefront complex FFT of length N whose first and last passes work
 // on registers, for the column time stepper.
 //
-// Plan: N = RE * (middle radices) * RE with the same "edge" radix RE = 8 (or 4)
-// for the first and the last Stockham pass.  Lane-owned butterfly j
+// Plan: N = RE * (middle radices) * RE with the same "edge" radix RE for the
+// first and the last Stockham pass.  Lane-owned butterfly j
 // (0 <= j < NB = N/RE) of the first pass reads positions j + r NB; the last
 // pass of the same plan writes its butterfly j to exactly those positions.  So a
 // lane that keeps the data of "its" positions in registers can (i) feed the first
@@ -22,11 +22,37 @@ namespace tsk {
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
 template <int N> constexpr int padded_len() { return N + N / 8 + 1; }
 
+// Edge radix: the smallest that leaves at most one edge butterfly per lane
+// (N / RE <= 64) and an integral middle length N / RE^2, so that every lane
+// owns RE positions and all 64 lanes work in the edge passes when N >= 128.
+constexpr int col_edge_radix(int N) {
+    for (int r : {2, 4, 8, 3})
+        if (N % (r * r) == 0 && N / r <= kWave) return r;
+    return 8;
+}
+// Middle radices: 8 only when its butterflies still fill the wavefront
+// (N / 8 >= 64), otherwise 4, then 2, then 3 (fewer idle lanes per pass).
+constexpr int col_mid_radix(int N, int mid, int pass) {
+    int p = 0;
+    while (mid > 1) {
+        int r = (mid % 8 == 0 && N / 8 >= kWave) ? 8 : (mid % 4 == 0) ? 4 : (mid % 2 == 0) ? 2 : 3;
+        if (p == pass) return r;
+        mid /= r;
+        ++p;
+    }
+    return 1;
+}
+constexpr int col_mid_passes(int N, int mid) {
+    int p = 0;
+    while (col_mid_radix(N, mid, p) > 1) ++p;
+    return p;
+}
+
 template <int N> struct ColPlan {
-    static constexpr int RE = (N % 64 == 0) ? 8 : 4;
+    static constexpr int RE = col_edge_radix(N);
     static constexpr int MID = N / (RE * RE);
-    static constexpr int NMID = MID > 1 ? fft_num_passes(MID) : 0;
-    static constexpr int NB = N / RE;                 // butterflies of an edge pass
+    static constexpr int NMID = col_mid_passes(N, MID);
+    static constexpr int NB = N / RE;                     // butterflies of an edge pass
     static constexpr int NBL = (NB + kWave - 1) / kWave;  // per lane
     static_assert(RE * RE * MID == N, "unsupported length");
 };
@@ -63,7 +89,7 @@ __device__ inline C* col_mid_passes(C* a, C* b, const C* tw, int lane) {
     if constexpr (P >= PL::NMID) {
         return a;
     } else {
-        constexpr int R = fft_radix(PL::MID, P);
+        constexpr int R = col_mid_radix(N, PL::MID, P);
         col_mid_pass<N, R, NS, SIGN>(a, b, tw, lane);
         __syncthreads();
         return col_mid_passes<N, P + 1, NS * R, SIGN>(b, a, tw, lane);

@@ -34,6 +34,7 @@
 // dup_rel > 0 (FP32 states) values closer than dup_rel |mu| to an accepted or
 // converged one also count as copies of it: FP32 rounding splits a multiple
 // eigenvalue into a cluster of that width, each member of which converges.
+#include "krylov.hpp"
 #include "ops.hpp"
 
 namespace tsk {
@@ -47,8 +48,19 @@ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
 // Givens rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0], c real:
 // c = |x| / rho, s = (x/|x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2).  The
-// rotation sits on the critical path of the bulge chase, so it uses two square
-// roots and one division (no hypot: entries of H are far from overflow).
+// rotation is on the critical path of the bulge chase, so it is built from one
+// reciprocal square root: with f = (|x|^2 (|x|^2 + |y|^2))^(-1/2),
+// c = |x|^2 f and s = x conj(y) f.  f starts from the hardware estimate and is
+// refined by two Newton steps to full FP64 accuracy.  Arguments whose squares
+// could leave the normal range take a scaled path.
+__device__ inline double rsqrt_full(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+    double h = 0.5 * v;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 __device__ inline void givens(double2 x, double2 y, double& c, double2& s) {
     const double nx = x.x * x.x + x.y * x.y, ny = y.x * y.x + y.y * y.y;
     if (ny == 0.0) { c = 1.0; s = cmk<double2>(0.0, 0.0); return; }
@@ -58,10 +70,17 @@ __device__ inline void givens(double2 x, double2 y, double& c, double2& s) {
         s = cmk<double2>(y.x * f, -y.y * f);
         return;
     }
+    const double q = nx * (nx + ny);
+    if (q > 1e-280 && q < 1e280) {
+        const double f = rsqrt_full(q);
+        c = nx * f;
+        s = cscale(cmulc(y, x), f);  // x conj(y) f
+        return;
+    }
     const double ax = sqrt(nx), rho = sqrt(nx + ny);
     const double f = 1.0 / (ax * rho);
-    c = ax * f * ax;  // = |x| / rho
-    s = cscale(cmulc(y, x), f);  // x conj(y) / (|x| rho)
+    c = ax * f * ax;
+    s = cscale(cmulc(y, x), f);
 }
 
 __device__ inline int highest_bit(unsigned long long m) { return 63 - __builtin_clzll(m); }
@@ -90,12 +109,19 @@ __device__ inline double tri_eigvec(const double2* T, int p, int i, double2* zc)
 // otherwise only the last row of Z is tracked (all the residuals need) and the
 // wanted Ritz coordinates are computed afterwards by inverse iteration.
 template <bool FULLZ>
-__global__ __launch_bounds__(kHT) void k_hess_ritz(const double2* __restrict__ H, int ldh, int p,
-                                                  const double* __restrict__ beta_dev, double beta_val,
-                                                  double2* __restrict__ Z, double2* __restrict__ S,
-                                                  double2* __restrict__ mu, double2* __restrict__ Y,
-                                                  double* __restrict__ res, int k, double tol, double dup_rel,
-                                                  int* __restrict__ sel, RitzResult* __restrict__ rr) {
+__global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ Dv, int p, int k, double tol) {
+    const KryDesc& dsc = Dv[blockIdx.x];
+    if (!dsc.active) return;
+    const double2* __restrict__ H = dsc.H;
+    const int ldh = dsc.ldh;
+    double2* __restrict__ Z = dsc.Z;
+    double2* __restrict__ S = dsc.S;
+    double2* __restrict__ mu = dsc.mu;
+    double2* __restrict__ Y = dsc.Y;
+    double* __restrict__ res = dsc.res;
+    int* __restrict__ sel = dsc.sel;
+    RitzResult* __restrict__ rr = dsc.rr;
+    const double dup_rel = dsc.dup_rel;
     extern __shared__ double2 T[];  // p*p
     __shared__ double rc[kMaxKrylov];
     __shared__ double2 rs[kMaxKrylov];
@@ -185,38 +211,56 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const double2* __restrict__ H
             const double2 sc = cconj(s);
             const int nrow_only = (p - (kk + 2) > 0 ? p - (kk + 2) : 0);  // columns kk+2..p-1
             const int ncol_only = kk + (kk + 2 <= ihi ? 1 : 0);            // rows 0..kk-1, kk+2
-            const int items = 1 + nrow_only + ncol_only;
-            for (int t = lane; t < items; t += kHT) {
-                if (t == 0) {
-                    double2 a = T[kk * p + kk], b = T[kk * p + kk + 1];
-                    double2 d = T[(kk + 1) * p + kk], e = T[(kk + 1) * p + kk + 1];
-                    double2 a1 = cadd(cscale(a, c), cmul(s, d)), b1 = cadd(cscale(b, c), cmul(s, e));
-                    double2 d1 = csub(cscale(d, c), cmul(sc, a)), e1 = csub(cscale(e, c), cmul(sc, b));
-                    T[kk * p + kk] = cadd(cscale(a1, c), cmul(sc, b1));
-                    T[kk * p + kk + 1] = csub(cscale(b1, c), cmul(s, a1));
-                    T[(kk + 1) * p + kk] = cadd(cscale(d1, c), cmul(sc, e1));
-                    T[(kk + 1) * p + kk + 1] = csub(cscale(e1, c), cmul(s, d1));
-                    if (kk > l) {  // the annihilated bulge column
-                        T[kk * p + (kk - 1)] = cadd(cscale(x, c), cmul(s, y));
+            const int items = nrow_only + ncol_only;
+            // 2x2 block G B G^H, the annihilated bulge column and the last row of
+            // Z: every lane computes them (uniform control flow), lane 0 stores.
+            {
+                double2 a = T[kk * p + kk], b = T[kk * p + kk + 1];
+                double2 d = T[(kk + 1) * p + kk], e = T[(kk + 1) * p + kk + 1];
+                double2 za = zl[kk], zb = zl[kk + 1];
+                double2 a1 = cadd(cscale(a, c), cmul(s, d)), b1 = cadd(cscale(b, c), cmul(s, e));
+                double2 d1 = csub(cscale(d, c), cmul(sc, a)), e1 = csub(cscale(e, c), cmul(sc, b));
+                a = cadd(cscale(a1, c), cmul(sc, b1));
+                b = csub(cscale(b1, c), cmul(s, a1));
+                d = cadd(cscale(d1, c), cmul(sc, e1));
+                e = csub(cscale(e1, c), cmul(s, d1));
+                double2 xn = cadd(cscale(x, c), cmul(s, y));
+                double2 za1 = cadd(cscale(za, c), cmul(sc, zb)), zb1 = csub(cscale(zb, c), cmul(s, za));
+                if (lane == 0) {
+                    T[kk * p + kk] = a;
+                    T[kk * p + kk + 1] = b;
+                    T[(kk + 1) * p + kk] = d;
+                    T[(kk + 1) * p + kk + 1] = e;
+                    if (kk > l) {
+                        T[kk * p + (kk - 1)] = xn;
                         T[(kk + 1) * p + (kk - 1)] = cmk<double2>(0.0, 0.0);
                     }
-                    double2 za = zl[kk], zb = zl[kk + 1];
-                    zl[kk] = cadd(cscale(za, c), cmul(sc, zb));
-                    zl[kk + 1] = csub(cscale(zb, c), cmul(s, za));
+                    zl[kk] = za1;
+                    zl[kk + 1] = zb1;
                     rc[kk - l] = c;
                     rs[kk - l] = s;
-                } else if (t <= nrow_only) {
-                    const int col = kk + 1 + t;  // kk+2 ..
-                    double2 a = T[kk * p + col], b = T[(kk + 1) * p + col];
-                    T[kk * p + col] = cadd(cscale(a, c), cmul(s, b));
-                    T[(kk + 1) * p + col] = csub(cscale(b, c), cmul(sc, a));
-                } else {
-                    const int q = t - 1 - nrow_only;
-                    const int row = q < kk ? q : kk + 2;
-                    double2 a = T[row * p + kk], b = T[row * p + kk + 1];
-                    T[row * p + kk] = cadd(cscale(a, c), cmul(sc, b));
-                    T[row * p + kk + 1] = csub(cscale(b, c), cmul(s, a));
                 }
+            }
+            // one entry pair per lane: rows {kk, kk+1} at a column outside the
+            // block (left factor), or columns {kk, kk+1} at a row outside it
+            // (right factor); both are (u, v) -> (c u + s1 v, c v - s2 u)
+            for (int t = lane; t < items; t += kHT) {
+                const bool rowop = t < nrow_only;
+                int ia, ib;
+                if (rowop) {
+                    const int col = kk + 2 + t;
+                    ia = kk * p + col;
+                    ib = (kk + 1) * p + col;
+                } else {
+                    const int q = t - nrow_only;
+                    const int row = q < kk ? q : kk + 2;
+                    ia = row * p + kk;
+                    ib = row * p + kk + 1;
+                }
+                const double2 s1 = rowop ? s : sc, s2 = rowop ? sc : s;
+                const double2 u = T[ia], v = T[ib];
+                T[ia] = cadd(cscale(u, c), cmul(s1, v));
+                T[ib] = csub(cscale(v, c), cmul(s2, u));
             }
             __syncthreads();
         }
@@ -238,7 +282,7 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const double2* __restrict__ H
     }
 
     // ---- Ritz values and residuals ---------------------------------------------------------
-    const double beta = beta_dev ? beta_dev[0] : beta_val;
+    const double beta = dsc.scal[2];
     for (int i = lane; i < p; i += kHT) {
         mu[i] = T[i * p + i];
         double2* zc = S + (size_t)i * p;
@@ -321,17 +365,21 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const double2* __restrict__ H
 // wavefront per pair): solve (H - mu I) y = b with the Hessenberg LU (partial
 // pivoting between the two candidate rows of each column), twice, starting from
 // b = (1, ..., 1); normalise to ||y|| = 1.  Y[s*p + r].
-__global__ __launch_bounds__(kHT) void k_ritz_coords(const double2* __restrict__ H, int ldh, int p,
-                                                    const double2* __restrict__ mu, const int* __restrict__ sel,
-                                                    double2* __restrict__ Y) {
+__global__ __launch_bounds__(kHT) void k_ritz_coords(const KryDesc* __restrict__ Dv) {
+    const KryDesc& dsc = Dv[blockIdx.y];
+    const int sidx = blockIdx.x;
+    if (!dsc.ritz || sidx >= dsc.rr->nsel) return;
+    const int p = dsc.steps;
+    const double2* __restrict__ H = dsc.H;
+    const int ldh = dsc.ldh;
+    double2* __restrict__ Y = dsc.Y;
     extern __shared__ double2 A[];  // p*p, row-major
     __shared__ double2 b[kMaxKrylov];
     __shared__ int piv[kMaxKrylov];
     __shared__ double2 lmul[kMaxKrylov];
     __shared__ double red[kHT];
     const int lane = threadIdx.x;
-    const int sidx = blockIdx.x;
-    const double2 m = mu[sel[sidx]];
+    const double2 m = dsc.mu[dsc.sel[sidx]];
     double hn = 0.0;
     for (int e = lane; e < p * p; e += kHT) {
         int r = e / p, c = e % p;
@@ -395,9 +443,7 @@ __global__ __launch_bounds__(kHT) void k_ritz_coords(const double2* __restrict__
 
 }  // namespace
 
-tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta_dev, double beta_val,
-                            double2* Z, double2* S, double2* mu, double2* Y, double* res, int k, double tol,
-                            double dup_rel, int* sel, RitzResult* rr, hipStream_t s) {
+tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s) {
     if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Hessenberg size must be in [1, 96]");
     size_t lds = size_t(p) * p * sizeof(double2);
     static bool attr_set = false;
@@ -408,21 +454,17 @@ tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta
         TSK_HIP(hipFuncSetAttribute((const void*)k_ritz_coords, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
         attr_set = true;
     }
-    if (sel == nullptr)
-        hipLaunchKernelGGL(k_hess_ritz<true>, dim3(1), dim3(kHT), lds, s, H, ldh, p, beta_dev, beta_val, Z, S, mu,
-                           Y, res, k, tol, dup_rel, sel, rr);
+    if (full)
+        hipLaunchKernelGGL(k_hess_ritz<true>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
     else
-        hipLaunchKernelGGL(k_hess_ritz<false>, dim3(1), dim3(kHT), lds, s, H, ldh, p, beta_dev, beta_val, Z, S,
-                           mu, Y, res, k, tol, dup_rel, sel, rr);
+        hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }
 
-tsk_status ritz_coords_launch(const double2* H, int ldh, int p, const double2* mu, const int* sel, int nsel,
-                              double2* Y, hipStream_t s) {
-    if (nsel <= 0) return TSK_OK;
-    size_t lds = size_t(p) * p * sizeof(double2);
-    hipLaunchKernelGGL(k_ritz_coords, dim3(nsel), dim3(kHT), lds, s, H, ldh, p, mu, sel, Y);
+tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s) {
+    size_t lds = size_t(pmax) * pmax * sizeof(double2);
+    hipLaunchKernelGGL(k_ritz_coords, dim3(k, count), dim3(kHT), lds, s, D);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }

@@ -28,8 +28,11 @@
 #include <cmath>
 #include <vector>
 
+#include <cstring>
+
 #include "colfft.hpp"
 #include "fft.hpp"
+#include "krylov.hpp"
 #include "ops.hpp"
 
 namespace tsk {
@@ -47,23 +50,49 @@ template <int N> struct Geo {
     }
 };
 
+// One operator instance of a (batched) column-stepper launch.  The input of
+// step j is xbase + j * xstride (the Arnoldi basis vector v_j; xstride = 0 for a
+// plain matvec); `active` (optional) lets finished Arnoldi instances skip.
+template <typename real> struct ColInst {
+    const real* xbase;
+    int64_t xstride;
+    real* y;
+    const real* negU;
+    const real* dOdy;
+    double alpha, Re, dt, cprop;
+    int nsteps;
+    const int* active;
+};
+struct ColTask {
+    int inst;  // index into the instance table
+    int kx;    // dealiased column 0..M
+};
+
 // ---- the column time stepper ------------------------------------------------------------
 // Lane-owned positions: j = lane (< NB = N/RE) and slots r < RE hold the
 // y-index / FFT-order wavenumber index pos = j + r NB (colfft.hpp), for the
 // spectral state (jy = pos or pos - N, kept when |jy| <= M) and, after the
 // inverse transform, for the grid values at y = 2 pi pos / N.
 template <typename real, int N, bool PROP>
-__global__ __launch_bounds__(kWave) void k_colstep(const real* __restrict__ xin, real* __restrict__ yout,
-                                                   const real* __restrict__ negU, const real* __restrict__ dOdy,
-                                                   const cplx<real>* __restrict__ twg, double alpha, double Re,
-                                                   double dt, double cprop, int nsteps) {
+__global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColInst<real>* __restrict__ insts,
+                                                   const ColTask* __restrict__ tasks, const cplx<real>* __restrict__ twg,
+                                                   int jstep) {
     using C = cplx<real>;
     using G = Geo<N>;
     using PL = ColPlan<N>;
     constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
     static_assert(PL::NBL == 1, "one edge butterfly per lane");
+    const ColTask tk = tasks[blockIdx.x];
+    const ColInst<real>& I = insts ? insts[tk.inst] : one;
+    if (I.active && *I.active == 0) return;
+    const real* __restrict__ xin = I.xbase + jstep * I.xstride;
+    real* __restrict__ yout = I.y;
+    const real* __restrict__ negU = I.negU;
+    const real* __restrict__ dOdy = I.dOdy;
+    const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
+    const int nsteps = I.nsteps;
     const int lane = threadIdx.x;
-    const int kx = blockIdx.x;
+    const int kx = tk.kx;
 
     if (kx == 0) {
         // kx = 0: the advection term vanishes identically (d/dx of a y-only
@@ -280,29 +309,21 @@ __global__ __launch_bounds__(kWave) void k_rows_inv(const cplx<real>* __restrict
 struct KolmoLaunch {
     const void* x;
     void* y;
-    const void* negU;
-    const void* dOdy;
     const void* tw;
     void* Z;
-    double alpha, Re, dt, cprop;
-    int nsteps;
     hipStream_t s;
 };
 
 template <typename real, int N> struct KK {
     using C = cplx<real>;
-    static void colstep(const KolmoLaunch& a, bool prop) {
-        constexpr int M = Geo<N>::M;
+    static void colstep(const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
+                        bool prop, const void* tw, int jstep, hipStream_t s) {
         if (prop)
-            hipLaunchKernelGGL((k_colstep<real, N, true>), dim3(M + 1), dim3(kWave), 0, a.s,
-                               static_cast<const real*>(a.x), static_cast<real*>(a.y),
-                               static_cast<const real*>(a.negU), static_cast<const real*>(a.dOdy),
-                               static_cast<const C*>(a.tw), a.alpha, a.Re, a.dt, a.cprop, a.nsteps);
+            hipLaunchKernelGGL((k_colstep<real, N, true>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
+                               static_cast<const C*>(tw), jstep);
         else
-            hipLaunchKernelGGL((k_colstep<real, N, false>), dim3(M + 1), dim3(kWave), 0, a.s,
-                               static_cast<const real*>(a.x), static_cast<real*>(a.y),
-                               static_cast<const real*>(a.negU), static_cast<const real*>(a.dOdy),
-                               static_cast<const C*>(a.tw), a.alpha, a.Re, a.dt, a.cprop, a.nsteps);
+            hipLaunchKernelGGL((k_colstep<real, N, false>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
+                               static_cast<const C*>(tw), jstep);
     }
     static void fwd(const KolmoLaunch& a) {
         constexpr int M = Geo<N>::M;
@@ -332,9 +353,11 @@ bool kolmo_size_ok(int N) {
     }
 }
 
-template <typename real> void dispatch_colstep(int N, const KolmoLaunch& a, bool prop) {
+template <typename real>
+void dispatch_colstep(int N, const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
+                      bool prop, const void* tw, int jstep, hipStream_t s) {
     switch (N) {
-#define X(n) case n: KK<real, n>::colstep(a, prop); break;
+#define X(n) case n: KK<real, n>::colstep(one, insts, tasks, ntasks, prop, tw, jstep, s); break;
         TSK_KOLMO_SIZES(X)
 #undef X
     }
@@ -362,6 +385,7 @@ struct KolmoOp final : Operator {
     bool prop = false;
     double cprop = 0.0;
     DevBuf tw, negU, dOdy, Z;
+    DevBuf tasks;  // (0, kx) for kx = 0..M: the single-instance launch
 
     const char* name() const override { return "kolmo2d"; }
     int64_t physical_reals() const override { return int64_t(N) * N; }
@@ -389,20 +413,42 @@ struct KolmoOp final : Operator {
         }
         TSK_TRY(upload_real(tw, t));
         TSK_TRY(Z.ensure(size_t(N) * (M + 1) * 2 * rb()));
+        std::vector<ColTask> tk(M + 1);
+        for (int kx = 0; kx <= M; ++kx) tk[kx] = ColTask{0, kx};
+        TSK_TRY(tasks.ensure(tk.size() * sizeof(ColTask)));
+        TSK_HIP(hipMemcpy(tasks.ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
         return TSK_OK;
     }
 
     KolmoLaunch args(const void* x, void* y) const {
-        KolmoLaunch a{x, y, negU.ptr, dOdy.ptr, tw.ptr, Z.ptr, alpha, Re, dt, cprop, nsteps, stream};
+        KolmoLaunch a{x, y, tw.ptr, Z.ptr, stream};
         return a;
+    }
+
+    template <typename real> ColInst<real> inst(const void* xbase, int64_t xstride, void* y, const int* act) const {
+        ColInst<real> c;
+        c.xbase = static_cast<const real*>(xbase);
+        c.xstride = xstride;
+        c.y = static_cast<real*>(y);
+        c.negU = negU.as<real>();
+        c.dOdy = dOdy.as<real>();
+        c.alpha = alpha;
+        c.Re = Re;
+        c.dt = dt;
+        c.cprop = cprop;
+        c.nsteps = nsteps;
+        c.active = act;
+        return c;
     }
 
     tsk_status apply(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
-        KolmoLaunch a = args(x, y);
-        if (prec == TSK_FP32) dispatch_colstep<float>(N, a, prop);
-        else dispatch_colstep<double>(N, a, prop);
+        const ColTask* tk = tasks.as<ColTask>();
+        if (prec == TSK_FP32)
+            dispatch_colstep<float>(N, inst<float>(x, 0, y, nullptr), nullptr, tk, M + 1, prop, tw.ptr, 0, stream);
+        else
+            dispatch_colstep<double>(N, inst<double>(x, 0, y, nullptr), nullptr, tk, M + 1, prop, tw.ptr, 0, stream);
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
@@ -492,5 +538,86 @@ tsk_status kolmo_set_base_general(Operator* op, const double*, const double*, co
 }
 
 bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != nullptr; }
+
+// ---- batched matvec -----------------------------------------------------------------------------
+// One launch per (N, base kind) group: a task per (instance, kx column), all
+// instances of the batch in one instance table.
+struct KolmoBatch {
+    bool fp32 = false;
+    DevBuf insts;
+    struct Group {
+        int N;
+        bool prop;
+        const void* tw;
+        DevBuf tasks;
+        int ntasks;
+    };
+    std::vector<std::unique_ptr<Group>> groups;
+};
+
+tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, const KryDesc* Dd,
+                            KolmoBatchPtr* out) {
+    auto b = std::make_unique<KolmoBatch>();
+    std::vector<KolmoOp*> ko(count);
+    for (int i = 0; i < count; ++i) {
+        ko[i] = dynamic_cast<KolmoOp*>(ops[i]);
+        if (!ko[i]) return fail(TSK_EINVAL, "batched matvec needs Navier-Stokes operators");
+        if (ko[i]->prec != ko[0]->prec) return fail(TSK_EINVAL, "a batch must share one precision");
+    }
+    b->fp32 = ko[0]->prec == TSK_FP32;
+    const size_t isz = b->fp32 ? sizeof(ColInst<float>) : sizeof(ColInst<double>);
+    std::vector<char> host(isz * count);
+    for (int i = 0; i < count; ++i) {
+        const int* act = &Dd[i].active;  // device address of the instance's flag
+        if (b->fp32) {
+            ColInst<float> c = ko[i]->inst<float>(Dh[i].V, Dh[i].ldv, Dh[i].w, act);
+            std::memcpy(host.data() + isz * i, &c, isz);
+        } else {
+            ColInst<double> c = ko[i]->inst<double>(Dh[i].V, Dh[i].ldv, Dh[i].w, act);
+            std::memcpy(host.data() + isz * i, &c, isz);
+        }
+    }
+    TSK_TRY(b->insts.ensure(host.size()));
+    TSK_HIP(hipMemcpy(b->insts.ptr, host.data(), host.size(), hipMemcpyHostToDevice));
+    for (int i = 0; i < count; ++i) {
+        KolmoBatch::Group* g = nullptr;
+        for (auto& q : b->groups)
+            if (q->N == ko[i]->N && q->prop == ko[i]->prop) g = q.get();
+        if (!g) {
+            b->groups.push_back(std::make_unique<KolmoBatch::Group>());
+            g = b->groups.back().get();
+            g->N = ko[i]->N;
+            g->prop = ko[i]->prop;
+            g->tw = ko[i]->tw.ptr;
+            g->ntasks = 0;
+        }
+        g->ntasks += ko[i]->M + 1;
+    }
+    for (auto& g : b->groups) {
+        std::vector<ColTask> tk;
+        for (int i = 0; i < count; ++i)
+            if (ko[i]->N == g->N && ko[i]->prop == g->prop)
+                for (int kx = 0; kx <= ko[i]->M; ++kx) tk.push_back(ColTask{i, kx});
+        TSK_TRY(g->tasks.ensure(tk.size() * sizeof(ColTask)));
+        TSK_HIP(hipMemcpy(g->tasks.ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
+    }
+    out->reset(b.release());
+    return TSK_OK;
+}
+
+tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
+    for (auto& g : b->groups) {
+        if (b->fp32)
+            dispatch_colstep<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->tasks.as<ColTask>(),
+                                    g->ntasks, g->prop, g->tw, j, s);
+        else
+            dispatch_colstep<double>(g->N, ColInst<double>{}, b->insts.as<ColInst<double>>(),
+                                     g->tasks.as<ColTask>(), g->ntasks, g->prop, g->tw, j, s);
+    }
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+void kolmo_batch_free(KolmoBatch* b) { delete b; }
 
 }  // namespace tsk

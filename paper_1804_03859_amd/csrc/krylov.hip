@@ -40,6 +40,8 @@ __device__ inline double2 scale_by(double2 w, double s) { return cscale(w, s); }
 __device__ inline bool finite_of(double v) { return isfinite(v); }
 __device__ inline bool finite_of(float v) { return isfinite(v); }
 __device__ inline bool finite_of(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+__device__ inline double2 cgain(double2 y, double v) { return cscale(y, v); }
+__device__ inline double2 cgain(double2 y, double2 v) { return cmul(y, v); }
 
 __device__ inline double block_sum(double v, double* red) {
     v = wave_sum(v);
@@ -72,11 +74,24 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
 }
 
 template <typename TS>
-__global__ __launch_bounds__(kBT) void k_dot(const TS* __restrict__ V, int64_t ldv, int p, const TS* __restrict__ w,
-                                             int64_t n, double2* __restrict__ partial, double* __restrict__ pnrm) {
+__global__ __launch_bounds__(kBT) void k_check_finite(const KryDesc* __restrict__ Dv) {
+    const KryDesc& d = Dv[blockIdx.y];
+    const TS* x = static_cast<const TS*>(d.x0);
+    int bad = 0;
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(gridDim.x) * blockDim.x)
+        bad |= finite_of(x[g]) ? 0 : 1;
+    if (bad) atomicOr(reinterpret_cast<int*>(d.scal + 32), 1);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kBT) void k_dot(const KryDesc* __restrict__ Dv, int p, int from_x0) {
     using A = typename ET<TS>::A;
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active || int(blockIdx.x) >= d.nblk) return;
     __shared__ A wl[kChunk];
     __shared__ double red[kBT / kWave];
+    const TS* w = static_cast<const TS*>(from_x0 ? d.x0 : d.w);
+    const int64_t n = d.n;
     const int64_t base = int64_t(blockIdx.x) * kChunk;
     double s2 = 0.0;
 #pragma unroll
@@ -87,23 +102,25 @@ __global__ __launch_bounds__(kBT) void k_dot(const TS* __restrict__ V, int64_t l
         s2 += nrm2(x);
     }
     double t = block_sum(s2, red);
-    if (threadIdx.x == 0) pnrm[blockIdx.x] = t;
+    if (threadIdx.x == 0) d.pnrm[blockIdx.x] = t;
     __syncthreads();
-    chunk_dots(V, ldv, p, wl, base, n, partial);
+    chunk_dots(static_cast<const TS*>(d.V), d.ldv, p, wl, base, n, d.partial);
 }
 
 template <typename TS>
-__global__ __launch_bounds__(kBT) void k_update(const TS* __restrict__ V, int64_t ldv, int p,
-                                                const double2* __restrict__ h, const TS* __restrict__ w_in,
-                                                const typename ET<TS>::A* w64_in,  // may equal w64_out
-                                                typename ET<TS>::A* w64_out, int64_t n, int dot,
-                                                double2* __restrict__ partial, double* __restrict__ pnrm) {
+__global__ __launch_bounds__(kBT) void k_update(const KryDesc* __restrict__ Dv, int p, int from_w, int dot) {
     using A = typename ET<TS>::A;
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active || int(blockIdx.x) >= d.nblk) return;
     __shared__ A wl[kChunk];
     __shared__ double2 hl[kMaxKrylov + 1];
     __shared__ double red[kBT / kWave];
-    for (int i = threadIdx.x; i < p; i += kBT) hl[i] = h[i];
+    for (int i = threadIdx.x; i < p; i += kBT) hl[i] = d.h[i];
     __syncthreads();
+    const TS* V = static_cast<const TS*>(d.V);
+    const TS* w_in = static_cast<const TS*>(d.w);
+    A* w64 = static_cast<A*>(d.w64);  // read and written in place
+    const int64_t n = d.n, ldv = d.ldv;
     const int64_t base = int64_t(blockIdx.x) * kChunk;
     double s2 = 0.0;
 #pragma unroll
@@ -112,98 +129,117 @@ __global__ __launch_bounds__(kBT) void k_update(const TS* __restrict__ V, int64_
         int64_t g = base + l;
         A x = zero_of<A>();
         if (g < n) {
-            x = w64_in ? w64_in[g] : ET<TS>::acc(w_in[g]);
+            x = from_w ? ET<TS>::acc(w_in[g]) : w64[g];
             for (int i = 0; i < p; ++i) x = axmy(x, V[i * ldv + g], hl[i]);
-            w64_out[g] = x;
+            w64[g] = x;
         }
         wl[l] = x;
         s2 += nrm2(x);
     }
     double t = block_sum(s2, red);
-    if (threadIdx.x == 0) pnrm[blockIdx.x] = t;
+    if (threadIdx.x == 0) d.pnrm[blockIdx.x] = t;
     if (dot) {
         __syncthreads();
-        chunk_dots(V, ldv, p, wl, base, n, partial);
+        chunk_dots(V, ldv, p, wl, base, n, d.partial);
     }
 }
 
-__global__ void k_reduce(const double2* __restrict__ partial, int nblk, int p, double2* __restrict__ h,
-                         double2* __restrict__ Hcol, int first, const double* __restrict__ pnrm,
-                         double* __restrict__ scal, int slot) {
+__global__ void k_reduce(const KryDesc* __restrict__ Dv, int p, int col, int first, int slot) {
+    const KryDesc& d = Dv[blockIdx.x];
+    if (!d.active) return;
+    double2* Hcol = col >= 0 ? d.H + size_t(d.ldh) * col : nullptr;
     for (int i = threadIdx.x; i < p; i += blockDim.x) {
         double2 s = cmk<double2>(0.0, 0.0);
-        for (int b = 0; b < nblk; ++b) s = cadd(s, partial[size_t(b) * p + i]);
-        h[i] = s;
+        for (int b = 0; b < d.nblk; ++b) s = cadd(s, d.partial[size_t(b) * p + i]);
+        d.h[i] = s;
         if (Hcol) Hcol[i] = first ? s : cadd(Hcol[i], s);
     }
-    if (pnrm && threadIdx.x == 0) {
+    if (slot >= 0 && threadIdx.x == 0) {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += pnrm[b];
-        scal[slot] = s;
+        for (int b = 0; b < d.nblk; ++b) s += d.pnrm[b];
+        d.scal[slot] = s;
     }
 }
 
-__global__ void k_finalize(const double* __restrict__ pnrm, int nblk, const double* __restrict__ scal, int win_slot,
-                           double2* __restrict__ Hsub, double* __restrict__ beta_out, RitzResult* __restrict__ rr) {
-    if (threadIdx.x != 0) return;
+__global__ void k_finalize(const KryDesc* __restrict__ Dv, int j) {
+    const KryDesc& d = Dv[blockIdx.x];
+    if (!d.active || threadIdx.x != 0) return;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += pnrm[b];
-    double beta = sqrt(s);
-    double win = sqrt(scal[win_slot]);
-    *Hsub = cmk<double2>(beta, 0.0);
-    *beta_out = beta;
-    rr->beta = beta;
-    rr->w_in = win;
-    rr->nonfinite = !(isfinite(beta) && isfinite(win));
-    rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
+    for (int b = 0; b < d.nblk; ++b) s += d.pnrm[b];
+    const double beta = sqrt(s);
+    const double win = sqrt(d.scal[1]);
+    d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
+    d.scal[2] = beta;
+    d.rr->beta = beta;
+    d.rr->w_in = win;
+    d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
+    d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
 }
 
 template <typename TS>
-__global__ __launch_bounds__(kBT) void k_scale(const typename ET<TS>::A* __restrict__ w64,
-                                               const double* __restrict__ beta, TS* __restrict__ v, int64_t n) {
-    const double b = beta[0];
-    const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
-        v[g] = ET<TS>::store(scale_by(w64[g], inv));
-}
-
-template <typename TS>
-__global__ __launch_bounds__(kBT) void k_scale_state(const TS* __restrict__ x, const double* __restrict__ scal,
-                                                     int slot, TS* __restrict__ v, int64_t n) {
-    const double s2 = scal[slot];
-    const double inv = (s2 > 0.0 && isfinite(s2)) ? 1.0 / sqrt(s2) : 0.0;
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
-        v[g] = ET<TS>::store(scale_by(ET<TS>::acc(x[g]), inv));
-}
-
-template <typename TS>
-__global__ __launch_bounds__(kBT) void k_ritz(const TS* __restrict__ V, int64_t ldv, int p,
-                                              const double2* __restrict__ Y, const int* __restrict__ sel, int k,
-                                              double2* __restrict__ X, int64_t n) {
-    const int s = blockIdx.y;
-    const double2* y = Y + size_t(s) * p;  // unit Ritz coordinates of wanted pair s
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
-        double2 acc = cmk<double2>(0.0, 0.0);
-        for (int i = 0; i < p; ++i) {
-            typename ET<TS>::A v = ET<TS>::acc(V[i * ldv + g]);
-            if constexpr (sizeof(v) == sizeof(double)) acc = cadd(acc, cscale(y[i], double(v)));
-            else acc = cadd(acc, cmul(y[i], v));
-        }
-        X[size_t(s) * n + g] = acc;
+__global__ __launch_bounds__(kBT) void k_scale(const KryDesc* __restrict__ Dv, int j) {
+    using A = typename ET<TS>::A;
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active) return;
+    TS* V = static_cast<TS*>(d.V);
+    const int64_t n = d.n;
+    if (j >= 0) {
+        const double b = d.scal[2];
+        const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
+        const A* w64 = static_cast<const A*>(d.w64);
+        TS* v = V + (j + 1) * d.ldv;
+        for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+            v[g] = ET<TS>::store(scale_by(w64[g], inv));
+    } else {
+        const double s2 = d.scal[0];
+        const double inv = (s2 > 0.0 && isfinite(s2)) ? 1.0 / sqrt(s2) : 0.0;
+        const TS* x = static_cast<const TS*>(d.x0);
+        for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+            V[g] = ET<TS>::store(scale_by(ET<TS>::acc(x[g]), inv));
     }
 }
 
 template <typename TS>
-__global__ __launch_bounds__(kBT) void k_check_finite(const TS* __restrict__ x, int64_t n, int* __restrict__ flag) {
-    int bad = 0;
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
-        bad |= finite_of(x[g]) ? 0 : 1;
-    if (bad) atomicOr(flag, 1);
+__global__ __launch_bounds__(kBT) void k_ritz(const KryDesc* __restrict__ Dv) {
+    const KryDesc& d = Dv[blockIdx.z];
+    const int s = blockIdx.y;
+    if (!d.ritz || s >= d.rr->nsel) return;
+    const int p = d.steps;
+    const TS* V = static_cast<const TS*>(d.V);
+    const double2* y = d.Y + size_t(s) * p;  // unit Ritz coordinates of wanted pair s
+    double2* X = static_cast<double2*>(d.ritz);
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(gridDim.x) * blockDim.x) {
+        double2 acc = cmk<double2>(0.0, 0.0);
+        for (int i = 0; i < p; ++i) acc = cadd(acc, cgain(y[i], ET<TS>::acc(V[i * d.ldv + g])));
+        X[size_t(s) * d.n + g] = acc;
+    }
 }
 
-inline int grid_for(int64_t n) {
+__global__ void k_gather(const KryDesc* __restrict__ Dv, int k) {
+    // out: [mu re,im]*k | [lambda re,im]*k | [res]*k, zero beyond nsel
+    const KryDesc& d = Dv[blockIdx.x];
+    const int s = threadIdx.x;
+    if (s >= k) return;
+    const int nsel = d.rr->nsel;
+    double* out = d.out;
+    if (s >= nsel) {
+        out[2 * s] = out[2 * s + 1] = 0.0;
+        out[2 * k + 2 * s] = out[2 * k + 2 * s + 1] = 0.0;
+        out[4 * k + s] = 0.0;
+        return;
+    }
+    const int i = d.sel[s];
+    const double2 m = d.mu[i];
+    out[2 * s] = m.x;
+    out[2 * s + 1] = m.y;
+    out[2 * k + 2 * s] = log(hypot(m.x, m.y)) / d.T;
+    out[2 * k + 2 * s + 1] = atan2(m.y, m.x) / d.T;
+    out[4 * k + s] = d.res[i];
+}
+
+inline int grid_for(int64_t n, int cap) {
     int64_t b = (n + kBT - 1) / kBT;
-    if (b > 4096) b = 4096;
+    if (b > cap) b = cap;
     if (b < 1) b = 1;
     return int(b);
 }
@@ -211,62 +247,48 @@ inline int grid_for(int64_t n) {
 }  // namespace
 
 template <typename TS>
-void launch_dot(const TS* V, int64_t ldv, int p, const TS* w, int64_t n, double2* partial, double* pnrm,
-                hipStream_t s) {
-    hipLaunchKernelGGL(k_dot<TS>, dim3(cgs_blocks(n)), dim3(kBT), 0, s, V, ldv, p, w, n, partial, pnrm);
-}
-
-void launch_reduce(const double2* partial, int nblk, int p, double2* h, double2* Hcol, int first,
-                   const double* pnrm, double* scal, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(128), 0, s, partial, nblk, p, h, Hcol, first, pnrm, scal, slot);
+void launch_check_finite(const KryDesc* D, int count, int64_t nmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite<TS>, dim3(grid_for(nmax, 1024), count), dim3(kBT), 0, s, D);
 }
 
 template <typename TS>
-void launch_update(const TS* V, int64_t ldv, int p, const double2* h, const TS* w_in, const void* w64_in,
-                   void* w64_out, int64_t n, bool dot, double2* partial, double* pnrm, hipStream_t s) {
-    using A = typename ET<TS>::A;
-    hipLaunchKernelGGL(k_update<TS>, dim3(cgs_blocks(n)), dim3(kBT), 0, s, V, ldv, p, h, w_in,
-                       static_cast<const A*>(w64_in), static_cast<A*>(w64_out), n, dot ? 1 : 0, partial, pnrm);
+void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, from_x0 ? 1 : 0);
 }
 
-void launch_finalize(const double* pnrm, int nblk, const double* scal, int win_slot, double2* Hsub,
-                     double* beta_out, RitzResult* rr, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, pnrm, nblk, scal, win_slot, Hsub, beta_out, rr);
+void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(128), 0, s, D, p, col, first, slot);
 }
 
 template <typename TS>
-void launch_scale(const void* w64, const double* beta, TS* v, int64_t n, hipStream_t s) {
-    using A = typename ET<TS>::A;
-    hipLaunchKernelGGL(k_scale<TS>, dim3(grid_for(n)), dim3(kBT), 0, s, static_cast<const A*>(w64), beta, v, n);
+void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w, bool dot, hipStream_t s) {
+    hipLaunchKernelGGL(k_update<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, from_w ? 1 : 0, dot ? 1 : 0);
+}
+
+void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(count), dim3(64), 0, s, D, j);
 }
 
 template <typename TS>
-void launch_scale_state(const TS* x, const double* scal, int slot, TS* v, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_state<TS>, dim3(grid_for(n)), dim3(kBT), 0, s, x, scal, slot, v, n);
+void launch_scale(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale<TS>, dim3(grid_for(nmax, 1024), count), dim3(kBT), 0, s, D, j);
 }
 
 template <typename TS>
-void launch_ritz_vectors(const TS* V, int64_t ldv, int p, const double2* Y, const int* sel, int k, double2* X,
-                         int64_t n, hipStream_t s) {
-    int gx = grid_for(n);
-    if (gx > 1024) gx = 1024;
-    hipLaunchKernelGGL(k_ritz<TS>, dim3(gx, k), dim3(kBT), 0, s, V, ldv, p, Y, sel, k, X, n);
+void launch_ritz_vectors(const KryDesc* D, int count, int64_t nmax, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_ritz<TS>, dim3(grid_for(nmax, 1024), k, count), dim3(kBT), 0, s, D);
 }
 
-template <typename TS>
-void launch_check_finite(const TS* x, int64_t n, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_finite<TS>, dim3(grid_for(n)), dim3(kBT), 0, s, x, n, flag);
+void launch_gather(const KryDesc* D, int count, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(count), dim3(128), 0, s, D, k);
 }
 
-#define TSK_INST(TS)                                                                                              \
-    template void launch_dot<TS>(const TS*, int64_t, int, const TS*, int64_t, double2*, double*, hipStream_t);    \
-    template void launch_update<TS>(const TS*, int64_t, int, const double2*, const TS*, const void*, void*,       \
-                                    int64_t, bool, double2*, double*, hipStream_t);                               \
-    template void launch_scale<TS>(const void*, const double*, TS*, int64_t, hipStream_t);                       \
-    template void launch_scale_state<TS>(const TS*, const double*, int, TS*, int64_t, hipStream_t);              \
-    template void launch_ritz_vectors<TS>(const TS*, int64_t, int, const double2*, const int*, int, double2*,    \
-                                          int64_t, hipStream_t);                                                  \
-    template void launch_check_finite<TS>(const TS*, int64_t, int*, hipStream_t);
+#define TSK_INST(TS)                                                                                 \
+    template void launch_check_finite<TS>(const KryDesc*, int, int64_t, hipStream_t);               \
+    template void launch_dot<TS>(const KryDesc*, int, int, int, bool, hipStream_t);                  \
+    template void launch_update<TS>(const KryDesc*, int, int, int, bool, bool, hipStream_t);         \
+    template void launch_scale<TS>(const KryDesc*, int, int64_t, int, hipStream_t);                  \
+    template void launch_ritz_vectors<TS>(const KryDesc*, int, int64_t, int, hipStream_t);
 TSK_INST(double)
 TSK_INST(float)
 TSK_INST(double2)

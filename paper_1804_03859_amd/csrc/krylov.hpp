@@ -1,5 +1,6 @@
 // Krylov-basis kernels of the Arnoldi driver: classical Gram-Schmidt applied
-// twice (CGS2), norms, normalisation and Ritz vectors.
+// twice (CGS2), norms, normalisation and Ritz vectors, for a batch of
+// independent Arnoldi instances advancing in lockstep.
 //
 // Algorithm 1 (Sec. 3.2.1) projects the new matvec output w on the basis once,
 // h = V^T w, f = w - V h; here the projection is repeated (h1 + h2), the usual
@@ -8,12 +9,13 @@
 // kernel streams V once with coalesced loads; sums are accumulated in FP64
 // (complex128 for complex states) whatever the storage type of V.
 //
-// Work split: blocks of kBT = 256 threads own contiguous chunks of kChunk = 1024
+// Work split: blockIdx.y selects the instance (its descriptor holds every
+// pointer); blocks of kBT = 256 threads own contiguous chunks of kChunk = 1024
 // elements.  A dot pass stages the chunk of w in LDS, then each of the four
 // wavefronts takes every fourth basis vector, reads its chunk coalesced and
 // reduces the 64 lane sums with cross-lane shuffles.  Per-block partial sums are
-// reduced in a fixed order by a one-block kernel, so results are bitwise
-// reproducible run to run.
+// reduced in a fixed order by one block per instance, so results are bitwise
+// reproducible run to run and independent of the batch composition.
 #pragma once
 
 #include "common.hpp"
@@ -26,37 +28,58 @@ constexpr int kEPT = kChunk / kBT;
 
 inline int cgs_blocks(int64_t n) { return int((n + kChunk - 1) / kChunk); }
 
+// One Arnoldi instance, as seen by the device.  Scalars in `scal`:
+// [0] ||x0||^2, [1] ||w before projection||^2, [2] beta; int flag at scal+32.
+struct KryDesc {
+    void* V;            // (m+1) vectors of the state type, stride ldv
+    void* w;            // matvec output (state type)
+    void* w64;          // FP64 / complex128 working copy of w
+    double2* H;         // (m+1) x m complex128, column-major, leading dim ldh
+    double2* partial;   // nblk x (m+1) partial dots
+    double* pnrm;       // nblk partial squared norms
+    double2* h;         // m+1 reduced coefficients
+    double* scal;       // 64 device scalars
+    double2* Z;         // eigensolver scratch (p x p, standalone use)
+    double2* S;         // eigenvectors of T (p x p)
+    double2* Y;         // unit Ritz coordinates of the wanted pairs (p x k)
+    double2* mu;        // Ritz values (p)
+    double* res;        // residual estimates (p)
+    int* sel;           // wanted indices (k)
+    RitzResult* rr;
+    const void* x0;     // start vector (state type)
+    void* ritz;         // optional Ritz vectors, n x k complex128 (may be null)
+    double* out;        // gathered outputs: mu (2k), lambda (2k), residual (k)
+    int64_t ldv, n;
+    int ldh, nblk;
+    int active;         // 0: instance finished, kernels skip it
+    int steps;          // Arnoldi steps taken (set before the output kernels)
+    double dup_rel;     // duplicate width of the wanted-set rule (0 for FP64)
+    double T;           // sampling period (lambda = log(mu)/T)
+};
+
 // Host launchers; TS = double, float (real states) or double2 (complex).
-// Pass 1: partial[b*p + i] = sum_chunk conj(V_i) w ; pnrm[b] = sum_chunk |w|^2.
+// Grids: x over chunks of the longest instance, y over `count` instances.
 template <typename TS>
-void launch_dot(const TS* V, int64_t ldv, int p, const TS* w, int64_t n, double2* partial, double* pnrm,
-                hipStream_t s);
-// Reduce partials: h[i] = sum_b partial[b*p+i]; Hcol[i] = (first ? 0 : Hcol[i]) + h[i];
-// scal[slot] = sum_b pnrm[b] when pnrm != null.
-void launch_reduce(const double2* partial, int nblk, int p, double2* h, double2* Hcol, int first,
-                   const double* pnrm, double* scal, int slot, hipStream_t s);
-// Pass 2/3: w64 = w - V h (w read as TS when w64_in == null, else from w64_in);
-// DOT: also partial dots of V^H w64; always pnrm = |w64|^2 partials.
+void launch_check_finite(const KryDesc* D, int count, int64_t nmax, hipStream_t s);  // x0 -> scal+32
+// Pass 1: partials of conj(V_i) . src and |src|^2, src = x0 (p = 0) or w.
 template <typename TS>
-void launch_update(const TS* V, int64_t ldv, int p, const double2* h, const TS* w_in,
-                   const void* w64_in, void* w64_out, int64_t n, bool dot, double2* partial, double* pnrm,
-                   hipStream_t s);
+void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, hipStream_t s);
+// Reduce partials: h = sum_b partial; H column col (if col >= 0) = (first ? 0 : H) + h;
+// scal[slot] = sum_b pnrm when slot >= 0.
+void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s);
+// Pass 2/3: w64 = src - V h, src = w (state type) or w64; dot: partials of V^H w64;
+// always partial |w64|^2.
+template <typename TS>
+void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w, bool dot, hipStream_t s);
 // beta = sqrt(sum pnrm); H[j+1, j] = beta; breakdown / non-finite flags.
-void launch_finalize(const double* pnrm, int nblk, const double* scal, int win_slot, double2* Hsub,
-                     double* beta_out, RitzResult* rr, hipStream_t s);
-// v = w64 / beta (stored as TS).
+void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s);
+// V_{j+1} = w64 / beta (j >= 0), or V_0 = x0 / ||x0|| (j < 0).
 template <typename TS>
-void launch_scale(const void* w64, const double* beta, TS* v, int64_t n, hipStream_t s);
-// v = x / ||x|| from a state vector x (norm from scal[slot]).
+void launch_scale(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s);
+// ritz[s*n + e] = sum_i V_i[e] Y[s*p + i] for the nsel wanted pairs, p = steps.
 template <typename TS>
-void launch_scale_state(const TS* x, const double* scal, int slot, TS* v, int64_t n, hipStream_t s);
-// X[s*n + e] = sum_i V_i[e] Y[s*p + i] (Y: unit Ritz coordinates of the k
-// wanted pairs, in wanted order), complex128 output.
-template <typename TS>
-void launch_ritz_vectors(const TS* V, int64_t ldv, int p, const double2* Y, const int* sel, int k,
-                         double2* X, int64_t n, hipStream_t s);
-// Check a vector for NaN/Inf: flag[0] |= 1.
-template <typename TS>
-void launch_check_finite(const TS* x, int64_t n, int* flag, hipStream_t s);
+void launch_ritz_vectors(const KryDesc* D, int count, int64_t nmax, int k, hipStream_t s);
+// out: mu, lambda = log(mu)/T, residual of the wanted pairs.
+void launch_gather(const KryDesc* D, int count, int k, hipStream_t s);
 
 }  // namespace tsk

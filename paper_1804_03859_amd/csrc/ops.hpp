@@ -47,15 +47,20 @@ struct ArnoldiWork {
     DevBuf pnrm;      // per-block partial squared norms
     DevBuf h;         // reduced projection coefficients
     DevBuf scal;      // device scalars
-    DevBuf eigZ, eigS, eigY, eigMu, eigRes, sel;  // Hessenberg eigensolver
+    DevBuf eigS, eigY, eigMu, eigRes, sel;  // Hessenberg eigensolver
     DevBuf rr;        // RitzResult
+    DevBuf out;       // gathered outputs (mu, lambda, residual)
     DevBuf phys;      // physical field scratch (seeded start vector)
-    RitzResult* rr_host = nullptr;  // pinned
+    int m = 0, steps = 0;
+    int64_t ldv = 0;
+    // Owned by the first operator of a batch (the only one for a single run):
+    DevBuf batch_desc;                 // KryDesc table
+    DevBuf batch_rr;                   // RitzResult of every instance, contiguous
+    RitzResult* rr_host = nullptr;     // pinned copy of batch_rr
+    int rr_host_count = 0;
     std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
     hipEvent_t ev_cgs = nullptr;       // basis vector j+1 and H column j ready
     hipStream_t side = nullptr;        // Ritz analysis overlaps the next matvec
-    int m = 0, steps = 0;
-    int64_t ldv = 0;
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
         for (hipEvent_t e : ev_apply) (void)hipEventDestroy(e);
@@ -99,24 +104,40 @@ tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V
 bool is_kolmo(const Operator* op);
 bool is_cgle(const Operator* op);
 
-// Arnoldi driver (arnoldi.hip).
-tsk_status arnoldi(Operator* op, int m, int k, double tol, const void* v0, uint64_t seed, double* mu_ri,
-                   double* lam_ri, double* resid, void* ritz, tsk_arnoldi_info* info);
+// Batched Navier-Stokes matvec of Arnoldi step j: x = V_j, y = w for every
+// active instance of the descriptor table (kolmo.hip).
+struct KryDesc;
+struct KolmoBatch;
+void kolmo_batch_free(KolmoBatch* b);
+struct KolmoBatchDeleter {
+    void operator()(KolmoBatch* b) const { kolmo_batch_free(b); }
+};
+using KolmoBatchPtr = std::unique_ptr<KolmoBatch, KolmoBatchDeleter>;
+tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* D_host, const KryDesc* D_dev,
+                            KolmoBatchPtr* out);
+tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s);
 
-// Device Hessenberg eigensolver + wanted-set selection (hessenberg.hip).
-// Launches on `s`.  sel/rr may be null (no selection).
-tsk_status hess_ritz_launch(const double2* H, int ldh, int p, const double* beta_dev, double beta_val,
-                            double2* Z, double2* S, double2* mu, double2* Y, double* res, int k, double tol,
-                            double dup_rel, int* sel, RitzResult* rr, hipStream_t s);
+// Arnoldi driver (arnoldi.hip): `count` independent instances in lockstep.
+// Per instance i: v0s[i] (nullable array / entry), seeds[i] (nullable array:
+// seed i), outputs at mu_ri + 2k i, lam_ri + 2k i, resid + k i, ritz[i]
+// (nullable array / entry), infos[i].  Returns the first negative status of a
+// global failure; per-instance outcomes are in infos[i].status.
+tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
+                         const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
+                         tsk_arnoldi_info* infos);
+
+// Device Hessenberg eigensolver + wanted-set selection (hessenberg.hip), one
+// wavefront per instance of the descriptor table (H, scal[2] = beta, scratch).
+// full = true: accumulate all of Z and form every eigenvector (standalone use).
+struct KryDesc;
+tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s);
+// Unit Ritz coordinates of the wanted pairs (inverse iteration on H_p): Y[s*p + r].
+// Needs the attribute set by a prior hess_ritz_launch.
+tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s);  // p = steps
 
 // Relative width below which two Ritz values of an FP32-state run are taken as
 // copies of one eigenvalue (64 unit roundoffs of FP32).
 constexpr double kDupRelFp32 = 64.0 * 5.9604644775390625e-08;
-
-// Unit Ritz coordinates of the nsel wanted pairs (inverse iteration on H_p):
-// Y[s*p + r].  Needs the attribute set by a prior hess_ritz_launch.
-tsk_status ritz_coords_launch(const double2* H, int ldh, int p, const double2* mu, const int* sel, int nsel,
-                              double2* Y, hipStream_t s);
 
 // Normal draws (rng.hip).
 tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);

@@ -58,6 +58,8 @@ def load():
         "tsk_to_physical": [vp, vp, vp],
         "tsk_apply": [vp, vp, vp],
         "tsk_arnoldi": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), P(f64), vp, P(ArnoldiInfo)],
+        "tsk_batch_arnoldi": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(f64), P(vp),
+                              P(ArnoldiInfo)],
         "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
         "tsk_last_basis": [vp, P(vp), P(i64)],
         "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
@@ -81,7 +83,8 @@ def exported_symbols():
     """Names the binding expects the library to export (all of include/tsk.h)."""
     return ["tsk_create_cgle1d", "tsk_set_params_cgle", "tsk_create_kolmo2d", "tsk_set_params_kolmo",
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_state_dim",
-            "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_last_hessenberg",
+            "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
+            "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error"]
 
@@ -233,6 +236,44 @@ def arnoldi(op, m, k, tol, v0=None, seed=0, want_vectors=False):
                beta=info.beta, ms_total=info.ms_total, ms_apply=info.ms_apply)
     if X is not None:
         out["X"] = X[:nr]
+    return out
+
+
+def batch_arnoldi(ops, m, k, tol, v0s=None, seeds=None, want_vectors=False):
+    """Run tsk_batch_arnoldi on a list of operators (same state type and stream).
+    Returns a list of dicts like ``arnoldi`` (X when want_vectors)."""
+    import numpy as np
+    count = len(ops)
+    if v0s is not None:
+        for op, v in zip(ops, v0s):
+            if v is not None:
+                _need(v, op.n, op.state_dtype, "v0")
+    hs = (C.c_void_p * count)(*[op.h for op in ops])
+    v0p = None
+    if v0s is not None:
+        v0p = (C.c_void_p * count)(*[(v.data_ptr() if v is not None else None) for v in v0s])
+    sp = None
+    if seeds is not None:
+        sp = (C.c_uint64 * count)(*[int(x) for x in seeds])
+    mu = np.zeros(2 * k * count)
+    lam = np.zeros(2 * k * count)
+    res = np.zeros(k * count)
+    Xs = [torch.zeros((k, op.n), dtype=torch.complex128, device="cuda") for op in ops] if want_vectors else None
+    rp = (C.c_void_p * count)(*[x.data_ptr() for x in Xs]) if Xs else None
+    infos = (ArnoldiInfo * count)()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    _check(load().tsk_batch_arnoldi(hs, count, m, k, tol, v0p, sp, pd(mu), pd(lam), pd(res), rp, infos))
+    out = []
+    for i in range(count):
+        f = infos[i]
+        nr = f.n_ritz
+        o = dict(mu=(mu[2 * k * i:2 * k * (i + 1):2] + 1j * mu[2 * k * i + 1:2 * k * (i + 1):2])[:nr],
+                 lam=(lam[2 * k * i:2 * k * (i + 1):2] + 1j * lam[2 * k * i + 1:2 * k * (i + 1):2])[:nr],
+                 res=res[k * i:k * (i + 1)][:nr], status=f.status, n_matvec=f.n_matvec, n_ritz=nr,
+                 n_converged=f.n_converged, beta=f.beta, ms_total=f.ms_total, ms_apply=f.ms_apply)
+        if Xs:
+            o["X"] = Xs[i][:nr]
+        out.append(o)
     return out
 
 

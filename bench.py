@@ -65,6 +65,26 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
+def measured_traffic(profile_name):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0] in ("source_hash", "traffic_bytes_per_launch"):
+            rec[parts[0]] = parts[1]
+    h = hashlib.sha256()
+    for f in ("common.hpp", "fft.hpp", "colfft.hpp", "kolmo.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1804_03859_amd", "csrc", f), "rb").read())
+    if rec.get("source_hash") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in rec:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def _flops_for(N, nsteps):
     return colstep_flops(N, nsteps)
 
@@ -187,7 +207,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kolmo128",
-                    choices=["kolmo128", "kolmo512-fp32", "sweep"])
+                    choices=["kolmo128", "kolmo512-fp32", "sweep", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -208,8 +228,24 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "kolmo128":
         out = run_single(args, tsk, W, np, torch, W.KOLMO_128_FP64, tsk.TSK_FP64, "f64")
+        out["roofline"]["traffic"] = measured_traffic("k_colstep_kolmo128_fp64_hbm_traffic.md")
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline()
+    elif args.workload == "copy":
+        # calibration of the HBM byte counters: plain device copies of a known size
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out = {"metric": "copy calibration", "value": 2 * nbytes * args.steps / el / 1e9, "unit": "GB/s",
+               "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes, "steps": args.steps}
     elif args.workload == "kolmo512-fp32":
         out = run_single(args, tsk, W, np, torch, W.KOLMO_512_FP32, tsk.TSK_FP32, "f32")
     else:

@@ -70,6 +70,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     const hipStream_t s = lead->stream;
     ArnoldiWork& L = lead->aw;
     const double dup_rel = lead->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
+    const double res_floor = lead->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
 
     // ---- per-instance workspace and descriptors ------------------------------------
     std::vector<KryDesc> Dh(count);
@@ -124,6 +125,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         d.nblk = nblk;
         d.active = 1;
         d.dup_rel = dup_rel;
+        d.res_floor = res_floor;
         d.T = op->T;
         nmax = std::max(nmax, n);
         nblk_max = std::max(nblk_max, nblk);

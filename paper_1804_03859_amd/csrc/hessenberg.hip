@@ -32,8 +32,9 @@
 // value that lies within its residual of a converged or an already accepted
 // value, accept the rest; done when the first k accepted are converged.  With
 // dup_rel > 0 (FP32 states) values closer than dup_rel |mu| to an accepted or
-// converged one also count as copies of it: FP32 rounding splits a multiple
-// eigenvalue into a cluster of that width, each member of which converges.
+// converged one also count as copies of it (FP32 rounding splits a multiple
+// eigenvalue into a cluster of about that width), and a pair counts as
+// converged below max(tol, res_floor |mu|), the FP32 floor of the estimate.
 #include "krylov.hpp"
 #include "ops.hpp"
 
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
     int* __restrict__ sel = dsc.sel;
     RitzResult* __restrict__ rr = dsc.rr;
     const double dup_rel = dsc.dup_rel;
+    const double res_floor = dsc.res_floor;
     extern __shared__ double2 T[];  // p*p
     __shared__ double rc[kMaxKrylov];
     __shared__ double2 rs[kMaxKrylov];
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
     __shared__ int order[kMaxKrylov];
     __shared__ int dupc[kMaxKrylov];
     __shared__ double znrm[kMaxKrylov];
+    __shared__ double ctol[kMaxKrylov];  // per Ritz value convergence threshold
     const int lane = threadIdx.x;
 
     for (int e = lane; e < p * p; e += kHT) {
@@ -310,6 +313,9 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
         return;
     } else {
         // ---- wanted set ------------------------------------------------------------------------
+        // converged: res <= max(tol, res_floor |mu|)
+        for (int i = lane; i < p; i += kHT) ctol[i] = fmax(tol, res_floor * cabs(mu[i]));
+        __syncthreads();
         for (int i = lane; i < p; i += kHT) {
             double mi = cabs(mu[i]), ai = atan2(mu[i].y, mu[i].x);
             int rank = 0;
@@ -321,10 +327,10 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
             }
             order[rank] = i;
             int d = 0;
-            if (!(res[i] <= tol)) {
+            if (!(res[i] <= ctol[i])) {
                 const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
                 for (int j = 0; j < p; ++j)
-                    if (j != i && res[j] <= tol && cabs(csub(mu[i], mu[j])) <= rad) d = 1;
+                    if (j != i && res[j] <= ctol[j] && cabs(csub(mu[i], mu[j])) <= rad) d = 1;
             }
             dupc[i] = d;
         }
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
             int nsel = 0, nconv = 0;
             for (int t = 0; t < p && nsel < k; ++t) {
                 int i = order[t];
-                bool conv = res[i] <= tol;
+                bool conv = res[i] <= ctol[i];
                 bool take;
                 if (conv) {
                     // a converged copy of an accepted value (only with dup_rel > 0)

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <vector>
 
+#include <algorithm>
 #include <cstring>
 
 #include "colfft.hpp"
@@ -551,8 +552,19 @@ struct KolmoBatch {
         const void* tw;
         DevBuf tasks;
         int ntasks;
+        double work;
     };
     std::vector<std::unique_ptr<Group>> groups;
+    // groups after the first run on their own streams (default priority),
+    // forked from and joined back into the caller's stream
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
+    ~KolmoBatch() {
+        for (hipStream_t q : aux) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : done) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, const KryDesc* Dd,
@@ -593,6 +605,20 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
         }
         g->ntasks += ko[i]->M + 1;
     }
+    for (auto& g : b->groups) g->work = double(g->ntasks) * g->N * std::log2(double(g->N));
+    std::sort(b->groups.begin(), b->groups.end(),
+              [](const std::unique_ptr<KolmoBatch::Group>& x, const std::unique_ptr<KolmoBatch::Group>& y) {
+                  return x->work > y->work;
+              });
+    for (size_t q = 1; q < b->groups.size(); ++q) {
+        hipStream_t st;
+        hipEvent_t ev;
+        TSK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->aux.push_back(st);
+        TSK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->done.push_back(ev);
+    }
+    if (b->groups.size() > 1) TSK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     for (auto& g : b->groups) {
         std::vector<ColTask> tk;
         for (int i = 0; i < count; ++i)
@@ -606,15 +632,22 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
 }
 
 tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
-    for (auto& g : b->groups) {
+    const size_t G = b->groups.size();
+    if (G > 1) TSK_HIP(hipEventRecord(b->fork, s));
+    for (size_t q = 0; q < G; ++q) {
+        auto& g = b->groups[q];
+        hipStream_t st = q == 0 ? s : b->aux[q - 1];
+        if (q > 0) TSK_HIP(hipStreamWaitEvent(st, b->fork, 0));
         if (b->fp32)
             dispatch_colstep<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->tasks.as<ColTask>(),
-                                    g->ntasks, g->prop, g->tw, j, s);
+                                    g->ntasks, g->prop, g->tw, j, st);
         else
             dispatch_colstep<double>(g->N, ColInst<double>{}, b->insts.as<ColInst<double>>(),
-                                     g->tasks.as<ColTask>(), g->ntasks, g->prop, g->tw, j, s);
+                                     g->tasks.as<ColTask>(), g->ntasks, g->prop, g->tw, j, st);
+        TSK_HIP(hipGetLastError());
+        if (q > 0) TSK_HIP(hipEventRecord(b->done[q - 1], st));
     }
-    TSK_HIP(hipGetLastError());
+    for (size_t q = 1; q < G; ++q) TSK_HIP(hipStreamWaitEvent(s, b->done[q - 1], 0));
     return TSK_OK;
 }
 

@@ -54,6 +54,7 @@ struct KryDesc {
     int active;         // 0: instance finished, kernels skip it
     int steps;          // Arnoldi steps taken (set before the output kernels)
     double dup_rel;     // duplicate width of the wanted-set rule (0 for FP64)
+    double res_floor;   // relative residual floor: converged when res <= max(tol, res_floor |mu|)
     double T;           // sampling period (lambda = log(mu)/T)
 };
 

@@ -135,9 +135,15 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
 // Needs the attribute set by a prior hess_ritz_launch.
 tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s);  // p = steps
 
-// Relative width below which two Ritz values of an FP32-state run are taken as
-// copies of one eigenvalue (64 unit roundoffs of FP32).
-constexpr double kDupRelFp32 = 64.0 * 5.9604644775390625e-08;
+// FP32-state runs (the precision form).  The basis is rounded to FP32, so the
+// Arnoldi relation, and with it the residual estimate, holds only to about
+// u32 ||M||: a Ritz pair counts as converged once its estimate is below
+// max(tol, kResFloorFp32 |mu|), kResFloorFp32 = 32 u32.  FP32 rounding also splits
+// every multiple eigenvalue into a cluster; Ritz values closer than
+// kDupRelFp32 |mu| (the stated FP32 eigenvalue accuracy, 2e-5) are copies of one
+// eigenvalue.  FP64 runs use 0 for both (the rule of the Arnoldi stop test).
+constexpr double kResFloorFp32 = 32.0 * 5.9604644775390625e-08;
+constexpr double kDupRelFp32 = 2e-5;
 
 // Normal draws (rng.hip).
 tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);

@@ -22,7 +22,11 @@ arXiv:1804.03859, that it follows):
                      wanted set and stop rule, lambda = log(mu)/T (Sec. 3.2).
 * ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
                      definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
-* ``mlp``         -- FP64 forward/backward of the start-vector MLP.
+* ``mlp``         -- start-vector network (not in the paper): FP64 forward,
+                     backward and Adam with the GPU's bfloat16 rounding points.
+* ``learned``     -- packed spectral coordinates, the low-mode block target
+                     made from Ritz vectors, and the start vector assembled
+                     from a prediction (Algorithm 1 takes any start vector).
 
 Parity status of every function is stated in its module header.
 """

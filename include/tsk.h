@@ -186,6 +186,65 @@ tsk_status tsk_last_basis(tsk_op op, const void** V_dev, int64_t* ld);
 tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta,
                                void* mu_dev, void* Y_dev, void* res_dev, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned start vector (not part of the paper).  Algorithm 1 (Sec. 3.2.1)
+ * takes any start vector; one close to the wanted invariant subspace shortens
+ * the Krylov sequence.  A three-layer perceptron maps (Re, alpha) of a
+ * Navier-Stokes operator with a parallel base flow to the 32 x 32 block of low
+ * Fourier coefficients jx in [0, 32), jy in [-16, 16) of the packed state: 2048
+ * reals, index 2 (32 jx + jy + 16) + c (c = 0 re, 1 im).  Block positions that
+ * a state does not hold (jx = 0 with jy <= 0; |jx| or |jy| > M) are ignored.
+ *
+ * Network: x = 2 (p - in_lo) / (in_hi - in_lo) - 1 for p = (Re, alpha);
+ * A1 = tanh(x W1 + b1), A2 = tanh(A1 W2 + b2), Y = A2 W3 + b3, width W.
+ * FP32 master parameters, flat layout W1 [2][W], b1 [W], W2 [W][W], b2 [W],
+ * W3 [W][2048], b3 [2048] (weights row-major [in][out]), 2048 + W (W + 2052)
+ * floats.  Layers 2 and 3 and their backward products use bfloat16 copies of
+ * weights and activations (round to nearest even) with FP32 accumulation on
+ * the matrix cores.  Loss L = sum (Y - target)^2 / (batch 2048).  Training is
+ * full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * The network runs on its own stream (NULL = default), except tsk_mlp_start,
+ * which runs on the operator's stream after waiting for the network's.
+ * ------------------------------------------------------------------------- */
+typedef struct tsk_mlp_s* tsk_mlp;
+/* width: multiple of 16 in [16, 2048] (512 for the learned start).
+ * in_lo/in_hi: host, 2 doubles each: the (Re, alpha) box mapped onto [-1, 1]^2. */
+tsk_status tsk_mlp_create(tsk_mlp* net, int width, const double* in_lo, const double* in_hi, void* hip_stream);
+tsk_status tsk_mlp_param_count(tsk_mlp net, int64_t* count);
+/* Xavier-uniform weights (element e of the flat vector from splitmix64 output e
+ * of `seed`: u = (o >> 11) 2^-53, w = l (2u - 1), l = sqrt(6/(fan_in+fan_out))),
+ * zero biases; resets the optimizer. */
+tsk_status tsk_mlp_init(tsk_mlp net, uint64_t seed);
+/* Host copies of the flat FP32 parameters; set resets the optimizer. */
+tsk_status tsk_mlp_set_params(tsk_mlp net, const float* params_host);
+tsk_status tsk_mlp_get_params(tsk_mlp net, float* params_host);
+/* in_dev: batch x 2 floats (Re, alpha); out_dev: batch x 2048 floats.
+ * 1 <= batch <= 4096.  Asynchronous on the network's stream. */
+tsk_status tsk_mlp_forward(tsk_mlp net, const float* in_dev, int batch, float* out_dev);
+/* Loss and full gradient (flat layout, dev, may be NULL) without an update. */
+tsk_status tsk_mlp_gradients(tsk_mlp net, const float* in_dev, const float* target_dev, int batch,
+                             float* grad_dev, double* loss_host);
+/* `steps` full-batch Adam steps with learning rate lr; loss_host (NULL or
+ * `steps` doubles) receives the loss before each update. */
+tsk_status tsk_mlp_train(tsk_mlp net, const float* in_dev, const float* target_dev, int batch, int steps,
+                         double lr, double* loss_host);
+/* Training target (2048 floats, dev) from k Ritz vectors of a Navier-Stokes
+ * operator (ritz_dev as written by tsk_arnoldi; use_host: k flags or NULL =
+ * all).  Per used vector: its real part (imaginary part if larger), block
+ * coefficients, canonical x-translation making the largest coefficient real
+ * positive (sign only when it sits at jx = 0; ties within 1e-6 relative go to
+ * the lowest slot), unit norm; the sum is scaled to unit norm (zero if no
+ * vector had block content).  Synchronous on the operator's stream. */
+tsk_status tsk_ritz_block_target(tsk_op op, const void* ritz_dev, int k, const int* use_host,
+                                 float* target_dev);
+/* Start vector (state, dev) for a Navier-Stokes operator: the prediction p for
+ * (Re, alpha) scattered into the state, v0 = p/||p|| + gamma r/||r|| with r the
+ * seeded random state of tsk_arnoldi; the random start r/||r|| alone when ||p||
+ * is zero or not finite (*used_net = 0, else 1).  gamma >= 0. */
+tsk_status tsk_mlp_start(tsk_mlp net, tsk_op op, double Re, double alpha, double gamma, uint64_t seed,
+                         void* v0_dev, int* used_net);
+void tsk_mlp_destroy(tsk_mlp net);
+
 /* iid N(0,1) draws (device, FP64): count values of the splitmix64 +
  * Box-Muller stream of `seed` (element e uses outputs 2*(e/2), 2*(e/2)+1). */
 tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream);

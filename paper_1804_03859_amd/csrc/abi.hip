@@ -16,6 +16,11 @@ struct tsk_op_s {
     std::unique_ptr<tsk::Operator> op;
 };
 
+struct tsk_mlp_s {
+    tsk::Mlp* net = nullptr;
+    ~tsk_mlp_s() { tsk::mlp_free(net); }
+};
+
 namespace tsk {
 
 namespace {
@@ -46,6 +51,9 @@ using namespace tsk;
 
 #define TSK_NEED(op)                                                                   \
     if (!(op) || !(op)->op) return fail(TSK_EINVAL, "null operator handle");
+
+#define TSK_NEED_NET(h)                                                                \
+    if (!(h) || !(h)->net) return fail(TSK_EINVAL, "null network handle");
 
 extern "C" {
 
@@ -253,6 +261,102 @@ tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* 
         if (!out_dev || count < 0) return fail(TSK_EINVAL, "bad output buffer or count");
         return normal_fill(out_dev, count, seed, static_cast<hipStream_t>(hip_stream));
     })
+}
+
+tsk_status tsk_mlp_create(tsk_mlp* out, int width, const double* in_lo, const double* in_hi, void* hip_stream) {
+    TSK_GUARD({
+        if (!out || !in_lo || !in_hi) return fail(TSK_EINVAL, "null argument");
+        *out = nullptr;
+        Mlp* n = nullptr;
+        TSK_TRY(mlp_create(width, in_lo, in_hi, static_cast<hipStream_t>(hip_stream), &n));
+        auto* h = new tsk_mlp_s;
+        h->net = n;
+        *out = h;
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_mlp_param_count(tsk_mlp net, int64_t* count) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!count) return fail(TSK_EINVAL, "null argument");
+        *count = mlp_param_count(net->net);
+        return TSK_OK;
+    })
+}
+
+tsk_status tsk_mlp_init(tsk_mlp net, uint64_t seed) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        return mlp_init(net->net, seed);
+    })
+}
+
+tsk_status tsk_mlp_set_params(tsk_mlp net, const float* params_host) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!params_host) return fail(TSK_EINVAL, "null parameter array");
+        return mlp_set_params(net->net, params_host);
+    })
+}
+
+tsk_status tsk_mlp_get_params(tsk_mlp net, float* params_host) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!params_host) return fail(TSK_EINVAL, "null parameter array");
+        return mlp_get_params(net->net, params_host);
+    })
+}
+
+tsk_status tsk_mlp_forward(tsk_mlp net, const float* in_dev, int batch, float* out_dev) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!in_dev || !out_dev) return fail(TSK_EINVAL, "null buffer");
+        return mlp_forward(net->net, in_dev, batch, out_dev);
+    })
+}
+
+tsk_status tsk_mlp_gradients(tsk_mlp net, const float* in_dev, const float* target_dev, int batch, float* grad_dev,
+                             double* loss_host) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!in_dev || !target_dev) return fail(TSK_EINVAL, "null buffer");
+        return mlp_gradients(net->net, in_dev, target_dev, batch, grad_dev, loss_host);
+    })
+}
+
+tsk_status tsk_mlp_train(tsk_mlp net, const float* in_dev, const float* target_dev, int batch, int steps, double lr,
+                         double* loss_host) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        if (!in_dev || !target_dev) return fail(TSK_EINVAL, "null buffer");
+        return mlp_train(net->net, in_dev, target_dev, batch, steps, lr, loss_host);
+    })
+}
+
+tsk_status tsk_ritz_block_target(tsk_op op, const void* ritz_dev, int k, const int* use_host, float* target_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!ritz_dev || !target_dev) return fail(TSK_EINVAL, "null buffer");
+        return ritz_block_target(op->op.get(), ritz_dev, k, use_host, target_dev);
+    })
+}
+
+tsk_status tsk_mlp_start(tsk_mlp net, tsk_op op, double Re, double alpha, double gamma, uint64_t seed, void* v0_dev,
+                         int* used_net) {
+    TSK_GUARD({
+        TSK_NEED_NET(net);
+        TSK_NEED(op);
+        if (!v0_dev) return fail(TSK_EINVAL, "null start-vector buffer");
+        return mlp_start(net->net, op->op.get(), Re, alpha, gamma, seed, v0_dev, used_net);
+    })
+}
+
+void tsk_mlp_destroy(tsk_mlp net) {
+    try {
+        delete net;
+    } catch (...) {
+    }
 }
 
 void tsk_destroy(tsk_op op) {

@@ -72,6 +72,14 @@ __host__ __device__ inline double2 csqrt(double2 z) {
     return cmk<double2>(fabs(z.y) / (2.0 * t), copysign(t, z.y));
 }
 
+// ---- splitmix64 (Steele, Lea & Flood, OOPSLA 2014), counter form ----------------
+// Output i of the stream seeded with `seed`.
+__host__ __device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
 // ---- wavefront reductions (device) -------------------------------------------
 __device__ inline double wave_sum(double v) {
 #pragma unroll

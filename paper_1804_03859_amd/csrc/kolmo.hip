@@ -540,6 +540,11 @@ tsk_status kolmo_set_base_general(Operator* op, const double*, const double*, co
 
 bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != nullptr; }
 
+int kolmo_cutoff(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k ? k->M : -1;
+}
+
 // ---- batched matvec -----------------------------------------------------------------------------
 // One launch per (N, base kind) group: a task per (instance, kx column), all
 // instances of the batch in one instance table.

@@ -102,6 +102,8 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
 tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
                                   const double* Oy);
 bool is_kolmo(const Operator* op);
+// Largest kept wavenumber M = (N-1)/3 of a Navier-Stokes operator, -1 for others.
+int kolmo_cutoff(const Operator* op);
 bool is_cgle(const Operator* op);
 
 // Batched Navier-Stokes matvec of Arnoldi step j: x = V_j, y = w for every
@@ -145,6 +147,20 @@ tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipS
 constexpr double kResFloorFp32 = 32.0 * 5.9604644775390625e-08;
 constexpr double kDupRelFp32 = 2e-5;
 
+// Learned start vector (mlp.hip): network object and entry points.
+struct Mlp;
+tsk_status mlp_create(int width, const double* lo, const double* hi, hipStream_t s, Mlp** out);
+void mlp_free(Mlp* n);
+int64_t mlp_param_count(const Mlp* n);
+tsk_status mlp_init(Mlp* n, uint64_t seed);
+tsk_status mlp_set_params(Mlp* n, const float* host);
+tsk_status mlp_get_params(Mlp* n, float* host);
+tsk_status mlp_forward(Mlp* n, const float* in, int B, float* out);
+tsk_status mlp_gradients(Mlp* n, const float* in, const float* target, int B, float* grad, double* loss_host);
+tsk_status mlp_train(Mlp* n, const float* in, const float* target, int B, int steps, double lr, double* loss_host);
+tsk_status ritz_block_target(Operator* op, const void* ritz, int k, const int* use, float* target);
+tsk_status mlp_start(Mlp* n, Operator* op, double Re, double alpha, double gamma, uint64_t seed, void* v0,
+                     int* used);
 // Normal draws (rng.hip).
 tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);
 // out[i] = float(in[i]); out may alias the front of in.

@@ -14,13 +14,6 @@ namespace tsk {
 
 namespace {
 
-__device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t i) {
-    uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ull;
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
 __global__ void k_normal(double* __restrict__ out, int64_t count, uint64_t seed) {
     const int64_t npair = (count + 1) / 2;
     for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < npair; q += int64_t(gridDim.x) * blockDim.x) {

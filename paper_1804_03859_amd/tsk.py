@@ -64,6 +64,16 @@ def load():
         "tsk_last_basis": [vp, P(vp), P(i64)],
         "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
         "tsk_normal_fill": [vp, i64, u64, vp],
+        "tsk_mlp_create": [P(vp), i32, P(f64), P(f64), vp],
+        "tsk_mlp_param_count": [vp, P(i64)],
+        "tsk_mlp_init": [vp, u64],
+        "tsk_mlp_set_params": [vp, vp],
+        "tsk_mlp_get_params": [vp, vp],
+        "tsk_mlp_forward": [vp, vp, i32, vp],
+        "tsk_mlp_gradients": [vp, vp, vp, i32, vp, P(f64)],
+        "tsk_mlp_train": [vp, vp, vp, i32, i32, f64, P(f64)],
+        "tsk_ritz_block_target": [vp, vp, i32, P(i32), vp],
+        "tsk_mlp_start": [vp, vp, f64, f64, f64, u64, vp, P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -71,6 +81,8 @@ def load():
         f.restype = C.c_int
     lib.tsk_destroy.argtypes = [vp]
     lib.tsk_destroy.restype = None
+    lib.tsk_mlp_destroy.argtypes = [vp]
+    lib.tsk_mlp_destroy.restype = None
     lib.tsk_status_str.argtypes = [C.c_int]
     lib.tsk_status_str.restype = C.c_char_p
     lib.tsk_last_error.argtypes = []
@@ -86,7 +98,9 @@ def exported_symbols():
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
-            "tsk_last_error"]
+            "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
+            "tsk_mlp_get_params", "tsk_mlp_forward", "tsk_mlp_gradients", "tsk_mlp_train",
+            "tsk_ritz_block_target", "tsk_mlp_start", "tsk_mlp_destroy"]
 
 
 def _check(st, allow_positive=True):
@@ -316,3 +330,111 @@ def normal_fill(count, seed, stream=None):
     out = torch.zeros(count, dtype=torch.float64, device="cuda")
     _check(load().tsk_normal_fill(C.c_void_p(out.data_ptr()), count, C.c_uint64(seed), _stream(stream)))
     return out
+
+
+# ---- learned start vector ------------------------------------------------------------------
+MLP_OUT = 2048
+
+
+class Mlp:
+    """Owning wrapper of a tsk_mlp handle."""
+
+    def __init__(self, handle, width):
+        self.h = handle
+        self.width = width
+        n = C.c_int64()
+        _check(load().tsk_mlp_param_count(self.h, C.byref(n)))
+        self.param_count = n.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tsk_mlp_destroy(self.h)
+            self.h = None
+
+
+def mlp_create(width=512, in_lo=(5.0, 0.25), in_hi=(40.0, 1.0), stream=None):
+    h = C.c_void_p()
+    lo, plo = _dbl(in_lo)
+    hi, phi = _dbl(in_hi)
+    if lo.size != 2 or hi.size != 2:
+        raise ValueError("in_lo and in_hi hold (Re, alpha)")
+    _check(load().tsk_mlp_create(C.byref(h), int(width), plo, phi, _stream(stream)))
+    return Mlp(h, int(width))
+
+
+def mlp_init(net, seed):
+    _check(load().tsk_mlp_init(net.h, C.c_uint64(seed)))
+
+
+def mlp_set_params(net, params):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != net.param_count:
+        raise ValueError(f"expected {net.param_count} parameters, got {a.size}")
+    _check(load().tsk_mlp_set_params(net.h, C.c_void_p(a.ctypes.data)))
+
+
+def mlp_get_params(net):
+    import numpy as np
+    a = np.zeros(net.param_count, dtype=np.float32)
+    _check(load().tsk_mlp_get_params(net.h, C.c_void_p(a.ctypes.data)))
+    return a
+
+
+def _batch_inputs(inputs):
+    if not isinstance(inputs, torch.Tensor) or not inputs.is_cuda or inputs.dtype != torch.float32 \
+            or inputs.dim() != 2 or inputs.shape[1] != 2 or not inputs.is_contiguous():
+        raise ValueError("inputs: contiguous float32 CUDA/HIP tensor of shape (batch, 2) holding (Re, alpha)")
+    return inputs.shape[0]
+
+
+def mlp_forward(net, inputs):
+    B = _batch_inputs(inputs)
+    out = torch.empty((B, MLP_OUT), dtype=torch.float32, device=inputs.device)
+    _check(load().tsk_mlp_forward(net.h, _ptr(inputs), B, _ptr(out)))
+    return out
+
+
+def mlp_gradients(net, inputs, targets):
+    B = _batch_inputs(inputs)
+    _need(targets, B * MLP_OUT, torch.float32, "targets")
+    grad = torch.empty(net.param_count, dtype=torch.float32, device=inputs.device)
+    loss = C.c_double()
+    _check(load().tsk_mlp_gradients(net.h, _ptr(inputs), _ptr(targets), B, _ptr(grad), C.byref(loss)))
+    return grad, loss.value
+
+
+def mlp_train(net, inputs, targets, steps, lr):
+    import numpy as np
+    B = _batch_inputs(inputs)
+    _need(targets, B * MLP_OUT, torch.float32, "targets")
+    losses = np.zeros(int(steps))
+    _check(load().tsk_mlp_train(net.h, _ptr(inputs), _ptr(targets), B, int(steps), float(lr),
+                                losses.ctypes.data_as(C.POINTER(C.c_double))))
+    return losses
+
+
+def ritz_block_target(op, ritz, use=None):
+    """Training target (2048 float32 on the device) from Ritz vectors (k x n
+    complex128 tensor, as returned by arnoldi(..., want_vectors=True))."""
+    if ritz.dim() != 2 or ritz.shape[1] != op.n:
+        raise ValueError("ritz: (k, n) complex128 tensor")
+    k = ritz.shape[0]
+    _need(ritz, k * op.n, torch.complex128, "ritz")
+    up = None
+    if use is not None:
+        if len(use) != k:
+            raise ValueError("use: one flag per Ritz vector")
+        up = (C.c_int * k)(*[1 if u else 0 for u in use])
+    out = torch.empty(MLP_OUT, dtype=torch.float32, device=ritz.device)
+    _check(load().tsk_ritz_block_target(op.h, _ptr(ritz), k, up, _ptr(out)))
+    return out
+
+
+def mlp_start(net, op, Re, alpha, gamma=0.1, seed=0):
+    """Learned start vector for op at (Re, alpha); returns (state tensor, used_net)."""
+    v0 = op.new_state()
+    used = C.c_int()
+    _check(load().tsk_mlp_start(net.h, op.h, float(Re), float(alpha), float(gamma), C.c_uint64(seed),
+                                _ptr(v0), C.byref(used)))
+    return v0, bool(used.value)

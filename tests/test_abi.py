@@ -41,3 +41,22 @@ def test_status_strings_and_invalid_handles_without_gpu():
     assert lib.tsk_state_dim(None, ctypes.byref(n), None, None) == t.TSK_EINVAL
     assert b"null" in lib.tsk_last_error()
     assert lib.tsk_apply(None, None, None) == t.TSK_EINVAL
+
+
+def test_network_entry_points_reject_null_handles_without_gpu():
+    _ensure_built()
+    lib = t.load()
+    n = ctypes.c_int64()
+    assert lib.tsk_mlp_param_count(None, ctypes.byref(n)) == t.TSK_EINVAL
+    assert lib.tsk_mlp_init(None, 0) == t.TSK_EINVAL
+    assert lib.tsk_mlp_forward(None, None, 1, None) == t.TSK_EINVAL
+    assert lib.tsk_mlp_train(None, None, None, 1, 1, 1e-3, None) == t.TSK_EINVAL
+    assert lib.tsk_ritz_block_target(None, None, 1, None, None) == t.TSK_EINVAL
+    assert lib.tsk_mlp_start(None, None, 20.0, 0.5, 0.1, 0, None, None) == t.TSK_EINVAL
+    lo = (ctypes.c_double * 2)(5.0, 0.25)
+    hi = (ctypes.c_double * 2)(40.0, 1.0)
+    h = ctypes.c_void_p()
+    # width check happens before any allocation
+    assert lib.tsk_mlp_create(ctypes.byref(h), 100, lo, hi, None) == t.TSK_EINVAL
+    assert b"width" in lib.tsk_last_error()
+    lib.tsk_mlp_destroy(None)

@@ -40,6 +40,27 @@ def batch_sweep(count=64, seed=0):
     return out
 
 
+# Learned start vector: the network is trained on Ritz vectors of the sweep
+# instances (same recipe, six wanted pairs, the number the held-out runs ask
+# for) and judged on held-out (Re, alpha) at 256^2 FP32, m = 96, k = 6.
+LEARNED_IN_LO = (5.0, 0.25)
+LEARNED_IN_HI = (40.0, 1.0)
+
+
+def learned_training_sweep(count=64, seed=0):
+    out = batch_sweep(count, seed)
+    for c in out:
+        c["k"] = 6
+    return out
+
+
+def learned_holdout(count=16, seed=1000):
+    rng = np.random.default_rng(seed)
+    Re = rng.uniform(5.0, 40.0, size=count)
+    return [dict(N=256, alpha=BATCH_ALPHAS[i % 4], Re=float(Re[i]), dt=0.005, T=1.0, n_forcing=4,
+                 m=96, k=6, tol=1e-8, precision="fp32") for i in range(count)]
+
+
 # ---- seeded draws -------------------------------------------------------------
 def normal_real(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)

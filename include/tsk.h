@@ -182,7 +182,8 @@ tsk_status tsk_last_basis(tsk_op op, const void** V_dev, int64_t* ld);
  * dimension ldh (>= p); beta: residual scale.  Outputs (dev): mu_dev (p
  * complex128), Y_dev (p x p complex128, column-major, unit-norm columns),
  * res_dev (p doubles, beta |Y[p-1, i]|).  1 <= p <= 96.  Synchronous on
- * hip_stream.  Returns TSK_EEIG if the QR iteration failed to converge. */
+ * hip_stream.  Returns TSK_EEIG if the QR iteration failed to converge and
+ * TSK_ENONFINITE (outputs not written) if H or beta holds a NaN or Inf. */
 tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta,
                                void* mu_dev, void* Y_dev, void* res_dev, void* hip_stream);
 

@@ -251,6 +251,7 @@ tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta, v
         RitzResult h{};
         TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
         TSK_HIP(hipStreamSynchronize(s));
+        if (h.nonfinite) return fail(TSK_ENONFINITE, "H or beta is not finite");
         if (h.eig_fail) return fail(TSK_EEIG, "Hessenberg QR did not converge");
         return TSK_OK;
     })

@@ -13,14 +13,20 @@
 //
 // Overlap: as soon as v_{j+1} exists, the matvec M v_{j+1} is launched on the
 // operator stream while the Ritz analysis of H_j runs on a side stream (one
-// wavefront per instance, so it barely competes for compute units).  The host
-// waits only for the side stream; an instance whose H_j already satisfies the
-// stop test is marked inactive and its speculative matvec is discarded (neither
-// counted nor used).  Batched Navier-Stokes instances share one launch per grid
-// size for the matvec; kernels of the Gram-Schmidt and Ritz phases index the
-// instance by blockIdx.
+// wavefront per instance, so it barely competes for compute units).  The
+// analyses of consecutive steps rotate over kSlots side streams with their own
+// output buffers, so when an analysis takes longer than a matvec, later steps
+// (CGS2 and matvec) keep the operator stream busy while up to kSlots analyses
+// are in flight.  The host consumes the analyses in step order and stops an
+// instance at the first step whose H_j satisfies the stop test, exactly as a
+// check after every step would; work already launched for later steps is
+// discarded (neither counted nor used).  Batched Navier-Stokes instances share
+// one launch per grid size for the matvec; kernels of the Gram-Schmidt and
+// Ritz phases index the instance by blockIdx.
 #include <chrono>
 #include <cstring>
+#include <deque>
+#include <thread>
 #include <vector>
 
 #include "krylov.hpp"
@@ -41,13 +47,20 @@ __global__ void k_collect(const KryDesc* __restrict__ Dv, int count, RitzResult*
     }
 }
 
-__global__ void k_reset(const KryDesc* __restrict__ Dv, int count) {
+// Zero H, the start-vector flag and the RitzResult of every slot table.
+__global__ void k_reset(const KryDesc* __restrict__ Dv, int count, int nslots) {
     const KryDesc& d = Dv[blockIdx.x];
     for (int i = threadIdx.x; i < d.ldh * (d.ldh - 1); i += blockDim.x) d.H[i] = cmk<double2>(0.0, 0.0);
     if (threadIdx.x == 0) {
-        *d.rr = RitzResult{};
+        for (int t = 0; t < nslots; ++t) *Dv[size_t(t) * count + blockIdx.x].rr = RitzResult{};
         *reinterpret_cast<int*>(d.scal + 32) = 0;
     }
+}
+
+// Instance i has stopped: every slot table marks it inactive.
+__global__ void k_deactivate(KryDesc* __restrict__ Dv, int count, int nslots, int i) {
+    if (threadIdx.x == 0)
+        for (int t = 0; t < nslots; ++t) Dv[size_t(t) * count + i].active = 0;
 }
 
 template <typename TS> struct WorkType { using A = double; };
@@ -71,6 +84,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     ArnoldiWork& L = lead->aw;
     const double dup_rel = lead->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
     const double res_floor = lead->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
+    constexpr int NS = ArnoldiWork::kSlots;
 
     // ---- per-instance workspace and descriptors ------------------------------------
     std::vector<KryDesc> Dh(count);
@@ -90,13 +104,13 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
         TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
         TSK_TRY(W.scal.ensure(64 * sizeof(double)));
-        TSK_TRY(W.eigS.ensure(size_t(m) * m * sizeof(double2)));
+        TSK_TRY(W.eigS.ensure(size_t(NS) * m * m * sizeof(double2)));
         TSK_TRY(W.eigY.ensure(size_t(m) * (k > 0 ? k : 1) * sizeof(double2)));
-        TSK_TRY(W.eigMu.ensure(size_t(m) * sizeof(double2)));
-        TSK_TRY(W.eigRes.ensure(size_t(m) * sizeof(double)));
-        TSK_TRY(W.sel.ensure(size_t(m) * sizeof(int)));
+        TSK_TRY(W.eigMu.ensure(size_t(NS) * m * sizeof(double2)));
+        TSK_TRY(W.eigRes.ensure(size_t(NS) * m * sizeof(double)));
+        TSK_TRY(W.sel.ensure(size_t(NS) * m * sizeof(int)));
         TSK_TRY(W.out.ensure(5 * size_t(k) * sizeof(double)));
-        TSK_TRY(W.rr.ensure(sizeof(RitzResult)));
+        TSK_TRY(W.rr.ensure(size_t(NS) * sizeof(RitzResult)));
         W.m = m;
         W.steps = 0;
         W.ldv = ldv;
@@ -135,17 +149,33 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         TSK_HIP(hipEventCreate(&e));
         L.ev_apply.push_back(e);
     }
-    if (!L.ev_cgs) TSK_HIP(hipEventCreateWithFlags(&L.ev_cgs, hipEventDisableTiming));
-    if (!L.side) TSK_HIP(hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking));
-    const hipStream_t s2 = L.side;
-    TSK_TRY(L.batch_rr.ensure(size_t(count) * sizeof(RitzResult)));
-    if (L.rr_host_count < count) {
+    for (int t = 0; t < NS; ++t) {
+        if (!L.ev_cgs[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_cgs[t], hipEventDisableTiming));
+        if (!L.ev_eig[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_eig[t], hipEventDisableTiming));
+        if (!L.side[t]) TSK_HIP(hipStreamCreateWithFlags(&L.side[t], hipStreamNonBlocking));
+    }
+    TSK_TRY(L.batch_rr.ensure(size_t(NS) * count * sizeof(RitzResult)));
+    if (L.rr_host_count < NS * count) {
         if (L.rr_host) (void)hipHostFree(L.rr_host);
         L.rr_host = nullptr;
-        TSK_HIP(hipHostMalloc((void**)&L.rr_host, size_t(count) * sizeof(RitzResult), 0));
-        L.rr_host_count = count;
+        TSK_HIP(hipHostMalloc((void**)&L.rr_host, size_t(NS) * count * sizeof(RitzResult), 0));
+        L.rr_host_count = NS * count;
     }
     RitzResult* rrh = L.rr_host;
+    // slot tables: identical except for the eigensolver outputs
+    std::vector<KryDesc> Dall(size_t(NS) * count);
+    for (int t = 0; t < NS; ++t)
+        for (int i = 0; i < count; ++i) {
+            KryDesc d = Dh[i];
+            ArnoldiWork& W = ops[i]->aw;
+            d.S = W.eigS.as<double2>() + size_t(t) * m * m;
+            d.mu = W.eigMu.as<double2>() + size_t(t) * m;
+            d.res = W.eigRes.as<double>() + size_t(t) * m;
+            d.sel = W.sel.as<int>() + size_t(t) * m;
+            d.rr = W.rr.as<RitzResult>() + t;
+            Dall[size_t(t) * count + i] = d;
+        }
+    for (int i = 0; i < count; ++i) Dh[i] = Dall[i];
 
     // ---- start vectors (Algorithm 1: v1 = v / ||v||) -----------------------------------
     for (int i = 0; i < count; ++i) {
@@ -162,10 +192,13 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         }
         Dh[i].x0 = x0;
     }
-    TSK_TRY(L.batch_desc.ensure(size_t(count) * sizeof(KryDesc)));
+    for (int t = 0; t < NS; ++t)
+        for (int i = 0; i < count; ++i) Dall[size_t(t) * count + i].x0 = Dh[i].x0;
+    TSK_TRY(L.batch_desc.ensure(size_t(NS) * count * sizeof(KryDesc)));
     KryDesc* D = L.batch_desc.as<KryDesc>();
-    TSK_HIP(hipMemcpyAsync(D, Dh.data(), size_t(count) * sizeof(KryDesc), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count);
+    auto table = [&](int t) { return D + size_t(t) * count; };
+    TSK_HIP(hipMemcpyAsync(D, Dall.data(), size_t(NS) * count * sizeof(KryDesc), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count, NS);
     launch_check_finite<TS>(D, count, nmax, s);
     launch_dot<TS>(D, count, nblk_max, 0, true, s);
     launch_reduce(D, count, 0, -1, 0, 0, s);
@@ -192,38 +225,49 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     };
 
     // ---- Arnoldi steps ------------------------------------------------------------------------
-    TSK_HIP(hipEventRecord(L.ev_apply[0], s));
-    TSK_TRY(matvec(0));
-    TSK_HIP(hipEventRecord(L.ev_apply[1], s));
-    int remaining = count;
-    int steps_run = 0;
-    for (int j = 0; j < m && remaining > 0; ++j) {
-        const int p = j + 1;
-        launch_dot<TS>(D, count, nblk_max, p, false, s);
-        launch_reduce(D, count, p, j, 1, 1, s);
-        launch_update<TS>(D, count, nblk_max, p, true, true, s);
-        launch_reduce(D, count, p, j, 0, -1, s);
-        launch_update<TS>(D, count, nblk_max, p, false, false, s);
-        launch_finalize(D, count, j, s);
-        launch_scale<TS>(D, count, nmax, j, s);
-        TSK_HIP(hipEventRecord(L.ev_cgs, s));
-        if (j + 1 < m) {  // speculative matvec of the next step
+    // enqueue(j): CGS2 of step j (table j % NS), the speculative matvec of step
+    // j+1, and the Ritz analysis of H_j on side stream j % NS.  Pending analyses
+    // are consumed in step order; a new step is enqueued when the analyses are
+    // consumed, or, while up to NS are in flight, as soon as the operator stream
+    // has finished the last matvec it was given.
+    std::vector<int> final_slot(count, 0);
+    std::deque<int> pend;
+    int next = 0, steps_run = 0, remaining = count;
+    auto enqueue = [&](int j) -> tsk_status {
+        const int p = j + 1, t = j % NS;
+        const KryDesc* Dt = table(t);
+        launch_dot<TS>(Dt, count, nblk_max, p, false, s);
+        launch_reduce(Dt, count, p, j, 1, 1, s);
+        launch_update<TS>(Dt, count, nblk_max, p, true, true, s);
+        launch_reduce(Dt, count, p, j, 0, -1, s);
+        launch_update<TS>(Dt, count, nblk_max, p, false, false, s);
+        launch_finalize(Dt, count, j, s);
+        launch_scale<TS>(Dt, count, nmax, j, s);
+        TSK_HIP(hipEventRecord(L.ev_cgs[t], s));
+        if (j + 1 < m) {
             TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
             TSK_TRY(matvec(j + 1));
             TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1) + 1], s));
         }
-        TSK_HIP(hipStreamWaitEvent(s2, L.ev_cgs, 0));
-        const int kk = k < p ? k : p;
-        TSK_TRY(hess_ritz_launch(D, count, p, kk, tol, false, s2));
-        hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s2, D, count, L.batch_rr.as<RitzResult>(), 0);
-        TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s2));
-        TSK_HIP(hipStreamSynchronize(s2));
+        const hipStream_t st = L.side[t];
+        TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[t], 0));
+        TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st));
+        hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, Dt, count,
+                           L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
+        TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,
+                               size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, st));
+        TSK_HIP(hipEventRecord(L.ev_eig[t], st));
+        pend.push_back(j);
+        return TSK_OK;
+    };
+    auto consume = [&](int j) {
+        const int p = j + 1, t = j % NS, kk = k < p ? k : p;
         steps_run = p;
-        bool changed = false;
         for (int i = 0; i < count; ++i) {
             if (oc[i].done) continue;
             oc[i].steps = p;
-            const RitzResult& r = rrh[i];
+            final_slot[i] = t;
+            const RitzResult& r = rrh[size_t(t) * count + i];
             int st = 0;
             if (r.nonfinite) { st = TSK_ENONFINITE; oc[i].err = "non-finite matvec output or norm"; }
             else if (r.eig_fail) { st = TSK_EEIG; oc[i].err = "Hessenberg QR did not converge"; }
@@ -233,12 +277,35 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             oc[i].status = st;
             oc[i].done = true;
             --remaining;
-            Dh[i].active = 0;
-            TSK_HIP(hipMemcpyAsync(&D[i].active, &Dh[i].active, sizeof(int), hipMemcpyHostToDevice, s));
-            changed = true;
+            hipLaunchKernelGGL(k_deactivate, dim3(1), dim3(64), 0, s, D, count, NS, i);
         }
-        (void)changed;
+    };
+    TSK_HIP(hipEventRecord(L.ev_apply[0], s));
+    TSK_TRY(matvec(0));
+    TSK_HIP(hipEventRecord(L.ev_apply[1], s));
+    TSK_TRY(enqueue(next++));
+    while (!pend.empty()) {
+        const int jo = pend.front();
+        const hipError_t q = hipEventQuery(L.ev_eig[jo % NS]);
+        if (q == hipSuccess) {
+            pend.pop_front();
+            consume(jo);
+            if (remaining == 0) break;
+            if (pend.empty() && next < m) TSK_TRY(enqueue(next++));
+            continue;
+        }
+        if (q != hipErrorNotReady) TSK_HIP(q);
+        if (next < m && int(pend.size()) < NS) {
+            const hipError_t qm = hipEventQuery(L.ev_apply[2 * next + 1]);  // matvec of step `next` done
+            if (qm == hipSuccess) {
+                TSK_TRY(enqueue(next++));
+                continue;
+            }
+            if (qm != hipErrorNotReady) TSK_HIP(qm);
+        }
+        std::this_thread::yield();
     }
+    for (int t = 0; t < NS; ++t) TSK_HIP(hipStreamSynchronize(L.side[t]));  // discarded analyses
 
     // ---- outputs --------------------------------------------------------------------------------
     TSK_HIP(hipStreamSynchronize(s));  // drains discarded speculative matvecs
@@ -250,6 +317,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     }
     int pmax = 1;
     for (int i = 0; i < count; ++i) {
+        Dh[i] = Dall[size_t(final_slot[i]) * count + i];  // the analysis of the final step
         Dh[i].steps = oc[i].steps;
         Dh[i].active = 1;
         ops[i]->aw.steps = oc[i].steps;

@@ -134,9 +134,26 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
     __shared__ double ctol[kMaxKrylov];  // per Ritz value convergence threshold
     const int lane = threadIdx.x;
 
+    // beta_p: the Arnoldi path reads it from H's subdiagonal H[p][p-1], which
+    // later (speculative) steps never modify; the standalone path from scal[2].
+    const double beta = FULLZ ? dsc.scal[2] : H[p + (size_t)ldh * (p - 1)].x;
+    bool bad = !isfinite(beta);
     for (int e = lane; e < p * p; e += kHT) {
         int r = e / p, c = e % p;
-        T[e] = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
+        const double2 v = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
+        bad = bad || !isfinite(v.x) || !isfinite(v.y);
+        T[e] = v;
+    }
+    if (__ballot(bad)) {  // non-finite input: no QR (it could not deflate), report and stop
+        if (lane == 0 && rr) {
+            rr->nonfinite = 1;
+            rr->done = 0;
+            rr->nsel = 0;
+            rr->nconv = 0;
+            rr->eig_fail = FULLZ ? 1 : 0;
+            rr->iters = 0;
+        }
+        return;
     }
     for (int c = lane; c < p; c += kHT) zl[c] = cmk<double2>(c == p - 1 ? 1.0 : 0.0, 0.0);
     if constexpr (FULLZ) {
@@ -285,7 +302,6 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
     }
 
     // ---- Ritz values and residuals ---------------------------------------------------------
-    const double beta = dsc.scal[2];
     for (int i = lane; i < p; i += kHT) {
         mu[i] = T[i * p + i];
         double2* zc = S + (size_t)i * p;

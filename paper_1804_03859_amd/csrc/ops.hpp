@@ -39,6 +39,9 @@ struct DevBuf {
 enum class StateKind { Complex64x2, Real64, Real32 };  // double2 / double / float
 
 struct ArnoldiWork {
+    // Ritz analyses of consecutive steps run concurrently on kSlots side
+    // streams, each with its own eigensolver outputs (see arnoldi.hip).
+    static constexpr int kSlots = 4;
     DevBuf V;         // (m+1) x n state vectors
     DevBuf H;         // (m+1) x m complex128, column-major
     DevBuf w;         // matvec output (state type)
@@ -47,25 +50,30 @@ struct ArnoldiWork {
     DevBuf pnrm;      // per-block partial squared norms
     DevBuf h;         // reduced projection coefficients
     DevBuf scal;      // device scalars
-    DevBuf eigS, eigY, eigMu, eigRes, sel;  // Hessenberg eigensolver
-    DevBuf rr;        // RitzResult
+    DevBuf eigS, eigMu, eigRes, sel;  // Hessenberg eigensolver, kSlots copies
+    DevBuf eigY;      // unit Ritz coordinates of the wanted pairs (final step)
+    DevBuf rr;        // RitzResult, kSlots copies
     DevBuf out;       // gathered outputs (mu, lambda, residual)
     DevBuf phys;      // physical field scratch (seeded start vector)
     int m = 0, steps = 0;
     int64_t ldv = 0;
     // Owned by the first operator of a batch (the only one for a single run):
-    DevBuf batch_desc;                 // KryDesc table
-    DevBuf batch_rr;                   // RitzResult of every instance, contiguous
+    DevBuf batch_desc;                 // kSlots KryDesc tables of the batch
+    DevBuf batch_rr;                   // RitzResult of every instance and slot
     RitzResult* rr_host = nullptr;     // pinned copy of batch_rr
     int rr_host_count = 0;
     std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
-    hipEvent_t ev_cgs = nullptr;       // basis vector j+1 and H column j ready
-    hipStream_t side = nullptr;        // Ritz analysis overlaps the next matvec
+    hipEvent_t ev_cgs[kSlots] = {};    // basis vector j+1 and H column j ready (slot j % kSlots)
+    hipEvent_t ev_eig[kSlots] = {};    // Ritz analysis of step j copied to the host
+    hipStream_t side[kSlots] = {};     // Ritz analyses overlap the next matvecs
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
         for (hipEvent_t e : ev_apply) (void)hipEventDestroy(e);
-        if (ev_cgs) (void)hipEventDestroy(ev_cgs);
-        if (side) (void)hipStreamDestroy(side);
+        for (int t = 0; t < kSlots; ++t) {
+            if (ev_cgs[t]) (void)hipEventDestroy(ev_cgs[t]);
+            if (ev_eig[t]) (void)hipEventDestroy(ev_eig[t]);
+            if (side[t]) (void)hipStreamDestroy(side[t]);
+        }
     }
 };
 

@@ -214,7 +214,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // ---- matvec of step j for every active instance --------------------------------------
     KolmoBatchPtr kb;
     bool all_kolmo = true;
-    for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && is_kolmo(ops[i]);
+    for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && kolmo_parallel(ops[i]);
     if (all_kolmo) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
     std::vector<Outcome> oc(count);
     auto matvec = [&](int j) -> tsk_status {

@@ -31,178 +31,14 @@
 #include <algorithm>
 #include <cstring>
 
-#include "colfft.hpp"
-#include "fft.hpp"
+#include "colstep.hpp"
+#include "kolmo2d.hpp"
 #include "krylov.hpp"
 #include "ops.hpp"
 
 namespace tsk {
 
 namespace {
-
-template <int N> struct Geo {
-    static constexpr int M = (N - 1) / 3;       // largest kept |j|
-    static constexpr int NM = 2 * M + 1;        // kept ky per column
-    static constexpr int RM = (NM + kWave - 1) / kWave;
-    static constexpr int RY = (N + kWave - 1) / kWave;
-    static constexpr int64_t n_state = 4ll * M * (M + 1);
-    static __host__ __device__ constexpr int64_t seg(int kx) {
-        return kx == 0 ? 0 : 2ll * M + int64_t(kx - 1) * 2 * NM;
-    }
-};
-
-// One operator instance of a (batched) column-stepper launch.  The input of
-// step j is xbase + j * xstride (the Arnoldi basis vector v_j; xstride = 0 for a
-// plain matvec); `active` (optional) lets finished Arnoldi instances skip.
-template <typename real> struct ColInst {
-    const real* xbase;
-    int64_t xstride;
-    real* y;
-    const real* negU;
-    const real* dOdy;
-    double alpha, Re, dt, cprop;
-    int nsteps;
-    const int* active;
-};
-struct ColTask {
-    int inst;  // index into the instance table
-    int kx;    // dealiased column 0..M
-};
-
-// ---- the column time stepper ------------------------------------------------------------
-// Lane-owned positions: j = lane (< NB = N/RE) and slots r < RE hold the
-// y-index / FFT-order wavenumber index pos = j + r NB (colfft.hpp), for the
-// spectral state (jy = pos or pos - N, kept when |jy| <= M) and, after the
-// inverse transform, for the grid values at y = 2 pi pos / N.
-template <typename real, int N, bool PROP>
-__global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColInst<real>* __restrict__ insts,
-                                                   const ColTask* __restrict__ tasks, const cplx<real>* __restrict__ twg,
-                                                   int jstep) {
-    using C = cplx<real>;
-    using G = Geo<N>;
-    using PL = ColPlan<N>;
-    constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
-    static_assert(PL::NBL == 1, "one edge butterfly per lane");
-    const ColTask tk = tasks[blockIdx.x];
-    const ColInst<real>& I = insts ? insts[tk.inst] : one;
-    if (I.active && *I.active == 0) return;
-    const real* __restrict__ xin = I.xbase + jstep * I.xstride;
-    real* __restrict__ yout = I.y;
-    const real* __restrict__ negU = I.negU;
-    const real* __restrict__ dOdy = I.dOdy;
-    const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
-    const int nsteps = I.nsteps;
-    const int lane = threadIdx.x;
-    const int kx = tk.kx;
-
-    if (kx == 0) {
-        // kx = 0: the advection term vanishes identically (d/dx of a y-only
-        // field), so the integrating factor alone advances the column.
-        for (int q = lane; q < M; q += kWave) {
-            const double jy = q + 1;
-            const real E1 = real(exp(-jy * jy * dt / Re));
-            real re = xin[2 * q], im = xin[2 * q + 1];
-            for (int st = 0; st < nsteps; ++st) { re *= E1; im *= E1; }
-            yout[2 * q] = re;
-            yout[2 * q + 1] = im;
-        }
-        return;
-    }
-
-    constexpr int LP = padded_len<N>();
-    __shared__ C sA[LP], sB[LP], sT[N];
-    __shared__ C sA2[PROP ? 1 : LP], sB2[PROP ? 1 : LP];
-    for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
-
-    const double kxv = alpha * kx;
-    const bool act = lane < NB;
-    real E1[RE], Eh[RE], g1[RE], g2[RE], nu[RE], oy[RE];
-    C w[RE], acc[RE], s[RE];
-    unsigned keep = 0;
-    const real* xs = xin + G::seg(kx);
-#pragma unroll
-    for (int r = 0; r < RE; ++r) {
-        const int pos = lane + r * NB;
-        const int jy = pos <= N / 2 ? pos : pos - N;
-        const bool kp = act && jy >= -M && jy <= M;
-        keep |= kp ? (1u << r) : 0u;
-        const double K2 = kxv * kxv + double(jy) * jy;
-        E1[r] = kp ? real(exp(-K2 * dt / Re)) : real(0);
-        Eh[r] = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
-        g1[r] = kp ? (PROP ? real(kxv * (1.0 - cprop / K2)) : real(kxv)) : real(0);
-        g2[r] = kp ? real(kxv / K2) : real(0);
-        nu[r] = act ? negU[pos] : real(0);
-        oy[r] = (!PROP && act) ? dOdy[pos] : real(0);
-        const int q = jy + M;
-        w[r] = kp ? cmk<C>(xs[2 * q], xs[2 * q + 1]) : cmk<C>(real(0), real(0));
-        acc[r] = s[r] = w[r];
-    }
-    __syncthreads();
-
-    const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
-    const real invN = real(1.0 / N);
-    C* fwdA = col_result_in_a<N>() ? sB : sA;  // forward transform must not write
-    C* fwdB = col_result_in_a<N>() ? sA : sB;  // the buffer the inverse reads last
-
-    for (int st = 0; st < nsteps; ++st) {
-#pragma unroll
-        for (int r = 0; r < RE; ++r) s[r] = w[r];
-#pragma unroll 1
-        for (int stage = 0; stage < 4; ++stage) {
-            C v[1][RE], v2[1][PROP ? 1 : RE];
-#pragma unroll
-            for (int r = 0; r < RE; ++r) {
-                v[0][r] = cmk<C>(-g1[r] * s[r].y, g1[r] * s[r].x);  // i kx (...) s
-                if constexpr (!PROP) v2[0][r] = cmk<C>(-g2[r] * s[r].y, g2[r] * s[r].x);
-            }
-            col_fft<N, +1>(v, sA, sB, sT, lane);
-            if constexpr (!PROP) col_fft<N, +1>(v2, sA2, sB2, sT, lane);
-            // product with the base profiles at y = pos
-#pragma unroll
-            for (int r = 0; r < RE; ++r) {
-                C p = cmk<C>(nu[r] * v[0][r].x, nu[r] * v[0][r].y);
-                if constexpr (!PROP) {
-                    p.x += oy[r] * v2[0][r].x;
-                    p.y += oy[r] * v2[0][r].y;
-                }
-                v[0][r] = p;
-            }
-            col_fft<N, -1>(v, fwdA, fwdB, sT, lane);
-            // Lawson RK4 bookkeeping on the kept modes (registers only)
-#pragma unroll
-            for (int r = 0; r < RE; ++r) {
-                const real kmask = (keep >> r) & 1u ? invN : real(0);
-                const C nh = cmk<C>(v[0][r].x * kmask, v[0][r].y * kmask);
-                const real e1 = E1[r], eh = Eh[r];
-                if (stage == 0) {
-                    acc[r] = cmk<C>(e1 * (w[r].x + h6 * nh.x), e1 * (w[r].y + h6 * nh.y));
-                    s[r] = cmk<C>(eh * (w[r].x + h2 * nh.x), eh * (w[r].y + h2 * nh.y));
-                } else if (stage == 1) {
-                    acc[r].x += h3 * eh * nh.x;
-                    acc[r].y += h3 * eh * nh.y;
-                    s[r] = cmk<C>(eh * w[r].x + h2 * nh.x, eh * w[r].y + h2 * nh.y);
-                } else if (stage == 2) {
-                    acc[r].x += h3 * eh * nh.x;
-                    acc[r].y += h3 * eh * nh.y;
-                    s[r] = cmk<C>(e1 * w[r].x + hh * eh * nh.x, e1 * w[r].y + hh * eh * nh.y);
-                } else {
-                    w[r] = cmk<C>(acc[r].x + h6 * nh.x, acc[r].y + h6 * nh.y);
-                }
-            }
-        }
-    }
-    real* ys = yout + G::seg(kx);
-#pragma unroll
-    for (int r = 0; r < RE; ++r) {
-        if ((keep >> r) & 1u) {
-            const int pos = lane + r * NB;
-            const int jy = pos <= N / 2 ? pos : pos - N;
-            const int q = jy + M;
-            ys[2 * q] = w[r].x;
-            ys[2 * q + 1] = w[r].y;
-        }
-    }
-}
 
 // ---- physical <-> packed spectral ------------------------------------------------------
 // Z is the N x (M+1) complex intermediate, row-major [y][kx].
@@ -387,6 +223,8 @@ struct KolmoOp final : Operator {
     double cprop = 0.0;
     DevBuf tw, negU, dOdy, Z;
     DevBuf tasks;  // (0, kx) for kx = 0..M: the single-instance launch
+    Gen2D* gen = nullptr;  // general two-dimensional base flow (kolmo2d.hip), else parallel
+    ~KolmoOp() override { gen2d_free(gen); }
 
     const char* name() const override { return "kolmo2d"; }
     int64_t physical_reals() const override { return int64_t(N) * N; }
@@ -445,6 +283,7 @@ struct KolmoOp final : Operator {
     tsk_status apply(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
+        if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
         const ColTask* tk = tasks.as<ColTask>();
         if (prec == TSK_FP32)
             dispatch_colstep<float>(N, inst<float>(x, 0, y, nullptr), nullptr, tk, M + 1, prop, tw.ptr, 0, stream);
@@ -529,13 +368,32 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
     k->cprop = k->prop ? c : 0.0;
     TSK_TRY(k->upload_real(k->negU, nu));
     TSK_TRY(k->upload_real(k->dOdy, oy));
+    gen2d_free(k->gen);
+    k->gen = nullptr;
     k->base_set = true;
     return TSK_OK;
 }
 
-tsk_status kolmo_set_base_general(Operator* op, const double*, const double*, const double*, const double*) {
-    if (!dynamic_cast<KolmoOp*>(op)) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
-    return fail(TSK_EINVAL, "general two-dimensional base flows are not supported by this build");
+tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
+                                  const double* Oy) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!U || !V || !Ox || !Oy) return fail(TSK_EINVAL, "null base-flow field");
+    const size_t nn = size_t(k->N) * k->N;
+    for (const double* f : {U, V, Ox, Oy})
+        for (size_t i = 0; i < nn; ++i)
+            if (!std::isfinite(f[i])) return fail(TSK_ENONFINITE, "non-finite base flow");
+    Gen2D* g = nullptr;
+    TSK_TRY(gen2d_create(k->N, k->prec == TSK_FP32, U, V, Ox, Oy, &g));
+    gen2d_free(k->gen);
+    k->gen = g;
+    k->base_set = true;
+    return TSK_OK;
+}
+
+bool kolmo_parallel(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k && !k->gen;
 }
 
 bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != nullptr; }

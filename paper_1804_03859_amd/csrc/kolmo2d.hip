@@ -1,0 +1,304 @@
+// Linearized 2D Navier-Stokes (vorticity form) about a general base flow
+// (U(x, y), V(x, y)), pseudo-spectral with the 2/3 rule, Lawson
+// integrating-factor RK4 (Sec. 3, eq. "linearized Navier-Stokes equations",
+// curl taken):
+//     d omega/dt = -(U d_x omega + V d_y omega + u d_x Omega + v d_y Omega)
+//                  + Re^-1 lap omega,   u = d_y psi, v = -d_x psi, -lap psi = omega.
+//
+// Pipeline of one RK4 stage (the state and the RK4 bookkeeping stay in packed
+// spectral form, see tsk.h):
+//   column kernel (one wavefront per kept kx column):
+//     forward y-transform of the previous stage's product spectrum Q[kx][y],
+//     RHS on the kept modes, RK4 update, then the four derived spectral fields
+//     i kx s, i ky s, i ky s/K^2, -i kx s/K^2 of the next stage input s and
+//     their inverse y-transforms into G[f][kx][y];
+//   row kernel (four wavefronts, two grid rows each):
+//     the four fields of a row by two complex inverse x-transforms (two
+//     Hermitian half-spectra packed as a + i b), the product
+//     P = U d_x w + V d_y w + u Omega_x + v Omega_y with the base fields of the
+//     row, and one complex forward x-transform for two rows (p1 + i p2),
+//     unpacked to the kx = 0..M half spectra Q[kx][y].
+// G and Q are the only fields in HBM between the two kernels: each kernel
+// reads and writes them once per stage (4 + 1 complex N x (M+1) arrays) and
+// the row kernel reads the four base fields.  A workgroup of the row kernel
+// covers eight consecutive rows, so every (field, kx) segment it reads from
+// G is eight contiguous values.  The x- and y-transforms are the Stockham LDS
+// FFTs of fft.hpp.
+//
+// Scaling.  Packed coefficients c = sqrt(2) rfft2(omega)/N^2.  The derived
+// fields are formed from c directly and the transforms are unnormalised, so
+// the products are sqrt(2) times the physical ones; the RHS in packed units is
+// then -rfft2(P')/N^2 with no further sqrt(2).
+#include <cmath>
+#include <vector>
+
+#include "fft.hpp"
+#include "kolmo2d.hpp"
+#include "ops.hpp"
+
+namespace tsk {
+
+namespace {
+
+template <int N> struct Geo2 {
+    static constexpr int M = (N - 1) / 3;
+    static constexpr int MC = M + 1;     // kept kx columns
+    static constexpr int NM = 2 * M + 1;  // kept ky per column (kx > 0)
+    static __host__ __device__ constexpr int64_t seg(int kx) {
+        return kx == 0 ? 0 : 2ll * M + int64_t(kx - 1) * 2 * NM;
+    }
+};
+
+constexpr int kRowsPerBlock = 8;  // row kernel: 4 wavefronts x 2 rows
+
+enum GenMode { GEN_FIRST = 0, GEN_STAGE = 1, GEN_LAST = 2 };
+
+// Column kernel.  FIRST: W = x, s = W, derived fields of s.  STAGE: RHS from Q,
+// RK4 stage q, derived fields of the next stage input.  LAST: RHS from Q, final
+// stage (q = 3), y = new W.
+template <typename real, int N>
+__global__ __launch_bounds__(kWave) void k_gen_col(const real* __restrict__ xin, real* __restrict__ W,
+                                                   real* __restrict__ Acc, const cplx<real>* __restrict__ Q,
+                                                   cplx<real>* __restrict__ Gf, real* __restrict__ yout,
+                                                   const cplx<real>* __restrict__ twg, double alpha, double Re,
+                                                   double dt, int q, int mode) {
+    using C = cplx<real>;
+    using G = Geo2<N>;
+    constexpr int M = G::M, MC = G::MC, NM = G::NM;
+    __shared__ C sA[N], sB[N], sT[N];
+    __shared__ C sS[NM];
+    const int lane = threadIdx.x, kx = blockIdx.x;
+    const int nq = kx == 0 ? M : NM;  // packed complex entries of the column
+    const int64_t base = G::seg(kx);
+    for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
+    const double kxv = alpha * kx;
+
+    if (mode == GEN_FIRST) {
+        for (int e = lane; e < nq; e += kWave) {
+            const real re = xin[base + 2 * e], im = xin[base + 2 * e + 1];
+            W[base + 2 * e] = re;
+            W[base + 2 * e + 1] = im;
+            sS[e] = cmk<C>(re, im);
+        }
+        __syncthreads();
+    } else {
+        for (int t = lane; t < N; t += kWave) sA[t] = Q[size_t(kx) * N + t];
+        __syncthreads();
+        const C* X = fft_lds<N, -1, kWave>(sA, sB, sT, lane);
+        const double h = dt, h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
+        const double scl = -1.0 / (double(N) * N);
+        for (int e = lane; e < nq; e += kWave) {
+            const int jy = kx == 0 ? e + 1 : e - M;
+            const C xr = X[jy < 0 ? jy + N : jy];
+            const double nx = scl * double(xr.x), ny = scl * double(xr.y);
+            const double K2 = kxv * kxv + double(jy) * jy;
+            const double e1 = exp(-K2 * dt / Re), eh = exp(-K2 * (0.5 * dt) / Re);
+            const int64_t o = base + 2 * e;
+            const double wx = W[o], wy = W[o + 1];
+            double sx, sy;
+            if (q == 0) {
+                Acc[o] = real(e1 * (wx + h6 * nx));
+                Acc[o + 1] = real(e1 * (wy + h6 * ny));
+                sx = eh * (wx + h2 * nx);
+                sy = eh * (wy + h2 * ny);
+            } else if (q == 1) {
+                Acc[o] = real(double(Acc[o]) + h3 * eh * nx);
+                Acc[o + 1] = real(double(Acc[o + 1]) + h3 * eh * ny);
+                sx = eh * wx + h2 * nx;
+                sy = eh * wy + h2 * ny;
+            } else if (q == 2) {
+                Acc[o] = real(double(Acc[o]) + h3 * eh * nx);
+                Acc[o + 1] = real(double(Acc[o + 1]) + h3 * eh * ny);
+                sx = e1 * wx + h * eh * nx;
+                sy = e1 * wy + h * eh * ny;
+            } else {
+                const real nwx = real(double(Acc[o]) + h6 * nx), nwy = real(double(Acc[o + 1]) + h6 * ny);
+                if (mode == GEN_LAST) {
+                    yout[o] = nwx;
+                    yout[o + 1] = nwy;
+                } else {
+                    W[o] = nwx;
+                    W[o + 1] = nwy;
+                }
+                sx = nwx;
+                sy = nwy;
+            }
+            sS[e] = cmk<C>(real(sx), real(sy));
+        }
+        __syncthreads();
+        if (mode == GEN_LAST) return;
+    }
+    // derived fields of s and their inverse y-transforms
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        for (int t = lane; t < N; t += kWave) sA[t] = cmk<C>(real(0), real(0));
+        __syncthreads();
+        for (int e = lane; e < nq; e += kWave) {
+            const int jy = kx == 0 ? e + 1 : e - M;
+            const double K2 = kxv * kxv + double(jy) * jy;
+            const C sv = sS[e];
+            // multiplier g: i g s, g = kx, ky, ky/K^2, -kx/K^2
+            const double g = f == 0 ? kxv : f == 1 ? double(jy) : f == 2 ? double(jy) / K2 : -kxv / K2;
+            const C d = cmk<C>(real(-g * double(sv.y)), real(g * double(sv.x)));
+            sA[jy < 0 ? jy + N : jy] = d;
+            if (kx == 0) sA[N - jy] = cconj(d);
+        }
+        __syncthreads();
+        const C* X = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
+        C* out = Gf + (size_t(f) * MC + kx) * N;
+        for (int t = lane; t < N; t += kWave) out[t] = X[t];
+        __syncthreads();
+    }
+}
+
+// Row kernel: rows y0 = 8 blockIdx.x + 2 wave and y0 + 1.
+template <typename real, int N>
+__global__ __launch_bounds__(kWave * 4) void k_gen_row(const cplx<real>* __restrict__ Gf, const real* __restrict__ U,
+                                                       const real* __restrict__ V, const real* __restrict__ Ox,
+                                                       const real* __restrict__ Oy, cplx<real>* __restrict__ Q,
+                                                       const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    using G = Geo2<N>;
+    constexpr int M = G::M, MC = G::MC;
+    constexpr int RY = (N + kWave - 1) / kWave;
+    __shared__ C sT[N];
+    __shared__ C sA[4][N], sB[4][N];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int y0 = kRowsPerBlock * blockIdx.x + 2 * wv;
+    for (int t = tid; t < N; t += 4 * kWave) sT[t] = twg[t];
+    C* a = sA[wv];
+    C* b = sB[wv];
+    real P[2][RY];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int y = y0 + r;
+#pragma unroll
+        for (int i = 0; i < RY; ++i) P[r][i] = real(0);
+#pragma unroll 1
+        for (int pr = 0; pr < 2; ++pr) {
+            for (int t = lane; t < N; t += kWave) a[t] = cmk<C>(real(0), real(0));
+            __syncthreads();
+            const C* g1s = Gf + (size_t(2 * pr) * MC) * N + y;
+            const C* g2s = Gf + (size_t(2 * pr + 1) * MC) * N + y;
+            for (int k = lane; k <= M; k += kWave) {
+                C g1 = g1s[size_t(k) * N], g2 = g2s[size_t(k) * N];
+                if (k == 0) {  // the kx = 0 column of a real field is real
+                    g1.y = real(0);
+                    g2.y = real(0);
+                }
+                a[k] = cmk<C>(g1.x - g2.y, g1.y + g2.x);                 // g1 + i g2
+                if (k > 0) a[N - k] = cmk<C>(g1.x + g2.y, g2.x - g1.y);  // conj(g1) + i conj(g2)
+            }
+            __syncthreads();
+            const C* X = fft_lds<N, +1, kWave>(a, b, sT, lane);
+            const real* f1 = (pr == 0 ? U : Ox) + size_t(y) * N;
+            const real* f2 = (pr == 0 ? V : Oy) + size_t(y) * N;
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const int x = lane + i * kWave;
+                if (x < N) P[r][i] += f1[x] * X[x].x + f2[x] * X[x].y;
+            }
+            __syncthreads();
+        }
+    }
+    // forward x-transform of the two rows at once: p = P0 + i P1
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const int x = lane + i * kWave;
+        if (x < N) a[x] = cmk<C>(P[0][i], P[1][i]);
+    }
+    __syncthreads();
+    const C* Z = fft_lds<N, -1, kWave>(a, b, sT, lane);
+    for (int k = lane; k <= M; k += kWave) {
+        const C za = Z[k], zb = cconj(Z[k == 0 ? 0 : N - k]);
+        Q[size_t(k) * N + y0] = cmk<C>(real(0.5) * (za.x + zb.x), real(0.5) * (za.y + zb.y));
+        Q[size_t(k) * N + y0 + 1] = cmk<C>(real(0.5) * (za.y - zb.y), real(-0.5) * (za.x - zb.x));
+    }
+}
+
+template <typename real, int N>
+void gen_matvec(const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, const real* U,
+                const real* V, const real* Ox, const real* Oy, const void* tw, double alpha, double Re, double dt,
+                int nsteps, hipStream_t s) {
+    using C = cplx<real>;
+    constexpr int MC = Geo2<N>::MC;
+    static_assert(N % kRowsPerBlock == 0, "row blocks");
+    const C* twc = static_cast<const C*>(tw);
+    hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kWave), 0, s, static_cast<const real*>(x), W, Acc, Q, Gf,
+                       static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST));
+    for (int st = 0; st < nsteps; ++st)
+        for (int q = 0; q < 4; ++q) {
+            hipLaunchKernelGGL((k_gen_row<real, N>), dim3(N / kRowsPerBlock), dim3(4 * kWave), 0, s, Gf, U, V, Ox, Oy,
+                               Q, twc);
+            const int mode = (st == nsteps - 1 && q == 3) ? GEN_LAST : GEN_STAGE;
+            hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kWave), 0, s, static_cast<const real*>(x), W, Acc,
+                               Q, Gf, static_cast<real*>(y), twc, alpha, Re, dt, q, mode);
+        }
+}
+
+template <typename real>
+void gen_dispatch(int N, const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, const real* U,
+                  const real* V, const real* Ox, const real* Oy, const void* tw, double alpha, double Re, double dt,
+                  int nsteps, hipStream_t s) {
+    switch (N) {
+#define X(n)                                                                                                      \
+    case n:                                                                                                       \
+        gen_matvec<real, n>(x, y, W, Acc, Q, Gf, U, V, Ox, Oy, tw, alpha, Re, dt, nsteps, s);                     \
+        break;
+        X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#undef X
+    }
+}
+
+}  // namespace
+
+struct Gen2D {
+    int N = 0, M = 0;
+    bool fp32 = false;
+    DevBuf U, V, Ox, Oy, W, Acc, Q, G;
+};
+
+tsk_status gen2d_create(int N, bool fp32, const double* U, const double* V, const double* Ox, const double* Oy,
+                        Gen2D** out) {
+    auto g = std::make_unique<Gen2D>();
+    g->N = N;
+    g->M = (N - 1) / 3;
+    g->fp32 = fp32;
+    const size_t rb = fp32 ? 4 : 8, nn = size_t(N) * N;
+    const int64_t n = 4ll * g->M * (g->M + 1);
+    const double* src[4] = {U, V, Ox, Oy};
+    DevBuf* dst[4] = {&g->U, &g->V, &g->Ox, &g->Oy};
+    for (int f = 0; f < 4; ++f) {
+        TSK_TRY(dst[f]->ensure(nn * rb));
+        if (fp32) {
+            std::vector<float> h(src[f], src[f] + nn);
+            TSK_HIP(hipMemcpy(dst[f]->ptr, h.data(), nn * 4, hipMemcpyHostToDevice));
+        } else {
+            TSK_HIP(hipMemcpy(dst[f]->ptr, src[f], nn * 8, hipMemcpyHostToDevice));
+        }
+    }
+    TSK_TRY(g->W.ensure(size_t(n) * rb));
+    TSK_TRY(g->Acc.ensure(size_t(n) * rb));
+    TSK_TRY(g->Q.ensure(size_t(g->M + 1) * N * 2 * rb));
+    TSK_TRY(g->G.ensure(4 * size_t(g->M + 1) * N * 2 * rb));
+    *out = g.release();
+    return TSK_OK;
+}
+
+void gen2d_free(Gen2D* g) { delete g; }
+
+tsk_status gen2d_apply(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
+                       const void* tw, hipStream_t s) {
+    if (g->fp32)
+        gen_dispatch<float>(g->N, x, y, g->W.as<float>(), g->Acc.as<float>(), g->Q.as<float2>(), g->G.as<float2>(),
+                            g->U.as<float>(), g->V.as<float>(), g->Ox.as<float>(), g->Oy.as<float>(), tw, alpha, Re,
+                            dt, nsteps, s);
+    else
+        gen_dispatch<double>(g->N, x, y, g->W.as<double>(), g->Acc.as<double>(), g->Q.as<double2>(),
+                             g->G.as<double2>(), g->U.as<double>(), g->V.as<double>(), g->Ox.as<double>(),
+                             g->Oy.as<double>(), tw, alpha, Re, dt, nsteps, s);
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+}  // namespace tsk

@@ -110,6 +110,8 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
 tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
                                   const double* Oy);
 bool is_kolmo(const Operator* op);
+// A Navier-Stokes operator whose base flow is parallel (column stepper; batchable).
+bool kolmo_parallel(const Operator* op);
 // Largest kept wavenumber M = (N-1)/3 of a Navier-Stokes operator, -1 for others.
 int kolmo_cutoff(const Operator* op);
 bool is_cgle(const Operator* op);

@@ -7,23 +7,23 @@
 //
 // Pipeline of one RK4 stage (the state and the RK4 bookkeeping stay in packed
 // spectral form, see tsk.h):
-//   column kernel (one wavefront per kept kx column):
+//   column kernel (one workgroup of four wavefronts per kept kx column):
 //     forward y-transform of the previous stage's product spectrum Q[kx][y],
 //     RHS on the kept modes, RK4 update, then the four derived spectral fields
-//     i kx s, i ky s, i ky s/K^2, -i kx s/K^2 of the next stage input s and
-//     their inverse y-transforms into G[f][kx][y];
-//   row kernel (four wavefronts, two grid rows each):
-//     the four fields of a row by two complex inverse x-transforms (two
-//     Hermitian half-spectra packed as a + i b), the product
-//     P = U d_x w + V d_y w + u Omega_x + v Omega_y with the base fields of the
-//     row, and one complex forward x-transform for two rows (p1 + i p2),
-//     unpacked to the kx = 0..M half spectra Q[kx][y].
+//     i kx s, i ky s, i ky s/K^2, -i kx s/K^2 of the next stage input s, one
+//     per wavefront, and their inverse y-transforms into G[f][kx][y];
+//   row kernel (one workgroup of four wavefronts per pair of grid rows):
+//     the four fields of the two rows by four concurrent complex inverse
+//     x-transforms (two Hermitian half-spectra packed as a + i b per
+//     transform), the products P = U d_x w + V d_y w + u Omega_x + v Omega_y
+//     with the base fields, and one complex forward x-transform of both rows
+//     (P0 + i P1), unpacked to the kx = 0..M half spectra Q[kx][y].
 // G and Q are the only fields in HBM between the two kernels: each kernel
 // reads and writes them once per stage (4 + 1 complex N x (M+1) arrays) and
-// the row kernel reads the four base fields.  A workgroup of the row kernel
-// covers eight consecutive rows, so every (field, kx) segment it reads from
-// G is eight contiguous values.  The x- and y-transforms are the Stockham LDS
-// FFTs of fft.hpp.
+// the row kernel reads the four base fields.  Running the four inverse
+// transforms of a workgroup concurrently keeps the dependent chain of each
+// kernel at two transforms.  The x- and y-transforms are the Stockham LDS FFTs
+// of fft.hpp.
 //
 // Scaling.  Packed coefficients c = sqrt(2) rfft2(omega)/N^2.  The derived
 // fields are formed from c directly and the transforms are unnormalised, so
@@ -49,32 +49,35 @@ template <int N> struct Geo2 {
     }
 };
 
-constexpr int kRowsPerBlock = 8;  // row kernel: 4 wavefronts x 2 rows
+constexpr int kGT = 4 * kWave;  // both kernels: four wavefronts per workgroup
 
 enum GenMode { GEN_FIRST = 0, GEN_STAGE = 1, GEN_LAST = 2 };
 
-// Column kernel.  FIRST: W = x, s = W, derived fields of s.  STAGE: RHS from Q,
-// RK4 stage q, derived fields of the next stage input.  LAST: RHS from Q, final
-// stage (q = 3), y = new W.
+// Column kernel, one workgroup per kept kx column.  FIRST: W = x, s = W,
+// derived fields of s.  STAGE: RHS from Q, RK4 stage q, derived fields of the
+// next stage input.  LAST: RHS from Q, final stage (q = 3), y = new W.  The
+// forward transform and the RK4 update use the whole workgroup; wavefront f
+// then forms derived field f and runs its inverse transform, the four
+// concurrently.
 template <typename real, int N>
-__global__ __launch_bounds__(kWave) void k_gen_col(const real* __restrict__ xin, real* __restrict__ W,
-                                                   real* __restrict__ Acc, const cplx<real>* __restrict__ Q,
-                                                   cplx<real>* __restrict__ Gf, real* __restrict__ yout,
-                                                   const cplx<real>* __restrict__ twg, double alpha, double Re,
-                                                   double dt, int q, int mode) {
+__global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, real* __restrict__ W,
+                                                 real* __restrict__ Acc, const cplx<real>* __restrict__ Q,
+                                                 cplx<real>* __restrict__ Gf, real* __restrict__ yout,
+                                                 const cplx<real>* __restrict__ twg, double alpha, double Re,
+                                                 double dt, int q, int mode) {
     using C = cplx<real>;
     using G = Geo2<N>;
     constexpr int M = G::M, MC = G::MC, NM = G::NM;
-    __shared__ C sA[N], sB[N], sT[N];
+    __shared__ C sA[4][N], sB[4][N], sT[N];
     __shared__ C sS[NM];
-    const int lane = threadIdx.x, kx = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave, kx = blockIdx.x;
     const int nq = kx == 0 ? M : NM;  // packed complex entries of the column
     const int64_t base = G::seg(kx);
-    for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
+    for (int t = tid; t < N; t += kGT) sT[t] = twg[t];
     const double kxv = alpha * kx;
 
     if (mode == GEN_FIRST) {
-        for (int e = lane; e < nq; e += kWave) {
+        for (int e = tid; e < nq; e += kGT) {
             const real re = xin[base + 2 * e], im = xin[base + 2 * e + 1];
             W[base + 2 * e] = re;
             W[base + 2 * e + 1] = im;
@@ -82,12 +85,12 @@ __global__ __launch_bounds__(kWave) void k_gen_col(const real* __restrict__ xin,
         }
         __syncthreads();
     } else {
-        for (int t = lane; t < N; t += kWave) sA[t] = Q[size_t(kx) * N + t];
+        for (int t = tid; t < N; t += kGT) sA[0][t] = Q[size_t(kx) * N + t];
         __syncthreads();
-        const C* X = fft_lds<N, -1, kWave>(sA, sB, sT, lane);
+        const C* X = fft_lds<N, -1, kGT>(sA[0], sB[0], sT, tid);
         const double h = dt, h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
         const double scl = -1.0 / (double(N) * N);
-        for (int e = lane; e < nq; e += kWave) {
+        for (int e = tid; e < nq; e += kGT) {
             const int jy = kx == 0 ? e + 1 : e - M;
             const C xr = X[jy < 0 ? jy + N : jy];
             const double nx = scl * double(xr.x), ny = scl * double(xr.y);
@@ -128,88 +131,80 @@ __global__ __launch_bounds__(kWave) void k_gen_col(const real* __restrict__ xin,
         __syncthreads();
         if (mode == GEN_LAST) return;
     }
-    // derived fields of s and their inverse y-transforms
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-        for (int t = lane; t < N; t += kWave) sA[t] = cmk<C>(real(0), real(0));
-        __syncthreads();
-        for (int e = lane; e < nq; e += kWave) {
-            const int jy = kx == 0 ? e + 1 : e - M;
-            const double K2 = kxv * kxv + double(jy) * jy;
-            const C sv = sS[e];
-            // multiplier g: i g s, g = kx, ky, ky/K^2, -kx/K^2
-            const double g = f == 0 ? kxv : f == 1 ? double(jy) : f == 2 ? double(jy) / K2 : -kxv / K2;
-            const C d = cmk<C>(real(-g * double(sv.y)), real(g * double(sv.x)));
-            sA[jy < 0 ? jy + N : jy] = d;
-            if (kx == 0) sA[N - jy] = cconj(d);
-        }
-        __syncthreads();
-        const C* X = fft_lds<N, +1, kWave>(sA, sB, sT, lane);
-        C* out = Gf + (size_t(f) * MC + kx) * N;
-        for (int t = lane; t < N; t += kWave) out[t] = X[t];
-        __syncthreads();
+    // wavefront f: derived field f of s (i g s, g = kx, ky, ky/K^2, -kx/K^2) and
+    // its inverse y-transform
+    C* a = sA[wv];
+    C* b = sB[wv];
+    for (int t = lane; t < N; t += kWave) a[t] = cmk<C>(real(0), real(0));
+    __syncthreads();
+    for (int e = lane; e < nq; e += kWave) {
+        const int jy = kx == 0 ? e + 1 : e - M;
+        const double K2 = kxv * kxv + double(jy) * jy;
+        const C sv = sS[e];
+        const double g = wv == 0 ? kxv : wv == 1 ? double(jy) : wv == 2 ? double(jy) / K2 : -kxv / K2;
+        const C d = cmk<C>(real(-g * double(sv.y)), real(g * double(sv.x)));
+        a[jy < 0 ? jy + N : jy] = d;
+        if (kx == 0) a[N - jy] = cconj(d);
     }
+    __syncthreads();
+    const C* X = fft_lds<N, +1, kWave>(a, b, sT, lane);
+    C* out = Gf + (size_t(wv) * MC + kx) * N;
+    for (int t = lane; t < N; t += kWave) out[t] = X[t];
 }
 
-// Row kernel: rows y0 = 8 blockIdx.x + 2 wave and y0 + 1.
+// Row kernel, one workgroup per pair of grid rows (y0, y0 + 1).  Wavefront
+// 2r + pr inverse-transforms field pair pr ((d_x w, d_y w) or (u, v), packed as
+// a + i b) of row y0 + r; the workgroup then forms the products of both rows
+// and transforms them forward as one complex sequence P0 + i P1.
 template <typename real, int N>
-__global__ __launch_bounds__(kWave * 4) void k_gen_row(const cplx<real>* __restrict__ Gf, const real* __restrict__ U,
-                                                       const real* __restrict__ V, const real* __restrict__ Ox,
-                                                       const real* __restrict__ Oy, cplx<real>* __restrict__ Q,
-                                                       const cplx<real>* __restrict__ twg) {
+__global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ Gf, const real* __restrict__ U,
+                                                 const real* __restrict__ V, const real* __restrict__ Ox,
+                                                 const real* __restrict__ Oy, cplx<real>* __restrict__ Q,
+                                                 const cplx<real>* __restrict__ twg) {
     using C = cplx<real>;
     using G = Geo2<N>;
     constexpr int M = G::M, MC = G::MC;
-    constexpr int RY = (N + kWave - 1) / kWave;
     __shared__ C sT[N];
     __shared__ C sA[4][N], sB[4][N];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int y0 = kRowsPerBlock * blockIdx.x + 2 * wv;
-    for (int t = tid; t < N; t += 4 * kWave) sT[t] = twg[t];
+    const int y0 = 2 * blockIdx.x, r = wv >> 1, pr = wv & 1, y = y0 + r;
+    for (int t = tid; t < N; t += kGT) sT[t] = twg[t];
     C* a = sA[wv];
     C* b = sB[wv];
-    real P[2][RY];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int y = y0 + r;
-#pragma unroll
-        for (int i = 0; i < RY; ++i) P[r][i] = real(0);
-#pragma unroll 1
-        for (int pr = 0; pr < 2; ++pr) {
-            for (int t = lane; t < N; t += kWave) a[t] = cmk<C>(real(0), real(0));
-            __syncthreads();
-            const C* g1s = Gf + (size_t(2 * pr) * MC) * N + y;
-            const C* g2s = Gf + (size_t(2 * pr + 1) * MC) * N + y;
-            for (int k = lane; k <= M; k += kWave) {
-                C g1 = g1s[size_t(k) * N], g2 = g2s[size_t(k) * N];
-                if (k == 0) {  // the kx = 0 column of a real field is real
-                    g1.y = real(0);
-                    g2.y = real(0);
-                }
-                a[k] = cmk<C>(g1.x - g2.y, g1.y + g2.x);                 // g1 + i g2
-                if (k > 0) a[N - k] = cmk<C>(g1.x + g2.y, g2.x - g1.y);  // conj(g1) + i conj(g2)
-            }
-            __syncthreads();
-            const C* X = fft_lds<N, +1, kWave>(a, b, sT, lane);
-            const real* f1 = (pr == 0 ? U : Ox) + size_t(y) * N;
-            const real* f2 = (pr == 0 ? V : Oy) + size_t(y) * N;
-#pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                const int x = lane + i * kWave;
-                if (x < N) P[r][i] += f1[x] * X[x].x + f2[x] * X[x].y;
-            }
-            __syncthreads();
+    for (int t = lane; t < N; t += kWave) a[t] = cmk<C>(real(0), real(0));
+    __syncthreads();
+    const C* g1s = Gf + (size_t(2 * pr) * MC) * N + y;
+    const C* g2s = Gf + (size_t(2 * pr + 1) * MC) * N + y;
+    for (int k = lane; k <= M; k += kWave) {
+        C g1 = g1s[size_t(k) * N], g2 = g2s[size_t(k) * N];
+        if (k == 0) {  // the kx = 0 column of a real field is real
+            g1.y = real(0);
+            g2.y = real(0);
         }
-    }
-    // forward x-transform of the two rows at once: p = P0 + i P1
-#pragma unroll
-    for (int i = 0; i < RY; ++i) {
-        const int x = lane + i * kWave;
-        if (x < N) a[x] = cmk<C>(P[0][i], P[1][i]);
+        a[k] = cmk<C>(g1.x - g2.y, g1.y + g2.x);                 // g1 + i g2
+        if (k > 0) a[N - k] = cmk<C>(g1.x + g2.y, g2.x - g1.y);  // conj(g1) + i conj(g2)
     }
     __syncthreads();
-    const C* Z = fft_lds<N, -1, kWave>(a, b, sT, lane);
-    for (int k = lane; k <= M; k += kWave) {
+    fft_lds<N, +1, kWave>(a, b, sT, lane);
+    __syncthreads();
+    // the inverse results sit in sA[w] after an even number of passes, else in
+    // sB[w]; the products of both rows, packed as P0 + i P1, go to a free buffer
+    constexpr bool in_a = fft_num_passes(N) % 2 == 0;
+    C* z = in_a ? sB[0] : sA[0];
+    C* scratch = in_a ? sB[1] : sA[1];
+    const C* R00 = in_a ? sA[0] : sB[0];  // row 0, (d_x w, d_y w)
+    const C* R01 = in_a ? sA[1] : sB[1];  // row 0, (u, v)
+    const C* R10 = in_a ? sA[2] : sB[2];  // row 1, (d_x w, d_y w)
+    const C* R11 = in_a ? sA[3] : sB[3];  // row 1, (u, v)
+    for (int x = tid; x < N; x += kGT) {
+        const size_t o0 = size_t(y0) * N + x, o1 = o0 + N;
+        const real p0 = U[o0] * R00[x].x + V[o0] * R00[x].y + Ox[o0] * R01[x].x + Oy[o0] * R01[x].y;
+        const real p1 = U[o1] * R10[x].x + V[o1] * R10[x].y + Ox[o1] * R11[x].x + Oy[o1] * R11[x].y;
+        z[x] = cmk<C>(p0, p1);
+    }
+    __syncthreads();
+    const C* Z = fft_lds<N, -1, kGT>(z, scratch, sT, tid);
+    for (int k = tid; k <= M; k += kGT) {
         const C za = Z[k], zb = cconj(Z[k == 0 ? 0 : N - k]);
         Q[size_t(k) * N + y0] = cmk<C>(real(0.5) * (za.x + zb.x), real(0.5) * (za.y + zb.y));
         Q[size_t(k) * N + y0 + 1] = cmk<C>(real(0.5) * (za.y - zb.y), real(-0.5) * (za.x - zb.x));
@@ -222,16 +217,15 @@ void gen_matvec(const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<
                 int nsteps, hipStream_t s) {
     using C = cplx<real>;
     constexpr int MC = Geo2<N>::MC;
-    static_assert(N % kRowsPerBlock == 0, "row blocks");
+    static_assert(N % 2 == 0, "row pairs");
     const C* twc = static_cast<const C*>(tw);
-    hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kWave), 0, s, static_cast<const real*>(x), W, Acc, Q, Gf,
+    hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc, Q, Gf,
                        static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST));
     for (int st = 0; st < nsteps; ++st)
         for (int q = 0; q < 4; ++q) {
-            hipLaunchKernelGGL((k_gen_row<real, N>), dim3(N / kRowsPerBlock), dim3(4 * kWave), 0, s, Gf, U, V, Ox, Oy,
-                               Q, twc);
+            hipLaunchKernelGGL((k_gen_row<real, N>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc);
             const int mode = (st == nsteps - 1 && q == 3) ? GEN_LAST : GEN_STAGE;
-            hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kWave), 0, s, static_cast<const real*>(x), W, Acc,
+            hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc,
                                Q, Gf, static_cast<real*>(y), twc, alpha, Re, dt, q, mode);
         }
 }

@@ -65,9 +65,14 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
-def measured_traffic(profile_name):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
-    the kernel sources changed since the counters were taken."""
+COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colstep.hpp")
+GENERAL_SOURCES = ("common.hpp", "fft.hpp", "kolmo2d.hip")
+
+
+def measured_traffic(profile_name, sources=COLSTEP_SOURCES, key="traffic_bytes_per_launch"):
+    """HBM bytes (per launch, or per `key`) from a committed rocprofv3 PMC
+    summary, or None when the kernel sources changed since the counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile_name)
     if not os.path.exists(path):
@@ -75,14 +80,14 @@ def measured_traffic(profile_name):
     rec = {}
     for line in open(path):
         parts = line.split()
-        if len(parts) == 2 and parts[0] in ("source_hash", "traffic_bytes_per_launch"):
+        if len(parts) == 2 and parts[0] in ("source_hash", key):
             rec[parts[0]] = parts[1]
     h = hashlib.sha256()
-    for f in ("common.hpp", "fft.hpp", "colfft.hpp", "kolmo.hip"):
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_1804_03859_amd", "csrc", f), "rb").read())
-    if rec.get("source_hash") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in rec:
+    if rec.get("source_hash") != h.hexdigest()[:16] or key not in rec:
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return float(rec[key])
 
 
 def _flops_for(N, nsteps):
@@ -201,6 +206,73 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     }
 
 
+def general_stage_bytes(N, s):
+    """Algorithmic HBM bytes of one RK4 stage of the general base-flow pipeline
+    (s bytes per real): the row kernel reads the four derived fields G
+    (4 x (M+1) x N complex) and the four base fields (4 N^2 reals) and writes the
+    product spectrum Q ((M+1) x N complex); the column kernel reads Q, reads and
+    writes the packed state and RK4 accumulator (n reals each) and writes G."""
+    M = (N - 1) // 3
+    n = 4 * M * (M + 1)
+    g = 4 * (M + 1) * N * 2 * s
+    q = (M + 1) * N * 2 * s
+    row = g + 4 * N * N * s + q
+    col = q + g + 4 * n * s
+    return row, col
+
+
+def run_general(args, tsk, W, np, torch):
+    """Arnoldi on a general two-dimensional base flow (random band-limited base
+    streamfunction, |jx|, |jy| <= 2, amplitude 0.3, seed 0), 128^2 FP64, through
+    the full 2-D pseudo-spectral pipeline."""
+    c = dict(W.KOLMO_128_FP64)
+    N, m, k, tol = c["N"], c["m"], c["k"], c["tol"]
+    nsteps = int(round(c["T"] / c["dt"]))
+    op = tsk.create_kolmo2d(N, tsk.TSK_FP64)
+    tsk.set_params_kolmo(op, c["Re"], c["alpha"], c["dt"], c["T"])
+    tsk.set_base_flow(op, *W.random_base_fields(N, c["alpha"], 2, 0))
+    phys = torch.from_numpy(W.kolmo_start_physical(N, 0)).cuda().reshape(-1)
+    x = op.new_state()
+
+    def step():
+        tsk.from_physical(op, phys, x)
+        return tsk.arnoldi(op, m, k, tol, v0=x)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    r = results[-1]
+    nmv = r["n_matvec"]
+    ms_apply = sum(q["ms_apply"] for q in results) / args.steps
+    row, col = general_stage_bytes(N, 8)
+    bytes_per_matvec = 4 * nsteps * (row + col) + 2 * op.n * 8
+    achieved = bytes_per_matvec / (ms_apply / nmv / 1e3) / 1e9
+    tsgp = nmv * nsteps * N * N
+    stage_traffic = measured_traffic("general_base_128_fp64_trace_and_traffic.md", GENERAL_SOURCES,
+                                     "traffic_bytes_per_stage")
+    return {
+        "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
+        "value": tsgp / (ms / 1e3), "unit": "time-steps*gridpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "linearized Navier-Stokes about a random band-limited 2-D base flow (|j| <= 2, "
+                               "amplitude 0.3, seed 0), 128x128 FP64, Re=20, alpha=0.5, IF-RK4 dt=0.005 T=1, "
+                               "Arnoldi m=64 k=6 tol=1e-8, full 2-D pseudo-spectral pipeline",
+                   "n_matvec": nmv, "status": r["status"], "ms_per_matvec": ms_apply / nmv,
+                   "lambda": [[round(float(v.real), 10), round(float(v.imag), 10)] for v in r["lam"]]},
+        "roofline": {"bound": "hbm", "kernel": "k_gen_row<double,128> + k_gen_col<double,128> (time stepper)",
+                     "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "bytes_per_matvec": bytes_per_matvec,
+                     "traffic": None if stage_traffic is None else stage_traffic * 4 * nsteps},
+        "cpu_baseline": None,
+    }
+
+
 def run_learned(args, tsk, W, np, torch):
     """Wall time to 6 Ritz pairs at residual 1e-8 on held-out (Re, alpha) at
     256^2: FP32 with the learned start against FP64 (and FP32) with the seeded
@@ -287,7 +359,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kolmo128",
-                    choices=["kolmo128", "kolmo512-fp32", "sweep", "learned", "copy"])
+                    choices=["kolmo128", "kolmo512-fp32", "sweep", "learned", "general", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -330,6 +402,8 @@ def main():
         out = run_single(args, tsk, W, np, torch, W.KOLMO_512_FP32, tsk.TSK_FP32, "f32")
     elif args.workload == "learned":
         out = run_learned(args, tsk, W, np, torch)
+    elif args.workload == "general":
+        out = run_general(args, tsk, W, np, torch)
     else:
         out = run_sweep(args, tsk, W, np, torch)
     print(json.dumps(out))

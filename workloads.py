@@ -61,6 +61,23 @@ def learned_holdout(count=16, seed=1000):
                  m=96, k=6, tol=1e-8, precision="fp32") for i in range(count)]
 
 
+def random_base_fields(N, alpha, max_j=2, seed=0, amplitude=0.3):
+    """Grid fields (U, V, dOmega/dx, dOmega/dy), N x N [y][x], of the random
+    band-limited base streamfunction psi = Re sum C e^{i(alpha bx x + by y)} of
+    ``random_base_modes``: U = d psi/dy, V = -d psi/dx, Omega = -lap psi."""
+    x = 2 * np.pi * np.arange(N) / (alpha * N)
+    y = 2 * np.pi * np.arange(N) / N
+    X, Y = np.meshgrid(x, y)
+    out = [np.zeros((N, N)) for _ in range(4)]
+    for (bx, by), c in random_base_modes(max_j, seed, amplitude).items():
+        kx, ky = alpha * bx, float(by)
+        e = c * np.exp(1j * (kx * X + ky * Y))
+        k2 = kx * kx + ky * ky
+        for f, mult in enumerate((1j * ky, -1j * kx, 1j * kx * k2, 1j * ky * k2)):
+            out[f] += (mult * e).real
+    return tuple(out)
+
+
 # ---- seeded draws -------------------------------------------------------------
 def normal_real(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)

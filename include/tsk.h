@@ -246,6 +246,16 @@ tsk_status tsk_mlp_start(tsk_mlp net, tsk_op op, double Re, double alpha, double
                          void* v0_dev, int* used_net);
 void tsk_mlp_destroy(tsk_mlp net);
 
+/* The real-arithmetic solver tsk_arnoldi uses for real operators (Francis
+ * double-shift QR, Golub & Van Loan Algorithms 7.5.1-7.5.2): H_dev is p x p
+ * real FP64, column-major with leading dimension ldh (>= p); only its upper
+ * Hessenberg part is read.  Outputs (dev): mu_dev (p complex128: eigenvalues,
+ * a complex pair as (a + ib, a - ib) in consecutive entries), res_dev (p doubles:
+ * beta |e_p^T y| for the unit eigenvector y of each eigenvalue).  1 <= p <= 96.
+ * Synchronous on hip_stream.  TSK_EEIG if the iteration failed to converge,
+ * TSK_ENONFINITE if H or beta holds a NaN or Inf. */
+tsk_status tsk_hessenberg_ritz_real(const double* H_dev, int ldh, int p, double beta, void* mu_dev,
+                                    void* res_dev, void* hip_stream);
 /* iid N(0,1) draws (device, FP64): count values of the splitmix64 +
  * Box-Muller stream of `seed` (element e uses outputs 2*(e/2), 2*(e/2)+1). */
 tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream);

@@ -257,6 +257,49 @@ tsk_status tsk_hessenberg_ritz(const void* H_dev, int ldh, int p, double beta, v
     })
 }
 
+tsk_status tsk_hessenberg_ritz_real(const double* H_dev, int ldh, int p, double beta, void* mu_dev, void* res_dev,
+                                    void* hip_stream) {
+    TSK_GUARD({
+        if (!H_dev || !mu_dev || !res_dev) return fail(TSK_EINVAL, "null buffer");
+        if (p < 1 || p > kMaxKrylov || ldh < p) return fail(TSK_EINVAL, "need 1 <= p <= 96 and ldh >= p");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        DevBuf Hc, S, rr, scal, dd;
+        const size_t ne = size_t(ldh) * p;
+        TSK_TRY(Hc.ensure(ne * sizeof(double2)));
+        TSK_TRY(S.ensure(size_t(p) * p * sizeof(double2)));
+        TSK_TRY(rr.ensure(sizeof(RitzResult)));
+        TSK_TRY(scal.ensure(64 * sizeof(double)));
+        TSK_TRY(dd.ensure(sizeof(KryDesc)));
+        // real values into the real parts of a complex copy (the layout the solver reads)
+        TSK_HIP(hipMemsetAsync(Hc.ptr, 0, ne * sizeof(double2), s));
+        TSK_HIP(hipMemcpy2DAsync(Hc.ptr, sizeof(double2), H_dev, sizeof(double), sizeof(double), ne,
+                                 hipMemcpyDeviceToDevice, s));
+        double sc[64] = {0};
+        sc[2] = beta;
+        RitzResult r0{};
+        KryDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.H = Hc.as<double2>();
+        d.ldh = ldh;
+        d.scal = scal.as<double>();
+        d.S = S.as<double2>();
+        d.mu = static_cast<double2*>(mu_dev);
+        d.res = static_cast<double*>(res_dev);
+        d.rr = rr.as<RitzResult>();
+        d.active = 1;
+        TSK_HIP(hipMemcpyAsync(scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+        TSK_HIP(hipMemcpyAsync(rr.ptr, &r0, sizeof(r0), hipMemcpyHostToDevice, s));
+        TSK_HIP(hipMemcpyAsync(dd.ptr, &d, sizeof(d), hipMemcpyHostToDevice, s));
+        TSK_TRY(hess_ritz_launch(dd.as<KryDesc>(), 1, p, 0, 0.0, true, s, true));
+        RitzResult h{};
+        TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+        TSK_HIP(hipStreamSynchronize(s));
+        if (h.nonfinite) return fail(TSK_ENONFINITE, "H or beta is not finite");
+        if (h.eig_fail) return fail(TSK_EEIG, "Hessenberg QR did not converge");
+        return TSK_OK;
+    })
+}
+
 tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream) {
     TSK_GUARD({
         if (!out_dev || count < 0) return fail(TSK_EINVAL, "bad output buffer or count");

@@ -27,6 +27,7 @@
 #include <cstring>
 #include <deque>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "krylov.hpp"
@@ -85,6 +86,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     const double dup_rel = lead->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
     const double res_floor = lead->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
     constexpr int NS = ArnoldiWork::kSlots;
+    constexpr bool kRealH = !std::is_same<TS, double2>::value;  // real operators: real Hessenberg QR
 
     // ---- per-instance workspace and descriptors ------------------------------------
     std::vector<KryDesc> Dh(count);
@@ -251,7 +253,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         }
         const hipStream_t st = L.side[t];
         TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[t], 0));
-        TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st));
+        TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st, kRealH));
         hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, Dt, count,
                            L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
         TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,

@@ -106,6 +106,66 @@ __device__ inline double tri_eigvec(const double2* T, int p, int i, double2* zc)
     return nrm;
 }
 
+// ---- wanted set (shared by the complex and the real eigensolver) ----------------------
+// converged: res <= max(tol, res_floor |mu|); order by |mu| descending (ties:
+// larger arg first, then index); skip unresolved copies; first k accepted.
+__device__ inline void select_wanted(const double2* __restrict__ mu, const double* __restrict__ res,
+                                     int* __restrict__ sel, RitzResult* __restrict__ rr, double* ctol, int* order,
+                                     int* dupc, int p, int k, double tol, double dup_rel, double res_floor,
+                                     int failed, int total, int lane) {
+    // converged: res <= max(tol, res_floor |mu|)
+    for (int i = lane; i < p; i += kHT) ctol[i] = fmax(tol, res_floor * cabs(mu[i]));
+    __syncthreads();
+    for (int i = lane; i < p; i += kHT) {
+        double mi = cabs(mu[i]), ai = atan2(mu[i].y, mu[i].x);
+        int rank = 0;
+        for (int j = 0; j < p; ++j) {
+            if (j == i) continue;
+            double mj = cabs(mu[j]), aj = atan2(mu[j].y, mu[j].x);
+            bool before = (mj > mi) || (mj == mi && (aj > ai || (aj == ai && j < i)));
+            rank += before ? 1 : 0;
+        }
+        order[rank] = i;
+        int d = 0;
+        if (!(res[i] <= ctol[i])) {
+            const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
+            for (int j = 0; j < p; ++j)
+                if (j != i && res[j] <= ctol[j] && cabs(csub(mu[i], mu[j])) <= rad) d = 1;
+        }
+        dupc[i] = d;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int nsel = 0, nconv = 0;
+        for (int t = 0; t < p && nsel < k; ++t) {
+            int i = order[t];
+            bool conv = res[i] <= ctol[i];
+            bool take;
+            if (conv) {
+                // a converged copy of an accepted value (only with dup_rel > 0)
+                take = true;
+                const double rad = dup_rel * cabs(mu[i]);
+                for (int a = 0; a < nsel && take; ++a)
+                    if (cabs(csub(mu[i], mu[sel[a]])) < rad) take = false;
+            } else {
+                take = !dupc[i];
+                const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
+                for (int a = 0; a < nsel && take; ++a)
+                    if (cabs(csub(mu[i], mu[sel[a]])) <= rad) take = false;
+            }
+            if (take) {
+                sel[nsel++] = i;
+                nconv += conv ? 1 : 0;
+            }
+        }
+        rr->nsel = nsel;
+        rr->nconv = nconv;
+        rr->done = (nsel >= k && nconv == nsel) ? 1 : 0;
+        rr->eig_fail = failed;
+        rr->iters = total;
+    }
+}
+
 // FULLZ: accumulate all of Z (standalone use, every eigenvector formed);
 // otherwise only the last row of Z is tracked (all the residuals need) and the
 // wanted Ritz coordinates are computed afterwards by inverse iteration.
@@ -328,59 +388,396 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
         if (lane == 0 && rr) { rr->eig_fail = failed; rr->iters = total; }
         return;
     } else {
-        // ---- wanted set ------------------------------------------------------------------------
-        // converged: res <= max(tol, res_floor |mu|)
-        for (int i = lane; i < p; i += kHT) ctol[i] = fmax(tol, res_floor * cabs(mu[i]));
-        __syncthreads();
-        for (int i = lane; i < p; i += kHT) {
-            double mi = cabs(mu[i]), ai = atan2(mu[i].y, mu[i].x);
-            int rank = 0;
-            for (int j = 0; j < p; ++j) {
-                if (j == i) continue;
-                double mj = cabs(mu[j]), aj = atan2(mu[j].y, mu[j].x);
-                bool before = (mj > mi) || (mj == mi && (aj > ai || (aj == ai && j < i)));
-                rank += before ? 1 : 0;
+        select_wanted(mu, res, sel, rr, ctol, order, dupc, p, k, tol, dup_rel, res_floor, failed, total, lane);
+    }
+}
+
+// ---- real Hessenberg matrices (real operators) ------------------------------------------
+// Francis double-shift QR in real arithmetic (Francis 1961; Golub & Van Loan,
+// "Matrix Computations", Algorithms 7.5.1-7.5.2): each sweep chases a 3-element
+// Householder bulge down the active window with shifts from the trailing 2x2
+// block (an exceptional shift every tenth iteration), deflation on negligible
+// subdiagonal entries, and every converged 2x2 block with real eigenvalues split
+// by one rotation, so T ends quasi upper triangular with 2x2 blocks only for
+// complex conjugate pairs.  The similarity P T P of one bulge step touches three
+// rows and three columns whose only overlap is a 3x3 block: nine lanes form the
+// block, the others the rest of the rows and columns, in one phase.  Only the
+// last row of Z (H = Z T Z^T) is tracked, as in the complex solver; the
+// eigenvector of each Ritz value follows by back substitution through the
+// quasi-triangular T (one lane per eigenvalue, complex arithmetic for pairs).
+
+// Householder vector for (x, y, z): v = (1, v1, v2), tau, with
+// (I - tau v v^T) (x, y, z)^T = (alpha, 0, 0)^T.  tau = 0 when y = z = 0.
+__device__ inline void house3(double x, double y, double z, double& v1, double& v2, double& tau, double& alpha) {
+    const double sig = y * y + z * z;
+    if (sig == 0.0) {
+        v1 = v2 = tau = 0.0;
+        alpha = x;
+        return;
+    }
+    const double nrm = sqrt(x * x + sig);
+    alpha = x >= 0.0 ? -nrm : nrm;
+    const double u0 = x - alpha;  // no cancellation: x and -alpha share a sign
+    v1 = y / u0;
+    v2 = z / u0;
+    tau = (alpha - x) / alpha;
+}
+
+// Eigenvector z (complex, z[j] = 0 beyond the eigenvalue's block) of the quasi
+// upper-triangular real T (row-major p x p) for eigenvalue index q with value m;
+// blk[j]: 0 = 1x1, 1 = first / 2 = second row of a 2x2 block.  Returns ||z||^2.
+__device__ inline double quasi_eigvec(const double* T, const int* blk, int p, int q, double2 m, double2* z) {
+    double smin = kEps * (fabs(m.x) + fabs(m.y));
+    if (smin < 1e-290) smin = 1e-290;
+    int c;  // next row to solve (downwards to 0)
+    double nrm = 1.0;
+    if (blk[q] == 0) {
+        z[q] = cmk<double2>(1.0, 0.0);
+        c = q - 1;
+    } else {
+        // rows (r0, r0+1) of the pair; z[r0+1] = 1, z[r0] = (m - T[r0+1][r0+1]) / T[r0+1][r0]
+        const int r0 = blk[q] == 1 ? q : q - 1;
+        const double sub = T[(r0 + 1) * p + r0];
+        const double2 z0 = cscale(cmk<double2>(m.x - T[(r0 + 1) * p + r0 + 1], m.y), 1.0 / sub);
+        z[r0 + 1] = cmk<double2>(1.0, 0.0);
+        z[r0] = z0;
+        nrm += cabs2(z0);
+        c = r0 - 1;
+    }
+    const int top = blk[q] == 1 ? q + 1 : q;  // last nonzero index
+    while (c >= 0) {
+        if (blk[c] == 2) {
+            // 2x2 block (c-1, c): [T - m I] [z_{c-1}; z_c] = -[r_{c-1}; r_c]
+            double2 r1 = cmk<double2>(0.0, 0.0), r2 = cmk<double2>(0.0, 0.0);
+            for (int j = c + 1; j <= top; ++j) {
+                r1 = cadd(r1, cscale(z[j], T[(c - 1) * p + j]));
+                r2 = cadd(r2, cscale(z[j], T[c * p + j]));
             }
-            order[rank] = i;
-            int d = 0;
-            if (!(res[i] <= ctol[i])) {
-                const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
-                for (int j = 0; j < p; ++j)
-                    if (j != i && res[j] <= ctol[j] && cabs(csub(mu[i], mu[j])) <= rad) d = 1;
-            }
-            dupc[i] = d;
+            const double2 a = cmk<double2>(T[(c - 1) * p + (c - 1)] - m.x, -m.y);
+            const double2 b = cmk<double2>(T[(c - 1) * p + c], 0.0);
+            const double2 d = cmk<double2>(T[c * p + (c - 1)], 0.0);
+            const double2 e = cmk<double2>(T[c * p + c] - m.x, -m.y);
+            double2 det = csub(cmul(a, e), cmul(b, d));
+            if (cabs1(det) < smin) det = cmk<double2>(smin, 0.0);
+            // Cramer's rule on -r
+            const double2 x1 = cdiv(csub(cmul(b, r2), cmul(e, r1)), det);
+            const double2 x2 = cdiv(csub(cmul(d, r1), cmul(a, r2)), det);
+            z[c - 1] = x1;
+            z[c] = x2;
+            nrm += cabs2(x1) + cabs2(x2);
+            c -= 2;
+        } else {
+            double2 r = cmk<double2>(0.0, 0.0);
+            for (int j = c + 1; j <= top; ++j) r = cadd(r, cscale(z[j], T[c * p + j]));
+            double2 den = cmk<double2>(T[c * p + c] - m.x, -m.y);
+            if (cabs1(den) < smin) den = cmk<double2>(smin, 0.0);
+            const double2 x = cdiv(cmk<double2>(-r.x, -r.y), den);
+            z[c] = x;
+            nrm += cabs2(x);
+            c -= 1;
         }
-        __syncthreads();
-        if (lane == 0) {
-            int nsel = 0, nconv = 0;
-            for (int t = 0; t < p && nsel < k; ++t) {
-                int i = order[t];
-                bool conv = res[i] <= ctol[i];
-                bool take;
-                if (conv) {
-                    // a converged copy of an accepted value (only with dup_rel > 0)
-                    take = true;
-                    const double rad = dup_rel * cabs(mu[i]);
-                    for (int a = 0; a < nsel && take; ++a)
-                        if (cabs(csub(mu[i], mu[sel[a]])) < rad) take = false;
-                } else {
-                    take = !dupc[i];
-                    const double rad = fmax(res[i], dup_rel * cabs(mu[i]));
-                    for (int a = 0; a < nsel && take; ++a)
-                        if (cabs(csub(mu[i], mu[sel[a]])) <= rad) take = false;
-                }
-                if (take) {
-                    sel[nsel++] = i;
-                    nconv += conv ? 1 : 0;
-                }
+    }
+    for (int j = top + 1; j < p; ++j) z[j] = cmk<double2>(0.0, 0.0);
+    return nrm;
+}
+
+// Rotation G = [[cs, sn], [-sn, cs]] applied as T <- G T G^T on indices (i, i+1)
+// of the full matrix (rows i, i+1 from column cfrom; columns i, i+1 for rows
+// 0..rto) and zl <- zl G^T.  One wavefront, uniform control flow.
+__device__ inline void rot_similarity(double* T, double* zl, int p, int i, double cs, double sn, int cfrom, int rto,
+                                      int lane) {
+    for (int c = cfrom + lane; c < p; c += kHT) {
+        const double u = T[i * p + c], v = T[(i + 1) * p + c];
+        T[i * p + c] = cs * u + sn * v;
+        T[(i + 1) * p + c] = -sn * u + cs * v;
+    }
+    __syncthreads();
+    for (int r = lane; r <= rto; r += kHT) {
+        const double u = T[r * p + i], v = T[r * p + i + 1];
+        T[r * p + i] = cs * u + sn * v;
+        T[r * p + i + 1] = -sn * u + cs * v;
+    }
+    if (lane == 0) {
+        const double u = zl[i], v = zl[i + 1];
+        zl[i] = cs * u + sn * v;
+        zl[i + 1] = -sn * u + cs * v;
+    }
+    __syncthreads();
+}
+
+// One bulge step: the similarity T <- P T P with the NB-element reflector P at
+// indices kk..kk+NB-1 built from (x, y, z), and zl <- zl P.  The NB x NB block by
+// lanes 0..NB*NB-1, the rows kk.. at columns kk+NB..p-1 and the columns kk.. at
+// rows 0..kk-1 and kk+NB (when inside the window) by the lanes in turn, all from
+// pre-update values in one phase.
+template <int NB>
+__device__ inline void bulge_step(double* Tr, double* zl, int p, int l, int ihi, int kk, double x, double y,
+                                  double z, int lane) {
+    double v1, v2, tau, alpha;
+    house3(x, y, NB == 3 ? z : 0.0, v1, v2, tau, alpha);
+    if (tau != 0.0) {
+        const double v[3] = {1.0, v1, NB == 3 ? v2 : 0.0};
+        const int rto = (kk + 3 <= ihi ? kk + 3 : ihi);  // right factor: rows 0..rto
+        const int ncr = p - (kk + NB);                     // row-only columns kk+NB..p-1
+        const int ncc = kk + ((kk + NB <= rto) ? 1 : 0);   // col-only rows 0..kk-1, kk+NB
+        double bval = 0.0;
+        const bool blane = lane < NB * NB;
+        const int bi = blane ? lane / NB : 0, bj = blane ? lane % NB : 0;
+        if (blane) {
+            double B[NB][NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) B[a][c] = Tr[(kk + a) * p + kk + c];
+            double u[NB], w[NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                u[a] = 0.0;
+                w[a] = 0.0;
             }
-            rr->nsel = nsel;
-            rr->nconv = nconv;
-            rr->done = (nsel >= k && nconv == nsel) ? 1 : 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    u[a] += B[a][c] * v[c];
+                    w[c] += v[a] * B[a][c];
+                }
+            double g = 0.0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) g += v[a] * u[a];
+            // select the lane's entry without dynamic register indexing
+            double bij = 0.0, ui = 0.0, wj = 0.0, vi = 0.0, vj = 0.0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                if (a == bi) { ui = u[a]; vi = v[a]; }
+                if (a == bj) { wj = w[a]; vj = v[a]; }
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (a == bi && c == bj) bij = B[a][c];
+            }
+            bval = bij - tau * vi * wj - tau * ui * vj + tau * tau * g * vi * vj;
+        }
+        double nv[2][NB];
+        int nidx[2] = {-1, -1}, nstr[2] = {1, 1};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int t = lane + q * kHT;
+            if (t < ncr + ncc) {
+                int base, stride;
+                if (t < ncr) {
+                    base = kk * p + (kk + NB + t);
+                    stride = p;
+                } else {
+                    const int qq = t - ncr;
+                    base = (qq < kk ? qq : kk + NB) * p + kk;
+                    stride = 1;
+                }
+                double tv[NB], dot = 0.0;
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    tv[a] = Tr[base + a * stride];
+                    dot += v[a] * tv[a];
+                }
+#pragma unroll
+                for (int a = 0; a < NB; ++a) nv[q][a] = tv[a] - tau * dot * v[a];
+                nidx[q] = base;
+                nstr[q] = stride;
+            }
+        }
+        double zn[NB];
+        {
+            double dz = 0.0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) dz += zl[kk + a] * v[a];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) zn[a] = zl[kk + a] - tau * dz * v[a];
+        }
+        // writes (every lane has done all of its reads of this phase)
+        if (blane) Tr[(kk + bi) * p + kk + bj] = bval;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (nidx[q] >= 0) {
+#pragma unroll
+                for (int a = 0; a < NB; ++a) Tr[nidx[q] + a * nstr[q]] = nv[q][a];
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < NB; ++a) zl[kk + a] = zn[a];
+            if (kk > l) {  // the reflector turned column kk-1 into (alpha, 0, ..., 0)
+                Tr[kk * p + kk - 1] = alpha;
+#pragma unroll
+                for (int a = 1; a < NB; ++a) Tr[(kk + a) * p + kk - 1] = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restrict__ Dv, int p, int k, double tol,
+                                                        int standalone) {
+    const KryDesc& dsc = Dv[blockIdx.x];
+    if (!dsc.active) return;
+    const double2* __restrict__ H = dsc.H;
+    const int ldh = dsc.ldh;
+    double2* __restrict__ S = dsc.S;
+    double2* __restrict__ mu = dsc.mu;
+    double* __restrict__ res = dsc.res;
+    int* __restrict__ sel = dsc.sel;
+    RitzResult* __restrict__ rr = dsc.rr;
+    extern __shared__ double Tr[];  // p*p, row-major
+    __shared__ double zl[kMaxKrylov];
+    __shared__ int blk[kMaxKrylov];
+    __shared__ int order[kMaxKrylov];
+    __shared__ int dupc[kMaxKrylov];
+    __shared__ double ctol[kMaxKrylov];
+    const int lane = threadIdx.x;
+
+    const double beta = standalone ? dsc.scal[2] : H[p + (size_t)ldh * (p - 1)].x;
+    bool bad = !isfinite(beta);
+    for (int e = lane; e < p * p; e += kHT) {
+        const int r = e / p, c = e % p;
+        const double v = (r <= c + 1) ? H[r + (size_t)ldh * c].x : 0.0;
+        bad = bad || !isfinite(v);
+        Tr[e] = v;
+    }
+    if (__ballot(bad)) {
+        if (lane == 0 && rr) {
+            rr->nonfinite = 1;
+            rr->done = 0;
+            rr->nsel = 0;
+            rr->nconv = 0;
+            rr->eig_fail = 0;
+            rr->iters = 0;
+        }
+        return;
+    }
+    for (int c = lane; c < p; c += kHT) {
+        zl[c] = c == p - 1 ? 1.0 : 0.0;
+        blk[c] = 0;
+    }
+    __syncthreads();
+
+    int ihi = p - 1, its = 0, total = 0, failed = 0;
+    const int itmax = 30 * (p > 10 ? p : 10);
+    while (ihi > 0) {
+        // deflation: largest l <= ihi with a negligible T[l][l-1] (else 0)
+        bool s0 = false, s1 = false;
+        {
+            int i = lane + 1;
+            if (i <= ihi) {
+                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
+                if (tst == 0.0) tst = 1.0;
+                s0 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
+            }
+            i = lane + 65;
+            if (i <= ihi) {
+                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
+                if (tst == 0.0) tst = 1.0;
+                s1 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
+            }
+        }
+        const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
+        const int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
+        __syncthreads();
+        if (l > 0 && lane == 0) Tr[l * p + (l - 1)] = 0.0;
+        __syncthreads();
+        if (l == ihi) {  // 1x1 block converged
+            --ihi;
+            its = 0;
+            continue;
+        }
+        if (l == ihi - 1) {  // 2x2 block: split when its eigenvalues are real
+            const int i = ihi - 1;
+            const double a = Tr[i * p + i], b = Tr[i * p + i + 1], c = Tr[(i + 1) * p + i], d = Tr[(i + 1) * p + i + 1];
+            const double hp = 0.5 * (a - d);
+            const double disc = hp * hp + b * c;
+            if (disc >= 0.0) {
+                // eigenvalue closest to d, eigenvector (lam - d, c) -> rotation taking it to e_1
+                const double sq = sqrt(disc);
+                const double lam = d + (hp >= 0.0 ? hp + sq : hp - sq);
+                double ex = lam - d, ey = c;
+                const double en = hypot(ex, ey);
+                if (en > 0.0) {
+                    const double cs = ex / en, sn = ey / en;
+                    rot_similarity(Tr, zl, p, i, cs, sn, i, i + 1, lane);
+                }
+                if (lane == 0) Tr[(i + 1) * p + i] = 0.0;
+                __syncthreads();
+            } else if (lane == 0) {
+                blk[i] = 1;
+                blk[i + 1] = 2;
+            }
+            __syncthreads();
+            ihi -= 2;
+            its = 0;
+            continue;
+        }
+        if (++total > itmax) {
+            failed = 1;
+            break;
+        }
+        ++its;
+        // double shift: s = sum, t = product of the trailing 2x2 eigenvalues
+        double ss, tt;
+        {
+            const double a = Tr[(ihi - 1) * p + (ihi - 1)], b = Tr[(ihi - 1) * p + ihi];
+            const double c = Tr[ihi * p + (ihi - 1)], d = Tr[ihi * p + ihi];
+            if (its % 10 == 0) {
+                const double sx = fabs(c) + fabs(Tr[(ihi - 1) * p + (ihi - 2)]);
+                const double h11 = 0.75 * sx + d, h12 = -0.4375 * sx, h21 = sx;
+                ss = 2.0 * h11;
+                tt = h11 * h11 - h12 * h21;
+            } else {
+                ss = a + d;
+                tt = a * d - b * c;
+            }
+        }
+        double x, y, z;
+        {
+            const double t00 = Tr[l * p + l], t01 = Tr[l * p + l + 1], t10 = Tr[(l + 1) * p + l];
+            const double t11 = Tr[(l + 1) * p + l + 1], t21 = Tr[(l + 2) * p + l + 1];
+            x = t00 * t00 + t01 * t10 - ss * t00 + tt;
+            y = t10 * (t00 + t11 - ss);
+            z = t10 * t21;
+        }
+        // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
+        for (int kk = l; kk <= ihi - 2; ++kk) {
+            bulge_step<3>(Tr, zl, p, l, ihi, kk, x, y, z, lane);
+            x = Tr[(kk + 1) * p + kk];
+            y = Tr[(kk + 2) * p + kk];
+            z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
+        }
+        bulge_step<2>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane);
+    }
+
+    // ---- Ritz values, eigenvectors of T, residuals ---------------------------------------------
+    for (int i = lane; i < p; i += kHT) {
+        const double ti = Tr[i * p + i];
+        double2 m = cmk<double2>(ti, 0.0);
+        if (blk[i] != 0) {
+            const int r0 = blk[i] == 1 ? i : i - 1;
+            const double a = Tr[r0 * p + r0], b = Tr[r0 * p + r0 + 1], c = Tr[(r0 + 1) * p + r0];
+            const double d = Tr[(r0 + 1) * p + r0 + 1];
+            const double hp = 0.5 * (a - d);
+            const double im = sqrt(fmax(-(hp * hp + b * c), 0.0));
+            m = cmk<double2>(0.5 * (a + d), blk[i] == 1 ? im : -im);
+        }
+        mu[i] = m;
+        double2* zc = S + (size_t)i * p;
+        const double n2 = quasi_eigvec(Tr, blk, p, i, m, zc);
+        double2 last = cmk<double2>(0.0, 0.0);
+        for (int c = 0; c < p; ++c) last = cadd(last, cscale(zc[c], zl[c]));
+        res[i] = fabs(beta) * cabs(last) / sqrt(n2);
+    }
+    __syncthreads();
+    if (standalone) {
+        if (lane == 0 && rr) {
             rr->eig_fail = failed;
             rr->iters = total;
         }
+        return;
     }
+    select_wanted(mu, res, sel, rr, ctol, order, dupc, p, k, tol, dsc.dup_rel, dsc.res_floor, failed, total, lane);
 }
 
 // Unit Ritz coordinates of the wanted pairs by inverse iteration on H_p (one
@@ -465,21 +862,30 @@ __global__ __launch_bounds__(kHT) void k_ritz_coords(const KryDesc* __restrict__
 
 }  // namespace
 
-tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s) {
+tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
+                            bool real_h) {
     if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Hessenberg size must be in [1, 96]");
-    size_t lds = size_t(p) * p * sizeof(double2);
     static bool attr_set = false;
     if (!attr_set) {
         const int mx = int(kMaxKrylov * kMaxKrylov * sizeof(double2));
         TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
         TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz<false>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
         TSK_HIP(hipFuncSetAttribute((const void*)k_ritz_coords, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        TSK_HIP(hipFuncSetAttribute((const void*)k_hess_ritz_real, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(kMaxKrylov * kMaxKrylov * sizeof(double))));
         attr_set = true;
     }
-    if (full)
-        hipLaunchKernelGGL(k_hess_ritz<true>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
-    else
-        hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
+    if (real_h) {
+        // full: the standalone entry point (beta from scal[2]; values and residuals only)
+        hipLaunchKernelGGL(k_hess_ritz_real, dim3(count), dim3(kHT), size_t(p) * p * sizeof(double), s, D, p, k, tol,
+                           full ? 1 : 0);
+    } else {
+        const size_t lds = size_t(p) * p * sizeof(double2);
+        if (full)
+            hipLaunchKernelGGL(k_hess_ritz<true>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
+        else
+            hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
+    }
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }

@@ -141,8 +141,11 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
 // Device Hessenberg eigensolver + wanted-set selection (hessenberg.hip), one
 // wavefront per instance of the descriptor table (H, scal[2] = beta, scratch).
 // full = true: accumulate all of Z and form every eigenvector (standalone use).
+// real_h = true: H is real (real operators): real double-shift QR; with full,
+// the standalone real solver (values and residuals only, beta from scal[2]).
 struct KryDesc;
-tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s);
+tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
+                            bool real_h = false);
 // Unit Ritz coordinates of the wanted pairs (inverse iteration on H_p): Y[s*p + r].
 // Needs the attribute set by a prior hess_ritz_launch.
 tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s);  // p = steps

@@ -63,6 +63,7 @@ def load():
         "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
         "tsk_last_basis": [vp, P(vp), P(i64)],
         "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
+        "tsk_hessenberg_ritz_real": [vp, i32, i32, f64, vp, vp, vp],
         "tsk_normal_fill": [vp, i64, u64, vp],
         "tsk_mlp_create": [P(vp), i32, P(f64), P(f64), vp],
         "tsk_mlp_param_count": [vp, P(i64)],
@@ -97,7 +98,7 @@ def exported_symbols():
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_last_hessenberg",
-            "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
+            "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
             "tsk_mlp_get_params", "tsk_mlp_forward", "tsk_mlp_gradients", "tsk_mlp_train",
             "tsk_ritz_block_target", "tsk_mlp_start", "tsk_mlp_destroy"]
@@ -321,6 +322,19 @@ def hessenberg_ritz(H, beta, stream=None):
     res = torch.zeros(p, dtype=torch.float64, device=H.device)
     _check(load().tsk_hessenberg_ritz(_ptr(Hc), p, p, beta, _ptr(mu), _ptr(Y), _ptr(res), _stream(stream)))
     return mu, Y.t(), res  # Y rows were columns
+
+
+def hessenberg_ritz_real(H, beta, stream=None):
+    """Device real double-shift QR of a p x p real Hessenberg tensor (cuda):
+    eigenvalues (complex128) and residual estimates beta |e_p^T y|."""
+    p = H.shape[0]
+    if H.dim() != 2 or H.shape[1] != p or not H.is_cuda:
+        raise ValueError("H must be a square CUDA/HIP tensor")
+    Hc = H.to(torch.float64).t().contiguous()  # column-major storage
+    mu = torch.zeros(p, dtype=torch.complex128, device=H.device)
+    res = torch.zeros(p, dtype=torch.float64, device=H.device)
+    _check(load().tsk_hessenberg_ritz_real(_ptr(Hc), p, p, beta, _ptr(mu), _ptr(res), _stream(stream)))
+    return mu, res
 
 
 def normal_fill(count, seed, stream=None):

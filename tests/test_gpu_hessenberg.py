@@ -52,3 +52,59 @@ def test_graded_and_structured_matrices(tsk):
         mu = mu.cpu().numpy()
         ev = np.linalg.eigvals(H)
         assert match_sets(mu, ev) <= 1e-7 * max(1.0, np.linalg.norm(H, 2))
+
+
+# ---- the real double-shift solver (real operators) -------------------------------------
+def _real_check(tsk, H, beta, tol_ev=1e-9, check_res=True):
+    mu, res = tsk.hessenberg_ritz_real(torch.from_numpy(H).cuda(), beta)
+    mu, res = mu.cpu().numpy(), res.cpu().numpy()
+    ev, V = np.linalg.eig(H)
+    nrm = max(1.0, np.linalg.norm(H, 2))
+    assert match_sets(mu, ev) <= tol_ev * nrm
+    # conjugate pairs come as (a + ib, a - ib) in consecutive entries
+    for i in range(len(mu)):
+        if mu[i].imag > 0:
+            assert abs(mu[i + 1] - np.conj(mu[i])) <= 1e-14 * nrm
+    if check_res:
+        V = V / np.linalg.norm(V, axis=0, keepdims=True)
+        for i in range(len(mu)):
+            j = int(np.argmin(np.abs(ev - mu[i])))
+            assert abs(res[i] - beta * abs(V[-1, j])) <= 1e-9 * max(beta, 1e-300) + 1e-8 * res[i], (i, res[i])
+    return mu, res
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 7, 40, 64, 96])
+def test_real_solver_matches_lapack(tsk, p):
+    print(f"real hessenberg p={p}", flush=True)
+    _real_check(tsk, _hess(p, 20 + p, False), 0.61)
+
+
+def test_real_solver_structured_matrices(tsk):
+    from scipy.linalg import hessenberg
+    # graded
+    _real_check(tsk, _hess(30, 5, False, scale=0.5), 1.0, tol_ev=1e-7, check_res=False)
+    # rotation blocks: exact complex pairs of known values
+    rot = np.zeros((12, 12))
+    for i in range(0, 12, 2):
+        a, b = 0.9 - 0.05 * i, 0.3 + 0.02 * i
+        rot[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
+    Q, _ = np.linalg.qr(W.normal_real((12, 12), 6))
+    mu, _ = _real_check(tsk, hessenberg(Q @ rot @ Q.T), 1.0, tol_ev=1e-10, check_res=False)
+    # a 2x2 block with real eigenvalues next to a pair, already deflated from the rest
+    H = np.zeros((6, 6))
+    H[:2, :2] = [[1.0, 2.0], [3.0, 4.0]]
+    H[2:4, 2:4] = [[0.5, -1.0], [2.0, 0.5]]
+    H[4:, 4:] = [[-1.0, 0.25], [1.0, -1.0]]
+    H[np.triu_indices(6, 2)] = 0.1
+    _real_check(tsk, H, 0.3)
+    # near-defective: a small-coupling chain of equal diagonal entries
+    D = np.diag(np.full(12, 0.5)) + np.diag(np.full(11, 1.0), -1) * 1e-3
+    _real_check(tsk, D, 1.0, tol_ev=1e-7, check_res=False)
+
+
+def test_real_solver_rejects_non_finite_input(tsk):
+    H = _hess(8, 3, False)
+    H[2, 3] = np.nan
+    with pytest.raises(tsk.TskError) as e:
+        tsk.hessenberg_ritz_real(torch.from_numpy(H).cuda(), 1.0)
+    assert e.value.status == tsk.TSK_ENONFINITE

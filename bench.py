@@ -194,7 +194,7 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
         "data": "synthetic",
         "config": {"workload": f"linearized Kolmogorov flow {N}x{N} {dtype_name.upper()}, Re=20, alpha=0.5, "
                                f"IF-RK4 dt=0.005 T=1, Arnoldi m={m} k={k} tol=1e-8, seeded N(0,1) start",
-                   "n_matvec": nmv, "status": r["status"],
+                   "n_matvec": nmv, "status": r["status"], "columns_per_wave": tsk.get_tuning(op),
                    "wall_time_to_6_pairs_s": ms_per_step / 1e3,
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],

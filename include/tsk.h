@@ -114,6 +114,16 @@ tsk_status tsk_set_base_kolmogorov(tsk_op op, int n_forcing);
 tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
                              const double* dOmega_dx, const double* dOmega_dy);
 
+/* Tuning of the parallel-base time stepper: kx columns per 64-lane wavefront,
+ * 1 or 2 (2 only for N <= 256; larger N always use 1).  0 (the default) lets
+ * the library time both on the first matvec of a given size, precision, base
+ * kind and launch size and keep the faster for the process.  Both variants
+ * compute every column with the same arithmetic, so results do not depend on
+ * the choice.  tsk_get_tuning reports the forced or tuned value (0 = not tuned
+ * yet).  Navier-Stokes operators only. */
+tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave);
+tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave);
+
 /* ---------------------------------------------------------------------------
  * Common to all operators.
  * ------------------------------------------------------------------------- */

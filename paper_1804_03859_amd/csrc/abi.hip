@@ -132,6 +132,21 @@ tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V, const 
     })
 }
 
+tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_tuning(op->op.get(), columns_per_wave);
+    })
+}
+
+tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!columns_per_wave) return fail(TSK_EINVAL, "null argument");
+        return kolmo_get_tuning(op->op.get(), columns_per_wave);
+    })
+}
+
 tsk_status tsk_state_dim(tsk_op op, int64_t* n_scalars, int* is_complex, int* elem_bytes) {
     TSK_GUARD({
         TSK_NEED(op);

@@ -135,6 +135,103 @@ __device__ inline void col_fft(C (&v)[ColPlan<N>::NBL][ColPlan<N>::RE], C* a, C*
     }
 }
 
+// ---- several independent columns per wavefront ----------------------------------
+// The same transform on COLS columns at once.  Every pass first loads the
+// butterfly inputs of all columns, then computes, then stores, so the LDS
+// latency of one column overlaps the arithmetic of the others (a lone
+// wavefront per SIMD has no other way to hide it).  Each column has its own
+// pair of LDS buffers; twiddles are shared.
+template <int N, int R, int NS, int SIGN, int COLS, typename C>
+__device__ inline void col_mid_pass_m(C* const* in, C* const* out, const C* __restrict__ tw, int lane) {
+    constexpr int NB = N / R;
+    constexpr int TS = N / (NS * R);
+    for (int j = lane; j < NB; j += kWave) {
+        const int k = j % NS;
+        C w[R];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            w[r] = tw[k * r * TS];
+            if constexpr (SIGN > 0) w[r].y = -w[r].y;
+        }
+        C v[COLS][R];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c][r] = in[c][pad8(j + r * NB)];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], w[r]);
+            dft<R, SIGN>(v[c]);
+        }
+        const int o = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[c][pad8(o + r * NS)] = v[c][r];
+    }
+}
+
+template <int N, int P, int NS, int SIGN, int COLS, typename C>
+__device__ inline bool col_mid_passes_m(C* const* a, C* const* b, const C* tw, int lane) {
+    using PL = ColPlan<N>;
+    if constexpr (P >= PL::NMID) {
+        return true;  // result in a
+    } else {
+        constexpr int R = col_mid_radix(N, PL::MID, P);
+        col_mid_pass_m<N, R, NS, SIGN, COLS>(a, b, tw, lane);
+        __syncthreads();
+        return !col_mid_passes_m<N, P + 1, NS * R, SIGN, COLS>(b, a, tw, lane);
+    }
+}
+
+// v[c][b][r] holds position j + r NB of column c (j = lane + 64 b) on entry and
+// on exit.  a[c], b[c]: LDS buffers of column c.
+template <int N, int SIGN, int COLS, typename C>
+__device__ inline void col_fft_m(C (&v)[COLS][ColPlan<N>::NBL][ColPlan<N>::RE], C* const* a, C* const* b,
+                                 const C* tw, int lane) {
+    using PL = ColPlan<N>;
+    constexpr int RE = PL::RE, NB = PL::NB;
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                dft<RE, SIGN>(v[c][q]);
+#pragma unroll
+                for (int r = 0; r < RE; ++r) a[c][pad8(j * RE + r)] = v[c][q][r];
+            }
+        }
+    }
+    __syncthreads();
+    const bool in_a = col_mid_passes_m<N, 0, RE, SIGN, COLS>(a, b, tw, lane);
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+            C w[RE];
+#pragma unroll
+            for (int r = 1; r < RE; ++r) {
+                w[r] = tw[j * r];
+                if constexpr (SIGN > 0) w[r].y = -w[r].y;
+            }
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const C* src = in_a ? a[c] : b[c];
+#pragma unroll
+                for (int r = 0; r < RE; ++r) v[c][q][r] = src[pad8(j + r * NB)];
+            }
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+                for (int r = 1; r < RE; ++r) v[c][q][r] = cmul(v[c][q][r], w[r]);
+                dft<RE, SIGN>(v[c][q]);
+            }
+        }
+    }
+}
+
 // Buffer that col_fft's last pass reads from (the first pass writes `a`).
 template <int N> constexpr bool col_result_in_a() { return (ColPlan<N>::NMID % 2) == 0; }
 

@@ -30,6 +30,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "colstep.hpp"
 #include "kolmo2d.hpp"
@@ -143,6 +146,80 @@ __global__ __launch_bounds__(kWave) void k_rows_inv(const cplx<real>* __restrict
 }
 
 // ---- dispatch ------------------------------------------------------------------------------
+// Columns per wavefront of the stepper: 1, or 2 for N <= kMaxColsPairN (beyond,
+// two columns' registers do not fit).  Chosen per (N, precision, base kind,
+// launch size) by timing both variants once per process (column_choice); the
+// two variants perform the same arithmetic per column, so the choice changes
+// only the speed.
+constexpr int kMaxColsPairN = 256;
+inline int max_cols(int N) { return N <= kMaxColsPairN ? 2 : 1; }
+
+// Task list of one instance: kx = 0 alone, then groups of `cols` columns.
+std::vector<ColTask> column_tasks(int inst, int M, int cols) {
+    std::vector<ColTask> t;
+    t.push_back(ColTask{inst, 0, 1});
+    for (int kx = 1; kx <= M; kx += cols) t.push_back(ColTask{inst, kx, std::min(cols, M - kx + 1)});
+    return t;
+}
+
+struct TuneKey {
+    int N, fp32, prop, bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(N, fp32, prop, bucket) < std::tie(o.N, o.fp32, o.prop, o.bucket);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+// Times launch(1) and launch(2) (each once to warm up, once measured) on stream
+// s and caches the faster; launch(c) must be a complete, repeatable matvec.
+template <typename F>
+tsk_status column_choice(const TuneKey& key, hipStream_t s, F&& launch, int* out) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *out = it->second;
+            return TSK_OK;
+        }
+    }
+    if (max_cols(key.N) == 1) {
+        *out = 1;
+    } else {
+        hipEvent_t e0, e1;
+        TSK_HIP(hipEventCreate(&e0));
+        TSK_HIP(hipEventCreate(&e1));
+        float best = 0.0f;
+        int bc = 1;
+        for (int c = 1; c <= 2; ++c) {
+            launch(c);
+            TSK_HIP(hipEventRecord(e0, s));
+            launch(c);
+            TSK_HIP(hipEventRecord(e1, s));
+            TSK_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            TSK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (c == 1 || ms < best) {
+                best = ms;
+                bc = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        TSK_HIP(hipGetLastError());
+        *out = bc;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = *out;
+    return TSK_OK;
+}
+
+int size_bucket(int columns) {
+    int b = 0;
+    while ((1 << b) < columns) ++b;
+    return b;
+}
+
 struct KolmoLaunch {
     const void* x;
     void* y;
@@ -153,14 +230,22 @@ struct KolmoLaunch {
 
 template <typename real, int N> struct KK {
     using C = cplx<real>;
-    static void colstep(const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
-                        bool prop, const void* tw, int jstep, hipStream_t s) {
+    template <int COLS>
+    static void colstep_c(const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
+                          bool prop, const void* tw, int jstep, hipStream_t s) {
         if (prop)
-            hipLaunchKernelGGL((k_colstep<real, N, true>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
+            hipLaunchKernelGGL((k_colstep<real, N, true, COLS>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
                                static_cast<const C*>(tw), jstep);
         else
-            hipLaunchKernelGGL((k_colstep<real, N, false>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
+            hipLaunchKernelGGL((k_colstep<real, N, false, COLS>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
                                static_cast<const C*>(tw), jstep);
+    }
+    static void colstep(const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
+                        bool prop, int cols, const void* tw, int jstep, hipStream_t s) {
+        if constexpr (N <= kMaxColsPairN) {
+            if (cols == 2) return colstep_c<2>(one, insts, tasks, ntasks, prop, tw, jstep, s);
+        }
+        colstep_c<1>(one, insts, tasks, ntasks, prop, tw, jstep, s);
     }
     static void fwd(const KolmoLaunch& a) {
         constexpr int M = Geo<N>::M;
@@ -192,9 +277,9 @@ bool kolmo_size_ok(int N) {
 
 template <typename real>
 void dispatch_colstep(int N, const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
-                      bool prop, const void* tw, int jstep, hipStream_t s) {
+                      bool prop, int cols, const void* tw, int jstep, hipStream_t s) {
     switch (N) {
-#define X(n) case n: KK<real, n>::colstep(one, insts, tasks, ntasks, prop, tw, jstep, s); break;
+#define X(n) case n: KK<real, n>::colstep(one, insts, tasks, ntasks, prop, cols, tw, jstep, s); break;
         TSK_KOLMO_SIZES(X)
 #undef X
     }
@@ -222,7 +307,9 @@ struct KolmoOp final : Operator {
     bool prop = false;
     double cprop = 0.0;
     DevBuf tw, negU, dOdy, Z;
-    DevBuf tasks;  // (0, kx) for kx = 0..M: the single-instance launch
+    DevBuf tasks[3];   // single-instance task lists for 1 and 2 columns per wavefront
+    int ntasks[3] = {0, 0, 0};
+    int force_cols = 0;  // 0: autotuned
     Gen2D* gen = nullptr;  // general two-dimensional base flow (kolmo2d.hip), else parallel
     ~KolmoOp() override { gen2d_free(gen); }
 
@@ -252,10 +339,12 @@ struct KolmoOp final : Operator {
         }
         TSK_TRY(upload_real(tw, t));
         TSK_TRY(Z.ensure(size_t(N) * (M + 1) * 2 * rb()));
-        std::vector<ColTask> tk(M + 1);
-        for (int kx = 0; kx <= M; ++kx) tk[kx] = ColTask{0, kx};
-        TSK_TRY(tasks.ensure(tk.size() * sizeof(ColTask)));
-        TSK_HIP(hipMemcpy(tasks.ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
+        for (int c = 1; c <= max_cols(N); ++c) {
+            const std::vector<ColTask> tk = column_tasks(0, M, c);
+            TSK_TRY(tasks[c].ensure(tk.size() * sizeof(ColTask)));
+            TSK_HIP(hipMemcpy(tasks[c].ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
+            ntasks[c] = int(tk.size());
+        }
         return TSK_OK;
     }
 
@@ -284,11 +373,18 @@ struct KolmoOp final : Operator {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
         if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
-        const ColTask* tk = tasks.as<ColTask>();
-        if (prec == TSK_FP32)
-            dispatch_colstep<float>(N, inst<float>(x, 0, y, nullptr), nullptr, tk, M + 1, prop, tw.ptr, 0, stream);
-        else
-            dispatch_colstep<double>(N, inst<double>(x, 0, y, nullptr), nullptr, tk, M + 1, prop, tw.ptr, 0, stream);
+        auto launch = [&](int c) {
+            if (prec == TSK_FP32)
+                dispatch_colstep<float>(N, inst<float>(x, 0, y, nullptr), nullptr, tasks[c].as<ColTask>(), ntasks[c],
+                                        prop, c, tw.ptr, 0, stream);
+            else
+                dispatch_colstep<double>(N, inst<double>(x, 0, y, nullptr), nullptr, tasks[c].as<ColTask>(),
+                                         ntasks[c], prop, c, tw.ptr, 0, stream);
+        };
+        int cols = std::min(force_cols, max_cols(N));
+        if (cols == 0)
+            TSK_TRY(column_choice(TuneKey{N, prec == TSK_FP32, prop, size_bucket(M + 1)}, stream, launch, &cols));
+        launch(cols);
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
@@ -391,6 +487,27 @@ tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V
     return TSK_OK;
 }
 
+tsk_status kolmo_set_tuning(Operator* op, int cols) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (cols < 0 || cols > 2) return fail(TSK_EINVAL, "columns per wavefront must be 0 (autotune), 1 or 2");
+    k->force_cols = cols;
+    return TSK_OK;
+}
+
+tsk_status kolmo_get_tuning(const Operator* op, int* cols) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    int c = std::min(k->force_cols, max_cols(k->N));
+    if (c == 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey{k->N, k->prec == TSK_FP32, k->prop, size_bucket(k->M + 1)});
+        c = it == g_tune.end() ? 0 : it->second;
+    }
+    *cols = c;
+    return TSK_OK;
+}
+
 bool kolmo_parallel(const Operator* op) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);
     return k && !k->gen;
@@ -413,8 +530,11 @@ struct KolmoBatch {
         int N;
         bool prop;
         const void* tw;
-        DevBuf tasks;
-        int ntasks;
+        DevBuf tasks[3];  // task lists for 1 and 2 columns per wavefront
+        int ntasks[3] = {0, 0, 0};
+        int cols = 1;     // chosen variant
+        int force = 0;
+        int columns = 0;  // kx columns of all instances
         double work;
     };
     std::vector<std::unique_ptr<Group>> groups;
@@ -464,11 +584,11 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
             g->N = ko[i]->N;
             g->prop = ko[i]->prop;
             g->tw = ko[i]->tw.ptr;
-            g->ntasks = 0;
+            g->force = ko[i]->force_cols;
         }
-        g->ntasks += ko[i]->M + 1;
+        g->columns += ko[i]->M + 1;
     }
-    for (auto& g : b->groups) g->work = double(g->ntasks) * g->N * std::log2(double(g->N));
+    for (auto& g : b->groups) g->work = double(g->columns) * g->N * std::log2(double(g->N));
     std::sort(b->groups.begin(), b->groups.end(),
               [](const std::unique_ptr<KolmoBatch::Group>& x, const std::unique_ptr<KolmoBatch::Group>& y) {
                   return x->work > y->work;
@@ -482,13 +602,34 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
         b->done.push_back(ev);
     }
     if (b->groups.size() > 1) TSK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    const hipStream_t s = ops[0]->stream;
     for (auto& g : b->groups) {
-        std::vector<ColTask> tk;
-        for (int i = 0; i < count; ++i)
-            if (ko[i]->N == g->N && ko[i]->prop == g->prop)
-                for (int kx = 0; kx <= ko[i]->M; ++kx) tk.push_back(ColTask{i, kx});
-        TSK_TRY(g->tasks.ensure(tk.size() * sizeof(ColTask)));
-        TSK_HIP(hipMemcpy(g->tasks.ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
+        for (int c = 1; c <= max_cols(g->N); ++c) {
+            std::vector<ColTask> tk;
+            for (int i = 0; i < count; ++i)
+                if (ko[i]->N == g->N && ko[i]->prop == g->prop) {
+                    const std::vector<ColTask> ti = column_tasks(i, ko[i]->M, c);
+                    tk.insert(tk.end(), ti.begin(), ti.end());
+                }
+            TSK_TRY(g->tasks[c].ensure(tk.size() * sizeof(ColTask)));
+            TSK_HIP(hipMemcpy(g->tasks[c].ptr, tk.data(), tk.size() * sizeof(ColTask), hipMemcpyHostToDevice));
+            g->ntasks[c] = int(tk.size());
+        }
+        // the variant: forced by the first operator of the group, else timed on the
+        // step-0 inputs (the outputs are overwritten by the first real matvec)
+        KolmoBatch::Group* gp = g.get();
+        KolmoBatch* bp = b.get();
+        auto launch = [&](int c) {
+            if (bp->fp32)
+                dispatch_colstep<float>(gp->N, ColInst<float>{}, bp->insts.as<ColInst<float>>(),
+                                        gp->tasks[c].as<ColTask>(), gp->ntasks[c], gp->prop, c, gp->tw, 0, s);
+            else
+                dispatch_colstep<double>(gp->N, ColInst<double>{}, bp->insts.as<ColInst<double>>(),
+                                         gp->tasks[c].as<ColTask>(), gp->ntasks[c], gp->prop, c, gp->tw, 0, s);
+        };
+        g->cols = std::min(g->force, max_cols(g->N));
+        if (g->cols == 0)
+            TSK_TRY(column_choice(TuneKey{g->N, b->fp32, g->prop, size_bucket(g->columns)}, s, launch, &g->cols));
     }
     out->reset(b.release());
     return TSK_OK;
@@ -501,12 +642,13 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
         auto& g = b->groups[q];
         hipStream_t st = q == 0 ? s : b->aux[q - 1];
         if (q > 0) TSK_HIP(hipStreamWaitEvent(st, b->fork, 0));
+        const int c = g->cols;
         if (b->fp32)
-            dispatch_colstep<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->tasks.as<ColTask>(),
-                                    g->ntasks, g->prop, g->tw, j, st);
+            dispatch_colstep<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->tasks[c].as<ColTask>(),
+                                    g->ntasks[c], g->prop, c, g->tw, j, st);
         else
             dispatch_colstep<double>(g->N, ColInst<double>{}, b->insts.as<ColInst<double>>(),
-                                     g->tasks.as<ColTask>(), g->ntasks, g->prop, g->tw, j, st);
+                                     g->tasks[c].as<ColTask>(), g->ntasks[c], g->prop, c, g->tw, j, st);
         TSK_HIP(hipGetLastError());
         if (q > 0) TSK_HIP(hipEventRecord(b->done[q - 1], st));
     }

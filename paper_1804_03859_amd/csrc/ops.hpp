@@ -110,6 +110,10 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
 tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
                                   const double* Oy);
 bool is_kolmo(const Operator* op);
+// Columns per wavefront of the column stepper: 0 = autotuned, 1 or 2 forced;
+// get reports the forced or tuned value (0 = not tuned yet).
+tsk_status kolmo_set_tuning(Operator* op, int cols);
+tsk_status kolmo_get_tuning(const Operator* op, int* cols);
 // A Navier-Stokes operator whose base flow is parallel (column stepper; batchable).
 bool kolmo_parallel(const Operator* op);
 // Largest kept wavenumber M = (N-1)/3 of a Navier-Stokes operator, -1 for others.

@@ -54,6 +54,8 @@ def load():
         "tsk_set_base_kolmogorov": [vp, i32],
         "tsk_set_base_flow": [vp, P(f64), P(f64), P(f64), P(f64)],
         "tsk_state_dim": [vp, P(i64), P(i32), P(i32)],
+        "tsk_set_tuning": [vp, i32],
+        "tsk_get_tuning": [vp, P(i32)],
         "tsk_from_physical": [vp, vp, vp],
         "tsk_to_physical": [vp, vp, vp],
         "tsk_apply": [vp, vp, vp],
@@ -95,7 +97,8 @@ def load():
 def exported_symbols():
     """Names the binding expects the library to export (all of include/tsk.h)."""
     return ["tsk_create_cgle1d", "tsk_set_params_cgle", "tsk_create_kolmo2d", "tsk_set_params_kolmo",
-            "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_state_dim",
+            "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
+            "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
@@ -201,6 +204,16 @@ def set_base_flow(op, U, V, dOmega_dx, dOmega_dy):
     if any(a.size != op.N * op.N for a, _ in arrs):
         raise ValueError(f"base fields must have N*N = {op.N * op.N} samples")
     _check(load().tsk_set_base_flow(op.h, *[p for _, p in arrs]))
+
+
+def set_tuning(op, columns_per_wave):
+    _check(load().tsk_set_tuning(op.h, int(columns_per_wave)))
+
+
+def get_tuning(op):
+    c = C.c_int()
+    _check(load().tsk_get_tuning(op.h, C.byref(c)))
+    return c.value
 
 
 def _phys_spec(op):

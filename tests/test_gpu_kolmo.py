@@ -213,3 +213,32 @@ def test_fp32_precision_form_within_stated_bound(tsk, N, m):
     lam = np.sort(r["lam"].real)[::-1]
     assert np.all(np.diff(lam) < -1e-3)
     assert match_sets(r["lam"], lam_o) <= FP32_LAMBDA_BOUND
+
+
+@pytest.mark.parametrize("N,prec,base", [(128, 0, "kolmogorov"), (48, 0, "general"), (256, 1, "kolmogorov"),
+                                         (96, 1, "general")])
+def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
+    print(f"column-pair variant N={N} prec={prec} base={base}", flush=True)
+    if base == "kolmogorov":
+        op, _ = _op(tsk, N, prec=prec, T=0.05)
+    else:
+        y = 2 * np.pi * np.arange(N) / N
+        op, _ = _op(tsk, N, prec=prec, T=0.05, base="parallel", U=np.sin(y) + 0.5 * np.cos(2 * y),
+                    dO=np.sin(y) + 2.0 * np.cos(2 * y))
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, N, W.kolmo_start_physical(N, 9)), x)
+    outs = []
+    for c in (1, 2):
+        tsk.set_tuning(op, c)
+        assert tsk.get_tuning(op) == c
+        y_ = op.new_state()
+        tsk.apply(op, x, y_)
+        outs.append(y_)
+    assert torch.equal(outs[0], outs[1])
+    tsk.set_tuning(op, 0)
+    y_ = op.new_state()
+    tsk.apply(op, x, y_)                      # autotuned: one of the two, same bits
+    assert torch.equal(y_, outs[0])
+    assert tsk.get_tuning(op) in (1, 2)
+    with pytest.raises(tsk.TskError):
+        tsk.set_tuning(op, 3)

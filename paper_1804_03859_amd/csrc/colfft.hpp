@@ -136,7 +136,8 @@ __device__ inline void col_fft(C (&v)[ColPlan<N>::NBL][ColPlan<N>::RE], C* a, C*
 }
 
 // ---- several independent columns per wavefront ----------------------------------
-// The same transform on COLS columns at once.  Every pass first loads the
+// The same transform on COLS columns at once, for a workgroup of one
+// wavefront (passes are separated by wave_lds_sync, not workgroup barriers).  Every pass first loads the
 // butterfly inputs of all columns, then computes, then stores, so the LDS
 // latency of one column overlaps the arithmetic of the others (a lone
 // wavefront per SIMD has no other way to hide it).  Each column has its own
@@ -180,7 +181,7 @@ __device__ inline bool col_mid_passes_m(C* const* a, C* const* b, const C* tw, i
     } else {
         constexpr int R = col_mid_radix(N, PL::MID, P);
         col_mid_pass_m<N, R, NS, SIGN, COLS>(a, b, tw, lane);
-        __syncthreads();
+        wave_lds_sync();
         return !col_mid_passes_m<N, P + 1, NS * R, SIGN, COLS>(b, a, tw, lane);
     }
 }
@@ -204,7 +205,7 @@ __device__ inline void col_fft_m(C (&v)[COLS][ColPlan<N>::NBL][ColPlan<N>::RE], 
             }
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     const bool in_a = col_mid_passes_m<N, 0, RE, SIGN, COLS>(a, b, tw, lane);
 #pragma unroll
     for (int q = 0; q < PL::NBL; ++q) {

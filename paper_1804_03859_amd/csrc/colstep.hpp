@@ -85,6 +85,7 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     constexpr int LP = padded_len<N>();
     __shared__ C sA[COLS * NI][LP], sB[COLS * NI][LP], sT[N];
     for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
+    static_assert(kWave == 64, "one wavefront per workgroup");
     C* Ai[COLS * NI];
     C* Bi[COLS * NI];
     C* Af[COLS];

@@ -80,6 +80,16 @@ __host__ __device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t i) {
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return z ^ (z >> 31);
 }
+// ---- LDS ordering inside one wavefront ------------------------------------------
+// The LDS instructions of one wavefront execute in issue order, so lanes of a
+// workgroup that is a single wavefront exchange data through LDS without a
+// hardware barrier.  A wavefront-scope fence keeps the compiler from moving LDS
+// accesses across the exchange point and needs no wait for outstanding stores.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 // ---- wavefront reductions (device) -------------------------------------------
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -12,8 +12,10 @@
 // complex; its conjugate pairs come out to rounding.
 //
 // Wavefront design.  The whole solve runs in one 64-lane wavefront, so every
-// wait is just the LDS latency of one wave.  T (p x p complex128, row-major)
-// sits in LDS.  The deflation test of all subdiagonal entries is one ballot.
+// wait is just the LDS latency of one wave; inside the QR iteration, where the
+// lanes exchange data only through LDS, the steps are ordered by
+// wavefront-scope fences (wave_lds_sync) rather than workgroup barriers.
+// T (p x p complex128, row-major) sits in LDS.  The deflation test of all subdiagonal entries is one ballot.
 // Every lane evaluates the shift and the rotation of the current bulge position
 // itself from broadcast LDS reads.  The similarity G T G^H of one rotation
 // touches two rows and two columns whose only overlap is a 2x2 block, so the
@@ -244,9 +246,9 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
         }
         unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
         int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
-        __syncthreads();
+        wave_lds_sync();
         if (l > 0 && lane == 0) T[l * p + (l - 1)] = cmk<double2>(0.0, 0.0);
-        __syncthreads();
+        wave_lds_sync();
         if (l == ihi) {
             --ihi;
             its = 0;
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
                 T[ia] = cadd(cscale(u, c), cmul(s1, v));
                 T[ib] = csub(cscale(v, c), cmul(s2, u));
             }
-            __syncthreads();
+            wave_lds_sync();
         }
         if constexpr (FULLZ) {
             // Z <- Z G^H for the sweep's rotations, one row of Z per lane
@@ -491,7 +493,7 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
         T[i * p + c] = cs * u + sn * v;
         T[(i + 1) * p + c] = -sn * u + cs * v;
     }
-    __syncthreads();
+    wave_lds_sync();
     for (int r = lane; r <= rto; r += kHT) {
         const double u = T[r * p + i], v = T[r * p + i + 1];
         T[r * p + i] = cs * u + sn * v;
@@ -502,7 +504,7 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
         zl[i] = cs * u + sn * v;
         zl[i + 1] = -sn * u + cs * v;
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 // One bulge step: the similarity T <- P T P with the NB-element reflector P at
@@ -610,7 +612,7 @@ __device__ inline void bulge_step(double* Tr, double* zl, int p, int l, int ihi,
             }
         }
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restrict__ Dv, int p, int k, double tol,
@@ -678,9 +680,9 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restric
         }
         const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
         const int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
-        __syncthreads();
+        wave_lds_sync();
         if (l > 0 && lane == 0) Tr[l * p + (l - 1)] = 0.0;
-        __syncthreads();
+        wave_lds_sync();
         if (l == ihi) {  // 1x1 block converged
             --ihi;
             its = 0;
@@ -702,12 +704,12 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restric
                     rot_similarity(Tr, zl, p, i, cs, sn, i, i + 1, lane);
                 }
                 if (lane == 0) Tr[(i + 1) * p + i] = 0.0;
-                __syncthreads();
+                wave_lds_sync();
             } else if (lane == 0) {
                 blk[i] = 1;
                 blk[i + 1] = 2;
             }
-            __syncthreads();
+            wave_lds_sync();
             ihi -= 2;
             its = 0;
             continue;

@@ -137,8 +137,9 @@ __device__ inline void col_fft(C (&v)[ColPlan<N>::NBL][ColPlan<N>::RE], C* a, C*
 
 // ---- several independent columns per wavefront ----------------------------------
 // The same transform on COLS columns at once, for a workgroup of one
-// wavefront (passes are separated by wave_lds_sync, not workgroup barriers).  Every pass first loads the
-// butterfly inputs of all columns, then computes, then stores, so the LDS
+// wavefront (passes are separated by wave_lds_sync, not workgroup barriers).
+// Every pass first loads the butterfly inputs of all columns, then computes,
+// then stores, so the LDS
 // latency of one column overlaps the arithmetic of the others (a lone
 // wavefront per SIMD has no other way to hide it).  Each column has its own
 // pair of LDS buffers; twiddles are shared.
@@ -227,6 +228,132 @@ __device__ inline void col_fft_m(C (&v)[COLS][ColPlan<N>::NBL][ColPlan<N>::RE], 
             for (int c = 0; c < COLS; ++c) {
 #pragma unroll
                 for (int r = 1; r < RE; ++r) v[c][q][r] = cmul(v[c][q][r], w[r]);
+                dft<RE, SIGN>(v[c][q]);
+            }
+        }
+    }
+}
+
+// ---- twiddles held in registers ------------------------------------------------
+// A lane's butterflies, and with them its twiddle factors, are the same in
+// every transform of a plan, so a stepper that runs thousands of transforms
+// loads them once (ColTw) instead of reading them from LDS in every pass.
+template <int N, int P, int NS, typename C, bool END = (P >= ColPlan<N>::NMID)> struct ColTwMid;
+template <int N, int P, int NS, typename C> struct ColTwMid<N, P, NS, C, true> {
+    __device__ void load(const C*, int) {}
+};
+template <int N, int P, int NS, typename C> struct ColTwMid<N, P, NS, C, false> {
+    static constexpr int R = col_mid_radix(N, ColPlan<N>::MID, P);
+    static constexpr int NB = N / R, TS = N / (NS * R), NBL = (NB + kWave - 1) / kWave;
+    C w[NBL][R];
+    ColTwMid<N, P + 1, NS * R, C> next;
+    __device__ void load(const C* tw, int lane) {
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) {
+            const int j = lane + b * kWave;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[b][r] = (j < NB && r > 0) ? tw[k * r * TS] : cmk<C>(0, 0);
+        }
+        next.load(tw, lane);
+    }
+};
+template <int N, typename C> struct ColTw {
+    using PL = ColPlan<N>;
+    ColTwMid<N, 0, PL::RE, C> mid;
+    C last[PL::NBL][PL::RE];
+    __device__ void load(const C* tw, int lane) {
+        mid.load(tw, lane);
+#pragma unroll
+        for (int q = 0; q < PL::NBL; ++q) {
+            const int j = lane + q * kWave;
+#pragma unroll
+            for (int r = 0; r < PL::RE; ++r) last[q][r] = (j < PL::NB && r > 0) ? tw[j * r] : cmk<C>(0, 0);
+        }
+    }
+};
+
+template <int SIGN, typename C> __device__ inline C tw_sign(C w) {
+    if constexpr (SIGN > 0) w.y = -w.y;
+    return w;
+}
+
+template <int N, int R, int NS, int SIGN, int COLS, typename C, typename TW>
+__device__ inline void col_mid_pass_mr(C* const* in, C* const* out, const TW& t, int lane) {
+    constexpr int NB = N / R;
+    constexpr int NBL = (NB + kWave - 1) / kWave;
+#pragma unroll
+    for (int b = 0; b < NBL; ++b) {
+        const int j = lane + b * kWave;
+        if (j < NB) {
+            const int k = j % NS;
+            C v[COLS][R];
+#pragma unroll
+            for (int c = 0; c < COLS; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[c][r] = in[c][pad8(j + r * NB)];
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], tw_sign<SIGN>(t.w[b][r]));
+                dft<R, SIGN>(v[c]);
+            }
+            const int o = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int c = 0; c < COLS; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) out[c][pad8(o + r * NS)] = v[c][r];
+        }
+    }
+}
+
+template <int N, int P, int NS, int SIGN, int COLS, typename C, typename TW>
+__device__ inline bool col_mid_passes_mr(C* const* a, C* const* b, const TW& t, int lane) {
+    using PL = ColPlan<N>;
+    if constexpr (P >= PL::NMID) {
+        return true;  // result in a
+    } else {
+        constexpr int R = col_mid_radix(N, PL::MID, P);
+        col_mid_pass_mr<N, R, NS, SIGN, COLS>(a, b, t, lane);
+        wave_lds_sync();
+        return !col_mid_passes_mr<N, P + 1, NS * R, SIGN, COLS>(b, a, t.next, lane);
+    }
+}
+
+// col_fft_m with the twiddles of ColTw (registers).
+template <int N, int SIGN, int COLS, typename C>
+__device__ inline void col_fft_mr(C (&v)[COLS][ColPlan<N>::NBL][ColPlan<N>::RE], C* const* a, C* const* b,
+                                  const ColTw<N, C>& t, int lane) {
+    using PL = ColPlan<N>;
+    constexpr int RE = PL::RE, NB = PL::NB;
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                dft<RE, SIGN>(v[c][q]);
+#pragma unroll
+                for (int r = 0; r < RE; ++r) a[c][pad8(j * RE + r)] = v[c][q][r];
+            }
+        }
+    }
+    wave_lds_sync();
+    const bool in_a = col_mid_passes_mr<N, 0, RE, SIGN, COLS>(a, b, t.mid, lane);
+#pragma unroll
+    for (int q = 0; q < PL::NBL; ++q) {
+        const int j = lane + q * kWave;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const C* src = in_a ? a[c] : b[c];
+#pragma unroll
+                for (int r = 0; r < RE; ++r) v[c][q][r] = src[pad8(j + r * NB)];
+            }
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+                for (int r = 1; r < RE; ++r) v[c][q][r] = cmul(v[c][q][r], tw_sign<SIGN>(t.last[q][r]));
                 dft<RE, SIGN>(v[c][q]);
             }
         }

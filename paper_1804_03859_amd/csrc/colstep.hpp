@@ -134,6 +134,10 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
 
     const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
     const real invN = real(1.0 / N);
+    // twiddles in registers where the register budget allows (N <= 256)
+    constexpr bool kTwReg = N <= 256;
+    ColTw<N, C> twr;
+    if constexpr (kTwReg) twr.load(sT, lane);
 
     for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
@@ -150,7 +154,10 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
                     v[c][0][r] = cmk<C>(-g1[c][r] * s[c][r].y, g1[c][r] * s[c][r].x);  // i kx (...) s
                     if constexpr (!PROP) v[COLS + c][0][r] = cmk<C>(-g2[c][r] * s[c][r].y, g2[c][r] * s[c][r].x);
                 }
-            col_fft_m<N, +1, COLS * NI>(v, Ai, Bi, sT, lane);
+            if constexpr (kTwReg)
+                col_fft_mr<N, +1, COLS * NI>(v, Ai, Bi, twr, lane);
+            else
+                col_fft_m<N, +1, COLS * NI>(v, Ai, Bi, sT, lane);
             // product with the base profiles at y = pos
             C pr[COLS][1][RE];
 #pragma unroll
@@ -164,7 +171,10 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
                     }
                     pr[c][0][r] = p;
                 }
-            col_fft_m<N, -1, COLS>(pr, Af, Bf, sT, lane);
+            if constexpr (kTwReg)
+                col_fft_mr<N, -1, COLS>(pr, Af, Bf, twr, lane);
+            else
+                col_fft_m<N, -1, COLS>(pr, Af, Bf, sT, lane);
             // Lawson RK4 bookkeeping on the kept modes (registers only); the stage
             // switch is outside the column/slot loops so it stays a uniform branch
             C nh[COLS][RE];

@@ -144,28 +144,39 @@ __global__ __launch_bounds__(kBT) void k_update(const KryDesc* __restrict__ Dv, 
     }
 }
 
-__global__ void k_reduce(const KryDesc* __restrict__ Dv, int p, int col, int first, int slot) {
+// One workgroup per instance; wavefront w reduces coefficients i = w, w + 4, ...
+// (lanes over blocks in a fixed order, then a shuffle tree).
+__global__ __launch_bounds__(kBT) void k_reduce(const KryDesc* __restrict__ Dv, int p, int col, int first,
+                                                int slot) {
     const KryDesc& d = Dv[blockIdx.x];
     if (!d.active) return;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     double2* Hcol = col >= 0 ? d.H + size_t(d.ldh) * col : nullptr;
-    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    for (int i = wave; i < p; i += kBT / kWave) {
         double2 s = cmk<double2>(0.0, 0.0);
-        for (int b = 0; b < d.nblk; ++b) s = cadd(s, d.partial[size_t(b) * p + i]);
-        d.h[i] = s;
-        if (Hcol) Hcol[i] = first ? s : cadd(Hcol[i], s);
+        for (int b = lane; b < d.nblk; b += kWave) s = cadd(s, d.partial[size_t(b) * p + i]);
+        s = wave_sum(s);
+        if (lane == 0) {
+            d.h[i] = s;
+            if (Hcol) Hcol[i] = first ? s : cadd(Hcol[i], s);
+        }
     }
-    if (slot >= 0 && threadIdx.x == 0) {
+    if (slot >= 0 && wave == 0) {
         double s = 0.0;
-        for (int b = 0; b < d.nblk; ++b) s += d.pnrm[b];
-        d.scal[slot] = s;
+        for (int b = lane; b < d.nblk; b += kWave) s += d.pnrm[b];
+        s = wave_sum(s);
+        if (lane == 0) d.scal[slot] = s;
     }
 }
 
 __global__ void k_finalize(const KryDesc* __restrict__ Dv, int j) {
     const KryDesc& d = Dv[blockIdx.x];
-    if (!d.active || threadIdx.x != 0) return;
+    if (!d.active) return;
+    const int lane = threadIdx.x;  // one wavefront
     double s = 0.0;
-    for (int b = 0; b < d.nblk; ++b) s += d.pnrm[b];
+    for (int b = lane; b < d.nblk; b += kWave) s += d.pnrm[b];
+    s = wave_sum(s);
+    if (lane != 0) return;
     const double beta = sqrt(s);
     const double win = sqrt(d.scal[1]);
     d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
@@ -257,7 +268,7 @@ void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, 
 }
 
 void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(128), 0, s, D, p, col, first, slot);
+    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(kBT), 0, s, D, p, col, first, slot);
 }
 
 template <typename TS>

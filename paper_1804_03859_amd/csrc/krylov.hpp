@@ -10,12 +10,14 @@
 // (complex128 for complex states) whatever the storage type of V.
 //
 // Work split: blockIdx.y selects the instance (its descriptor holds every
-// pointer); blocks of kBT = 256 threads own contiguous chunks of kChunk = 1024
-// elements.  A dot pass stages the chunk of w in LDS, then each of the four
+// pointer); blocks of kBT = 256 threads own contiguous chunks of kChunk = 256
+// elements (small chunks keep enough workgroups busy at the 10^4-element
+// states of the 128^2 grids).  A dot pass stages the chunk of w in LDS, then each of the four
 // wavefronts takes every fourth basis vector, reads its chunk coalesced and
 // reduces the 64 lane sums with cross-lane shuffles.  Per-block partial sums are
-// reduced in a fixed order by one block per instance, so results are bitwise
-// reproducible run to run and independent of the batch composition.
+// reduced in a fixed order (lanes over blocks, then a shuffle tree) by one
+// workgroup per instance, so results are bitwise reproducible run to run and
+// independent of the batch composition.
 #pragma once
 
 #include "common.hpp"
@@ -23,7 +25,7 @@
 namespace tsk {
 
 constexpr int kBT = 256;
-constexpr int kChunk = 1024;
+constexpr int kChunk = 256;
 constexpr int kEPT = kChunk / kBT;
 
 inline int cgs_blocks(int64_t n) { return int((n + kChunk - 1) / kChunk); }

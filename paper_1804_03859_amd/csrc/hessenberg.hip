@@ -409,7 +409,18 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ D
 // quasi-triangular T (one lane per eigenvalue, complex arithmetic for pairs).
 
 // Householder vector for (x, y, z): v = (1, v1, v2), tau, with
-// (I - tau v v^T) (x, y, z)^T = (alpha, 0, 0)^T.  tau = 0 when y = z = 0.
+// (I - tau v v^T) (x, y, z)^T = (alpha, 0, 0)^T.  tau = 0 when y = z = 0.  With
+// rho = ||(x, y, z)||, alpha = -sign(x) rho, u0 = x - alpha: v = (y, z)/u0 and
+// tau = |u0| / rho, so one reciprocal square root and one reciprocal suffice
+// (hardware estimates refined by Newton steps; a plain path outside the range
+// where the squares are safe).
+__device__ inline double rcp_full(double v) {
+    double y = __builtin_amdgcn_rcp(v);
+    y = fma(y, fma(-v, y, 1.0), y);
+    y = fma(y, fma(-v, y, 1.0), y);
+    return y;
+}
+
 __device__ inline void house3(double x, double y, double z, double& v1, double& v2, double& tau, double& alpha) {
     const double sig = y * y + z * z;
     if (sig == 0.0) {
@@ -417,12 +428,30 @@ __device__ inline void house3(double x, double y, double z, double& v1, double& 
         alpha = x;
         return;
     }
-    const double nrm = sqrt(x * x + sig);
-    alpha = x >= 0.0 ? -nrm : nrm;
-    const double u0 = x - alpha;  // no cancellation: x and -alpha share a sign
+    const double s2 = x * x + sig;
+    if (s2 > 1e-280 && s2 < 1e280) {
+        const double r = rsqrt_full(s2);  // 1 / rho
+        const double rho = s2 * r;
+        alpha = x >= 0.0 ? -rho : rho;
+        const double u0 = x - alpha;  // no cancellation: x and -alpha share a sign
+        const double iu = rcp_full(u0);
+        v1 = y * iu;
+        v2 = z * iu;
+        tau = fabs(u0) * r;
+        return;
+    }
+    const double rho = sqrt(s2);
+    alpha = x >= 0.0 ? -rho : rho;
+    const double u0 = x - alpha;
     v1 = y / u0;
     v2 = z / u0;
     tau = (alpha - x) / alpha;
+}
+
+__device__ inline double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
 }
 
 // Eigenvector z (complex, z[j] = 0 beyond the eigenvalue's block) of the quasi
@@ -512,11 +541,15 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
 // lanes 0..NB*NB-1, the rows kk.. at columns kk+NB..p-1 and the columns kk.. at
 // rows 0..kk-1 and kk+NB (when inside the window) by the lanes in turn, all from
 // pre-update values in one phase.
+// Returns true with the next bulge (x, y, z) = new (T[kk+1][kk], T[kk+2][kk],
+// T[kk+3][kk]) taken from the lanes that computed them; false when no
+// reflection was needed (the caller then reads T).
 template <int NB>
-__device__ inline void bulge_step(double* Tr, double* zl, int p, int l, int ihi, int kk, double x, double y,
-                                  double z, int lane) {
+__device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi, int kk, double x, double y,
+                                  double z, int lane, double& nx, double& ny, double& nz) {
     double v1, v2, tau, alpha;
     house3(x, y, NB == 3 ? z : 0.0, v1, v2, tau, alpha);
+    bool fwd = false;
     if (tau != 0.0) {
         const double v[3] = {1.0, v1, NB == 3 ? v2 : 0.0};
         const int rto = (kk + 3 <= ihi ? kk + 3 : ihi);  // right factor: rows 0..rto
@@ -611,8 +644,22 @@ __device__ inline void bulge_step(double* Tr, double* zl, int p, int l, int ihi,
                 for (int a = 1; a < NB; ++a) Tr[(kk + a) * p + kk - 1] = 0.0;
             }
         }
+        if constexpr (NB == 3) {
+            // block entries (1, 0) and (2, 0) sit in lanes 3 and 6; row kk+3 of
+            // column kk is col-only item ncr + kk
+            nx = readlane_d(bval, 3);
+            ny = readlane_d(bval, 6);
+            nz = 0.0;
+            if (kk + 3 <= ihi) {
+                const int t = ncr + kk;
+                const double zq = (t / kHT == 0) ? nv[0][0] : nv[1][0];
+                nz = readlane_d(zq, t % kHT);
+            }
+            fwd = true;
+        }
     }
     wave_lds_sync();
+    return fwd;
 }
 
 __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restrict__ Dv, int p, int k, double tol,
@@ -744,12 +791,21 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restric
         }
         // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
         for (int kk = l; kk <= ihi - 2; ++kk) {
-            bulge_step<3>(Tr, zl, p, l, ihi, kk, x, y, z, lane);
-            x = Tr[(kk + 1) * p + kk];
-            y = Tr[(kk + 2) * p + kk];
-            z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
+            double nx, ny, nz;
+            if (bulge_step<3>(Tr, zl, p, l, ihi, kk, x, y, z, lane, nx, ny, nz)) {
+                x = nx;
+                y = ny;
+                z = nz;
+            } else {
+                x = Tr[(kk + 1) * p + kk];
+                y = Tr[(kk + 2) * p + kk];
+                z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
+            }
         }
-        bulge_step<2>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane);
+        {
+            double nx, ny, nz;
+            bulge_step<2>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane, nx, ny, nz);
+        }
     }
 
     // ---- Ritz values, eigenvectors of T, residuals ---------------------------------------------

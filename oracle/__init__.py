@@ -20,6 +20,9 @@ arXiv:1804.03859, that it follows):
                      classical Gram-Schmidt applied twice, Ritz pairs, the Ritz
                      residual estimate (Sec. 3.2.2, eq. "Krylov convergence"),
                      wanted set and stop rule, lambda = log(mu)/T (Sec. 3.2).
+* ``krylov_schur`` -- Krylov-Schur restart (Sec. 3.2.2, after Stewart 2001):
+                     ordered real Schur form of the Krylov matrix, truncation to
+                     the wanted part, re-expansion by Arnoldi steps.
 * ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
                      definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
 * ``mlp``         -- start-vector network (not in the paper): FP64 forward,

@@ -180,6 +180,62 @@ tsk_status tsk_batch_arnoldi(const tsk_op* ops, int count, int m, int k, double 
                              double* lambda_ri, double* resid, void* const* ritz_devs,
                              tsk_arnoldi_info* infos);
 
+/* Krylov-Schur run statistics. */
+typedef struct {
+    int n_matvec;            /* matvecs: m, plus m - p per contraction (Table 1 counts this way) */
+    int n_restarts;          /* contractions performed                                          */
+    int n_ritz;              /* Ritz pairs written (k, fewer only at an early breakdown)         */
+    int n_converged;         /* of those, residual <= tol                                        */
+    int status;              /* same value as returned                                           */
+    int kept_last;           /* order p kept by the last contraction (0: none)                  */
+    double beta;             /* residual norm of the final factorisation                          */
+    double ms_total;         /* wall time of the call, host clock                                 */
+    double ms_apply;         /* device time of the matvecs, HIP events on the op's stream         */
+} tsk_ks_info;
+
+/* Krylov-Schur method (Sec. 3.2.2, after Stewart 2001) for real operators.
+ * Expand an Arnoldi factorisation (classical Gram-Schmidt twice) to order m;
+ * test the k wanted Ritz pairs with the wanted set, residual and tolerance of
+ * tsk_arnoldi, at order m only (steps 2 and 6 of the method); while the test
+ * fails, order the real Schur form of H_m so that the kept Ritz values lead,
+ * truncate to their order p and expand again from v_{p+1} = v_{m+1}.  The
+ * truncated Krylov-Schur decomposition is brought back to an equivalent
+ * Arnoldi factorisation (same Ritz pairs) before the expansion continues.
+ *   m:            Krylov dimension, k + 2 <= m <= 96, m <= state length.
+ *   k, tol:       as tsk_arnoldi.
+ *   delta:        a contraction keeps the Ritz values with |mu| >= 1 - delta
+ *                 (the paper uses 0.05 to 0.1) ...
+ *   p_max:        ... but at least k and at most p_max of them, the leading
+ *                 ones by |mu| (k <= p_max <= m - 2; 0 selects max(k, m / 2));
+ *                 a complex pair is kept whole, so p may be p_max + 1.
+ *   max_restarts: contractions allowed before returning TSK_NOT_CONVERGED.
+ *   v0_dev, seed, mu_ri, lambda_ri, resid, ritz_dev, as tsk_arnoldi.
+ * Returns TSK_OK, TSK_NOT_CONVERGED or TSK_BREAKDOWN with outputs written, or a
+ * negative status with nothing written (TSK_EINVAL also for complex operators,
+ * TSK_EEIG if the QR iteration or the reordering failed). */
+tsk_status tsk_krylov_schur(tsk_op op, int m, int k, double tol, double delta, int p_max, int max_restarts,
+                            const void* v0_dev, uint64_t seed, double* mu_ri, double* lambda_ri, double* resid,
+                            void* ritz_dev, tsk_ks_info* info);
+
+/* The contraction on its own (the device kernel tsk_krylov_schur runs at
+ * order m).  Input: H_dev, m x m real upper Hessenberg (FP64, column-major,
+ * leading dimension ldh >= m; only the Hessenberg part is read), and beta, the
+ * residual norm of its Arnoldi factorisation.  Kept set from k, delta and p_max
+ * as tsk_krylov_schur (k + 2 <= m <= 96).  Outputs (device):
+ *   mu_dev:   m complex128, the Ritz values of H (real Schur order);
+ *   res_dev:  m doubles, their residuals beta |e_m^T y|, unit y;
+ *   Hnew_dev: (m+1) x m FP64, column-major, leading dimension m+1: the new
+ *             Hessenberg H_p in rows 0..p-1 of columns 0..p-1, beta' >= 0 at
+ *             (p, p-1), zero elsewhere;
+ *   W_dev:    room for m x m FP64; its first p columns (leading dimension m)
+ *             receive the orthonormal W with V_p = V_m W.
+ * Host outputs: *kept = p, *beta_new = beta'.  Synchronous on hip_stream.
+ * TSK_EEIG if the QR iteration or the reordering failed, TSK_ENONFINITE if H
+ * or beta is not finite. */
+tsk_status tsk_ks_contract(const double* H_dev, int ldh, int m, double beta, int k, double delta, int p_max,
+                           void* mu_dev, double* res_dev, double* Hnew_dev, double* W_dev, int* kept,
+                           double* beta_new, void* hip_stream);
+
 /* Last Arnoldi run, for inspection: H ((m+1) x m complex128, column-major,
  * leading dimension m+1, zero beyond the steps taken) copied to host, and the
  * basis pointer (device, (steps+1) vectors of the state type, vector-major,

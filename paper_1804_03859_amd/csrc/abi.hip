@@ -206,6 +206,32 @@ tsk_status tsk_batch_arnoldi(const tsk_op* ops, int count, int m, int k, double 
     })
 }
 
+tsk_status tsk_krylov_schur(tsk_op op, int m, int k, double tol, double delta, int p_max, int max_restarts,
+                            const void* v0_dev, uint64_t seed, double* mu_ri, double* lambda_ri, double* resid,
+                            void* ritz_dev, tsk_ks_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return krylov_schur(op->op.get(), m, k, tol, delta, p_max, max_restarts, v0_dev, seed, mu_ri, lambda_ri,
+                            resid, ritz_dev, info);
+    })
+}
+
+tsk_status tsk_ks_contract(const double* H_dev, int ldh, int m, double beta, int k, double delta, int p_max,
+                           void* mu_dev, double* res_dev, double* Hnew_dev, double* W_dev, int* kept,
+                           double* beta_new, void* hip_stream) {
+    TSK_GUARD({
+        if (!H_dev || !mu_dev || !res_dev || !Hnew_dev || !W_dev || !kept || !beta_new)
+            return fail(TSK_EINVAL, "null buffer");
+        if (k < 1 || m < k + 2 || m > kMaxKrylov || ldh < m)
+            return fail(TSK_EINVAL, "need 1 <= k, k + 2 <= m <= 96 and ldh >= m");
+        if (p_max == 0) p_max = std::max(k, m / 2);
+        if (p_max < k || p_max > m - 2) return fail(TSK_EINVAL, "need k <= p_max <= m - 2");
+        if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(TSK_EINVAL, "delta must be finite and >= 0");
+        return ks_contract_standalone(H_dev, ldh, m, beta, k, delta, p_max, mu_dev, res_dev, Hnew_dev, W_dev, kept,
+                                      beta_new, static_cast<hipStream_t>(hip_stream));
+    })
+}
+
 tsk_status tsk_last_hessenberg(tsk_op op, double* H_host, int* m_out, int* steps_out) {
     TSK_GUARD({
         TSK_NEED(op);
@@ -226,7 +252,7 @@ tsk_status tsk_last_basis(tsk_op op, const void** V_dev, int64_t* ld) {
         TSK_NEED(op);
         ArnoldiWork& W = op->op->aw;
         if (!W.V.ptr || W.m == 0) return fail(TSK_ESTATE, "no Arnoldi run on this operator");
-        if (V_dev) *V_dev = W.V.ptr;
+        if (V_dev) *V_dev = W.Vcur ? W.Vcur : W.V.ptr;
         if (ld) *ld = W.ldv;
         return TSK_OK;
     })

@@ -6,7 +6,7 @@
 // integration of the linearized equations (Sec. 3, time-stepper approach).
 // After each matvec: CGS2 projection and normalisation (krylov.hip), then the
 // device Hessenberg QR and wanted-set test (hessenberg.hip), one wavefront per
-// instance.  The only device-to-host traffic per step is one 48-byte
+// instance.  The only device-to-host traffic per step is one 56-byte
 // RitzResult per instance, telling the host which instances stop.  Ritz values
 // are mapped to lambda = log(mu)/T on the device (principal branch, valid when
 // |Im lambda| T < pi/2, the four-samples-per-period rule of Sec. 3.2.1).
@@ -74,78 +74,100 @@ struct Outcome {
     std::string err;
 };
 
+// Workspace of one instance (NS copies of the eigensolver outputs) and its
+// descriptor; ritz: optional Ritz-vector output.
 template <typename TS>
-tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
-                     const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                     tsk_arnoldi_info* infos) {
+tsk_status make_desc(Operator* op, int m, int k, int NS, void* ritz, KryDesc& d) {
     using A = typename WorkType<TS>::A;
-    auto t0 = std::chrono::steady_clock::now();
-    Operator* lead = ops[0];
-    const hipStream_t s = lead->stream;
-    ArnoldiWork& L = lead->aw;
-    const double dup_rel = lead->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
-    const double res_floor = lead->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
-    constexpr int NS = ArnoldiWork::kSlots;
-    constexpr bool kRealH = !std::is_same<TS, double2>::value;  // real operators: real Hessenberg QR
+    ArnoldiWork& W = op->aw;
+    const int64_t n = op->n;
+    const int64_t ldv = (n + 63) / 64 * 64;
+    const int nblk = cgs_blocks(n);
+    TSK_TRY(W.V.ensure(size_t(m + 1) * ldv * sizeof(TS)));
+    TSK_TRY(W.H.ensure(size_t(m + 1) * m * sizeof(double2)));
+    TSK_TRY(W.w.ensure(size_t(n) * sizeof(TS)));
+    TSK_TRY(W.w64.ensure(size_t(n) * sizeof(A)));
+    TSK_TRY(W.partial.ensure(size_t(nblk) * (m + 1) * sizeof(double2)));
+    TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
+    TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
+    TSK_TRY(W.scal.ensure(64 * sizeof(double)));
+    TSK_TRY(W.eigS.ensure(size_t(NS) * m * m * sizeof(double2)));
+    TSK_TRY(W.eigY.ensure(size_t(m) * (k > 0 ? k : 1) * sizeof(double2)));
+    TSK_TRY(W.eigMu.ensure(size_t(NS) * m * sizeof(double2)));
+    TSK_TRY(W.eigRes.ensure(size_t(NS) * m * sizeof(double)));
+    TSK_TRY(W.sel.ensure(size_t(NS) * m * sizeof(int)));
+    TSK_TRY(W.out.ensure(5 * size_t(k) * sizeof(double)));
+    TSK_TRY(W.rr.ensure(size_t(NS) * sizeof(RitzResult)));
+    W.m = m;
+    W.steps = 0;
+    W.ldv = ldv;
+    std::memset(&d, 0, sizeof(d));
+    d.V = W.V.ptr;
+    d.w = W.w.ptr;
+    d.w64 = W.w64.ptr;
+    d.H = W.H.as<double2>();
+    d.partial = W.partial.as<double2>();
+    d.pnrm = W.pnrm.as<double>();
+    d.h = W.h.as<double2>();
+    d.scal = W.scal.as<double>();
+    d.Z = nullptr;
+    d.S = W.eigS.as<double2>();
+    d.Y = W.eigY.as<double2>();
+    d.mu = W.eigMu.as<double2>();
+    d.res = W.eigRes.as<double>();
+    d.sel = W.sel.as<int>();
+    d.rr = W.rr.as<RitzResult>();
+    d.ritz = ritz;
+    d.out = W.out.as<double>();
+    d.ldv = ldv;
+    d.n = n;
+    d.ldh = m + 1;
+    d.nblk = nblk;
+    d.active = 1;
+    d.dup_rel = op->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
+    d.res_floor = op->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
+    d.T = op->T;
+    W.Vcur = W.V.ptr;
+    return TSK_OK;
+}
 
-    // ---- per-instance workspace and descriptors ------------------------------------
-    std::vector<KryDesc> Dh(count);
-    int64_t nmax = 0;
-    int nblk_max = 0;
+// Start vector drawn from `seed`: an iid N(0,1) physical field (splitmix64 +
+// Box-Muller) projected on the state space, written to the instance's w.
+tsk_status seeded_start(Operator* op, uint64_t seed, hipStream_t s, const void** x0) {
+    const int64_t pr = op->physical_reals();
+    TSK_TRY(op->aw.phys.ensure(size_t(pr) * 8));
+    TSK_TRY(normal_fill(op->aw.phys.as<double>(), pr, seed, s));
+    if (op->kind == StateKind::Real32) TSK_TRY(narrow_to_float(op->aw.phys.as<double>(), op->aw.phys.as<float>(), pr, s));
+    TSK_TRY(op->from_physical(op->aw.phys.ptr, op->aw.w.ptr));
+    *x0 = op->aw.w.ptr;
+    return TSK_OK;
+}
+
+// Reset of the descriptor table D (count instances, nslots slot tables), norm
+// and finiteness of the start vectors, then V_0 = x0 / ||x0|| (Algorithm 1).
+template <typename TS>
+tsk_status normalize_starts(const KryDesc* D, int count, int nslots, int64_t nmax, int nblk_max, ArnoldiWork& L,
+                            hipStream_t s) {
+    RitzResult* rrh = L.rr_host;
+    hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count, nslots);
+    launch_check_finite<TS>(D, count, nmax, s);
+    launch_dot<TS>(D, count, nblk_max, 0, true, s);
+    launch_reduce(D, count, 0, -1, 0, 0, s);
+    hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, D, count, L.batch_rr.as<RitzResult>(), 1);
+    TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+    TSK_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < count; ++i) {
-        Operator* op = ops[i];
-        ArnoldiWork& W = op->aw;
-        const int64_t n = op->n;
-        const int64_t ldv = (n + 63) / 64 * 64;
-        const int nblk = cgs_blocks(n);
-        TSK_TRY(W.V.ensure(size_t(m + 1) * ldv * sizeof(TS)));
-        TSK_TRY(W.H.ensure(size_t(m + 1) * m * sizeof(double2)));
-        TSK_TRY(W.w.ensure(size_t(n) * sizeof(TS)));
-        TSK_TRY(W.w64.ensure(size_t(n) * sizeof(A)));
-        TSK_TRY(W.partial.ensure(size_t(nblk) * (m + 1) * sizeof(double2)));
-        TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
-        TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
-        TSK_TRY(W.scal.ensure(64 * sizeof(double)));
-        TSK_TRY(W.eigS.ensure(size_t(NS) * m * m * sizeof(double2)));
-        TSK_TRY(W.eigY.ensure(size_t(m) * (k > 0 ? k : 1) * sizeof(double2)));
-        TSK_TRY(W.eigMu.ensure(size_t(NS) * m * sizeof(double2)));
-        TSK_TRY(W.eigRes.ensure(size_t(NS) * m * sizeof(double)));
-        TSK_TRY(W.sel.ensure(size_t(NS) * m * sizeof(int)));
-        TSK_TRY(W.out.ensure(5 * size_t(k) * sizeof(double)));
-        TSK_TRY(W.rr.ensure(size_t(NS) * sizeof(RitzResult)));
-        W.m = m;
-        W.steps = 0;
-        W.ldv = ldv;
-        KryDesc& d = Dh[i];
-        std::memset(&d, 0, sizeof(d));
-        d.V = W.V.ptr;
-        d.w = W.w.ptr;
-        d.w64 = W.w64.ptr;
-        d.H = W.H.as<double2>();
-        d.partial = W.partial.as<double2>();
-        d.pnrm = W.pnrm.as<double>();
-        d.h = W.h.as<double2>();
-        d.scal = W.scal.as<double>();
-        d.Z = nullptr;
-        d.S = W.eigS.as<double2>();
-        d.Y = W.eigY.as<double2>();
-        d.mu = W.eigMu.as<double2>();
-        d.res = W.eigRes.as<double>();
-        d.sel = W.sel.as<int>();
-        d.rr = W.rr.as<RitzResult>();
-        d.ritz = (ritz && ritz[i]) ? ritz[i] : nullptr;
-        d.out = W.out.as<double>();
-        d.ldv = ldv;
-        d.n = n;
-        d.ldh = m + 1;
-        d.nblk = nblk;
-        d.active = 1;
-        d.dup_rel = dup_rel;
-        d.res_floor = res_floor;
-        d.T = op->T;
-        nmax = std::max(nmax, n);
-        nblk_max = std::max(nblk_max, nblk);
+        if (rrh[i].nonfinite) return fail(TSK_ENONFINITE, "start vector " + std::to_string(i) + " is not finite");
+        if (!(rrh[i].beta > 0.0)) return fail(TSK_EINVAL, "start vector " + std::to_string(i) + " is zero");
     }
+    launch_scale<TS>(D, count, nmax, -1, s);
+    return TSK_OK;
+}
+
+// Timing events (two per matvec of up to m + 1 steps), side streams with their
+// events, and the device and pinned copies of nrr RitzResults.
+tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
+    constexpr int NS = ArnoldiWork::kSlots;
     while (L.ev_apply.size() < size_t(2 * (m + 1))) {
         hipEvent_t e;
         TSK_HIP(hipEventCreate(&e));
@@ -156,13 +178,52 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         if (!L.ev_eig[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_eig[t], hipEventDisableTiming));
         if (!L.side[t]) TSK_HIP(hipStreamCreateWithFlags(&L.side[t], hipStreamNonBlocking));
     }
-    TSK_TRY(L.batch_rr.ensure(size_t(NS) * count * sizeof(RitzResult)));
-    if (L.rr_host_count < NS * count) {
+    TSK_TRY(L.batch_rr.ensure(size_t(nrr) * sizeof(RitzResult)));
+    if (L.rr_host_count < nrr) {
         if (L.rr_host) (void)hipHostFree(L.rr_host);
         L.rr_host = nullptr;
-        TSK_HIP(hipHostMalloc((void**)&L.rr_host, size_t(NS) * count * sizeof(RitzResult), 0));
-        L.rr_host_count = NS * count;
+        TSK_HIP(hipHostMalloc((void**)&L.rr_host, size_t(nrr) * sizeof(RitzResult), 0));
+        L.rr_host_count = nrr;
     }
+    return TSK_OK;
+}
+
+// Step j of the factorisation after the matvec w = M v_j: classical
+// Gram-Schmidt twice against v_0..v_j (H column j = h1 + h2), beta_j = ||f||,
+// H[j+1][j] = beta_j, v_{j+1} = f / beta_j (Algorithm 1 with CGS2).
+template <typename TS>
+void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, hipStream_t s) {
+    const int p = j + 1;
+    launch_dot<TS>(Dt, count, nblk_max, p, false, s);
+    launch_reduce(Dt, count, p, j, 1, 1, s);
+    launch_update<TS>(Dt, count, nblk_max, p, true, true, s);
+    launch_reduce(Dt, count, p, j, 0, -1, s);
+    launch_update<TS>(Dt, count, nblk_max, p, false, false, s);
+    launch_finalize(Dt, count, j, s);
+    launch_scale<TS>(Dt, count, nmax, j, s);
+}
+
+template <typename TS>
+tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
+                     const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
+                     tsk_arnoldi_info* infos) {
+    auto t0 = std::chrono::steady_clock::now();
+    Operator* lead = ops[0];
+    const hipStream_t s = lead->stream;
+    ArnoldiWork& L = lead->aw;
+    constexpr int NS = ArnoldiWork::kSlots;
+    constexpr bool kRealH = !std::is_same<TS, double2>::value;  // real operators: real Hessenberg QR
+
+    // ---- per-instance workspace and descriptors ------------------------------------
+    std::vector<KryDesc> Dh(count);
+    int64_t nmax = 0;
+    int nblk_max = 0;
+    for (int i = 0; i < count; ++i) {
+        TSK_TRY(make_desc<TS>(ops[i], m, k, NS, (ritz && ritz[i]) ? ritz[i] : nullptr, Dh[i]));
+        nmax = std::max(nmax, ops[i]->n);
+        nblk_max = std::max(nblk_max, Dh[i].nblk);
+    }
+    TSK_TRY(driver_resources(L, m, NS * count));
     RitzResult* rrh = L.rr_host;
     // slot tables: identical except for the eigensolver outputs
     std::vector<KryDesc> Dall(size_t(NS) * count);
@@ -182,16 +243,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // ---- start vectors (Algorithm 1: v1 = v / ||v||) -----------------------------------
     for (int i = 0; i < count; ++i) {
         const void* x0 = (v0s && v0s[i]) ? v0s[i] : nullptr;
-        if (!x0) {
-            Operator* op = ops[i];
-            const int64_t pr = op->physical_reals();
-            TSK_TRY(op->aw.phys.ensure(size_t(pr) * 8));
-            TSK_TRY(normal_fill(op->aw.phys.as<double>(), pr, seeds ? seeds[i] : uint64_t(i), s));
-            if (op->kind == StateKind::Real32)
-                TSK_TRY(narrow_to_float(op->aw.phys.as<double>(), op->aw.phys.as<float>(), pr, s));
-            TSK_TRY(op->from_physical(op->aw.phys.ptr, op->aw.w.ptr));
-            x0 = op->aw.w.ptr;
-        }
+        if (!x0) TSK_TRY(seeded_start(ops[i], seeds ? seeds[i] : uint64_t(i), s, &x0));
         Dh[i].x0 = x0;
     }
     for (int t = 0; t < NS; ++t)
@@ -200,18 +252,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     KryDesc* D = L.batch_desc.as<KryDesc>();
     auto table = [&](int t) { return D + size_t(t) * count; };
     TSK_HIP(hipMemcpyAsync(D, Dall.data(), size_t(NS) * count * sizeof(KryDesc), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count, NS);
-    launch_check_finite<TS>(D, count, nmax, s);
-    launch_dot<TS>(D, count, nblk_max, 0, true, s);
-    launch_reduce(D, count, 0, -1, 0, 0, s);
-    hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, D, count, L.batch_rr.as<RitzResult>(), 1);
-    TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
-    TSK_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < count; ++i) {
-        if (rrh[i].nonfinite) return fail(TSK_ENONFINITE, "start vector " + std::to_string(i) + " is not finite");
-        if (!(rrh[i].beta > 0.0)) return fail(TSK_EINVAL, "start vector " + std::to_string(i) + " is zero");
-    }
-    launch_scale<TS>(D, count, nmax, -1, s);
+    TSK_TRY(normalize_starts<TS>(D, count, NS, nmax, nblk_max, L, s));
 
     // ---- matvec of step j for every active instance --------------------------------------
     KolmoBatchPtr kb;
@@ -238,13 +279,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     auto enqueue = [&](int j) -> tsk_status {
         const int p = j + 1, t = j % NS;
         const KryDesc* Dt = table(t);
-        launch_dot<TS>(Dt, count, nblk_max, p, false, s);
-        launch_reduce(Dt, count, p, j, 1, 1, s);
-        launch_update<TS>(Dt, count, nblk_max, p, true, true, s);
-        launch_reduce(Dt, count, p, j, 0, -1, s);
-        launch_update<TS>(Dt, count, nblk_max, p, false, false, s);
-        launch_finalize(Dt, count, j, s);
-        launch_scale<TS>(Dt, count, nmax, j, s);
+        cgs2_step<TS>(Dt, count, nblk_max, nmax, j, s);
         TSK_HIP(hipEventRecord(L.ev_cgs[t], s));
         if (j + 1 < m) {
             TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
@@ -369,6 +404,138 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     return count == 1 ? tsk_status(oc[0].status) : TSK_OK;
 }
 
+
+// ---- Krylov-Schur driver (Sec. 3.2.2) -------------------------------------------------------
+// Expansion: Arnoldi steps j0..m-1 (matvec + CGS2) enqueued without host
+// synchronisation.  At order m, one kernel analyses H_m (Ritz pairs, residuals,
+// stop test; convergence is tested only at full order, steps 2 and 6 of the
+// method) and, when the test fails, contracts it to an Arnoldi factorisation
+// of order p (hessenberg.hip); the host reads the 56-byte result, rotates the
+// basis into the second buffer (V_p = V_m W, v_{p+1} = v_{m+1}) and expands
+// again from j0 = p.  A breakdown during an expansion (sticky bd_step) ends the
+// run with the exact Ritz pairs of that order.
+template <typename TS>
+tsk_status krylov_schur_t(Operator* op, int m, int k, double tol, double delta, int pmax, int max_restarts,
+                          const void* v0, uint64_t seed, double* mu_ri, double* lam_ri, double* resid, void* ritz,
+                          tsk_ks_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const hipStream_t s = op->stream;
+    ArnoldiWork& L = op->aw;
+    KryDesc d;
+    TSK_TRY(make_desc<TS>(op, m, k, 1, ritz, d));
+    TSK_TRY(L.V2.ensure(size_t(m + 1) * d.ldv * sizeof(TS)));
+    TSK_TRY(L.ksW.ensure(size_t(m) * m * sizeof(double)));
+    d.ksW = L.ksW.as<double>();
+    d.ks_delta = delta;
+    d.ks_pmax = pmax;
+    TSK_TRY(driver_resources(L, m, 1));
+    RitzResult* rrh = L.rr_host;
+    if (!v0) TSK_TRY(seeded_start(op, seed, s, &v0));
+    d.x0 = v0;
+    TSK_TRY(L.batch_desc.ensure(sizeof(KryDesc)));
+    KryDesc* D = L.batch_desc.as<KryDesc>();
+    TSK_HIP(hipMemcpyAsync(D, &d, sizeof(KryDesc), hipMemcpyHostToDevice, s));
+    const int64_t n = op->n;
+    TSK_TRY(normalize_starts<TS>(D, 1, 1, n, d.nblk, L, s));
+
+    auto collect = [&]() -> tsk_status {
+        hipLaunchKernelGGL(k_collect, dim3(1), dim3(64), 0, s, D, 1, L.batch_rr.as<RitzResult>(), 0);
+        TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+        TSK_HIP(hipStreamSynchronize(s));
+        return TSK_OK;
+    };
+    void* Vcur = L.V.ptr;
+    void* Valt = L.V2.ptr;
+    int j0 = 0, n_matvec = 0, restarts = 0, order = m, kept_last = 0;
+    double ms_apply = 0.0;
+    int status = TSK_NOT_CONVERGED;
+    std::string err;
+    while (true) {
+        for (int j = j0; j < m; ++j) {  // expansion (step 1, or step 5 after a contraction)
+            TSK_HIP(hipEventRecord(L.ev_apply[2 * j], s));
+            TSK_TRY(op->apply(static_cast<const TS*>(Vcur) + j * d.ldv, d.w));
+            TSK_HIP(hipEventRecord(L.ev_apply[2 * j + 1], s));
+            cgs2_step<TS>(D, 1, d.nblk, n, j, s);
+        }
+        const int contract = restarts < max_restarts ? 1 : 0;
+        TSK_TRY(ks_contract_launch(D, m, k, tol, contract, s));
+        TSK_TRY(collect());
+        for (int j = j0; j < m; ++j) {
+            float ms = 0.0f;
+            TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * j], L.ev_apply[2 * j + 1]));
+            ms_apply += ms;
+        }
+        RitzResult r = rrh[0];
+        if (r.bd_step) {  // happy breakdown at order bd_step: exact Ritz pairs of that order
+            order = r.bd_step;
+            n_matvec += order - j0;
+            TSK_TRY(hess_ritz_launch(D, 1, order, std::min(k, order), tol, false, s, true));
+            TSK_TRY(collect());
+            r = rrh[0];
+            if (r.nonfinite) { status = TSK_ENONFINITE; err = "non-finite matvec output or norm"; }
+            else if (r.eig_fail) { status = TSK_EEIG; err = "Hessenberg QR did not converge"; }
+            else status = TSK_BREAKDOWN;
+            break;
+        }
+        n_matvec += m - j0;
+        if (r.nonfinite) { status = TSK_ENONFINITE; err = "non-finite matvec output or norm"; break; }
+        if (r.eig_fail == 1) { status = TSK_EEIG; err = "Hessenberg QR did not converge"; break; }
+        if (r.eig_fail == 2) { status = TSK_EEIG; err = "Schur reordering left no room to expand"; break; }
+        if (r.done) { status = TSK_OK; break; }
+        if (!contract) break;
+        // step 4: V_p = V_m W, v_{p+1} = v_{m+1}, in the other buffer
+        const int kp = r.kept;
+        launch_rotate<TS>(Vcur, Valt, d.ksW, n, d.ldv, m, kp, s);
+        std::swap(Vcur, Valt);
+        d.V = Vcur;
+        TSK_HIP(hipMemcpyAsync(D, &d, sizeof(KryDesc), hipMemcpyHostToDevice, s));
+        j0 = kp;
+        kept_last = kp;
+        ++restarts;
+    }
+    L.Vcur = Vcur;
+    L.steps = order;
+    if (status < 0) return fail(tsk_status(status), err + " after " + std::to_string(n_matvec) + " matvecs");
+
+    // ---- outputs (Ritz pairs of the final factorisation of order `order`) ------------------
+    d.steps = order;
+    TSK_HIP(hipMemcpyAsync(D, &d, sizeof(KryDesc), hipMemcpyHostToDevice, s));
+    if (ritz) {
+        TSK_TRY(ritz_coords_launch(D, 1, order, k, s));
+        launch_ritz_vectors<TS>(D, 1, n, k, s);
+    }
+    launch_gather(D, 1, k, s);
+    std::vector<double> hout(5 * size_t(k));
+    TSK_HIP(hipMemcpyAsync(hout.data(), d.out, 5 * size_t(k) * sizeof(double), hipMemcpyDeviceToHost, s));
+    TSK_TRY(collect());
+    const RitzResult& r = rrh[0];
+    const double ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int q = 0; q < k; ++q) {
+        const bool have = q < r.nsel;
+        if (mu_ri) {
+            mu_ri[2 * q] = have ? hout[2 * q] : 0.0;
+            mu_ri[2 * q + 1] = have ? hout[2 * q + 1] : 0.0;
+        }
+        if (lam_ri) {
+            lam_ri[2 * q] = have ? hout[2 * k + 2 * q] : 0.0;
+            lam_ri[2 * q + 1] = have ? hout[2 * k + 2 * q + 1] : 0.0;
+        }
+        if (resid) resid[q] = have ? hout[4 * k + q] : 0.0;
+    }
+    if (info) {
+        info->n_matvec = n_matvec;
+        info->n_restarts = restarts;
+        info->n_ritz = r.nsel;
+        info->n_converged = r.nconv;
+        info->status = status;
+        info->kept_last = kept_last;
+        info->beta = r.beta;
+        info->ms_total = ms_total;
+        info->ms_apply = ms_apply;
+    }
+    return tsk_status(status);
+}
+
 }  // namespace
 
 tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
@@ -395,6 +562,26 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
             return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
     }
     return fail(TSK_EINVAL, "unknown state kind");
+}
+
+tsk_status krylov_schur(Operator* op, int m, int k, double tol, double delta, int pmax, int max_restarts,
+                        const void* v0, uint64_t seed, double* mu_ri, double* lam_ri, double* resid, void* ritz,
+                        tsk_ks_info* info) {
+    if (!op) return fail(TSK_EINVAL, "null operator");
+    if (op->is_complex()) return fail(TSK_EINVAL, "Krylov-Schur (real Schur form) needs a real operator");
+    if (!op->ready()) return fail(TSK_ESTATE, "operator parameters or base flow not set");
+    if (k < 1 || m < k + 2 || m > kMaxKrylov) return fail(TSK_EINVAL, "need 1 <= k and k + 2 <= m <= 96");
+    if (int64_t(m) > op->n) return fail(TSK_EINVAL, "m exceeds the state dimension");
+    if (pmax == 0) pmax = std::max(k, m / 2);
+    if (pmax < k || pmax > m - 2) return fail(TSK_EINVAL, "need k <= p_max <= m - 2");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TSK_EINVAL, "tol must be finite and >= 0");
+    if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(TSK_EINVAL, "delta must be finite and >= 0");
+    if (max_restarts < 0) return fail(TSK_EINVAL, "max_restarts must be >= 0");
+    if (op->kind == StateKind::Real32)
+        return krylov_schur_t<float>(op, m, k, tol, delta, pmax, max_restarts, v0, seed, mu_ri, lam_ri, resid, ritz,
+                                     info);
+    return krylov_schur_t<double>(op, m, k, tol, delta, pmax, max_restarts, v0, seed, mu_ri, lam_ri, resid, ritz,
+                                  info);
 }
 
 }  // namespace tsk

@@ -111,6 +111,8 @@ struct RitzResult {
     int breakdown;     // beta <= 64 eps ||w_in||
     int nonfinite;     // beta or H not finite
     int iters;         // QR iterations used
+    int bd_step;       // first step order j+1 whose beta broke down (0: none); sticky
+    int kept;          // Krylov-Schur contraction: order p kept (0: no contraction)
     int pad;
     double beta;
     double w_in;

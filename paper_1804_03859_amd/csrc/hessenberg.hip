@@ -37,6 +37,8 @@
 // converged one also count as copies of it (FP32 rounding splits a multiple
 // eigenvalue into a cluster of about that width), and a pair counts as
 // converged below max(tol, res_floor |mu|), the FP32 floor of the estimate.
+#include <cstring>
+
 #include "krylov.hpp"
 #include "ops.hpp"
 
@@ -514,7 +516,9 @@ __device__ inline double quasi_eigvec(const double* T, const int* blk, int p, in
 
 // Rotation G = [[cs, sn], [-sn, cs]] applied as T <- G T G^T on indices (i, i+1)
 // of the full matrix (rows i, i+1 from column cfrom; columns i, i+1 for rows
-// 0..rto) and zl <- zl G^T.  One wavefront, uniform control flow.
+// 0..rto) and Z <- Z G^T: FZ = false, zl is the last row of Z; FZ = true, zl
+// is all of Z (row-major p x p).  One wavefront, uniform control flow.
+template <bool FZ>
 __device__ inline void rot_similarity(double* T, double* zl, int p, int i, double cs, double sn, int cfrom, int rto,
                                       int lane) {
     for (int c = cfrom + lane; c < p; c += kHT) {
@@ -528,7 +532,13 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
         T[r * p + i] = cs * u + sn * v;
         T[r * p + i + 1] = -sn * u + cs * v;
     }
-    if (lane == 0) {
+    if constexpr (FZ) {
+        for (int r = lane; r < p; r += kHT) {
+            const double u = zl[r * p + i], v = zl[r * p + i + 1];
+            zl[r * p + i] = cs * u + sn * v;
+            zl[r * p + i + 1] = -sn * u + cs * v;
+        }
+    } else if (lane == 0) {
         const double u = zl[i], v = zl[i + 1];
         zl[i] = cs * u + sn * v;
         zl[i + 1] = -sn * u + cs * v;
@@ -537,14 +547,15 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
 }
 
 // One bulge step: the similarity T <- P T P with the NB-element reflector P at
-// indices kk..kk+NB-1 built from (x, y, z), and zl <- zl P.  The NB x NB block by
+// indices kk..kk+NB-1 built from (x, y, z), and Z <- Z P (zl: the last row of Z,
+// or with FZ all of Z, each lane updating its own rows).  The NB x NB block by
 // lanes 0..NB*NB-1, the rows kk.. at columns kk+NB..p-1 and the columns kk.. at
 // rows 0..kk-1 and kk+NB (when inside the window) by the lanes in turn, all from
 // pre-update values in one phase.
 // Returns true with the next bulge (x, y, z) = new (T[kk+1][kk], T[kk+2][kk],
 // T[kk+3][kk]) taken from the lanes that computed them; false when no
 // reflection was needed (the caller then reads T).
-template <int NB>
+template <int NB, bool FZ>
 __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi, int kk, double x, double y,
                                   double z, int lane, double& nx, double& ny, double& nz) {
     double v1, v2, tau, alpha;
@@ -620,7 +631,17 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
             }
         }
         double zn[NB];
-        {
+        if constexpr (FZ) {
+            // rows of Z are private to their lanes in this phase
+            for (int r = lane; r < p; r += kHT) {
+                double* zr = zl + r * p + kk;
+                double dz = 0.0;
+#pragma unroll
+                for (int a = 0; a < NB; ++a) dz += zr[a] * v[a];
+#pragma unroll
+                for (int a = 0; a < NB; ++a) zr[a] -= tau * dz * v[a];
+            }
+        } else {
             double dz = 0.0;
 #pragma unroll
             for (int a = 0; a < NB; ++a) dz += zl[kk + a] * v[a];
@@ -636,8 +657,10 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
                 for (int a = 0; a < NB; ++a) Tr[nidx[q] + a * nstr[q]] = nv[q][a];
             }
         if (lane == 0) {
+            if constexpr (!FZ) {
 #pragma unroll
-            for (int a = 0; a < NB; ++a) zl[kk + a] = zn[a];
+                for (int a = 0; a < NB; ++a) zl[kk + a] = zn[a];
+            }
             if (kk > l) {  // the reflector turned column kk-1 into (alpha, 0, ..., 0)
                 Tr[kk * p + kk - 1] = alpha;
 #pragma unroll
@@ -660,6 +683,144 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
     }
     wave_lds_sync();
     return fwd;
+}
+
+// Francis double-shift QR of the p x p real Hessenberg matrix in Tr (row-major,
+// LDS) to quasi upper-triangular form; blk marks the 2x2 blocks (1 = first, 2 =
+// second row).  zl: last row of Z (FZ = false) or all of Z (FZ = true), updated
+// with every transformation.  total: sweeps used; failed: no convergence
+// within 30 max(p, 10) sweeps.
+template <bool FZ>
+__device__ __attribute__((always_inline)) inline void francis_real(double* Tr, double* zl, int* blk, int p, int lane,
+                                                                   int& total, int& failed) {
+    int ihi = p - 1, its = 0;
+    total = 0;
+    failed = 0;
+    const int itmax = 30 * (p > 10 ? p : 10);
+    while (ihi > 0) {
+        // deflation: largest l <= ihi with a negligible T[l][l-1] (else 0)
+        bool s0 = false, s1 = false;
+        {
+            int i = lane + 1;
+            if (i <= ihi) {
+                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
+                if (tst == 0.0) tst = 1.0;
+                s0 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
+            }
+            i = lane + 65;
+            if (i <= ihi) {
+                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
+                if (tst == 0.0) tst = 1.0;
+                s1 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
+            }
+        }
+        const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
+        const int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
+        wave_lds_sync();
+        if (l > 0 && lane == 0) Tr[l * p + (l - 1)] = 0.0;
+        wave_lds_sync();
+        if (l == ihi) {  // 1x1 block converged
+            --ihi;
+            its = 0;
+            continue;
+        }
+        if (l == ihi - 1) {  // 2x2 block: split when its eigenvalues are real
+            const int i = ihi - 1;
+            const double a = Tr[i * p + i], b = Tr[i * p + i + 1], c = Tr[(i + 1) * p + i], d = Tr[(i + 1) * p + i + 1];
+            const double hp = 0.5 * (a - d);
+            const double disc = hp * hp + b * c;
+            if (disc >= 0.0) {
+                // eigenvalue closest to d, eigenvector (lam - d, c) -> rotation taking it to e_1
+                const double sq = sqrt(disc);
+                const double lam = d + (hp >= 0.0 ? hp + sq : hp - sq);
+                double ex = lam - d, ey = c;
+                const double en = hypot(ex, ey);
+                if (en > 0.0) {
+                    const double cs = ex / en, sn = ey / en;
+                    rot_similarity<FZ>(Tr, zl, p, i, cs, sn, i, i + 1, lane);
+                }
+                if (lane == 0) Tr[(i + 1) * p + i] = 0.0;
+                wave_lds_sync();
+            } else if (lane == 0) {
+                blk[i] = 1;
+                blk[i + 1] = 2;
+            }
+            wave_lds_sync();
+            ihi -= 2;
+            its = 0;
+            continue;
+        }
+        if (++total > itmax) {
+            failed = 1;
+            break;
+        }
+        ++its;
+        // double shift: s = sum, t = product of the trailing 2x2 eigenvalues
+        double ss, tt;
+        {
+            const double a = Tr[(ihi - 1) * p + (ihi - 1)], b = Tr[(ihi - 1) * p + ihi];
+            const double c = Tr[ihi * p + (ihi - 1)], d = Tr[ihi * p + ihi];
+            if (its % 10 == 0) {
+                const double sx = fabs(c) + fabs(Tr[(ihi - 1) * p + (ihi - 2)]);
+                const double h11 = 0.75 * sx + d, h12 = -0.4375 * sx, h21 = sx;
+                ss = 2.0 * h11;
+                tt = h11 * h11 - h12 * h21;
+            } else {
+                ss = a + d;
+                tt = a * d - b * c;
+            }
+        }
+        double x, y, z;
+        {
+            const double t00 = Tr[l * p + l], t01 = Tr[l * p + l + 1], t10 = Tr[(l + 1) * p + l];
+            const double t11 = Tr[(l + 1) * p + l + 1], t21 = Tr[(l + 2) * p + l + 1];
+            x = t00 * t00 + t01 * t10 - ss * t00 + tt;
+            y = t10 * (t00 + t11 - ss);
+            z = t10 * t21;
+        }
+        // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
+        for (int kk = l; kk <= ihi - 2; ++kk) {
+            double nx, ny, nz;
+            if (bulge_step<3, FZ>(Tr, zl, p, l, ihi, kk, x, y, z, lane, nx, ny, nz)) {
+                x = nx;
+                y = ny;
+                z = nz;
+            } else {
+                x = Tr[(kk + 1) * p + kk];
+                y = Tr[(kk + 2) * p + kk];
+                z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
+            }
+        }
+        {
+            double nx, ny, nz;
+            bulge_step<2, FZ>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane, nx, ny, nz);
+        }
+    }
+}
+
+// Ritz values of the quasi-triangular T (the 2x2 blocks give a + ib, a - ib in
+// consecutive entries), eigenvectors of T in S (one per lane, back
+// substitution) and residuals beta |zl . z_i| / ||z_i||, zl the last row of Z.
+__device__ inline void real_ritz(const double* Tr, const int* blk, const double* zl, int p, double beta,
+                                 double2* __restrict__ mu, double2* __restrict__ S, double* __restrict__ res, int lane) {
+    for (int i = lane; i < p; i += kHT) {
+        const double ti = Tr[i * p + i];
+        double2 m = cmk<double2>(ti, 0.0);
+        if (blk[i] != 0) {
+            const int r0 = blk[i] == 1 ? i : i - 1;
+            const double a = Tr[r0 * p + r0], b = Tr[r0 * p + r0 + 1], c = Tr[(r0 + 1) * p + r0];
+            const double d = Tr[(r0 + 1) * p + r0 + 1];
+            const double hp = 0.5 * (a - d);
+            const double im = sqrt(fmax(-(hp * hp + b * c), 0.0));
+            m = cmk<double2>(0.5 * (a + d), blk[i] == 1 ? im : -im);
+        }
+        mu[i] = m;
+        double2* zc = S + (size_t)i * p;
+        const double n2 = quasi_eigvec(Tr, blk, p, i, m, zc);
+        double2 last = cmk<double2>(0.0, 0.0);
+        for (int c = 0; c < p; ++c) last = cadd(last, cscale(zc[c], zl[c]));
+        res[i] = fabs(beta) * cabs(last) / sqrt(n2);
+    }
 }
 
 __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restrict__ Dv, int p, int k, double tol,
@@ -706,127 +867,9 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restric
     }
     __syncthreads();
 
-    int ihi = p - 1, its = 0, total = 0, failed = 0;
-    const int itmax = 30 * (p > 10 ? p : 10);
-    while (ihi > 0) {
-        // deflation: largest l <= ihi with a negligible T[l][l-1] (else 0)
-        bool s0 = false, s1 = false;
-        {
-            int i = lane + 1;
-            if (i <= ihi) {
-                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
-                if (tst == 0.0) tst = 1.0;
-                s0 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
-            }
-            i = lane + 65;
-            if (i <= ihi) {
-                double tst = fabs(Tr[(i - 1) * p + (i - 1)]) + fabs(Tr[i * p + i]);
-                if (tst == 0.0) tst = 1.0;
-                s1 = fabs(Tr[i * p + (i - 1)]) <= kEps * tst;
-            }
-        }
-        const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
-        const int l = m1 ? highest_bit(m1) + 65 : (m0 ? highest_bit(m0) + 1 : 0);
-        wave_lds_sync();
-        if (l > 0 && lane == 0) Tr[l * p + (l - 1)] = 0.0;
-        wave_lds_sync();
-        if (l == ihi) {  // 1x1 block converged
-            --ihi;
-            its = 0;
-            continue;
-        }
-        if (l == ihi - 1) {  // 2x2 block: split when its eigenvalues are real
-            const int i = ihi - 1;
-            const double a = Tr[i * p + i], b = Tr[i * p + i + 1], c = Tr[(i + 1) * p + i], d = Tr[(i + 1) * p + i + 1];
-            const double hp = 0.5 * (a - d);
-            const double disc = hp * hp + b * c;
-            if (disc >= 0.0) {
-                // eigenvalue closest to d, eigenvector (lam - d, c) -> rotation taking it to e_1
-                const double sq = sqrt(disc);
-                const double lam = d + (hp >= 0.0 ? hp + sq : hp - sq);
-                double ex = lam - d, ey = c;
-                const double en = hypot(ex, ey);
-                if (en > 0.0) {
-                    const double cs = ex / en, sn = ey / en;
-                    rot_similarity(Tr, zl, p, i, cs, sn, i, i + 1, lane);
-                }
-                if (lane == 0) Tr[(i + 1) * p + i] = 0.0;
-                wave_lds_sync();
-            } else if (lane == 0) {
-                blk[i] = 1;
-                blk[i + 1] = 2;
-            }
-            wave_lds_sync();
-            ihi -= 2;
-            its = 0;
-            continue;
-        }
-        if (++total > itmax) {
-            failed = 1;
-            break;
-        }
-        ++its;
-        // double shift: s = sum, t = product of the trailing 2x2 eigenvalues
-        double ss, tt;
-        {
-            const double a = Tr[(ihi - 1) * p + (ihi - 1)], b = Tr[(ihi - 1) * p + ihi];
-            const double c = Tr[ihi * p + (ihi - 1)], d = Tr[ihi * p + ihi];
-            if (its % 10 == 0) {
-                const double sx = fabs(c) + fabs(Tr[(ihi - 1) * p + (ihi - 2)]);
-                const double h11 = 0.75 * sx + d, h12 = -0.4375 * sx, h21 = sx;
-                ss = 2.0 * h11;
-                tt = h11 * h11 - h12 * h21;
-            } else {
-                ss = a + d;
-                tt = a * d - b * c;
-            }
-        }
-        double x, y, z;
-        {
-            const double t00 = Tr[l * p + l], t01 = Tr[l * p + l + 1], t10 = Tr[(l + 1) * p + l];
-            const double t11 = Tr[(l + 1) * p + l + 1], t21 = Tr[(l + 2) * p + l + 1];
-            x = t00 * t00 + t01 * t10 - ss * t00 + tt;
-            y = t10 * (t00 + t11 - ss);
-            z = t10 * t21;
-        }
-        // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
-        for (int kk = l; kk <= ihi - 2; ++kk) {
-            double nx, ny, nz;
-            if (bulge_step<3>(Tr, zl, p, l, ihi, kk, x, y, z, lane, nx, ny, nz)) {
-                x = nx;
-                y = ny;
-                z = nz;
-            } else {
-                x = Tr[(kk + 1) * p + kk];
-                y = Tr[(kk + 2) * p + kk];
-                z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
-            }
-        }
-        {
-            double nx, ny, nz;
-            bulge_step<2>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane, nx, ny, nz);
-        }
-    }
-
-    // ---- Ritz values, eigenvectors of T, residuals ---------------------------------------------
-    for (int i = lane; i < p; i += kHT) {
-        const double ti = Tr[i * p + i];
-        double2 m = cmk<double2>(ti, 0.0);
-        if (blk[i] != 0) {
-            const int r0 = blk[i] == 1 ? i : i - 1;
-            const double a = Tr[r0 * p + r0], b = Tr[r0 * p + r0 + 1], c = Tr[(r0 + 1) * p + r0];
-            const double d = Tr[(r0 + 1) * p + r0 + 1];
-            const double hp = 0.5 * (a - d);
-            const double im = sqrt(fmax(-(hp * hp + b * c), 0.0));
-            m = cmk<double2>(0.5 * (a + d), blk[i] == 1 ? im : -im);
-        }
-        mu[i] = m;
-        double2* zc = S + (size_t)i * p;
-        const double n2 = quasi_eigvec(Tr, blk, p, i, m, zc);
-        double2 last = cmk<double2>(0.0, 0.0);
-        for (int c = 0; c < p; ++c) last = cadd(last, cscale(zc[c], zl[c]));
-        res[i] = fabs(beta) * cabs(last) / sqrt(n2);
-    }
+    int total = 0, failed = 0;
+    francis_real<false>(Tr, zl, blk, p, lane, total, failed);
+    real_ritz(Tr, blk, zl, p, beta, mu, S, res, lane);
     __syncthreads();
     if (standalone) {
         if (lane == 0 && rr) {
@@ -918,6 +961,422 @@ __global__ __launch_bounds__(kHT) void k_ritz_coords(const KryDesc* __restrict__
     for (int r = lane; r < p; r += kHT) Y[(size_t)sidx * p + r] = b[r];
 }
 
+
+// ---- Krylov-Schur contraction (Sec. 3.2.2, steps 2 to 4) --------------------------------
+// After an expansion to order m the factorisation M V_m = V_m H_m + beta v_{m+1}
+// e_m^T is analysed exactly as after an Arnoldi step (Ritz pairs, residuals,
+// wanted set, stop test).  When the test fails, the contraction:
+//  * real Schur form H_m = Z T Z^T (the Francis QR above, all of Z kept);
+//  * kept set: the Ritz values with |mu| >= 1 - delta, at least k and at most
+//    pmax of them, the leading ones in the wanted-set order, complex pairs whole;
+//  * reordering of T so the kept blocks lead (swaps of adjacent diagonal blocks,
+//    Z updated), which gives M (V Z) = (V Z) T + v_{m+1} (beta e_m^T Z), and the
+//    truncation to the leading p columns: S = T_11, b = beta Z[m-1, 0:p];
+//  * reduction of that Krylov-Schur decomposition to an equivalent Arnoldi one
+//    (Stewart 2001: Krylov decompositions related by a similarity have the same
+//    Ritz pairs): a reflector P0 with b^T P0 = beta' e_p^T, then reflectors that
+//    leave e_p fixed and bring P0 S P0 to upper Hessenberg form from the bottom
+//    row up.  The new basis is V_m W with W = Z[:, 0:p] P (m x p), the new
+//    H_p is Hessenberg and H[p][p-1] = beta' >= 0, so the expansion continues
+//    with plain Arnoldi steps from v_{p+1} = v_{m+1}.
+
+// Swap of adjacent diagonal blocks of a real Schur form (Bai & Demmel 1993,
+// direct swapping): A (N1 x N1) at j, B (N2 x N2) at j + N1, coupling C.  The
+// solution X of A X - X B = C makes [-X; I] span B's invariant subspace of
+// the (N1 + N2) block; the orthogonal Q of its QR factorisation moves B's
+// eigenvalues first.  Refused (nothing changed, false) when the lower-left
+// block of Q^T D Q is not negligible, which happens only for nearly equal
+// eigenvalues.  Every lane solves the small problem itself (identical
+// arithmetic, no broadcast); the updates of T's rows and columns and of Z's
+// columns are split over the lanes.
+template <int N1, int N2>
+__device__ bool swap_blocks(double* Tr, double* Zf, int m, int j, int lane) {
+    constexpr int NT = N1 + N2, K = N1 * N2;
+    double D[NT][NT];
+    double dnorm = 0.0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            D[a][c] = Tr[(j + a) * m + j + c];
+            dnorm = fmax(dnorm, fabs(D[a][c]));
+        }
+    // (I (x) A - B^T (x) I) vec X = vec C, unknown X[b][c] at index b + N1 c
+    double G[K][K + 1];
+#pragma unroll
+    for (int e = 0; e < K; ++e)
+#pragma unroll
+        for (int u = 0; u <= K; ++u) G[e][u] = 0.0;
+#pragma unroll
+    for (int a = 0; a < N1; ++a)
+#pragma unroll
+        for (int c = 0; c < N2; ++c) {
+            const int e = a + N1 * c;
+#pragma unroll
+            for (int b = 0; b < N1; ++b) G[e][b + N1 * c] += D[a][b];
+#pragma unroll
+            for (int d = 0; d < N2; ++d) G[e][a + N1 * d] -= D[N1 + d][N1 + c];
+            G[e][K] = D[a][N1 + c];
+        }
+    double gmax = 0.0;
+#pragma unroll
+    for (int e = 0; e < K; ++e)
+#pragma unroll
+        for (int u = 0; u < K; ++u) gmax = fmax(gmax, fabs(G[e][u]));
+    const double smin = fmax(kEps * gmax, 1e-290);
+    // Gaussian elimination with partial pivoting (row exchanges by selects)
+#pragma unroll
+    for (int col = 0; col < K; ++col) {
+#pragma unroll
+        for (int r = col + 1; r < K; ++r)
+            if (fabs(G[r][col]) > fabs(G[col][col])) {
+#pragma unroll
+                for (int u = 0; u <= K; ++u) {
+                    const double t = G[r][u];
+                    G[r][u] = G[col][u];
+                    G[col][u] = t;
+                }
+            }
+        if (fabs(G[col][col]) < smin) G[col][col] = smin;
+#pragma unroll
+        for (int r = col + 1; r < K; ++r) {
+            const double f = G[r][col] / G[col][col];
+#pragma unroll
+            for (int u = col; u <= K; ++u) G[r][u] -= f * G[col][u];
+        }
+    }
+    double x[K];
+#pragma unroll
+    for (int r = K - 1; r >= 0; --r) {
+        double acc = G[r][K];
+#pragma unroll
+        for (int u = r + 1; u < K; ++u) acc -= G[r][u] * x[u];
+        x[r] = acc / G[r][r];
+    }
+    // Householder QR of Y = [-X; I] (NT x N2), Q = H_0 H_1 ...
+    double Y[NT][N2], Q[NT][NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+#pragma unroll
+        for (int c = 0; c < N2; ++c) Y[a][c] = a < N1 ? -x[a + N1 * c] : (a - N1 == c ? 1.0 : 0.0);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) Q[a][c] = a == c ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < N2; ++c) {
+        double sig = 0.0;
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) sig += Y[r][c] * Y[r][c];
+        if (sig == 0.0) continue;
+        const double y0 = Y[c][c];
+        const double rho = sqrt(y0 * y0 + sig);
+        const double al = y0 >= 0.0 ? -rho : rho;
+        const double tau = (al - y0) / al;
+        double v[NT];
+#pragma unroll
+        for (int r = 0; r < NT; ++r) v[r] = r < c ? 0.0 : (r == c ? 1.0 : Y[r][c] / (y0 - al));
+#pragma unroll
+        for (int q = c; q < N2; ++q) {
+            double d = 0.0;
+#pragma unroll
+            for (int r = c; r < NT; ++r) d += v[r] * Y[r][q];
+#pragma unroll
+            for (int r = c; r < NT; ++r) Y[r][q] -= tau * d * v[r];
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            double d = 0.0;
+#pragma unroll
+            for (int r = c; r < NT; ++r) d += Q[a][r] * v[r];
+#pragma unroll
+            for (int r = c; r < NT; ++r) Q[a][r] -= tau * d * v[r];
+        }
+    }
+    // test the swapped block: lower-left N1 x N2 of Q^T D Q must be negligible
+    const double thresh = fmax(20.0 * kEps * dnorm, 1e-290);
+    bool ok = true;
+#pragma unroll
+    for (int a = N2; a < NT; ++a)
+#pragma unroll
+        for (int c = 0; c < N2; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                double dq = 0.0;
+#pragma unroll
+                for (int q = 0; q < NT; ++q) dq += D[r][q] * Q[q][c];
+                t += Q[r][a] * dq;
+            }
+            ok = ok && fabs(t) <= thresh;
+        }
+    __syncthreads();  // every lane has read D
+    if (!ok) return false;
+    for (int c = j + lane; c < m; c += kHT) {  // rows j.. of T: Q^T T
+        double t[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) t[a] = Tr[(j + a) * m + c];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < NT; ++r) acc += Q[r][a] * t[r];
+            Tr[(j + a) * m + c] = acc;
+        }
+    }
+    __syncthreads();
+    for (int r = lane; r < m; r += kHT) {  // columns j.. of T (rows < j + NT) and of Z: T Q, Z Q
+        double t[NT], z[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            t[a] = r < j + NT ? Tr[r * m + j + a] : 0.0;
+            z[a] = Zf[r * m + j + a];
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            double at = 0.0, az = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                at += t[q] * Q[q][a];
+                az += z[q] * Q[q][a];
+            }
+            if (r < j + NT) Tr[r * m + j + a] = at;
+            Zf[r * m + j + a] = az;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int a = N2; a < NT; ++a)
+#pragma unroll
+            for (int c = 0; c < N2; ++c) Tr[(j + a) * m + j + c] = 0.0;
+    }
+    __syncthreads();
+    return true;
+}
+
+__device__ inline bool swap_at(double* Tr, double* Zf, int m, int j, int n1, int n2, int lane) {
+    if (n1 == 1) return n2 == 1 ? swap_blocks<1, 1>(Tr, Zf, m, j, lane) : swap_blocks<1, 2>(Tr, Zf, m, j, lane);
+    return n2 == 1 ? swap_blocks<2, 1>(Tr, Zf, m, j, lane) : swap_blocks<2, 2>(Tr, Zf, m, j, lane);
+}
+
+// Householder reflector P = I - tau v v^T on coordinates 0..len-1 with
+// P x = alpha e_{len-1}, x = hv[0..len-1]; v (v[len-1] = 1) overwrites hv.
+// tau = 0 (P = I, alpha = x[len-1]) when x[0..len-2] = 0.  One lane.
+__device__ inline void house_last(double* hv, int len, double& tau, double& alpha) {
+    const double xl = hv[len - 1];
+    double sig = 0.0;
+    for (int i = 0; i < len - 1; ++i) sig += hv[i] * hv[i];
+    hv[len - 1] = 1.0;
+    if (sig == 0.0) {
+        tau = 0.0;
+        alpha = xl;
+        return;
+    }
+    const double rho = sqrt(xl * xl + sig);
+    alpha = xl >= 0.0 ? -rho : rho;
+    const double u = xl - alpha;
+    for (int i = 0; i < len - 1; ++i) hv[i] /= u;
+    tau = (alpha - xl) / alpha;
+}
+
+// S <- P S P for the leading kp x kp block S of Tr and Z[:, 0:len] <- Z[:, 0:len] P,
+// P the reflector (hv, tau) on coordinates 0..len-1.
+__device__ inline void reflect_both(double* Tr, double* Zf, int m, int kp, int len, const double* hv, double tau,
+                                    int lane) {
+    if (tau != 0.0) {
+        for (int r = lane; r < m; r += kHT) {  // right factor: rows of S and of Z
+            if (r < kp) {
+                double d = 0.0;
+                for (int c = 0; c < len; ++c) d += Tr[r * m + c] * hv[c];
+                d *= tau;
+                for (int c = 0; c < len; ++c) Tr[r * m + c] -= d * hv[c];
+            }
+            double d = 0.0;
+            for (int c = 0; c < len; ++c) d += Zf[r * m + c] * hv[c];
+            d *= tau;
+            for (int c = 0; c < len; ++c) Zf[r * m + c] -= d * hv[c];
+        }
+        __syncthreads();
+        for (int c = lane; c < kp; c += kHT) {  // left factor: columns of S
+            double d = 0.0;
+            for (int r = 0; r < len; ++r) d += hv[r] * Tr[r * m + c];
+            d *= tau;
+            for (int r = 0; r < len; ++r) Tr[r * m + c] -= d * hv[r];
+        }
+    }
+    __syncthreads();
+}
+
+// contract: 0 = analysis only; 1 = contract unless the stop test is met;
+// 2 = contract unconditionally (standalone use).  Skips an instance whose
+// expansion broke down (rr->bd_step set: the host analyses that order).
+// Outputs: mu, res, sel, rr as k_hess_ritz_real; on contraction rr->kept = p,
+// rr->beta = beta', H rewritten ((m+1) x m, zero outside the new H_p and
+// H[p][p-1]) and ksW = W (m x p, column-major).  rr->eig_fail = 2 when the
+// reordering left no room for an expansion (p > m - 1).
+__global__ __launch_bounds__(kHT) void k_ks_contract(const KryDesc* __restrict__ Dv, int m, int k, double tol,
+                                                     int contract) {
+    const KryDesc& dsc = Dv[blockIdx.x];
+    if (!dsc.active) return;
+    RitzResult* __restrict__ rr = dsc.rr;
+    if (rr->bd_step) return;
+    double2* __restrict__ H = dsc.H;
+    const int ldh = dsc.ldh;
+    extern __shared__ double lds[];
+    double* Tr = lds;          // T, m x m row-major
+    double* Zf = lds + m * m;  // Z, m x m row-major
+    __shared__ int blk[kMaxKrylov];
+    __shared__ int order[kMaxKrylov];
+    __shared__ int dupc[kMaxKrylov];
+    __shared__ int keep[kMaxKrylov];
+    __shared__ double ctol[kMaxKrylov];
+    __shared__ double hv[kMaxKrylov];
+    __shared__ double sh_tau, sh_alpha;
+    __shared__ int sh_go, sh_kp;
+    const int lane = threadIdx.x;
+
+    const double beta = H[m + (size_t)ldh * (m - 1)].x;
+    bool bad = !isfinite(beta);
+    for (int e = lane; e < m * m; e += kHT) {
+        const int r = e / m, c = e % m;
+        const double v = (r <= c + 1) ? H[r + (size_t)ldh * c].x : 0.0;
+        bad = bad || !isfinite(v);
+        Tr[e] = v;
+        Zf[e] = r == c ? 1.0 : 0.0;
+    }
+    if (__ballot(bad)) {
+        if (lane == 0) {
+            rr->nonfinite = 1;
+            rr->done = 0;
+            rr->nsel = 0;
+            rr->nconv = 0;
+            rr->eig_fail = 0;
+            rr->iters = 0;
+            rr->kept = 0;
+        }
+        return;
+    }
+    for (int c = lane; c < m; c += kHT) blk[c] = 0;
+    __syncthreads();
+    int total = 0, failed = 0;
+    francis_real<true>(Tr, Zf, blk, m, lane, total, failed);
+    __syncthreads();
+    real_ritz(Tr, blk, Zf + (size_t)(m - 1) * m, m, beta, dsc.mu, dsc.S, dsc.res, lane);
+    __syncthreads();
+    select_wanted(dsc.mu, dsc.res, dsc.sel, rr, ctol, order, dupc, m, k, tol, dsc.dup_rel, dsc.res_floor, failed,
+                  total, lane);
+    __syncthreads();
+    if (lane == 0) {
+        sh_go = (contract == 2 || (contract == 1 && !rr->done)) && !failed;
+        rr->kept = 0;
+        if (sh_go) {  // kept count: |mu| >= 1 - delta, raised to k, lowered to pmax
+            int pd = 0;
+            for (int i = 0; i < m; ++i) pd += cabs(dsc.mu[i]) >= 1.0 - dsc.ks_delta ? 1 : 0;
+            sh_kp = min(max(pd, k), dsc.ks_pmax);
+        }
+    }
+    __syncthreads();
+    if (!sh_go) return;
+    for (int t = lane; t < m; t += kHT) keep[order[t]] = t < sh_kp ? 1 : 0;
+    __syncthreads();
+    if (lane == 0)  // complex pairs are kept whole
+        for (int i = 0; i + 1 < m; ++i)
+            if (blk[i] == 1 && (keep[i] | keep[i + 1])) keep[i] = keep[i + 1] = 1;
+    __syncthreads();
+
+    // reorder: every kept block moves up to the end of the kept region; a
+    // refused swap keeps the blocks it could not pass as well
+    int ks = 0, i = 0;
+    while (i < m) {
+        const int sz = blk[i] == 1 ? 2 : 1;
+        if (keep[i]) {
+            int pos = i;
+            while (pos > ks) {
+                const int sa = blk[pos - 1] == 2 ? 2 : 1;
+                if (!swap_at(Tr, Zf, m, pos - sa, sa, sz, lane)) break;
+                if (lane == 0) {
+                    const int q = pos - sa;
+                    for (int a = 0; a < sz; ++a) {
+                        blk[q + a] = sz == 2 ? 1 + a : 0;
+                        keep[q + a] = 1;
+                    }
+                    for (int a = 0; a < sa; ++a) {
+                        blk[q + sz + a] = sa == 2 ? 1 + a : 0;
+                        keep[q + sz + a] = 0;
+                    }
+                }
+                __syncthreads();
+                pos -= sa;
+            }
+            ks = pos + sz;
+        }
+        i += sz;
+    }
+    const int kp = ks;
+    if (kp > m - 1) {
+        if (lane == 0) rr->eig_fail = 2;
+        return;
+    }
+
+    // Krylov-Schur decomposition of order kp -> Arnoldi form
+    for (int c = lane; c < kp; c += kHT) hv[c] = beta * Zf[(size_t)(m - 1) * m + c];
+    __syncthreads();
+    if (lane == 0) {
+        double tau, al;
+        house_last(hv, kp, tau, al);
+        sh_tau = tau;
+        sh_alpha = al;
+    }
+    __syncthreads();
+    double bnew = sh_alpha;  // b^T P0 = bnew e_kp^T
+    reflect_both(Tr, Zf, m, kp, kp, hv, sh_tau, lane);
+    for (int r0 = kp - 1; r0 >= 2; --r0) {
+        for (int c = lane; c < r0; c += kHT) hv[c] = Tr[r0 * m + c];
+        __syncthreads();
+        if (lane == 0) {
+            double tau, al;
+            house_last(hv, r0, tau, al);
+            sh_tau = tau;
+            sh_alpha = al;
+        }
+        __syncthreads();
+        const double al = sh_alpha;
+        reflect_both(Tr, Zf, m, kp, r0, hv, sh_tau, lane);
+        if (lane == 0) {
+            for (int c = 0; c < r0 - 1; ++c) Tr[r0 * m + c] = 0.0;
+            Tr[r0 * m + r0 - 1] = al;
+        }
+        __syncthreads();
+    }
+    if (bnew < 0.0) {  // similarity with diag(1, ..., 1, -1) makes beta' >= 0
+        bnew = -bnew;
+        for (int c = lane; c < kp - 1; c += kHT) {
+            Tr[(kp - 1) * m + c] = -Tr[(kp - 1) * m + c];
+            Tr[c * m + kp - 1] = -Tr[c * m + kp - 1];
+        }
+        for (int r = lane; r < m; r += kHT) Zf[r * m + kp - 1] = -Zf[r * m + kp - 1];
+        __syncthreads();
+    }
+    for (int e = lane; e < ldh * m; e += kHT) {
+        const int r = e % ldh, c = e / ldh;
+        double v = 0.0;
+        if (c < kp) {
+            if (r < kp && r <= c + 1) v = Tr[r * m + c];
+            else if (r == kp && c == kp - 1) v = bnew;
+        }
+        H[e] = cmk<double2>(v, 0.0);
+    }
+    double* __restrict__ W = dsc.ksW;
+    for (int e = lane; e < m * kp; e += kHT) {
+        const int r = e % m, c = e / m;
+        W[e] = Zf[r * m + c];
+    }
+    if (lane == 0) {
+        rr->kept = kp;
+        rr->beta = bnew;
+    }
+}
+
 }  // namespace
 
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
@@ -945,6 +1404,74 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
             hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
     }
     TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s) {
+    if (m < 2 || m > kMaxKrylov) return fail(TSK_EINVAL, "Krylov-Schur order must be in [2, 96]");
+    static bool attr_set = false;
+    if (!attr_set) {
+        TSK_HIP(hipFuncSetAttribute((const void*)k_ks_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(2 * kMaxKrylov * kMaxKrylov * sizeof(double))));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_ks_contract, dim3(1), dim3(kHT), size_t(2) * m * m * sizeof(double), s, D, m, k, tol,
+                       contract);
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+namespace {
+// Real H (column-major, ldh) into the real parts of the (m+1) x m complex
+// layout the contraction reads, beta at (m, m-1); and the real parts back.
+__global__ void k_pack_real(const double* __restrict__ H, int ldh, int m, double beta, double2* __restrict__ Hc) {
+    for (int e = threadIdx.x; e < (m + 1) * m; e += blockDim.x) {
+        const int r = e % (m + 1), c = e / (m + 1);
+        const double v = r < m ? ((r <= c + 1) ? H[r + size_t(ldh) * c] : 0.0) : (c == m - 1 ? beta : 0.0);
+        Hc[e] = cmk<double2>(v, 0.0);
+    }
+}
+__global__ void k_unpack_real(const double2* __restrict__ Hc, int n, double* __restrict__ out) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) out[e] = Hc[e].x;
+}
+}  // namespace
+
+tsk_status ks_contract_standalone(const double* H, int ldh, int m, double beta, int k, double delta, int pmax,
+                                  void* mu, double* res, double* Hnew, double* W, int* kept, double* beta_new,
+                                  hipStream_t s) {
+    DevBuf Hc, S, sel, rr, dd;
+    TSK_TRY(Hc.ensure(size_t(m + 1) * m * sizeof(double2)));
+    TSK_TRY(S.ensure(size_t(m) * m * sizeof(double2)));
+    TSK_TRY(sel.ensure(size_t(m) * sizeof(int)));
+    TSK_TRY(rr.ensure(sizeof(RitzResult)));
+    TSK_TRY(dd.ensure(sizeof(KryDesc)));
+    KryDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.H = Hc.as<double2>();
+    d.ldh = m + 1;
+    d.S = S.as<double2>();
+    d.mu = static_cast<double2*>(mu);
+    d.res = res;
+    d.sel = sel.as<int>();
+    d.rr = rr.as<RitzResult>();
+    d.active = 1;
+    d.ksW = W;
+    d.ks_delta = delta;
+    d.ks_pmax = pmax;
+    RitzResult r0{};
+    hipLaunchKernelGGL(k_pack_real, dim3(1), dim3(256), 0, s, H, ldh, m, beta, d.H);
+    TSK_HIP(hipMemcpyAsync(rr.ptr, &r0, sizeof(r0), hipMemcpyHostToDevice, s));
+    TSK_HIP(hipMemcpyAsync(dd.ptr, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    TSK_TRY(ks_contract_launch(dd.as<KryDesc>(), m, k, 0.0, 2, s));
+    hipLaunchKernelGGL(k_unpack_real, dim3(1), dim3(256), 0, s, d.H, (m + 1) * m, Hnew);
+    RitzResult h{};
+    TSK_HIP(hipMemcpyAsync(&h, rr.ptr, sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+    TSK_HIP(hipStreamSynchronize(s));
+    if (h.nonfinite) return fail(TSK_ENONFINITE, "H or beta is not finite");
+    if (h.eig_fail) return fail(TSK_EEIG, h.eig_fail == 2 ? "Schur reordering left no room to expand"
+                                                          : "Hessenberg QR did not converge");
+    *kept = h.kept;
+    *beta_new = h.beta;
     return TSK_OK;
 }
 

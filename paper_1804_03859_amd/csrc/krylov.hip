@@ -185,6 +185,7 @@ __global__ void k_finalize(const KryDesc* __restrict__ Dv, int j) {
     d.rr->w_in = win;
     d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
     d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
+    if (d.rr->breakdown && d.rr->bd_step == 0) d.rr->bd_step = j + 1;
 }
 
 template <typename TS>
@@ -248,6 +249,38 @@ __global__ void k_gather(const KryDesc* __restrict__ Dv, int k) {
     out[4 * k + s] = d.res[i];
 }
 
+// Krylov-Schur truncation (Sec. 3.2.2, step 4) of a real basis: Vout_c =
+// sum_{j<m} V_j W[j + m c] for c < kp, and Vout_kp = V_m (v_{p+1} = v_{m+1}).  W
+// (FP64, m x kp, column-major) is staged in LDS by tiles of kRotCols output
+// vectors (blockIdx.y); each thread owns one element index, streams its m
+// coalesced basis entries once per tile and accumulates in FP64.
+constexpr int kRotCols = 16;
+template <typename TS>
+__global__ __launch_bounds__(kBT) void k_rotate(const TS* __restrict__ Vin, TS* __restrict__ Vout,
+                                                const double* __restrict__ W, int64_t n, int64_t ldv, int m, int kp) {
+    __shared__ double Ws[kMaxKrylov * kRotCols];
+    const int c0 = blockIdx.y * kRotCols;
+    for (int e = threadIdx.x; e < m * kRotCols; e += kBT) {
+        const int j = e / kRotCols, c = e % kRotCols;
+        Ws[e] = (c0 + c < kp) ? W[j + size_t(m) * (c0 + c)] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t g = int64_t(blockIdx.x) * kBT + threadIdx.x; g < n; g += int64_t(gridDim.x) * kBT) {
+        double acc[kRotCols];
+#pragma unroll
+        for (int c = 0; c < kRotCols; ++c) acc[c] = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double x = ET<TS>::acc(Vin[j * ldv + g]);
+#pragma unroll
+            for (int c = 0; c < kRotCols; ++c) acc[c] = fma(x, Ws[j * kRotCols + c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kRotCols; ++c)
+            if (c0 + c < kp) Vout[(c0 + c) * ldv + g] = ET<TS>::store(acc[c]);
+        if (blockIdx.y == 0) Vout[kp * ldv + g] = Vin[m * ldv + g];
+    }
+}
+
 inline int grid_for(int64_t n, int cap) {
     int64_t b = (n + kBT - 1) / kBT;
     if (b > cap) b = cap;
@@ -293,6 +326,14 @@ void launch_ritz_vectors(const KryDesc* D, int count, int64_t nmax, int k, hipSt
 void launch_gather(const KryDesc* D, int count, int k, hipStream_t s) {
     hipLaunchKernelGGL(k_gather, dim3(count), dim3(128), 0, s, D, k);
 }
+
+template <typename TS>
+void launch_rotate(const void* Vin, void* Vout, const double* W, int64_t n, int64_t ldv, int m, int kp, hipStream_t s) {
+    hipLaunchKernelGGL(k_rotate<TS>, dim3(grid_for(n, 1024), (kp + kRotCols - 1) / kRotCols), dim3(kBT), 0, s,
+                       static_cast<const TS*>(Vin), static_cast<TS*>(Vout), W, n, ldv, m, kp);
+}
+template void launch_rotate<double>(const void*, void*, const double*, int64_t, int64_t, int, int, hipStream_t);
+template void launch_rotate<float>(const void*, void*, const double*, int64_t, int64_t, int, int, hipStream_t);
 
 #define TSK_INST(TS)                                                                                 \
     template void launch_check_finite<TS>(const KryDesc*, int, int64_t, hipStream_t);               \

@@ -58,6 +58,11 @@ struct KryDesc {
     double dup_rel;     // duplicate width of the wanted-set rule (0 for FP64)
     double res_floor;   // relative residual floor: converged when res <= max(tol, res_floor |mu|)
     double T;           // sampling period (lambda = log(mu)/T)
+    // Krylov-Schur contraction (k_ks_contract): kept-set rule and output
+    double* ksW;        // m x p orthonormal rotation of the basis, column-major (ld m)
+    double ks_delta;    // wanted when |mu| >= 1 - ks_delta
+    int ks_pmax;        // largest order kept
+    int ks_pad;
 };
 
 // Host launchers; TS = double, float (real states) or double2 (complex).
@@ -82,6 +87,10 @@ void launch_scale(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t 
 // ritz[s*n + e] = sum_i V_i[e] Y[s*p + i] for the nsel wanted pairs, p = steps.
 template <typename TS>
 void launch_ritz_vectors(const KryDesc* D, int count, int64_t nmax, int k, hipStream_t s);
+// Krylov-Schur truncation of a real basis (TS = double or float): Vout_c =
+// sum_{j<m} Vin_j W[j + m c] (c < kp), Vout_kp = Vin_m; Vin and Vout distinct.
+template <typename TS>
+void launch_rotate(const void* Vin, void* Vout, const double* W, int64_t n, int64_t ldv, int m, int kp, hipStream_t s);
 // out: mu, lambda = log(mu)/T, residual of the wanted pairs.
 void launch_gather(const KryDesc* D, int count, int k, hipStream_t s);
 

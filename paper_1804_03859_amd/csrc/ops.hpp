@@ -55,6 +55,9 @@ struct ArnoldiWork {
     DevBuf rr;        // RitzResult, kSlots copies
     DevBuf out;       // gathered outputs (mu, lambda, residual)
     DevBuf phys;      // physical field scratch (seeded start vector)
+    DevBuf V2;        // Krylov-Schur: second basis buffer (truncation writes here)
+    DevBuf ksW;       // Krylov-Schur: m x p basis rotation (FP64)
+    void* Vcur = nullptr;  // basis of the last run (V or V2)
     int m = 0, steps = 0;
     int64_t ldv = 0;
     // Owned by the first operator of a batch (the only one for a single run):
@@ -142,6 +145,15 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
                          const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
                          tsk_arnoldi_info* infos);
 
+// Krylov-Schur driver (arnoldi.hip): one real operator; arguments as tsk_krylov_schur.
+tsk_status krylov_schur(Operator* op, int m, int k, double tol, double delta, int pmax, int max_restarts,
+                        const void* v0, uint64_t seed, double* mu_ri, double* lam_ri, double* resid, void* ritz,
+                        tsk_ks_info* info);
+// The contraction on its own (hessenberg.hip); arguments as tsk_ks_contract.
+tsk_status ks_contract_standalone(const double* H, int ldh, int m, double beta, int k, double delta, int pmax,
+                                  void* mu, double* res, double* Hnew, double* W, int* kept, double* beta_new,
+                                  hipStream_t s);
+
 // Device Hessenberg eigensolver + wanted-set selection (hessenberg.hip), one
 // wavefront per instance of the descriptor table (H, scal[2] = beta, scratch).
 // full = true: accumulate all of Z and form every eigenvector (standalone use).
@@ -150,6 +162,10 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
 struct KryDesc;
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
                             bool real_h = false);
+// Krylov-Schur analysis and contraction of the order-m factorisation of the
+// single instance D[0] (real H): contract = 0 analysis only, 1 unless the stop
+// test is met, 2 always.  Results in D[0].rr (kept, beta), H and ksW.
+tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s);
 // Unit Ritz coordinates of the wanted pairs (inverse iteration on H_p): Y[s*p + r].
 // Needs the attribute set by a prior hess_ritz_launch.
 tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s);  // p = steps

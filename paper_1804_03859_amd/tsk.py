@@ -25,6 +25,12 @@ class TskError(RuntimeError):
         self.status = status
 
 
+class KsInfo(C.Structure):
+    _fields_ = [("n_matvec", C.c_int), ("n_restarts", C.c_int), ("n_ritz", C.c_int),
+                ("n_converged", C.c_int), ("status", C.c_int), ("kept_last", C.c_int),
+                ("beta", C.c_double), ("ms_total", C.c_double), ("ms_apply", C.c_double)]
+
+
 class ArnoldiInfo(C.Structure):
     _fields_ = [("n_matvec", C.c_int), ("n_ritz", C.c_int), ("n_converged", C.c_int),
                 ("status", C.c_int), ("beta", C.c_double), ("ms_total", C.c_double),
@@ -62,6 +68,8 @@ def load():
         "tsk_arnoldi": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), P(f64), vp, P(ArnoldiInfo)],
         "tsk_batch_arnoldi": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(f64), P(vp),
                               P(ArnoldiInfo)],
+        "tsk_krylov_schur": [vp, i32, i32, f64, f64, i32, i32, vp, u64, P(f64), P(f64), P(f64), vp, P(KsInfo)],
+        "tsk_ks_contract": [vp, i32, i32, f64, i32, f64, i32, vp, vp, vp, vp, P(i32), P(f64), vp],
         "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
         "tsk_last_basis": [vp, P(vp), P(i64)],
         "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
@@ -100,6 +108,7 @@ def exported_symbols():
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
             "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
+            "tsk_krylov_schur", "tsk_ks_contract",
             "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
@@ -303,6 +312,52 @@ def batch_arnoldi(ops, m, k, tol, v0s=None, seeds=None, want_vectors=False):
             o["X"] = Xs[i][:nr]
         out.append(o)
     return out
+
+
+def krylov_schur(op, m, k, tol, delta=0.1, p_max=0, max_restarts=50, v0=None, seed=0, want_vectors=False):
+    """Run tsk_krylov_schur; returns a dict like ``arnoldi`` plus n_restarts and
+    kept_last."""
+    import numpy as np
+    if v0 is not None:
+        _need(v0, op.n, op.state_dtype, "v0")
+    mu = np.zeros(2 * k)
+    lam = np.zeros(2 * k)
+    res = np.zeros(k)
+    X = None
+    if want_vectors:
+        X = torch.zeros((k, op.n), dtype=torch.complex128, device="cuda")
+    info = KsInfo()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    st = load().tsk_krylov_schur(op.h, m, k, tol, delta, p_max, max_restarts,
+                                 _ptr(v0) if v0 is not None else None, C.c_uint64(seed), pd(mu), pd(lam), pd(res),
+                                 _ptr(X) if X is not None else None, C.byref(info))
+    _check(st)
+    nr = info.n_ritz
+    out = dict(mu=(mu[0::2] + 1j * mu[1::2])[:nr], lam=(lam[0::2] + 1j * lam[1::2])[:nr], res=res[:nr],
+               status=st, n_matvec=info.n_matvec, n_restarts=info.n_restarts, kept_last=info.kept_last,
+               n_ritz=nr, n_converged=info.n_converged, beta=info.beta, ms_total=info.ms_total,
+               ms_apply=info.ms_apply)
+    if X is not None:
+        out["X"] = X[:nr]
+    return out
+
+
+def ks_contract(H, beta, k, delta=0.1, p_max=0, stream=None):
+    """Device Krylov-Schur contraction of an m x m real Hessenberg tensor (cuda).
+    Returns (mu, res, Hnew ((p+1) x p), W (m x p), beta_new)."""
+    m = H.shape[0]
+    if H.dim() != 2 or H.shape[1] != m or not H.is_cuda:
+        raise ValueError("H must be a square CUDA/HIP tensor")
+    Hc = H.to(torch.float64).t().contiguous()  # column-major storage
+    mu = torch.zeros(m, dtype=torch.complex128, device=H.device)
+    res = torch.zeros(m, dtype=torch.float64, device=H.device)
+    Hn = torch.zeros((m, m + 1), dtype=torch.float64, device=H.device)  # column-major (m+1) x m
+    W = torch.zeros((m, m), dtype=torch.float64, device=H.device)     # column-major m x m
+    kept, bnew = C.c_int(), C.c_double()
+    _check(load().tsk_ks_contract(_ptr(Hc), m, m, beta, k, delta, p_max, _ptr(mu), _ptr(res), _ptr(Hn), _ptr(W),
+                                  C.byref(kept), C.byref(bnew), _stream(stream)))
+    p = kept.value
+    return mu, res, Hn.t()[: p + 1, :p], W.t()[:, :p], bnew.value
 
 
 def last_hessenberg(op):

@@ -12,7 +12,7 @@ import torch
 import workloads as W
 from conftest import match_sets
 from oracle.arnoldi import arnoldi as oracle_arnoldi
-from oracle.kolmogorov import Kolmogorov, base_from_streamfunction
+from oracle.kolmogorov import Kolmogorov, base_from_streamfunction, galerkin_sinusoidal_blocks
 from oracle.krylov_schur import kept_count, krylov_schur as oracle_ks
 
 pytestmark = pytest.mark.gpu
@@ -113,9 +113,20 @@ def test_general_base_run_matches_oracle_restart_by_restart(tsk, m):
     assert match_sets(_fold(r["lam"]), _fold(o["lam"])) <= 1e-8
 
 
+def _distinct(lam, tol=1e-7):
+    out = []
+    for z in sorted(lam, key=lambda z: -z.real):
+        if all(abs(z - w) > tol for w in out):
+            out.append(z)
+    return np.array(out)
+
+
 def test_kolmogorov_run_matches_oracle(tsk):
-    # the x-translation symmetry makes the leading eigenvalues double; the second
-    # copies enter through rounding, so the contraction sizes may differ by one
+    # The x-translation symmetry makes every real eigenvalue with kx != 0 double.
+    # Its second copy enters the Krylov space only through rounding, and
+    # restarts amplify it, so a run may resolve both copies (two of the k slots)
+    # or one: compare the distinct leading values, and check every value
+    # against the dense Galerkin spectrum.
     N, m, k = 32, 24, 6
     print(f"ks kolmogorov N={N} m={m}", flush=True)
     op, ref = _kolmo(tsk, N)
@@ -125,7 +136,14 @@ def test_kolmogorov_run_matches_oracle(tsk):
                   T=ref.T)
     assert r["status"] == o["status"] == 0
     assert abs(r["n_matvec"] - o["n_matvec"]) <= m
-    assert match_sets(r["lam"], o["lam"]) <= 1e-8
+    dg, do = _distinct(r["lam"]), _distinct(o["lam"])
+    n = min(len(dg), len(do))
+    assert n >= k // 2
+    assert np.max(np.abs(dg[:n] - do[:n])) <= 1e-8
+    blocks = galerkin_sinusoidal_blocks(N, 0.5, 20.0)
+    ev = np.concatenate([np.linalg.eigvals(A) for _, A in blocks.values()])
+    for lam in r["lam"]:
+        assert np.min(np.abs(ev - lam)) <= 5e-8
 
 
 def test_without_contraction_equals_arnoldi_at_order_m(tsk):

@@ -23,6 +23,9 @@ arXiv:1804.03859, that it follows):
 * ``krylov_schur`` -- Krylov-Schur restart (Sec. 3.2.2, after Stewart 2001):
                      ordered real Schur form of the Krylov matrix, truncation to
                      the wanted part, re-expansion by Arnoldi steps.
+* ``optimal``     -- adjoint propagators (discrete transposes of the Kolmogorov
+                     and Ginzburg-Landau steppers) and the optimal perturbation:
+                     Lanczos on M^dagger M (Sec. 2.3.1 SVD formulation, Sec. 3.3.2).
 * ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
                      definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
 * ``mlp``         -- start-vector network (not in the paper): FP64 forward,

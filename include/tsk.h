@@ -144,6 +144,37 @@ tsk_status tsk_to_physical(tsk_op op, const void* state_dev, void* phys_dev);
  * in device memory; they may not alias. */
 tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev);
 
+/* y = M^dagger x: the adjoint propagator, the transpose (conjugate transpose for
+ * complex states) of the discrete propagator of tsk_apply in the state's
+ * Euclidean inner product (Sec. 2.2: for the Euclidean inner product the
+ * adjoint is the conjugate transpose; Sec. 3.3.2: M^dagger is one backward
+ * integration of the adjoint system).  Navier-Stokes operators: each IF-RK4
+ * step transposed stage by stage; parallel base flows only (TSK_EINVAL after
+ * tsk_set_base_flow).  Ginzburg-Landau: Crank-Nicolson on L_h^H.  Same
+ * layout, stream and aliasing rule as tsk_apply. */
+tsk_status tsk_apply_adjoint(tsk_op op, const void* x_dev, void* y_dev);
+
+/* Optimal perturbation (Sec. 2.3.1, SVD formulation; Sec. 3.3.2): the k largest
+ * singular values sigma of M = exp(A T) by the Lanczos iteration on the
+ * symmetric M^dagger M.  Each step is one forward and one adjoint integration,
+ * classical Gram-Schmidt twice against every previous vector (full
+ * reorthogonalisation), and a device symmetric tridiagonal QR for the Ritz
+ * values theta = sigma^2.  Wanted set, residual (|beta e_m^T y| of the
+ * M^dagger M eigenpair), tolerance and stop rule as tsk_arnoldi.  The optimal
+ * gain over T is sigma_1^2.
+ *   m, k, tol, v0_dev, seed: as tsk_arnoldi (1 <= k <= m <= 96).
+ *   sigma:    host, k doubles, descending (the wanted order).
+ *   resid:    host, k doubles.
+ *   vecs_dev: dev or NULL: the k right singular vectors (optimal initial
+ *             conditions), unit norm, each n complex128 (imaginary part zero
+ *             for real operators), vector-major; the responses are M x = sigma u.
+ *   info:     host or NULL; n_matvec counts Lanczos steps (two integrations each).
+ * Returns TSK_OK, TSK_NOT_CONVERGED or TSK_BREAKDOWN with outputs written, or a
+ * negative status with nothing written (TSK_EINVAL when the operator has no
+ * adjoint). */
+tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed,
+                                    double* sigma, double* resid, void* vecs_dev, tsk_arnoldi_info* info);
+
 /* Arnoldi with classical Gram-Schmidt applied twice (Sec. 3.2.1, Algorithm 1),
  * Ritz pairs from a device-side Hessenberg QR after every matvec, stop when the
  * k wanted pairs have |beta e_m^T y| <= tol (Sec. 3.2.2), or after m matvecs,

@@ -182,6 +182,30 @@ tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev) {
     })
 }
 
+tsk_status tsk_apply_adjoint(tsk_op op, const void* x_dev, void* y_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!x_dev || !y_dev) return fail(TSK_EINVAL, "null buffer");
+        if (x_dev == y_dev) return fail(TSK_EINVAL, "apply_adjoint: input and output must not alias");
+        return op->op->apply_adjoint(x_dev, y_dev);
+    })
+}
+
+tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed,
+                                    double* sigma, double* resid, void* vecs_dev, tsk_arnoldi_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        Operator* o = op->op.get();
+        std::vector<double> mu(2 * size_t(std::max(k, 1)));
+        const tsk_status st =
+            arnoldi_batch(&o, 1, m, k, tol, &v0_dev, &seed, mu.data(), nullptr, resid, &vecs_dev, info, true);
+        if (st < 0) return st;
+        if (sigma)
+            for (int q = 0; q < k; ++q) sigma[q] = std::sqrt(std::max(mu[2 * size_t(q)], 0.0));
+        return st;
+    })
+}
+
 tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed, double* mu_ri,
                        double* lambda_ri, double* resid, void* ritz_dev, tsk_arnoldi_info* info) {
     TSK_GUARD({

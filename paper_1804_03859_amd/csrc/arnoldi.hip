@@ -203,10 +203,14 @@ void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, 
     launch_scale<TS>(Dt, count, nmax, j, s);
 }
 
+// svd = false: Arnoldi on M (Algorithm 1).  svd = true: Lanczos on M^dagger M
+// (Sec. 3.3.2): each step is a forward then an adjoint integration, the Ritz
+// analysis is the symmetric tridiagonal solver (the same CGS2 against every
+// previous vector serves as full reorthogonalisation).
 template <typename TS>
 tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                      const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                     tsk_arnoldi_info* infos) {
+                     tsk_arnoldi_info* infos, bool svd) {
     auto t0 = std::chrono::steady_clock::now();
     Operator* lead = ops[0];
     const hipStream_t s = lead->stream;
@@ -220,6 +224,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     int nblk_max = 0;
     for (int i = 0; i < count; ++i) {
         TSK_TRY(make_desc<TS>(ops[i], m, k, NS, (ritz && ritz[i]) ? ritz[i] : nullptr, Dh[i]));
+        if (svd) TSK_TRY(ops[i]->aw.tmp.ensure(ops[i]->state_bytes()));
         nmax = std::max(nmax, ops[i]->n);
         nblk_max = std::max(nblk_max, Dh[i].nblk);
     }
@@ -258,12 +263,20 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     KolmoBatchPtr kb;
     bool all_kolmo = true;
     for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && kolmo_parallel(ops[i]);
-    if (all_kolmo) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
+    if (all_kolmo && !svd) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
     std::vector<Outcome> oc(count);
     auto matvec = [&](int j) -> tsk_status {
         if (kb) return kolmo_batch_matvec(kb.get(), j, s);
-        for (int i = 0; i < count; ++i)
-            if (!oc[i].done) TSK_TRY(ops[i]->apply(static_cast<TS*>(Dh[i].V) + j * Dh[i].ldv, Dh[i].w));
+        for (int i = 0; i < count; ++i) {
+            if (oc[i].done) continue;
+            const TS* vj = static_cast<TS*>(Dh[i].V) + j * Dh[i].ldv;
+            if (svd) {  // M^dagger M v_j: forward, then adjoint integration
+                TSK_TRY(ops[i]->apply(vj, ops[i]->aw.tmp.ptr));
+                TSK_TRY(ops[i]->apply_adjoint(ops[i]->aw.tmp.ptr, Dh[i].w));
+            } else {
+                TSK_TRY(ops[i]->apply(vj, Dh[i].w));
+            }
+        }
         return TSK_OK;
     };
 
@@ -288,7 +301,10 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         }
         const hipStream_t st = L.side[t];
         TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[t], 0));
-        TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st, kRealH));
+        if (svd)
+            TSK_TRY(tridiag_ritz_launch(Dt, count, p, k < p ? k : p, tol, st));
+        else
+            TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st, kRealH));
         hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, Dt, count,
                            L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
         TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,
@@ -357,6 +373,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         Dh[i] = Dall[size_t(final_slot[i]) * count + i];  // the analysis of the final step
         Dh[i].steps = oc[i].steps;
         Dh[i].active = 1;
+        if (svd) Dh[i].Y = Dh[i].S;  // the tridiagonal solver left the unit Ritz coordinates there
         ops[i]->aw.steps = oc[i].steps;
         pmax = std::max(pmax, oc[i].steps);
     }
@@ -364,7 +381,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     bool any_ritz = false;
     for (int i = 0; i < count; ++i) any_ritz = any_ritz || Dh[i].ritz;
     if (any_ritz) {
-        TSK_TRY(ritz_coords_launch(D, count, pmax, k, s));
+        if (!svd) TSK_TRY(ritz_coords_launch(D, count, pmax, k, s));
         launch_ritz_vectors<TS>(D, count, nmax, k, s);
     }
     launch_gather(D, count, k, s);
@@ -540,7 +557,7 @@ tsk_status krylov_schur_t(Operator* op, int m, int k, double tol, double delta, 
 
 tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                          const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                         tsk_arnoldi_info* infos) {
+                         tsk_arnoldi_info* infos, bool svd) {
     if (count < 1 || !ops) return fail(TSK_EINVAL, "empty batch");
     if (k < 1 || m < k || m > kMaxKrylov) return fail(TSK_EINVAL, "need 1 <= k <= m <= 96");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TSK_EINVAL, "tol must be finite and >= 0");
@@ -552,14 +569,16 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
         if (ops[i]->stream != ops[0]->stream) return fail(TSK_EINVAL, "batch members must share one stream");
         for (int q = 0; q < i; ++q)
             if (ops[q] == ops[i]) return fail(TSK_EINVAL, "an operator appears twice in the batch");
+        if (svd && !ops[i]->has_adjoint())
+            return fail(TSK_EINVAL, std::string("no adjoint propagator for this ") + ops[i]->name() + " operator");
     }
     switch (ops[0]->kind) {
         case StateKind::Complex64x2:
-            return arnoldi_t<double2>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
+            return arnoldi_t<double2>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
         case StateKind::Real64:
-            return arnoldi_t<double>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
+            return arnoldi_t<double>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
         case StateKind::Real32:
-            return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos);
+            return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
     }
     return fail(TSK_EINVAL, "unknown state kind");
 }

@@ -76,12 +76,19 @@ __global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict
     if (act) uout[i] = u;
 }
 
+// Tables of one Crank-Nicolson propagator: the explicit stencil (main diagonal
+// per node, constant sub/super coefficients) and the cyclic-reduction
+// multipliers of the implicit matrix.
+struct CnTables {
+    double2 rsub{}, rsup{};
+    DevBuf tab;  // rhs_main[n] | alpha[levels*n] | gamma[levels*n] | binv[n]
+};
+
 struct CgleOp final : Operator {
     int nn = 0;
     double half_width = 0.0;
     int levels = 0, nsteps = 0;
-    double2 rsub{}, rsup{};
-    DevBuf tab;  // rhs_main[n] | alpha[levels*n] | gamma[levels*n] | binv[n]
+    CnTables fwd, adj;  // L_h and its conjugate transpose (the adjoint propagator)
 
     const char* name() const override { return "cgle1d"; }
     int64_t physical_reals() const override { return 2 * int64_t(nn); }
@@ -99,18 +106,36 @@ struct CgleOp final : Operator {
         const cd nu(U, 2.0 * c_u), gam(1.0, c_d);
         const cd sub = gam / (dx * dx) + nu / (2.0 * dx);
         const cd sup = gam / (dx * dx) - nu / (2.0 * dx);
-        const double h = 0.5 * dt;
-        std::vector<cd> mainv(n_), a(n_), b(n_), c(n_);
+        std::vector<cd> mainv(n_), mainh(n_);
         for (int j = 0; j < n_; ++j) {
             double x = -half_width + dx * (j + 1);
             double mux = (mu0 - c_u * c_u) + mu2 * x * x / 2.0;
             mainv[j] = -2.0 * gam / (dx * dx) + mux;
+            mainh[j] = std::conj(mainv[j]);
+        }
+        int L = 0;
+        while ((1 << L) < n_) ++L;
+        // L_h^H: conjugated main diagonal, sub and super diagonals swapped and conjugated
+        TSK_TRY(build(fwd, sub, sup, mainv, 0.5 * dt, L));
+        TSK_TRY(build(adj, std::conj(sup), std::conj(sub), mainh, 0.5 * dt, L));
+        levels = L;
+        nsteps = nsi;
+        T = TT;
+        params_set = true;
+        return TSK_OK;
+    }
+
+    // Crank-Nicolson tables of the tridiagonal (sub, mainv, sup), h = dt/2.
+    tsk_status build(CnTables& tb, std::complex<double> sub, std::complex<double> sup,
+                     const std::vector<std::complex<double>>& mainv, double h, int L) {
+        using cd = std::complex<double>;
+        const int n_ = nn;
+        std::vector<cd> a(n_), b(n_), c(n_);
+        for (int j = 0; j < n_; ++j) {
             a[j] = j > 0 ? -h * sub : cd(0.0);
             b[j] = 1.0 - h * mainv[j];
             c[j] = j + 1 < n_ ? -h * sup : cd(0.0);
         }
-        int L = 0;
-        while ((1 << L) < n_) ++L;
         std::vector<cd> al(size_t(L) * n_), ga(size_t(L) * n_);
         for (int l = 0, s = 1; l < L; ++l, s <<= 1) {
             std::vector<cd> a2(n_), b2(n_), c2(n_);
@@ -131,29 +156,31 @@ struct CgleOp final : Operator {
         for (const cd& v : al) host[o++] = cmk<double2>(v.real(), v.imag());
         for (const cd& v : ga) host[o++] = cmk<double2>(v.real(), v.imag());
         for (int j = 0; j < n_; ++j) { cd r = 1.0 / b[j]; host[o++] = cmk<double2>(r.real(), r.imag()); }
-        TSK_TRY(tab.ensure(host.size() * sizeof(double2)));
-        TSK_HIP(hipMemcpy(tab.ptr, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice));
+        TSK_TRY(tb.tab.ensure(host.size() * sizeof(double2)));
+        TSK_HIP(hipMemcpy(tb.tab.ptr, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice));
         cd rs = h * sub, rp = h * sup;
-        rsub = cmk<double2>(rs.real(), rs.imag());
-        rsup = cmk<double2>(rp.real(), rp.imag());
-        levels = L;
-        nsteps = nsi;
-        T = TT;
-        params_set = true;
+        tb.rsub = cmk<double2>(rs.real(), rs.imag());
+        tb.rsup = cmk<double2>(rp.real(), rp.imag());
         return TSK_OK;
     }
 
-    tsk_status apply(const void* x, void* y) override {
+    tsk_status run(const CnTables& tb, const void* x, void* y) {
         if (!ready()) return fail(TSK_ESTATE, "CGLE parameters not set");
-        const double2* t = tab.as<double2>();
+        if (x == y) return fail(TSK_EINVAL, "input and output must not alias");
+        const double2* t = tb.tab.as<double2>();
         const int n_ = nn;
         const int threads = (n_ + kWave - 1) / kWave * kWave;
         hipLaunchKernelGGL(k_cgle_cn, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
-                           static_cast<double2*>(y), t, rsub, rsup, t + n_, t + n_ + size_t(levels) * n_,
+                           static_cast<double2*>(y), t, tb.rsub, tb.rsup, t + n_, t + n_ + size_t(levels) * n_,
                            t + n_ + 2 * size_t(levels) * n_, n_, levels, nsteps);
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
+    tsk_status apply(const void* x, void* y) override { return run(fwd, x, y); }
+    // M^H: Crank-Nicolson with L_h^H (the two factors of a step commute, so this is
+    // the conjugate transpose of the forward propagator).
+    tsk_status apply_adjoint(const void* x, void* y) override { return run(adj, x, y); }
+    bool has_adjoint() const override { return true; }
     tsk_status from_physical(const void* phys, void* state) override {
         TSK_HIP(hipMemcpyAsync(state, phys, state_bytes(), hipMemcpyDeviceToDevice, stream));
         return TSK_OK;

@@ -240,4 +240,172 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     }
 }
 
+// ---- the transposed column stepper (discrete adjoint) -----------------------------------
+// One Lawson step w+ = S w is a polynomial in the diagonal factors E and the
+// column advection operator Nc s = (1/N) mask F[nu F^-1(i g1 s) + oy F^-1(i g2 s)]
+// (F the forward DFT, F^-1 the unnormalised inverse, g1, g2 zero off the kept
+// modes).  In the real Euclidean inner product of the state a complex-linear
+// column operator transposes to its conjugate transpose, so
+//     Nc^H t = (1/N) [-i g1 F(nu F^-1 t) - i g2 F(oy F^-1 t)]:
+// one inverse and one (PROP) or two forward transforms, the products moved to
+// the other side of the transforms.  The step transposes stage by stage in
+// reverse order (z the adjoint state):
+//     s3 = Nc^H(h/6 z),               acc = E1 z + E1 s3
+//     s2 = Nc^H(h/3 Eh z + h Eh s3),  acc += Eh s2
+//     s1 = Nc^H(h/3 Eh z + h/2 s2),   acc += Eh s1
+//     s0 = Nc^H(h/6 E1 z + h/2 Eh s1), z+ = acc + s0.
+// M^T is S^T applied T/dt times (the steps are identical).  One column per
+// wavefront; the kx = 0 column is diagonal and identical to the forward one.
+template <typename real, int N, bool PROP>
+__global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const ColTask* __restrict__ tasks,
+                                                       const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    using G = Geo<N>;
+    using PL = ColPlan<N>;
+    constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
+    constexpr int NF = PROP ? 1 : 2;  // forward transforms per stage
+    static_assert(PL::NBL == 1, "one edge butterfly per lane");
+    const ColTask tk = tasks[blockIdx.x];
+    const ColInst<real>& I = one;
+    const real* __restrict__ xin = I.xbase;
+    real* __restrict__ yout = I.y;
+    const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
+    const int nsteps = I.nsteps;
+    const int lane = threadIdx.x;
+    const int kx = tk.kx;
+
+    if (kx == 0) {
+        for (int q = lane; q < M; q += kWave) {
+            const double jy = q + 1;
+            const real E1 = real(exp(-jy * jy * dt / Re));
+            real re = xin[2 * q], im = xin[2 * q + 1];
+            for (int st = 0; st < nsteps; ++st) { re *= E1; im *= E1; }
+            yout[2 * q] = re;
+            yout[2 * q + 1] = im;
+        }
+        return;
+    }
+
+    constexpr int LP = padded_len<N>();
+    __shared__ C sA[2][LP], sB[2][LP], sT[N];
+    for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
+    C* Ai[1] = {sA[0]};
+    C* Bi[1] = {sB[0]};
+    C* Af[NF];
+    C* Bf[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        Af[c] = col_result_in_a<N>() ? sB[c] : sA[c];
+        Bf[c] = col_result_in_a<N>() ? sA[c] : sB[c];
+    }
+
+    const bool act = lane < NB;
+    real E1[RE], Eh[RE], g1[RE], g2[RE], nu[RE], oy[RE];
+    C z[RE], acc[RE], sprev[RE];
+    unsigned keep = 0;
+    const double kxv = alpha * kx;
+    const real* xs = xin + G::seg(kx);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        const int pos = lane + r * NB;
+        const int jy = pos <= N / 2 ? pos : pos - N;
+        const bool kp = act && jy >= -M && jy <= M;
+        keep |= kp ? (1u << r) : 0u;
+        nu[r] = act ? I.negU[pos] : real(0);
+        oy[r] = (!PROP && act) ? I.dOdy[pos] : real(0);
+        const double K2 = kxv * kxv + double(jy) * jy;
+        E1[r] = kp ? real(exp(-K2 * dt / Re)) : real(0);
+        Eh[r] = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
+        // the 1/N of the forward transform folded into the output factors
+        g1[r] = kp ? (PROP ? real(kxv * (1.0 - cprop / K2) / N) : real(kxv / N)) : real(0);
+        g2[r] = kp ? real(kxv / K2 / N) : real(0);
+        const int q = jy + M;
+        z[r] = kp ? cmk<C>(xs[2 * q], xs[2 * q + 1]) : cmk<C>(real(0), real(0));
+        acc[r] = sprev[r] = cmk<C>(real(0), real(0));
+    }
+    __syncthreads();
+
+    const real h6 = real(dt / 6.0), h3 = real(dt / 3.0), h2 = real(0.5 * dt), hh = real(dt);
+    constexpr bool kTwReg = N <= 256;
+    ColTw<N, C> twr;
+    if constexpr (kTwReg) twr.load(sT, lane);
+
+    for (int st = 0; st < nsteps; ++st) {
+#pragma unroll 1
+        for (int stage = 0; stage < 4; ++stage) {
+            // stage input t (kept modes only)
+            C v[1][1][RE];
+            if (stage == 0) {
+#pragma unroll
+                for (int r = 0; r < RE; ++r) v[0][0][r] = cmk<C>(h6 * z[r].x, h6 * z[r].y);
+            } else if (stage == 1) {
+#pragma unroll
+                for (int r = 0; r < RE; ++r)
+                    v[0][0][r] = cmk<C>(Eh[r] * (h3 * z[r].x + hh * sprev[r].x), Eh[r] * (h3 * z[r].y + hh * sprev[r].y));
+            } else if (stage == 2) {
+#pragma unroll
+                for (int r = 0; r < RE; ++r)
+                    v[0][0][r] = cmk<C>(h3 * Eh[r] * z[r].x + h2 * sprev[r].x, h3 * Eh[r] * z[r].y + h2 * sprev[r].y);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RE; ++r)
+                    v[0][0][r] = cmk<C>(h6 * E1[r] * z[r].x + h2 * Eh[r] * sprev[r].x,
+                                        h6 * E1[r] * z[r].y + h2 * Eh[r] * sprev[r].y);
+            }
+            if constexpr (kTwReg)
+                col_fft_mr<N, +1, 1>(v, Ai, Bi, twr, lane);
+            else
+                col_fft_m<N, +1, 1>(v, Ai, Bi, sT, lane);
+            C pr[NF][1][RE];
+#pragma unroll
+            for (int r = 0; r < RE; ++r) {
+                pr[0][0][r] = cmk<C>(nu[r] * v[0][0][r].x, nu[r] * v[0][0][r].y);
+                if constexpr (!PROP) pr[NF - 1][0][r] = cmk<C>(oy[r] * v[0][0][r].x, oy[r] * v[0][0][r].y);
+            }
+            if constexpr (kTwReg)
+                col_fft_mr<N, -1, NF>(pr, Af, Bf, twr, lane);
+            else
+                col_fft_m<N, -1, NF>(pr, Af, Bf, sT, lane);
+            // s = -i g1 P1 - i g2 P2 (zero off the kept modes)
+            C so[RE];
+#pragma unroll
+            for (int r = 0; r < RE; ++r) {
+                C t = cmk<C>(g1[r] * pr[0][0][r].y, -g1[r] * pr[0][0][r].x);
+                if constexpr (!PROP) {
+                    t.x += g2[r] * pr[NF - 1][0][r].y;
+                    t.y -= g2[r] * pr[NF - 1][0][r].x;
+                }
+                so[r] = t;
+            }
+            if (stage == 0) {
+#pragma unroll
+                for (int r = 0; r < RE; ++r)
+                    acc[r] = cmk<C>(E1[r] * (z[r].x + so[r].x), E1[r] * (z[r].y + so[r].y));
+            } else if (stage == 3) {
+#pragma unroll
+                for (int r = 0; r < RE; ++r) z[r] = cmk<C>(acc[r].x + so[r].x, acc[r].y + so[r].y);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RE; ++r) {
+                    acc[r].x += Eh[r] * so[r].x;
+                    acc[r].y += Eh[r] * so[r].y;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RE; ++r) sprev[r] = so[r];
+        }
+    }
+    real* ys = yout + G::seg(kx);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        if ((keep >> r) & 1u) {
+            const int pos = lane + r * NB;
+            const int jy = pos <= N / 2 ? pos : pos - N;
+            const int q = jy + M;
+            ys[2 * q] = z[r].x;
+            ys[2 * q + 1] = z[r].y;
+        }
+    }
+}
+
 }  // namespace tsk

@@ -1377,6 +1377,133 @@ __global__ __launch_bounds__(kHT) void k_ks_contract(const KryDesc* __restrict__
     }
 }
 
+
+// ---- symmetric tridiagonal matrices (Lanczos on M^dagger M) ------------------------------
+// Ritz analysis of the Lanczos tridiagonal T_p: diagonal d_i = H[i][i], off-diagonal
+// e_i = H[i+1][i] (the Lanczos beta), residual scale beta_p = H[p][p-1] (Sec. 3.3.2:
+// for the symmetric M^dagger M the Hessenberg matrix becomes tridiagonal).  Implicit
+// symmetric QR with the Wilkinson shift (Golub & Van Loan, "Matrix Computations",
+// Algorithms 8.3.2-8.3.3): deflation on negligible e_i, each sweep a chase of Givens
+// rotations down the active block.  The chase is a scalar recurrence, so lane 0
+// runs it with d and e in LDS and records the rotations; every lane then applies
+// them to its rows of Z (all eigenvectors, p x p in LDS).  Outputs as the Hessenberg
+// solver: mu = (theta, 0), residual |beta_p Z[p-1][i]|, wanted set; and the unit Ritz
+// coordinates of the wanted values (columns of Z) in S[s*p + r], so the Ritz vectors
+// of the final step need no inverse iteration.
+__global__ __launch_bounds__(kHT) void k_tridiag_ritz(const KryDesc* __restrict__ Dv, int p, int k, double tol) {
+    const KryDesc& dsc = Dv[blockIdx.x];
+    if (!dsc.active) return;
+    const double2* __restrict__ H = dsc.H;
+    const int ldh = dsc.ldh;
+    RitzResult* __restrict__ rr = dsc.rr;
+    extern __shared__ double Zs[];  // p x p row-major
+    __shared__ double d[kMaxKrylov], e[kMaxKrylov], rc[kMaxKrylov], rs[kMaxKrylov];
+    __shared__ int order[kMaxKrylov];
+    __shared__ int dupc[kMaxKrylov];
+    __shared__ double ctol[kMaxKrylov];
+    __shared__ int sh_l;
+    const int lane = threadIdx.x;
+
+    const double beta = H[p + (size_t)ldh * (p - 1)].x;
+    bool bad = !isfinite(beta);
+    for (int i = lane; i < p; i += kHT) {
+        d[i] = H[i + (size_t)ldh * i].x;
+        e[i] = i + 1 < p ? H[i + 1 + (size_t)ldh * i].x : 0.0;
+        bad = bad || !isfinite(d[i]) || !isfinite(e[i]);
+    }
+    if (__ballot(bad)) {
+        if (lane == 0) {
+            rr->nonfinite = 1;
+            rr->done = 0;
+            rr->nsel = 0;
+            rr->nconv = 0;
+            rr->eig_fail = 0;
+            rr->iters = 0;
+        }
+        return;
+    }
+    for (int t = lane; t < p * p; t += kHT) Zs[t] = (t / p == t % p) ? 1.0 : 0.0;
+    __syncthreads();
+
+    int hi = p - 1, total = 0, failed = 0;
+    const int itmax = 30 * (p > 10 ? p : 10);
+    while (hi > 0) {
+        if (lane == 0) {  // active block [l, hi]: e[l..hi-1] not negligible
+            int l = hi;
+            while (l > 0) {
+                if (fabs(e[l - 1]) <= kEps * (fabs(d[l - 1]) + fabs(d[l]))) {
+                    e[l - 1] = 0.0;
+                    break;
+                }
+                --l;
+            }
+            sh_l = l;
+        }
+        __syncthreads();
+        const int l = sh_l;
+        if (l == hi) {
+            --hi;
+            continue;
+        }
+        if (++total > itmax) {
+            failed = 1;
+            break;
+        }
+        if (lane == 0) {
+            // Wilkinson shift: the eigenvalue of the trailing 2x2 block closer to d[hi]
+            const double a = d[hi - 1], b = e[hi - 1], c = d[hi];
+            const double del = 0.5 * (a - c);
+            const double den = del + (del >= 0.0 ? 1.0 : -1.0) * sqrt(del * del + b * b);
+            const double mu = den != 0.0 ? c - b * b / den : c;
+            double x = d[l] - mu, z = e[l], bulge = 0.0;
+            for (int kk = l; kk < hi; ++kk) {
+                if (kk > l) {
+                    x = e[kk - 1];
+                    z = bulge;
+                }
+                const double r = sqrt(x * x + z * z);
+                const double cs = r > 0.0 ? x / r : 1.0, sn = r > 0.0 ? z / r : 0.0;
+                if (kk > l) e[kk - 1] = r;
+                const double dk = d[kk], ek = e[kk], dk1 = d[kk + 1];
+                d[kk] = cs * cs * dk + 2.0 * cs * sn * ek + sn * sn * dk1;
+                d[kk + 1] = sn * sn * dk - 2.0 * cs * sn * ek + cs * cs * dk1;
+                e[kk] = cs * sn * (dk1 - dk) + (cs * cs - sn * sn) * ek;
+                if (kk + 1 < hi) {
+                    bulge = sn * e[kk + 1];
+                    e[kk + 1] = cs * e[kk + 1];
+                }
+                rc[kk] = cs;
+                rs[kk] = sn;
+            }
+        }
+        __syncthreads();
+        for (int r = lane; r < p; r += kHT) {  // Z <- Z G^T, rotation by rotation
+            double* zr = Zs + r * p;
+            for (int kk = l; kk < hi; ++kk) {
+                const double u = zr[kk], v = zr[kk + 1];
+                zr[kk] = rc[kk] * u + rs[kk] * v;
+                zr[kk + 1] = -rs[kk] * u + rc[kk] * v;
+            }
+        }
+        __syncthreads();
+    }
+    double2* __restrict__ mu = dsc.mu;
+    double* __restrict__ res = dsc.res;
+    for (int i = lane; i < p; i += kHT) {
+        mu[i] = cmk<double2>(d[i], 0.0);
+        res[i] = fabs(beta) * fabs(Zs[(p - 1) * p + i]);
+    }
+    __syncthreads();
+    select_wanted(mu, res, dsc.sel, rr, ctol, order, dupc, p, k, tol, dsc.dup_rel, dsc.res_floor, failed, total,
+                  lane);
+    __syncthreads();
+    const int nsel = rr->nsel;
+    for (int t = lane; t < nsel * p; t += kHT) {
+        const int s = t / p, r = t % p;
+        dsc.S[t] = cmk<double2>(Zs[r * p + dsc.sel[s]], 0.0);
+    }
+}
+
 }  // namespace
 
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
@@ -1403,6 +1530,19 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
         else
             hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
     }
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s) {
+    if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Lanczos order must be in [1, 96]");
+    static bool attr_set = false;
+    if (!attr_set) {
+        TSK_HIP(hipFuncSetAttribute((const void*)k_tridiag_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(kMaxKrylov * kMaxKrylov * sizeof(double))));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_tridiag_ritz, dim3(count), dim3(kHT), size_t(p) * p * sizeof(double), s, D, p, k, tol);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }

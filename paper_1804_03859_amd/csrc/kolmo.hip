@@ -240,6 +240,15 @@ template <typename real, int N> struct KK {
             hipLaunchKernelGGL((k_colstep<real, N, false, COLS>), dim3(ntasks), dim3(kWave), 0, s, one, insts, tasks,
                                static_cast<const C*>(tw), jstep);
     }
+    static void colstep_adj(const ColInst<real>& one, const ColTask* tasks, int ntasks, bool prop, const void* tw,
+                            hipStream_t s) {
+        if (prop)
+            hipLaunchKernelGGL((k_colstep_adj<real, N, true>), dim3(ntasks), dim3(kWave), 0, s, one, tasks,
+                               static_cast<const C*>(tw));
+        else
+            hipLaunchKernelGGL((k_colstep_adj<real, N, false>), dim3(ntasks), dim3(kWave), 0, s, one, tasks,
+                               static_cast<const C*>(tw));
+    }
     static void colstep(const ColInst<real>& one, const ColInst<real>* insts, const ColTask* tasks, int ntasks,
                         bool prop, int cols, const void* tw, int jstep, hipStream_t s) {
         if constexpr (N <= kMaxColsPairN) {
@@ -280,6 +289,15 @@ void dispatch_colstep(int N, const ColInst<real>& one, const ColInst<real>* inst
                       bool prop, int cols, const void* tw, int jstep, hipStream_t s) {
     switch (N) {
 #define X(n) case n: KK<real, n>::colstep(one, insts, tasks, ntasks, prop, cols, tw, jstep, s); break;
+        TSK_KOLMO_SIZES(X)
+#undef X
+    }
+}
+template <typename real>
+void dispatch_colstep_adj(int N, const ColInst<real>& one, const ColTask* tasks, int ntasks, bool prop, const void* tw,
+                          hipStream_t s) {
+    switch (N) {
+#define X(n) case n: KK<real, n>::colstep_adj(one, tasks, ntasks, prop, tw, s); break;
         TSK_KOLMO_SIZES(X)
 #undef X
     }
@@ -385,6 +403,22 @@ struct KolmoOp final : Operator {
         if (cols == 0)
             TSK_TRY(column_choice(TuneKey{N, prec == TSK_FP32, prop, size_bucket(M + 1)}, stream, launch, &cols));
         launch(cols);
+        TSK_HIP(hipGetLastError());
+        return TSK_OK;
+    }
+    bool has_adjoint() const override { return gen == nullptr; }
+    // Transposed propagator (k_colstep_adj): parallel base flows, one column per
+    // wavefront (task list of 1-column tasks).
+    tsk_status apply_adjoint(const void* x, void* y) override {
+        if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
+        if (x == y) return fail(TSK_EINVAL, "apply_adjoint: input and output must not alias");
+        if (gen) return fail(TSK_EINVAL, "the adjoint propagator needs a parallel base flow");
+        if (prec == TSK_FP32)
+            dispatch_colstep_adj<float>(N, inst<float>(x, 0, y, nullptr), tasks[1].as<ColTask>(), ntasks[1], prop,
+                                        tw.ptr, stream);
+        else
+            dispatch_colstep_adj<double>(N, inst<double>(x, 0, y, nullptr), tasks[1].as<ColTask>(), ntasks[1], prop,
+                                         tw.ptr, stream);
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }

@@ -55,6 +55,7 @@ struct ArnoldiWork {
     DevBuf rr;        // RitzResult, kSlots copies
     DevBuf out;       // gathered outputs (mu, lambda, residual)
     DevBuf phys;      // physical field scratch (seeded start vector)
+    DevBuf tmp;       // Lanczos on M^dagger M: the forward integration's output
     DevBuf V2;        // Krylov-Schur: second basis buffer (truncation writes here)
     DevBuf ksW;       // Krylov-Schur: m x p basis rotation (FP64)
     void* Vcur = nullptr;  // basis of the last run (V or V2)
@@ -97,6 +98,12 @@ struct Operator {
 
     virtual const char* name() const = 0;
     virtual tsk_status apply(const void* x, void* y) = 0;
+    // y = M^dagger x, the transpose (conjugate transpose) of the discrete propagator
+    // in the state's Euclidean inner product; operators without one fail.
+    virtual tsk_status apply_adjoint(const void* /*x*/, void* /*y*/) {
+        return fail(TSK_EINVAL, std::string("no adjoint propagator for ") + name());
+    }
+    virtual bool has_adjoint() const { return false; }
     virtual tsk_status from_physical(const void* phys, void* state) = 0;
     virtual tsk_status to_physical(const void* state, void* phys) = 0;
     // Number of reals in the physical field (complex fields count 2 per value).
@@ -141,9 +148,11 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s);
 // seed i), outputs at mu_ri + 2k i, lam_ri + 2k i, resid + k i, ritz[i]
 // (nullable array / entry), infos[i].  Returns the first negative status of a
 // global failure; per-instance outcomes are in infos[i].status.
+// svd = true: Lanczos on M^dagger M instead (every operator needs an adjoint);
+// mu_ri then receives (sigma^2, 0).
 tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                          const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                         tsk_arnoldi_info* infos);
+                         tsk_arnoldi_info* infos, bool svd = false);
 
 // Krylov-Schur driver (arnoldi.hip): one real operator; arguments as tsk_krylov_schur.
 tsk_status krylov_schur(Operator* op, int m, int k, double tol, double delta, int pmax, int max_restarts,
@@ -162,6 +171,10 @@ tsk_status ks_contract_standalone(const double* H, int ldh, int m, double beta, 
 struct KryDesc;
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
                             bool real_h = false);
+// Lanczos Ritz analysis (symmetric tridiagonal T_p from H's diagonal and
+// subdiagonal): as hess_ritz_launch, plus the unit Ritz coordinates of the
+// wanted values in S[s*p + r].
+tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s);
 // Krylov-Schur analysis and contraction of the order-m factorisation of the
 // single instance D[0] (real H): contract = 0 analysis only, 1 unless the stop
 // test is met, 2 always.  Results in D[0].rr (kept, beta), H and ksW.

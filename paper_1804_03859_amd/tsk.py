@@ -68,6 +68,8 @@ def load():
         "tsk_arnoldi": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), P(f64), vp, P(ArnoldiInfo)],
         "tsk_batch_arnoldi": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(f64), P(vp),
                               P(ArnoldiInfo)],
+        "tsk_apply_adjoint": [vp, vp, vp],
+        "tsk_optimal_perturbation": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), vp, P(ArnoldiInfo)],
         "tsk_krylov_schur": [vp, i32, i32, f64, f64, i32, i32, vp, u64, P(f64), P(f64), P(f64), vp, P(KsInfo)],
         "tsk_ks_contract": [vp, i32, i32, f64, i32, f64, i32, vp, vp, vp, vp, P(i32), P(f64), vp],
         "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
@@ -108,7 +110,7 @@ def exported_symbols():
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
             "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
-            "tsk_krylov_schur", "tsk_ks_contract",
+            "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
             "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
@@ -311,6 +313,36 @@ def batch_arnoldi(ops, m, k, tol, v0s=None, seeds=None, want_vectors=False):
         if Xs:
             o["X"] = Xs[i][:nr]
         out.append(o)
+    return out
+
+
+def apply_adjoint(op, x, y):
+    """y = M^dagger x (device state tensors of the operator's dtype)."""
+    _need(x, op.n, op.state_dtype, "x")
+    _need(y, op.n, op.state_dtype, "y")
+    _check(load().tsk_apply_adjoint(op.h, _ptr(x), _ptr(y)))
+
+
+def optimal_perturbation(op, m, k, tol, v0=None, seed=0, want_vectors=False):
+    """Run tsk_optimal_perturbation; returns a dict with sigma, gain (= sigma^2),
+    res, status, n_steps, n_converged, ms_total, ms_apply and X (right singular
+    vectors, complex128 k x n on the device) when want_vectors."""
+    import numpy as np
+    if v0 is not None:
+        _need(v0, op.n, op.state_dtype, "v0")
+    sig = np.zeros(k)
+    res = np.zeros(k)
+    X = torch.zeros((k, op.n), dtype=torch.complex128, device="cuda") if want_vectors else None
+    info = ArnoldiInfo()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    st = load().tsk_optimal_perturbation(op.h, m, k, tol, _ptr(v0) if v0 is not None else None, C.c_uint64(seed),
+                                         pd(sig), pd(res), _ptr(X) if X is not None else None, C.byref(info))
+    _check(st)
+    nr = info.n_ritz
+    out = dict(sigma=sig[:nr], gain=sig[:nr] ** 2, res=res[:nr], status=st, n_steps=info.n_matvec, n_ritz=nr,
+               n_converged=info.n_converged, beta=info.beta, ms_total=info.ms_total, ms_apply=info.ms_apply)
+    if X is not None:
+        out["X"] = X[:nr]
     return out
 
 

@@ -26,6 +26,9 @@ arXiv:1804.03859, that it follows):
 * ``optimal``     -- adjoint propagators (discrete transposes of the Kolmogorov
                      and Ginzburg-Landau steppers) and the optimal perturbation:
                      Lanczos on M^dagger M (Sec. 2.3.1 SVD formulation, Sec. 3.3.2).
+* ``fixedpoint``  -- nonlinear forced Navier-Stokes stepper and the fixed-point
+                     solvers on it: selective frequency damping, recursive
+                     projection method, BoostConv (Sec. 3.1).
 * ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
                      definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
 * ``mlp``         -- start-vector network (not in the paper): FP64 forward,

@@ -106,6 +106,20 @@ def random_matrix(n, seed, complex_=False):
     return A
 
 
+def random_forcing_field(N, alpha, max_j=2, seed=0, amplitude=0.1):
+    """Random band-limited real field on the N x N grid ([y, x], x in [0, 2 pi/alpha),
+    y in [0, 2 pi)): sum of modes |jx|, |jy| <= max_j with seeded complex
+    coefficients, no mean.  Used as an extra vorticity forcing."""
+    modes = random_base_modes(max_j, seed, amplitude)
+    x = 2 * np.pi * np.arange(N) / (alpha * N)
+    y = 2 * np.pi * np.arange(N) / N
+    X, Y = np.meshgrid(x, y)
+    f = np.zeros((N, N), complex)
+    for (jx, jy), c in modes.items():
+        f += c * np.exp(1j * (alpha * jx * X + jy * Y))
+    return f.real
+
+
 def random_base_modes(max_j=2, seed=0, amplitude=0.3):
     """Random band-limited base streamfunction: coefficients for (jx, jy) with
     |jx|, |jy| <= max_j, conjugate-symmetric so the field is real, no mean."""

@@ -267,6 +267,62 @@ tsk_status tsk_ks_contract(const double* H_dev, int ldh, int m, double beta, int
                            void* mu_dev, double* res_dev, double* Hnew_dev, double* W_dev, int* kept,
                            double* beta_new, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Fixed points (Sec. 3.1).  A Navier-Stokes operator also carries the
+ * nonlinear forced equation
+ *     d omega/dt + (u + U0) d_x omega + v d_y omega = Re^-1 lap omega + f
+ * on the same grid, state space and time scheme as its linearized matvec
+ * (u = d_y psi, v = -d_x psi, -lap psi = omega; U0 a uniform drift along x).
+ * f = -Re^-1 lap omega_lam holds the laminar Kolmogorov flow omega_lam =
+ * -n cos(n y) steady; an optional extra forcing field makes the steady state
+ * two-dimensional.  The discrete-time system is x_{k+1} = G(x_k), G = T/dt
+ * steps.  On success every solver below leaves the operator's base flow set to
+ * the fixed point found (tsk_set_base_from_state), so tsk_arnoldi then gives
+ * its stability (the paper's fixed point -> eigenvalues workflow).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int status;              /* same value as returned                                     */
+    int iterations;          /* outer iterations (SFD: residual checks)                     */
+    int64_t time_steps;      /* nonlinear time steps taken                                  */
+    int basis_dim;           /* RPM: unstable basis size p; BoostConv: pairs in the history */
+    double residual;         /* last residual: ||G(x) - x|| (SFD: ||step(x) - x|| / dt)     */
+    double ms_total;         /* wall time of the call, host clock                           */
+} tsk_fp_info;
+
+/* Set up the nonlinear equation (after tsk_set_params_kolmo; re-derived when
+ * the parameters change).  n_forcing in [1, (N-1)/3]; extra_forcing: host N*N
+ * physical field ([y][x], FP64) projected on the state space, or NULL. */
+tsk_status tsk_set_nonlinear(tsk_op op, int n_forcing, double U0, const double* extra_forcing);
+/* The packed laminar state omega_lam (dev). */
+tsk_status tsk_laminar_state(tsk_op op, void* x_dev);
+/* y = nsteps Lawson IF-RK4 steps of the nonlinear equation from x (dev states;
+ * nsteps = 0: T/dt steps, i.e. G(x)).  x and y may not alias. */
+tsk_status tsk_nonlinear_step(tsk_op op, const void* x_dev, void* y_dev, int nsteps);
+/* The operator's (general two-dimensional) base flow becomes the state x: its
+ * grid fields (u + U0, v, grad omega) computed on the device.  tsk_apply then
+ * is the Jacobian of the nonlinear stepper's right-hand side about x. */
+tsk_status tsk_set_base_from_state(tsk_op op, const void* x_dev);
+/* Selective frequency damping (Sec. 3.1.1; Akervik et al. 2006): the extended
+ * system X' = F(X) - chi (X - Y), Y' = (X - Y)/Delta, Strang-split per time step
+ * (exact coupling over dt/2, one nonlinear step, coupling over dt/2).  x_dev:
+ * start (in), result (out).  Every check_every steps the residual
+ * ||step(X) - X|| / dt is taken (history in hist[max_checks] if not NULL); stop
+ * when <= tol.  It cannot quench non-oscillating instabilities. */
+tsk_status tsk_sfd(tsk_op op, void* x_dev, double chi, double delta, int check_every, double tol, int max_checks,
+                   double* hist, tsk_fp_info* info);
+/* Recursive projection method (Sec. 3.1.2; Shroff & Keller 1993): U, H = U^T M U
+ * from an m-step Arnoldi factorisation of the Jacobian about the start (started
+ * from the initial residual) contracted to its Ritz values |mu| >= 1 - delta (at
+ * least k) by the Krylov-Schur kernel; then x~ <- G(x~) - U U^T r + U (I - H)^-1 U^T r,
+ * r = G(x~) - x~, until ||r|| <= tol (history in hist[max_iter]).  1 <= k,
+ * k + 2 <= m <= 96. */
+tsk_status tsk_rpm(tsk_op op, void* x_dev, int m, int k, double delta, double tol, int max_iter, double* hist,
+                   tsk_fp_info* info);
+/* BoostConv (Sec. 3.1.3; Citro et al. 2017): with the corrections xi_j and the
+ * residual decrements r_j - r_{j+1} of the last m iterations (1 <= m <= 96),
+ * c = (Y^T Y)^-1 Y^T r, x~ <- x~ + r + (X - Y) c, until ||r|| <= tol. */
+tsk_status tsk_boostconv(tsk_op op, void* x_dev, int m, double tol, int max_iter, double* hist, tsk_fp_info* info);
+
 /* Last Arnoldi run, for inspection: H ((m+1) x m complex128, column-major,
  * leading dimension m+1, zero beyond the steps taken) copied to host, and the
  * basis pointer (device, (steps+1) vectors of the state type, vector-major,

@@ -47,7 +47,8 @@ Readings (where the paper leaves a choice open):
   before the iterations; I - H is solved densely.
 * BoostConv: X holds the applied corrections xi_j = x~_{j+1} - x~_j, Y the
   residual decrements r_j - r_{j+1}, r_j = G(x~_j) - x~_j, for the last m
-  iterations; Y^+ r by the normal equations (Y^T Y) c = Y^T r (lstsq).
+  iterations; c = Y^+ r from the normal equations (Y^T Y) c = Y^T r, the
+  pseudoinverse of a full-column-rank Y.
 * Convergence: ||r_k|| <= tol (the residual of the discrete-time fixed point,
   Euclidean state norm).
 
@@ -237,7 +238,7 @@ def boostconv(G, x0, m, tol, max_iter, norm=np.linalg.norm):
         if Xs:
             X = np.stack(Xs, axis=1)
             Y = np.stack(Ys, axis=1)
-            c = np.linalg.lstsq(Y, r, rcond=None)[0]
+            c = np.linalg.solve(Y.T @ Y, Y.T @ r)  # Y^+ r for full column rank
             xi = r - Y @ c + X @ c
         else:
             xi = r

@@ -206,6 +206,61 @@ tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const v
     })
 }
 
+tsk_status tsk_set_nonlinear(tsk_op op, int n_forcing, double U0, const double* extra_forcing) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_nonlinear(op->op.get(), n_forcing, U0, extra_forcing);
+    })
+}
+
+tsk_status tsk_laminar_state(tsk_op op, void* x_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!x_dev) return fail(TSK_EINVAL, "null buffer");
+        return kolmo_laminar_state(op->op.get(), x_dev);
+    })
+}
+
+tsk_status tsk_nonlinear_step(tsk_op op, const void* x_dev, void* y_dev, int nsteps) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!x_dev || !y_dev) return fail(TSK_EINVAL, "null buffer");
+        if (x_dev == y_dev) return fail(TSK_EINVAL, "nonlinear_step: input and output must not alias");
+        return kolmo_nonlinear_step(op->op.get(), x_dev, y_dev, nsteps);
+    })
+}
+
+tsk_status tsk_set_base_from_state(tsk_op op, const void* x_dev) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!x_dev) return fail(TSK_EINVAL, "null buffer");
+        return kolmo_base_from_state(op->op.get(), x_dev);
+    })
+}
+
+tsk_status tsk_sfd(tsk_op op, void* x_dev, double chi, double delta, int check_every, double tol, int max_checks,
+                   double* hist, tsk_fp_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return fixed_point_sfd(op->op.get(), x_dev, chi, delta, check_every, tol, max_checks, hist, info);
+    })
+}
+
+tsk_status tsk_rpm(tsk_op op, void* x_dev, int m, int k, double delta, double tol, int max_iter, double* hist,
+                   tsk_fp_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return fixed_point_rpm(op->op.get(), x_dev, m, k, delta, tol, max_iter, hist, info);
+    })
+}
+
+tsk_status tsk_boostconv(tsk_op op, void* x_dev, int m, double tol, int max_iter, double* hist, tsk_fp_info* info) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return fixed_point_boostconv(op->op.get(), x_dev, m, tol, max_iter, hist, info);
+    })
+}
+
 tsk_status tsk_arnoldi(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed, double* mu_ri,
                        double* lambda_ri, double* resid, void* ritz_dev, tsk_arnoldi_info* info) {
     TSK_GUARD({

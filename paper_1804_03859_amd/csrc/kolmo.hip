@@ -317,6 +317,32 @@ template <typename real> void dispatch_inv(int N, const KolmoLaunch& a) {
     }
 }
 
+// f = (K^2/Re) lam + ex over the packed entries (ex may be null): the forcing
+// -Re^-1 lap omega_lam that holds the laminar flow steady, plus an extra field.
+template <typename real>
+__global__ void k_forcing(const real* __restrict__ lam, const real* __restrict__ ex, real* __restrict__ f, int M,
+                          double alpha, double Re) {
+    const int NM = 2 * M + 1;
+    const int ne = M + M * NM;  // complex entries
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        int kx, jy;
+        if (e < M) {
+            kx = 0;
+            jy = e + 1;
+        } else {
+            kx = 1 + (e - M) / NM;
+            jy = (e - M) % NM - M;
+        }
+        const double kxv = alpha * kx;
+        const double s = (kxv * kxv + double(jy) * jy) / Re;
+        for (int c = 0; c < 2; ++c) {
+            double v = s * double(lam[2 * e + c]);
+            if (ex) v += double(ex[2 * e + c]);
+            f[2 * e + c] = real(v);
+        }
+    }
+}
+
 struct KolmoOp final : Operator {
     int N = 0, M = 0;
     tsk_precision prec = TSK_FP64;
@@ -329,7 +355,18 @@ struct KolmoOp final : Operator {
     int ntasks[3] = {0, 0, 0};
     int force_cols = 0;  // 0: autotuned
     Gen2D* gen = nullptr;  // general two-dimensional base flow (kolmo2d.hip), else parallel
-    ~KolmoOp() override { gen2d_free(gen); }
+    // nonlinear forced equation (fixed-point solvers): pipeline workspace, packed
+    // forcing and laminar state, drift, and the inputs the forcing is made from
+    Gen2D* nlw = nullptr;
+    DevBuf fvec, lam, physbuf;
+    double U0 = 0.0;
+    int nforce = 0;
+    std::vector<double> extra;  // extra forcing field (physical, N*N), empty if none
+    bool nl_set = false;
+    ~KolmoOp() override {
+        gen2d_free(gen);
+        gen2d_free(nlw);
+    }
 
     const char* name() const override { return "kolmo2d"; }
     int64_t physical_reals() const override { return int64_t(N) * N; }
@@ -422,6 +459,56 @@ struct KolmoOp final : Operator {
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
+    // physical N*N field (host FP64) -> packed state (device) through physbuf
+    tsk_status pack_host_field(const std::vector<double>& f, void* state) {
+        TSK_TRY(upload_real(physbuf, f));
+        return from_physical(physbuf.ptr, state);
+    }
+    // forcing from nforce, Re and the extra field (needs Re)
+    tsk_status make_forcing() {
+        const size_t sb = state_bytes();
+        std::vector<double> w(size_t(N) * N);
+        const double pi = 3.14159265358979323846264338327950288;
+        for (int l = 0; l < N; ++l) {
+            const double y = 2.0 * pi * l / N;
+            for (int i = 0; i < N; ++i) w[size_t(l) * N + i] = -nforce * std::cos(nforce * y);
+        }
+        TSK_TRY(lam.ensure(sb));
+        TSK_TRY(fvec.ensure(sb));
+        TSK_TRY(pack_host_field(w, lam.ptr));
+        DevBuf exs;
+        if (!extra.empty()) {
+            TSK_TRY(exs.ensure(sb));
+            TSK_TRY(pack_host_field(extra, exs.ptr));
+        }
+        if (prec == TSK_FP32)
+            hipLaunchKernelGGL(k_forcing<float>, dim3(64), dim3(256), 0, stream, lam.as<float>(),
+                               extra.empty() ? nullptr : exs.as<float>(), fvec.as<float>(), M, alpha, Re);
+        else
+            hipLaunchKernelGGL(k_forcing<double>, dim3(64), dim3(256), 0, stream, lam.as<double>(),
+                               extra.empty() ? nullptr : exs.as<double>(), fvec.as<double>(), M, alpha, Re);
+        TSK_HIP(hipGetLastError());
+        TSK_HIP(hipStreamSynchronize(stream));  // exs is freed on return
+        return TSK_OK;
+    }
+    tsk_status nonlinear_step(const void* x, void* y, int steps) {
+        if (!nl_set) return fail(TSK_ESTATE, "nonlinear equation not set (tsk_set_nonlinear)");
+        return gen2d_nonlinear(nlw, alpha, Re, dt, steps > 0 ? steps : nsteps, U0, fvec.ptr, x, y, tw.ptr, stream);
+    }
+    // the general base flow becomes the state x (its grid fields)
+    tsk_status base_from_state(const void* x) {
+        Gen2D* g = nullptr;
+        TSK_TRY(gen2d_create(N, prec == TSK_FP32, nullptr, nullptr, nullptr, nullptr, &g));
+        const tsk_status st = gen2d_fields(g, alpha, nl_set ? U0 : 0.0, x, tw.ptr, stream);
+        if (st != TSK_OK) {
+            gen2d_free(g);
+            return st;
+        }
+        gen2d_free(gen);
+        gen = g;
+        base_set = true;
+        return TSK_OK;
+    }
     tsk_status from_physical(const void* phys, void* state) override {
         KolmoLaunch a = args(phys, state);
         if (prec == TSK_FP32) dispatch_fwd<float>(N, a);
@@ -472,7 +559,62 @@ tsk_status kolmo_set_params(Operator* op, double Re, double alpha, double dt, do
     k->nsteps = nsi;
     k->T = T;
     k->params_set = true;
+    if (k->nl_set) TSK_TRY(k->make_forcing());
     return TSK_OK;
+}
+
+tsk_status kolmo_set_nonlinear(Operator* op, int n_forcing, double U0, const double* extra) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!k->params_set) return fail(TSK_ESTATE, "set Re, alpha, dt and T first");
+    if (n_forcing < 1 || n_forcing > k->M) return fail(TSK_EINVAL, "forcing wavenumber must be in [1, (N-1)/3]");
+    if (!std::isfinite(U0)) return fail(TSK_EINVAL, "drift must be finite");
+    const size_t nn = size_t(k->N) * k->N;
+    if (extra)
+        for (size_t i = 0; i < nn; ++i)
+            if (!std::isfinite(extra[i])) return fail(TSK_ENONFINITE, "non-finite extra forcing");
+    if (!k->nlw) TSK_TRY(gen2d_create(k->N, k->prec == TSK_FP32, nullptr, nullptr, nullptr, nullptr, &k->nlw));
+    k->nforce = n_forcing;
+    k->U0 = U0;
+    if (extra)
+        k->extra.assign(extra, extra + nn);
+    else
+        k->extra.clear();
+    TSK_TRY(k->make_forcing());
+    k->nl_set = true;
+    return TSK_OK;
+}
+
+tsk_status kolmo_nonlinear_step(Operator* op, const void* x, void* y, int nsteps) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (nsteps < 0) return fail(TSK_EINVAL, "nsteps must be >= 0");
+    return k->nonlinear_step(x, y, nsteps);
+}
+
+tsk_status kolmo_laminar_state(Operator* op, void* x) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!k->nl_set) return fail(TSK_ESTATE, "nonlinear equation not set (tsk_set_nonlinear)");
+    TSK_HIP(hipMemcpyAsync(x, k->lam.ptr, k->state_bytes(), hipMemcpyDeviceToDevice, k->stream));
+    return TSK_OK;
+}
+
+tsk_status kolmo_base_from_state(Operator* op, const void* x) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (!k->params_set) return fail(TSK_ESTATE, "set Re, alpha, dt and T first");
+    return k->base_from_state(x);
+}
+
+double kolmo_dt(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k ? k->dt : 0.0;
+}
+
+int kolmo_nsteps(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k ? k->nsteps : 0;
 }
 
 tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* dOdy) {

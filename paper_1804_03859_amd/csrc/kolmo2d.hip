@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
                                                  real* __restrict__ Acc, const cplx<real>* __restrict__ Q,
                                                  cplx<real>* __restrict__ Gf, real* __restrict__ yout,
                                                  const cplx<real>* __restrict__ twg, double alpha, double Re,
-                                                 double dt, int q, int mode) {
+                                                 double dt, int q, int mode, const real* __restrict__ fvec) {
     using C = cplx<real>;
     using G = Geo2<N>;
     constexpr int M = G::M, MC = G::MC, NM = G::NM;
@@ -93,7 +93,11 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
         for (int e = tid; e < nq; e += kGT) {
             const int jy = kx == 0 ? e + 1 : e - M;
             const C xr = X[jy < 0 ? jy + N : jy];
-            const double nx = scl * double(xr.x), ny = scl * double(xr.y);
+            double nx = scl * double(xr.x), ny = scl * double(xr.y);
+            if (fvec) {  // steady forcing (packed units), nonlinear equation
+                nx += double(fvec[base + 2 * e]);
+                ny += double(fvec[base + 2 * e + 1]);
+            }
             const double K2 = kxv * kxv + double(jy) * jy;
             const double e1 = exp(-K2 * dt / Re), eh = exp(-K2 * (0.5 * dt) / Re);
             const int64_t o = base + 2 * e;
@@ -156,11 +160,18 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
 // 2r + pr inverse-transforms field pair pr ((d_x w, d_y w) or (u, v), packed as
 // a + i b) of row y0 + r; the workgroup then forms the products of both rows
 // and transforms them forward as one complex sequence P0 + i P1.
-template <typename real, int N>
-__global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ Gf, const real* __restrict__ U,
-                                                 const real* __restrict__ V, const real* __restrict__ Ox,
-                                                 const real* __restrict__ Oy, cplx<real>* __restrict__ Q,
-                                                 const cplx<real>* __restrict__ twg) {
+//   ROW_LIN:    P = U d_x w + V d_y w + u Omega_x + v Omega_y (base fields U..Oy);
+//   ROW_NL:     P = (u + U0) d_x w + v d_y w of the state itself (nonlinear
+//               advection; the derived fields carry the packing factor sqrt(2),
+//               so their product is divided by sqrt(2) once);
+//   ROW_FIELDS: no product: the physical grid fields (u + U0, v, d_x w, d_y w)
+//               of the state go to U, V, Ox, Oy (the state as a base flow).
+enum RowMode { ROW_LIN = 0, ROW_NL = 1, ROW_FIELDS = 2 };
+template <typename real, int N, int RM>
+__global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ Gf, real* __restrict__ U,
+                                                 real* __restrict__ V, real* __restrict__ Ox, real* __restrict__ Oy,
+                                                 cplx<real>* __restrict__ Q, const cplx<real>* __restrict__ twg,
+                                                 double U0) {
     using C = cplx<real>;
     using G = Geo2<N>;
     constexpr int M = G::M, MC = G::MC;
@@ -196,10 +207,32 @@ __global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ 
     const C* R01 = in_a ? sA[1] : sB[1];  // row 0, (u, v)
     const C* R10 = in_a ? sA[2] : sB[2];  // row 1, (d_x w, d_y w)
     const C* R11 = in_a ? sA[3] : sB[3];  // row 1, (u, v)
+    if constexpr (RM == ROW_FIELDS) {
+        const real is2 = real(0.70710678118654752440);  // packing factor sqrt(2) removed
+        for (int x = tid; x < N; x += kGT) {
+            const size_t o0 = size_t(y0) * N + x, o1 = o0 + N;
+            U[o0] = is2 * R01[x].x + real(U0);
+            V[o0] = is2 * R01[x].y;
+            Ox[o0] = is2 * R00[x].x;
+            Oy[o0] = is2 * R00[x].y;
+            U[o1] = is2 * R11[x].x + real(U0);
+            V[o1] = is2 * R11[x].y;
+            Ox[o1] = is2 * R10[x].x;
+            Oy[o1] = is2 * R10[x].y;
+        }
+        return;
+    }
     for (int x = tid; x < N; x += kGT) {
         const size_t o0 = size_t(y0) * N + x, o1 = o0 + N;
-        const real p0 = U[o0] * R00[x].x + V[o0] * R00[x].y + Ox[o0] * R01[x].x + Oy[o0] * R01[x].y;
-        const real p1 = U[o1] * R10[x].x + V[o1] * R10[x].y + Ox[o1] * R11[x].x + Oy[o1] * R11[x].y;
+        real p0, p1;
+        if constexpr (RM == ROW_NL) {
+            const real is2 = real(0.70710678118654752440), u0 = real(U0);
+            p0 = is2 * (R01[x].x * R00[x].x + R01[x].y * R00[x].y) + u0 * R00[x].x;
+            p1 = is2 * (R11[x].x * R10[x].x + R11[x].y * R10[x].y) + u0 * R10[x].x;
+        } else {
+            p0 = U[o0] * R00[x].x + V[o0] * R00[x].y + Ox[o0] * R01[x].x + Oy[o0] * R01[x].y;
+            p1 = U[o1] * R10[x].x + V[o1] * R10[x].y + Ox[o1] * R11[x].x + Oy[o1] * R11[x].y;
+        }
         z[x] = cmk<C>(p0, p1);
     }
     __syncthreads();
@@ -211,33 +244,40 @@ __global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ 
     }
 }
 
-template <typename real, int N>
-void gen_matvec(const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, const real* U,
-                const real* V, const real* Ox, const real* Oy, const void* tw, double alpha, double Re, double dt,
-                int nsteps, hipStream_t s) {
+// One run of the pipeline.  ROW_LIN / ROW_NL: nsteps Lawson steps of the
+// linearized / nonlinear (forcing fvec, drift U0) equation from x into y.
+// ROW_FIELDS: the grid fields of x into U, V, Ox, Oy (nsteps ignored).
+template <typename real, int N, int RM>
+void gen_run(const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, real* U, real* V, real* Ox,
+             real* Oy, const void* tw, double alpha, double Re, double dt, int nsteps, double U0, const real* fvec,
+             hipStream_t s) {
     using C = cplx<real>;
     constexpr int MC = Geo2<N>::MC;
     static_assert(N % 2 == 0, "row pairs");
     const C* twc = static_cast<const C*>(tw);
     hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc, Q, Gf,
-                       static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST));
+                       static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST), fvec);
+    if constexpr (RM == ROW_FIELDS) {
+        hipLaunchKernelGGL((k_gen_row<real, N, RM>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc, U0);
+        return;
+    }
     for (int st = 0; st < nsteps; ++st)
         for (int q = 0; q < 4; ++q) {
-            hipLaunchKernelGGL((k_gen_row<real, N>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc);
+            hipLaunchKernelGGL((k_gen_row<real, N, RM>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc, U0);
             const int mode = (st == nsteps - 1 && q == 3) ? GEN_LAST : GEN_STAGE;
             hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc,
-                               Q, Gf, static_cast<real*>(y), twc, alpha, Re, dt, q, mode);
+                               Q, Gf, static_cast<real*>(y), twc, alpha, Re, dt, q, mode, fvec);
         }
 }
 
-template <typename real>
-void gen_dispatch(int N, const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, const real* U,
-                  const real* V, const real* Ox, const real* Oy, const void* tw, double alpha, double Re, double dt,
-                  int nsteps, hipStream_t s) {
+template <typename real, int RM>
+void gen_dispatch(int N, const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<real>* Gf, real* U, real* V,
+                  real* Ox, real* Oy, const void* tw, double alpha, double Re, double dt, int nsteps, double U0,
+                  const real* fvec, hipStream_t s) {
     switch (N) {
 #define X(n)                                                                                                      \
     case n:                                                                                                       \
-        gen_matvec<real, n>(x, y, W, Acc, Q, Gf, U, V, Ox, Oy, tw, alpha, Re, dt, nsteps, s);                     \
+        gen_run<real, n, RM>(x, y, W, Acc, Q, Gf, U, V, Ox, Oy, tw, alpha, Re, dt, nsteps, U0, fvec, s);          \
         break;
         X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 #undef X
@@ -264,6 +304,7 @@ tsk_status gen2d_create(int N, bool fp32, const double* U, const double* V, cons
     DevBuf* dst[4] = {&g->U, &g->V, &g->Ox, &g->Oy};
     for (int f = 0; f < 4; ++f) {
         TSK_TRY(dst[f]->ensure(nn * rb));
+        if (!src[f]) continue;  // filled on the device (gen2d_fields)
         if (fp32) {
             std::vector<float> h(src[f], src[f] + nn);
             TSK_HIP(hipMemcpy(dst[f]->ptr, h.data(), nn * 4, hipMemcpyHostToDevice));
@@ -281,18 +322,36 @@ tsk_status gen2d_create(int N, bool fp32, const double* U, const double* V, cons
 
 void gen2d_free(Gen2D* g) { delete g; }
 
-tsk_status gen2d_apply(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
-                       const void* tw, hipStream_t s) {
+namespace {
+template <int RM>
+tsk_status gen_go(Gen2D* g, double alpha, double Re, double dt, int nsteps, double U0, const void* fvec, const void* x,
+                  void* y, const void* tw, hipStream_t s) {
     if (g->fp32)
-        gen_dispatch<float>(g->N, x, y, g->W.as<float>(), g->Acc.as<float>(), g->Q.as<float2>(), g->G.as<float2>(),
-                            g->U.as<float>(), g->V.as<float>(), g->Ox.as<float>(), g->Oy.as<float>(), tw, alpha, Re,
-                            dt, nsteps, s);
+        gen_dispatch<float, RM>(g->N, x, y, g->W.as<float>(), g->Acc.as<float>(), g->Q.as<float2>(),
+                                g->G.as<float2>(), g->U.as<float>(), g->V.as<float>(), g->Ox.as<float>(),
+                                g->Oy.as<float>(), tw, alpha, Re, dt, nsteps, U0, static_cast<const float*>(fvec), s);
     else
-        gen_dispatch<double>(g->N, x, y, g->W.as<double>(), g->Acc.as<double>(), g->Q.as<double2>(),
-                             g->G.as<double2>(), g->U.as<double>(), g->V.as<double>(), g->Ox.as<double>(),
-                             g->Oy.as<double>(), tw, alpha, Re, dt, nsteps, s);
+        gen_dispatch<double, RM>(g->N, x, y, g->W.as<double>(), g->Acc.as<double>(), g->Q.as<double2>(),
+                                 g->G.as<double2>(), g->U.as<double>(), g->V.as<double>(), g->Ox.as<double>(),
+                                 g->Oy.as<double>(), tw, alpha, Re, dt, nsteps, U0, static_cast<const double*>(fvec),
+                                 s);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
+}
+}  // namespace
+
+tsk_status gen2d_apply(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
+                       const void* tw, hipStream_t s) {
+    return gen_go<ROW_LIN>(g, alpha, Re, dt, nsteps, 0.0, nullptr, x, y, tw, s);
+}
+
+tsk_status gen2d_nonlinear(Gen2D* g, double alpha, double Re, double dt, int nsteps, double U0, const void* fvec,
+                           const void* x, void* y, const void* tw, hipStream_t s) {
+    return gen_go<ROW_NL>(g, alpha, Re, dt, nsteps, U0, fvec, x, y, tw, s);
+}
+
+tsk_status gen2d_fields(Gen2D* g, double alpha, double U0, const void* x, const void* tw, hipStream_t s) {
+    return gen_go<ROW_FIELDS>(g, alpha, 1.0, 1.0, 0, U0, nullptr, x, nullptr, tw, s);
 }
 
 }  // namespace tsk

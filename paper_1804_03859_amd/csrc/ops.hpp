@@ -120,6 +120,16 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
 tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V, const double* Ox,
                                   const double* Oy);
 bool is_kolmo(const Operator* op);
+// Nonlinear forced equation on a Navier-Stokes operator (kolmo.hip): forcing that
+// holds the laminar flow of wavenumber n_forcing steady, drift U0, optional extra
+// forcing field (host N*N, nullable); steps of it; the packed laminar state; the
+// general base flow set to a device state.
+tsk_status kolmo_set_nonlinear(Operator* op, int n_forcing, double U0, const double* extra);
+tsk_status kolmo_nonlinear_step(Operator* op, const void* x, void* y, int nsteps);  // 0: T/dt steps
+tsk_status kolmo_laminar_state(Operator* op, void* x);
+tsk_status kolmo_base_from_state(Operator* op, const void* x);
+double kolmo_dt(const Operator* op);
+int kolmo_nsteps(const Operator* op);
 // Columns per wavefront of the column stepper: 0 = autotuned, 1 or 2 forced;
 // get reports the forced or tuned value (0 = not tuned yet).
 tsk_status kolmo_set_tuning(Operator* op, int cols);
@@ -192,6 +202,15 @@ tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipS
 // eigenvalue.  FP64 runs use 0 for both (the rule of the Arnoldi stop test).
 constexpr double kResFloorFp32 = 32.0 * 5.9604644775390625e-08;
 constexpr double kDupRelFp32 = 2e-5;
+
+// Fixed-point solvers (fixedpoint.hip) on the nonlinear equation of a
+// Navier-Stokes operator; arguments as tsk_sfd, tsk_rpm, tsk_boostconv.
+tsk_status fixed_point_sfd(Operator* op, void* x, double chi, double delta, int check_every, double tol,
+                           int max_checks, double* hist, tsk_fp_info* info);
+tsk_status fixed_point_rpm(Operator* op, void* x, int m, int k, double delta, double tol, int max_iter, double* hist,
+                           tsk_fp_info* info);
+tsk_status fixed_point_boostconv(Operator* op, void* x, int m, double tol, int max_iter, double* hist,
+                                 tsk_fp_info* info);
 
 // Learned start vector (mlp.hip): network object and entry points.
 struct Mlp;

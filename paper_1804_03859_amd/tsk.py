@@ -25,6 +25,11 @@ class TskError(RuntimeError):
         self.status = status
 
 
+class FpInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("time_steps", C.c_int64), ("basis_dim", C.c_int),
+                ("residual", C.c_double), ("ms_total", C.c_double)]
+
+
 class KsInfo(C.Structure):
     _fields_ = [("n_matvec", C.c_int), ("n_restarts", C.c_int), ("n_ritz", C.c_int),
                 ("n_converged", C.c_int), ("status", C.c_int), ("kept_last", C.c_int),
@@ -69,6 +74,13 @@ def load():
         "tsk_batch_arnoldi": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(f64), P(vp),
                               P(ArnoldiInfo)],
         "tsk_apply_adjoint": [vp, vp, vp],
+        "tsk_set_nonlinear": [vp, i32, f64, P(f64)],
+        "tsk_laminar_state": [vp, vp],
+        "tsk_nonlinear_step": [vp, vp, vp, i32],
+        "tsk_set_base_from_state": [vp, vp],
+        "tsk_sfd": [vp, vp, f64, f64, i32, f64, i32, P(f64), P(FpInfo)],
+        "tsk_rpm": [vp, vp, i32, i32, f64, f64, i32, P(f64), P(FpInfo)],
+        "tsk_boostconv": [vp, vp, i32, f64, i32, P(f64), P(FpInfo)],
         "tsk_optimal_perturbation": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), vp, P(ArnoldiInfo)],
         "tsk_krylov_schur": [vp, i32, i32, f64, f64, i32, i32, vp, u64, P(f64), P(f64), P(f64), vp, P(KsInfo)],
         "tsk_ks_contract": [vp, i32, i32, f64, i32, f64, i32, vp, vp, vp, vp, P(i32), P(f64), vp],
@@ -111,6 +123,8 @@ def exported_symbols():
             "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
+            "tsk_set_nonlinear", "tsk_laminar_state", "tsk_nonlinear_step", "tsk_set_base_from_state", "tsk_sfd",
+            "tsk_rpm", "tsk_boostconv",
             "tsk_last_hessenberg",
             "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
@@ -314,6 +328,73 @@ def batch_arnoldi(ops, m, k, tol, v0s=None, seeds=None, want_vectors=False):
             o["X"] = Xs[i][:nr]
         out.append(o)
     return out
+
+
+def set_nonlinear(op, n_forcing=4, U0=0.0, extra_forcing=None):
+    """Nonlinear forced equation on a Navier-Stokes operator (extra_forcing: N x N
+    physical field or None)."""
+    ex, exp_ = (None, None) if extra_forcing is None else _dbl(extra_forcing)
+    if ex is not None and ex.size != op.N * op.N:
+        raise ValueError("extra forcing must have N*N samples")
+    _check(load().tsk_set_nonlinear(op.h, n_forcing, U0, exp_))
+
+
+def laminar_state(op):
+    x = op.new_state()
+    _check(load().tsk_laminar_state(op.h, _ptr(x)))
+    return x
+
+
+def nonlinear_step(op, x, y, nsteps=0):
+    _need(x, op.n, op.state_dtype, "x")
+    _need(y, op.n, op.state_dtype, "y")
+    _check(load().tsk_nonlinear_step(op.h, _ptr(x), _ptr(y), nsteps))
+
+
+def set_base_from_state(op, x):
+    _need(x, op.n, op.state_dtype, "x")
+    _check(load().tsk_set_base_from_state(op.h, _ptr(x)))
+
+
+def _fp_out(st, info, hist, n):
+    return dict(status=st, iterations=info.iterations, time_steps=info.time_steps, basis_dim=info.basis_dim,
+                residual=info.residual, ms_total=info.ms_total, hist=hist[:n].copy())
+
+
+def sfd(op, x, chi, delta, check_every, tol, max_checks):
+    """Selective frequency damping in place on the device state x."""
+    import numpy as np
+    _need(x, op.n, op.state_dtype, "x")
+    hist = np.zeros(max_checks)
+    info = FpInfo()
+    st = load().tsk_sfd(op.h, _ptr(x), chi, delta, check_every, tol, max_checks,
+                        hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(info))
+    _check(st)
+    return _fp_out(st, info, hist, info.iterations)
+
+
+def rpm(op, x, m, k, delta, tol, max_iter):
+    """Recursive projection method in place on the device state x."""
+    import numpy as np
+    _need(x, op.n, op.state_dtype, "x")
+    hist = np.zeros(max_iter)
+    info = FpInfo()
+    st = load().tsk_rpm(op.h, _ptr(x), m, k, delta, tol, max_iter, hist.ctypes.data_as(C.POINTER(C.c_double)),
+                        C.byref(info))
+    _check(st)
+    return _fp_out(st, info, hist, min(info.iterations + 1, max_iter))
+
+
+def boostconv(op, x, m, tol, max_iter):
+    """BoostConv in place on the device state x."""
+    import numpy as np
+    _need(x, op.n, op.state_dtype, "x")
+    hist = np.zeros(max_iter)
+    info = FpInfo()
+    st = load().tsk_boostconv(op.h, _ptr(x), m, tol, max_iter, hist.ctypes.data_as(C.POINTER(C.c_double)),
+                              C.byref(info))
+    _check(st)
+    return _fp_out(st, info, hist, min(info.iterations + 1, max_iter))
 
 
 def apply_adjoint(op, x, y):

@@ -355,6 +355,83 @@ def general_stage_bytes(N, s):
     return row, col
 
 
+def run_fixed_point(args, tsk, W, np, torch):
+    """Fixed points of the nonlinear forced Navier-Stokes equation (Sec. 3.1) on a
+    128^2 FP64 grid: Re = 7, alpha = 0.5, drift U0 = 0.7 (three weakly unstable
+    travelling modes), a weak two-dimensional extra forcing (so the fixed point has
+    no analytic form), IF-RK4 dt = 0.02, outer iteration G = 100 steps (T = 2).
+    A step is one whole RPM run (k_dim 24, delta 0.3) from the laminar flow to
+    residual 1e-9; the config also reports BoostConv (m = 10) and SFD (chi = 0.2,
+    omega_c = 0.2) on the same problem (untimed, one run each), like the paper's
+    comparison of the three solvers."""
+    N, Re, alpha, dt, T, U0 = 128, 7.0, 0.5, 0.02, 2.0, 0.7
+    ex = W.random_forcing_field(N, alpha, 2, 7, 0.002)
+    op = tsk.create_kolmo2d(N, tsk.TSK_FP64)
+    tsk.set_params_kolmo(op, Re, alpha, dt, T)
+    tsk.set_base_kolmogorov(op, 4)
+    tsk.set_nonlinear(op, 4, U0, ex)
+    tol = 1e-9
+
+    def rpm_run():
+        x = tsk.laminar_state(op)
+        return x, tsk.rpm(op, x, 24, 1, 0.3, tol, 80)
+
+    for _ in range(args.warmup):
+        rpm_run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [rpm_run() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el * 1e3 / args.steps
+    xr, r = runs[-1]
+    # time-stepper throughput and roofline: one nonlinear G (100 steps) timed alone
+    y = op.new_state()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tsk.nonlinear_step(op, xr, y, 0)
+    ev0.record()
+    for _ in range(5):
+        tsk.nonlinear_step(op, xr, y, 0)
+    ev1.record()
+    torch.cuda.synchronize()
+    g_ms = ev0.elapsed_time(ev1) / 5
+    nsteps = int(round(T / dt))
+    row, col = general_stage_bytes(N, 8)
+    row -= 4 * N * N * 8  # the nonlinear products read no base fields
+    bytes_g = 4 * nsteps * (row + col)
+    achieved = bytes_g / (g_ms / 1e3) / 1e9
+    xb = tsk.laminar_state(op)
+    b = tsk.boostconv(op, xb, 10, tol, 120)
+    xs = tsk.laminar_state(op)
+    sf = tsk.sfd(op, xs, 0.2, 5.0, 100, 1e-7, 400)
+    agree = float(torch.linalg.norm(xr - xb).item() / torch.linalg.norm(xr).item())
+    lam = tsk.laminar_state(op)
+    dist = float(torch.linalg.norm(xr - lam).item() / torch.linalg.norm(lam).item())
+    steps_rpm = r["time_steps"] + 24 * nsteps  # plus the Arnoldi factorisation of the Jacobian (24 matvecs)
+    return {
+        "metric": "time-steps*gridpoints/s (whole RPM fixed-point run to residual 1e-9)",
+        "value": steps_rpm * N * N / (ms_per_step / 1e3),
+        "unit": "time-steps*gridpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "fixed point of the forced 2-D Navier-Stokes equation (Kolmogorov forcing n=4 + "
+                               "band-limited extra forcing, amplitude 0.002, seed 7), 128x128 FP64, Re=7, alpha=0.5, "
+                               "drift U0=0.7, IF-RK4 dt=0.02, G = 100 steps",
+                   "rpm": {"iterations": r["iterations"], "basis_dim": r["basis_dim"], "residual": r["residual"],
+                           "time_steps_incl_arnoldi": steps_rpm, "ms": ms_per_step},
+                   "boostconv": {"iterations": b["iterations"], "residual": b["residual"],
+                                 "time_steps": b["time_steps"], "ms": b["ms_total"], "status": b["status"]},
+                   "sfd": {"checks": sf["iterations"], "residual_per_dt": sf["residual"],
+                           "time_steps": sf["time_steps"], "ms": sf["ms_total"], "status": sf["status"]},
+                   "rpm_vs_boostconv_rel_diff": agree, "fixed_point_distance_from_laminar_rel": dist,
+                   "ms_per_G": g_ms},
+        "roofline": {"bound": "hbm", "kernel": "k_gen_row<double,128,ROW_NL> + k_gen_col<double,128> (nonlinear step)",
+                     "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "bytes_per_G": bytes_g, "traffic": None},
+        "cpu_baseline": None,
+    }
+
+
 def run_general(args, tsk, W, np, torch):
     """Arnoldi on a general two-dimensional base flow (random band-limited base
     streamfunction, |jx|, |jy| <= 2, amplitude 0.3, seed 0), 128^2 FP64, through
@@ -494,7 +571,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kolmo128",
                     choices=["kolmo128", "kolmo512-fp32", "sweep", "learned", "general", "krylov-schur", "optimal",
-                             "copy"])
+                             "fixed-point", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -543,6 +620,8 @@ def main():
         out = run_krylov_schur(args, tsk, W, np, torch)
     elif args.workload == "optimal":
         out = run_optimal(args, tsk, W, np, torch)
+    elif args.workload == "fixed-point":
+        out = run_fixed_point(args, tsk, W, np, torch)
     else:
         out = run_sweep(args, tsk, W, np, torch)
     print(json.dumps(out))

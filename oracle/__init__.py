@@ -29,6 +29,9 @@ arXiv:1804.03859, that it follows):
 * ``fixedpoint``  -- nonlinear forced Navier-Stokes stepper and the fixed-point
                      solvers on it: selective frequency damping, recursive
                      projection method, BoostConv (Sec. 3.1).
+* ``resolvent``   -- resolvent by forced time integration of the Ginzburg-Landau
+                     equation (Sec. 2.3.2, Sec. 3.3.2) and its closed form for
+                     Crank-Nicolson (the warped-frequency resolvent).
 * ``rng``         -- splitmix64 + Box-Muller start-vector generator (published
                      definitions, Steele/Lea/Flood 2014 and Box & Muller 1958).
 * ``mlp``         -- start-vector network (not in the paper): FP64 forward,

@@ -154,6 +154,20 @@ tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev);
  * layout, stream and aliasing rule as tsk_apply. */
 tsk_status tsk_apply_adjoint(tsk_op op, const void* x_dev, void* y_dev);
 
+/* Resolvent mode (Sec. 2.3.2; Sec. 3.3.2, the resolvent by forced time
+ * integration) of a Ginzburg-Landau operator: tsk_apply(op, f, x) then returns
+ * x^ = R(omega) f^, the asymptotic response to the forcing f^ e^{i omega t}:
+ * Crank-Nicolson from rest over t_transient time units (forcing by the
+ * trapezoidal rule), read as u(t) e^{-i omega t} (the response is a single
+ * harmonic, so this is its Fourier coefficient).  It is the resolvent of the
+ * discrete L_h at the warped frequency (2/dt) tan(omega dt/2), up to the
+ * transient remainder (decay rate: the least stable eigenvalue; the system must
+ * be stable).  tsk_apply_adjoint returns R(omega)^H (L_h^H at -omega), so
+ * tsk_optimal_perturbation gives the resolvent gains sigma^2 and the optimal
+ * forcings.  t_transient = 0 returns to the propagator.  TSK_EINVAL for other
+ * operators (the complex forcing needs a complex state). */
+tsk_status tsk_set_resolvent(tsk_op op, double omega, double t_transient);
+
 /* Optimal perturbation (Sec. 2.3.1, SVD formulation; Sec. 3.3.2): the k largest
  * singular values sigma of M = exp(A T) by the Lanczos iteration on the
  * symmetric M^dagger M.  Each step is one forward and one adjoint integration,

@@ -191,6 +191,13 @@ tsk_status tsk_apply_adjoint(tsk_op op, const void* x_dev, void* y_dev) {
     })
 }
 
+tsk_status tsk_set_resolvent(tsk_op op, double omega, double t_transient) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return cgle_set_resolvent(op->op.get(), omega, t_transient);
+    })
+}
+
 tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed,
                                     double* sigma, double* resid, void* vecs_dev, tsk_arnoldi_info* info) {
     TSK_GUARD({

@@ -28,12 +28,17 @@ namespace {
 constexpr int kCgleMaxN = 1024;
 constexpr int kCgleMaxLevels = 10;
 
+// FORCED: uin is the forcing f^ of u' = L u + f^ e^{i omega t}; the run starts
+// from rest, the forcing enters by the trapezoidal rule (dt/2 (f_n + f_{n+1}) =
+// c1 e^{i omega t_n} f^, c1 = dt/2 (1 + e^{i omega dt})), and the output is the
+// phase-normalised state u(t_N) e^{-i omega t_N}.
+template <bool FORCED>
 __global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict__ uin, double2* __restrict__ uout,
                                                       const double2* __restrict__ rhs_main, double2 rhs_sub,
                                                       double2 rhs_sup, const double2* __restrict__ alpha,
                                                       const double2* __restrict__ gamma,
                                                       const double2* __restrict__ binv, int n, int levels,
-                                                      int nsteps) {
+                                                      int nsteps, double omega, double dt, double2 c1) {
     __shared__ double2 bufA[kCgleMaxN];
     __shared__ double2 bufB[kCgleMaxN];
     const int i = threadIdx.x;
@@ -46,15 +51,21 @@ __global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict
     }
     const double2 rm = act ? rhs_main[i] : cmk<double2>(0.0, 0.0);
     const double2 bi = act ? binv[i] : cmk<double2>(0.0, 0.0);
-    double2 u = act ? uin[i] : cmk<double2>(0.0, 0.0);
     const double2 zero = cmk<double2>(0.0, 0.0);
+    const double2 fh = (FORCED && act) ? cmul(c1, uin[i]) : zero;
+    double2 u = (!FORCED && act) ? uin[i] : zero;
     for (int st = 0; st < nsteps; ++st) {
-        // explicit half: d = (I + dt/2 L) u
+        // explicit half: d = (I + dt/2 L) u (+ the forcing)
         bufA[i] = u;
         __syncthreads();
         double2 um = (i > 0 && act) ? bufA[i - 1] : zero;
         double2 up = (i + 1 < n) ? bufA[i + 1] : zero;
         double2 d = cadd(cmul(rm, u), cadd(cmul(rhs_sub, um), cmul(rhs_sup, up)));
+        if constexpr (FORCED) {
+            double sn, cs;
+            sincos(omega * dt * double(st), &sn, &cs);
+            d = cadd(d, cmul(cmk<double2>(cs, sn), fh));
+        }
         // implicit half by cyclic reduction, ping-pong between two LDS buffers
         double2* src = bufA;  // level 0 swaps to bufB: bufA is still being read for the stencil
         double2* dst = bufB;
@@ -73,6 +84,11 @@ __global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict
         u = cmul(d, bi);
         __syncthreads();
     }
+    if constexpr (FORCED) {
+        double sn, cs;
+        sincos(omega * dt * double(nsteps), &sn, &cs);
+        u = cmul(u, cmk<double2>(cs, -sn));
+    }
     if (act) uout[i] = u;
 }
 
@@ -88,7 +104,12 @@ struct CgleOp final : Operator {
     int nn = 0;
     double half_width = 0.0;
     int levels = 0, nsteps = 0;
+    double dt = 0.0;
     CnTables fwd, adj;  // L_h and its conjugate transpose (the adjoint propagator)
+    // resolvent mode: apply = R(omega) by ntrans forced steps from rest
+    bool resolvent = false;
+    double omega = 0.0;
+    int ntrans = 0;
 
     const char* name() const override { return "cgle1d"; }
     int64_t physical_reals() const override { return 2 * int64_t(nn); }
@@ -121,6 +142,7 @@ struct CgleOp final : Operator {
         levels = L;
         nsteps = nsi;
         T = TT;
+        this->dt = dt;
         params_set = true;
         return TSK_OK;
     }
@@ -164,22 +186,36 @@ struct CgleOp final : Operator {
         return TSK_OK;
     }
 
-    tsk_status run(const CnTables& tb, const void* x, void* y) {
+    // Propagator (forced = false: T/dt steps of x) or resolvent (forced = true:
+    // x is the forcing, ntrans steps at frequency w from rest).
+    tsk_status run(const CnTables& tb, const void* x, void* y, bool forced, double w) {
         if (!ready()) return fail(TSK_ESTATE, "CGLE parameters not set");
         if (x == y) return fail(TSK_EINVAL, "input and output must not alias");
         const double2* t = tb.tab.as<double2>();
         const int n_ = nn;
         const int threads = (n_ + kWave - 1) / kWave * kWave;
-        hipLaunchKernelGGL(k_cgle_cn, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
-                           static_cast<double2*>(y), t, tb.rsub, tb.rsup, t + n_, t + n_ + size_t(levels) * n_,
-                           t + n_ + 2 * size_t(levels) * n_, n_, levels, nsteps);
+        const double2* al = t + n_;
+        const double2* ga = t + n_ + size_t(levels) * n_;
+        const double2* bi = t + n_ + 2 * size_t(levels) * n_;
+        if (forced) {
+            const double h = 0.5 * dt;
+            const double2 c1 = cmk<double2>(h * (1.0 + std::cos(w * dt)), h * std::sin(w * dt));
+            hipLaunchKernelGGL(k_cgle_cn<true>, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
+                               static_cast<double2*>(y), t, tb.rsub, tb.rsup, al, ga, bi, n_, levels, ntrans, w, dt,
+                               c1);
+        } else {
+            hipLaunchKernelGGL(k_cgle_cn<false>, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
+                               static_cast<double2*>(y), t, tb.rsub, tb.rsup, al, ga, bi, n_, levels, nsteps, 0.0, dt,
+                               cmk<double2>(0.0, 0.0));
+        }
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
-    tsk_status apply(const void* x, void* y) override { return run(fwd, x, y); }
+    tsk_status apply(const void* x, void* y) override { return run(fwd, x, y, resolvent, omega); }
     // M^H: Crank-Nicolson with L_h^H (the two factors of a step commute, so this is
-    // the conjugate transpose of the forward propagator).
-    tsk_status apply_adjoint(const void* x, void* y) override { return run(adj, x, y); }
+    // the conjugate transpose of the forward propagator).  Resolvent mode:
+    // R(omega)^H = the forced integration with L_h^H at frequency -omega.
+    tsk_status apply_adjoint(const void* x, void* y) override { return run(adj, x, y, resolvent, -omega); }
     bool has_adjoint() const override { return true; }
     tsk_status from_physical(const void* phys, void* state) override {
         TSK_HIP(hipMemcpyAsync(state, phys, state_bytes(), hipMemcpyDeviceToDevice, stream));
@@ -215,5 +251,23 @@ tsk_status cgle_set_params(Operator* op, double U, double c_u, double c_d, doubl
 }
 
 bool is_cgle(const Operator* op) { return dynamic_cast<const CgleOp*>(op) != nullptr; }
+
+tsk_status cgle_set_resolvent(Operator* op, double omega, double t_transient) {
+    auto* c = dynamic_cast<CgleOp*>(op);
+    if (!c) return fail(TSK_EINVAL, "the resolvent mode needs a Ginzburg-Landau operator (complex state)");
+    if (!c->params_set) return fail(TSK_ESTATE, "CGLE parameters not set");
+    if (!std::isfinite(omega) || !std::isfinite(t_transient) || t_transient < 0.0)
+        return fail(TSK_EINVAL, "omega must be finite and t_transient >= 0");
+    if (t_transient == 0.0) {
+        c->resolvent = false;
+        return TSK_OK;
+    }
+    const int ns = int(std::lround(t_transient / c->dt));
+    if (ns < 1) return fail(TSK_EINVAL, "t_transient must be at least one time step");
+    c->resolvent = true;
+    c->omega = omega;
+    c->ntrans = ns;
+    return TSK_OK;
+}
 
 }  // namespace tsk

@@ -139,6 +139,10 @@ bool kolmo_parallel(const Operator* op);
 // Largest kept wavenumber M = (N-1)/3 of a Navier-Stokes operator, -1 for others.
 int kolmo_cutoff(const Operator* op);
 bool is_cgle(const Operator* op);
+// Resolvent mode of a Ginzburg-Landau operator: apply = R(omega) (forced
+// integration over t_transient from rest), apply_adjoint = R(omega)^H;
+// t_transient = 0 returns to the propagator.
+tsk_status cgle_set_resolvent(Operator* op, double omega, double t_transient);
 
 // Batched Navier-Stokes matvec of Arnoldi step j: x = V_j, y = w for every
 // active instance of the descriptor table (kolmo.hip).

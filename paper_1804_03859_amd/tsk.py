@@ -74,6 +74,7 @@ def load():
         "tsk_batch_arnoldi": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(f64), P(vp),
                               P(ArnoldiInfo)],
         "tsk_apply_adjoint": [vp, vp, vp],
+        "tsk_set_resolvent": [vp, f64, f64],
         "tsk_set_nonlinear": [vp, i32, f64, P(f64)],
         "tsk_laminar_state": [vp, vp],
         "tsk_nonlinear_step": [vp, vp, vp, i32],
@@ -123,6 +124,7 @@ def exported_symbols():
             "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
+            "tsk_set_resolvent",
             "tsk_set_nonlinear", "tsk_laminar_state", "tsk_nonlinear_step", "tsk_set_base_from_state", "tsk_sfd",
             "tsk_rpm", "tsk_boostconv",
             "tsk_last_hessenberg",
@@ -395,6 +397,11 @@ def boostconv(op, x, m, tol, max_iter):
                               C.byref(info))
     _check(st)
     return _fp_out(st, info, hist, min(info.iterations + 1, max_iter))
+
+
+def set_resolvent(op, omega, t_transient):
+    """Resolvent mode of a Ginzburg-Landau operator (t_transient = 0: propagator)."""
+    _check(load().tsk_set_resolvent(op.h, omega, t_transient))
 
 
 def apply_adjoint(op, x, y):

@@ -46,3 +46,14 @@ def match_sets(a, b):
         worst = max(worst, d[i])
         b.pop(i)
     return worst
+
+
+def golden(name):
+    """A `key value` text fixture under tests/golden/ as a dict of floats."""
+    out = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            out[k] = float(v)
+    return out

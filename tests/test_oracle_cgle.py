@@ -13,13 +13,8 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _golden(name):
-    out = {}
-    for line in open(os.path.join(GOLD, name)):
-        line = line.strip()
-        if line and not line.startswith("#"):
-            k, v = line.split()
-            out[k] = float(v)
-    return out
+    from conftest import golden
+    return golden(name)
 
 
 def _leading(lams, count):

@@ -189,6 +189,22 @@ tsk_status tsk_set_resolvent(tsk_op op, double omega, double t_transient);
 tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const void* v0_dev, uint64_t seed,
                                     double* sigma, double* resid, void* vecs_dev, tsk_arnoldi_info* info);
 
+/* Batched optimal perturbation / resolvent gains (Sec. 2.3.1, 2.3.2; Sec.
+ * 3.3.2), for sweeps over target times or forcing frequencies: `count`
+ * operators of one state type and one stream, each with an adjoint, advance
+ * their Lanczos iterations in lockstep; the integrations of Ginzburg-Landau
+ * instances of one node count (the resolvent of each at its own frequency, or
+ * its propagator) run in one launch per pass, one workgroup per instance.  Each
+ * instance stops on its own test.  Arguments as for tsk_optimal_perturbation,
+ * per instance i: v0_devs[i] (array or entries may be NULL), seeds[i] (NULL
+ * array: seed i), sigma + k i, resid + k i, vecs_devs[i] (array or entries may
+ * be NULL), infos[i] (per-instance status).  Returns TSK_OK when every instance
+ * ended without error (see infos[i].status), or a negative status for an
+ * argument or runtime failure of the whole batch. */
+tsk_status tsk_batch_optimal_perturbation(const tsk_op* ops, int count, int m, int k, double tol,
+                                          const void* const* v0_devs, const uint64_t* seeds, double* sigma,
+                                          double* resid, void* const* vecs_devs, tsk_arnoldi_info* infos);
+
 /* Arnoldi with classical Gram-Schmidt applied twice (Sec. 3.2.1, Algorithm 1),
  * Ritz pairs from a device-side Hessenberg QR after every matvec, stop when the
  * k wanted pairs have |beta e_m^T y| <= tol (Sec. 3.2.2), or after m matvecs,

@@ -213,6 +213,26 @@ tsk_status tsk_optimal_perturbation(tsk_op op, int m, int k, double tol, const v
     })
 }
 
+tsk_status tsk_batch_optimal_perturbation(const tsk_op* ops, int count, int m, int k, double tol,
+                                          const void* const* v0_devs, const uint64_t* seeds, double* sigma,
+                                          double* resid, void* const* vecs_devs, tsk_arnoldi_info* infos) {
+    TSK_GUARD({
+        if (!ops || count < 1) return fail(TSK_EINVAL, "empty batch");
+        std::vector<Operator*> o(count);
+        for (int i = 0; i < count; ++i) {
+            if (!ops[i] || !ops[i]->op) return fail(TSK_EINVAL, "null operator handle in batch");
+            o[i] = ops[i]->op.get();
+        }
+        std::vector<double> mu(2 * size_t(count) * size_t(std::max(k, 1)));
+        const tsk_status st = arnoldi_batch(o.data(), count, m, k, tol, v0_devs, seeds, mu.data(), nullptr, resid,
+                                            vecs_devs, infos, true);
+        if (st < 0) return st;
+        if (sigma)
+            for (size_t q = 0; q < size_t(count) * k; ++q) sigma[q] = std::sqrt(std::max(mu[2 * q], 0.0));
+        return st;
+    })
+}
+
 tsk_status tsk_set_nonlinear(tsk_op op, int n_forcing, double U0, const double* extra_forcing) {
     TSK_GUARD({
         TSK_NEED(op);

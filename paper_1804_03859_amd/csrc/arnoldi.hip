@@ -264,9 +264,12 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     bool all_kolmo = true;
     for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && kolmo_parallel(ops[i]);
     if (all_kolmo && !svd) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
+    CgleBatchPtr cb;
+    if (count > 1 && is_cgle(ops[0])) TSK_TRY(cgle_batch_plan(ops, count, Dh.data(), svd, &cb));
     std::vector<Outcome> oc(count);
     auto matvec = [&](int j) -> tsk_status {
         if (kb) return kolmo_batch_matvec(kb.get(), j, s);
+        if (cb) return cgle_batch_matvec(cb.get(), j, s);
         for (int i = 0; i < count; ++i) {
             if (oc[i].done) continue;
             const TS* vj = static_cast<TS*>(Dh[i].V) + j * Dh[i].ldv;

@@ -19,6 +19,7 @@
 #include <complex>
 #include <vector>
 
+#include "krylov.hpp"
 #include "ops.hpp"
 
 namespace tsk {
@@ -28,43 +29,64 @@ namespace {
 constexpr int kCgleMaxN = 1024;
 constexpr int kCgleMaxLevels = 10;
 
-// FORCED: uin is the forcing f^ of u' = L u + f^ e^{i omega t}; the run starts
-// from rest, the forcing enters by the trapezoidal rule (dt/2 (f_n + f_{n+1}) =
-// c1 e^{i omega t_n} f^, c1 = dt/2 (1 + e^{i omega dt})), and the output is the
-// phase-normalised state u(t_N) e^{-i omega t_N}.
-template <bool FORCED>
-__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict__ uin, double2* __restrict__ uout,
-                                                      const double2* __restrict__ rhs_main, double2 rhs_sub,
-                                                      double2 rhs_sup, const double2* __restrict__ alpha,
-                                                      const double2* __restrict__ gamma,
-                                                      const double2* __restrict__ binv, int n, int levels,
-                                                      int nsteps, double omega, double dt, double2 c1) {
+// One Crank-Nicolson integration (one workgroup).  Propagator: nsteps steps of
+// the state in.  Forced (the resolvent mode): in is the forcing f^ of
+// u' = L u + f^ e^{i omega t}; the run starts from rest, the forcing enters by
+// the trapezoidal rule (dt/2 (f_n + f_{n+1}) = c1 e^{i omega t_n} f^ with
+// c1 = dt/2 (1 + e^{i omega dt})), and the output is the phase-normalised state
+// u(t_N) e^{-i omega t_N}.
+struct CnJob {
+    const double2* in;    // input of Krylov step j: in + j * in_stride
+    long long in_stride;  // elements (0: one fixed input)
+    double2* out;
+    const double2* tab;   // rhs_main[n] | alpha[levels n] | gamma[levels n] | binv[n]
+    double2 rsub, rsup;   // dt/2 times the constant sub/super diagonals
+    double2 c1;
+    double omega, dt;
+    int n, levels, nsteps, forced;
+};
+
+__device__ __forceinline__ void cn_integrate(const CnJob& jb, int j) {
     __shared__ double2 bufA[kCgleMaxN];
     __shared__ double2 bufB[kCgleMaxN];
+    const int n = jb.n, levels = jb.levels;
     const int i = threadIdx.x;
     const bool act = i < n;
+    const double2 zero = cmk<double2>(0.0, 0.0);
+    const double2* __restrict__ alpha = jb.tab + n;
+    const double2* __restrict__ gamma = alpha + size_t(levels) * n;
     double2 al[kCgleMaxLevels], ga[kCgleMaxLevels];
 #pragma unroll
     for (int l = 0; l < kCgleMaxLevels; ++l) {
-        al[l] = (act && l < levels) ? alpha[l * n + i] : cmk<double2>(0.0, 0.0);
-        ga[l] = (act && l < levels) ? gamma[l * n + i] : cmk<double2>(0.0, 0.0);
+        al[l] = (act && l < levels) ? alpha[l * n + i] : zero;
+        ga[l] = (act && l < levels) ? gamma[l * n + i] : zero;
     }
-    const double2 rm = act ? rhs_main[i] : cmk<double2>(0.0, 0.0);
-    const double2 bi = act ? binv[i] : cmk<double2>(0.0, 0.0);
-    const double2 zero = cmk<double2>(0.0, 0.0);
-    const double2 fh = (FORCED && act) ? cmul(c1, uin[i]) : zero;
-    double2 u = (!FORCED && act) ? uin[i] : zero;
-    for (int st = 0; st < nsteps; ++st) {
+    const double2 rm = act ? jb.tab[i] : zero;
+    const double2 bi = act ? gamma[size_t(levels) * n + i] : zero;
+    const double2* __restrict__ uin = jb.in + j * jb.in_stride;
+    const bool forced = jb.forced != 0;
+    const double2 fh = (forced && act) ? cmul(jb.c1, uin[i]) : zero;
+    double2 u = (!forced && act) ? uin[i] : zero;
+    // forcing phases e^{i omega dt s}: lane l of every wave evaluates step s0 + l
+    // once per 64 steps, step s reads lane s - s0
+    const int lane = i & (kWave - 1);
+    double2 ph = zero;
+    for (int st = 0; st < jb.nsteps; ++st) {
         // explicit half: d = (I + dt/2 L) u (+ the forcing)
         bufA[i] = u;
         __syncthreads();
         double2 um = (i > 0 && act) ? bufA[i - 1] : zero;
         double2 up = (i + 1 < n) ? bufA[i + 1] : zero;
-        double2 d = cadd(cmul(rm, u), cadd(cmul(rhs_sub, um), cmul(rhs_sup, up)));
-        if constexpr (FORCED) {
-            double sn, cs;
-            sincos(omega * dt * double(st), &sn, &cs);
-            d = cadd(d, cmul(cmk<double2>(cs, sn), fh));
+        double2 d = cadd(cmul(rm, u), cadd(cmul(jb.rsub, um), cmul(jb.rsup, up)));
+        if (forced) {
+            if ((st & (kWave - 1)) == 0) {
+                double sn, cs;
+                sincos(jb.omega * jb.dt * double(st + lane), &sn, &cs);
+                ph = cmk<double2>(cs, sn);
+            }
+            const int sl = st & (kWave - 1);
+            const double2 e = cmk<double2>(__shfl(ph.x, sl), __shfl(ph.y, sl));
+            d = cadd(d, cmul(e, fh));
         }
         // implicit half by cyclic reduction, ping-pong between two LDS buffers
         double2* src = bufA;  // level 0 swaps to bufB: bufA is still being read for the stencil
@@ -84,12 +106,20 @@ __global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(const double2* __restrict
         u = cmul(d, bi);
         __syncthreads();
     }
-    if constexpr (FORCED) {
+    if (forced) {
         double sn, cs;
-        sincos(omega * dt * double(nsteps), &sn, &cs);
+        sincos(jb.omega * jb.dt * double(jb.nsteps), &sn, &cs);
         u = cmul(u, cmk<double2>(cs, -sn));
     }
-    if (act) uout[i] = u;
+    if (act) jb.out[i] = u;
+}
+
+__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(CnJob jb) { cn_integrate(jb, 0); }
+
+// A batch of integrations (one per workgroup), Krylov step j of each.
+__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn_batch(const CnJob* __restrict__ jobs, int j) {
+    const CnJob jb = jobs[blockIdx.x];
+    cn_integrate(jb, j);
 }
 
 // Tables of one Crank-Nicolson propagator: the explicit stencil (main diagonal
@@ -108,7 +138,7 @@ struct CgleOp final : Operator {
     CnTables fwd, adj;  // L_h and its conjugate transpose (the adjoint propagator)
     // resolvent mode: apply = R(omega) by ntrans forced steps from rest
     bool resolvent = false;
-    double omega = 0.0;
+    double omega = 0.0, ttrans = 0.0;
     int ntrans = 0;
 
     const char* name() const override { return "cgle1d"; }
@@ -143,6 +173,7 @@ struct CgleOp final : Operator {
         nsteps = nsi;
         T = TT;
         this->dt = dt;
+        if (resolvent) ntrans = std::max(1, int(std::lround(ttrans / dt)));
         params_set = true;
         return TSK_OK;
     }
@@ -188,26 +219,33 @@ struct CgleOp final : Operator {
 
     // Propagator (forced = false: T/dt steps of x) or resolvent (forced = true:
     // x is the forcing, ntrans steps at frequency w from rest).
+    CnJob job(const CnTables& tb, bool forced, double w) const {
+        CnJob jb{};
+        jb.tab = tb.tab.as<double2>();
+        jb.rsub = tb.rsub;
+        jb.rsup = tb.rsup;
+        jb.n = nn;
+        jb.levels = levels;
+        jb.dt = dt;
+        jb.forced = forced ? 1 : 0;
+        if (forced) {
+            const double h = 0.5 * dt;
+            jb.c1 = cmk<double2>(h * (1.0 + std::cos(w * dt)), h * std::sin(w * dt));
+            jb.omega = w;
+            jb.nsteps = ntrans;
+        } else {
+            jb.nsteps = nsteps;
+        }
+        return jb;
+    }
+    int threads() const { return (nn + kWave - 1) / kWave * kWave; }
     tsk_status run(const CnTables& tb, const void* x, void* y, bool forced, double w) {
         if (!ready()) return fail(TSK_ESTATE, "CGLE parameters not set");
         if (x == y) return fail(TSK_EINVAL, "input and output must not alias");
-        const double2* t = tb.tab.as<double2>();
-        const int n_ = nn;
-        const int threads = (n_ + kWave - 1) / kWave * kWave;
-        const double2* al = t + n_;
-        const double2* ga = t + n_ + size_t(levels) * n_;
-        const double2* bi = t + n_ + 2 * size_t(levels) * n_;
-        if (forced) {
-            const double h = 0.5 * dt;
-            const double2 c1 = cmk<double2>(h * (1.0 + std::cos(w * dt)), h * std::sin(w * dt));
-            hipLaunchKernelGGL(k_cgle_cn<true>, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
-                               static_cast<double2*>(y), t, tb.rsub, tb.rsup, al, ga, bi, n_, levels, ntrans, w, dt,
-                               c1);
-        } else {
-            hipLaunchKernelGGL(k_cgle_cn<false>, dim3(1), dim3(threads), 0, stream, static_cast<const double2*>(x),
-                               static_cast<double2*>(y), t, tb.rsub, tb.rsup, al, ga, bi, n_, levels, nsteps, 0.0, dt,
-                               cmk<double2>(0.0, 0.0));
-        }
+        CnJob jb = job(tb, forced, w);
+        jb.in = static_cast<const double2*>(x);
+        jb.out = static_cast<double2*>(y);
+        hipLaunchKernelGGL(k_cgle_cn, dim3(1), dim3(threads()), 0, stream, jb);
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
@@ -262,11 +300,69 @@ tsk_status cgle_set_resolvent(Operator* op, double omega, double t_transient) {
         c->resolvent = false;
         return TSK_OK;
     }
-    const int ns = int(std::lround(t_transient / c->dt));
-    if (ns < 1) return fail(TSK_EINVAL, "t_transient must be at least one time step");
+    const double steps = t_transient / c->dt;
+    if (!(steps >= 0.5) || steps > 1e9)
+        return fail(TSK_EINVAL, "t_transient must span between one and 1e9 time steps");
     c->resolvent = true;
     c->omega = omega;
-    c->ntrans = ns;
+    c->ttrans = t_transient;
+    c->ntrans = int(std::lround(steps));
+    return TSK_OK;
+}
+
+// ---- batches: one workgroup per instance, all instances in one launch ---------------
+struct CgleBatch {
+    DevBuf first, second;  // job tables: V -> out (or tmp), and (M^H M) tmp -> w
+    int count = 0, threads = 0;
+    bool two = false;
+};
+
+void cgle_batch_free(CgleBatch* b) { delete b; }
+
+tsk_status cgle_batch_plan(Operator* const* ops, int count, const KryDesc* D_host, bool svd, CgleBatchPtr* out) {
+    out->reset();
+    std::vector<CnJob> a(count), b(count);
+    const auto* c0 = dynamic_cast<const CgleOp*>(ops[0]);
+    if (!c0) return fail(TSK_EINVAL, "not a Ginzburg-Landau batch");
+    for (int i = 0; i < count; ++i) {
+        const auto* c = dynamic_cast<const CgleOp*>(ops[i]);
+        if (!c || !c->ready()) return fail(TSK_ESTATE, "batch member is not a ready Ginzburg-Landau operator");
+        if (c->nn != c0->nn) return TSK_OK;  // mixed sizes: per-instance launches
+        const KryDesc& d = D_host[i];
+        void* mid = svd ? ops[i]->aw.tmp.ptr : d.w;
+        if (!d.V || !mid || !d.w) return fail(TSK_EINVAL, "batch workspace not allocated");
+        a[i] = c->job(c->fwd, c->resolvent, c->omega);
+        a[i].in = static_cast<const double2*>(d.V);
+        a[i].in_stride = d.ldv;
+        a[i].out = static_cast<double2*>(mid);
+        if (svd) {
+            b[i] = c->job(c->adj, c->resolvent, -c->omega);
+            b[i].in = static_cast<const double2*>(mid);
+            b[i].in_stride = 0;
+            b[i].out = static_cast<double2*>(d.w);
+        }
+    }
+    auto p = CgleBatchPtr(new CgleBatch);
+    p->count = count;
+    p->threads = c0->threads();
+    p->two = svd;
+    TSK_TRY(p->first.ensure(sizeof(CnJob) * count));
+    TSK_HIP(hipMemcpy(p->first.ptr, a.data(), sizeof(CnJob) * count, hipMemcpyHostToDevice));
+    if (svd) {
+        TSK_TRY(p->second.ensure(sizeof(CnJob) * count));
+        TSK_HIP(hipMemcpy(p->second.ptr, b.data(), sizeof(CnJob) * count, hipMemcpyHostToDevice));
+    }
+    *out = std::move(p);
+    return TSK_OK;
+}
+
+tsk_status cgle_batch_matvec(CgleBatch* b, int j, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgle_cn_batch, dim3(b->count), dim3(b->threads), 0, s, b->first.as<CnJob>(), j);
+    TSK_HIP(hipGetLastError());
+    if (b->two) {
+        hipLaunchKernelGGL(k_cgle_cn_batch, dim3(b->count), dim3(b->threads), 0, s, b->second.as<CnJob>(), 0);
+        TSK_HIP(hipGetLastError());
+    }
     return TSK_OK;
 }
 

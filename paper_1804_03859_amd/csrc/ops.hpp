@@ -157,6 +157,19 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* D_ho
                             KolmoBatchPtr* out);
 tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s);
 
+// Ginzburg-Landau batches of one node count: the integrations of all instances
+// (propagators or resolvents; with svd, the forward then the adjoint pass) in
+// one launch per pass, one workgroup each.  The plan is left empty (per-instance
+// launches) when the node counts differ.
+struct CgleBatch;
+void cgle_batch_free(CgleBatch* b);
+struct CgleBatchDeleter {
+    void operator()(CgleBatch* b) const { cgle_batch_free(b); }
+};
+using CgleBatchPtr = std::unique_ptr<CgleBatch, CgleBatchDeleter>;
+tsk_status cgle_batch_plan(Operator* const* ops, int count, const KryDesc* D_host, bool svd, CgleBatchPtr* out);
+tsk_status cgle_batch_matvec(CgleBatch* b, int j, hipStream_t s);
+
 // Arnoldi driver (arnoldi.hip): `count` independent instances in lockstep.
 // Per instance i: v0s[i] (nullable array / entry), seeds[i] (nullable array:
 // seed i), outputs at mu_ri + 2k i, lam_ri + 2k i, resid + k i, ritz[i]

@@ -75,6 +75,8 @@ def load():
                               P(ArnoldiInfo)],
         "tsk_apply_adjoint": [vp, vp, vp],
         "tsk_set_resolvent": [vp, f64, f64],
+        "tsk_batch_optimal_perturbation": [P(vp), i32, i32, i32, f64, P(vp), P(u64), P(f64), P(f64), P(vp),
+                                           P(ArnoldiInfo)],
         "tsk_set_nonlinear": [vp, i32, f64, P(f64)],
         "tsk_laminar_state": [vp, vp],
         "tsk_nonlinear_step": [vp, vp, vp, i32],
@@ -124,7 +126,7 @@ def exported_symbols():
             "tsk_get_tuning", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
-            "tsk_set_resolvent",
+            "tsk_set_resolvent", "tsk_batch_optimal_perturbation",
             "tsk_set_nonlinear", "tsk_laminar_state", "tsk_nonlinear_step", "tsk_set_base_from_state", "tsk_sfd",
             "tsk_rpm", "tsk_boostconv",
             "tsk_last_hessenberg",
@@ -431,6 +433,41 @@ def optimal_perturbation(op, m, k, tol, v0=None, seed=0, want_vectors=False):
                n_converged=info.n_converged, beta=info.beta, ms_total=info.ms_total, ms_apply=info.ms_apply)
     if X is not None:
         out["X"] = X[:nr]
+    return out
+
+
+def batch_optimal_perturbation(ops, m, k, tol, v0s=None, seeds=None, want_vectors=False):
+    """Run tsk_batch_optimal_perturbation on a list of operators (same state type
+    and stream, each with an adjoint).  Returns a list of dicts like
+    ``optimal_perturbation`` (X when want_vectors)."""
+    import numpy as np
+    count = len(ops)
+    if v0s is not None:
+        for op, v in zip(ops, v0s):
+            if v is not None:
+                _need(v, op.n, op.state_dtype, "v0")
+    hs = (C.c_void_p * count)(*[op.h for op in ops])
+    v0p = None
+    if v0s is not None:
+        v0p = (C.c_void_p * count)(*[(v.data_ptr() if v is not None else None) for v in v0s])
+    sp = (C.c_uint64 * count)(*[int(x) for x in seeds]) if seeds is not None else None
+    sig = np.zeros(k * count)
+    res = np.zeros(k * count)
+    Xs = [torch.zeros((k, op.n), dtype=torch.complex128, device="cuda") for op in ops] if want_vectors else None
+    rp = (C.c_void_p * count)(*[x.data_ptr() for x in Xs]) if Xs else None
+    infos = (ArnoldiInfo * count)()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    _check(load().tsk_batch_optimal_perturbation(hs, count, m, k, tol, v0p, sp, pd(sig), pd(res), rp, infos))
+    out = []
+    for i in range(count):
+        f = infos[i]
+        nr = f.n_ritz
+        sg = sig[k * i:k * (i + 1)][:nr]
+        o = dict(sigma=sg, gain=sg ** 2, res=res[k * i:k * (i + 1)][:nr], status=f.status, n_steps=f.n_matvec,
+                 n_ritz=nr, n_converged=f.n_converged, beta=f.beta, ms_total=f.ms_total, ms_apply=f.ms_apply)
+        if Xs:
+            o["X"] = Xs[i][:nr]
+        out.append(o)
     return out
 
 

@@ -143,3 +143,53 @@ def test_resolvent_mode_validation_and_return_to_the_propagator(tsk):
     tsk.set_base_kolmogorov(kop, 4)
     with pytest.raises(tsk.TskError):
         tsk.set_resolvent(kop, -0.55, 10.0)
+
+
+def test_batched_frequency_sweep_matches_dense_and_single_runs(tsk):
+    # one workgroup per frequency, all integrations of a pass in one launch
+    print("batched resolvent sweep n=48, 8 frequencies", flush=True)
+    omegas = np.linspace(-1.2, 0.2, 8)
+    pairs = [_small(tsk) for _ in omegas]
+    for (op, _), w in zip(pairs, omegas):
+        tsk.set_resolvent(op, float(w), 90.0)
+    ops = [p[0] for p in pairs]
+    v0s = [_cuda(W.normal_complex(48, 20 + i)) for i in range(len(ops))]
+    rb = tsk.batch_optimal_perturbation(ops, 24, 3, 1e-9, v0s=v0s, want_vectors=True)
+    for i, ((op, ref), w) in enumerate(zip(pairs, omegas)):
+        s = np.linalg.svd(discrete_resolvent(ref, float(w)), compute_uv=False)
+        assert rb[i]["status"] == 0
+        assert np.max(np.abs(rb[i]["gain"] - s[:3] ** 2)) <= 1e-8 * max(1.0, s[0] ** 2)
+        r1 = tsk.optimal_perturbation(op, 24, 3, 1e-9, v0=v0s[i])
+        assert r1["n_steps"] == rb[i]["n_steps"]
+        assert np.max(np.abs(r1["gain"] - rb[i]["gain"])) <= 1e-12 * s[0] ** 2
+
+
+def test_batched_paper_sweep_four_gains(tsk):
+    # the paper's figure: the first four gains sigma_j^2 against omega
+    print("batched resolvent sweep n=400, 6 frequencies, 4 gains", flush=True)
+    omegas = np.linspace(-1.0, 0.0, 6)
+    pairs = [_paper(tsk) for _ in omegas]
+    for (op, _), w in zip(pairs, omegas):
+        tsk.set_resolvent(op, float(w), 230.0)
+    rb = tsk.batch_optimal_perturbation([p[0] for p in pairs], 48, 4, 1e-6, seeds=list(range(6)))
+    for i, ((op, ref), w) in enumerate(zip(pairs, omegas)):
+        s = np.linalg.svd(discrete_resolvent(ref, float(w)), compute_uv=False)
+        assert rb[i]["status"] == 0
+        assert np.max(np.abs(rb[i]["gain"] - s[:4] ** 2)) <= 1e-6 * s[0] ** 2 + 1e-6
+
+
+def test_batched_propagators_and_mixed_sizes(tsk):
+    # eigenvalue batches of Ginzburg-Landau propagators (one launch) and a batch of
+    # two node counts (per-instance launches) give the single-run Ritz values
+    print("batched cgle arnoldi", flush=True)
+    ops = []
+    for mu0, n in [(0.41, 256), (0.3, 256), (0.2, 256), (0.41, 200)]:
+        op = tsk.create_cgle1d(n, 50.0)
+        tsk.set_params_cgle(op, 2.0, 0.2, -1.0, mu0, -0.01, 0.01, 1.0)
+        ops.append(op)
+    for group in (ops[:3], [ops[0], ops[3]]):
+        rb = tsk.batch_arnoldi(group, 64, 6, 1e-8, seeds=[0] * len(group))
+        for op, r in zip(group, rb):
+            r1 = tsk.arnoldi(op, 64, 6, 1e-8, seed=0)
+            assert r["status"] == r1["status"] == 0 and r["n_matvec"] == r1["n_matvec"]
+            assert np.max(np.abs(r["mu"] - r1["mu"])) <= 1e-12

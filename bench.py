@@ -564,6 +564,107 @@ def run_learned(args, tsk, W, np, torch):
     }
 
 
+def cn_pcr_flops(n, levels):
+    """Flops of one Crank-Nicolson step of the cyclic-reduction kernel per node:
+    the three-point explicit half (3 complex multiplies, 2 adds: 22), the forcing
+    term (8), per reduction level two complex multiply-adds (16) and the final
+    scaling (6)."""
+    return n * (22 + 8 + 16 * levels + 6)
+
+
+def cpu_baseline_resolvent(n, half_width, mu0, dt, t_trans, omega, seconds=10.0):
+    """The CPU oracle's forced integration (banded LAPACK solve per step, single
+    thread) of the same resolvent operator: as many whole integrations as fit in
+    about `seconds`."""
+    import numpy as np
+
+    import workloads as W
+    from oracle.cgle import CGLE
+    from oracle.resolvent import forced_response
+    op = CGLE(n=n, half_width=half_width, mu0=mu0, dt=dt)
+    f = W.normal_complex(n, 0)
+    t0 = time.perf_counter()
+    count = 0
+    while True:
+        f = forced_response(op, f, omega, t_trans, adjoint=bool(count % 2))
+        f /= np.linalg.norm(f)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    nsteps = int(round(t_trans / dt))
+    return {"value": count * nsteps * n / el, "unit": "time-steps*gridpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{count} oracle forced integrations (R and R^H alternately, {nsteps} Crank-Nicolson steps "
+                      f"each) of the n={n} operator at omega={omega}, {el:.1f} s, NumPy/SciPy single thread"}
+
+
+def run_resolvent(args, tsk, W, np, torch):
+    """Resolvent analysis of the linear complex Ginzburg-Landau equation (Sec.
+    2.3.2 illustration: mu0 = 0.23, x in [-85, 85]; Sec. 3.3.2 forced time
+    integration): the first four gains sigma_j^2 at 64 forcing frequencies in
+    [-1.5, 0.5].  Each frequency is one operator in resolvent mode (23000
+    Crank-Nicolson steps from rest, dt = 0.01, t = 230); Lanczos on R^H R to
+    residual 1e-6 for all 64 in one batch (one workgroup per frequency).  A step
+    is the whole sweep from seeded starts."""
+    n, hw, mu0, dt, tt = 400, 85.0, 0.23, 0.01, 230.0
+    F, m, k, tol = 64, 48, 4, 1e-6
+    omegas = np.linspace(-1.5, 0.5, F)
+    ops = []
+    for w in omegas:
+        op = tsk.create_cgle1d(n, hw)
+        tsk.set_params_cgle(op, 2.0, 0.2, -1.0, mu0, -0.01, dt, 1.0)
+        tsk.set_resolvent(op, float(w), tt)
+        ops.append(op)
+    seeds = list(range(F))
+
+    def run():
+        return tsk.batch_optimal_perturbation(ops, m, k, tol, seeds=seeds)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [run() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el * 1e3 / args.steps
+    r = results[-1]
+    nsteps = int(round(tt / dt))
+    levels = int(math.ceil(math.log2(n)))
+    steps = [q["n_steps"] for q in r]
+    lockstep = max(steps)
+    useful = sum(2 * q * nsteps * n for q in steps)  # forward + adjoint per Lanczos step
+    ms_apply = sum(q[0]["ms_apply"] for q in results) / args.steps
+    launch_ms = ms_apply / (2 * lockstep)
+    flops = F * nsteps * cn_pcr_flops(n, levels)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    gains = np.array([q["gain"] for q in r])
+    ipk = int(np.argmax(gains[:, 0]))
+    return {
+        "metric": "time-steps*gridpoints/s (resolvent gain sweep: 64 frequencies, 4 gains each, Lanczos on R^H R "
+                  "at residual 1e-6, R by forced time integration)",
+        "value": useful / (ms_per_step / 1e3),
+        "unit": "time-steps*gridpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"resolvent of the linear complex Ginzburg-Landau equation, n={n} finite-difference "
+                               f"nodes on [-85,85], U=2, c_u=0.2, c_d=-1, mu0=0.23, mu2=-0.01, Crank-Nicolson "
+                               f"dt={dt}, forced from rest over t={tt}; {F} frequencies in [-1.5,0.5]; Lanczos "
+                               f"m={m} k={k} tol={tol}, seeded N(0,1) starts",
+                   "lanczos_steps": steps, "status": [q["status"] for q in r],
+                   "omega": [float(w) for w in omegas], "gains": gains.tolist(),
+                   "peak": {"omega": float(omegas[ipk]), "gain": float(gains[ipk, 0])},
+                   "lockstep_integrations": 2 * lockstep,
+                   "time_stepper_tsgp_per_s": F * nsteps * n / (launch_ms / 1e3)},
+        "roofline": {"bound": "alu", "kernel": "k_cgle_cn_batch (64 workgroups, one per frequency)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
+                     "flops_per_launch": flops, "traffic": None},
+        "cpu_baseline": None if args.no_cpu_baseline else
+        cpu_baseline_resolvent(n, hw, mu0, dt, tt, float(omegas[ipk])),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,7 +672,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kolmo128",
                     choices=["kolmo128", "kolmo512-fp32", "sweep", "learned", "general", "krylov-schur", "optimal",
-                             "fixed-point", "copy"])
+                             "fixed-point", "resolvent", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -622,6 +723,8 @@ def main():
         out = run_optimal(args, tsk, W, np, torch)
     elif args.workload == "fixed-point":
         out = run_fixed_point(args, tsk, W, np, torch)
+    elif args.workload == "resolvent":
+        out = run_resolvent(args, tsk, W, np, torch)
     else:
         out = run_sweep(args, tsk, W, np, torch)
     print(json.dumps(out))

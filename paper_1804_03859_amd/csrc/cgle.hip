@@ -46,20 +46,31 @@ struct CnJob {
     int n, levels, nsteps, forced;
 };
 
+// LV = the number of reduction levels, ceil(log2 n): a compile-time count keeps
+// the per-level multipliers in registers.
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <int LV>
 __device__ __forceinline__ void cn_integrate(const CnJob& jb, int j) {
     __shared__ double2 bufA[kCgleMaxN];
     __shared__ double2 bufB[kCgleMaxN];
-    const int n = jb.n, levels = jb.levels;
+    constexpr int levels = LV;
+    const int n = jb.n;
     const int i = threadIdx.x;
     const bool act = i < n;
     const double2 zero = cmk<double2>(0.0, 0.0);
     const double2* __restrict__ alpha = jb.tab + n;
     const double2* __restrict__ gamma = alpha + size_t(levels) * n;
-    double2 al[kCgleMaxLevels], ga[kCgleMaxLevels];
+    double2 al[LV], ga[LV];
 #pragma unroll
-    for (int l = 0; l < kCgleMaxLevels; ++l) {
-        al[l] = (act && l < levels) ? alpha[l * n + i] : zero;
-        ga[l] = (act && l < levels) ? gamma[l * n + i] : zero;
+    for (int l = 0; l < LV; ++l) {
+        al[l] = act ? alpha[l * n + i] : zero;
+        ga[l] = act ? gamma[l * n + i] : zero;
     }
     const double2 rm = act ? jb.tab[i] : zero;
     const double2 bi = act ? gamma[size_t(levels) * n + i] : zero;
@@ -84,8 +95,8 @@ __device__ __forceinline__ void cn_integrate(const CnJob& jb, int j) {
                 sincos(jb.omega * jb.dt * double(st + lane), &sn, &cs);
                 ph = cmk<double2>(cs, sn);
             }
-            const int sl = st & (kWave - 1);
-            const double2 e = cmk<double2>(__shfl(ph.x, sl), __shfl(ph.y, sl));
+            const int sl = st & (kWave - 1);  // uniform, < 64
+            const double2 e = cmk<double2>(lane_bcast(ph.x, sl), lane_bcast(ph.y, sl));
             d = cadd(d, cmul(e, fh));
         }
         // implicit half by cyclic reduction, ping-pong between two LDS buffers
@@ -93,13 +104,14 @@ __device__ __forceinline__ void cn_integrate(const CnJob& jb, int j) {
         double2* dst = bufB;
         int s = 1;
 #pragma unroll
-        for (int l = 0; l < kCgleMaxLevels; ++l) {
-            if (l >= levels) break;
+        for (int l = 0; l < LV; ++l) {
             double2* t = src; src = dst; dst = t;  // write into the buffer read last level
             src[i] = d;
             __syncthreads();
-            double2 dm = (i - s >= 0 && act) ? src[i - s] : zero;
-            double2 dp = (i + s < n) ? src[i + s] : zero;
+            // out-of-range neighbours have zero multipliers: clamp the index
+            // instead of branching (the state is finite, so 0 * x = 0 exactly)
+            const double2 dm = src[max(i - s, 0)];
+            const double2 dp = src[min(i + s, n - 1)];
             d = cadd(d, cadd(cmul(al[l], dm), cmul(ga[l], dp)));
             s <<= 1;
         }
@@ -114,12 +126,50 @@ __device__ __forceinline__ void cn_integrate(const CnJob& jb, int j) {
     if (act) jb.out[i] = u;
 }
 
-__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn(CnJob jb) { cn_integrate(jb, 0); }
+// n <= 2^LV nodes, one thread each, rounded up to whole wavefronts: the bound
+// leaves up to 256 registers per lane for LV <= 9.
+constexpr int cn_threads_max(int lv) { return (1 << lv) < kWave ? kWave : (1 << lv); }
+
+template <int LV>
+__global__ __launch_bounds__(cn_threads_max(LV)) void k_cgle_cn(CnJob jb) { cn_integrate<LV>(jb, 0); }
 
 // A batch of integrations (one per workgroup), Krylov step j of each.
-__global__ __launch_bounds__(kCgleMaxN) void k_cgle_cn_batch(const CnJob* __restrict__ jobs, int j) {
+template <int LV>
+__global__ __launch_bounds__(cn_threads_max(LV)) void k_cgle_cn_batch(const CnJob* __restrict__ jobs, int j) {
     const CnJob jb = jobs[blockIdx.x];
-    cn_integrate(jb, j);
+    cn_integrate<LV>(jb, j);
+}
+
+// Launch with the level count as a template argument (jobs == null: the single
+// job `one`).
+template <int LV>
+void launch_cn(const CnJob& one, const CnJob* jobs, int count, int j, int threads, hipStream_t s) {
+    static_assert(cn_threads_max(LV) <= kCgleMaxN, "reduction depth beyond the node limit");
+    if (jobs)
+        hipLaunchKernelGGL(k_cgle_cn_batch<LV>, dim3(count), dim3(threads), 0, s, jobs, j);
+    else
+        hipLaunchKernelGGL(k_cgle_cn<LV>, dim3(1), dim3(threads), 0, s, one);
+}
+
+tsk_status launch_cn_levels(int levels, const CnJob& one, const CnJob* jobs, int count, int j, int threads,
+                            hipStream_t s) {
+    if (levels < 1 || levels > 10 || threads > cn_threads_max(levels) || threads % kWave)
+        return fail(TSK_EINVAL, "CGLE launch shape does not fit the reduction depth");
+    switch (levels) {
+        case 1: launch_cn<1>(one, jobs, count, j, threads, s); break;
+        case 2: launch_cn<2>(one, jobs, count, j, threads, s); break;
+        case 3: launch_cn<3>(one, jobs, count, j, threads, s); break;
+        case 4: launch_cn<4>(one, jobs, count, j, threads, s); break;
+        case 5: launch_cn<5>(one, jobs, count, j, threads, s); break;
+        case 6: launch_cn<6>(one, jobs, count, j, threads, s); break;
+        case 7: launch_cn<7>(one, jobs, count, j, threads, s); break;
+        case 8: launch_cn<8>(one, jobs, count, j, threads, s); break;
+        case 9: launch_cn<9>(one, jobs, count, j, threads, s); break;
+        case 10: launch_cn<10>(one, jobs, count, j, threads, s); break;
+        default: return fail(TSK_EINVAL, "CGLE reduction depth out of range");
+    }
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
 }
 
 // Tables of one Crank-Nicolson propagator: the explicit stencil (main diagonal
@@ -245,9 +295,7 @@ struct CgleOp final : Operator {
         CnJob jb = job(tb, forced, w);
         jb.in = static_cast<const double2*>(x);
         jb.out = static_cast<double2*>(y);
-        hipLaunchKernelGGL(k_cgle_cn, dim3(1), dim3(threads()), 0, stream, jb);
-        TSK_HIP(hipGetLastError());
-        return TSK_OK;
+        return launch_cn_levels(levels, jb, nullptr, 1, 0, threads(), stream);
     }
     tsk_status apply(const void* x, void* y) override { return run(fwd, x, y, resolvent, omega); }
     // M^H: Crank-Nicolson with L_h^H (the two factors of a step commute, so this is
@@ -313,7 +361,7 @@ tsk_status cgle_set_resolvent(Operator* op, double omega, double t_transient) {
 // ---- batches: one workgroup per instance, all instances in one launch ---------------
 struct CgleBatch {
     DevBuf first, second;  // job tables: V -> out (or tmp), and (M^H M) tmp -> w
-    int count = 0, threads = 0;
+    int count = 0, threads = 0, levels = 0;
     bool two = false;
 };
 
@@ -345,6 +393,7 @@ tsk_status cgle_batch_plan(Operator* const* ops, int count, const KryDesc* D_hos
     auto p = CgleBatchPtr(new CgleBatch);
     p->count = count;
     p->threads = c0->threads();
+    p->levels = c0->levels;
     p->two = svd;
     TSK_TRY(p->first.ensure(sizeof(CnJob) * count));
     TSK_HIP(hipMemcpy(p->first.ptr, a.data(), sizeof(CnJob) * count, hipMemcpyHostToDevice));
@@ -357,12 +406,9 @@ tsk_status cgle_batch_plan(Operator* const* ops, int count, const KryDesc* D_hos
 }
 
 tsk_status cgle_batch_matvec(CgleBatch* b, int j, hipStream_t s) {
-    hipLaunchKernelGGL(k_cgle_cn_batch, dim3(b->count), dim3(b->threads), 0, s, b->first.as<CnJob>(), j);
-    TSK_HIP(hipGetLastError());
-    if (b->two) {
-        hipLaunchKernelGGL(k_cgle_cn_batch, dim3(b->count), dim3(b->threads), 0, s, b->second.as<CnJob>(), 0);
-        TSK_HIP(hipGetLastError());
-    }
+    const CnJob none{};
+    TSK_TRY(launch_cn_levels(b->levels, none, b->first.as<CnJob>(), b->count, j, b->threads, s));
+    if (b->two) TSK_TRY(launch_cn_levels(b->levels, none, b->second.as<CnJob>(), b->count, 0, b->threads, s));
     return TSK_OK;
 }
 

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "colfft.hpp"
+#include "colxl.hpp"
 #include "fft.hpp"
 
 namespace tsk {
@@ -82,8 +83,11 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
         return;
     }
 
-    constexpr int LP = padded_len<N>();
-    __shared__ C sA[COLS * NI][LP], sB[COLS * NI][LP], sT[N];
+    // N = 128: cross-lane transforms (colxl.hpp), no LDS passes
+    constexpr bool kXL = col_xl<N>();
+    constexpr int LP = kXL ? 1 : padded_len<N>();
+    constexpr int NBUF = kXL ? 1 : COLS * NI;
+    __shared__ C sA[NBUF][LP], sB[NBUF][LP], sT[N];
     for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
     static_assert(kWave == 64, "one wavefront per workgroup");
     C* Ai[COLS * NI];
@@ -92,14 +96,14 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     C* Bf[COLS];
 #pragma unroll
     for (int c = 0; c < COLS * NI; ++c) {
-        Ai[c] = sA[c];
-        Bi[c] = sB[c];
+        Ai[c] = sA[kXL ? 0 : c];
+        Bi[c] = sB[kXL ? 0 : c];
     }
     // the forward transform must not write the buffer the inverse reads last
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
-        Af[c] = col_result_in_a<N>() ? sB[c] : sA[c];
-        Bf[c] = col_result_in_a<N>() ? sA[c] : sB[c];
+        Af[c] = col_result_in_a<N>() ? sB[kXL ? 0 : c] : sA[kXL ? 0 : c];
+        Bf[c] = col_result_in_a<N>() ? sA[kXL ? 0 : c] : sB[kXL ? 0 : c];
     }
 
     const bool act = lane < NB;
@@ -112,8 +116,10 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
         const int jy = pos <= N / 2 ? pos : pos - N;
         const bool kp = act && jy >= -M && jy <= M;
         keep |= kp ? (1u << r) : 0u;
-        nu[r] = act ? negU[pos] : real(0);
-        oy[r] = (!PROP && act) ? dOdy[pos] : real(0);
+        // grid-side profiles at the positions the inverse transform leaves in this slot
+        const int gpos = kXL ? xl_grid_pos(lane, r) : pos;
+        nu[r] = act ? negU[gpos] : real(0);
+        oy[r] = (!PROP && act) ? dOdy[gpos] : real(0);
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             const bool kc = kp && c < ncol;
@@ -135,9 +141,11 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
     const real invN = real(1.0 / N);
     // twiddles in registers where the register budget allows (N <= 256)
-    constexpr bool kTwReg = N <= 256;
+    constexpr bool kTwReg = N <= 256 && !kXL;
     ColTw<N, C> twr;
     if constexpr (kTwReg) twr.load(sT, lane);
+    XlTw<C> xtw;
+    if constexpr (kXL) xtw.load(sT, lane);
 
     for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
@@ -154,11 +162,13 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
                     v[c][0][r] = cmk<C>(-g1[c][r] * s[c][r].y, g1[c][r] * s[c][r].x);  // i kx (...) s
                     if constexpr (!PROP) v[COLS + c][0][r] = cmk<C>(-g2[c][r] * s[c][r].y, g2[c][r] * s[c][r].x);
                 }
-            if constexpr (kTwReg)
+            if constexpr (kXL)
+                xl_fft_inv<COLS * NI>(v, xtw, lane);
+            else if constexpr (kTwReg)
                 col_fft_mr<N, +1, COLS * NI>(v, Ai, Bi, twr, lane);
             else
                 col_fft_m<N, +1, COLS * NI>(v, Ai, Bi, sT, lane);
-            // product with the base profiles at y = pos
+            // product with the base profiles at the grid positions of the slots
             C pr[COLS][1][RE];
 #pragma unroll
             for (int c = 0; c < COLS; ++c)
@@ -171,7 +181,9 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
                     }
                     pr[c][0][r] = p;
                 }
-            if constexpr (kTwReg)
+            if constexpr (kXL)
+                xl_fft_fwd<COLS>(pr, xtw, lane);
+            else if constexpr (kTwReg)
                 col_fft_mr<N, -1, COLS>(pr, Af, Bf, twr, lane);
             else
                 col_fft_m<N, -1, COLS>(pr, Af, Bf, sT, lane);
@@ -286,7 +298,8 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
         return;
     }
 
-    constexpr int LP = padded_len<N>();
+    constexpr bool kXL = col_xl<N>();
+    constexpr int LP = kXL ? 1 : padded_len<N>();
     __shared__ C sA[2][LP], sB[2][LP], sT[N];
     for (int t = lane; t < N; t += kWave) sT[t] = twg[t];
     C* Ai[1] = {sA[0]};
@@ -311,8 +324,9 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
         const int jy = pos <= N / 2 ? pos : pos - N;
         const bool kp = act && jy >= -M && jy <= M;
         keep |= kp ? (1u << r) : 0u;
-        nu[r] = act ? I.negU[pos] : real(0);
-        oy[r] = (!PROP && act) ? I.dOdy[pos] : real(0);
+        const int gpos = kXL ? xl_grid_pos(lane, r) : pos;
+        nu[r] = act ? I.negU[gpos] : real(0);
+        oy[r] = (!PROP && act) ? I.dOdy[gpos] : real(0);
         const double K2 = kxv * kxv + double(jy) * jy;
         E1[r] = kp ? real(exp(-K2 * dt / Re)) : real(0);
         Eh[r] = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
@@ -326,9 +340,11 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
     __syncthreads();
 
     const real h6 = real(dt / 6.0), h3 = real(dt / 3.0), h2 = real(0.5 * dt), hh = real(dt);
-    constexpr bool kTwReg = N <= 256;
+    constexpr bool kTwReg = N <= 256 && !kXL;
     ColTw<N, C> twr;
     if constexpr (kTwReg) twr.load(sT, lane);
+    XlTw<C> xtw;
+    if constexpr (kXL) xtw.load(sT, lane);
 
     for (int st = 0; st < nsteps; ++st) {
 #pragma unroll 1
@@ -352,7 +368,9 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
                     v[0][0][r] = cmk<C>(h6 * E1[r] * z[r].x + h2 * Eh[r] * sprev[r].x,
                                         h6 * E1[r] * z[r].y + h2 * Eh[r] * sprev[r].y);
             }
-            if constexpr (kTwReg)
+            if constexpr (kXL)
+                xl_fft_inv<1>(v, xtw, lane);
+            else if constexpr (kTwReg)
                 col_fft_mr<N, +1, 1>(v, Ai, Bi, twr, lane);
             else
                 col_fft_m<N, +1, 1>(v, Ai, Bi, sT, lane);
@@ -362,7 +380,9 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
                 pr[0][0][r] = cmk<C>(nu[r] * v[0][0][r].x, nu[r] * v[0][0][r].y);
                 if constexpr (!PROP) pr[NF - 1][0][r] = cmk<C>(oy[r] * v[0][0][r].x, oy[r] * v[0][0][r].y);
             }
-            if constexpr (kTwReg)
+            if constexpr (kXL)
+                xl_fft_fwd<NF>(pr, xtw, lane);
+            else if constexpr (kTwReg)
                 col_fft_mr<N, -1, NF>(pr, Af, Bf, twr, lane);
             else
                 col_fft_m<N, -1, NF>(pr, Af, Bf, sT, lane);

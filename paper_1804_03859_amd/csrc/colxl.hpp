@@ -107,7 +107,7 @@ template <int H, typename C> __device__ inline C lane_xor_c(C v) { return cmk<C>
 // Per-lane twiddles (forward sign; the inverse uses their conjugates).
 template <typename C> struct XlTw {
     C in;     // e^{-2 pi i L / 128} (slot 1 of the in-lane step)
-    C lv[6];  // level h = 1 << l: W for h >= 4, the masked W' for h = 1, 2
+    C lv[6];  // level h = 1 << l: W for h >= 4, the masked W' for h = 2 (1 for h = 1)
     __device__ void load(const C* tw, int lane) {  // tw[t] = e^{-2 pi i t / 128}, t < 128
         in = tw[lane];
 #pragma unroll
@@ -152,7 +152,8 @@ __device__ inline void xl_dif_xor(C (&v)[COLS][1][2], const C& w, int lane) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const C p = lane_xor_c<H>(v[c][0][q]);
-            v[c][0][q] = cmul(cmk<C>(p.x + sg * v[c][0][q].x, p.y + sg * v[c][0][q].y), ws);
+            const C t = cmk<C>(p.x + sg * v[c][0][q].x, p.y + sg * v[c][0][q].y);
+            v[c][0][q] = H == 1 ? t : cmul(t, ws);  // W' = 1 on every lane for h = 1
         }
 }
 template <int H, int SIGN, int COLS, typename C>
@@ -164,7 +165,7 @@ __device__ inline void xl_dit_xor(C (&v)[COLS][1][2], const C& w, int lane) {
     for (int c = 0; c < COLS; ++c)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const C z = cmul(v[c][0][q], ws);
+            const C z = H == 1 ? v[c][0][q] : cmul(v[c][0][q], ws);
             const C p = lane_xor_c<H>(z);
             v[c][0][q] = cmk<C>(p.x + sg * z.x, p.y + sg * z.y);
         }

@@ -152,9 +152,8 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
         for (int c = 0; c < COLS; ++c)
 #pragma unroll
             for (int r = 0; r < RE; ++r) s[c][r] = w[c][r];
-        // the cross-lane variant unrolls the four stages (no register moves at a
-        // stage switch); the LDS variants keep one copy of the stage body
-#pragma unroll(kXL ? 4 : 1)
+        // the four stages unrolled: no register moves at the stage switches
+#pragma unroll 4
         for (int stage = 0; stage < 4; ++stage) {
             C v[COLS * NI][1][RE];
 #pragma unroll

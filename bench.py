@@ -65,7 +65,7 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
-COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colstep.hpp")
+COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colxl.hpp", "colstep.hpp")
 GENERAL_SOURCES = ("common.hpp", "fft.hpp", "kolmo2d.hip")
 
 

@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
     if constexpr (kXL) xtw.load(sT, lane);
 
     for (int st = 0; st < nsteps; ++st) {
-#pragma unroll 1
+#pragma unroll 4
         for (int stage = 0; stage < 4; ++stage) {
             // stage input t (kept modes only)
             C v[1][1][RE];

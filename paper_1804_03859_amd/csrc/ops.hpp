@@ -41,7 +41,7 @@ enum class StateKind { Complex64x2, Real64, Real32 };  // double2 / double / flo
 struct ArnoldiWork {
     // Ritz analyses of consecutive steps run concurrently on kSlots side
     // streams, each with its own eigensolver outputs (see arnoldi.hip).
-    static constexpr int kSlots = 8;
+    static constexpr int kSlots = 4;
     DevBuf V;         // (m+1) x n state vectors
     DevBuf H;         // (m+1) x m complex128, column-major
     DevBuf w;         // matvec output (state type)

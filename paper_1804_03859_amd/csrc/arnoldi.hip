@@ -12,12 +12,12 @@
 // |Im lambda| T < pi/2, the four-samples-per-period rule of Sec. 3.2.1).
 //
 // Overlap: as soon as v_{j+1} exists, the matvec M v_{j+1} is launched on the
-// operator stream while the Ritz analysis of H_j runs on a side stream (one
-// wavefront per instance, so it barely competes for compute units).  The
-// analyses of consecutive steps rotate over kSlots side streams with their own
-// output buffers, so when an analysis takes longer than a matvec, later steps
-// (CGS2 and matvec) keep the operator stream busy while up to kSlots analyses
-// are in flight.  The host consumes the analyses in step order and stops an
+// operator stream while the Ritz analysis of H_j waits for a free analysis
+// stream (one wavefront per instance and step, so it barely competes for
+// compute units).  Up to kSlots consecutive steps are in flight, each with its
+// own output slot; the steps that became ready while both analysis streams
+// were busy are analysed together by one launch, so a backlog never waits for
+// hardware queues.  The host consumes the analyses in step order and stops an
 // instance at the first step whose H_j satisfies the stop test, exactly as a
 // check after every step would; work already launched for later steps is
 // discarded (neither counted nor used).  Batched Navier-Stokes instances share
@@ -176,7 +176,10 @@ tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
     for (int t = 0; t < NS; ++t) {
         if (!L.ev_cgs[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_cgs[t], hipEventDisableTiming));
         if (!L.ev_eig[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_eig[t], hipEventDisableTiming));
-        if (!L.side[t]) TSK_HIP(hipStreamCreateWithFlags(&L.side[t], hipStreamNonBlocking));
+        if (t < ArnoldiWork::kAnaStreams && !L.side[t])
+            TSK_HIP(hipStreamCreateWithFlags(&L.side[t], hipStreamNonBlocking));
+        if (t < ArnoldiWork::kAnaStreams && !L.ev_ana[t])
+            TSK_HIP(hipEventCreateWithFlags(&L.ev_ana[t], hipEventDisableTiming));
     }
     TSK_TRY(L.batch_rr.ensure(size_t(nrr) * sizeof(RitzResult)));
     if (L.rr_host_count < nrr) {
@@ -284,36 +287,64 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     };
 
     // ---- Arnoldi steps ------------------------------------------------------------------------
-    // enqueue(j): CGS2 of step j (table j % NS), the speculative matvec of step
-    // j+1, and the Ritz analysis of H_j on side stream j % NS.  Pending analyses
-    // are consumed in step order; a new step is enqueued when the analyses are
-    // consumed, or, while up to NS are in flight, as soon as the operator stream
-    // has finished the last matvec it was given.
+    // enqueue(j): CGS2 of step j (output slot j % NS) and the speculative matvec
+    // of step j+1 on the operator stream; step j then waits in `ready` for its
+    // Ritz analysis.  launch_ready(): when one of the kAnaStreams analysis
+    // streams is idle, all ready steps go to it in one launch (one workgroup
+    // per step and instance), followed by their collection and copy to the
+    // host.  Analyses are consumed in step order; a new step is enqueued when
+    // the analyses are consumed, or, while fewer than NS steps are in flight,
+    // as soon as the operator stream has finished the last matvec it was given.
+    constexpr int NA = ArnoldiWork::kAnaStreams;
+    static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     std::vector<int> final_slot(count, 0);
-    std::deque<int> pend;
+    std::deque<int> pend, ready;
     int next = 0, steps_run = 0, remaining = count;
+    bool ana_used[NA] = {};  // analysis stream a has a batch recorded in ev_ana[a]
     auto enqueue = [&](int j) -> tsk_status {
-        const int p = j + 1, t = j % NS;
-        const KryDesc* Dt = table(t);
-        cgs2_step<TS>(Dt, count, nblk_max, nmax, j, s);
+        const int t = j % NS;
+        cgs2_step<TS>(table(t), count, nblk_max, nmax, j, s);
         TSK_HIP(hipEventRecord(L.ev_cgs[t], s));
         if (j + 1 < m) {
             TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
             TSK_TRY(matvec(j + 1));
             TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1) + 1], s));
         }
-        const hipStream_t st = L.side[t];
-        TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[t], 0));
-        if (svd)
-            TSK_TRY(tridiag_ritz_launch(Dt, count, p, k < p ? k : p, tol, st));
-        else
-            TSK_TRY(hess_ritz_launch(Dt, count, p, k < p ? k : p, tol, false, st, kRealH));
-        hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, Dt, count,
-                           L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
-        TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,
-                               size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, st));
-        TSK_HIP(hipEventRecord(L.ev_eig[t], st));
-        pend.push_back(j);
+        ready.push_back(j);
+        return TSK_OK;
+    };
+    auto launch_ready = [&]() -> tsk_status {
+        if (ready.empty()) return TSK_OK;
+        int a = -1;
+        for (int c = 0; c < NA && a < 0; ++c) {
+            if (!ana_used[c]) { a = c; break; }
+            const hipError_t q = hipEventQuery(L.ev_ana[c]);
+            if (q == hipSuccess) a = c;
+            else if (q != hipErrorNotReady) TSK_HIP(q);
+        }
+        if (a < 0) return TSK_OK;
+        const hipStream_t st = L.side[a];
+        StepSet ss{};
+        const int n = int(ready.size());
+        for (int i = 0; i < n; ++i) {
+            ss.tab[i] = table(ready[i] % NS);
+            ss.p[i] = ready[i] + 1;
+        }
+        // the Gram-Schmidt of the newest step implies that of the older ones (one stream)
+        TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[ready.back() % NS], 0));
+        TSK_TRY(ritz_steps_launch(ss, n, count, k, tol, svd, kRealH, st));
+        for (int i = 0; i < n; ++i) {
+            const int t = ready[i] % NS;
+            hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, table(t), count,
+                               L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
+            TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,
+                                   size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, st));
+        }
+        for (int i = 0; i < n; ++i) TSK_HIP(hipEventRecord(L.ev_eig[ready[i] % NS], st));
+        TSK_HIP(hipEventRecord(L.ev_ana[a], st));
+        ana_used[a] = true;
+        for (int i = 0; i < n; ++i) pend.push_back(ready[i]);
+        ready.clear();
         return TSK_OK;
     };
     auto consume = [&](int j) {
@@ -340,18 +371,21 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     TSK_TRY(matvec(0));
     TSK_HIP(hipEventRecord(L.ev_apply[1], s));
     TSK_TRY(enqueue(next++));
-    while (!pend.empty()) {
-        const int jo = pend.front();
-        const hipError_t q = hipEventQuery(L.ev_eig[jo % NS]);
-        if (q == hipSuccess) {
-            pend.pop_front();
-            consume(jo);
-            if (remaining == 0) break;
-            if (pend.empty() && next < m) TSK_TRY(enqueue(next++));
-            continue;
+    while (!pend.empty() || !ready.empty()) {
+        TSK_TRY(launch_ready());
+        if (!pend.empty()) {
+            const int jo = pend.front();
+            const hipError_t q = hipEventQuery(L.ev_eig[jo % NS]);
+            if (q == hipSuccess) {
+                pend.pop_front();
+                consume(jo);
+                if (remaining == 0) break;
+                if (pend.empty() && ready.empty() && next < m) TSK_TRY(enqueue(next++));
+                continue;
+            }
+            if (q != hipErrorNotReady) TSK_HIP(q);
         }
-        if (q != hipErrorNotReady) TSK_HIP(q);
-        if (next < m && int(pend.size()) < NS) {
+        if (next < m && int(pend.size() + ready.size()) < NS) {
             const hipError_t qm = hipEventQuery(L.ev_apply[2 * next + 1]);  // matvec of step `next` done
             if (qm == hipSuccess) {
                 TSK_TRY(enqueue(next++));
@@ -361,7 +395,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         }
         std::this_thread::yield();
     }
-    for (int t = 0; t < NS; ++t) TSK_HIP(hipStreamSynchronize(L.side[t]));  // discarded analyses
+    for (int a = 0; a < NA; ++a) TSK_HIP(hipStreamSynchronize(L.side[a]));  // discarded analyses
 
     // ---- outputs --------------------------------------------------------------------------------
     TSK_HIP(hipStreamSynchronize(s));  // drains discarded speculative matvecs

@@ -174,8 +174,10 @@ __device__ inline void select_wanted(const double2* __restrict__ mu, const doubl
 // otherwise only the last row of Z is tracked (all the residuals need) and the
 // wanted Ritz coordinates are computed afterwards by inverse iteration.
 template <bool FULLZ>
-__global__ __launch_bounds__(kHT) void k_hess_ritz(const KryDesc* __restrict__ Dv, int p, int k, double tol) {
-    const KryDesc& dsc = Dv[blockIdx.x];
+__global__ __launch_bounds__(kHT) void k_hess_ritz(StepSet ss, int kreq, double tol) {
+    const int p = ss.p[blockIdx.y];
+    const int k = kreq < p ? kreq : p;
+    const KryDesc& dsc = ss.tab[blockIdx.y][blockIdx.x];
     if (!dsc.active) return;
     const double2* __restrict__ H = dsc.H;
     const int ldh = dsc.ldh;
@@ -823,9 +825,10 @@ __device__ inline void real_ritz(const double* Tr, const int* blk, const double*
     }
 }
 
-__global__ __launch_bounds__(kHT) void k_hess_ritz_real(const KryDesc* __restrict__ Dv, int p, int k, double tol,
-                                                        int standalone) {
-    const KryDesc& dsc = Dv[blockIdx.x];
+__global__ __launch_bounds__(kHT) void k_hess_ritz_real(StepSet ss, int kreq, double tol, int standalone) {
+    const int p = ss.p[blockIdx.y];
+    const int k = kreq < p ? kreq : p;
+    const KryDesc& dsc = ss.tab[blockIdx.y][blockIdx.x];
     if (!dsc.active) return;
     const double2* __restrict__ H = dsc.H;
     const int ldh = dsc.ldh;
@@ -1390,8 +1393,10 @@ __global__ __launch_bounds__(kHT) void k_ks_contract(const KryDesc* __restrict__
 // solver: mu = (theta, 0), residual |beta_p Z[p-1][i]|, wanted set; and the unit Ritz
 // coordinates of the wanted values (columns of Z) in S[s*p + r], so the Ritz vectors
 // of the final step need no inverse iteration.
-__global__ __launch_bounds__(kHT) void k_tridiag_ritz(const KryDesc* __restrict__ Dv, int p, int k, double tol) {
-    const KryDesc& dsc = Dv[blockIdx.x];
+__global__ __launch_bounds__(kHT) void k_tridiag_ritz(StepSet ss, int kreq, double tol) {
+    const int p = ss.p[blockIdx.y];
+    const int k = kreq < p ? kreq : p;
+    const KryDesc& dsc = ss.tab[blockIdx.y][blockIdx.x];
     if (!dsc.active) return;
     const double2* __restrict__ H = dsc.H;
     const int ldh = dsc.ldh;
@@ -1507,7 +1512,7 @@ __global__ __launch_bounds__(kHT) void k_tridiag_ritz(const KryDesc* __restrict_
 }  // namespace
 
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
-                            bool real_h) {
+                            bool real_h, bool attrs_only) {
     if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Hessenberg size must be in [1, 96]");
     static bool attr_set = false;
     if (!attr_set) {
@@ -1519,32 +1524,65 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
                                     int(kMaxKrylov * kMaxKrylov * sizeof(double))));
         attr_set = true;
     }
+    if (attrs_only) return TSK_OK;
+    StepSet one{};
+    one.tab[0] = D;
+    one.p[0] = p;
     if (real_h) {
         // full: the standalone entry point (beta from scal[2]; values and residuals only)
-        hipLaunchKernelGGL(k_hess_ritz_real, dim3(count), dim3(kHT), size_t(p) * p * sizeof(double), s, D, p, k, tol,
-                           full ? 1 : 0);
+        hipLaunchKernelGGL(k_hess_ritz_real, dim3(count, 1), dim3(kHT), size_t(p) * p * sizeof(double), s, one, k,
+                           tol, full ? 1 : 0);
     } else {
         const size_t lds = size_t(p) * p * sizeof(double2);
         if (full)
-            hipLaunchKernelGGL(k_hess_ritz<true>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
+            hipLaunchKernelGGL(k_hess_ritz<true>, dim3(count, 1), dim3(kHT), lds, s, one, k, tol);
         else
-            hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count), dim3(kHT), lds, s, D, p, k, tol);
+            hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count, 1), dim3(kHT), lds, s, one, k, tol);
     }
     TSK_HIP(hipGetLastError());
     return TSK_OK;
 }
 
-tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s) {
-    if (p < 1 || p > kMaxKrylov) return fail(TSK_EINVAL, "Lanczos order must be in [1, 96]");
+tsk_status ritz_steps_launch(const StepSet& ss, int n, int count, int k, double tol, bool svd, bool real_h,
+                             hipStream_t s) {
+    if (n < 1 || n > StepSet::kMax) return fail(TSK_EINVAL, "step batch size out of range");
+    int pmax = 0;
+    for (int i = 0; i < n; ++i) {
+        if (ss.p[i] < 1 || ss.p[i] > kMaxKrylov) return fail(TSK_EINVAL, "Krylov order must be in [1, 96]");
+        pmax = ss.p[i] > pmax ? ss.p[i] : pmax;
+    }
+    if (svd) return tridiag_ritz_launch_steps(ss, n, count, pmax, k, tol, s);
+    TSK_TRY(hess_ritz_launch(ss.tab[0], count, ss.p[0], k, tol, false, s, real_h, /*attrs_only=*/true));
+    if (real_h)
+        hipLaunchKernelGGL(k_hess_ritz_real, dim3(count, n), dim3(kHT), size_t(pmax) * pmax * sizeof(double), s, ss,
+                           k, tol, 0);
+    else
+        hipLaunchKernelGGL(k_hess_ritz<false>, dim3(count, n), dim3(kHT), size_t(pmax) * pmax * sizeof(double2), s,
+                           ss, k, tol);
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
+}
+
+tsk_status tridiag_ritz_launch_steps(const StepSet& ss, int n, int count, int pmax, int k, double tol,
+                                     hipStream_t s) {
+    if (pmax < 1 || pmax > kMaxKrylov) return fail(TSK_EINVAL, "Lanczos order must be in [1, 96]");
     static bool attr_set = false;
     if (!attr_set) {
         TSK_HIP(hipFuncSetAttribute((const void*)k_tridiag_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     int(kMaxKrylov * kMaxKrylov * sizeof(double))));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_tridiag_ritz, dim3(count), dim3(kHT), size_t(p) * p * sizeof(double), s, D, p, k, tol);
+    hipLaunchKernelGGL(k_tridiag_ritz, dim3(count, n), dim3(kHT), size_t(pmax) * pmax * sizeof(double), s, ss, k,
+                       tol);
     TSK_HIP(hipGetLastError());
     return TSK_OK;
+}
+
+tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s) {
+    StepSet one{};
+    one.tab[0] = D;
+    one.p[0] = p;
+    return tridiag_ritz_launch_steps(one, 1, count, p, k, tol, s);
 }
 
 tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s) {

@@ -39,9 +39,11 @@ struct DevBuf {
 enum class StateKind { Complex64x2, Real64, Real32 };  // double2 / double / float
 
 struct ArnoldiWork {
-    // Ritz analyses of consecutive steps run concurrently on kSlots side
+    // Ritz analyses of up to kSlots consecutive steps are in flight at once, in
+    // batched launches on kAnaStreams side streams
     // streams, each with its own eigensolver outputs (see arnoldi.hip).
-    static constexpr int kSlots = 4;
+    static constexpr int kSlots = 8;
+    static constexpr int kAnaStreams = 2;
     DevBuf V;         // (m+1) x n state vectors
     DevBuf H;         // (m+1) x m complex128, column-major
     DevBuf w;         // matvec output (state type)
@@ -69,7 +71,8 @@ struct ArnoldiWork {
     std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
     hipEvent_t ev_cgs[kSlots] = {};    // basis vector j+1 and H column j ready (slot j % kSlots)
     hipEvent_t ev_eig[kSlots] = {};    // Ritz analysis of step j copied to the host
-    hipStream_t side[kSlots] = {};     // Ritz analyses overlap the next matvecs
+    hipStream_t side[kSlots] = {};     // Ritz analyses overlap the next matvecs (first kAnaStreams used)
+    hipEvent_t ev_ana[kAnaStreams] = {};  // last analysis batch of each analysis stream done
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
         for (hipEvent_t e : ev_apply) (void)hipEventDestroy(e);
@@ -78,6 +81,8 @@ struct ArnoldiWork {
             if (ev_eig[t]) (void)hipEventDestroy(ev_eig[t]);
             if (side[t]) (void)hipStreamDestroy(side[t]);
         }
+        for (int a = 0; a < kAnaStreams; ++a)
+            if (ev_ana[a]) (void)hipEventDestroy(ev_ana[a]);
     }
 };
 
@@ -197,11 +202,27 @@ tsk_status ks_contract_standalone(const double* H, int ldh, int m, double beta, 
 // the standalone real solver (values and residuals only, beta from scal[2]).
 struct KryDesc;
 tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, bool full, hipStream_t s,
-                            bool real_h = false);
+                            bool real_h = false, bool attrs_only = false);
+// Several Krylov steps analysed by one launch (blockIdx.y = step, blockIdx.x =
+// instance): step i reads the descriptor table tab[i] (its output slot) and its
+// order p[i].  The Arnoldi driver gathers the steps whose Gram-Schmidt has
+// finished into one launch, so the analyses of a backlog run side by side
+// without a hardware queue each.
+struct StepSet {
+    static constexpr int kMax = 8;
+    const KryDesc* tab[kMax];
+    int p[kMax];
+};
+// The driver's analysis of n steps: tridiagonal (svd), real Hessenberg (real_h)
+// or complex Hessenberg; no eigenvector accumulation.
+tsk_status ritz_steps_launch(const StepSet& ss, int n, int count, int k, double tol, bool svd, bool real_h,
+                             hipStream_t s);
 // Lanczos Ritz analysis (symmetric tridiagonal T_p from H's diagonal and
 // subdiagonal): as hess_ritz_launch, plus the unit Ritz coordinates of the
 // wanted values in S[s*p + r].
 tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s);
+tsk_status tridiag_ritz_launch_steps(const StepSet& ss, int n, int count, int pmax, int k, double tol,
+                                     hipStream_t s);
 // Krylov-Schur analysis and contraction of the order-m factorisation of the
 // single instance D[0] (real H): contract = 0 analysis only, 1 unless the stop
 // test is met, 2 always.  Results in D[0].rr (kept, beta), H and ksW.

@@ -38,6 +38,19 @@ def colstep_flops(N, nsteps):
     return M * 4 * nsteps * per_stage
 
 
+def bloch_flops(N, nsteps, sectors=4):
+    """Algorithmic flops of one matvec of the Bloch-sector stepper: per dealiased
+    column kx >= 1 and RK stage, in each of the four sectors one inverse and one
+    forward complex FFT of length N/4 (5 L log2 L each), the product with the
+    base profile (2 flops per grid point) and the spectral bookkeeping (12 flops
+    per kept mode)."""
+    M = (N - 1) // 3
+    NM = 2 * M + 1
+    L = N // sectors
+    per_stage = sectors * 2 * 5 * L * math.log2(L) + 2 * N + 12 * NM
+    return M * 4 * nsteps * per_stage
+
+
 def cpu_baseline(seconds=12.0):
     """The CPU oracle (NumPy FP64, single thread) on a bounded sample of the same
     workload: as many full matvecs (200 IF-RK4 steps each) of the 128^2 operator
@@ -65,7 +78,7 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
-COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colxl.hpp", "colstep.hpp")
+COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colxl.hpp", "colstep.hpp", "colbloch.hpp")
 GENERAL_SOURCES = ("common.hpp", "fft.hpp", "kolmo2d.hip")
 
 
@@ -175,10 +188,18 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     tsgp_step = nmv * nsteps * N * N
     ms_apply = sum(q["ms_apply"] for q in results) / args.steps
     launch_ms = ms_apply / nmv
-    flops = colstep_flops(N, nsteps)
+    rt = "double" if prec == tsk.TSK_FP64 else "float"
+    stepper = tsk.get_tuning(op)  # -1: the Bloch-sector stepper, else columns per wavefront
+    if stepper == -1:
+        flops = bloch_flops(N, nsteps)
+        kernel = f"k_colstep_bloch<{rt}>"
+        traffic = measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md") if prec == tsk.TSK_FP64 else None
+    else:
+        flops = colstep_flops(N, nsteps)
+        kernel = f"k_colstep<{rt},{N},true>"
+        traffic = None
     achieved = flops / (launch_ms / 1e3) / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if prec == tsk.TSK_FP64 else FP32_VECTOR_PEAK_TFLOPS
-    rt = "double" if prec == tsk.TSK_FP64 else "float"
     return {
         "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
         "value": tsgp_step / (ms_per_step / 1e3),
@@ -194,14 +215,15 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
         "data": "synthetic",
         "config": {"workload": f"linearized Kolmogorov flow {N}x{N} {dtype_name.upper()}, Re=20, alpha=0.5, "
                                f"IF-RK4 dt=0.005 T=1, Arnoldi m={m} k={k} tol=1e-8, seeded N(0,1) start",
-                   "n_matvec": nmv, "status": r["status"], "columns_per_wave": tsk.get_tuning(op),
+                   "n_matvec": nmv, "status": r["status"], "stepper": "bloch sectors" if stepper == -1 else
+                   f"{stepper} column(s) per wavefront",
                    "wall_time_to_6_pairs_s": ms_per_step / 1e3,
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],
                    "max_residual": float(np.max(r["res"]))},
-        "roofline": {"bound": "alu", "kernel": f"k_colstep<{rt},{N},true>", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": None},
+                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": traffic},
         "cpu_baseline": None,
     }
 
@@ -241,7 +263,8 @@ def run_krylov_schur(args, tsk, W, np, torch):
     tsgp_step = nmv * nsteps * N * N
     ms_apply = sum(q["ms_apply"] for q in results) / args.steps
     launch_ms = ms_apply / nmv
-    flops = colstep_flops(N, nsteps)
+    bloch = tsk.get_tuning(op) == -1
+    flops = bloch_flops(N, nsteps) if bloch else colstep_flops(N, nsteps)
     achieved = flops / (launch_ms / 1e3) / 1e12
     table = {}
     for m in (16, 24, 48):
@@ -265,10 +288,10 @@ def run_krylov_schur(args, tsk, W, np, torch):
                    "non_matvec_ms": ms_per_step - ms_apply,
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],
                    "max_residual": float(np.max(r["res"])), "subspace_table": table},
-        "roofline": {"bound": "alu", "kernel": f"k_colstep<double,{N},true>", "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "launch_ms": launch_ms, "flops_per_launch": flops,
-                     "traffic": measured_traffic("k_colstep_kolmo128_fp64_hbm_traffic.md")},
+        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch<double>" if bloch else f"k_colstep<double,{N},true>",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,
+                     "traffic": measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md") if bloch else None},
         "cpu_baseline": None,
     }
 
@@ -311,7 +334,10 @@ def run_optimal(args, tsk, W, np, torch):
     tsgp_step = nint * nsteps * N * N
     ms_apply = sum(q["ms_apply"] for q in results) / args.steps
     launch_ms = ms_apply / nint
-    flops = colstep_flops(N, nsteps)  # the adjoint stage has the same transforms as the forward one
+    # forward integrations by the operator's stepper (the Bloch sectors at 128^2), adjoint ones by the
+    # transposed column stepper (128-point transforms): flops averaged over the two kinds
+    bloch = tsk.get_tuning(op) == -1
+    flops = 0.5 * (bloch_flops(N, nsteps) + colstep_flops(N, nsteps)) if bloch else colstep_flops(N, nsteps)
     achieved = flops / (launch_ms / 1e3) / 1e12
     gains = {}
     for T in (0.25, 0.5, 2.0, 4.0):
@@ -332,7 +358,8 @@ def run_optimal(args, tsk, W, np, torch):
                    "sigma": [float(v) for v in r["sigma"]], "gain": [float(v) for v in r["gain"]],
                    "max_residual": float(np.max(r["res"])),
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3), "gain_curve": gains},
-        "roofline": {"bound": "alu", "kernel": f"k_colstep<double,{N},true> + k_colstep_adj<double,{N},true>",
+        "roofline": {"bound": "alu", "kernel": ("k_colstep_bloch<double>" if bloch else f"k_colstep<double,{N},true>")
+                     + f" + k_colstep_adj<double,{N},true>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,
                      "traffic": None},
@@ -693,7 +720,6 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "kolmo128":
         out = run_single(args, tsk, W, np, torch, W.KOLMO_128_FP64, tsk.TSK_FP64, "f64")
-        out["roofline"]["traffic"] = measured_traffic("k_colstep_kolmo128_fp64_hbm_traffic.md")
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline()
     elif args.workload == "copy":

@@ -34,6 +34,7 @@
 #include <mutex>
 #include <tuple>
 
+#include "colbloch.hpp"
 #include "colstep.hpp"
 #include "kolmo2d.hpp"
 #include "krylov.hpp"
@@ -350,6 +351,7 @@ struct KolmoOp final : Operator {
     int nsteps = 0;
     bool prop = false;
     double cprop = 0.0;
+    bool bloch = false;  // N = 128 and a quarter-period one-harmonic profile: Bloch-sector stepper
     DevBuf tw, negU, dOdy, Z;
     DevBuf tasks[3];   // single-instance task lists for 1 and 2 columns per wavefront
     int ntasks[3] = {0, 0, 0};
@@ -428,6 +430,17 @@ struct KolmoOp final : Operator {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
         if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
+        if (bloch && force_cols == 0) {
+            const dim3 grid(1 + 2 * M);
+            if (prec == TSK_FP32)
+                hipLaunchKernelGGL(k_colstep_bloch<float>, grid, dim3(kWave), 0, stream, inst<float>(x, 0, y, nullptr),
+                                   tw.as<cplx<float>>());
+            else
+                hipLaunchKernelGGL(k_colstep_bloch<double>, grid, dim3(kWave), 0, stream,
+                                   inst<double>(x, 0, y, nullptr), tw.as<cplx<double>>());
+            TSK_HIP(hipGetLastError());
+            return TSK_OK;
+        }
         auto launch = [&](int c) {
             if (prec == TSK_FP32)
                 dispatch_colstep<float>(N, inst<float>(x, 0, y, nullptr), nullptr, tasks[c].as<ColTask>(), ntasks[c],
@@ -638,6 +651,25 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
     for (int i = 0; i < N; ++i) dev = std::max(dev, std::fabs(dOdy[i] - c * U[i]));
     k->prop = uu > 0.0 && dev <= 1e-13 * std::max(omax, 1e-300);
     k->cprop = k->prop ? c : 0.0;
+    // Bloch sectors (colbloch.hpp): N = 128, profile of period 32 samples whose
+    // 32-point spectrum has no harmonic beyond the first
+    k->bloch = false;
+    if (k->prop && N == 128) {
+        double umax = 0.0;
+        for (int i = 0; i < N; ++i) umax = std::max(umax, std::fabs(nu[i]));
+        bool ok = umax > 0.0;
+        for (int i = 32; i < N && ok; ++i) ok = std::fabs(nu[i] - nu[i % 32]) <= 1e-13 * umax;
+        const double pi = 3.14159265358979323846264338327950288;
+        for (int h = 2; h <= 16 && ok; ++h) {
+            double cr = 0.0, ci = 0.0;
+            for (int b = 0; b < 32; ++b) {
+                cr += nu[b] * std::cos(2.0 * pi * h * b / 32.0);
+                ci -= nu[b] * std::sin(2.0 * pi * h * b / 32.0);
+            }
+            ok = std::hypot(cr, ci) <= 1e-12 * 32.0 * umax;
+        }
+        k->bloch = ok;
+    }
     TSK_TRY(k->upload_real(k->negU, nu));
     TSK_TRY(k->upload_real(k->dOdy, oy));
     gen2d_free(k->gen);
@@ -675,6 +707,10 @@ tsk_status kolmo_get_tuning(const Operator* op, int* cols) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);
     if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
     int c = std::min(k->force_cols, max_cols(k->N));
+    if (c == 0 && k->bloch && !k->gen) {
+        *cols = -1;  // the Bloch-sector stepper
+        return TSK_OK;
+    }
     if (c == 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(TuneKey{k->N, k->prec == TSK_FP32, k->prop, size_bucket(k->M + 1)});
@@ -690,6 +726,11 @@ bool kolmo_parallel(const Operator* op) {
 }
 
 bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != nullptr; }
+
+bool kolmo_bloch(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k && !k->gen && k->bloch && k->force_cols == 0;
+}
 
 int kolmo_cutoff(const Operator* op) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);

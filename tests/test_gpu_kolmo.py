@@ -215,8 +215,8 @@ def test_fp32_precision_form_within_stated_bound(tsk, N, m):
     assert match_sets(r["lam"], lam_o) <= FP32_LAMBDA_BOUND
 
 
-@pytest.mark.parametrize("N,prec,base", [(128, 0, "kolmogorov"), (48, 0, "general"), (256, 1, "kolmogorov"),
-                                         (96, 1, "general")])
+@pytest.mark.parametrize("N,prec,base", [(128, 0, "kolmogorov"), (128, 1, "kolmogorov"), (128, 0, "general"),
+                                         (48, 0, "general"), (256, 1, "kolmogorov"), (96, 1, "general")])
 def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
     print(f"column-pair variant N={N} prec={prec} base={base}", flush=True)
     if base == "kolmogorov":
@@ -237,8 +237,16 @@ def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
     assert torch.equal(outs[0], outs[1])
     tsk.set_tuning(op, 0)
     y_ = op.new_state()
-    tsk.apply(op, x, y_)                      # autotuned: one of the two, same bits
-    assert torch.equal(y_, outs[0])
-    assert tsk.get_tuning(op) in (1, 2)
+    tsk.apply(op, x, y_)
+    if N == 128 and base == "kolmogorov":
+        # the default at 128^2 with the quarter-period base is the Bloch-sector
+        # stepper: the same operator, other rounding
+        tol = 1e-13 if prec == 0 else 2e-6
+        assert torch.max(torch.abs(y_ - outs[0])).item() <= tol * torch.max(torch.abs(outs[0])).item()
+        assert not torch.equal(y_, outs[0])
+        assert tsk.get_tuning(op) == -1
+    else:
+        assert torch.equal(y_, outs[0])       # autotuned: one of the two, same bits
+        assert tsk.get_tuning(op) in (1, 2)
     with pytest.raises(tsk.TskError):
         tsk.set_tuning(op, 3)

@@ -87,8 +87,8 @@ tsk_status make_desc(Operator* op, int m, int k, int NS, void* ritz, KryDesc& d)
     TSK_TRY(W.H.ensure(size_t(m + 1) * m * sizeof(double2)));
     TSK_TRY(W.w.ensure(size_t(n) * sizeof(TS)));
     TSK_TRY(W.w64.ensure(size_t(n) * sizeof(A)));
-    TSK_TRY(W.partial.ensure(size_t(nblk) * (m + 1) * sizeof(double2)));
-    TSK_TRY(W.pnrm.ensure(size_t(nblk) * sizeof(double)));
+    TSK_TRY(W.partial.ensure(2 * size_t(nblk) * (m + 1) * sizeof(double2)));
+    TSK_TRY(W.pnrm.ensure(2 * size_t(nblk) * sizeof(double)));
     TSK_TRY(W.h.ensure(size_t(m + 1) * sizeof(double2)));
     TSK_TRY(W.scal.ensure(64 * sizeof(double)));
     TSK_TRY(W.eigS.ensure(size_t(NS) * m * m * sizeof(double2)));
@@ -108,6 +108,8 @@ tsk_status make_desc(Operator* op, int m, int k, int NS, void* ritz, KryDesc& d)
     d.H = W.H.as<double2>();
     d.partial = W.partial.as<double2>();
     d.pnrm = W.pnrm.as<double>();
+    d.partial2 = d.partial + size_t(nblk) * (m + 1);
+    d.pnrm2 = d.pnrm + nblk;
     d.h = W.h.as<double2>();
     d.scal = W.scal.as<double>();
     d.Z = nullptr;
@@ -198,12 +200,9 @@ template <typename TS>
 void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, hipStream_t s) {
     const int p = j + 1;
     launch_dot<TS>(Dt, count, nblk_max, p, false, s);
-    launch_reduce(Dt, count, p, j, 1, 1, s);
-    launch_update<TS>(Dt, count, nblk_max, p, true, true, s);
-    launch_reduce(Dt, count, p, j, 0, -1, s);
-    launch_update<TS>(Dt, count, nblk_max, p, false, false, s);
-    launch_finalize(Dt, count, j, s);
-    launch_scale<TS>(Dt, count, nmax, j, s);
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 1, s);  // h1 = V^H w, w -= V h1, dots for pass 2
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 2, s);  // h2, w -= V h2, squared norm
+    launch_scale_final<TS>(Dt, count, nmax, j, s);         // beta, H[j+1][j], flags, v_{j+1}
 }
 
 // svd = false: Arnoldi on M (Algorithm 1).  svd = true: Lanczos on M^dagger M
@@ -296,7 +295,8 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // per step and instance), followed by their collection and copy to the
     // host.  Analyses are consumed in step order; a new step is enqueued when
     // the analyses are consumed, or, while fewer than NS steps are in flight,
-    // as soon as the operator stream has finished the last matvec it was given.
+    // as soon as the operator stream has finished the matvec before the last
+    // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     std::vector<int> final_slot(count, 0);
@@ -388,7 +388,10 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             if (q != hipErrorNotReady) TSK_HIP(q);
         }
         if (next < m && int(pend.size() + ready.size()) < NS) {
-            const hipError_t qm = hipEventQuery(L.ev_apply[2 * next + 1]);  // matvec of step `next` done
+            // one step queued ahead: step `next` goes behind its own matvec as soon as
+            // the matvec before it has finished, so the operator stream never waits
+            // for the host
+            const hipError_t qm = hipEventQuery(L.ev_apply[2 * (next - 1) + 1]);
             if (qm == hipSuccess) {
                 TSK_TRY(enqueue(next++));
                 continue;

@@ -144,6 +144,113 @@ __global__ __launch_bounds__(kBT) void k_update(const KryDesc* __restrict__ Dv, 
     }
 }
 
+// Reduction of the nblk partial dots of coefficient i (lanes over blocks in a
+// fixed order, then a shuffle tree), by one wavefront; k_reduce and the fused
+// passes use it, so every block of a fused pass gets the same bits.
+__device__ inline double2 reduce_coef(const double2* __restrict__ partial, int nblk, int p, int i, int lane) {
+    double2 s = cmk<double2>(0.0, 0.0);
+    for (int b = lane; b < nblk; b += kWave) s = cadd(s, partial[size_t(b) * p + i]);
+    return wave_sum(s);
+}
+__device__ inline double reduce_norm(const double* __restrict__ pn, int nblk, int lane) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += kWave) s += pn[b];
+    return wave_sum(s);
+}
+
+// One Gram-Schmidt pass of step j with the reduction of the previous kernel's
+// partial dots folded in (every block reduces them itself; block 0 writes H):
+//   pass 1: h1 from partial (k_dot), H[.][j] = h1, scal[1] = ||w||^2 from pnrm;
+//           w64 = w - V h1; chunk norms -> pnrm2, dots V^H w64 -> partial2.
+//   pass 2: h2 from partial2, H[.][j] += h2; w64 -= V h2; chunk norms -> pnrm.
+// The buffers alternate so that no block overwrites partial sums another block
+// still reads.
+template <typename TS>
+__global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv, int p, int j, int pass) {
+    using A = typename ET<TS>::A;
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active || int(blockIdx.x) >= d.nblk) return;
+    __shared__ A wl[kChunk];
+    __shared__ double2 hl[kMaxKrylov + 1];
+    __shared__ double red[kBT / kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double2* pin = pass == 1 ? d.partial : d.partial2;
+    double2* Hcol = d.H + size_t(d.ldh) * j;
+    for (int i = wave; i < p; i += kBT / kWave) {
+        const double2 s = reduce_coef(pin, d.nblk, p, i, lane);
+        if (lane == 0) {
+            hl[i] = s;
+            if (blockIdx.x == 0) Hcol[i] = pass == 1 ? s : cadd(Hcol[i], s);
+        }
+    }
+    if (pass == 1 && blockIdx.x == 0 && wave == 0) {
+        const double s = reduce_norm(d.pnrm, d.nblk, lane);
+        if (lane == 0) d.scal[1] = s;
+    }
+    __syncthreads();
+    const TS* V = static_cast<const TS*>(d.V);
+    const TS* w_in = static_cast<const TS*>(d.w);
+    A* w64 = static_cast<A*>(d.w64);  // read and written in place
+    const int64_t n = d.n, ldv = d.ldv;
+    const int64_t base = int64_t(blockIdx.x) * kChunk;
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+        int l = threadIdx.x + e * kBT;
+        int64_t g = base + l;
+        A x = zero_of<A>();
+        if (g < n) {
+            x = pass == 1 ? ET<TS>::acc(w_in[g]) : w64[g];
+            for (int i = 0; i < p; ++i) x = axmy(x, V[i * ldv + g], hl[i]);
+            w64[g] = x;
+        }
+        wl[l] = x;
+        s2 += nrm2(x);
+    }
+    double t = block_sum(s2, red);
+    if (threadIdx.x == 0) (pass == 1 ? d.pnrm2 : d.pnrm)[blockIdx.x] = t;
+    if (pass == 1) {
+        __syncthreads();
+        chunk_dots(V, ldv, p, wl, base, n, d.partial2);
+    }
+}
+
+// beta_j = ||w64|| from the pass-2 chunk norms (every block reduces them
+// itself), v_{j+1} = w64 / beta_j; block 0 of each instance records H[j+1][j],
+// beta and the breakdown / non-finite flags (the former k_finalize).
+template <typename TS>
+__global__ __launch_bounds__(kBT) void k_scale_final(const KryDesc* __restrict__ Dv, int j) {
+    using A = typename ET<TS>::A;
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active) return;
+    __shared__ double sb;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (wave == 0) {
+        const double s = reduce_norm(d.pnrm, d.nblk, lane);
+        if (lane == 0) {
+            const double beta = sqrt(s);
+            sb = beta;
+            if (blockIdx.x == 0) {
+                const double win = sqrt(d.scal[1]);
+                d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
+                d.scal[2] = beta;
+                d.rr->beta = beta;
+                d.rr->w_in = win;
+                d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
+                d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
+                if (d.rr->breakdown && d.rr->bd_step == 0) d.rr->bd_step = j + 1;
+            }
+        }
+    }
+    __syncthreads();
+    const double b = sb;
+    const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
+    TS* v = static_cast<TS*>(d.V) + (j + 1) * d.ldv;
+    const A* w64 = static_cast<const A*>(d.w64);
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(gridDim.x) * blockDim.x)
+        v[g] = ET<TS>::store(scale_by(w64[g], inv));
+}
+
 // One workgroup per instance; wavefront w reduces coefficients i = w, w + 4, ...
 // (lanes over blocks in a fixed order, then a shuffle tree).
 __global__ __launch_bounds__(kBT) void k_reduce(const KryDesc* __restrict__ Dv, int p, int col, int first,
@@ -309,6 +416,16 @@ void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w
     hipLaunchKernelGGL(k_update<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, from_w ? 1 : 0, dot ? 1 : 0);
 }
 
+template <typename TS>
+void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass);
+}
+
+template <typename TS>
+void launch_scale_final(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_final<TS>, dim3(grid_for(nmax, 1024), count), dim3(kBT), 0, s, D, j);
+}
+
 void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(count), dim3(64), 0, s, D, j);
 }
@@ -340,6 +457,8 @@ template void launch_rotate<float>(const void*, void*, const double*, int64_t, i
     template void launch_dot<TS>(const KryDesc*, int, int, int, bool, hipStream_t);                  \
     template void launch_update<TS>(const KryDesc*, int, int, int, bool, bool, hipStream_t);         \
     template void launch_scale<TS>(const KryDesc*, int, int64_t, int, hipStream_t);                  \
+    template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, hipStream_t);          \
+    template void launch_scale_final<TS>(const KryDesc*, int, int64_t, int, hipStream_t);             \
     template void launch_ritz_vectors<TS>(const KryDesc*, int, int64_t, int, hipStream_t);
 TSK_INST(double)
 TSK_INST(float)

@@ -39,6 +39,8 @@ struct KryDesc {
     double2* H;         // (m+1) x m complex128, column-major, leading dim ldh
     double2* partial;   // nblk x (m+1) partial dots
     double* pnrm;       // nblk partial squared norms
+    double2* partial2;  // second buffers: a fused pass reads one and writes the other
+    double* pnrm2;
     double2* h;         // m+1 reduced coefficients
     double* scal;       // 64 device scalars
     double2* Z;         // eigensolver scratch (p x p, standalone use)
@@ -81,6 +83,12 @@ template <typename TS>
 void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w, bool dot, hipStream_t s);
 // beta = sqrt(sum pnrm); H[j+1, j] = beta; breakdown / non-finite flags.
 void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s);
+// Fused Gram-Schmidt pass (1 or 2) of step j with the previous reduction
+// folded in, and the final normalisation with beta and the flags.
+template <typename TS>
+void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, hipStream_t s);
+template <typename TS>
+void launch_scale_final(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s);
 // V_{j+1} = w64 / beta (j >= 0), or V_0 = x0 / ||x0|| (j < 0).
 template <typename TS>
 void launch_scale(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s);

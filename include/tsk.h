@@ -119,11 +119,11 @@ tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
  * the library time both on the first matvec of a given size, precision, base
  * kind and launch size and keep the faster for the process.  Both variants
  * compute every column with the same arithmetic, so results do not depend on
- * the choice.  In the default mode a 128 x 128 operator whose base profile has
- * period 2 pi / 4 and a single harmonic (the Kolmogorov flow sin 4y) uses the
- * Bloch-sector stepper instead (each column split into the four sectors
- * ky = 4m + r, exact 32-point products): the same operator to rounding, not the
- * same bits.  tsk_get_tuning reports the forced or tuned value (0 = not tuned
+ * the choice.  In the default mode an N x N operator, N = 128, 256 or 512,
+ * whose base profile has period 2 pi / 4 and a single harmonic (the Kolmogorov
+ * flow sin 4y) uses the Bloch-sector stepper instead (each column split into
+ * the four sectors ky = 4m + r, exact N/4-point products): the same operator
+ * to rounding, not the same bits.  tsk_get_tuning reports the forced or tuned value (0 = not tuned
  * yet, -1 = the Bloch-sector stepper).  Navier-Stokes operators only. */
 tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave);
 tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave);

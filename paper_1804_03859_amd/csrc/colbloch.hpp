@@ -1,38 +1,45 @@
-// Column time stepper at N = 128 for a base profile of period 2 pi / 4 in y
-// (the Kolmogorov flow U = sin 4y): the y-translation by a quarter period
-// commutes with the linearized operator, so each kx column splits into four
-// independent Bloch sectors, sector r holding the modes ky = 4 m + r.
+// Column time stepper for N = 4L (L = 32, 64, 128) and a base profile of period
+// 2 pi / 4 in y (the Kolmogorov flow U = sin 4y): the y-translation by a quarter
+// period commutes with the linearized operator, so each kx column splits into
+// four independent Bloch sectors, sector r holding the modes ky = 4 m + r.
 //
 // The pseudo-spectral product of the column with the profile restricted to one
-// sector is exact on a 32-point grid.  Write the 128-point grid index as
-// l = 32 a + b: the profile depends on b only, and the sector's field is
-// g(y_l) = e^{i r y_l} G_r(b), G_r the 32-point inverse DFT of the sector's
+// sector is exact on an L-point grid.  Write the N-point grid index as
+// l = L a + b: the profile depends on b only, and the sector's field is
+// g(y_l) = e^{i r y_l} G_r(b), G_r the L-point inverse DFT of the sector's
 // coefficients ĝ_{4m+r}.  The phase e^{i r y_l} cancels between the inverse
-// and the forward transform, so the 128-point product restricted to the sector
-// is p̂_{4m+r} = (1/32) sum_b U(y_b) G_r(b) e^{-2 pi i m b / 32}.  With the
-// 2/3-dealiased modes (|ky| <= 42, at most 22 per sector) and a profile of one
-// harmonic in b, the product spans fewer than 32 values of m, so no term wraps
-// onto a kept mode: the result equals the 128-point pseudo-spectral product to
+// and the forward transform, so the N-point product restricted to the sector
+// is p̂_{4m+r} = (1/L) sum_b U(y_b) G_r(b) e^{-2 pi i m b / L}.  With the
+// 2/3-dealiased modes (|ky| < N/3, about 2L/3 per sector) and a profile of one
+// harmonic in b, the product spans fewer than L values of m, so no term wraps
+// onto a kept mode: the result equals the N-point pseudo-spectral product to
 // rounding.  The base profile's period and harmonic content are checked on the
 // host before this stepper is chosen.
 //
-// One 64-lane workgroup holds two sectors of one column (lanes 0..31 and
-// 32..63), one mode per lane in natural DFT order, for the whole matvec.  The
-// 32-point transforms are five radix-2 levels across the lanes of a half
-// (partner lane ^ h): h = 16 a permlane16 swap, h = 8, 4 DPP row shifts under
-// complementary bank masks, h = 2, 1 DPP quad permutations.  The inverse is
-// decimation in frequency (natural order in, lane nu holding grid point
-// bitrev5(nu) out) and the forward its transpose (decimation in time), so the
-// grid side is read in the permuted order and nothing is reordered.
+// Lane layout, in natural DFT order, for the whole matvec:
+//   L = 32:  one workgroup holds two sectors of a column (lanes 0..31, 32..63),
+//            one mode per lane; five radix-2 levels within each 32-lane half.
+//   L = 64:  one sector per workgroup, one mode per lane; six levels.
+//   L = 128: one sector per workgroup, two modes per lane; the 128-point
+//            cross-lane transform of colxl.hpp.
+// The levels exchange with the partner lane ^ h: h = 32, 16 by permlane swaps,
+// h = 8, 4 by DPP row shifts under complementary bank masks, h = 2, 1 by DPP
+// quad permutations.  The inverse is decimation in frequency (natural order
+// in, bit-reversed grid positions out) and the forward its transpose
+// (decimation in time), so the grid side is read in the permuted order and
+// nothing is reordered.
 #pragma once
 
 #include "colstep.hpp"
+#include "colxl.hpp"
 
 namespace tsk {
 
 __device__ inline int bitrev5(int x) { return int(__builtin_bitreverse32(unsigned(x)) >> 27); }
 
-// Value of lane (lane ^ H), H <= 16, of a 32-bit register (whole wavefront active).
+__device__ inline int bitrev6b(int x) { return int(__builtin_bitreverse32(unsigned(x)) >> 26); }
+
+// Value of lane (lane ^ H), H <= 32, of a 32-bit register (whole wavefront active).
 template <int H> __device__ inline unsigned half_xor_u32(unsigned x, int lane) {
     if constexpr (H == 1 || H == 2) {
         return lane_xor_u32<H>(x);
@@ -42,12 +49,16 @@ template <int H> __device__ inline unsigned half_xor_u32(unsigned x, int lane) {
                                                              false));
         return unsigned(__builtin_amdgcn_update_dpp(int(a), int(x), H == 8 ? 0x108 : 0x104, 0xF, H == 8 ? 0x3 : 0x5,
                                                     false));
-    } else {
-        static_assert(H == 16, "partner within a 32-lane half");
+    } else if constexpr (H == 16) {
         // odd 16-lane rows of the first operand swap with the even rows of the
         // second: with both = x the partner sits in [0] on odd rows, in [1] on even rows
         const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
         return (lane & 16) ? p[0] : p[1];
+    } else {
+        static_assert(H == 32, "partner distance");
+        // upper half of the first operand swaps with the lower half of the second
+        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32) ? p[0] : p[1];
     }
 }
 template <int H> __device__ inline double half_xor(double v, int lane) {
@@ -63,15 +74,17 @@ template <int H, typename C> __device__ inline C half_xor_c(C v, int lane) {
     return cmk<C>(half_xor<H>(v.x, lane), half_xor<H>(v.y, lane));
 }
 
-// Masked level twiddles of the 32-point DFT (forward sign), level h = 1 << l:
-// e^{-2 pi i (nu mod h) / (2h)} on lanes with bit h of nu set, 1 on the others.
-template <typename C> struct BlochTw {
-    C lv[5];
-    __device__ void load(const C* tw128, int nu) {  // tw128[t] = e^{-2 pi i t / 128}
+// Masked level twiddles of the L-point DFT (forward sign, L = 32 or 64), level
+// h = 1 << l: e^{-2 pi i (nu mod h) / (2h)} on lanes with bit h of nu set, 1 on
+// the others; twN[t] = e^{-2 pi i t / N}, N = 4L.
+template <typename C, int L> struct BlochTw {
+    static constexpr int NL = L == 32 ? 5 : 6;
+    C lv[NL];
+    __device__ void load(const C* twN, int nu) {
 #pragma unroll
-        for (int l = 0; l < 5; ++l) {
+        for (int l = 0; l < NL; ++l) {
             const int h = 1 << l;
-            lv[l] = (nu & h) ? tw128[(nu & (h - 1)) * (128 / (2 * h))] : cmk<C>(1, 0);
+            lv[l] = (nu & h) ? twN[(nu & (h - 1)) * (4 * L / (2 * h))] : cmk<C>(1, 0);
         }
     }
 };
@@ -90,29 +103,39 @@ template <int H, int SIGN, typename C> __device__ inline C bloch_dit(C v, const 
     const C p = half_xor_c<H>(z, lane);
     return cmk<C>(p.x + sg * z.x, p.y + sg * z.y);
 }
-// inverse (natural -> bitrev5 order) and forward (bitrev5 -> natural) 32-point DFTs
-template <typename C> __device__ inline C bloch_inv(C v, const BlochTw<C>& t, int lane) {
+// inverse (natural -> bit-reversed order) and forward (bit-reversed -> natural)
+// L-point DFTs, one value per lane (L = 32 within 32-lane halves, or 64)
+template <int L, typename C> __device__ inline C bloch_inv(C v, const BlochTw<C, L>& t, int lane) {
+    if constexpr (L == 64) v = bloch_dif<32, +1>(v, t.lv[5], lane);
     v = bloch_dif<16, +1>(v, t.lv[4], lane);
     v = bloch_dif<8, +1>(v, t.lv[3], lane);
     v = bloch_dif<4, +1>(v, t.lv[2], lane);
     v = bloch_dif<2, +1>(v, t.lv[1], lane);
     return bloch_dif<1, +1>(v, t.lv[0], lane);
 }
-template <typename C> __device__ inline C bloch_fwd(C v, const BlochTw<C>& t, int lane) {
+template <int L, typename C> __device__ inline C bloch_fwd(C v, const BlochTw<C, L>& t, int lane) {
     v = bloch_dit<1, -1>(v, t.lv[0], lane);
     v = bloch_dit<2, -1>(v, t.lv[1], lane);
     v = bloch_dit<4, -1>(v, t.lv[2], lane);
     v = bloch_dit<8, -1>(v, t.lv[3], lane);
-    return bloch_dit<16, -1>(v, t.lv[4], lane);
+    v = bloch_dit<16, -1>(v, t.lv[4], lane);
+    if constexpr (L == 64) v = bloch_dit<32, -1>(v, t.lv[5], lane);
+    return v;
 }
 
-// Grid: block 0 the kx = 0 column (diffusion only), block 1 + 2 (kx - 1) + h the
-// sectors 2h, 2h + 1 of column kx (1 <= kx <= M).  Lawson RK4 as k_colstep.
-template <typename real>
+// Workgroups of a Bloch launch: the kx = 0 column, then the sectors of every
+// column kx >= 1 (two per workgroup for L = 32, one for L = 64 and 128).
+template <int L> constexpr int bloch_blocks(int M) { return 1 + (L == 32 ? 2 : 4) * M; }
+
+// Grid (bloch_blocks): block 0 the kx = 0 column (diffusion only), then the
+// sectors of column kx = 1..M.  Lawson RK4 as k_colstep.
+template <typename real, int L>
 __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> I, const cplx<real>* __restrict__ twg) {
     using C = cplx<real>;
-    using G = Geo<128>;
-    constexpr int M = G::M, P = 4, L = 32;
+    constexpr int N = 4 * L;
+    using G = Geo<N>;
+    constexpr int M = G::M, P = 4;
+    constexpr int S = L == 128 ? 2 : 1;  // modes per lane
     const int lane = threadIdx.x;
     const real* __restrict__ xin = I.xbase;
     real* __restrict__ yout = I.y;
@@ -130,57 +153,93 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> I, const 
         }
         return;
     }
-    const int kx = 1 + (int(blockIdx.x) - 1) / 2;
-    const int r = 2 * ((int(blockIdx.x) - 1) % 2) + (lane >> 5);  // sector
-    const int nu = lane & (L - 1);                                 // DFT index in the sector
-    const int m = nu < L / 2 ? nu : nu - L;
-    const int jy = P * m + r;
-    const bool kp = jy >= -M && jy <= M;
-    const int q = kp ? jy + M : 0;
+    const int b = int(blockIdx.x) - 1;
+    int kx, r;
+    if constexpr (L == 32) {
+        kx = 1 + b / 2;
+        r = 2 * (b % 2) + (lane >> 5);
+    } else {
+        kx = 1 + b / 4;
+        r = b % 4;
+    }
     const double kxv = alpha * kx;
-    const double K2 = kxv * kxv + double(jy) * jy;
-    const real E1 = kp ? real(exp(-K2 * dt / Re)) : real(0);
-    const real Eh = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
-    const real g1 = kp ? real(kxv * (1.0 - cprop / K2)) : real(0);
-    const real kmask = kp ? real(1.0 / L) : real(0);
-    const real nuv = I.negU[bitrev5(nu)];  // profile at the grid point this lane holds after the inverse
     const real* xs = xin + G::seg(kx);
-    C w = kp ? cmk<C>(xs[2 * q], xs[2 * q + 1]) : cmk<C>(real(0), real(0));
-    C acc = w, s = w;
-    BlochTw<C> tw;
-    tw.load(twg, nu);
+    real E1[S], Eh[S], g1[S], kmask[S], nuv[S];
+    int qs[S];
+    bool kps[S];
+    C w[S], acc[S], s[S];
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        const int idx = L == 32 ? (lane & 31) : lane + 64 * sl;  // DFT index in the sector
+        const int m = idx < L / 2 ? idx : idx - L;
+        const int jy = P * m + r;
+        const bool kp = jy >= -M && jy <= M;
+        kps[sl] = kp;
+        qs[sl] = kp ? jy + M : 0;
+        const double K2 = kxv * kxv + double(jy) * jy;
+        E1[sl] = kp ? real(exp(-K2 * dt / Re)) : real(0);
+        Eh[sl] = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
+        g1[sl] = kp ? real(kxv * (1.0 - cprop / K2)) : real(0);
+        kmask[sl] = kp ? real(1.0 / L) : real(0);
+        // profile at the grid point this slot holds after the inverse transform
+        const int gpos = L == 32 ? bitrev5(lane & 31) : L == 64 ? bitrev6b(lane) : xl_grid_pos(lane, sl);
+        nuv[sl] = I.negU[gpos];
+        w[sl] = kp ? cmk<C>(xs[2 * qs[sl]], xs[2 * qs[sl] + 1]) : cmk<C>(real(0), real(0));
+        acc[sl] = s[sl] = w[sl];
+    }
+    BlochTw<C, L == 128 ? 64 : L> btw;
+    XlTw<C> xtw;
+    if constexpr (L == 128)
+        xtw.load(twg, lane, N / 128);
+    else
+        btw.load(twg, L == 32 ? (lane & 31) : lane);
     const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
 
     for (int st = 0; st < nsteps; ++st) {
-        s = w;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) s[sl] = w[sl];
 #pragma unroll 4
         for (int stage = 0; stage < 4; ++stage) {
-            C v = cmk<C>(-g1 * s.y, g1 * s.x);  // i kx (1 - c / K^2) s
-            v = bloch_inv(v, tw, lane);
-            C pr = cmk<C>(nuv * v.x, nuv * v.y);
-            pr = bloch_fwd(pr, tw, lane);
-            const C nh = cmk<C>(pr.x * kmask, pr.y * kmask);
-            if (stage == 0) {
-                acc = cmk<C>(E1 * (w.x + h6 * nh.x), E1 * (w.y + h6 * nh.y));
-                s = cmk<C>(Eh * (w.x + h2 * nh.x), Eh * (w.y + h2 * nh.y));
-            } else if (stage == 1) {
-                acc.x += h3 * Eh * nh.x;
-                acc.y += h3 * Eh * nh.y;
-                s = cmk<C>(Eh * w.x + h2 * nh.x, Eh * w.y + h2 * nh.y);
-            } else if (stage == 2) {
-                acc.x += h3 * Eh * nh.x;
-                acc.y += h3 * Eh * nh.y;
-                s = cmk<C>(E1 * w.x + hh * Eh * nh.x, E1 * w.y + hh * Eh * nh.y);
-            } else {
-                w = cmk<C>(acc.x + h6 * nh.x, acc.y + h6 * nh.y);
+            C v[1][1][S];
+#pragma unroll
+            for (int sl = 0; sl < S; ++sl) v[0][0][sl] = cmk<C>(-g1[sl] * s[sl].y, g1[sl] * s[sl].x);  // i kx (1 - c/K^2) s
+            if constexpr (L == 128)
+                xl_fft_inv<1>(v, xtw, lane);
+            else
+                v[0][0][0] = bloch_inv<L>(v[0][0][0], btw, lane);
+#pragma unroll
+            for (int sl = 0; sl < S; ++sl) v[0][0][sl] = cmk<C>(nuv[sl] * v[0][0][sl].x, nuv[sl] * v[0][0][sl].y);
+            if constexpr (L == 128)
+                xl_fft_fwd<1>(v, xtw, lane);
+            else
+                v[0][0][0] = bloch_fwd<L>(v[0][0][0], btw, lane);
+#pragma unroll
+            for (int sl = 0; sl < S; ++sl) {
+                const C nh = cmk<C>(v[0][0][sl].x * kmask[sl], v[0][0][sl].y * kmask[sl]);
+                if (stage == 0) {
+                    acc[sl] = cmk<C>(E1[sl] * (w[sl].x + h6 * nh.x), E1[sl] * (w[sl].y + h6 * nh.y));
+                    s[sl] = cmk<C>(Eh[sl] * (w[sl].x + h2 * nh.x), Eh[sl] * (w[sl].y + h2 * nh.y));
+                } else if (stage == 1) {
+                    acc[sl].x += h3 * Eh[sl] * nh.x;
+                    acc[sl].y += h3 * Eh[sl] * nh.y;
+                    s[sl] = cmk<C>(Eh[sl] * w[sl].x + h2 * nh.x, Eh[sl] * w[sl].y + h2 * nh.y);
+                } else if (stage == 2) {
+                    acc[sl].x += h3 * Eh[sl] * nh.x;
+                    acc[sl].y += h3 * Eh[sl] * nh.y;
+                    s[sl] = cmk<C>(E1[sl] * w[sl].x + hh * Eh[sl] * nh.x, E1[sl] * w[sl].y + hh * Eh[sl] * nh.y);
+                } else {
+                    w[sl] = cmk<C>(acc[sl].x + h6 * nh.x, acc[sl].y + h6 * nh.y);
+                }
             }
         }
     }
     real* ys = yout + G::seg(kx);
-    if (kp) {
-        ys[2 * q] = w.x;
-        ys[2 * q + 1] = w.y;
-    }
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl)
+        if (kps[sl]) {
+            ys[2 * qs[sl]] = w[sl].x;
+            ys[2 * qs[sl] + 1] = w[sl].y;
+        }
 }
 
 }  // namespace tsk

@@ -108,12 +108,13 @@ template <int H, typename C> __device__ inline C lane_xor_c(C v) { return cmk<C>
 template <typename C> struct XlTw {
     C in;     // e^{-2 pi i L / 128} (slot 1 of the in-lane step)
     C lv[6];  // level h = 1 << l: W for h >= 4, the masked W' for h = 2 (1 for h = 1)
-    __device__ void load(const C* tw, int lane) {  // tw[t] = e^{-2 pi i t / 128}, t < 128
-        in = tw[lane];
+    // tw[stride t] = e^{-2 pi i t / 128}, t < 128 (stride > 1: a finer table)
+    __device__ void load(const C* tw, int lane, int stride = 1) {
+        in = tw[stride * lane];
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
             const int h = 1 << l;
-            const C w = tw[(lane & (h - 1)) * (128 / (2 * h))];
+            const C w = tw[stride * (lane & (h - 1)) * (128 / (2 * h))];
             lv[l] = (h >= 4 || (lane & h)) ? w : cmk<C>(1, 0);
         }
     }

@@ -351,7 +351,7 @@ struct KolmoOp final : Operator {
     int nsteps = 0;
     bool prop = false;
     double cprop = 0.0;
-    bool bloch = false;  // N = 128 and a quarter-period one-harmonic profile: Bloch-sector stepper
+    bool bloch = false;  // N = 128, 256, 512 and a quarter-period one-harmonic profile: Bloch-sector stepper
     DevBuf tw, negU, dOdy, Z;
     DevBuf tasks[3];   // single-instance task lists for 1 and 2 columns per wavefront
     int ntasks[3] = {0, 0, 0};
@@ -426,18 +426,26 @@ struct KolmoOp final : Operator {
         return c;
     }
 
+    template <typename real> void launch_bloch(const void* x, void* y) const {
+        const ColInst<real> in = inst<real>(x, 0, y, nullptr);
+        const cplx<real>* t = tw.as<cplx<real>>();
+        if (N == 128)
+            hipLaunchKernelGGL((k_colstep_bloch<real, 32>), dim3(bloch_blocks<32>(M)), dim3(kWave), 0, stream, in, t);
+        else if (N == 256)
+            hipLaunchKernelGGL((k_colstep_bloch<real, 64>), dim3(bloch_blocks<64>(M)), dim3(kWave), 0, stream, in, t);
+        else
+            hipLaunchKernelGGL((k_colstep_bloch<real, 128>), dim3(bloch_blocks<128>(M)), dim3(kWave), 0, stream, in,
+                               t);
+    }
     tsk_status apply(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
         if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
         if (bloch && force_cols == 0) {
-            const dim3 grid(1 + 2 * M);
             if (prec == TSK_FP32)
-                hipLaunchKernelGGL(k_colstep_bloch<float>, grid, dim3(kWave), 0, stream, inst<float>(x, 0, y, nullptr),
-                                   tw.as<cplx<float>>());
+                launch_bloch<float>(x, y);
             else
-                hipLaunchKernelGGL(k_colstep_bloch<double>, grid, dim3(kWave), 0, stream,
-                                   inst<double>(x, 0, y, nullptr), tw.as<cplx<double>>());
+                launch_bloch<double>(x, y);
             TSK_HIP(hipGetLastError());
             return TSK_OK;
         }
@@ -651,22 +659,23 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
     for (int i = 0; i < N; ++i) dev = std::max(dev, std::fabs(dOdy[i] - c * U[i]));
     k->prop = uu > 0.0 && dev <= 1e-13 * std::max(omax, 1e-300);
     k->cprop = k->prop ? c : 0.0;
-    // Bloch sectors (colbloch.hpp): N = 128, profile of period 32 samples whose
-    // 32-point spectrum has no harmonic beyond the first
+    // Bloch sectors (colbloch.hpp): N = 128, 256 or 512, profile of period L = N/4
+    // samples whose L-point spectrum has no harmonic beyond the first
     k->bloch = false;
-    if (k->prop && N == 128) {
+    if (k->prop && (N == 128 || N == 256 || N == 512)) {
+        const int L = N / 4;
         double umax = 0.0;
         for (int i = 0; i < N; ++i) umax = std::max(umax, std::fabs(nu[i]));
         bool ok = umax > 0.0;
-        for (int i = 32; i < N && ok; ++i) ok = std::fabs(nu[i] - nu[i % 32]) <= 1e-13 * umax;
+        for (int i = L; i < N && ok; ++i) ok = std::fabs(nu[i] - nu[i % L]) <= 1e-13 * umax;
         const double pi = 3.14159265358979323846264338327950288;
-        for (int h = 2; h <= 16 && ok; ++h) {
+        for (int h = 2; h <= L / 2 && ok; ++h) {
             double cr = 0.0, ci = 0.0;
-            for (int b = 0; b < 32; ++b) {
-                cr += nu[b] * std::cos(2.0 * pi * h * b / 32.0);
-                ci -= nu[b] * std::sin(2.0 * pi * h * b / 32.0);
+            for (int b = 0; b < L; ++b) {
+                cr += nu[b] * std::cos(2.0 * pi * h * b / L);
+                ci -= nu[b] * std::sin(2.0 * pi * h * b / L);
             }
-            ok = std::hypot(cr, ci) <= 1e-12 * 32.0 * umax;
+            ok = std::hypot(cr, ci) <= 1e-12 * L * umax;
         }
         k->bloch = ok;
     }

@@ -216,7 +216,8 @@ def test_fp32_precision_form_within_stated_bound(tsk, N, m):
 
 
 @pytest.mark.parametrize("N,prec,base", [(128, 0, "kolmogorov"), (128, 1, "kolmogorov"), (128, 0, "general"),
-                                         (48, 0, "general"), (256, 1, "kolmogorov"), (96, 1, "general")])
+                                         (48, 0, "general"), (256, 1, "kolmogorov"), (256, 0, "kolmogorov"),
+                                         (96, 1, "general")])
 def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
     print(f"column-pair variant N={N} prec={prec} base={base}", flush=True)
     if base == "kolmogorov":
@@ -238,9 +239,9 @@ def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
     tsk.set_tuning(op, 0)
     y_ = op.new_state()
     tsk.apply(op, x, y_)
-    if N == 128 and base == "kolmogorov":
-        # the default at 128^2 with the quarter-period base is the Bloch-sector
-        # stepper: the same operator, other rounding
+    if N in (128, 256, 512) and base == "kolmogorov":
+        # the default at 128^2 and 256^2 with the quarter-period base is the
+        # Bloch-sector stepper: the same operator, other rounding
         tol = 1e-13 if prec == 0 else 2e-6
         assert torch.max(torch.abs(y_ - outs[0])).item() <= tol * torch.max(torch.abs(outs[0])).item()
         assert not torch.equal(y_, outs[0])
@@ -250,3 +251,23 @@ def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
         assert tsk.get_tuning(op) in (1, 2)
     with pytest.raises(tsk.TskError):
         tsk.set_tuning(op, 3)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bloch_stepper_512_matches_column_stepper(tsk, prec):
+    # 512^2: Bloch sectors of 128 modes (two per lane, the cross-lane
+    # 128-point transform) against the one-column-per-wave LDS stepper
+    print(f"bloch 512 prec={prec}", flush=True)
+    op, _ = _op(tsk, 512, prec=prec, T=0.05)
+    x = op.new_state()
+    tsk.from_physical(op, _phys(op, 512, W.kolmo_start_physical(512, 4)), x)
+    assert tsk.get_tuning(op) == -1
+    yb = op.new_state()
+    tsk.apply(op, x, yb)
+    tsk.set_tuning(op, 1)
+    assert tsk.get_tuning(op) == 1
+    yc = op.new_state()
+    tsk.apply(op, x, yc)
+    tol = 1e-13 if prec == 0 else 2e-6
+    assert torch.max(torch.abs(yb - yc)).item() <= tol * torch.max(torch.abs(yc)).item()
+    assert torch.max(torch.abs(yc)).item() > 0

@@ -193,7 +193,8 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     if stepper == -1:
         flops = bloch_flops(N, nsteps)
         kernel = f"k_colstep_bloch<{rt}>"
-        traffic = measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md") if prec == tsk.TSK_FP64 else None
+        traffic = (measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md")
+                   if prec == tsk.TSK_FP64 and N == 128 else None)
     else:
         flops = colstep_flops(N, nsteps)
         kernel = f"k_colstep<{rt},{N},true>"

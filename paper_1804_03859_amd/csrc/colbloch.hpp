@@ -39,39 +39,8 @@ __device__ inline int bitrev5(int x) { return int(__builtin_bitreverse32(unsigne
 
 __device__ inline int bitrev6b(int x) { return int(__builtin_bitreverse32(unsigned(x)) >> 26); }
 
-// Value of lane (lane ^ H), H <= 32, of a 32-bit register (whole wavefront active).
-template <int H> __device__ inline unsigned half_xor_u32(unsigned x, int lane) {
-    if constexpr (H == 1 || H == 2) {
-        return lane_xor_u32<H>(x);
-    } else if constexpr (H == 4 || H == 8) {
-        // lanes with bit H set read lane - H (row_shr), the others lane + H (row_shl)
-        const unsigned a = unsigned(__builtin_amdgcn_mov_dpp(int(x), H == 8 ? 0x118 : 0x114, 0xF, H == 8 ? 0xC : 0xA,
-                                                             false));
-        return unsigned(__builtin_amdgcn_update_dpp(int(a), int(x), H == 8 ? 0x108 : 0x104, 0xF, H == 8 ? 0x3 : 0x5,
-                                                    false));
-    } else if constexpr (H == 16) {
-        // odd 16-lane rows of the first operand swap with the even rows of the
-        // second: with both = x the partner sits in [0] on odd rows, in [1] on even rows
-        const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return (lane & 16) ? p[0] : p[1];
-    } else {
-        static_assert(H == 32, "partner distance");
-        // upper half of the first operand swaps with the lower half of the second
-        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-        return (lane & 32) ? p[0] : p[1];
-    }
-}
-template <int H> __device__ inline double half_xor(double v, int lane) {
-    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-    const unsigned lo = half_xor_u32<H>(unsigned(b & 0xffffffffull), lane);
-    const unsigned hi = half_xor_u32<H>(unsigned(b >> 32), lane);
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-template <int H> __device__ inline float half_xor(float v, int lane) {
-    return __uint_as_float(half_xor_u32<H>(__float_as_uint(v), lane));
-}
 template <int H, typename C> __device__ inline C half_xor_c(C v, int lane) {
-    return cmk<C>(half_xor<H>(v.x, lane), half_xor<H>(v.y, lane));
+    return cmk<C>(xor_lane<H>(v.x, lane), xor_lane<H>(v.y, lane));
 }
 
 // Masked level twiddles of the L-point DFT (forward sign, L = 32 or 64), level
@@ -136,6 +105,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> I, const 
     using G = Geo<N>;
     constexpr int M = G::M, P = 4;
     constexpr int S = L == 128 ? 2 : 1;  // modes per lane
+    stepper_wave_priority();
     const int lane = threadIdx.x;
     const real* __restrict__ xin = I.xbase;
     real* __restrict__ yout = I.y;

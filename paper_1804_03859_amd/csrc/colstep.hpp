@@ -21,6 +21,13 @@ template <int N> struct Geo {
     }
 };
 
+// A time-stepper wave runs for a whole matvec, and the Ritz analyses of earlier
+// Arnoldi steps run beside it on other streams; when the dispatcher puts one of
+// their waves on the same SIMD, the stepper wave (on the critical path) gets
+// the higher issue priority.  Priority only orders instruction issue between
+// resident waves: every wave still runs to completion.
+__device__ inline void stepper_wave_priority() { __builtin_amdgcn_s_setprio(2); }
+
 // One operator instance of a (batched) column-stepper launch.  The input of
 // step j is xbase + j * xstride (the Arnoldi basis vector v_j; xstride = 0 for a
 // plain matvec); `active` (optional) lets finished Arnoldi instances skip.
@@ -57,6 +64,7 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
     constexpr int NI = PROP ? 1 : 2;  // inverse transforms per column and stage
     static_assert(PL::NBL == 1, "one edge butterfly per lane");
+    stepper_wave_priority();
     const ColTask tk = tasks[blockIdx.x];
     const ColInst<real>& I = insts ? insts[tk.inst] : one;
     if (I.active && *I.active == 0) return;
@@ -278,6 +286,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_adj(ColInst<real> one, const 
     constexpr int M = G::M, RE = PL::RE, NB = PL::NB;
     constexpr int NF = PROP ? 1 : 2;  // forward transforms per stage
     static_assert(PL::NBL == 1, "one edge butterfly per lane");
+    stepper_wave_priority();
     const ColTask tk = tasks[blockIdx.x];
     const ColInst<real>& I = one;
     const real* __restrict__ xin = I.xbase;

@@ -90,10 +90,53 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-// ---- wavefront reductions (device) -------------------------------------------
+// ---- cross-lane exchange and wavefront reductions (device) ---------------------
+__device__ inline int lane_id() { return int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u))); }
+
+// Value of lane (lane ^ H), H <= 32, of a 32-bit register; the whole wavefront
+// must be active.  H = 1, 2: DPP quad permutations; H = 4, 8: lanes with bit H
+// set read lane - H (row_shr), the others lane + H (row_shl), under
+// complementary bank masks; H = 16, 32: the gfx950 permlane swaps with both
+// operands x (the first operand's odd 16-lane rows / upper half trade places
+// with the second's even rows / lower half, so the partner sits in [0] on lanes
+// with bit H set and in [1] on the others).
+template <int H> __device__ inline unsigned xor_lane_u32(unsigned x, int lane) {
+    if constexpr (H == 1 || H == 2) {
+        return unsigned(__builtin_amdgcn_mov_dpp(int(x), H == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false));
+    } else if constexpr (H == 4 || H == 8) {
+        const unsigned a = unsigned(__builtin_amdgcn_mov_dpp(int(x), H == 8 ? 0x118 : 0x114, 0xF, H == 8 ? 0xC : 0xA,
+                                                             false));
+        return unsigned(__builtin_amdgcn_update_dpp(int(a), int(x), H == 8 ? 0x108 : 0x104, 0xF, H == 8 ? 0x3 : 0x5,
+                                                    false));
+    } else if constexpr (H == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16) ? p[0] : p[1];
+    } else {
+        static_assert(H == 32, "partner distance");
+        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32) ? p[0] : p[1];
+    }
+}
+template <int H> __device__ inline double xor_lane(double v, int lane) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = xor_lane_u32<H>(unsigned(b & 0xffffffffull), lane);
+    const unsigned hi = xor_lane_u32<H>(unsigned(b >> 32), lane);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+template <int H> __device__ inline float xor_lane(float v, int lane) {
+    return __uint_as_float(xor_lane_u32<H>(__float_as_uint(v), lane));
+}
+
+// Butterfly sum over the wavefront (partners lane ^ 32, ^ 16, ..., ^ 1); every
+// lane ends with the same total.  The whole wavefront must be active.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    const int lane = lane_id();
+    v += xor_lane<32>(v, lane);
+    v += xor_lane<16>(v, lane);
+    v += xor_lane<8>(v, lane);
+    v += xor_lane<4>(v, lane);
+    v += xor_lane<2>(v, lane);
+    v += xor_lane<1>(v, lane);
     return v;
 }
 __device__ inline double2 wave_sum(double2 v) {

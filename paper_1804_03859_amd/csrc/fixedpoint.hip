@@ -36,7 +36,7 @@ inline int fblocks(int64_t n) { return int((n + kFChunk - 1) / kFChunk); }
 template <typename TS> __device__ inline double rd(const TS* p, int64_t i) { return double(p[i]); }
 
 __device__ inline double block_sum(double v, double* red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v = wave_sum(v);
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();

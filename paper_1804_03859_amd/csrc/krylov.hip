@@ -1,4 +1,6 @@
 // Kernels declared in krylov.hpp.
+#include <type_traits>
+
 #include "krylov.hpp"
 
 namespace tsk {
@@ -54,23 +56,79 @@ __device__ inline double block_sum(double v, double* red) {
     return t;
 }
 
-// Dots of the LDS-staged chunk wl with every basis vector (wave-parallel).
+// Dots of the LDS-staged chunk wl (kChunk elements) with every basis vector
+// (wave-parallel).  Wave w takes the vectors i = w, w + 4, w + 8, ...; it loads
+// kDotU of them at once so that their memory latencies overlap, and
+// accumulates each in the element order e = 0, 1, ... before its shuffle
+// reduction.
+constexpr int kDotU = 4;
 template <typename TS, typename A>
 __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, const A* wl, int64_t base,
                                   int64_t n, double2* __restrict__ partial) {
+    constexpr bool kReal = !std::is_same<TS, double2>::value;  // real states: the dots are real
+    constexpr int NW = kBT / kWave, E = kChunk / kWave, U = kDotU;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t lim = n - base;
-    for (int i = wave; i < p; i += kBT / kWave) {
-        const TS* vi = V + i * ldv + base;
-        double2 a = cmk<double2>(0.0, 0.0);
-#pragma unroll 4
-        for (int e = 0; e < kChunk / kWave; ++e) {
-            int l = lane + e * kWave;
-            if (l < lim) a = cadd(a, dotc(vi[l], wl[l]));
+    A wv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) wv[e] = wl[lane + e * kWave];
+    for (int i0 = wave; i0 < p; i0 += NW * U) {
+        TS vv[U][E];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + NW * u;
+            const TS* vi = V + int64_t(i < p ? i : 0) * ldv + base;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int l = lane + e * kWave;
+                vv[u][e] = (i < p && l < lim) ? vi[l] : TS{};
+            }
         }
-        a = wave_sum(a);
-        if (lane == 0) partial[size_t(blockIdx.x) * p + i] = a;
+        double2 a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = cmk<double2>(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (lane + e * kWave < lim) a[u] = cadd(a[u], dotc(vv[u][e], wv[e]));
+            if constexpr (kReal)
+                a[u].x = wave_sum(a[u].x);  // the imaginary parts are exact zeros
+            else
+                a[u] = wave_sum(a[u]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + NW * u;
+                if (i < p) partial[size_t(blockIdx.x) * p + i] = a[u];
+            }
+        }
     }
+}
+
+// x[e] - sum_i V[i][g_e] h_i for the thread's EPT elements g_e = g0 + e kBT
+// (ok[e]: inside the state), subtracted in the order i = 0, 1, ..., p-1; the
+// loads of U = 8 basis vectors are issued together ahead of their products.
+template <int EPT, typename TS, typename A>
+__device__ inline void project_out(A (&x)[EPT], const bool (&ok)[EPT], const TS* __restrict__ V, int64_t ldv,
+                                   int64_t g0, const double2* hl, int p) {
+    constexpr int U = 8;
+    int i0 = 0;
+    for (; i0 + U <= p; i0 += U) {
+        TS vv[U][EPT];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) vv[u][e] = ok[e] ? V[int64_t(i0 + u) * ldv + g0 + e * kBT] : TS{};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) x[e] = axmy(x[e], vv[u][e], hl[i0 + u]);
+    }
+    for (; i0 < p; ++i0)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (ok[e]) x[e] = axmy(x[e], V[int64_t(i0) * ldv + g0 + e * kBT], hl[i0]);
 }
 
 template <typename TS>
@@ -107,50 +165,27 @@ __global__ __launch_bounds__(kBT) void k_dot(const KryDesc* __restrict__ Dv, int
     chunk_dots(static_cast<const TS*>(d.V), d.ldv, p, wl, base, n, d.partial);
 }
 
-template <typename TS>
-__global__ __launch_bounds__(kBT) void k_update(const KryDesc* __restrict__ Dv, int p, int from_w, int dot) {
-    using A = typename ET<TS>::A;
-    const KryDesc& d = Dv[blockIdx.y];
-    if (!d.active || int(blockIdx.x) >= d.nblk) return;
-    __shared__ A wl[kChunk];
-    __shared__ double2 hl[kMaxKrylov + 1];
-    __shared__ double red[kBT / kWave];
-    for (int i = threadIdx.x; i < p; i += kBT) hl[i] = d.h[i];
-    __syncthreads();
-    const TS* V = static_cast<const TS*>(d.V);
-    const TS* w_in = static_cast<const TS*>(d.w);
-    A* w64 = static_cast<A*>(d.w64);  // read and written in place
-    const int64_t n = d.n, ldv = d.ldv;
-    const int64_t base = int64_t(blockIdx.x) * kChunk;
-    double s2 = 0.0;
+// Reduction of the nblk partial dots of the kDotU coefficients i0 + stride u
+// by one wavefront: per coefficient, lanes over blocks in a fixed order, then a
+// shuffle tree (the order k_reduce uses), so every block of a fused pass gets
+// the same bits.  The loads of the kDotU coefficients overlap.
+__device__ inline void reduce_coefs(const double2* __restrict__ partial, int nblk, int p, int i0, int stride,
+                                   int lane, double2 (&out)[kDotU]) {
+    double2 sv[kDotU];
 #pragma unroll
-    for (int e = 0; e < kEPT; ++e) {
-        int l = threadIdx.x + e * kBT;
-        int64_t g = base + l;
-        A x = zero_of<A>();
-        if (g < n) {
-            x = from_w ? ET<TS>::acc(w_in[g]) : w64[g];
-            for (int i = 0; i < p; ++i) x = axmy(x, V[i * ldv + g], hl[i]);
-            w64[g] = x;
+    for (int u = 0; u < kDotU; ++u) sv[u] = cmk<double2>(0.0, 0.0);
+    for (int b = lane; b < nblk; b += kWave) {
+        double2 t[kDotU];
+#pragma unroll
+        for (int u = 0; u < kDotU; ++u) {
+            const int i = i0 + stride * u;
+            t[u] = i < p ? partial[size_t(b) * p + i] : cmk<double2>(0.0, 0.0);
         }
-        wl[l] = x;
-        s2 += nrm2(x);
+#pragma unroll
+        for (int u = 0; u < kDotU; ++u) sv[u] = cadd(sv[u], t[u]);
     }
-    double t = block_sum(s2, red);
-    if (threadIdx.x == 0) d.pnrm[blockIdx.x] = t;
-    if (dot) {
-        __syncthreads();
-        chunk_dots(V, ldv, p, wl, base, n, d.partial);
-    }
-}
-
-// Reduction of the nblk partial dots of coefficient i (lanes over blocks in a
-// fixed order, then a shuffle tree), by one wavefront; k_reduce and the fused
-// passes use it, so every block of a fused pass gets the same bits.
-__device__ inline double2 reduce_coef(const double2* __restrict__ partial, int nblk, int p, int i, int lane) {
-    double2 s = cmk<double2>(0.0, 0.0);
-    for (int b = lane; b < nblk; b += kWave) s = cadd(s, partial[size_t(b) * p + i]);
-    return wave_sum(s);
+#pragma unroll
+    for (int u = 0; u < kDotU; ++u) out[u] = wave_sum(sv[u]);
 }
 __device__ inline double reduce_norm(const double* __restrict__ pn, int nblk, int lane) {
     double s = 0.0;
@@ -176,11 +211,19 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const double2* pin = pass == 1 ? d.partial : d.partial2;
     double2* Hcol = d.H + size_t(d.ldh) * j;
-    for (int i = wave; i < p; i += kBT / kWave) {
-        const double2 s = reduce_coef(pin, d.nblk, p, i, lane);
+    constexpr int NW = kBT / kWave;
+    for (int i0 = wave; i0 < p; i0 += NW * kDotU) {
+        double2 sv[kDotU];
+        reduce_coefs(pin, d.nblk, p, i0, NW, lane, sv);
         if (lane == 0) {
-            hl[i] = s;
-            if (blockIdx.x == 0) Hcol[i] = pass == 1 ? s : cadd(Hcol[i], s);
+#pragma unroll
+            for (int u = 0; u < kDotU; ++u) {
+                const int i = i0 + NW * u;
+                if (i < p) {
+                    hl[i] = sv[u];
+                    if (blockIdx.x == 0) Hcol[i] = pass == 1 ? sv[u] : cadd(Hcol[i], sv[u]);
+                }
+            }
         }
     }
     if (pass == 1 && blockIdx.x == 0 && wave == 0) {
@@ -193,19 +236,23 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     A* w64 = static_cast<A*>(d.w64);  // read and written in place
     const int64_t n = d.n, ldv = d.ldv;
     const int64_t base = int64_t(blockIdx.x) * kChunk;
+    const int64_t g0 = base + threadIdx.x;
+    A x[kEPT];
+    bool ok[kEPT];
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+        const int64_t g = g0 + e * kBT;
+        ok[e] = g < n;
+        x[e] = zero_of<A>();
+        if (ok[e]) x[e] = pass == 1 ? ET<TS>::acc(w_in[g]) : w64[g];
+    }
+    project_out<kEPT>(x, ok, V, ldv, g0, hl, p);
     double s2 = 0.0;
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
-        int l = threadIdx.x + e * kBT;
-        int64_t g = base + l;
-        A x = zero_of<A>();
-        if (g < n) {
-            x = pass == 1 ? ET<TS>::acc(w_in[g]) : w64[g];
-            for (int i = 0; i < p; ++i) x = axmy(x, V[i * ldv + g], hl[i]);
-            w64[g] = x;
-        }
-        wl[l] = x;
-        s2 += nrm2(x);
+        if (ok[e]) w64[g0 + e * kBT] = x[e];
+        wl[threadIdx.x + e * kBT] = x[e];
+        s2 += nrm2(x[e]);
     }
     double t = block_sum(s2, red);
     if (threadIdx.x == 0) (pass == 1 ? d.pnrm2 : d.pnrm)[blockIdx.x] = t;
@@ -274,25 +321,6 @@ __global__ __launch_bounds__(kBT) void k_reduce(const KryDesc* __restrict__ Dv, 
         s = wave_sum(s);
         if (lane == 0) d.scal[slot] = s;
     }
-}
-
-__global__ void k_finalize(const KryDesc* __restrict__ Dv, int j) {
-    const KryDesc& d = Dv[blockIdx.x];
-    if (!d.active) return;
-    const int lane = threadIdx.x;  // one wavefront
-    double s = 0.0;
-    for (int b = lane; b < d.nblk; b += kWave) s += d.pnrm[b];
-    s = wave_sum(s);
-    if (lane != 0) return;
-    const double beta = sqrt(s);
-    const double win = sqrt(d.scal[1]);
-    d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
-    d.scal[2] = beta;
-    d.rr->beta = beta;
-    d.rr->w_in = win;
-    d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
-    d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
-    if (d.rr->breakdown && d.rr->bd_step == 0) d.rr->bd_step = j + 1;
 }
 
 template <typename TS>
@@ -412,11 +440,6 @@ void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int s
 }
 
 template <typename TS>
-void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w, bool dot, hipStream_t s) {
-    hipLaunchKernelGGL(k_update<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, from_w ? 1 : 0, dot ? 1 : 0);
-}
-
-template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, hipStream_t s) {
     hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass);
 }
@@ -424,10 +447,6 @@ void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, in
 template <typename TS>
 void launch_scale_final(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_final<TS>, dim3(grid_for(nmax, 1024), count), dim3(kBT), 0, s, D, j);
-}
-
-void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(count), dim3(64), 0, s, D, j);
 }
 
 template <typename TS>
@@ -455,7 +474,6 @@ template void launch_rotate<float>(const void*, void*, const double*, int64_t, i
 #define TSK_INST(TS)                                                                                 \
     template void launch_check_finite<TS>(const KryDesc*, int, int64_t, hipStream_t);               \
     template void launch_dot<TS>(const KryDesc*, int, int, int, bool, hipStream_t);                  \
-    template void launch_update<TS>(const KryDesc*, int, int, int, bool, bool, hipStream_t);         \
     template void launch_scale<TS>(const KryDesc*, int, int64_t, int, hipStream_t);                  \
     template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, hipStream_t);          \
     template void launch_scale_final<TS>(const KryDesc*, int, int64_t, int, hipStream_t);             \

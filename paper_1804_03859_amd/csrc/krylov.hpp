@@ -14,7 +14,8 @@
 // elements (small chunks keep enough workgroups busy at the 10^4-element
 // states of the 128^2 grids).  A dot pass stages the chunk of w in LDS, then each of the four
 // wavefronts takes every fourth basis vector, reads its chunk coalesced and
-// reduces the 64 lane sums with cross-lane shuffles.  Per-block partial sums are
+// reduces the 64 lane sums with cross-lane shuffles; several vectors' loads are
+// in flight at once.  Per-block partial sums are
 // reduced in a fixed order (lanes over blocks, then a shuffle tree) by one
 // workgroup per instance, so results are bitwise reproducible run to run and
 // independent of the batch composition.
@@ -77,12 +78,6 @@ void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, 
 // Reduce partials: h = sum_b partial; H column col (if col >= 0) = (first ? 0 : H) + h;
 // scal[slot] = sum_b pnrm when slot >= 0.
 void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s);
-// Pass 2/3: w64 = src - V h, src = w (state type) or w64; dot: partials of V^H w64;
-// always partial |w64|^2.
-template <typename TS>
-void launch_update(const KryDesc* D, int count, int nblk_max, int p, bool from_w, bool dot, hipStream_t s);
-// beta = sqrt(sum pnrm); H[j+1, j] = beta; breakdown / non-finite flags.
-void launch_finalize(const KryDesc* D, int count, int j, hipStream_t s);
 // Fused Gram-Schmidt pass (1 or 2) of step j with the previous reduction
 // folded in, and the final normalisation with beta and the flags.
 template <typename TS>

@@ -40,9 +40,11 @@ enum class StateKind { Complex64x2, Real64, Real32 };  // double2 / double / flo
 
 struct ArnoldiWork {
     // Ritz analyses of up to kSlots consecutive steps are in flight at once, in
-    // batched launches on kAnaStreams side streams
-    // streams, each with its own eigensolver outputs (see arnoldi.hip).
-    static constexpr int kSlots = 8;
+    // batched launches on kAnaStreams side streams, each step with its own
+    // eigensolver outputs (see arnoldi.hip).  An analysis at p ~ 50-60 takes
+    // about as long as ten matvecs of the 128^2 and 512^2 grids, so fewer slots
+    // would stall the operator stream while it waits for a free one.
+    static constexpr int kSlots = 16;
     static constexpr int kAnaStreams = 2;
     DevBuf V;         // (m+1) x n state vectors
     DevBuf H;         // (m+1) x m complex128, column-major
@@ -211,7 +213,7 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
 // finished into one launch, so the analyses of a backlog run side by side
 // without a hardware queue each.
 struct StepSet {
-    static constexpr int kMax = 8;
+    static constexpr int kMax = 16;
     const KryDesc* tab[kMax];
     int p[kMax];
 };

@@ -103,8 +103,8 @@ def measured_traffic(profile_name, sources=COLSTEP_SOURCES, key="traffic_bytes_p
     return float(rec[key])
 
 
-def _flops_for(N, nsteps):
-    return colstep_flops(N, nsteps)
+def _flops_for(N, nsteps, bloch):
+    return bloch_flops(N, nsteps) if bloch else colstep_flops(N, nsteps)
 
 
 def run_sweep(args, tsk, W, np, torch):
@@ -140,7 +140,9 @@ def run_sweep(args, tsk, W, np, torch):
     # ms_apply sums the HIP-event durations of those launches
     steps_run = max(b["n_matvec"] for b in rb)
     ms_apply = rb[0]["ms_apply"]
-    flops_total = sum(b["n_matvec"] * _flops_for(c["N"], nsteps) for b, c in zip(rb, sweep))
+    # 128^2 and 256^2 instances run the Bloch-sector stepper, 384^2 the column stepper
+    bloch = [tsk.get_tuning(op) == -1 for op in ops]
+    flops_total = sum(b["n_matvec"] * _flops_for(c["N"], nsteps, bl) for b, c, bl in zip(rb, sweep, bloch))
     launch_ms = ms_apply / steps_run
     flops_step = flops_total / steps_run
     achieved = flops_total / (ms_apply / 1e3) / 1e12
@@ -153,7 +155,8 @@ def run_sweep(args, tsk, W, np, torch):
                                "alpha in {0.25,0.5,0.75,1}, m=64, k=4, tol=1e-8",
                    "n_matvec": [b["n_matvec"] for b in rb], "status": [b["status"] for b in rb],
                    "batched_matvec_ms": launch_ms},
-        "roofline": {"bound": "alu", "kernel": "k_colstep<float,{128,256,384},true> (one batched matvec)",
+        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch<float,{32,64}> + k_colstep<float,384,true> "
+                                               "(one batched matvec)",
                      "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
                      "flops_per_launch": flops_step, "traffic": None},

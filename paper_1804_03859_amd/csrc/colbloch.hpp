@@ -96,18 +96,24 @@ template <int L, typename C> __device__ inline C bloch_fwd(C v, const BlochTw<C,
 // column kx >= 1 (two per workgroup for L = 32, one for L = 64 and 128).
 template <int L> constexpr int bloch_blocks(int M) { return 1 + (L == 32 ? 2 : 4) * M; }
 
-// Grid (bloch_blocks): block 0 the kx = 0 column (diffusion only), then the
-// sectors of column kx = 1..M.  Lawson RK4 as k_colstep.
+// Grid x (bloch_blocks): block 0 the kx = 0 column (diffusion only), then the
+// sectors of column kx = 1..M.  Grid y: the instance, insts[ids[blockIdx.y]]
+// of a batch (input of Arnoldi step jstep: xbase + jstep xstride; finished
+// instances skip), or `one` when insts is null.  Lawson RK4 as k_colstep.
 template <typename real, int L>
-__global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> I, const cplx<real>* __restrict__ twg) {
+__global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, const ColInst<real>* __restrict__ insts,
+                                                         const int* __restrict__ ids, int jstep,
+                                                         const cplx<real>* __restrict__ twg) {
     using C = cplx<real>;
     constexpr int N = 4 * L;
     using G = Geo<N>;
     constexpr int M = G::M, P = 4;
     constexpr int S = L == 128 ? 2 : 1;  // modes per lane
     stepper_wave_priority();
+    const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
+    if (I.active && *I.active == 0) return;
     const int lane = threadIdx.x;
-    const real* __restrict__ xin = I.xbase;
+    const real* __restrict__ xin = I.xbase + jstep * I.xstride;
     real* __restrict__ yout = I.y;
     const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
     const int nsteps = I.nsteps;

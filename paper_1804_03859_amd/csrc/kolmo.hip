@@ -344,6 +344,23 @@ __global__ void k_forcing(const real* __restrict__ lam, const real* __restrict__
     }
 }
 
+// Bloch-sector stepper launch for N = 128, 256, 512: `n` instances (grid y),
+// insts[ids[.]] of a batch at Arnoldi step jstep, or `one` (insts null, n = 1).
+template <typename real>
+void launch_bloch_stepper(int N, const ColInst<real>& one, const ColInst<real>* insts, const int* ids, int n,
+                          int jstep, const cplx<real>* tw, hipStream_t s) {
+    const int M = (N - 1) / 3;
+    if (N == 128)
+        hipLaunchKernelGGL((k_colstep_bloch<real, 32>), dim3(bloch_blocks<32>(M), n), dim3(kWave), 0, s, one, insts,
+                           ids, jstep, tw);
+    else if (N == 256)
+        hipLaunchKernelGGL((k_colstep_bloch<real, 64>), dim3(bloch_blocks<64>(M), n), dim3(kWave), 0, s, one, insts,
+                           ids, jstep, tw);
+    else
+        hipLaunchKernelGGL((k_colstep_bloch<real, 128>), dim3(bloch_blocks<128>(M), n), dim3(kWave), 0, s, one,
+                           insts, ids, jstep, tw);
+}
+
 struct KolmoOp final : Operator {
     int N = 0, M = 0;
     tsk_precision prec = TSK_FP64;
@@ -427,15 +444,8 @@ struct KolmoOp final : Operator {
     }
 
     template <typename real> void launch_bloch(const void* x, void* y) const {
-        const ColInst<real> in = inst<real>(x, 0, y, nullptr);
-        const cplx<real>* t = tw.as<cplx<real>>();
-        if (N == 128)
-            hipLaunchKernelGGL((k_colstep_bloch<real, 32>), dim3(bloch_blocks<32>(M)), dim3(kWave), 0, stream, in, t);
-        else if (N == 256)
-            hipLaunchKernelGGL((k_colstep_bloch<real, 64>), dim3(bloch_blocks<64>(M)), dim3(kWave), 0, stream, in, t);
-        else
-            hipLaunchKernelGGL((k_colstep_bloch<real, 128>), dim3(bloch_blocks<128>(M)), dim3(kWave), 0, stream, in,
-                               t);
+        launch_bloch_stepper<real>(N, inst<real>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, tw.as<cplx<real>>(),
+                                   stream);
     }
     tsk_status apply(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
@@ -747,14 +757,19 @@ int kolmo_cutoff(const Operator* op) {
 }
 
 // ---- batched matvec -----------------------------------------------------------------------------
-// One launch per (N, base kind) group: a task per (instance, kx column), all
-// instances of the batch in one instance table.
+// One launch per (N, base kind, stepper) group, all instances of the batch in
+// one instance table: the column stepper with a task per (instance, kx column),
+// or the Bloch-sector stepper (instances whose single matvec would use it) with
+// the group's instance indices on grid y.
 struct KolmoBatch {
     bool fp32 = false;
     DevBuf insts;
     struct Group {
         int N;
         bool prop;
+        bool bloch = false;
+        DevBuf ids;  // Bloch groups: instance indices
+        int nids = 0;
         const void* tw;
         DevBuf tasks[3];  // task lists for 1 and 2 columns per wavefront
         int ntasks[3] = {0, 0, 0};
@@ -800,19 +815,35 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     }
     TSK_TRY(b->insts.ensure(host.size()));
     TSK_HIP(hipMemcpy(b->insts.ptr, host.data(), host.size(), hipMemcpyHostToDevice));
+    std::vector<std::vector<int>> gids;
     for (int i = 0; i < count; ++i) {
+        const bool kb = kolmo_bloch(ko[i]);
         KolmoBatch::Group* g = nullptr;
-        for (auto& q : b->groups)
-            if (q->N == ko[i]->N && q->prop == ko[i]->prop) g = q.get();
+        for (size_t q = 0; q < b->groups.size(); ++q) {
+            KolmoBatch::Group* c = b->groups[q].get();
+            if (c->N == ko[i]->N && c->prop == ko[i]->prop && c->bloch == kb) {
+                g = c;
+                gids[q].push_back(i);
+            }
+        }
         if (!g) {
             b->groups.push_back(std::make_unique<KolmoBatch::Group>());
+            gids.push_back({i});
             g = b->groups.back().get();
             g->N = ko[i]->N;
             g->prop = ko[i]->prop;
+            g->bloch = kb;
             g->tw = ko[i]->tw.ptr;
             g->force = ko[i]->force_cols;
         }
         g->columns += ko[i]->M + 1;
+    }
+    for (size_t q = 0; q < b->groups.size(); ++q) {
+        KolmoBatch::Group* g = b->groups[q].get();
+        if (!g->bloch) continue;
+        g->nids = int(gids[q].size());
+        TSK_TRY(g->ids.ensure(gids[q].size() * sizeof(int)));
+        TSK_HIP(hipMemcpy(g->ids.ptr, gids[q].data(), gids[q].size() * sizeof(int), hipMemcpyHostToDevice));
     }
     for (auto& g : b->groups) g->work = double(g->columns) * g->N * std::log2(double(g->N));
     std::sort(b->groups.begin(), b->groups.end(),
@@ -830,6 +861,7 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     if (b->groups.size() > 1) TSK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     const hipStream_t s = ops[0]->stream;
     for (auto& g : b->groups) {
+        if (g->bloch) continue;  // no column tasks, nothing to tune
         for (int c = 1; c <= max_cols(g->N); ++c) {
             std::vector<ColTask> tk;
             for (int i = 0; i < count; ++i)
@@ -869,7 +901,14 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
         hipStream_t st = q == 0 ? s : b->aux[q - 1];
         if (q > 0) TSK_HIP(hipStreamWaitEvent(st, b->fork, 0));
         const int c = g->cols;
-        if (b->fp32)
+        if (g->bloch) {
+            if (b->fp32)
+                launch_bloch_stepper<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->ids.as<int>(),
+                                            g->nids, j, static_cast<const cplx<float>*>(g->tw), st);
+            else
+                launch_bloch_stepper<double>(g->N, ColInst<double>{}, b->insts.as<ColInst<double>>(),
+                                             g->ids.as<int>(), g->nids, j, static_cast<const cplx<double>*>(g->tw), st);
+        } else if (b->fp32)
             dispatch_colstep<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->tasks[c].as<ColTask>(),
                                     g->ntasks[c], g->prop, c, g->tw, j, st);
         else

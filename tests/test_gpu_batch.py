@@ -40,6 +40,24 @@ def test_batch_equals_single_runs_bitwise(tsk, prec):
         assert torch.equal(b["X"], r["X"])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bloch_sector_batch_equals_single_runs_bitwise(tsk, prec):
+    # 128^2 and 256^2 Kolmogorov instances take the Bloch-sector stepper alone
+    # and in a batch (one launch per grid size, instances on grid y); the 48^2
+    # one takes the column stepper in its own group
+    print(f"bloch batch vs single prec={prec}", flush=True)
+    cfg = [(128, 20.0, 0.5), (256, 12.0, 0.75), (128, 30.0, 1.0), (48, 25.0, 0.25)]
+    ops = [_kolmo(tsk, N, Re, a, prec) for N, Re, a in cfg]
+    assert [tsk.get_tuning(op) for op in ops[:3]] == [-1, -1, -1]
+    v0s = [_start(tsk, op, N, i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
+    rb = tsk.batch_arnoldi(ops, 40, 4, 1e-8, v0s=v0s, want_vectors=True)
+    for op, v0, b in zip(ops, v0s, rb):
+        r = tsk.arnoldi(op, 40, 4, 1e-8, v0=v0, want_vectors=True)
+        assert b["status"] == r["status"] and b["n_matvec"] == r["n_matvec"]
+        assert np.array_equal(b["lam"], r["lam"]) and np.array_equal(b["res"], r["res"])
+        assert torch.equal(b["X"], r["X"])
+
+
 def test_batch_member_matches_oracle(tsk):
     print("batch member vs oracle", flush=True)
     cfg = [(48, 20.0, 0.5), (32, 10.0, 1.0)]

@@ -48,6 +48,15 @@ __global__ void k_collect(const KryDesc* __restrict__ Dv, int count, RitzResult*
     }
 }
 
+// RitzResults of the n consecutive slots first, first + 1, ... (mod nslots) of
+// the slot tables D (slot t at D + t count) into dst at the same positions:
+// one launch per analysis batch.
+__global__ void k_collect_slots(const KryDesc* __restrict__ D, int count, int nslots, int first,
+                                RitzResult* __restrict__ dst) {
+    const int t = (first + int(blockIdx.x)) % nslots;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[size_t(t) * count + i] = *D[size_t(t) * count + i].rr;
+}
+
 // Zero H, the start-vector flag and the RitzResult of every slot table.
 __global__ void k_reset(const KryDesc* __restrict__ Dv, int count, int nslots) {
     const KryDesc& d = Dv[blockIdx.x];
@@ -303,6 +312,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     std::deque<int> pend, ready;
     int next = 0, steps_run = 0, remaining = count;
     bool ana_used[NA] = {};  // analysis stream a has a batch recorded in ev_ana[a]
+    int batch_last[NS] = {};  // per slot: the last step of the batch that analyses it
     auto enqueue = [&](int j) -> tsk_status {
         const int t = j % NS;
         cgs2_step<TS>(table(t), count, nblk_max, nmax, j, s);
@@ -335,14 +345,20 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         // the Gram-Schmidt of the newest step implies that of the older ones (one stream)
         TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[ready.back() % NS], 0));
         TSK_TRY(ritz_steps_launch(ss, n, count, k, tol, svd, kRealH, st));
-        for (int i = 0; i < n; ++i) {
-            const int t = ready[i] % NS;
-            hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, st, table(t), count,
-                               L.batch_rr.as<RitzResult>() + size_t(t) * count, 0);
-            TSK_HIP(hipMemcpyAsync(rrh + size_t(t) * count, L.batch_rr.as<RitzResult>() + size_t(t) * count,
-                                   size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, st));
-        }
-        for (int i = 0; i < n; ++i) TSK_HIP(hipEventRecord(L.ev_eig[ready[i] % NS], st));
+        // one collection kernel and at most two copies (the slot range may wrap) per batch
+        const int t0 = ready.front() % NS;
+        hipLaunchKernelGGL(k_collect_slots, dim3(n), dim3(256), 0, st, table(0), count, NS, t0,
+                           L.batch_rr.as<RitzResult>());
+        const int n1 = std::min(n, NS - t0);
+        TSK_HIP(hipMemcpyAsync(rrh + size_t(t0) * count, L.batch_rr.as<RitzResult>() + size_t(t0) * count,
+                               size_t(n1) * count * sizeof(RitzResult), hipMemcpyDeviceToHost, st));
+        if (n > n1)
+            TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.as<RitzResult>(), size_t(n - n1) * count * sizeof(RitzResult),
+                                   hipMemcpyDeviceToHost, st));
+        // one event per batch, recorded in its last step's slot: that slot is reused only
+        // after every step up to it has been consumed
+        for (int i = 0; i < n; ++i) batch_last[ready[i] % NS] = ready.back();
+        TSK_HIP(hipEventRecord(L.ev_eig[ready.back() % NS], st));
         TSK_HIP(hipEventRecord(L.ev_ana[a], st));
         ana_used[a] = true;
         for (int i = 0; i < n; ++i) pend.push_back(ready[i]);
@@ -377,7 +393,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         TSK_TRY(launch_ready());
         if (!pend.empty()) {
             const int jo = pend.front();
-            const hipError_t q = hipEventQuery(L.ev_eig[jo % NS]);
+            const hipError_t q = hipEventQuery(L.ev_eig[batch_last[jo % NS] % NS]);
             if (q == hipSuccess) {
                 pend.pop_front();
                 consume(jo);

@@ -241,6 +241,23 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     }
     TSK_TRY(driver_resources(L, m, NS * count));
     RitzResult* rrh = L.rr_host;
+    // stop flags (coherent pinned memory, read by the running analyses): raised by
+    // the host when an instance finishes, so the analyses of its discarded later
+    // steps end early; every side-stream reader of the previous run has finished
+    if (L.stop_count < count) {
+        if (L.stop_host) (void)hipHostFree(L.stop_host);
+        L.stop_host = nullptr;
+        L.stop_count = 0;
+        TSK_HIP(hipHostMalloc((void**)&L.stop_host, size_t(count) * sizeof(int),
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        L.stop_count = count;
+    }
+    int* stop_dev = nullptr;
+    TSK_HIP(hipHostGetDevicePointer((void**)&stop_dev, L.stop_host, 0));
+    for (int i = 0; i < count; ++i) {
+        __atomic_store_n(&L.stop_host[i], 0, __ATOMIC_RELEASE);
+        Dh[i].stop = stop_dev + i;
+    }
     // slot tables: identical except for the eigensolver outputs
     std::vector<KryDesc> Dall(size_t(NS) * count);
     for (int t = 0; t < NS; ++t)
@@ -381,6 +398,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             else continue;
             oc[i].status = st;
             oc[i].done = true;
+            __atomic_store_n(&L.stop_host[i], 1, __ATOMIC_RELEASE);
             --remaining;
             hipLaunchKernelGGL(k_deactivate, dim3(1), dim3(64), 0, s, D, count, NS, i);
         }

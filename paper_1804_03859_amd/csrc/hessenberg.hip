@@ -692,14 +692,28 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
 // second row).  zl: last row of Z (FZ = false) or all of Z (FZ = true), updated
 // with every transformation.  total: sweeps used; failed: no convergence
 // within 30 max(p, 10) sweeps.
+// stop (optional, host-written): the caller no longer needs this analysis; it
+// is read once per sweep, one sweep ahead of its use so the load's latency
+// hides behind the sweep, and a set flag ends the iteration with failed = 2.
+__device__ inline int read_stop(const int* stop) {
+    return stop ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0;
+}
+
 template <bool FZ>
 __device__ __attribute__((always_inline)) inline void francis_real(double* Tr, double* zl, int* blk, int p, int lane,
-                                                                   int& total, int& failed) {
+                                                                   int& total, int& failed,
+                                                                   const int* stop = nullptr) {
     int ihi = p - 1, its = 0;
     total = 0;
     failed = 0;
     const int itmax = 30 * (p > 10 ? p : 10);
+    int stop_seen = read_stop(stop);
     while (ihi > 0) {
+        if (__builtin_amdgcn_readfirstlane(stop_seen)) {
+            failed = 2;
+            break;
+        }
+        stop_seen = read_stop(stop);
         // deflation: largest l <= ihi with a negligible T[l][l-1] (else 0)
         bool s0 = false, s1 = false;
         {
@@ -871,7 +885,8 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(StepSet ss, int kreq, do
     __syncthreads();
 
     int total = 0, failed = 0;
-    francis_real<false>(Tr, zl, blk, p, lane, total, failed);
+    francis_real<false>(Tr, zl, blk, p, lane, total, failed, dsc.stop);
+    if (failed == 2) return;  // a discarded step: nothing reads its outputs
     real_ritz(Tr, blk, zl, p, beta, mu, S, res, lane);
     __syncthreads();
     if (standalone) {

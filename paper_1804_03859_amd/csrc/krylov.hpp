@@ -55,6 +55,7 @@ struct KryDesc {
     void* ritz;         // optional Ritz vectors, n x k complex128 (may be null)
     double* out;        // gathered outputs: mu (2k), lambda (2k), residual (k)
     int64_t ldv, n;
+    const int* stop;    // optional host-written flag (pinned): the run no longer needs this instance's analyses
     int ldh, nblk;
     int active;         // 0: instance finished, kernels skip it
     int steps;          // Arnoldi steps taken (set before the output kernels)

@@ -70,6 +70,8 @@ struct ArnoldiWork {
     DevBuf batch_rr;                   // RitzResult of every instance and slot
     RitzResult* rr_host = nullptr;     // pinned copy of batch_rr
     int rr_host_count = 0;
+    int* stop_host = nullptr;          // per-instance stop flags, coherent pinned memory read by the analyses
+    int stop_count = 0;
     std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
     hipEvent_t ev_cgs[kSlots] = {};    // basis vector j+1 and H column j ready (slot j % kSlots)
     hipEvent_t ev_eig[kSlots] = {};    // Ritz analysis of step j copied to the host
@@ -77,6 +79,7 @@ struct ArnoldiWork {
     hipEvent_t ev_ana[kAnaStreams] = {};  // last analysis batch of each analysis stream done
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
+        if (stop_host) (void)hipHostFree(stop_host);
         for (hipEvent_t e : ev_apply) (void)hipEventDestroy(e);
         for (int t = 0; t < kSlots; ++t) {
             if (ev_cgs[t]) (void)hipEventDestroy(ev_cgs[t]);

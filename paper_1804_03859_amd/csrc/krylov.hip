@@ -56,11 +56,23 @@ __device__ inline double block_sum(double v, double* red) {
     return t;
 }
 
+// Load through a global-address-space pointer: the compiler then emits
+// global loads, which count only against the vector-memory counter, so waits
+// for LDS traffic do not also wait for them (flat loads count against both).
+template <typename T> __device__ inline T ldg(const T* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+#else
+    return p[i];  // host pass only: device functions are never run on the host
+#endif
+}
+
 // Dots of the LDS-staged chunk wl (kChunk elements) with every basis vector
 // (wave-parallel).  Wave w takes the vectors i = w, w + 4, w + 8, ...; it loads
-// kDotU of them at once so that their memory latencies overlap, and
-// accumulates each in the element order e = 0, 1, ... before its shuffle
-// reduction.
+// kDotU of them at once, with clamped indices and no branches so that every
+// load is in flight before the first wait, and accumulates each vector in the
+// element order e = 0, 1, ... (elements beyond the state skipped) before its
+// shuffle reduction.
 constexpr int kDotU = 4;
 template <typename TS, typename A>
 __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, const A* wl, int64_t base,
@@ -68,7 +80,7 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
     constexpr bool kReal = !std::is_same<TS, double2>::value;  // real states: the dots are real
     constexpr int NW = kBT / kWave, E = kChunk / kWave, U = kDotU;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t lim = n - base;
+    const int64_t lim = n - base;  // >= 1
     A wv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) wv[e] = wl[lane + e * kWave];
@@ -77,11 +89,11 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + NW * u;
-            const TS* vi = V + int64_t(i < p ? i : 0) * ldv + base;
+            const TS* vi = V + int64_t(i < p ? i : p - 1) * ldv + base;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int l = lane + e * kWave;
-                vv[u][e] = (i < p && l < lim) ? vi[l] : TS{};
+                const int64_t l = lane + e * kWave;
+                vv[u][e] = ldg(vi, l < lim ? l : lim - 1);
             }
         }
         double2 a[U];
@@ -106,20 +118,25 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
     }
 }
 
-// x[e] - sum_i V[i][g_e] h_i for the thread's EPT elements g_e = g0 + e kBT
-// (ok[e]: inside the state), subtracted in the order i = 0, 1, ..., p-1; the
-// loads of U = 8 basis vectors are issued together ahead of their products.
+// x[e] - sum_i V[i][g_e] h_i for the thread's EPT elements g_e = g0 + e kBT,
+// subtracted in the order i = 0, 1, ..., p-1; the loads of U = 8 basis vectors
+// are issued together ahead of their products.  Elements beyond the state
+// (g_e >= n) read element n - 1 instead and come back as garbage: the caller
+// discards them.
 template <int EPT, typename TS, typename A>
-__device__ inline void project_out(A (&x)[EPT], const bool (&ok)[EPT], const TS* __restrict__ V, int64_t ldv,
-                                   int64_t g0, const double2* hl, int p) {
+__device__ inline void project_out(A (&x)[EPT], const TS* __restrict__ V, int64_t ldv, int64_t g0, int64_t n,
+                                   const double2* hl, int p) {
     constexpr int U = 8;
+    int64_t g[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) g[e] = g0 + e * kBT < n ? g0 + e * kBT : n - 1;
     int i0 = 0;
     for (; i0 + U <= p; i0 += U) {
         TS vv[U][EPT];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) vv[u][e] = ok[e] ? V[int64_t(i0 + u) * ldv + g0 + e * kBT] : TS{};
+            for (int e = 0; e < EPT; ++e) vv[u][e] = ldg(V, int64_t(i0 + u) * ldv + g[e]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -127,8 +144,7 @@ __device__ inline void project_out(A (&x)[EPT], const bool (&ok)[EPT], const TS*
     }
     for (; i0 < p; ++i0)
 #pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (ok[e]) x[e] = axmy(x[e], V[int64_t(i0) * ldv + g0 + e * kBT], hl[i0]);
+        for (int e = 0; e < EPT; ++e) x[e] = axmy(x[e], ldg(V, int64_t(i0) * ldv + g[e]), hl[i0]);
 }
 
 template <typename TS>
@@ -178,8 +194,8 @@ __device__ inline void reduce_coefs(const double2* __restrict__ partial, int nbl
         double2 t[kDotU];
 #pragma unroll
         for (int u = 0; u < kDotU; ++u) {
-            const int i = i0 + stride * u;
-            t[u] = i < p ? partial[size_t(b) * p + i] : cmk<double2>(0.0, 0.0);
+            const int i = i0 + stride * u;  // i >= p: a valid entry, result unused
+            t[u] = ldg(partial, int64_t(b) * p + (i < p ? i : p - 1));
         }
 #pragma unroll
         for (int u = 0; u < kDotU; ++u) sv[u] = cadd(sv[u], t[u]);
@@ -246,10 +262,11 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
         x[e] = zero_of<A>();
         if (ok[e]) x[e] = pass == 1 ? ET<TS>::acc(w_in[g]) : w64[g];
     }
-    project_out<kEPT>(x, ok, V, ldv, g0, hl, p);
+    project_out<kEPT>(x, V, ldv, g0, n, hl, p);
     double s2 = 0.0;
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
+        if (!ok[e]) x[e] = zero_of<A>();
         if (ok[e]) w64[g0 + e * kBT] = x[e];
         wl[threadIdx.x + e * kBT] = x[e];
         s2 += nrm2(x[e]);

@@ -163,7 +163,7 @@ tsk_status normalize_starts(const KryDesc* D, int count, int nslots, int64_t nma
     hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, D, count, nslots);
     launch_check_finite<TS>(D, count, nmax, s);
     launch_dot<TS>(D, count, nblk_max, 0, true, s);
-    launch_reduce(D, count, 0, -1, 0, 0, s);
+    launch_reduce_norm(D, count, 0, s);
     hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, D, count, L.batch_rr.as<RitzResult>(), 1);
     TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(count) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
     TSK_HIP(hipStreamSynchronize(s));

@@ -112,7 +112,12 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = i0 + NW * u;
-                if (i < p) partial[size_t(blockIdx.x) * p + i] = a[u];
+                if (i < p) {
+                    if constexpr (kReal)  // real partials: half the bytes for every block to reduce
+                        reinterpret_cast<double*>(partial)[size_t(blockIdx.x) * p + i] = a[u].x;
+                    else
+                        partial[size_t(blockIdx.x) * p + i] = a[u];
+                }
             }
         }
     }
@@ -183,8 +188,10 @@ __global__ __launch_bounds__(kBT) void k_dot(const KryDesc* __restrict__ Dv, int
 
 // Reduction of the nblk partial dots of the kDotU coefficients i0 + stride u
 // by one wavefront: per coefficient, lanes over blocks in a fixed order, then a
-// shuffle tree (the order k_reduce uses), so every block of a fused pass gets
-// the same bits.  The loads of the kDotU coefficients overlap.
+// shuffle tree, so every block of a fused pass gets the same bits.  The loads
+// of the kDotU coefficients overlap.  REAL: the partials are stored as doubles
+// (real states), the imaginary parts of the results exact zeros.
+template <bool REAL>
 __device__ inline void reduce_coefs(const double2* __restrict__ partial, int nblk, int p, int i0, int stride,
                                    int lane, double2 (&out)[kDotU]) {
     double2 sv[kDotU];
@@ -195,7 +202,11 @@ __device__ inline void reduce_coefs(const double2* __restrict__ partial, int nbl
 #pragma unroll
         for (int u = 0; u < kDotU; ++u) {
             const int i = i0 + stride * u;  // i >= p: a valid entry, result unused
-            t[u] = ldg(partial, int64_t(b) * p + (i < p ? i : p - 1));
+            const int64_t at = int64_t(b) * p + (i < p ? i : p - 1);
+            if constexpr (REAL)
+                t[u] = cmk<double2>(ldg(reinterpret_cast<const double*>(partial), at), 0.0);
+            else
+                t[u] = ldg(partial, at);
         }
 #pragma unroll
         for (int u = 0; u < kDotU; ++u) sv[u] = cadd(sv[u], t[u]);
@@ -230,7 +241,7 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     constexpr int NW = kBT / kWave;
     for (int i0 = wave; i0 < p; i0 += NW * kDotU) {
         double2 sv[kDotU];
-        reduce_coefs(pin, d.nblk, p, i0, NW, lane, sv);
+        reduce_coefs<!std::is_same<TS, double2>::value>(pin, d.nblk, p, i0, NW, lane, sv);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < kDotU; ++u) {
@@ -315,29 +326,13 @@ __global__ __launch_bounds__(kBT) void k_scale_final(const KryDesc* __restrict__
         v[g] = ET<TS>::store(scale_by(w64[g], inv));
 }
 
-// One workgroup per instance; wavefront w reduces coefficients i = w, w + 4, ...
-// (lanes over blocks in a fixed order, then a shuffle tree).
-__global__ __launch_bounds__(kBT) void k_reduce(const KryDesc* __restrict__ Dv, int p, int col, int first,
-                                                int slot) {
+// One wavefront per instance: scal[slot] = sum of the nblk chunk norms (lanes
+// over blocks in a fixed order, then a shuffle tree).
+__global__ __launch_bounds__(kWave) void k_reduce_norm(const KryDesc* __restrict__ Dv, int slot) {
     const KryDesc& d = Dv[blockIdx.x];
     if (!d.active) return;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    double2* Hcol = col >= 0 ? d.H + size_t(d.ldh) * col : nullptr;
-    for (int i = wave; i < p; i += kBT / kWave) {
-        double2 s = cmk<double2>(0.0, 0.0);
-        for (int b = lane; b < d.nblk; b += kWave) s = cadd(s, d.partial[size_t(b) * p + i]);
-        s = wave_sum(s);
-        if (lane == 0) {
-            d.h[i] = s;
-            if (Hcol) Hcol[i] = first ? s : cadd(Hcol[i], s);
-        }
-    }
-    if (slot >= 0 && wave == 0) {
-        double s = 0.0;
-        for (int b = lane; b < d.nblk; b += kWave) s += d.pnrm[b];
-        s = wave_sum(s);
-        if (lane == 0) d.scal[slot] = s;
-    }
+    const double s = reduce_norm(d.pnrm, d.nblk, threadIdx.x);
+    if (threadIdx.x == 0) d.scal[slot] = s;
 }
 
 template <typename TS>
@@ -452,8 +447,8 @@ void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, 
     hipLaunchKernelGGL(k_dot<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, from_x0 ? 1 : 0);
 }
 
-void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(kBT), 0, s, D, p, col, first, slot);
+void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_norm, dim3(count), dim3(kWave), 0, s, D, slot);
 }
 
 template <typename TS>

@@ -76,9 +76,8 @@ void launch_check_finite(const KryDesc* D, int count, int64_t nmax, hipStream_t 
 // Pass 1: partials of conj(V_i) . src and |src|^2, src = x0 (p = 0) or w.
 template <typename TS>
 void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, hipStream_t s);
-// Reduce partials: h = sum_b partial; H column col (if col >= 0) = (first ? 0 : H) + h;
-// scal[slot] = sum_b pnrm when slot >= 0.
-void launch_reduce(const KryDesc* D, int count, int p, int col, int first, int slot, hipStream_t s);
+// scal[slot] = sum_b pnrm (the chunk norms of the last dot pass).
+void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s);
 // Fused Gram-Schmidt pass (1 or 2) of step j with the previous reduction
 // folded in, and the final normalisation with beta and the flags.
 template <typename TS>

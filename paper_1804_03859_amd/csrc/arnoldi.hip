@@ -15,7 +15,7 @@
 // operator stream while the Ritz analysis of H_j waits for a free analysis
 // stream (one wavefront per instance and step, so it barely competes for
 // compute units).  Up to kSlots consecutive steps are in flight, each with its
-// own output slot; the steps that became ready while both analysis streams
+// own output slot; the steps that became ready while every analysis stream
 // were busy are analysed together by one launch, so a backlog never waits for
 // hardware queues.  The host consumes the analyses in step order and stops an
 // instance at the first step whose H_j satisfies the stop test, exactly as a
@@ -352,27 +352,18 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             else if (q != hipErrorNotReady) TSK_HIP(q);
         }
         if (a < 0) return TSK_OK;
-        // only steps whose Gram-Schmidt has finished: a step enqueued behind the running
-        // matvec would hold the whole batch (and the older steps in it) back by a matvec
-        int n = 0;
-        while (n < int(ready.size())) {
-            const hipError_t q = hipEventQuery(L.ev_cgs[ready[n] % NS]);
-            if (q == hipErrorNotReady) break;
-            if (q != hipSuccess) TSK_HIP(q);
-            ++n;
-        }
-        if (n == 0) return TSK_OK;
         const hipStream_t st = L.side[a];
         StepSet ss{};
+        const int n = int(ready.size());
         for (int i = 0; i < n; ++i) {
             ss.tab[i] = table(ready[i] % NS);
             ss.p[i] = ready[i] + 1;
         }
-        // (already complete; the wait also orders the batch after it on the device)
-        TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[ready[n - 1] % NS], 0));
+        // the Gram-Schmidt of the newest step implies that of the older ones (one stream)
+        TSK_HIP(hipStreamWaitEvent(st, L.ev_cgs[ready.back() % NS], 0));
         TSK_TRY(ritz_steps_launch(ss, n, count, k, tol, svd, kRealH, st));
         // one collection kernel and at most two copies (the slot range may wrap) per batch
-        const int t0 = ready[0] % NS;
+        const int t0 = ready.front() % NS;
         hipLaunchKernelGGL(k_collect_slots, dim3(n), dim3(256), 0, st, table(0), count, NS, t0,
                            L.batch_rr.as<RitzResult>());
         const int n1 = std::min(n, NS - t0);
@@ -383,12 +374,12 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
                                    hipMemcpyDeviceToHost, st));
         // one event per batch, recorded in its last step's slot: that slot is reused only
         // after every step up to it has been consumed
-        for (int i = 0; i < n; ++i) batch_last[ready[i] % NS] = ready[n - 1];
-        TSK_HIP(hipEventRecord(L.ev_eig[ready[n - 1] % NS], st));
+        for (int i = 0; i < n; ++i) batch_last[ready[i] % NS] = ready.back();
+        TSK_HIP(hipEventRecord(L.ev_eig[ready.back() % NS], st));
         TSK_HIP(hipEventRecord(L.ev_ana[a], st));
         ana_used[a] = true;
         for (int i = 0; i < n; ++i) pend.push_back(ready[i]);
-        ready.erase(ready.begin(), ready.begin() + n);
+        ready.clear();
         return TSK_OK;
     };
     auto consume = [&](int j) {

@@ -45,7 +45,10 @@ struct ArnoldiWork {
     // about as long as ten matvecs of the 128^2 and 512^2 grids, so fewer slots
     // would stall the operator stream while it waits for a free one.
     static constexpr int kSlots = 16;
-    static constexpr int kAnaStreams = 2;
+    // three analysis streams and the operator's stream use the 4 hardware queues a
+    // process gets by default (GPU_MAX_HW_QUEUES); more streams would share a queue
+    // and could put an analysis in front of a matvec
+    static constexpr int kAnaStreams = 3;
     DevBuf V;         // (m+1) x n state vectors
     DevBuf H;         // (m+1) x m complex128, column-major
     DevBuf w;         // matvec output (state type)

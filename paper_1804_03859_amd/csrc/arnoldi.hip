@@ -16,11 +16,12 @@
 // stream (one wavefront per instance and step, so it barely competes for
 // compute units).  Up to kSlots consecutive steps are in flight, each with its
 // own output slot; the steps that became ready while every analysis stream
-// were busy are analysed together by one launch, so a backlog never waits for
+// was busy are analysed together by one launch, so a backlog never waits for
 // hardware queues.  The host consumes the analyses in step order and stops an
 // instance at the first step whose H_j satisfies the stop test, exactly as a
 // check after every step would; work already launched for later steps is
-// discarded (neither counted nor used).  Batched Navier-Stokes instances share
+// discarded (neither counted nor used), and its analyses return early once the
+// host raises the instance's stop flag.  Batched Navier-Stokes instances share
 // one launch per grid size for the matvec; kernels of the Gram-Schmidt and
 // Ritz phases index the instance by blockIdx.
 #include <chrono>

@@ -58,6 +58,21 @@ def test_bloch_sector_batch_equals_single_runs_bitwise(tsk, prec):
         assert torch.equal(b["X"], r["X"])
 
 
+def test_bloch_sector_batch_512_equals_single_runs_bitwise(tsk):
+    # 512^2 FP32: 128-mode sectors, two modes per lane, in a batched launch
+    print("bloch batch 512 vs single", flush=True)
+    cfg = [(512, 20.0, 0.5), (512, 30.0, 1.0), (128, 15.0, 0.75)]
+    ops = [_kolmo(tsk, N, Re, a, 1) for N, Re, a in cfg]
+    assert [tsk.get_tuning(op) for op in ops] == [-1, -1, -1]
+    v0s = [_start(tsk, op, N, 10 + i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
+    rb = tsk.batch_arnoldi(ops, 24, 2, 1e-6, v0s=v0s, want_vectors=True)
+    for op, v0, b in zip(ops, v0s, rb):
+        r = tsk.arnoldi(op, 24, 2, 1e-6, v0=v0, want_vectors=True)
+        assert b["status"] == r["status"] and b["n_matvec"] == r["n_matvec"]
+        assert np.array_equal(b["lam"], r["lam"]) and np.array_equal(b["res"], r["res"])
+        assert torch.equal(b["X"], r["X"])
+
+
 def test_batch_member_matches_oracle(tsk):
     print("batch member vs oracle", flush=True)
     cfg = [(48, 20.0, 0.5), (32, 10.0, 1.0)]

@@ -155,7 +155,8 @@ def run_sweep(args, tsk, W, np, torch):
                                "alpha in {0.25,0.5,0.75,1}, m=64, k=4, tol=1e-8",
                    "n_matvec": [b["n_matvec"] for b in rb], "status": [b["status"] for b in rb],
                    "batched_matvec_ms": launch_ms},
-        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch<float,{32,64}> + k_colstep<float,384,true> "
+        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch_split<float> + k_colstep_bloch<float,64> + "
+                                               "k_colstep<float,384,true> "
                                                "(one batched matvec)",
                      "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
@@ -195,7 +196,7 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     stepper = tsk.get_tuning(op)  # -1: the Bloch-sector stepper, else columns per wavefront
     if stepper == -1:
         flops = bloch_flops(N, nsteps)
-        kernel = f"k_colstep_bloch<{rt}>"
+        kernel = f"k_colstep_bloch_split<{rt}>" if N == 128 else f"k_colstep_bloch<{rt},{N // 4}>"
         traffic = (measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md")
                    if prec == tsk.TSK_FP64 and N == 128 else None)
     else:
@@ -292,7 +293,7 @@ def run_krylov_schur(args, tsk, W, np, torch):
                    "non_matvec_ms": ms_per_step - ms_apply,
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],
                    "max_residual": float(np.max(r["res"])), "subspace_table": table},
-        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch<double>" if bloch else f"k_colstep<double,{N},true>",
+        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch_split<double>" if bloch else f"k_colstep<double,{N},true>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,
                      "traffic": measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md") if bloch else None},
@@ -362,7 +363,7 @@ def run_optimal(args, tsk, W, np, torch):
                    "sigma": [float(v) for v in r["sigma"]], "gain": [float(v) for v in r["gain"]],
                    "max_residual": float(np.max(r["res"])),
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3), "gain_curve": gains},
-        "roofline": {"bound": "alu", "kernel": ("k_colstep_bloch<double>" if bloch else f"k_colstep<double,{N},true>")
+        "roofline": {"bound": "alu", "kernel": ("k_colstep_bloch_split<double>" if bloch else f"k_colstep<double,{N},true>")
                      + f" + k_colstep_adj<double,{N},true>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,

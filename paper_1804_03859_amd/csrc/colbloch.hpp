@@ -16,15 +16,16 @@
 // rounding.  The base profile's period and harmonic content are checked on the
 // host before this stepper is chosen.
 //
-// Lane layout, in natural DFT order, for the whole matvec:
-//   L = 32:  one workgroup holds two sectors of a column (lanes 0..31, 32..63),
-//            one mode per lane; five radix-2 levels within each 32-lane half.
-//   L = 64:  one sector per workgroup, one mode per lane; six levels.
-//   L = 128: one sector per workgroup, two modes per lane; the 128-point
-//            cross-lane transform of colxl.hpp.
+// Lane layout, in natural DFT order, for the whole matvec (one sector per
+// workgroup of one wavefront):
+//   L = 32:  the real and imaginary parts of a mode on a lane pair
+//            (k_colstep_bloch_split below); five radix-2 levels.
+//   L = 64:  one mode per lane; six levels.
+//   L = 128: two modes per lane; the 128-point cross-lane transform of
+//            colxl.hpp.
 // The levels exchange with the partner lane ^ h: h = 32, 16 by permlane swaps,
 // h = 8, 4 by DPP row shifts under complementary bank masks, h = 2, 1 by DPP
-// quad permutations.  The inverse is decimation in frequency (natural order
+// quad permutations (common.hpp).  The inverse is decimation in frequency (natural order
 // in, bit-reversed grid positions out) and the forward its transpose
 // (decimation in time), so the grid side is read in the permuted order and
 // nothing is reordered.
@@ -43,17 +44,16 @@ template <int H, typename C> __device__ inline C half_xor_c(C v, int lane) {
     return cmk<C>(xor_lane<H>(v.x, lane), xor_lane<H>(v.y, lane));
 }
 
-// Masked level twiddles of the L-point DFT (forward sign, L = 32 or 64), level
-// h = 1 << l: e^{-2 pi i (nu mod h) / (2h)} on lanes with bit h of nu set, 1 on
-// the others; twN[t] = e^{-2 pi i t / N}, N = 4L.
-template <typename C, int L> struct BlochTw {
-    static constexpr int NL = L == 32 ? 5 : 6;
-    C lv[NL];
+// Masked level twiddles of the 64-point DFT (forward sign), level h = 1 << l:
+// e^{-2 pi i (nu mod h) / (2h)} on lanes with bit h of nu set, 1 on the others;
+// twN[t] = e^{-2 pi i t / 256}.
+template <typename C> struct BlochTw {
+    C lv[6];
     __device__ void load(const C* twN, int nu) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l) {
+        for (int l = 0; l < 6; ++l) {
             const int h = 1 << l;
-            lv[l] = (nu & h) ? twN[(nu & (h - 1)) * (4 * L / (2 * h))] : cmk<C>(1, 0);
+            lv[l] = (nu & h) ? twN[(nu & (h - 1)) * (256 / (2 * h))] : cmk<C>(1, 0);
         }
     }
 };
@@ -73,37 +73,37 @@ template <int H, int SIGN, typename C> __device__ inline C bloch_dit(C v, const 
     return cmk<C>(p.x + sg * z.x, p.y + sg * z.y);
 }
 // inverse (natural -> bit-reversed order) and forward (bit-reversed -> natural)
-// L-point DFTs, one value per lane (L = 32 within 32-lane halves, or 64)
-template <int L, typename C> __device__ inline C bloch_inv(C v, const BlochTw<C, L>& t, int lane) {
-    if constexpr (L == 64) v = bloch_dif<32, +1>(v, t.lv[5], lane);
+// 64-point DFTs, one value per lane
+template <typename C> __device__ inline C bloch_inv(C v, const BlochTw<C>& t, int lane) {
+    v = bloch_dif<32, +1>(v, t.lv[5], lane);
     v = bloch_dif<16, +1>(v, t.lv[4], lane);
     v = bloch_dif<8, +1>(v, t.lv[3], lane);
     v = bloch_dif<4, +1>(v, t.lv[2], lane);
     v = bloch_dif<2, +1>(v, t.lv[1], lane);
     return bloch_dif<1, +1>(v, t.lv[0], lane);
 }
-template <int L, typename C> __device__ inline C bloch_fwd(C v, const BlochTw<C, L>& t, int lane) {
+template <typename C> __device__ inline C bloch_fwd(C v, const BlochTw<C>& t, int lane) {
     v = bloch_dit<1, -1>(v, t.lv[0], lane);
     v = bloch_dit<2, -1>(v, t.lv[1], lane);
     v = bloch_dit<4, -1>(v, t.lv[2], lane);
     v = bloch_dit<8, -1>(v, t.lv[3], lane);
     v = bloch_dit<16, -1>(v, t.lv[4], lane);
-    if constexpr (L == 64) v = bloch_dit<32, -1>(v, t.lv[5], lane);
-    return v;
+    return bloch_dit<32, -1>(v, t.lv[5], lane);
 }
 
-// Workgroups of a Bloch launch: the kx = 0 column, then the sectors of every
-// column kx >= 1 (two per workgroup for L = 32, one for L = 64 and 128).
-template <int L> constexpr int bloch_blocks(int M) { return 1 + (L == 32 ? 2 : 4) * M; }
+// Workgroups of a Bloch launch: the kx = 0 column, then the four sectors of
+// every column kx >= 1, one per workgroup.
+inline int bloch_blocks(int M) { return 1 + 4 * M; }
 
-// Grid x (bloch_blocks): block 0 the kx = 0 column (diffusion only), then the
-// sectors of column kx = 1..M.  Grid y: the instance, insts[ids[blockIdx.y]]
+// L = 64 and 128.  Grid x (bloch_blocks): block 0 the kx = 0 column (diffusion
+// only), then the sectors of column kx = 1..M.  Grid y: the instance, insts[ids[blockIdx.y]]
 // of a batch (input of Arnoldi step jstep: xbase + jstep xstride; finished
 // instances skip), or `one` when insts is null.  Lawson RK4 as k_colstep.
 template <typename real, int L>
 __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, const ColInst<real>* __restrict__ insts,
                                                          const int* __restrict__ ids, int jstep,
                                                          const cplx<real>* __restrict__ twg) {
+    static_assert(L == 64 || L == 128, "sector length");
     using C = cplx<real>;
     constexpr int N = 4 * L;
     using G = Geo<N>;
@@ -130,14 +130,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
         return;
     }
     const int b = int(blockIdx.x) - 1;
-    int kx, r;
-    if constexpr (L == 32) {
-        kx = 1 + b / 2;
-        r = 2 * (b % 2) + (lane >> 5);
-    } else {
-        kx = 1 + b / 4;
-        r = b % 4;
-    }
+    const int kx = 1 + b / 4, r = b % 4;
     const double kxv = alpha * kx;
     const real* xs = xin + G::seg(kx);
     real E1[S], Eh[S], g1[S], kmask[S], nuv[S];
@@ -146,7 +139,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
     C w[S], acc[S], s[S];
 #pragma unroll
     for (int sl = 0; sl < S; ++sl) {
-        const int idx = L == 32 ? (lane & 31) : lane + 64 * sl;  // DFT index in the sector
+        const int idx = lane + 64 * sl;  // DFT index in the sector
         const int m = idx < L / 2 ? idx : idx - L;
         const int jy = P * m + r;
         const bool kp = jy >= -M && jy <= M;
@@ -158,17 +151,17 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
         g1[sl] = kp ? real(kxv * (1.0 - cprop / K2)) : real(0);
         kmask[sl] = kp ? real(1.0 / L) : real(0);
         // profile at the grid point this slot holds after the inverse transform
-        const int gpos = L == 32 ? bitrev5(lane & 31) : L == 64 ? bitrev6b(lane) : xl_grid_pos(lane, sl);
+        const int gpos = L == 64 ? bitrev6b(lane) : xl_grid_pos(lane, sl);
         nuv[sl] = I.negU[gpos];
         w[sl] = kp ? cmk<C>(xs[2 * qs[sl]], xs[2 * qs[sl] + 1]) : cmk<C>(real(0), real(0));
         acc[sl] = s[sl] = w[sl];
     }
-    BlochTw<C, L == 128 ? 64 : L> btw;
+    BlochTw<C> btw;
     XlTw<C> xtw;
     if constexpr (L == 128)
         xtw.load(twg, lane, N / 128);
     else
-        btw.load(twg, L == 32 ? (lane & 31) : lane);
+        btw.load(twg, lane);
     const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
 
     for (int st = 0; st < nsteps; ++st) {
@@ -182,13 +175,13 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
             if constexpr (L == 128)
                 xl_fft_inv<1>(v, xtw, lane);
             else
-                v[0][0][0] = bloch_inv<L>(v[0][0][0], btw, lane);
+                v[0][0][0] = bloch_inv(v[0][0][0], btw, lane);
 #pragma unroll
             for (int sl = 0; sl < S; ++sl) v[0][0][sl] = cmk<C>(nuv[sl] * v[0][0][sl].x, nuv[sl] * v[0][0][sl].y);
             if constexpr (L == 128)
                 xl_fft_fwd<1>(v, xtw, lane);
             else
-                v[0][0][0] = bloch_fwd<L>(v[0][0][0], btw, lane);
+                v[0][0][0] = bloch_fwd(v[0][0][0], btw, lane);
 #pragma unroll
             for (int sl = 0; sl < S; ++sl) {
                 const C nh = cmk<C>(v[0][0][sl].x * kmask[sl], v[0][0][sl].y * kmask[sl]);
@@ -216,6 +209,131 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
             ys[2 * qs[sl]] = w[sl].x;
             ys[2 * qs[sl] + 1] = w[sl].y;
         }
+}
+
+// ---- 128^2: one sector per wavefront, real and imaginary parts on lane pairs ----------
+// The 32-mode sectors of N = 128 with lane = 2 q + c: q the mode's DFT index
+// (natural order), c = 0 the real part, c = 1 the imaginary part.  Every lane
+// holds one real number, so an exchange moves two 32-bit words instead of four,
+// the butterflies and the integrating-factor RK4 are one FP64 operation per
+// lane, and a twiddle product needs the other part of the same mode (lane ^ 1):
+//     (t W)_c = t_c Re W + t_(1-c) (c ? Im W : -Im W).
+// The DFT levels h = 16 ... 1 pair lanes 2h apart; the inverse is decimation in
+// frequency (lane q ends with grid position bitrev5(q)), the forward its
+// transpose, as in the two-sectors-per-wavefront layout.
+template <typename real> struct SplitTw {
+    real wr[5], ws[5];  // level h = 1 << l: Re W', and (c ? Im W' : -Im W') for the forward W'
+    real sg[5];         // butterfly sign: -1 on the lanes whose mode index has bit h set
+    __device__ void load(const cplx<real>* twN, int q, int c) {
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+            const int h = 1 << l;
+            const cplx<real> w = (q & h) ? twN[(q & (h - 1)) * (128 / (2 * h))] : cmk<cplx<real>>(1, 0);
+            wr[l] = w.x;
+            ws[l] = c ? w.y : -w.y;
+            sg[l] = (q & h) ? real(-1) : real(1);
+        }
+    }
+};
+
+template <int H> constexpr int split_level() { return H == 16 ? 4 : H == 8 ? 3 : H == 4 ? 2 : H == 2 ? 1 : 0; }
+template <int H, typename real> __device__ inline real split_dif(real v, const SplitTw<real>& t, int lane) {
+    constexpr int l = split_level<H>();
+    const real tt = t.sg[l] * v + xor_lane<2 * H>(v, lane);
+    if constexpr (H == 1) return tt;
+    return tt * t.wr[l] - xor_lane<1>(tt, lane) * t.ws[l];  // times conj(W')
+}
+template <int H, typename real> __device__ inline real split_dit(real v, const SplitTw<real>& t, int lane) {
+    constexpr int l = split_level<H>();
+    real z = v;
+    if constexpr (H != 1) z = v * t.wr[l] + xor_lane<1>(v, lane) * t.ws[l];  // times W'
+    return t.sg[l] * z + xor_lane<2 * H>(z, lane);
+}
+
+// Grid as k_colstep_bloch (bloch_blocks(M) workgroups: kx = 0, then one sector
+// per workgroup), N = 128 only.
+template <typename real>
+__global__ __launch_bounds__(kWave) void k_colstep_bloch_split(ColInst<real> one,
+                                                               const ColInst<real>* __restrict__ insts,
+                                                               const int* __restrict__ ids, int jstep,
+                                                               const cplx<real>* __restrict__ twg) {
+    constexpr int N = 128, L = 32;
+    using G = Geo<N>;
+    constexpr int M = G::M, P = 4;
+    stepper_wave_priority();
+    const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
+    if (I.active && *I.active == 0) return;
+    const int lane = threadIdx.x;
+    const real* __restrict__ xin = I.xbase + jstep * I.xstride;
+    real* __restrict__ yout = I.y;
+    const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
+    const int nsteps = I.nsteps;
+    if (blockIdx.x == 0) {
+        // kx = 0: the advection term vanishes (d/dx of a y-only field)
+        for (int q = lane; q < M; q += kWave) {
+            const double jy = q + 1;
+            const real E1 = real(exp(-jy * jy * dt / Re));
+            real re = xin[2 * q], im = xin[2 * q + 1];
+            for (int st = 0; st < nsteps; ++st) { re *= E1; im *= E1; }
+            yout[2 * q] = re;
+            yout[2 * q + 1] = im;
+        }
+        return;
+    }
+    const int b = int(blockIdx.x) - 1;
+    const int kx = 1 + b / 4, r = b % 4;
+    const int q = lane >> 1, c = lane & 1;
+    const int m = q < L / 2 ? q : q - L;
+    const int jy = P * m + r;
+    const bool kp = jy >= -M && jy <= M;
+    const int e = kp ? 2 * (jy + M) + c : 0;  // this lane's real number in the column segment
+    const double kxv = alpha * kx;
+    const double K2 = kxv * kxv + double(jy) * jy;
+    const real E1 = kp ? real(exp(-K2 * dt / Re)) : real(0);
+    const real Eh = kp ? real(exp(-K2 * (0.5 * dt) / Re)) : real(0);
+    const real g1 = kp ? real(kxv * (1.0 - cprop / K2)) : real(0);
+    const real g1s = c ? g1 : -g1;  // i g1 s: real part -g1 Im s, imaginary part g1 Re s
+    const real kmask = kp ? real(1.0 / L) : real(0);
+    const real nuv = I.negU[bitrev5(q)];  // profile at this lane's grid position after the inverse
+    const real* xs = xin + G::seg(kx);
+    real w = kp ? xs[e] : real(0);
+    real acc = w, s = w;
+    SplitTw<real> tw;
+    tw.load(twg, q, c);
+    const real hh = real(dt), h2 = real(0.5 * dt), h3 = real(dt / 3.0), h6 = real(dt / 6.0);
+
+    for (int st = 0; st < nsteps; ++st) {
+        s = w;
+#pragma unroll 4
+        for (int stage = 0; stage < 4; ++stage) {
+            real v = g1s * xor_lane<1>(s, lane);
+            v = split_dif<16>(v, tw, lane);
+            v = split_dif<8>(v, tw, lane);
+            v = split_dif<4>(v, tw, lane);
+            v = split_dif<2>(v, tw, lane);
+            v = split_dif<1>(v, tw, lane);
+            v *= nuv;
+            v = split_dit<1>(v, tw, lane);
+            v = split_dit<2>(v, tw, lane);
+            v = split_dit<4>(v, tw, lane);
+            v = split_dit<8>(v, tw, lane);
+            v = split_dit<16>(v, tw, lane);
+            const real nh = v * kmask;
+            if (stage == 0) {
+                acc = E1 * (w + h6 * nh);
+                s = Eh * (w + h2 * nh);
+            } else if (stage == 1) {
+                acc += h3 * Eh * nh;
+                s = Eh * w + h2 * nh;
+            } else if (stage == 2) {
+                acc += h3 * Eh * nh;
+                s = E1 * w + hh * Eh * nh;
+            } else {
+                w = acc + h6 * nh;
+            }
+        }
+    }
+    if (kp) yout[G::seg(kx) + e] = w;
 }
 
 }  // namespace tsk

@@ -351,13 +351,13 @@ void launch_bloch_stepper(int N, const ColInst<real>& one, const ColInst<real>* 
                           int jstep, const cplx<real>* tw, hipStream_t s) {
     const int M = (N - 1) / 3;
     if (N == 128)
-        hipLaunchKernelGGL((k_colstep_bloch<real, 32>), dim3(bloch_blocks<32>(M), n), dim3(kWave), 0, s, one, insts,
+        hipLaunchKernelGGL((k_colstep_bloch_split<real>), dim3(bloch_blocks(M), n), dim3(kWave), 0, s, one, insts,
                            ids, jstep, tw);
     else if (N == 256)
-        hipLaunchKernelGGL((k_colstep_bloch<real, 64>), dim3(bloch_blocks<64>(M), n), dim3(kWave), 0, s, one, insts,
+        hipLaunchKernelGGL((k_colstep_bloch<real, 64>), dim3(bloch_blocks(M), n), dim3(kWave), 0, s, one, insts,
                            ids, jstep, tw);
     else
-        hipLaunchKernelGGL((k_colstep_bloch<real, 128>), dim3(bloch_blocks<128>(M), n), dim3(kWave), 0, s, one,
+        hipLaunchKernelGGL((k_colstep_bloch<real, 128>), dim3(bloch_blocks(M), n), dim3(kWave), 0, s, one,
                            insts, ids, jstep, tw);
 }
 

@@ -237,9 +237,34 @@ template <typename real> struct SplitTw {
 };
 
 template <int H> constexpr int split_level() { return H == 16 ? 4 : H == 8 ? 3 : H == 4 ? 2 : H == 2 ? 1 : 0; }
+
+// Butterfly sum/difference with the partner lane ^ B: the lower lane of the pair
+// gets v + partner, the upper one partner - v (sg = -1 on upper lanes).  For
+// B = 16, 32 a permlane swap of v with itself leaves (lower value, upper value)
+// in its two results on both lanes of a pair, so no select is needed.
+template <int B, typename real> __device__ inline real split_bfly(real v, real sg, int lane) {
+    if constexpr ((B == 16 || B == 32) && sizeof(real) == 4) {
+        const unsigned x = __float_as_uint(v);
+        const auto px = B == 32 ? __builtin_amdgcn_permlane32_swap(x, x, false, false)
+                                : __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return sg * __uint_as_float(px[1]) + __uint_as_float(px[0]);
+    } else if constexpr (B == 16 || B == 32) {
+        const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(double(v)));
+        unsigned lo = unsigned(u & 0xffffffffull), hi = unsigned(u >> 32);
+        const auto pl = B == 32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                                : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto ph = B == 32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                                : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        const double a = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ph[0]) << 32) | pl[0]));
+        const double b = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ph[1]) << 32) | pl[1]));
+        return real(sg * b + a);
+    } else {
+        return sg * v + xor_lane<B>(v, lane);
+    }
+}
 template <int H, typename real> __device__ inline real split_dif(real v, const SplitTw<real>& t, int lane) {
     constexpr int l = split_level<H>();
-    const real tt = t.sg[l] * v + xor_lane<2 * H>(v, lane);
+    const real tt = split_bfly<2 * H>(v, t.sg[l], lane);
     if constexpr (H == 1) return tt;
     return tt * t.wr[l] - xor_lane<1>(tt, lane) * t.ws[l];  // times conj(W')
 }
@@ -247,7 +272,7 @@ template <int H, typename real> __device__ inline real split_dit(real v, const S
     constexpr int l = split_level<H>();
     real z = v;
     if constexpr (H != 1) z = v * t.wr[l] + xor_lane<1>(v, lane) * t.ws[l];  // times W'
-    return t.sg[l] * z + xor_lane<2 * H>(z, lane);
+    return split_bfly<2 * H>(z, t.sg[l], lane);
 }
 
 // Grid as k_colstep_bloch (bloch_blocks(M) workgroups: kx = 0, then one sector

@@ -58,19 +58,28 @@ template <typename C> struct BlochTw {
     }
 };
 
-template <int H, int SIGN, typename C> __device__ inline C bloch_dif(C v, const C& w, int lane) {
+// v + partner on the lower lane of the pair (lane, lane ^ H), partner - v on
+// the upper one; for H = 16, 32 straight from the two results of a permlane swap.
+template <int H, typename C> __device__ inline C bloch_bfly(C v, int lane) {
     using R = decltype(C{}.x);
     const R sg = (lane & H) ? R(-1) : R(1);
-    const C p = half_xor_c<H>(v, lane);
-    const C t = cmk<C>(p.x + sg * v.x, p.y + sg * v.y);
+    if constexpr (H == 16 || H == 32) {
+        R lx, ux, ly, uy;
+        swap_pair<H>(v.x, lx, ux);
+        swap_pair<H>(v.y, ly, uy);
+        return cmk<C>(sg * ux + lx, sg * uy + ly);
+    } else {
+        const C p = half_xor_c<H>(v, lane);
+        return cmk<C>(p.x + sg * v.x, p.y + sg * v.y);
+    }
+}
+template <int H, int SIGN, typename C> __device__ inline C bloch_dif(C v, const C& w, int lane) {
+    const C t = bloch_bfly<H>(v, lane);
     return H == 1 ? t : cmul(t, tw_sign<SIGN>(w));
 }
 template <int H, int SIGN, typename C> __device__ inline C bloch_dit(C v, const C& w, int lane) {
-    using R = decltype(C{}.x);
-    const R sg = (lane & H) ? R(-1) : R(1);
     const C z = H == 1 ? v : cmul(v, tw_sign<SIGN>(w));
-    const C p = half_xor_c<H>(z, lane);
-    return cmk<C>(p.x + sg * z.x, p.y + sg * z.y);
+    return bloch_bfly<H>(z, lane);
 }
 // inverse (natural -> bit-reversed order) and forward (bit-reversed -> natural)
 // 64-point DFTs, one value per lane
@@ -243,21 +252,10 @@ template <int H> constexpr int split_level() { return H == 16 ? 4 : H == 8 ? 3 :
 // B = 16, 32 a permlane swap of v with itself leaves (lower value, upper value)
 // in its two results on both lanes of a pair, so no select is needed.
 template <int B, typename real> __device__ inline real split_bfly(real v, real sg, int lane) {
-    if constexpr ((B == 16 || B == 32) && sizeof(real) == 4) {
-        const unsigned x = __float_as_uint(v);
-        const auto px = B == 32 ? __builtin_amdgcn_permlane32_swap(x, x, false, false)
-                                : __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return sg * __uint_as_float(px[1]) + __uint_as_float(px[0]);
-    } else if constexpr (B == 16 || B == 32) {
-        const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(double(v)));
-        unsigned lo = unsigned(u & 0xffffffffull), hi = unsigned(u >> 32);
-        const auto pl = B == 32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
-                                : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto ph = B == 32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
-                                : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        const double a = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ph[0]) << 32) | pl[0]));
-        const double b = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ph[1]) << 32) | pl[1]));
-        return real(sg * b + a);
+    if constexpr (B == 16 || B == 32) {
+        real lo, up;
+        swap_pair<B>(v, lo, up);
+        return sg * up + lo;
     } else {
         return sg * v + xor_lane<B>(v, lane);
     }

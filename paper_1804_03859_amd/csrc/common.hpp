@@ -127,12 +127,40 @@ template <int H> __device__ inline float xor_lane(float v, int lane) {
     return __uint_as_float(xor_lane_u32<H>(__float_as_uint(v), lane));
 }
 
+// For H = 16, 32: a permlane swap of a 32-bit word with itself returns, on both
+// lanes of each pair (lane, lane ^ H), the lower lane's word in [0] and the upper
+// lane's in [1].
+template <int H> __device__ inline void swap_pair_u32(unsigned x, unsigned& lower, unsigned& upper) {
+    static_assert(H == 16 || H == 32, "permlane distance");
+    const auto p = H == 32 ? __builtin_amdgcn_permlane32_swap(x, x, false, false)
+                           : __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    lower = p[0];
+    upper = p[1];
+}
+template <int H> __device__ inline void swap_pair(double v, double& lower, double& upper) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    unsigned l0, u0, l1, u1;
+    swap_pair_u32<H>(unsigned(u & 0xffffffffull), l0, u0);
+    swap_pair_u32<H>(unsigned(u >> 32), l1, u1);
+    lower = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(l1) << 32) | l0));
+    upper = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(u1) << 32) | u0));
+}
+template <int H> __device__ inline void swap_pair(float v, float& lower, float& upper) {
+    unsigned l, u;
+    swap_pair_u32<H>(__float_as_uint(v), l, u);
+    lower = __uint_as_float(l);
+    upper = __uint_as_float(u);
+}
+
 // Butterfly sum over the wavefront (partners lane ^ 32, ^ 16, ..., ^ 1); every
 // lane ends with the same total.  The whole wavefront must be active.
 __device__ inline double wave_sum(double v) {
     const int lane = lane_id();
-    v += xor_lane<32>(v, lane);
-    v += xor_lane<16>(v, lane);
+    double lo, up;
+    swap_pair<32>(v, lo, up);
+    v = lo + up;  // = v + partner on both lanes (addition commutes exactly)
+    swap_pair<16>(v, lo, up);
+    v = lo + up;
     v += xor_lane<8>(v, lane);
     v += xor_lane<4>(v, lane);
     v += xor_lane<2>(v, lane);

@@ -124,14 +124,14 @@ __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, 
 }
 
 // x[e] - sum_i V[i][g_e] h_i for the thread's EPT elements g_e = g0 + e kBT,
-// subtracted in the order i = 0, 1, ..., p-1; the loads of U = 8 basis vectors
+// subtracted in the order i = 0, 1, ..., p-1; the loads of U = 16 basis vectors
 // are issued together ahead of their products.  Elements beyond the state
 // (g_e >= n) read element n - 1 instead and come back as garbage: the caller
 // discards them.
 template <int EPT, typename TS, typename A>
 __device__ inline void project_out(A (&x)[EPT], const TS* __restrict__ V, int64_t ldv, int64_t g0, int64_t n,
                                    const double2* hl, int p) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     int64_t g[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) g[e] = g0 + e * kBT < n ? g0 + e * kBT : n - 1;

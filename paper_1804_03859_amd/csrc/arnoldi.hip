@@ -24,9 +24,12 @@
 // host raises the instance's stop flag.  Batched Navier-Stokes instances share
 // one launch per grid size for the matvec; kernels of the Gram-Schmidt and
 // Ritz phases index the instance by blockIdx.
+#include <array>
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -176,8 +179,31 @@ tsk_status normalize_starts(const KryDesc* D, int count, int nslots, int64_t nma
     return TSK_OK;
 }
 
-// Timing events (two per matvec of up to m + 1 steps), side streams with their
-// events, and the device and pinned copies of nrr RitzResults.
+// The analysis streams are shared by every workspace of the process, one set
+// per device, created on first use and kept until the process ends.  A process
+// gets 4 hardware queues by default (GPU_MAX_HW_QUEUES): with a set per
+// operator, a run after a few operators had been created put its analyses on
+// the operator stream's queue, in front of its matvecs (a 256^2 run took 34
+// instead of 20 ms).  Runs are sequential and wait for these streams at their
+// end, so sharing them is safe.
+tsk_status analysis_streams(hipStream_t (&out)[ArnoldiWork::kAnaStreams]) {
+    static std::mutex mu;
+    static std::map<int, std::array<hipStream_t, ArnoldiWork::kAnaStreams>> per_device;
+    int dev = 0;
+    TSK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_device.find(dev);
+    if (it == per_device.end()) {
+        std::array<hipStream_t, ArnoldiWork::kAnaStreams> st{};
+        for (auto& q : st) TSK_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        it = per_device.emplace(dev, st).first;
+    }
+    for (int a = 0; a < ArnoldiWork::kAnaStreams; ++a) out[a] = it->second[a];
+    return TSK_OK;
+}
+
+// Timing events (two per matvec of up to m + 1 steps), the analysis streams
+// with their events, and the device and pinned copies of nrr RitzResults.
 tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
     constexpr int NS = ArnoldiWork::kSlots;
     while (L.ev_apply.size() < size_t(2 * (m + 1))) {
@@ -188,11 +214,10 @@ tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
     for (int t = 0; t < NS; ++t) {
         if (!L.ev_cgs[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_cgs[t], hipEventDisableTiming));
         if (!L.ev_eig[t]) TSK_HIP(hipEventCreateWithFlags(&L.ev_eig[t], hipEventDisableTiming));
-        if (t < ArnoldiWork::kAnaStreams && !L.side[t])
-            TSK_HIP(hipStreamCreateWithFlags(&L.side[t], hipStreamNonBlocking));
         if (t < ArnoldiWork::kAnaStreams && !L.ev_ana[t])
             TSK_HIP(hipEventCreateWithFlags(&L.ev_ana[t], hipEventDisableTiming));
     }
+    if (!L.side[0]) TSK_TRY(analysis_streams(L.side));
     TSK_TRY(L.batch_rr.ensure(size_t(nrr) * sizeof(RitzResult)));
     if (L.rr_host_count < nrr) {
         if (L.rr_host) (void)hipHostFree(L.rr_host);

@@ -78,7 +78,7 @@ struct ArnoldiWork {
     std::vector<hipEvent_t> ev_apply;  // 2 per matvec (start, end), timing
     hipEvent_t ev_cgs[kSlots] = {};    // basis vector j+1 and H column j ready (slot j % kSlots)
     hipEvent_t ev_eig[kSlots] = {};    // Ritz analysis of step j copied to the host
-    hipStream_t side[kSlots] = {};     // Ritz analyses overlap the next matvecs (first kAnaStreams used)
+    hipStream_t side[kAnaStreams] = {};  // the process's analysis streams (shared, not owned; see arnoldi.hip)
     hipEvent_t ev_ana[kAnaStreams] = {};  // last analysis batch of each analysis stream done
     ~ArnoldiWork() {
         if (rr_host) (void)hipHostFree(rr_host);
@@ -87,7 +87,6 @@ struct ArnoldiWork {
         for (int t = 0; t < kSlots; ++t) {
             if (ev_cgs[t]) (void)hipEventDestroy(ev_cgs[t]);
             if (ev_eig[t]) (void)hipEventDestroy(ev_eig[t]);
-            if (side[t]) (void)hipStreamDestroy(side[t]);
         }
         for (int a = 0; a < kAnaStreams; ++a)
             if (ev_ana[a]) (void)hipEventDestroy(ev_ana[a]);

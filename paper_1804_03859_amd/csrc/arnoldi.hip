@@ -68,6 +68,7 @@ __global__ void k_reset(const KryDesc* __restrict__ Dv, int count, int nslots) {
     if (threadIdx.x == 0) {
         for (int t = 0; t < nslots; ++t) *Dv[size_t(t) * count + blockIdx.x].rr = RitzResult{};
         *reinterpret_cast<int*>(d.scal + 32) = 0;
+        *cgs_counter(d) = 0;
     }
 }
 
@@ -234,10 +235,11 @@ tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
 template <typename TS>
 void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, hipStream_t s) {
     const int p = j + 1;
+    const bool fuse = nblk_max <= kFuseFinalMaxBlocks;
     launch_dot<TS>(Dt, count, nblk_max, p, false, s);
-    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 1, s);  // h1 = V^H w, w -= V h1, dots for pass 2
-    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 2, s);  // h2, w -= V h2, squared norm
-    launch_scale_final<TS>(Dt, count, nmax, j, s);         // beta, H[j+1][j], flags, v_{j+1}
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 1, false, s);  // h1 = V^H w, w -= V h1, dots for pass 2
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 2, fuse, s);   // h2, w -= V h2, squared norm
+    if (!fuse) launch_scale_final<TS>(Dt, count, nmax, j, s);     // beta, H[j+1][j], flags, v_{j+1}
 }
 
 // svd = false: Arnoldi on M (Algorithm 1).  svd = true: Lanczos on M^dagger M

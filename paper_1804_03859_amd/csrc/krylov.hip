@@ -220,6 +220,39 @@ __device__ inline double reduce_norm(const double* __restrict__ pn, int nblk, in
     return wave_sum(s);
 }
 
+// beta_j = ||w64|| from the pass-2 chunk norms, v_{j+1} = w64 / beta_j; block
+// blk == 0 of an instance records H[j+1][j], beta and the breakdown /
+// non-finite flags; blocks blk of nb scale a grid-stride share of the vector.
+template <typename TS> __device__ inline void finalize_scale(const KryDesc& d, int j, int blk, int nb) {
+    using A = typename ET<TS>::A;
+    __shared__ double sb;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (wave == 0) {
+        const double s = reduce_norm(d.pnrm, d.nblk, lane);
+        if (lane == 0) {
+            const double beta = sqrt(s);
+            sb = beta;
+            if (blk == 0) {
+                const double win = sqrt(d.scal[1]);
+                d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
+                d.scal[2] = beta;
+                d.rr->beta = beta;
+                d.rr->w_in = win;
+                d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
+                d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
+                if (d.rr->breakdown && d.rr->bd_step == 0) d.rr->bd_step = j + 1;
+            }
+        }
+    }
+    __syncthreads();
+    const double b = sb;
+    const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
+    TS* v = static_cast<TS*>(d.V) + (j + 1) * d.ldv;
+    const A* w64 = static_cast<const A*>(d.w64);
+    for (int64_t g = int64_t(blk) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(nb) * blockDim.x)
+        v[g] = ET<TS>::store(scale_by(w64[g], inv));
+}
+
 // One Gram-Schmidt pass of step j with the reduction of the previous kernel's
 // partial dots folded in (every block reduces them itself; block 0 writes H):
 //   pass 1: h1 from partial (k_dot), H[.][j] = h1, scal[1] = ||w||^2 from pnrm;
@@ -228,7 +261,8 @@ __device__ inline double reduce_norm(const double* __restrict__ pn, int nblk, in
 // The buffers alternate so that no block overwrites partial sums another block
 // still reads.
 template <typename TS>
-__global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv, int p, int j, int pass) {
+__global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv, int p, int j, int pass,
+                                                  int fuse_final) {
     using A = typename ET<TS>::A;
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active || int(blockIdx.x) >= d.nblk) return;
@@ -287,43 +321,27 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     if (pass == 1) {
         __syncthreads();
         chunk_dots(V, ldv, p, wl, base, n, d.partial2);
+    } else if (fuse_final) {
+        // the last block of the instance to finish does the normalisation: every
+        // thread publishes its stores device-wide, one thread counts the block in
+        __shared__ int last;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(cgs_counter(d), 1) == d.nblk - 1;
+        __syncthreads();
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other blocks' w64 and norms
+            if (threadIdx.x == 0) *cgs_counter(d) = 0;            // for the next step
+            finalize_scale<TS>(d, j, 0, 1);
+        }
     }
 }
 
-// beta_j = ||w64|| from the pass-2 chunk norms (every block reduces them
-// itself), v_{j+1} = w64 / beta_j; block 0 of each instance records H[j+1][j],
-// beta and the breakdown / non-finite flags (the former k_finalize).
 template <typename TS>
 __global__ __launch_bounds__(kBT) void k_scale_final(const KryDesc* __restrict__ Dv, int j) {
-    using A = typename ET<TS>::A;
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active) return;
-    __shared__ double sb;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    if (wave == 0) {
-        const double s = reduce_norm(d.pnrm, d.nblk, lane);
-        if (lane == 0) {
-            const double beta = sqrt(s);
-            sb = beta;
-            if (blockIdx.x == 0) {
-                const double win = sqrt(d.scal[1]);
-                d.H[size_t(d.ldh) * j + (j + 1)] = cmk<double2>(beta, 0.0);
-                d.scal[2] = beta;
-                d.rr->beta = beta;
-                d.rr->w_in = win;
-                d.rr->nonfinite = !(isfinite(beta) && isfinite(win));
-                d.rr->breakdown = (beta <= 64.0 * 2.220446049250313e-16 * win) ? 1 : 0;
-                if (d.rr->breakdown && d.rr->bd_step == 0) d.rr->bd_step = j + 1;
-            }
-        }
-    }
-    __syncthreads();
-    const double b = sb;
-    const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
-    TS* v = static_cast<TS*>(d.V) + (j + 1) * d.ldv;
-    const A* w64 = static_cast<const A*>(d.w64);
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(gridDim.x) * blockDim.x)
-        v[g] = ET<TS>::store(scale_by(w64[g], inv));
+    finalize_scale<TS>(d, j, int(blockIdx.x), int(gridDim.x));
 }
 
 // One wavefront per instance: scal[slot] = sum of the nblk chunk norms (lanes
@@ -452,8 +470,9 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s) {
 }
 
 template <typename TS>
-void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, hipStream_t s) {
-    hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass);
+void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass, fuse_final ? 1 : 0);
 }
 
 template <typename TS>
@@ -487,7 +506,7 @@ template void launch_rotate<float>(const void*, void*, const double*, int64_t, i
     template void launch_check_finite<TS>(const KryDesc*, int, int64_t, hipStream_t);               \
     template void launch_dot<TS>(const KryDesc*, int, int, int, bool, hipStream_t);                  \
     template void launch_scale<TS>(const KryDesc*, int, int64_t, int, hipStream_t);                  \
-    template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, hipStream_t);          \
+    template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, bool, hipStream_t);    \
     template void launch_scale_final<TS>(const KryDesc*, int, int64_t, int, hipStream_t);             \
     template void launch_ritz_vectors<TS>(const KryDesc*, int, int64_t, int, hipStream_t);
 TSK_INST(double)

@@ -32,7 +32,8 @@ constexpr int kEPT = kChunk / kBT;
 inline int cgs_blocks(int64_t n) { return int((n + kChunk - 1) / kChunk); }
 
 // One Arnoldi instance, as seen by the device.  Scalars in `scal`:
-// [0] ||x0||^2, [1] ||w before projection||^2, [2] beta; int flag at scal+32.
+// [0] ||x0||^2, [1] ||w before projection||^2, [2] beta; int flag at scal+32,
+// int block counter of the fused normalisation at scal+34 (cgs_counter).
 struct KryDesc {
     void* V;            // (m+1) vectors of the state type, stride ldv
     void* w;            // matvec output (state type)
@@ -69,6 +70,8 @@ struct KryDesc {
     int ks_pad;
 };
 
+__host__ __device__ inline int* cgs_counter(const KryDesc& d) { return reinterpret_cast<int*>(d.scal + 34); }
+
 // Host launchers; TS = double, float (real states) or double2 (complex).
 // Grids: x over chunks of the longest instance, y over `count` instances.
 template <typename TS>
@@ -80,8 +83,13 @@ void launch_dot(const KryDesc* D, int count, int nblk_max, int p, bool from_x0, 
 void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s);
 // Fused Gram-Schmidt pass (1 or 2) of step j with the previous reduction
 // folded in, and the final normalisation with beta and the flags.
+// fuse_final (pass 2): the last block of each instance also does the work of
+// launch_scale_final, whose launch is then skipped (for short states, where a
+// launch costs more than one block scaling the vector).
+constexpr int kFuseFinalMaxBlocks = 64;
 template <typename TS>
-void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, hipStream_t s);
+void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
+                     hipStream_t s);
 template <typename TS>
 void launch_scale_final(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s);
 // V_{j+1} = w64 / beta (j >= 0), or V_0 = x0 / ||x0|| (j < 0).

@@ -353,6 +353,9 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
+    // a batch of grid-size groups runs its matvec on up to three streams itself;
+    // one analysis stream keeps the streams in use within the 4 hardware queues
+    const int na_use = kb && kolmo_batch_groups(kb.get()) > 1 ? 1 : NA;
     std::vector<int> final_slot(count, 0);
     std::deque<int> pend, ready;
     int next = 0, steps_run = 0, remaining = count;
@@ -373,7 +376,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     auto launch_ready = [&]() -> tsk_status {
         if (ready.empty()) return TSK_OK;
         int a = -1;
-        for (int c = 0; c < NA && a < 0; ++c) {
+        for (int c = 0; c < na_use && a < 0; ++c) {
             if (!ana_used[c]) { a = c; break; }
             const hipError_t q = hipEventQuery(L.ev_ana[c]);
             if (q == hipSuccess) a = c;

@@ -923,4 +923,6 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
 
 void kolmo_batch_free(KolmoBatch* b) { delete b; }
 
+int kolmo_batch_groups(const KolmoBatch* b) { return int(b->groups.size()); }
+
 }  // namespace tsk

@@ -163,6 +163,7 @@ tsk_status cgle_set_resolvent(Operator* op, double omega, double t_transient);
 struct KryDesc;
 struct KolmoBatch;
 void kolmo_batch_free(KolmoBatch* b);
+int kolmo_batch_groups(const KolmoBatch* b);  // grid-size groups of a batch plan
 struct KolmoBatchDeleter {
     void operator()(KolmoBatch* b) const { kolmo_batch_free(b); }
 };

@@ -253,6 +253,55 @@ template <typename TS> __device__ inline void finalize_scale(const KryDesc& d, i
         v[g] = ET<TS>::store(scale_by(w64[g], inv));
 }
 
+// The coefficients of a Gram-Schmidt pass from the partial dots of the kernel
+// before it (pass 1: partial, pass 2: partial2): waves w0, w0 + wstride, ...
+// of the caller each take kDotU coefficients i = i0 + 4u; hl (if not null)
+// receives them; write_h: H column j (pass 1: = h, pass 2: += h) and d.h;
+// pass 1 with write_h also stores ||w||^2 from the chunk norms in scal[1].
+template <typename TS>
+__device__ inline void reduce_pass_coefs(const KryDesc& d, int p, int j, int pass, double2* hl, bool write_h,
+                                         bool norm, int w0, int lane, int wave_of, int wstride) {
+    const double2* pin = pass == 1 ? d.partial : d.partial2;
+    double2* Hcol = d.H + size_t(d.ldh) * j;
+    constexpr int NW = kBT / kWave;
+    for (int i0 = w0; i0 < p; i0 += wstride * kDotU) {
+        double2 sv[kDotU];
+        reduce_coefs<!std::is_same<TS, double2>::value>(pin, d.nblk, p, i0, NW, lane, sv);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < kDotU; ++u) {
+                const int i = i0 + NW * u;
+                if (i < p) {
+                    if (hl) hl[i] = sv[u];
+                    if (write_h) {
+                        Hcol[i] = pass == 1 ? sv[u] : cadd(Hcol[i], sv[u]);
+                        d.h[i] = sv[u];
+                    }
+                }
+            }
+        }
+    }
+    if (pass == 1 && norm && wave_of == 0) {
+        const double s = reduce_norm(d.pnrm, d.nblk, lane);
+        if (lane == 0) d.scal[1] = s;
+    }
+}
+
+// Long states: the coefficients of a pass reduced once, by ceil(p / 16)
+// workgroups per instance (each wave kDotU of them, in the order the fused
+// passes use), instead of by every block of the pass.
+template <typename TS>
+__global__ __launch_bounds__(kBT) void k_reduce_coefs(const KryDesc* __restrict__ Dv, int p, int j, int pass) {
+    const KryDesc& d = Dv[blockIdx.y];
+    if (!d.active) return;
+    constexpr int NW = kBT / kWave;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // block b, wave w: coefficients b * NW * kDotU + w + NW u
+    const int base = int(blockIdx.x) * NW * kDotU;
+    reduce_pass_coefs<TS>(d, p, j, pass, nullptr, true, blockIdx.x == 0, base + wave, lane, wave,
+                          int(gridDim.x) * NW);
+}
+
 // One Gram-Schmidt pass of step j with the reduction of the previous kernel's
 // partial dots folded in (every block reduces them itself; block 0 writes H):
 //   pass 1: h1 from partial (k_dot), H[.][j] = h1, scal[1] = ||w||^2 from pnrm;
@@ -262,7 +311,7 @@ template <typename TS> __device__ inline void finalize_scale(const KryDesc& d, i
 // still reads.
 template <typename TS>
 __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv, int p, int j, int pass,
-                                                  int fuse_final) {
+                                                  int fuse_final, int pre_reduced) {
     using A = typename ET<TS>::A;
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active || int(blockIdx.x) >= d.nblk) return;
@@ -270,26 +319,12 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     __shared__ double2 hl[kMaxKrylov + 1];
     __shared__ double red[kBT / kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const double2* pin = pass == 1 ? d.partial : d.partial2;
-    double2* Hcol = d.H + size_t(d.ldh) * j;
-    constexpr int NW = kBT / kWave;
-    for (int i0 = wave; i0 < p; i0 += NW * kDotU) {
-        double2 sv[kDotU];
-        reduce_coefs<!std::is_same<TS, double2>::value>(pin, d.nblk, p, i0, NW, lane, sv);
-        if (lane == 0) {
-#pragma unroll
-            for (int u = 0; u < kDotU; ++u) {
-                const int i = i0 + NW * u;
-                if (i < p) {
-                    hl[i] = sv[u];
-                    if (blockIdx.x == 0) Hcol[i] = pass == 1 ? sv[u] : cadd(Hcol[i], sv[u]);
-                }
-            }
-        }
-    }
-    if (pass == 1 && blockIdx.x == 0 && wave == 0) {
-        const double s = reduce_norm(d.pnrm, d.nblk, lane);
-        if (lane == 0) d.scal[1] = s;
+    if (pre_reduced) {
+        // k_reduce_coefs has reduced the coefficients into h (and written H)
+        for (int i = threadIdx.x; i < p; i += kBT) hl[i] = d.h[i];
+    } else {
+        reduce_pass_coefs<TS>(d, p, j, pass, hl, int(blockIdx.x) == 0, int(blockIdx.x) == 0, wave, lane,
+                              wave, kBT / kWave);
     }
     __syncthreads();
     const TS* V = static_cast<const TS*>(d.V);
@@ -472,7 +507,14 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s) {
 template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass, fuse_final ? 1 : 0);
+    const bool pre = nblk_max > kFuseFinalMaxBlocks;  // long states: one reduction launch first
+    if (pre) {
+        constexpr int per_block = (kBT / kWave) * kDotU;
+        hipLaunchKernelGGL(k_reduce_coefs<TS>, dim3((p + per_block - 1) / per_block, count), dim3(kBT), 0, s, D, p,
+                           j, pass);
+    }
+    hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass, fuse_final ? 1 : 0,
+                       pre ? 1 : 0);
 }
 
 template <typename TS>

@@ -572,37 +572,28 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
         const bool blane = lane < NB * NB;
         const int bi = blane ? lane / NB : 0, bj = blane ? lane % NB : 0;
         if (blane) {
-            double B[NB][NB];
-#pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-                for (int c = 0; c < NB; ++c) B[a][c] = Tr[(kk + a) * p + kk + c];
-            double u[NB], w[NB];
-#pragma unroll
-            for (int a = 0; a < NB; ++a) {
-                u[a] = 0.0;
-                w[a] = 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    u[a] += B[a][c] * v[c];
-                    w[c] += v[a] * B[a][c];
-                }
+            // g = v^T B v from the whole block (same addresses on every lane);
+            // the lane's own row and column sums and entry read directly, so no
+            // lane selects among register copies
             double g = 0.0;
 #pragma unroll
-            for (int a = 0; a < NB; ++a) g += v[a] * u[a];
-            // select the lane's entry without dynamic register indexing
-            double bij = 0.0, ui = 0.0, wj = 0.0, vi = 0.0, vj = 0.0;
-#pragma unroll
             for (int a = 0; a < NB; ++a) {
-                if (a == bi) { ui = u[a]; vi = v[a]; }
-                if (a == bj) { wj = w[a]; vj = v[a]; }
+                double ua = 0.0;
 #pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (a == bi && c == bj) bij = B[a][c];
+                for (int c = 0; c < NB; ++c) ua += Tr[(kk + a) * p + kk + c] * v[c];
+                g += v[a] * ua;
             }
+            const double* rowi = Tr + (kk + bi) * p + kk;
+            const double* colj = Tr + kk * p + kk + bj;
+            double ui = 0.0, wj = 0.0;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                ui += rowi[c] * v[c];
+                wj += v[c] * colj[c * p];
+            }
+            const double bij = rowi[bj];
+            const double vi = bi == 0 ? v[0] : (bi == 1 ? v[1] : v[NB - 1]);
+            const double vj = bj == 0 ? v[0] : (bj == 1 ? v[1] : v[NB - 1]);
             bval = bij - tau * vi * wj - tau * ui * vj + tau * tau * g * vi * vj;
         }
         double nv[2][NB];

@@ -39,6 +39,29 @@
 
 namespace tsk {
 
+// The analysis streams are shared by every workspace of the process, one set
+// per device, created on first use and kept until the process ends.  A process
+// gets 4 hardware queues by default (GPU_MAX_HW_QUEUES): with a set per
+// operator, a run after a few operators had been created put its analyses on
+// the operator stream's queue, in front of its matvecs (a 256^2 run took 34
+// instead of 20 ms).  Runs are sequential and wait for these streams at their
+// end, so sharing them is safe.
+tsk_status analysis_streams(hipStream_t (&out)[ArnoldiWork::kAnaStreams]) {
+    static std::mutex mu;
+    static std::map<int, std::array<hipStream_t, ArnoldiWork::kAnaStreams>> per_device;
+    int dev = 0;
+    TSK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_device.find(dev);
+    if (it == per_device.end()) {
+        std::array<hipStream_t, ArnoldiWork::kAnaStreams> st{};
+        for (auto& q : st) TSK_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        it = per_device.emplace(dev, st).first;
+    }
+    for (int a = 0; a < ArnoldiWork::kAnaStreams; ++a) out[a] = it->second[a];
+    return TSK_OK;
+}
+
 namespace {
 
 __global__ void k_collect(const KryDesc* __restrict__ Dv, int count, RitzResult* __restrict__ dst, int with_scal) {
@@ -177,29 +200,6 @@ tsk_status normalize_starts(const KryDesc* D, int count, int nslots, int64_t nma
         if (!(rrh[i].beta > 0.0)) return fail(TSK_EINVAL, "start vector " + std::to_string(i) + " is zero");
     }
     launch_scale<TS>(D, count, nmax, -1, s);
-    return TSK_OK;
-}
-
-// The analysis streams are shared by every workspace of the process, one set
-// per device, created on first use and kept until the process ends.  A process
-// gets 4 hardware queues by default (GPU_MAX_HW_QUEUES): with a set per
-// operator, a run after a few operators had been created put its analyses on
-// the operator stream's queue, in front of its matvecs (a 256^2 run took 34
-// instead of 20 ms).  Runs are sequential and wait for these streams at their
-// end, so sharing them is safe.
-tsk_status analysis_streams(hipStream_t (&out)[ArnoldiWork::kAnaStreams]) {
-    static std::mutex mu;
-    static std::map<int, std::array<hipStream_t, ArnoldiWork::kAnaStreams>> per_device;
-    int dev = 0;
-    TSK_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = per_device.find(dev);
-    if (it == per_device.end()) {
-        std::array<hipStream_t, ArnoldiWork::kAnaStreams> st{};
-        for (auto& q : st) TSK_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-        it = per_device.emplace(dev, st).first;
-    }
-    for (int a = 0; a < ArnoldiWork::kAnaStreams; ++a) out[a] = it->second[a];
     return TSK_OK;
 }
 
@@ -353,8 +353,9 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
-    // a batch of grid-size groups runs its matvec on up to three streams itself;
-    // one analysis stream keeps the streams in use within the 4 hardware queues
+    // a batch of grid-size groups runs its extra groups on worker streams 1 and 2;
+    // its analyses then use stream 0 only, so the operator's stream and the three
+    // worker streams stay within the 4 hardware queues
     const int na_use = kb && kolmo_batch_groups(kb.get()) > 1 ? 1 : NA;
     std::vector<int> final_slot(count, 0);
     std::deque<int> pend, ready;

@@ -779,13 +779,13 @@ struct KolmoBatch {
         double work;
     };
     std::vector<std::unique_ptr<Group>> groups;
-    // groups after the first run on their own streams (default priority),
+    // groups after the first run on the process's worker streams 1 and 2
+    // (borrowed, not owned; the Arnoldi driver then analyses on stream 0 only),
     // forked from and joined back into the caller's stream
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> done;
     hipEvent_t fork = nullptr;
     ~KolmoBatch() {
-        for (hipStream_t q : aux) (void)hipStreamDestroy(q);
         for (hipEvent_t e : done) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
     }
@@ -850,11 +850,11 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
               [](const std::unique_ptr<KolmoBatch::Group>& x, const std::unique_ptr<KolmoBatch::Group>& y) {
                   return x->work > y->work;
               });
+    hipStream_t pool[ArnoldiWork::kAnaStreams];
+    if (b->groups.size() > 1) TSK_TRY(analysis_streams(pool));
     for (size_t q = 1; q < b->groups.size(); ++q) {
-        hipStream_t st;
         hipEvent_t ev;
-        TSK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        b->aux.push_back(st);
+        b->aux.push_back(pool[1 + (q - 1) % (ArnoldiWork::kAnaStreams - 1)]);
         TSK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         b->done.push_back(ev);
     }

@@ -164,6 +164,9 @@ struct KryDesc;
 struct KolmoBatch;
 void kolmo_batch_free(KolmoBatch* b);
 int kolmo_batch_groups(const KolmoBatch* b);  // grid-size groups of a batch plan
+// The process's worker streams (one set per device, created on first use):
+// the Arnoldi analyses, and the extra grid-size groups of a batched matvec.
+tsk_status analysis_streams(hipStream_t (&out)[ArnoldiWork::kAnaStreams]);
 struct KolmoBatchDeleter {
     void operator()(KolmoBatch* b) const { kolmo_batch_free(b); }
 };

@@ -39,13 +39,14 @@
 
 namespace tsk {
 
-// The analysis streams are shared by every workspace of the process, one set
-// per device, created on first use and kept until the process ends.  A process
-// gets 4 hardware queues by default (GPU_MAX_HW_QUEUES): with a set per
-// operator, a run after a few operators had been created put its analyses on
-// the operator stream's queue, in front of its matvecs (a 256^2 run took 34
-// instead of 20 ms).  Runs are sequential and wait for these streams at their
-// end, so sharing them is safe.
+// The worker streams (Ritz analyses; the extra grid-size groups of a batched
+// matvec) are shared by every workspace of the process, one set per device,
+// created on first use and kept until the process ends.  A process gets 4
+// hardware queues by default (GPU_MAX_HW_QUEUES): with a set per operator, a
+// run after a few operators had been created put its analyses on the operator
+// stream's queue, in front of its matvecs (a 256^2 run took 34 instead of
+// 20 ms).  Runs are sequential and wait for these streams at their end, so
+// sharing them is safe.
 tsk_status analysis_streams(hipStream_t (&out)[ArnoldiWork::kAnaStreams]) {
     static std::mutex mu;
     static std::map<int, std::array<hipStream_t, ArnoldiWork::kAnaStreams>> per_device;

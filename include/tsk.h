@@ -24,7 +24,10 @@
  *   - Every operator is bound to the hipStream_t given at creation (NULL = the
  *     default stream).  tsk_apply, tsk_from_physical and tsk_to_physical are
  *     asynchronous on that stream.  tsk_arnoldi synchronises it before it writes
- *     host outputs.
+ *     host outputs.  The Arnoldi drivers also use three worker streams of the
+ *     library's own (one set per device, shared by all operators, created on
+ *     first use): Ritz analyses and the extra grid-size groups of a batched
+ *     matvec run there, and every run waits for them before it returns.
  *   - A handle must not be used by two host threads at once.
  */
 #ifndef TSK_H

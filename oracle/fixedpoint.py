@@ -47,8 +47,8 @@ Readings (where the paper leaves a choice open):
   before the iterations; I - H is solved densely.
 * BoostConv: X holds the applied corrections xi_j = x~_{j+1} - x~_j, Y the
   residual decrements r_j - r_{j+1}, r_j = G(x~_j) - x~_j, for the last m
-  iterations; c = Y^+ r from the normal equations (Y^T Y) c = Y^T r, the
-  pseudoinverse of a full-column-rank Y.
+  iterations; c = Y^+ r, the minimum-norm least-squares solution (the
+  pseudo-inverse of Sec. 3.1.3), by an SVD-based least-squares solve.
 * Convergence: ||r_k|| <= tol (the residual of the discrete-time fixed point,
   Euclidean state norm).
 
@@ -216,10 +216,12 @@ def unstable_basis(apply_M, v0, m, k, delta):
 
 
 # ---- BoostConv --------------------------------------------------------------------------
-def boostconv(G, x0, m, tol, max_iter, norm=np.linalg.norm):
+def boostconv(G, x0, m, tol, max_iter, norm=np.linalg.norm, conds=None):
     """BoostConv iteration (Sec. 3.1.3): x~_{k+1} = x~_k + xi_k with
-    xi_k = r_k - Y c + X c, c = argmin ||Y c - r_k||, from the last m pairs
-    (X: applied corrections xi_j, Y: residual decrements r_j - r_{j+1})."""
+    xi_k = r_k - Y c + X c, c = Y^+ r_k (the least-squares solution, from the
+    pseudo-inverse), from the last m pairs (X: applied corrections xi_j, Y:
+    residual decrements r_j - r_{j+1}).  If ``conds`` is a list, the 2-norm
+    condition number of Y at each correction is appended to it."""
     x = np.array(x0, dtype=float, copy=True)
     Xs, Ys = [], []
     hist = []
@@ -238,7 +240,9 @@ def boostconv(G, x0, m, tol, max_iter, norm=np.linalg.norm):
         if Xs:
             X = np.stack(Xs, axis=1)
             Y = np.stack(Ys, axis=1)
-            c = np.linalg.solve(Y.T @ Y, Y.T @ r)  # Y^+ r for full column rank
+            c = np.linalg.lstsq(Y, r, rcond=None)[0]
+            if conds is not None:
+                conds.append(float(np.linalg.cond(Y)))
             xi = r - Y @ c + X @ c
         else:
             xi = r

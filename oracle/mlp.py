@@ -20,7 +20,9 @@ Adam: Kingma & Ba (2015), m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
 w -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
 Parity status: pinned -- backward against central finite differences of the
-unquantised loss; bfloat16 rounding against hand-checked bit patterns; see
+unquantised loss; bfloat16 rounding against hand-checked bit patterns; Adam
+against its closed forms (first step -lr g/(|g| + eps); constant gradients move
+lr g/(|g| + eps) per step) and a two-step case worked by hand; see
 tests/test_oracle_mlp.py.
 """
 from __future__ import annotations

@@ -112,13 +112,20 @@ def test_boostconv_matches_oracle(tsk):
     x = tsk.laminar_state(op)
     r = tsk.boostconv(op, x, 10, 1e-9, 80)
     G, x0 = _oracle_problem(ref, N)
-    xo, ho, ito = boostconv(G, x0, 10, 1e-9 * N, 80)
+    conds = []
+    xo, ho, ito = boostconv(G, x0, 10, 1e-9 * N, 80, conds=conds)
+    # The device solves for c = Y^+ r by the normal equations, the oracle by an
+    # SVD least-squares solve: they differ by about cond(Y)^2 u per iteration.
+    # With cond(Y) <= 1e4 along the run that is <= 1e-8, far below the 1e-5 bar
+    # on the residual histories (which also carry the stepper's 1e-11).
+    assert max(conds) <= 1e4, max(conds)
     assert r["status"] == 0
     assert abs(r["iterations"] - ito) <= 3
     got = _phys(tsk, op, x).ravel()
     assert np.linalg.norm(got - xo) <= 1e-7 * np.linalg.norm(xo)
-    n = min(len(r["hist"]), len(ho), 6)
-    assert np.max(np.abs(N * r["hist"][:n] - ho[:n]) / ho[:n]) <= 1e-5
+    n = min(len(r["hist"]), len(ho))
+    big = ho[:n] >= 1e-6   # well above the tolerance, where relative deviations are meaningful
+    assert np.max(np.abs(N * r["hist"][:n] - ho[:n])[big] / ho[:n][big]) <= 1e-5
 
 
 def test_sfd_matches_oracle(tsk):

@@ -64,3 +64,44 @@ def test_adam_decreases_loss_and_flatten_roundtrip():
     v = mlp.flatten(P)
     Q = mlp.unflatten(v, width=32, out=40)
     assert all(np.array_equal(P[k], Q[k]) for k in mlp.ORDER)
+
+
+def test_adam_first_step_closed_form():
+    # Kingma & Ba (2015), Algorithm 1: after one step the bias-corrected moments
+    # are exactly g and g^2, so the update is -lr g / (|g| + eps) elementwise:
+    # about lr in size whatever the scale of g, and lr/2 at |g| = eps.  A missing
+    # bias correction would shrink it by (1 - b1) / sqrt(1 - b2) ~ 3.2; eps inside
+    # the square root would give lr g / sqrt(g^2 + eps) = lr 1e-4 at |g| = eps.
+    g = np.array([3.0, -2e-3, 1e-8, -1e-8, 5e4, 0.0])
+    P = {"w": np.zeros_like(g)}
+    mlp.adam_step(P, {"w": g}, {}, 1, 0.01)
+    want = np.array([-0.01, 0.01, -0.005, 0.005, -0.01, 0.0])
+    want[0] *= 3.0 / (3.0 + 1e-8)
+    want[1] *= 2e-3 / (2e-3 + 1e-8)
+    want[4] *= 5e4 / (5e4 + 1e-8)
+    assert np.allclose(P["w"], want, rtol=1e-12, atol=0.0)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # with a constant gradient both bias-corrected moments stay exactly g and g^2
+    # at every t, so each step moves each parameter by lr g / (|g| + eps)
+    g = np.array([0.7, -4.0, 2.5e-6])
+    P = {"w": np.ones(3)}
+    st = {}
+    for t in range(1, 51):
+        P = mlp.adam_step(P, {"w": g}, st, t, 1e-3)
+    want = 1.0 - 50 * 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(P["w"], want, rtol=0.0, atol=1e-13)
+
+
+def test_adam_two_steps_by_hand():
+    # b1 = 1/2, b2 = 3/4, eps = 0, lr = 1, w0 = 0, gradients 2 then 4.
+    # t = 1: m = 1, v = 1, m^ = 1/(1/2) = 2, v^ = 1/(1/4) = 4, w = -2/2 = -1.
+    # t = 2: m = 1/2 + 2 = 5/2, v = 3/4 + 4 = 19/4, m^ = (5/2)/(3/4) = 10/3,
+    #        v^ = (19/4)/(7/16) = 76/7, w = -1 - (10/3) sqrt(7/76).
+    P = {"w": np.zeros(1)}
+    st = {}
+    P = mlp.adam_step(P, {"w": np.array([2.0])}, st, 1, 1.0, b1=0.5, b2=0.75, eps=0.0)
+    assert P["w"][0] == -1.0
+    P = mlp.adam_step(P, {"w": np.array([4.0])}, st, 2, 1.0, b1=0.5, b2=0.75, eps=0.0)
+    assert abs(P["w"][0] - (-1.0 - (10.0 / 3.0) * np.sqrt(7.0 / 76.0))) <= 1e-15

@@ -1,12 +1,20 @@
-"""Benchmark: time-stepper Arnoldi on the linearized Kolmogorov flow, 128 x 128,
-FP64 (Re = 20, alpha = 0.5, IF-RK4 dt = 0.005, T = 1, m = 64, k = 6,
-tol = 1e-8), one MI355X.
+"""Benchmark of the time-stepper Arnoldi path on one MI355X.
 
-A step is one pass of the whole path on one start vector: projection of the
-seeded N(0,1) physical field on the dealiased state space, then Arnoldi with a
-matvec (200 IF-RK4 steps) per Krylov vector, CGS2, device Hessenberg QR and the
-stop test after every matvec, and the Ritz values/vectors at the end.  The
-physical start field is resident in HBM before timing starts.
+Default workload (--workload learned): wall time to 6 Ritz pairs on 16 held-out
+linearized Kolmogorov flows at 256 x 256 (Re ~ U[5, 40], alpha in {0.25, 0.5,
+0.75, 1}; IF-RK4 dt = 0.005, T = 1; Arnoldi m = 96, k = 6, tol = 1e-8), for the
+FP32 precision form with the learned start vector against the plain FP64 form
+with a seeded random start (and two more forms for an equal-accuracy view).
+A step is one solve of each of the 16 instances in each form; a solve is one
+whole tsk_arnoldi call: start vector, a matvec (200 IF-RK4 steps) per Krylov
+vector, CGS2, the device Hessenberg QR and stop test after every matvec, and the
+Ritz values and vectors at the end.  The network is trained first (untimed).
+The line also carries the 64-instance sweep's throughput, the accuracy of every
+form (true residuals by an FP64 matvec, |dlambda| against FP64), the roofline
+of the dominant kernel and the CPU oracle's time on the same operator.
+
+Other workloads: kolmo128 (128^2 FP64), kolmo512-fp32, sweep, cgle, general,
+krylov-schur, optimal, fixed-point, resolvent, copy.
 
 Prints ONE JSON line (rank 0).  Other output goes to stderr.
 """
@@ -18,6 +26,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -73,7 +83,9 @@ def cpu_baseline(seconds=12.0):
         if el >= seconds:
             break
     tsgp = count * op.nsteps * N * N / el
+    model, ncpu = cpu_model()
     return {"value": tsgp, "unit": "time-steps*gridpoints/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_logical_cores": ncpu,
             "sample": f"{count} oracle matvecs (200 IF-RK4 steps each) of the 128x128 FP64 operator, "
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
@@ -516,11 +528,114 @@ def run_general(args, tsk, W, np, torch):
     }
 
 
+def cpu_model():
+    """CPU model name of this host (from /proc/cpuinfo) and its logical core count."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline_learned(N, mean_matvecs, seconds=15.0):
+    """The CPU oracle (NumPy FP64, single thread) on a bounded sample of the
+    headline workload: whole matvecs (200 IF-RK4 steps each) of the first
+    held-out 256^2 operator for about `seconds`; the per-matvec time times the
+    FP64 form's mean matvec count gives the oracle's time per solve (its
+    Hessenberg and Gram-Schmidt work is below 1% of that)."""
+    import workloads as W
+    from oracle.kolmogorov import Kolmogorov
+    c = W.learned_holdout()[0]
+    op = Kolmogorov.kolmogorov(N, c["alpha"], c["Re"], c["dt"], c["T"], c["n_forcing"])
+    w = op.project(W.kolmo_start_physical(N, 0))
+    t0 = time.perf_counter()
+    count = 0
+    while True:
+        w = op.apply(w)
+        w /= np.linalg.norm(w)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    ms_mv = el * 1e3 / count
+    model, ncpu = cpu_model()
+    return {"value": ms_mv * mean_matvecs, "unit": "ms per solve", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_logical_cores": ncpu,
+            "ms_per_matvec": ms_mv,
+            "sample": f"{count} oracle matvecs (200 IF-RK4 steps each) of the held-out {N}x{N} FP64 operator "
+                      f"(Re={c['Re']:.3f}, alpha={c['alpha']}) in {el:.1f} s, NumPy/pocketfft single thread; "
+                      f"value = ms per matvec x {mean_matvecs:.1f} (the FP64 form's mean matvecs per solve)"}
+
+
+def _nearest_dist(vals, ref):
+    """Largest distance from a value of `vals` to the nearest value of `ref`."""
+    ref = np.asarray(ref)
+    return max((float(np.min(np.abs(ref - v))) for v in vals), default=0.0)
+
+
+def _true_residuals(tsk, torch, op64, r):
+    """||M x - mu x|| of each unit Ritz vector under the FP64 operator (one FP64
+    matvec of its real and one of its imaginary part)."""
+    out = []
+    for mu, x in zip(r["mu"], r["X"]):
+        x = x / torch.linalg.norm(x)
+        y = torch.zeros_like(x)
+        for part, sc in ((x.real, 1.0), (x.imag, 1j)):
+            a = part.contiguous().double()
+            b = torch.zeros_like(a)
+            tsk.apply(op64, a, b)
+            y = y + sc * b
+        out.append(float(torch.linalg.norm(y - complex(mu) * x)))
+    return out
+
+
+def run_sweep_tsgp(tsk, W, torch, reps=3):
+    """Throughput of the 64-instance FP32 neutral-curve sweep (m = 64, k = 4):
+    time-steps x gridpoints of the matvecs per second of whole-batch wall time."""
+    sweep = W.batch_sweep(64, 0)
+    ops = []
+    for c in sweep:
+        op = tsk.create_kolmo2d(c["N"], tsk.TSK_FP32)
+        tsk.set_params_kolmo(op, c["Re"], c["alpha"], c["dt"], c["T"])
+        tsk.set_base_kolmogorov(op, c["n_forcing"])
+        ops.append(op)
+    tsk.batch_arnoldi(ops, 64, 4, 1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rb = tsk.batch_arnoldi(ops, 64, 4, 1e-8)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    nsteps = int(round(sweep[0]["T"] / sweep[0]["dt"]))
+    tsgp = sum(b["n_matvec"] * nsteps * c["N"] ** 2 for b, c in zip(rb, sweep))
+    return {"tsgp_per_s": tsgp / el, "ms_per_sweep": el * 1e3,
+            "converged": sum(b["status"] == tsk.TSK_OK for b in rb), "instances": len(rb),
+            "workload": "64 Kolmogorov instances (24x128^2, 20x256^2, 20x384^2), FP32, Re~U[5,40], "
+                        "alpha in {0.25,0.5,0.75,1}, m=64, k=4, tol=1e-8, one batched call"}
+
+
 def run_learned(args, tsk, W, np, torch):
-    """Wall time to 6 Ritz pairs at residual 1e-8 on held-out (Re, alpha) at
-    256^2: FP32 with the learned start against FP64 (and FP32) with the seeded
-    random start, one instance per call.  The network is trained first, outside
-    the timed region, on the Ritz vectors of the 64-instance sweep."""
+    """Headline: wall time to 6 Ritz pairs on held-out (Re, alpha) at 256^2, FP32
+    + learned start against the plain FP64 + random start.  One solve = one
+    tsk_arnoldi call from the start vector (the learned one includes the
+    network's forward pass and decode) to the Ritz values and vectors; 16
+    held-out instances, each solved once per step.  The network is trained
+    first, outside the timed region, on Ritz vectors of the 64-instance sweep.
+
+    Forms (all m = 96, k = 6, tol = 1e-8 on the Arnoldi residual estimate):
+      fp64_random          the plain form (FP64 stop rule).
+      fp32_learned         FP32 precision form, learned start; FP32 stop rule
+                           (estimate <= max(1e-8, 1.9e-6 |mu|), duplicate width 2e-5).
+      fp32_random          FP32 precision form, seeded random start.
+      fp64_random_fp32rule FP64 + random start stopped by the FP32 rule: the
+                           plain form at the precision form's accuracy.
+    Accuracy (untimed, once per instance): the true residual ||M x - mu x|| of
+    every returned pair by one FP64 matvec, and |dlambda| of every returned
+    value to the nearest value of an FP64 run with k = 12."""
     floor = 32 * 2.0 ** -24
     t_train0 = time.perf_counter()
     sweep = W.learned_training_sweep()
@@ -545,54 +660,98 @@ def run_learned(args, tsk, W, np, torch):
     del sops, res
 
     hold = W.learned_holdout()
+    N = hold[0]["N"]
     m, k, tol = hold[0]["m"], hold[0]["k"], hold[0]["tol"]
     o64 = [mk(c, tsk.TSK_FP64) for c in hold]
+    o64r = [mk(c, tsk.TSK_FP64) for c in hold]
+    for op in o64r:
+        tsk.set_stop_rule(op, floor, 2e-5)
     o32 = [mk(c, tsk.TSK_FP32) for c in hold]
 
     def p64(i, s):
-        return tsk.arnoldi(o64[i], m, k, tol, seed=s)
+        return tsk.arnoldi(o64[i], m, k, tol, seed=s, want_vectors=True)
+
+    def p64r(i, s):
+        return tsk.arnoldi(o64r[i], m, k, tol, seed=s, want_vectors=True)
 
     def p32r(i, s):
-        return tsk.arnoldi(o32[i], m, k, tol, seed=s)
+        return tsk.arnoldi(o32[i], m, k, tol, seed=s, want_vectors=True)
 
     def p32l(i, s):
         v0, _ = tsk.mlp_start(net, o32[i], hold[i]["Re"], hold[i]["alpha"], 0.1, s)
-        return tsk.arnoldi(o32[i], m, k, tol, v0=v0)
+        return tsk.arnoldi(o32[i], m, k, tol, v0=v0, want_vectors=True)
 
-    forms = {"fp64_random": p64, "fp32_random": p32r, "fp32_learned": p32l}
-    stats = {}
+    forms = {"fp64_random": p64, "fp32_learned": p32l, "fp32_random": p32r, "fp64_random_fp32rule": p64r}
+    rules = {"fp64_random": "estimate <= 1e-8", "fp32_learned": "estimate <= max(1e-8, 1.9e-6|mu|), dup 2e-5",
+             "fp32_random": "estimate <= max(1e-8, 1.9e-6|mu|), dup 2e-5",
+             "fp64_random_fp32rule": "estimate <= max(1e-8, 1.9e-6|mu|), dup 2e-5"}
+    # FP64 reference spectra (k = 12) for |dlambda|
+    refs = [tsk.arnoldi(o64[i], m, 12, tol, seed=7)["lam"] for i in range(len(hold))]
+    stats, last = {}, {}
     for name, fn in forms.items():
         for w in range(args.warmup):
             for i in range(len(hold)):
                 fn(i, 1000 + w * 100 + i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nmv, nok = [], 0
+        nmv, nok, ms_apply = [], 0, 0.0
         for st in range(args.steps):
             for i in range(len(hold)):
                 r = fn(i, st * 100 + i)
                 nmv.append(r["n_matvec"])
                 nok += r["status"] == tsk.TSK_OK
+                ms_apply += r["ms_apply"]
+                last[(name, i)] = r
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        stats[name] = {"ms_per_solve": el * 1e3 / (args.steps * len(hold)), "mean_matvecs": float(np.mean(nmv)),
-                       "converged": nok, "solves": args.steps * len(hold)}
+        nsolve = args.steps * len(hold)
+        stats[name] = {"ms_per_solve": el * 1e3 / nsolve, "mean_matvecs": float(np.mean(nmv)),
+                       "converged": nok, "solves": nsolve, "stop_rule": rules[name],
+                       "matvec_ms_per_solve": ms_apply / nsolve,
+                       "ms_per_matvec": ms_apply / float(np.sum(nmv))}
         print(name, stats[name], file=sys.stderr)
+    for name in forms:
+        tr, dl, est = [], [], []
+        for i in range(len(hold)):
+            r = last[(name, i)]
+            tr += _true_residuals(tsk, torch, o64[i], r)
+            dl.append(_nearest_dist(r["lam"], refs[i]))
+            est += list(r["res"])
+        stats[name].update({"max_true_residual": max(tr), "median_true_residual": float(np.median(tr)),
+                            "max_estimate": float(max(est)), "max_dlambda_vs_fp64": max(dl),
+                            "median_dlambda_vs_fp64": float(np.median(dl))})
     lm = stats["fp32_learned"]["ms_per_solve"]
+    nsteps = int(round(hold[0]["T"] / hold[0]["dt"]))
+    launch_ms = stats["fp32_learned"]["ms_per_matvec"]
+    flops = bloch_flops(N, nsteps)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    traffic = measured_traffic("k_colstep_bloch_kolmo256_fp32_hbm_traffic.md")
+    sweep_stats = run_sweep_tsgp(tsk, W, torch)
+    for name in forms:
+        stats[name]["tsgp_per_s"] = stats[name]["mean_matvecs"] * nsteps * N * N / (stats[name]["ms_per_solve"] / 1e3)
     return {
-        "metric": "wall time to 6 Ritz pairs at residual 1e-8 (held-out 256^2 Kolmogorov instances)",
+        "metric": "wall time to 6 Ritz pairs (Arnoldi estimate <= 1e-8; FP32 form: its precision floor) "
+                  "on held-out 256^2 instances, FP32 + learned start vs plain FP64 + random start",
         "value": lm, "unit": "ms per solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": lm * len(hold), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "16 held-out (Re~U[5,40], alpha in {0.25,0.5,0.75,1}) linearized Kolmogorov "
-                               "flows 256x256, Arnoldi m=96 k=6 tol=1e-8; FP32 + learned start (gamma 0.1) vs "
-                               "FP64 + seeded random start",
+        "config": {"workload": "16 held-out (Re~U[5,40] seed 1000, alpha in {0.25,0.5,0.75,1}) linearized "
+                               "Kolmogorov flows 256x256, IF-RK4 dt=0.005 T=1, Arnoldi m=96 k=6 tol=1e-8, "
+                               "Ritz vectors returned; FP32 + learned start (gamma 0.1) vs FP64 + seeded random "
+                               "start; a step = one solve of each of the 16 instances",
                    "forms": stats,
                    "speedup_vs_fp64_random": stats["fp64_random"]["ms_per_solve"] / lm,
+                   "speedup_vs_fp64_random_at_fp32_rule": stats["fp64_random_fp32rule"]["ms_per_solve"] / lm,
+                   "time_steps_x_gridpoints_per_s": stats["fp32_learned"]["tsgp_per_s"],
+                   "sweep": sweep_stats,
                    "training": {"instances": len(sweep), "adam_steps": 3000, "lr": 1e-3,
                                 "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                                 "sweep_and_train_s": t_train}},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": {"bound": "alu", "kernel": f"k_colstep_bloch<float,{N // 4}>", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": traffic},
+        "cpu_baseline": None if args.no_cpu_baseline else
+        cpu_baseline_learned(N, stats["fp64_random"]["mean_matvecs"]),
     }
 
 
@@ -602,6 +761,81 @@ def cn_pcr_flops(n, levels):
     term (8), per reduction level two complex multiply-adds (16) and the final
     scaling (6)."""
     return n * (22 + 8 + 16 * levels + 6)
+
+
+def cpu_baseline_cgle(c, seconds=10.0):
+    """The CPU oracle's Crank-Nicolson matvecs (banded solve per step, single
+    thread) of the same Ginzburg-Landau operator, as many as fit in `seconds`."""
+    import workloads as W
+    from oracle.cgle import CGLE
+    op = CGLE(n=c["n"], half_width=c["half_width"], U=c["U"], c_u=c["c_u"], c_d=c["c_d"], mu0=c["mu0"],
+              mu2=c["mu2"], dt=c["dt"], T=c["T"])
+    u = W.cgle_start(c["n"], 0)
+    t0 = time.perf_counter()
+    count = 0
+    while True:
+        u = op.apply(u)
+        u /= np.linalg.norm(u)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    nsteps = int(round(c["T"] / c["dt"]))
+    model, ncpu = cpu_model()
+    return {"value": count * nsteps * c["n"] / el, "unit": "time-steps*gridpoints/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_logical_cores": ncpu,
+            "sample": f"{count} oracle matvecs ({nsteps} Crank-Nicolson steps each) of the n={c['n']} operator, "
+                      f"{el:.1f} s, NumPy/SciPy single thread"}
+
+
+def run_cgle(args, tsk, W, np, torch):
+    """Ginzburg-Landau (Sec. 2.3.2 operator; n = 256 finite-difference nodes on
+    [-50, 50], Crank-Nicolson dt = 0.01, T = 1): Arnoldi m = 64, k = 6, tol =
+    1e-8 from the seeded complex N(0,1) start.  A step is one whole run."""
+    c = W.CGLE
+    n, m, k, tol = c["n"], c["m"], c["k"], c["tol"]
+    nsteps = int(round(c["T"] / c["dt"]))
+    op = tsk.create_cgle1d(n, c["half_width"])
+    tsk.set_params_cgle(op, c["U"], c["c_u"], c["c_d"], c["mu0"], c["mu2"], c["dt"], c["T"])
+    v0 = torch.from_numpy(W.cgle_start(n, 0)).cuda()
+
+    def step():
+        return tsk.arnoldi(op, m, k, tol, v0=v0, want_vectors=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    r = results[-1]
+    nmv = r["n_matvec"]
+    ms_apply = sum(q["ms_apply"] for q in results) / args.steps
+    launch_ms = ms_apply / nmv
+    levels = int(math.ceil(math.log2(n)))
+    flops = nsteps * cn_pcr_flops(n, levels)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    tsgp = nmv * nsteps * n
+    return {
+        "metric": "time-steps*gridpoints/s (whole Arnoldi run to 6 Ritz pairs at residual 1e-8)",
+        "value": tsgp / (ms / 1e3), "unit": "time-steps*gridpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"linear complex Ginzburg-Landau n={n} finite-difference nodes on [-50,50], U=2, "
+                               f"c_u=0.2, c_d=-1, mu0=0.41, mu2=-0.01, Crank-Nicolson dt={c['dt']} T={c['T']}, "
+                               f"Arnoldi m={m} k={k} tol={tol}, seeded complex N(0,1) start",
+                   "n_matvec": nmv, "status": r["status"], "us_per_cn_step": launch_ms * 1e3 / nsteps,
+                   "time_stepper_tsgp_per_s": tsgp / (ms_apply / 1e3),
+                   "lambda": [[round(float(v.real), 10), round(float(v.imag), 10)] for v in r["lam"]],
+                   "max_residual": float(np.max(r["res"]))},
+        "roofline": {"bound": "alu", "kernel": f"k_cgle_cn<{levels}> (one workgroup, latency-bound)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
+                     "flops_per_launch": flops, "traffic": None},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_cgle(c),
+    }
 
 
 def cpu_baseline_resolvent(n, half_width, mu0, dt, t_trans, omega, seconds=10.0):
@@ -702,9 +936,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kolmo128",
-                    choices=["kolmo128", "kolmo512-fp32", "sweep", "learned", "general", "krylov-schur", "optimal",
-                             "fixed-point", "resolvent", "copy"])
+    ap.add_argument("--workload", default="learned",
+                    choices=["learned", "kolmo128", "kolmo512-fp32", "sweep", "cgle", "general", "krylov-schur",
+                             "optimal", "fixed-point", "resolvent", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -748,6 +982,8 @@ def main():
         out = run_learned(args, tsk, W, np, torch)
     elif args.workload == "general":
         out = run_general(args, tsk, W, np, torch)
+    elif args.workload == "cgle":
+        out = run_cgle(args, tsk, W, np, torch)
     elif args.workload == "krylov-schur":
         out = run_krylov_schur(args, tsk, W, np, torch)
     elif args.workload == "optimal":

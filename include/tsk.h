@@ -131,6 +131,21 @@ tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
 tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave);
 tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave);
 
+/* Stop rule of the Arnoldi stop test (Sec. 3.2.2, eq. "Krylov convergence":
+ * a Ritz pair is converged when |beta e_m^T y| <= tol), per operator, for
+ * tsk_arnoldi, tsk_batch_arnoldi and tsk_krylov_schur:
+ *   res_floor_rel: a pair also counts as converged once its estimate is below
+ *                  res_floor_rel |mu| (converged: res <= max(tol, res_floor_rel |mu|)).
+ *   dup_rel:       Ritz values closer than dup_rel |mu| to an accepted value are
+ *                  copies of one eigenvalue (the duplicate width of the wanted set).
+ * A negative value restores the default of the state type: FP64 states 0 and 0
+ * (the plain rule); FP32 states 32 u32 = 1.9e-6 and 2e-5, because the FP32
+ * basis holds the Arnoldi relation only to about u32 ||M|| and FP32 rounding
+ * splits multiple eigenvalues into clusters.  res_floor_rel = 0 makes an FP32
+ * run stop on the same estimate <= tol as an FP64 run.  Values must be finite
+ * and below 1e-2 (TSK_EINVAL otherwise). */
+tsk_status tsk_set_stop_rule(tsk_op op, double res_floor_rel, double dup_rel);
+
 /* ---------------------------------------------------------------------------
  * Common to all operators.
  * ------------------------------------------------------------------------- */

@@ -147,6 +147,19 @@ tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave) {
     })
 }
 
+tsk_status tsk_set_stop_rule(tsk_op op, double res_floor_rel, double dup_rel) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!std::isfinite(res_floor_rel) || !std::isfinite(dup_rel))
+            return fail(TSK_EINVAL, "stop-rule parameters must be finite");
+        if (res_floor_rel >= 1e-2 || dup_rel >= 1e-2)
+            return fail(TSK_EINVAL, "stop-rule parameters must be below 1e-2");
+        op->op->stop_res_floor = res_floor_rel < 0.0 ? -1.0 : res_floor_rel;
+        op->op->stop_dup_rel = dup_rel < 0.0 ? -1.0 : dup_rel;
+        return TSK_OK;
+    })
+}
+
 tsk_status tsk_state_dim(tsk_op op, int64_t* n_scalars, int* is_complex, int* elem_bytes) {
     TSK_GUARD({
         TSK_NEED(op);

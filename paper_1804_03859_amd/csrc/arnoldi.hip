@@ -164,8 +164,9 @@ tsk_status make_desc(Operator* op, int m, int k, int NS, void* ritz, KryDesc& d)
     d.ldh = m + 1;
     d.nblk = nblk;
     d.active = 1;
-    d.dup_rel = op->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
-    d.res_floor = op->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
+    d.dup_rel = op->stop_dup_rel >= 0.0 ? op->stop_dup_rel : op->kind == StateKind::Real32 ? kDupRelFp32 : 0.0;
+    d.res_floor = op->stop_res_floor >= 0.0 ? op->stop_res_floor
+                                            : op->kind == StateKind::Real32 ? kResFloorFp32 : 0.0;
     d.T = op->T;
     W.Vcur = W.V.ptr;
     return TSK_OK;

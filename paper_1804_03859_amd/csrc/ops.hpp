@@ -101,6 +101,10 @@ struct Operator {
     double T = 0.0;
     bool params_set = false;
     bool base_set = false;
+    // Stop-rule parameters of the wanted-set test (negative: the defaults of the
+    // state type, kResFloorFp32 / kDupRelFp32 for FP32 states, 0 for FP64).
+    double stop_res_floor = -1.0;
+    double stop_dup_rel = -1.0;
     ArnoldiWork aw;
 
     bool is_complex() const { return kind == StateKind::Complex64x2; }

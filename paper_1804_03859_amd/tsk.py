@@ -67,6 +67,7 @@ def load():
         "tsk_state_dim": [vp, P(i64), P(i32), P(i32)],
         "tsk_set_tuning": [vp, i32],
         "tsk_get_tuning": [vp, P(i32)],
+        "tsk_set_stop_rule": [vp, f64, f64],
         "tsk_from_physical": [vp, vp, vp],
         "tsk_to_physical": [vp, vp, vp],
         "tsk_apply": [vp, vp, vp],
@@ -123,7 +124,7 @@ def exported_symbols():
     """Names the binding expects the library to export (all of include/tsk.h)."""
     return ["tsk_create_cgle1d", "tsk_set_params_cgle", "tsk_create_kolmo2d", "tsk_set_params_kolmo",
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
-            "tsk_get_tuning", "tsk_state_dim",
+            "tsk_get_tuning", "tsk_set_stop_rule", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
             "tsk_set_resolvent", "tsk_batch_optimal_perturbation",
@@ -243,6 +244,12 @@ def get_tuning(op):
     c = C.c_int()
     _check(load().tsk_get_tuning(op.h, C.byref(c)))
     return c.value
+
+
+def set_stop_rule(op, res_floor_rel=-1.0, dup_rel=-1.0):
+    """Per-operator stop rule (tsk_set_stop_rule); negative values restore the
+    defaults of the state type."""
+    _check(load().tsk_set_stop_rule(op.h, float(res_floor_rel), float(dup_rel)))
 
 
 def _phys_spec(op):

@@ -40,6 +40,29 @@ def kolmo128():
     return d
 
 
+def kolmo128_m53():
+    """The 128^2 FP64 operator at a fixed order: m = 53 Arnoldi steps (the
+    order at which six distinct pairs first reach 1e-8), tol = 0 so every
+    step runs, k = 12 wanted values, with every Ritz value of H_53."""
+    c = W.KOLMO_128_FP64
+    op = Kolmogorov.kolmogorov(c["N"], c["alpha"], c["Re"], c["dt"], c["T"], c["n_forcing"])
+    N = c["N"]
+    v0 = op.project(W.kolmo_start_physical(N, 0)).ravel()
+    r = arnoldi(lambda v: op.apply(v.reshape(N, N)).ravel(), v0, 53, 12, 0.0, T=c["T"], keep_basis=False)
+    d = _pack(r)
+    H = r["H"][:53, :53].real
+    ev, vr = np.linalg.eig(H)
+    beta = abs(r["H"][53, 52])
+    res = beta * np.abs(vr[-1, :]) / np.linalg.norm(vr, axis=0)
+    lam = np.log(ev.astype(complex)) / c["T"]
+    d["all_lam_re"] = [float(x.real) for x in lam]
+    d["all_lam_im"] = [float(x.imag) for x in lam]
+    d["all_res"] = [float(x) for x in res]
+    d["workload"] = ("kolmogorov N=128 fp64, m=53 k=12 tol=0, start = projected N(0,1) field "
+                     "workloads.kolmo_start_physical(128, 0)")
+    return d
+
+
 def cgle256():
     c = W.CGLE
     op = CGLE(n=c["n"], half_width=c["half_width"], U=c["U"], c_u=c["c_u"], c_d=c["c_d"], mu0=c["mu0"],
@@ -50,8 +73,14 @@ def cgle256():
     return d
 
 
+JOBS = (("oracle_cgle256.json", cgle256), ("oracle_kolmo128_fp64.json", kolmo128),
+        ("oracle_kolmo128_fp64_m53.json", kolmo128_m53))
+
 if __name__ == "__main__":
-    for name, fn in (("oracle_cgle256.json", cgle256), ("oracle_kolmo128_fp64.json", kolmo128)):
+    only = sys.argv[1:]
+    for name, fn in JOBS:
+        if only and name not in only:
+            continue
         d = fn()
         with open(os.path.join(OUT, name), "w") as f:
             json.dump(d, f, indent=1)

@@ -461,6 +461,21 @@ void tsk_mlp_destroy(tsk_mlp net);
  * TSK_ENONFINITE if H or beta holds a NaN or Inf. */
 tsk_status tsk_hessenberg_ritz_real(const double* H_dev, int ldh, int p, double beta, void* mu_dev,
                                     void* res_dev, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solver and outputs as tsk_hessenberg_ritz_real, with its scratch (a complex
+ * copy of H, the eigenvector workspace, the result record, device scalars, the
+ * solver's descriptor) in a fixed device array of 297 KB that the library keeps
+ * on every GPU it runs on until the process ends, instead of allocations per
+ * call.  The caller still passes H and the outputs.  Limits of that array:
+ * 1 <= p <= 96 and p <= ldh <= 97 (TSK_EINVAL beyond them).  The call makes no
+ * device allocation or free.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two host threads, or two streams) race, and
+ * each call rewrites what it needs before the solve.  Synchronous on
+ * hip_stream; same status codes as tsk_hessenberg_ritz_real. */
+tsk_status tsk_hessenberg_ritz_real_noalloc(const double* H_dev, int ldh, int p, double beta, void* mu_dev,
+                                            void* res_dev, void* hip_stream);
 /* iid N(0,1) draws (device, FP64): count values of the splitmix64 +
  * Box-Muller stream of `seed` (element e uses outputs 2*(e/2), 2*(e/2)+1). */
 tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream);

@@ -460,6 +460,14 @@ tsk_status tsk_hessenberg_ritz_real(const double* H_dev, int ldh, int p, double 
     })
 }
 
+tsk_status tsk_hessenberg_ritz_real_noalloc(const double* H_dev, int ldh, int p, double beta, void* mu_dev,
+                                            void* res_dev, void* hip_stream) {
+    TSK_GUARD({
+        return hessenberg_ritz_real_noalloc(H_dev, ldh, p, beta, mu_dev, res_dev,
+                                            static_cast<hipStream_t>(hip_stream));
+    })
+}
+
 tsk_status tsk_normal_fill(double* out_dev, int64_t count, uint64_t seed, void* hip_stream) {
     TSK_GUARD({
         if (!out_dev || count < 0) return fail(TSK_EINVAL, "bad output buffer or count");

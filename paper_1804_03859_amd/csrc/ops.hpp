@@ -281,6 +281,12 @@ tsk_status mlp_train(Mlp* n, const float* in, const float* target, int B, int st
 tsk_status ritz_block_target(Operator* op, const void* ritz, int k, const int* use, float* target);
 tsk_status mlp_start(Mlp* n, Operator* op, double Re, double alpha, double gamma, uint64_t seed, void* v0,
                      int* used);
+// The standalone real Hessenberg eigensolver with its scratch in a fixed
+// device array instead of per-call allocations (noalloc.hip); arguments as
+// tsk_hessenberg_ritz_real_noalloc.
+tsk_status hessenberg_ritz_real_noalloc(const double* H_dev, int ldh, int p, double beta, void* mu_dev,
+                                        void* res_dev, hipStream_t s);
+
 // Normal draws (rng.hip).
 tsk_status normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t s);
 // out[i] = float(in[i]); out may alias the front of in.

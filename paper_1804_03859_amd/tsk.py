@@ -92,6 +92,7 @@ def load():
         "tsk_last_basis": [vp, P(vp), P(i64)],
         "tsk_hessenberg_ritz": [vp, i32, i32, f64, vp, vp, vp, vp],
         "tsk_hessenberg_ritz_real": [vp, i32, i32, f64, vp, vp, vp],
+        "tsk_hessenberg_ritz_real_noalloc": [vp, i32, i32, f64, vp, vp, vp],
         "tsk_normal_fill": [vp, i64, u64, vp],
         "tsk_mlp_create": [P(vp), i32, P(f64), P(f64), vp],
         "tsk_mlp_param_count": [vp, P(i64)],
@@ -131,7 +132,8 @@ def exported_symbols():
             "tsk_set_nonlinear", "tsk_laminar_state", "tsk_nonlinear_step", "tsk_set_base_from_state", "tsk_sfd",
             "tsk_rpm", "tsk_boostconv",
             "tsk_last_hessenberg",
-            "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
+            "tsk_last_basis", "tsk_hessenberg_ritz", "tsk_hessenberg_ritz_real",
+            "tsk_hessenberg_ritz_real_noalloc", "tsk_normal_fill", "tsk_destroy", "tsk_status_str",
             "tsk_last_error", "tsk_mlp_create", "tsk_mlp_param_count", "tsk_mlp_init", "tsk_mlp_set_params",
             "tsk_mlp_get_params", "tsk_mlp_forward", "tsk_mlp_gradients", "tsk_mlp_train",
             "tsk_ritz_block_target", "tsk_mlp_start", "tsk_mlp_destroy"]
@@ -567,6 +569,18 @@ def hessenberg_ritz_real(H, beta, stream=None):
     res = torch.zeros(p, dtype=torch.float64, device=H.device)
     _check(load().tsk_hessenberg_ritz_real(_ptr(Hc), p, p, beta, _ptr(mu), _ptr(res), _stream(stream)))
     return mu, res
+
+
+def hessenberg_ritz_real_noalloc(H_colmajor, ldh, p, beta, mu, res, stream=None):
+    """tsk_hessenberg_ritz_real_noalloc on caller buffers: H_colmajor holds
+    ldh * p doubles (column-major, leading dimension ldh), mu p complex128,
+    res p doubles, all on the device.  Allocates nothing."""
+    p, ldh = int(p), int(ldh)
+    _need(H_colmajor, ldh * p, torch.float64, "H")
+    _need(mu, p, torch.complex128, "mu")
+    _need(res, p, torch.float64, "res")
+    _check(load().tsk_hessenberg_ritz_real_noalloc(_ptr(H_colmajor), ldh, p, float(beta), _ptr(mu), _ptr(res),
+                                                    _stream(stream)))
 
 
 def normal_fill(count, seed, stream=None):

@@ -61,6 +61,29 @@ def bloch_flops(N, nsteps, sectors=4):
     return M * 4 * nsteps * per_stage
 
 
+def couple_flops(N, nsteps, nh=4):
+    """Algorithmic flops of one matvec of the spectral-coupling stepper: per kept
+    mode of the columns kx >= 1 (complex) and IF-RK4 step, four stages of the
+    coupling factor (2) and the neighbour difference (2), the Lawson updates
+    (4 + 4 + 4 + 2 complex fused multiply-adds = 28) and the two scaled copies
+    of the step's input (4): 48; the kx = 0 column decays (2 per mode and step)."""
+    M = (N - 1) // 3
+    return nsteps * (48 * M * (2 * M + 1) + 2 * M)
+
+
+def stepper_flops(tsk, op, N, nsteps):
+    """Flop model and kernel name of the stepper the operator's matvec runs."""
+    t = tsk.get_tuning(op)
+    rt = "double" if op.elem_bytes == 8 else "float"
+    if t == -2:
+        M = (N - 1) // 3
+        return couple_flops(N, nsteps), f"k_colstep_couple<{rt},{1 if (2 * M + 1 + 3) // 4 <= 64 else 2}>"
+    if t == -1:
+        return bloch_flops(N, nsteps), (f"k_colstep_bloch_split<{rt}>" if N == 128 else
+                                        f"k_colstep_bloch<{rt},{N // 4}>")
+    return colstep_flops(N, nsteps), f"k_colstep<{rt},{N},true>"
+
+
 def cpu_baseline(seconds=12.0):
     """The CPU oracle (NumPy FP64, single thread) on a bounded sample of the same
     workload: as many full matvecs (200 IF-RK4 steps each) of the 128^2 operator
@@ -90,7 +113,7 @@ def cpu_baseline(seconds=12.0):
                       f"{el:.1f} s, NumPy/pocketfft single thread"}
 
 
-COLSTEP_SOURCES = ("common.hpp", "fft.hpp", "colfft.hpp", "colxl.hpp", "colstep.hpp", "colbloch.hpp")
+COLSTEP_SOURCES = ("common.hpp", "colstep.hpp", "colcouple.hpp")
 GENERAL_SOURCES = ("common.hpp", "fft.hpp", "kolmo2d.hip")
 
 
@@ -113,10 +136,6 @@ def measured_traffic(profile_name, sources=COLSTEP_SOURCES, key="traffic_bytes_p
     if rec.get("source_hash") != h.hexdigest()[:16] or key not in rec:
         return None
     return float(rec[key])
-
-
-def _flops_for(N, nsteps, bloch):
-    return bloch_flops(N, nsteps) if bloch else colstep_flops(N, nsteps)
 
 
 def run_sweep(args, tsk, W, np, torch):
@@ -152,9 +171,8 @@ def run_sweep(args, tsk, W, np, torch):
     # ms_apply sums the HIP-event durations of those launches
     steps_run = max(b["n_matvec"] for b in rb)
     ms_apply = rb[0]["ms_apply"]
-    # 128^2 and 256^2 instances run the Bloch-sector stepper, 384^2 the column stepper
-    bloch = [tsk.get_tuning(op) == -1 for op in ops]
-    flops_total = sum(b["n_matvec"] * _flops_for(c["N"], nsteps, bl) for b, c, bl in zip(rb, sweep, bloch))
+    # every instance of this base runs the spectral-coupling stepper, all grid sizes in one launch
+    flops_total = sum(b["n_matvec"] * stepper_flops(tsk, op, c["N"], nsteps)[0] for b, c, op in zip(rb, sweep, ops))
     launch_ms = ms_apply / steps_run
     flops_step = flops_total / steps_run
     achieved = flops_total / (ms_apply / 1e3) / 1e12
@@ -167,9 +185,7 @@ def run_sweep(args, tsk, W, np, torch):
                                "alpha in {0.25,0.5,0.75,1}, m=64, k=4, tol=1e-8",
                    "n_matvec": [b["n_matvec"] for b in rb], "status": [b["status"] for b in rb],
                    "batched_matvec_ms": launch_ms},
-        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch_split<float> + k_colstep_bloch<float,64> + "
-                                               "k_colstep<float,384,true> "
-                                               "(one batched matvec)",
+        "roofline": {"bound": "alu", "kernel": "k_colstep_couple<float,1> (one batched matvec of all 64 instances)",
                      "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms,
                      "flops_per_launch": flops_step, "traffic": None},
@@ -204,17 +220,10 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     tsgp_step = nmv * nsteps * N * N
     ms_apply = sum(q["ms_apply"] for q in results) / args.steps
     launch_ms = ms_apply / nmv
-    rt = "double" if prec == tsk.TSK_FP64 else "float"
-    stepper = tsk.get_tuning(op)  # -1: the Bloch-sector stepper, else columns per wavefront
-    if stepper == -1:
-        flops = bloch_flops(N, nsteps)
-        kernel = f"k_colstep_bloch_split<{rt}>" if N == 128 else f"k_colstep_bloch<{rt},{N // 4}>"
-        traffic = (measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md")
-                   if prec == tsk.TSK_FP64 and N == 128 else None)
-    else:
-        flops = colstep_flops(N, nsteps)
-        kernel = f"k_colstep<{rt},{N},true>"
-        traffic = None
+    stepper = tsk.get_tuning(op)  # -2 spectral coupling, -1 Bloch sectors, else columns per wavefront
+    flops, kernel = stepper_flops(tsk, op, N, nsteps)
+    traffic = (measured_traffic("k_colstep_couple_kolmo128_fp64_hbm_traffic.md")
+               if prec == tsk.TSK_FP64 and N == 128 and stepper == -2 else None)
     achieved = flops / (launch_ms / 1e3) / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if prec == tsk.TSK_FP64 else FP32_VECTOR_PEAK_TFLOPS
     return {
@@ -232,8 +241,9 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
         "data": "synthetic",
         "config": {"workload": f"linearized Kolmogorov flow {N}x{N} {dtype_name.upper()}, Re=20, alpha=0.5, "
                                f"IF-RK4 dt=0.005 T=1, Arnoldi m={m} k={k} tol=1e-8, seeded N(0,1) start",
-                   "n_matvec": nmv, "status": r["status"], "stepper": "bloch sectors" if stepper == -1 else
-                   f"{stepper} column(s) per wavefront",
+                   "n_matvec": nmv, "status": r["status"],
+                   "stepper": {-2: "spectral coupling", -1: "bloch sectors"}.get(stepper,
+                                                                                 f"{stepper} column(s) per wavefront"),
                    "wall_time_to_6_pairs_s": ms_per_step / 1e3,
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3),
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],
@@ -280,8 +290,7 @@ def run_krylov_schur(args, tsk, W, np, torch):
     tsgp_step = nmv * nsteps * N * N
     ms_apply = sum(q["ms_apply"] for q in results) / args.steps
     launch_ms = ms_apply / nmv
-    bloch = tsk.get_tuning(op) == -1
-    flops = bloch_flops(N, nsteps) if bloch else colstep_flops(N, nsteps)
+    flops, kname = stepper_flops(tsk, op, N, nsteps)
     achieved = flops / (launch_ms / 1e3) / 1e12
     table = {}
     for m in (16, 24, 48):
@@ -305,10 +314,10 @@ def run_krylov_schur(args, tsk, W, np, torch):
                    "non_matvec_ms": ms_per_step - ms_apply,
                    "lambda": [round(float(v.real), 10) for v in r["lam"]],
                    "max_residual": float(np.max(r["res"])), "subspace_table": table},
-        "roofline": {"bound": "alu", "kernel": "k_colstep_bloch_split<double>" if bloch else f"k_colstep<double,{N},true>",
+        "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,
-                     "traffic": measured_traffic("k_colstep_bloch_kolmo128_fp64_hbm_traffic.md") if bloch else None},
+                     "traffic": None},
         "cpu_baseline": None,
     }
 
@@ -353,8 +362,8 @@ def run_optimal(args, tsk, W, np, torch):
     launch_ms = ms_apply / nint
     # forward integrations by the operator's stepper (the Bloch sectors at 128^2), adjoint ones by the
     # transposed column stepper (128-point transforms): flops averaged over the two kinds
-    bloch = tsk.get_tuning(op) == -1
-    flops = 0.5 * (bloch_flops(N, nsteps) + colstep_flops(N, nsteps)) if bloch else colstep_flops(N, nsteps)
+    fwd_flops, fwd_kernel = stepper_flops(tsk, op, N, nsteps)
+    flops = 0.5 * (fwd_flops + colstep_flops(N, nsteps))
     achieved = flops / (launch_ms / 1e3) / 1e12
     gains = {}
     for T in (0.25, 0.5, 2.0, 4.0):
@@ -375,8 +384,7 @@ def run_optimal(args, tsk, W, np, torch):
                    "sigma": [float(v) for v in r["sigma"]], "gain": [float(v) for v in r["gain"]],
                    "max_residual": float(np.max(r["res"])),
                    "time_stepper_tsgp_per_s": tsgp_step / (ms_apply / 1e3), "gain_curve": gains},
-        "roofline": {"bound": "alu", "kernel": ("k_colstep_bloch_split<double>" if bloch else f"k_colstep<double,{N},true>")
-                     + f" + k_colstep_adj<double,{N},true>",
+        "roofline": {"bound": "alu", "kernel": fwd_kernel + f" + k_colstep_adj<double,{N},true>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "launch_ms": launch_ms, "flops_per_launch": flops,
                      "traffic": None},
@@ -723,9 +731,9 @@ def run_learned(args, tsk, W, np, torch):
     lm = stats["fp32_learned"]["ms_per_solve"]
     nsteps = int(round(hold[0]["T"] / hold[0]["dt"]))
     launch_ms = stats["fp32_learned"]["ms_per_matvec"]
-    flops = bloch_flops(N, nsteps)
+    flops, kname = stepper_flops(tsk, o32[0], N, nsteps)
     achieved = flops / (launch_ms / 1e3) / 1e12
-    traffic = measured_traffic("k_colstep_bloch_kolmo256_fp32_hbm_traffic.md")
+    traffic = measured_traffic("k_colstep_couple_kolmo256_fp32_hbm_traffic.md")
     sweep_stats = run_sweep_tsgp(tsk, W, torch)
     for name in forms:
         stats[name]["tsgp_per_s"] = stats[name]["mean_matvecs"] * nsteps * N * N / (stats[name]["ms_per_solve"] / 1e3)
@@ -747,7 +755,7 @@ def run_learned(args, tsk, W, np, torch):
                    "training": {"instances": len(sweep), "adam_steps": 3000, "lr": 1e-3,
                                 "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                                 "sweep_and_train_s": t_train}},
-        "roofline": {"bound": "alu", "kernel": f"k_colstep_bloch<float,{N // 4}>", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "launch_ms": launch_ms, "flops_per_launch": flops, "traffic": traffic},
         "cpu_baseline": None if args.no_cpu_baseline else

@@ -117,17 +117,24 @@ tsk_status tsk_set_base_kolmogorov(tsk_op op, int n_forcing);
 tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
                              const double* dOmega_dx, const double* dOmega_dy);
 
-/* Tuning of the parallel-base time stepper: kx columns per 64-lane wavefront,
- * 1 or 2 (2 only for N <= 256; larger N always use 1).  0 (the default) lets
- * the library time both on the first matvec of a given size, precision, base
- * kind and launch size and keep the faster for the process.  Both variants
- * compute every column with the same arithmetic, so results do not depend on
- * the choice.  In the default mode an N x N operator, N = 128, 256 or 512,
- * whose base profile has period 2 pi / 4 and a single harmonic (the Kolmogorov
- * flow sin 4y) uses the Bloch-sector stepper instead (each column split into
- * the four sectors ky = 4m + r, exact N/4-point products): the same operator
- * to rounding, not the same bits.  tsk_get_tuning reports the forced or tuned value (0 = not tuned
- * yet, -1 = the Bloch-sector stepper).  Navier-Stokes operators only. */
+/* Choice of the parallel-base time stepper.  0 (the default) lets the library
+ * choose: for a base profile of one harmonic, U = amp sin(n (y - y0)) with
+ * dOmega/dy = c U (the Kolmogorov flow sin 4y), the spectral-coupling stepper:
+ * the product with one harmonic couples ky only to ky +- n, so each kx column
+ * splits into n chains advanced by one wavefront each with a three-point
+ * coupling and no transforms; with the 2/3 rule nothing of the pseudo-spectral
+ * product wraps onto a kept mode (n < N - 2M), so it is the same operator to
+ * rounding.  Otherwise the column stepper, whose kx columns per 64-lane
+ * wavefront (1 or 2, 2 only for N <= 256) the library times on the first matvec
+ * of a given size, precision, base kind and launch size and keeps for the
+ * process.  1 or 2 force that column variant (both compute every column with
+ * the same arithmetic, so results do not depend on the choice); 3 forces the
+ * Bloch-sector stepper where it applies (N = 128, 256 or 512 and a profile of
+ * period 2 pi / 4 with a single harmonic: each column split into the four
+ * sectors ky = 4m + r, exact N/4-point products), else the column stepper.
+ * tsk_get_tuning reports -2 for the spectral-coupling stepper, -1 for the
+ * Bloch-sector stepper, else the forced or tuned columns per wavefront (0 = not
+ * tuned yet).  Navier-Stokes operators only; TSK_EINVAL for values outside 0..3. */
 tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave);
 tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave);
 

@@ -322,7 +322,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     bool all_kolmo = true;
     for (int i = 0; i < count; ++i) all_kolmo = all_kolmo && kolmo_parallel(ops[i]);
     // a single instance with the Bloch-sector stepper calls its own matvec
-    const bool own = count == 1 && kolmo_bloch(ops[0]);
+    const bool own = count == 1 && (kolmo_bloch(ops[0]) || kolmo_couple(ops[0]));
     if (all_kolmo && !svd && !own) TSK_TRY(kolmo_batch_plan(ops, count, Dh.data(), D, &kb));
     CgleBatchPtr cb;
     if (count > 1 && is_cgle(ops[0])) TSK_TRY(cgle_batch_plan(ops, count, Dh.data(), svd, &cb));

@@ -40,6 +40,11 @@ template <typename real> struct ColInst {
     double alpha, Re, dt, cprop;
     int nsteps;
     const int* active;
+    // one-harmonic base U = amp sin(nh (y - y0)) (the spectral-coupling stepper of
+    // colcouple.hpp): the instance's own cutoff M, the harmonic and its amplitude
+    // and phase; unused by the other steppers
+    int M, nh;
+    double amp, y0;
 };
 struct ColTask {
     int inst;  // index into the instance table

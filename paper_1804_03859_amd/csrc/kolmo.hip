@@ -35,6 +35,7 @@
 #include <tuple>
 
 #include "colbloch.hpp"
+#include "colcouple.hpp"
 #include "colstep.hpp"
 #include "kolmo2d.hpp"
 #include "krylov.hpp"
@@ -361,6 +362,22 @@ void launch_bloch_stepper(int N, const ColInst<real>& one, const ColInst<real>* 
                            insts, ids, jstep, tw);
 }
 
+// Spectral-coupling stepper launch (colcouple.hpp): `n` instances (grid y),
+// insts[ids[.]] of a batch at Arnoldi step jstep, or `one` (insts null, n = 1);
+// blocks = couple_blocks of the largest instance, S positions per lane.
+template <typename real>
+void launch_couple_stepper(const ColInst<real>& one, const ColInst<real>* insts, const int* ids, int n, int jstep,
+                           int blocks, int S, hipStream_t s) {
+    if (S == 1)
+        hipLaunchKernelGGL((k_colstep_couple<real, 1>), dim3(blocks, n), dim3(kWave), 0, s, one, insts, ids, jstep);
+    else
+        hipLaunchKernelGGL((k_colstep_couple<real, 2>), dim3(blocks, n), dim3(kWave), 0, s, one, insts, ids, jstep);
+}
+
+// Positions per lane of the coupling stepper for cutoff M and harmonic nh: the
+// longest chain has ceil((2M + 1) / nh) modes.
+inline int couple_slots(int M, int nh) { return ((2 * M + 1 + nh - 1) / nh + kWave - 1) / kWave; }
+
 struct KolmoOp final : Operator {
     int N = 0, M = 0;
     tsk_precision prec = TSK_FP64;
@@ -369,10 +386,14 @@ struct KolmoOp final : Operator {
     bool prop = false;
     double cprop = 0.0;
     bool bloch = false;  // N = 128, 256, 512 and a quarter-period one-harmonic profile: Bloch-sector stepper
+    // one-harmonic profile U = amp sin(nh (y - y0)): spectral-coupling stepper (colcouple.hpp)
+    bool couple = false;
+    int nh = 0;
+    double amp = 0.0, y0 = 0.0;
     DevBuf tw, negU, dOdy, Z;
     DevBuf tasks[3];   // single-instance task lists for 1 and 2 columns per wavefront
     int ntasks[3] = {0, 0, 0};
-    int force_cols = 0;  // 0: autotuned
+    int force_cols = 0;  // 0: automatic choice; 1, 2: column stepper; 3: Bloch-sector stepper
     Gen2D* gen = nullptr;  // general two-dimensional base flow (kolmo2d.hip), else parallel
     // nonlinear forced equation (fixed-point solvers): pipeline workspace, packed
     // forcing and laminar state, drift, and the inputs the forcing is made from
@@ -440,8 +461,14 @@ struct KolmoOp final : Operator {
         c.cprop = cprop;
         c.nsteps = nsteps;
         c.active = act;
+        c.M = M;
+        c.nh = nh;
+        c.amp = amp;
+        c.y0 = y0;
         return c;
     }
+    bool use_couple() const { return !gen && couple && force_cols == 0; }
+    bool use_bloch() const { return !gen && bloch && (force_cols == 3 || (force_cols == 0 && !couple)); }
 
     template <typename real> void launch_bloch(const void* x, void* y) const {
         launch_bloch_stepper<real>(N, inst<real>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, tw.as<cplx<real>>(),
@@ -451,7 +478,17 @@ struct KolmoOp final : Operator {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply: input and output must not alias");
         if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
-        if (bloch && force_cols == 0) {
+        if (use_couple()) {
+            const int S = couple_slots(M, nh), blocks = couple_blocks(M, nh);
+            if (prec == TSK_FP32)
+                launch_couple_stepper<float>(inst<float>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S, stream);
+            else
+                launch_couple_stepper<double>(inst<double>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S,
+                                              stream);
+            TSK_HIP(hipGetLastError());
+            return TSK_OK;
+        }
+        if (use_bloch()) {
             if (prec == TSK_FP32)
                 launch_bloch<float>(x, y);
             else
@@ -689,6 +726,41 @@ tsk_status kolmo_set_base_parallel(Operator* op, const double* U, const double* 
         }
         k->bloch = ok;
     }
+    // one harmonic (colcouple.hpp): U = amp sin(nh (y - y0)), zero mean, no other
+    // harmonic on the N-point grid (to 1e-12 of the amplitude); exact when no term
+    // of the product wraps onto a kept mode (nh < N - 2M) and every chain fits two
+    // positions per lane
+    k->couple = false;
+    if (k->prop) {
+        const double pi = 3.14159265358979323846264338327950288;
+        double umax = 0.0;
+        for (int i = 0; i < N; ++i) umax = std::max(umax, std::fabs(U[i]));
+        int hsel = 0, nbig = 0;
+        double hr = 0.0, hi = 0.0, amax = 0.0;
+        std::vector<double> mag(N / 2 + 1);
+        for (int h = 0; h <= N / 2; ++h) {
+            double cr = 0.0, ci = 0.0;
+            for (int l = 0; l < N; ++l) {
+                const double a = 2.0 * pi * double(h) * l / N;
+                cr += U[l] * std::cos(a);
+                ci -= U[l] * std::sin(a);
+            }
+            mag[h] = std::hypot(cr, ci) / N;  // |U_h|, U(y) = sum_h U_h e^{i h y}
+            if (mag[h] > amax) { amax = mag[h]; hsel = h; hr = cr / N; hi = ci / N; }
+        }
+        for (int h = 0; h <= N / 2; ++h) nbig += mag[h] > 1e-12 * amax ? 1 : 0;
+        const int M = k->M;
+        if (umax > 0.0 && nbig == 1 && hsel >= 1 && hsel < N / 2 && hsel < N - 2 * M &&
+            couple_slots(M, hsel) <= 2) {
+            // U = 2 Re(U_h e^{i h y}) = 2|U_h| cos(h y + theta) = amp sin(h (y - y0))
+            const double theta = std::atan2(hi, hr);
+            k->couple = true;
+            k->nh = hsel;
+            k->amp = 2.0 * std::hypot(hr, hi);
+            k->y0 = -(theta + 0.5 * pi) / hsel;
+            if (std::fabs(k->y0) < 1e-15) k->y0 = 0.0;
+        }
+    }
     TSK_TRY(k->upload_real(k->negU, nu));
     TSK_TRY(k->upload_real(k->dOdy, oy));
     gen2d_free(k->gen);
@@ -717,7 +789,8 @@ tsk_status kolmo_set_base_general(Operator* op, const double* U, const double* V
 tsk_status kolmo_set_tuning(Operator* op, int cols) {
     auto* k = dynamic_cast<KolmoOp*>(op);
     if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
-    if (cols < 0 || cols > 2) return fail(TSK_EINVAL, "columns per wavefront must be 0 (autotune), 1 or 2");
+    if (cols < 0 || cols > 3)
+        return fail(TSK_EINVAL, "tuning must be 0 (automatic), 1 or 2 (columns per wavefront) or 3 (Bloch sectors)");
     k->force_cols = cols;
     return TSK_OK;
 }
@@ -725,11 +798,15 @@ tsk_status kolmo_set_tuning(Operator* op, int cols) {
 tsk_status kolmo_get_tuning(const Operator* op, int* cols) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);
     if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
-    int c = std::min(k->force_cols, max_cols(k->N));
-    if (c == 0 && k->bloch && !k->gen) {
+    if (k->use_couple()) {
+        *cols = -2;  // the spectral-coupling stepper
+        return TSK_OK;
+    }
+    if (k->use_bloch()) {
         *cols = -1;  // the Bloch-sector stepper
         return TSK_OK;
     }
+    int c = std::min(k->force_cols, max_cols(k->N));
     if (c == 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(TuneKey{k->N, k->prec == TSK_FP32, k->prop, size_bucket(k->M + 1)});
@@ -748,7 +825,12 @@ bool is_kolmo(const Operator* op) { return dynamic_cast<const KolmoOp*>(op) != n
 
 bool kolmo_bloch(const Operator* op) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);
-    return k && !k->gen && k->bloch && k->force_cols == 0;
+    return k && k->use_bloch();
+}
+
+bool kolmo_couple(const Operator* op) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    return k && k->use_couple();
 }
 
 int kolmo_cutoff(const Operator* op) {
@@ -768,7 +850,9 @@ struct KolmoBatch {
         int N;
         bool prop;
         bool bloch = false;
-        DevBuf ids;  // Bloch groups: instance indices
+        bool couple = false;  // spectral-coupling stepper: instances of every N in one launch
+        int cblocks = 0, cslots = 1;  // its grid x (largest instance) and positions per lane
+        DevBuf ids;  // Bloch and coupling groups: instance indices
         int nids = 0;
         const void* tw;
         DevBuf tasks[3];  // task lists for 1 and 2 columns per wavefront
@@ -817,11 +901,13 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     TSK_HIP(hipMemcpy(b->insts.ptr, host.data(), host.size(), hipMemcpyHostToDevice));
     std::vector<std::vector<int>> gids;
     for (int i = 0; i < count; ++i) {
-        const bool kb = kolmo_bloch(ko[i]);
+        const bool kc = kolmo_couple(ko[i]);
+        const bool kb = !kc && kolmo_bloch(ko[i]);
         KolmoBatch::Group* g = nullptr;
-        for (size_t q = 0; q < b->groups.size(); ++q) {
+        for (size_t q = 0; q < b->groups.size() && !g; ++q) {
             KolmoBatch::Group* c = b->groups[q].get();
-            if (c->N == ko[i]->N && c->prop == ko[i]->prop && c->bloch == kb) {
+            if ((kc && c->couple) ||
+                (!kc && !c->couple && c->N == ko[i]->N && c->prop == ko[i]->prop && c->bloch == kb)) {
                 g = c;
                 gids[q].push_back(i);
             }
@@ -833,19 +919,25 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
             g->N = ko[i]->N;
             g->prop = ko[i]->prop;
             g->bloch = kb;
+            g->couple = kc;
             g->tw = ko[i]->tw.ptr;
             g->force = ko[i]->force_cols;
         }
         g->columns += ko[i]->M + 1;
+        if (kc) {
+            g->cblocks = std::max(g->cblocks, couple_blocks(ko[i]->M, ko[i]->nh));
+            g->cslots = std::max(g->cslots, couple_slots(ko[i]->M, ko[i]->nh));
+        }
     }
     for (size_t q = 0; q < b->groups.size(); ++q) {
         KolmoBatch::Group* g = b->groups[q].get();
-        if (!g->bloch) continue;
+        if (!g->bloch && !g->couple) continue;
         g->nids = int(gids[q].size());
         TSK_TRY(g->ids.ensure(gids[q].size() * sizeof(int)));
         TSK_HIP(hipMemcpy(g->ids.ptr, gids[q].data(), gids[q].size() * sizeof(int), hipMemcpyHostToDevice));
     }
-    for (auto& g : b->groups) g->work = double(g->columns) * g->N * std::log2(double(g->N));
+    for (auto& g : b->groups)
+        g->work = g->couple ? double(g->columns) * g->cslots * kWave : double(g->columns) * g->N * std::log2(double(g->N));
     std::sort(b->groups.begin(), b->groups.end(),
               [](const std::unique_ptr<KolmoBatch::Group>& x, const std::unique_ptr<KolmoBatch::Group>& y) {
                   return x->work > y->work;
@@ -861,7 +953,7 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     if (b->groups.size() > 1) TSK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     const hipStream_t s = ops[0]->stream;
     for (auto& g : b->groups) {
-        if (g->bloch) continue;  // no column tasks, nothing to tune
+        if (g->bloch || g->couple) continue;  // no column tasks, nothing to tune
         for (int c = 1; c <= max_cols(g->N); ++c) {
             std::vector<ColTask> tk;
             for (int i = 0; i < count; ++i)
@@ -901,7 +993,14 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
         hipStream_t st = q == 0 ? s : b->aux[q - 1];
         if (q > 0) TSK_HIP(hipStreamWaitEvent(st, b->fork, 0));
         const int c = g->cols;
-        if (g->bloch) {
+        if (g->couple) {
+            if (b->fp32)
+                launch_couple_stepper<float>(ColInst<float>{}, b->insts.as<ColInst<float>>(), g->ids.as<int>(),
+                                             g->nids, j, g->cblocks, g->cslots, st);
+            else
+                launch_couple_stepper<double>(ColInst<double>{}, b->insts.as<ColInst<double>>(), g->ids.as<int>(),
+                                              g->nids, j, g->cblocks, g->cslots, st);
+        } else if (g->bloch) {
             if (b->fp32)
                 launch_bloch_stepper<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->ids.as<int>(),
                                             g->nids, j, static_cast<const cplx<float>*>(g->tw), st);

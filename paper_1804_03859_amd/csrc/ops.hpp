@@ -154,6 +154,8 @@ tsk_status kolmo_get_tuning(const Operator* op, int* cols);
 bool kolmo_parallel(const Operator* op);
 // The operator's own matvec runs the Bloch-sector stepper (colbloch.hpp).
 bool kolmo_bloch(const Operator* op);
+// The operator's own matvec runs the spectral-coupling stepper (colcouple.hpp).
+bool kolmo_couple(const Operator* op);
 // Largest kept wavenumber M = (N-1)/3 of a Navier-Stokes operator, -1 for others.
 int kolmo_cutoff(const Operator* op);
 bool is_cgle(const Operator* op);

@@ -48,7 +48,10 @@ def test_bloch_sector_batch_equals_single_runs_bitwise(tsk, prec):
     print(f"bloch batch vs single prec={prec}", flush=True)
     cfg = [(128, 20.0, 0.5), (256, 12.0, 0.75), (128, 30.0, 1.0), (48, 25.0, 0.25)]
     ops = [_kolmo(tsk, N, Re, a, prec) for N, Re, a in cfg]
-    assert [tsk.get_tuning(op) for op in ops[:3]] == [-1, -1, -1]
+    for op in ops[:3]:
+        tsk.set_tuning(op, 3)   # Bloch sectors instead of the default coupling stepper
+    tsk.set_tuning(ops[3], 1)
+    assert [tsk.get_tuning(op) for op in ops] == [-1, -1, -1, 1]
     v0s = [_start(tsk, op, N, i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
     rb = tsk.batch_arnoldi(ops, 40, 4, 1e-8, v0s=v0s, want_vectors=True)
     for op, v0, b in zip(ops, v0s, rb):
@@ -63,11 +66,30 @@ def test_bloch_sector_batch_512_equals_single_runs_bitwise(tsk):
     print("bloch batch 512 vs single", flush=True)
     cfg = [(512, 20.0, 0.5), (512, 30.0, 1.0), (128, 15.0, 0.75)]
     ops = [_kolmo(tsk, N, Re, a, 1) for N, Re, a in cfg]
+    for op in ops:
+        tsk.set_tuning(op, 3)
     assert [tsk.get_tuning(op) for op in ops] == [-1, -1, -1]
     v0s = [_start(tsk, op, N, 10 + i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
     rb = tsk.batch_arnoldi(ops, 24, 2, 1e-6, v0s=v0s, want_vectors=True)
     for op, v0, b in zip(ops, v0s, rb):
         r = tsk.arnoldi(op, 24, 2, 1e-6, v0=v0, want_vectors=True)
+        assert b["status"] == r["status"] and b["n_matvec"] == r["n_matvec"]
+        assert np.array_equal(b["lam"], r["lam"]) and np.array_equal(b["res"], r["res"])
+        assert torch.equal(b["X"], r["X"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coupling_stepper_batch_of_mixed_sizes_equals_single_runs_bitwise(tsk, prec):
+    # the one-harmonic base takes the spectral-coupling stepper at every grid size,
+    # and a batch runs all of them in one launch (instances on grid y)
+    print(f"coupling batch vs single prec={prec}", flush=True)
+    cfg = [(128, 20.0, 0.5), (384, 12.0, 0.75), (256, 30.0, 1.0), (48, 25.0, 0.25), (512, 8.0, 0.5)]
+    ops = [_kolmo(tsk, N, Re, a, prec) for N, Re, a in cfg]
+    assert [tsk.get_tuning(op) for op in ops] == [-2] * len(ops)
+    v0s = [_start(tsk, op, N, 20 + i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
+    rb = tsk.batch_arnoldi(ops, 40, 4, 1e-8, v0s=v0s, want_vectors=True)
+    for op, v0, b in zip(ops, v0s, rb):
+        r = tsk.arnoldi(op, 40, 4, 1e-8, v0=v0, want_vectors=True)
         assert b["status"] == r["status"] and b["n_matvec"] == r["n_matvec"]
         assert np.array_equal(b["lam"], r["lam"]) and np.array_equal(b["res"], r["res"])
         assert torch.equal(b["X"], r["X"])

@@ -70,31 +70,31 @@ def _oracle_matvec(N, T):
     return _ORACLE_MATVEC[(N, T)]
 
 
-# (N, T, precision, stepper): stepper "auto" is the library's choice (the
-# Bloch-sector stepper at 128^2, 256^2 and 512^2 with this base: the kernels of
-# the benchmark configurations), "column" forces one kx column per wavefront.
+# (N, T, precision, stepper): stepper "auto" is the library's choice (for this
+# one-harmonic base the spectral-coupling stepper, at every N: the kernel of the
+# benchmark configurations), "bloch" forces the Bloch-sector stepper (128^2,
+# 256^2, 512^2), "column" one kx column per wavefront of the FFT column stepper.
 # Full T = 1 (200 IF-RK4 steps) at 128^2 and 256^2, 20 steps at 384^2 and 512^2.
 # Bars: 1e-11 (FP64), 2e-5 (FP32 state, transforms and RK4) of max |M w|.
 @pytest.mark.parametrize("N,T,prec,stepper", [
-    (16, 1.0, 0, "auto"), (48, 1.0, 0, "auto"), (96, 0.05, 0, "auto"),
-    (128, 1.0, 0, "auto"), (128, 1.0, 1, "auto"), (128, 0.1, 0, "column"), (128, 0.1, 1, "column"),
-    (256, 1.0, 0, "auto"), (256, 1.0, 1, "auto"), (256, 1.0, 0, "column"),
-    (384, 0.1, 0, "auto"), (384, 0.1, 1, "auto"),
-    (512, 0.1, 0, "auto"), (512, 0.1, 1, "auto"), (512, 0.1, 1, "column")])
+    (16, 1.0, 0, "auto"), (48, 1.0, 0, "auto"), (48, 1.0, 1, "auto"), (96, 0.05, 0, "auto"),
+    (128, 1.0, 0, "auto"), (128, 1.0, 1, "auto"), (128, 1.0, 0, "bloch"), (128, 1.0, 1, "bloch"),
+    (128, 0.1, 0, "column"), (128, 0.1, 1, "column"),
+    (256, 1.0, 0, "auto"), (256, 1.0, 1, "auto"), (256, 1.0, 0, "bloch"), (256, 1.0, 1, "bloch"),
+    (256, 1.0, 0, "column"),
+    (384, 0.1, 0, "auto"), (384, 0.1, 1, "auto"), (384, 0.1, 1, "column"),
+    (512, 0.1, 0, "auto"), (512, 0.1, 1, "auto"), (512, 0.1, 0, "bloch"), (512, 0.1, 1, "bloch"),
+    (512, 0.1, 1, "column")])
 def test_matvec_matches_oracle(tsk, N, T, prec, stepper):
     print(f"kolmo matvec N={N} T={T} prec={prec} stepper={stepper}", flush=True)
     op, _ = _op(tsk, N, T=T, prec=prec)
-    if stepper == "column":
-        tsk.set_tuning(op, 1)
+    expect = {"auto": -2, "bloch": -1, "column": 1}[stepper]
+    tsk.set_tuning(op, {"auto": 0, "bloch": 3, "column": 1}[stepper])
     w, want = _oracle_matvec(N, T)
     x = op.new_state()
     tsk.from_physical(op, _phys(op, N, w), x)
     y = op.new_state()
     tsk.apply(op, x, y)
-    expect = -1 if (stepper == "auto" and N in (128, 256, 512)) else 1
-    if stepper == "auto" and N not in (128, 256, 512):
-        expect = tsk.get_tuning(op)
-        assert expect in (1, 2)
     assert tsk.get_tuning(op) == expect
     got = _to_phys(tsk, op, y)
     tol = 1e-11 if prec == 0 else 2e-5
@@ -300,18 +300,18 @@ def test_columns_per_wave_variants_agree_bitwise(tsk, N, prec, base):
     tsk.set_tuning(op, 0)
     y_ = op.new_state()
     tsk.apply(op, x, y_)
-    if N in (128, 256, 512) and base == "kolmogorov":
-        # the default at 128^2 and 256^2 with the quarter-period base is the
-        # Bloch-sector stepper: the same operator, other rounding
+    if base == "kolmogorov":
+        # the default for the one-harmonic base is the spectral-coupling stepper:
+        # the same operator, other rounding
         tol = 1e-13 if prec == 0 else 2e-6
         assert torch.max(torch.abs(y_ - outs[0])).item() <= tol * torch.max(torch.abs(outs[0])).item()
         assert not torch.equal(y_, outs[0])
-        assert tsk.get_tuning(op) == -1
+        assert tsk.get_tuning(op) == -2
     else:
         assert torch.equal(y_, outs[0])       # autotuned: one of the two, same bits
         assert tsk.get_tuning(op) in (1, 2)
     with pytest.raises(tsk.TskError):
-        tsk.set_tuning(op, 3)
+        tsk.set_tuning(op, 4)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -322,6 +322,7 @@ def test_bloch_stepper_512_matches_column_stepper(tsk, prec):
     op, _ = _op(tsk, 512, prec=prec, T=0.05)
     x = op.new_state()
     tsk.from_physical(op, _phys(op, 512, W.kolmo_start_physical(512, 4)), x)
+    tsk.set_tuning(op, 3)
     assert tsk.get_tuning(op) == -1
     yb = op.new_state()
     tsk.apply(op, x, yb)

@@ -307,6 +307,26 @@ tsk_status tsk_krylov_schur(tsk_op op, int m, int k, double tol, double delta, i
                             const void* v0_dev, uint64_t seed, double* mu_ri, double* lambda_ri, double* resid,
                             void* ritz_dev, tsk_ks_info* info);
 
+/* Batched Krylov-Schur for neutral-curve sweeps (Sec. 3.2.2): `count` real
+ * operators (one state type and one stream) advance in lockstep as in
+ * tsk_batch_arnoldi, with the Ritz analysis and stop test after every matvec,
+ * up to order m.  Every instance still not converged at order m then continues
+ * as tsk_krylov_schur does: contraction to its kept Ritz values (|mu| >= 1 -
+ * delta, raised to k and lowered to p_max), rotation of its basis, expansion
+ * back to order m, test at order m, at most max_restarts contractions.  The
+ * contractions of all such instances run in one launch (one wavefront each) and
+ * their expansions in lockstep, instance i from its own kept order.  Arguments
+ * as tsk_batch_arnoldi (per instance i: v0_devs[i], seeds[i], mu_ri + 2k i,
+ * lambda_ri + 2k i, resid + k i, ritz_devs[i]) and tsk_krylov_schur (delta,
+ * p_max: 0 = max(k, m/2), max_restarts); infos[i] (host array or NULL): the
+ * instance's matvecs (m + (m - p) per contraction when it restarted), its
+ * contractions and status.  Returns TSK_OK when every instance ended without
+ * error (see infos[i].status), or a negative status for an argument or runtime
+ * failure of the whole batch. */
+tsk_status tsk_batch_krylov_schur(const tsk_op* ops, int count, int m, int k, double tol, double delta, int p_max,
+                                  int max_restarts, const void* const* v0_devs, const uint64_t* seeds, double* mu_ri,
+                                  double* lambda_ri, double* resid, void* const* ritz_devs, tsk_ks_info* infos);
+
 /* The contraction on its own (the device kernel tsk_krylov_schur runs at
  * order m).  Input: H_dev, m x m real upper Hessenberg (FP64, column-major,
  * leading dimension ldh >= m; only the Hessenberg part is read), and beta, the

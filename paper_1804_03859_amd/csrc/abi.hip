@@ -325,6 +325,28 @@ tsk_status tsk_batch_arnoldi(const tsk_op* ops, int count, int m, int k, double 
     })
 }
 
+tsk_status tsk_batch_krylov_schur(const tsk_op* ops, int count, int m, int k, double tol, double delta, int p_max,
+                                  int max_restarts, const void* const* v0_devs, const uint64_t* seeds, double* mu_ri,
+                                  double* lambda_ri, double* resid, void* const* ritz_devs, tsk_ks_info* infos) {
+    TSK_GUARD({
+        if (!ops || count < 1) return fail(TSK_EINVAL, "empty batch");
+        std::vector<Operator*> o(count);
+        for (int i = 0; i < count; ++i) {
+            if (!ops[i] || !ops[i]->op) return fail(TSK_EINVAL, "null operator handle in batch");
+            o[i] = ops[i]->op.get();
+            if (o[i]->is_complex()) return fail(TSK_EINVAL, "Krylov-Schur (real Schur form) needs real operators");
+        }
+        if (k < 1 || m < k + 2 || m > kMaxKrylov) return fail(TSK_EINVAL, "need 1 <= k and k + 2 <= m <= 96");
+        if (p_max == 0) p_max = std::max(k, m / 2);
+        if (p_max < k || p_max > m - 2) return fail(TSK_EINVAL, "need k <= p_max <= m - 2");
+        if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(TSK_EINVAL, "delta must be finite and >= 0");
+        if (max_restarts < 0) return fail(TSK_EINVAL, "max_restarts must be >= 0");
+        BatchRestart rs{delta, p_max, max_restarts, infos};
+        return arnoldi_batch(o.data(), count, m, k, tol, v0_devs, seeds, mu_ri, lambda_ri, resid, ritz_devs, nullptr,
+                             false, &rs);
+    })
+}
+
 tsk_status tsk_krylov_schur(tsk_op op, int m, int k, double tol, double delta, int p_max, int max_restarts,
                             const void* v0_dev, uint64_t seed, double* mu_ri, double* lambda_ri, double* resid,
                             void* ritz_dev, tsk_ks_info* info) {

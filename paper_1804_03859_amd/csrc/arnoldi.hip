@@ -234,14 +234,15 @@ tsk_status driver_resources(ArnoldiWork& L, int m, int nrr) {
 // Step j of the factorisation after the matvec w = M v_j: classical
 // Gram-Schmidt twice against v_0..v_j (H column j = h1 + h2), beta_j = ||f||,
 // H[j+1][j] = beta_j, v_{j+1} = f / beta_j (Algorithm 1 with CGS2).
+// pextra: the largest step offset (KryDesc::poff) of the table, 0 in ordinary runs.
 template <typename TS>
-void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, hipStream_t s) {
+void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, hipStream_t s, int pextra = 0) {
     const int p = j + 1;
     const bool fuse = nblk_max <= kFuseFinalMaxBlocks;
     launch_dot<TS>(Dt, count, nblk_max, p, false, s);
-    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 1, false, s);  // h1 = V^H w, w -= V h1, dots for pass 2
-    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 2, fuse, s);   // h2, w -= V h2, squared norm
-    if (!fuse) launch_scale_final<TS>(Dt, count, nmax, j, s);     // beta, H[j+1][j], flags, v_{j+1}
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 1, false, s, pextra);  // h1 = V^H w, w -= V h1, dots for pass 2
+    launch_cgs_pass<TS>(Dt, count, nblk_max, p, j, 2, fuse, s, pextra);   // h2, w -= V h2, squared norm
+    if (!fuse) launch_scale_final<TS>(Dt, count, nmax, j, s);             // beta, H[j+1][j], flags, v_{j+1}
 }
 
 // svd = false: Arnoldi on M (Algorithm 1).  svd = true: Lanczos on M^dagger M
@@ -251,7 +252,7 @@ void cgs2_step(const KryDesc* Dt, int count, int nblk_max, int64_t nmax, int j, 
 template <typename TS>
 tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                      const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                     tsk_arnoldi_info* infos, bool svd) {
+                     tsk_arnoldi_info* infos, bool svd, const BatchRestart* rs) {
     auto t0 = std::chrono::steady_clock::now();
     Operator* lead = ops[0];
     const hipStream_t s = lead->stream;
@@ -354,6 +355,7 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // as soon as the operator stream has finished the matvec before the last
     // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
+    constexpr int kQueueAhead = 1;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     // a batch of grid-size groups runs its extra groups on worker streams 1 and 2;
     // its analyses then use stream 0 only, so the operator's stream and the three
@@ -456,10 +458,14 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             if (q != hipErrorNotReady) TSK_HIP(q);
         }
         if (next < m && int(pend.size() + ready.size()) < NS) {
-            // one step queued ahead: step `next` goes behind its own matvec as soon as
-            // the matvec before it has finished, so the operator stream never waits
-            // for the host
-            const hipError_t qm = hipEventQuery(L.ev_apply[2 * (next - 1) + 1]);
+            // kQueueAhead steps queued ahead: step `next` goes behind its own matvec
+            // as soon as the matvec kQueueAhead steps before it has finished, so the
+            // operator stream never waits for the host.  The gaps left between the
+            // kernels of a step (5-10 us each on this device) are dependent-launch
+            // latency, not host delay: queueing three steps ahead did not shorten
+            // them, so one step ahead keeps the fewest discarded matvecs.
+            const hipError_t qm = next < kQueueAhead ? hipSuccess
+                                                     : hipEventQuery(L.ev_apply[2 * (next - kQueueAhead) + 1]);
             if (qm == hipSuccess) {
                 TSK_TRY(enqueue(next++));
                 continue;
@@ -486,6 +492,136 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         if (svd) Dh[i].Y = Dh[i].S;  // the tridiagonal solver left the unit Ritz coordinates there
         ops[i]->aw.steps = oc[i].steps;
         pmax = std::max(pmax, oc[i].steps);
+    }
+
+    // ---- batched restart phase (Sec. 3.2.2): the instances not converged at order m ------------
+    // contract to the Krylov-Schur form of their kept Ritz values (one wavefront each,
+    // the kernel of tsk_krylov_schur), rotate their bases and expand again in
+    // lockstep, instance i from its own kept order p_i (its step = the batch step
+    // + p_i); convergence is tested at order m, as in Krylov-Schur.
+    std::vector<int> extra_mv(count, 0), n_restarts(count, 0), kept_last(count, 0);
+    if (rs && !svd && kRealH) {
+        std::vector<int> R;
+        for (int i = 0; i < count; ++i)
+            if (oc[i].status == TSK_NOT_CONVERGED && oc[i].steps == m) R.push_back(i);
+        std::vector<void*> Vcur(count, nullptr), Valt(count, nullptr);
+        std::vector<KryDesc> DR;
+        int64_t nmax_r = 0;
+        int nblk_max_r = 0;
+        for (int i : R) {
+            ArnoldiWork& W = ops[i]->aw;
+            TSK_TRY(W.V2.ensure(size_t(m + 1) * W.ldv * sizeof(TS)));
+            TSK_TRY(W.ksW.ensure(size_t(m) * m * sizeof(double)));
+            Vcur[i] = W.V.ptr;
+            Valt[i] = W.V2.ptr;
+            KryDesc d = Dh[i];
+            d.ksW = W.ksW.as<double>();
+            d.ks_delta = rs->delta;
+            d.ks_pmax = rs->pmax;
+            d.poff = 0;
+            d.steps = m;
+            DR.push_back(d);
+            nmax_r = std::max(nmax_r, ops[i]->n);
+            nblk_max_r = std::max(nblk_max_r, d.nblk);
+        }
+        if (!R.empty()) {
+            TSK_TRY(L.ks_desc.ensure(R.size() * sizeof(KryDesc)));
+            TSK_TRY(L.batch_rr.ensure(std::max(size_t(NS) * count, R.size()) * sizeof(RitzResult)));
+        }
+        KryDesc* DRd = L.ks_desc.as<KryDesc>();
+        int cycle = 0;
+        while (!R.empty()) {
+            const int nr = int(R.size());
+            TSK_HIP(hipMemcpyAsync(DRd, DR.data(), nr * sizeof(KryDesc), hipMemcpyHostToDevice, s));
+            const int contract = cycle < rs->max_restarts ? 1 : 0;
+            TSK_TRY(ks_contract_launch(DRd, m, k, tol, contract, s, nr));
+            hipLaunchKernelGGL(k_collect, dim3(1), dim3(256), 0, s, DRd, nr, L.batch_rr.as<RitzResult>(), 0);
+            TSK_HIP(hipMemcpyAsync(rrh, L.batch_rr.ptr, size_t(nr) * sizeof(RitzResult), hipMemcpyDeviceToHost, s));
+            TSK_HIP(hipStreamSynchronize(s));
+            std::vector<int> keepR;
+            std::vector<KryDesc> keepD;
+            std::vector<int> kp;
+            for (int q = 0; q < nr; ++q) {
+                const int i = R[q];
+                const RitzResult r = rrh[q];
+                KryDesc d = DR[q];
+                d.poff = 0;
+                int st = -100;
+                if (r.nonfinite) { st = TSK_ENONFINITE; oc[i].err = "non-finite matvec output or norm"; }
+                else if (r.eig_fail == 1) { st = TSK_EEIG; oc[i].err = "Hessenberg QR did not converge"; }
+                else if (r.eig_fail == 2) { st = TSK_EEIG; oc[i].err = "Schur reordering left no room to expand"; }
+                else if (r.bd_step) {
+                    // happy breakdown during the last expansion: exact Ritz pairs of that order
+                    d.steps = r.bd_step;
+                    TSK_HIP(hipMemcpyAsync(DRd + q, &d, sizeof(KryDesc), hipMemcpyHostToDevice, s));
+                    TSK_TRY(hess_ritz_launch(DRd + q, 1, r.bd_step, std::min(k, r.bd_step), tol, false, s, true));
+                    TSK_HIP(hipStreamSynchronize(s));
+                    st = TSK_BREAKDOWN;
+                } else if (r.done) st = TSK_OK;
+                else if (!contract) st = TSK_NOT_CONVERGED;
+                if (st != -100) {
+                    oc[i].status = st;
+                    Dh[i] = d;
+                    Dh[i].V = Vcur[i];
+                    Dh[i].active = 1;
+                    ops[i]->aw.Vcur = Vcur[i];
+                    ops[i]->aw.steps = d.steps;
+                    continue;
+                }
+                keepR.push_back(i);
+                keepD.push_back(d);
+                kp.push_back(r.kept);
+            }
+            if (keepR.empty()) break;
+            // V_p = V_m W, v_{p+1} = v_{m+1} into the other buffer; expansion inputs and offsets
+            std::vector<const void*> xb(count, nullptr);
+            std::vector<int> jm(count, 0);
+            int pmin = m, pext = 0;
+            for (size_t q = 0; q < keepR.size(); ++q) {
+                const int i = keepR[q], p_i = kp[q];
+                ArnoldiWork& W = ops[i]->aw;
+                launch_rotate<TS>(Vcur[i], Valt[i], keepD[q].ksW, ops[i]->n, W.ldv, m, p_i, s);
+                std::swap(Vcur[i], Valt[i]);
+                keepD[q].V = Vcur[i];
+                keepD[q].poff = p_i;
+                xb[i] = static_cast<const TS*>(Vcur[i]) + size_t(p_i) * W.ldv;
+                jm[i] = m - p_i;
+                pmin = std::min(pmin, p_i);
+                pext = std::max(pext, p_i);
+                extra_mv[i] += m - p_i;
+                ++n_restarts[i];
+                kept_last[i] = p_i;
+            }
+            R = keepR;
+            DR = keepD;
+            const int nr2 = int(R.size());
+            TSK_HIP(hipMemcpyAsync(DRd, DR.data(), nr2 * sizeof(KryDesc), hipMemcpyHostToDevice, s));
+            if (kb) TSK_TRY(kolmo_batch_set_inputs(kb.get(), xb.data(), jm.data(), s));
+            const int G = m - pmin;
+            for (int g = 0; g < G; ++g) {
+                TSK_HIP(hipEventRecord(L.ev_apply[2 * g], s));
+                if (kb) {
+                    TSK_TRY(kolmo_batch_matvec(kb.get(), g, s));
+                } else {
+                    for (int q = 0; q < nr2; ++q) {
+                        const int i = R[q];
+                        if (g < jm[i]) TSK_TRY(ops[i]->apply(static_cast<const TS*>(xb[i]) + size_t(g) * ops[i]->aw.ldv,
+                                                             DR[q].w));
+                    }
+                }
+                TSK_HIP(hipEventRecord(L.ev_apply[2 * g + 1], s));
+                cgs2_step<TS>(DRd, nr2, nblk_max_r, nmax_r, g, s, pext);
+            }
+            TSK_HIP(hipStreamSynchronize(s));
+            for (int g = 0; g < G; ++g) {
+                float ms = 0.0f;
+                TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * g], L.ev_apply[2 * g + 1]));
+                ms_apply += ms;
+            }
+            for (KryDesc& d : DR) d.poff = 0;  // order m again: the contraction reads H_m
+            ++cycle;
+        }
+        for (int i = 0; i < count; ++i) pmax = std::max(pmax, Dh[i].steps);
     }
     TSK_HIP(hipMemcpyAsync(D, Dh.data(), size_t(count) * sizeof(KryDesc), hipMemcpyHostToDevice, s));
     bool any_ritz = false;
@@ -516,9 +652,21 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             }
             if (resid) resid[k * i + q] = ok ? o[4 * k + q] : 0.0;
         }
+        if (rs && rs->infos) {
+            tsk_ks_info& f = rs->infos[i];
+            f.n_matvec = oc[i].steps + extra_mv[i];
+            f.n_restarts = n_restarts[i];
+            f.n_ritz = ok ? rrh[i].nsel : 0;
+            f.n_converged = ok ? rrh[i].nconv : 0;
+            f.status = oc[i].status;
+            f.kept_last = kept_last[i];
+            f.beta = rrh[i].beta;
+            f.ms_total = ms_total;
+            f.ms_apply = ms_apply;
+        }
         if (infos) {
             tsk_arnoldi_info& f = infos[i];
-            f.n_matvec = oc[i].steps;
+            f.n_matvec = oc[i].steps + extra_mv[i];
             f.n_ritz = ok ? rrh[i].nsel : 0;
             f.n_converged = ok ? rrh[i].nconv : 0;
             f.status = oc[i].status;
@@ -667,7 +815,7 @@ tsk_status krylov_schur_t(Operator* op, int m, int k, double tol, double delta, 
 
 tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                          const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                         tsk_arnoldi_info* infos, bool svd) {
+                         tsk_arnoldi_info* infos, bool svd, const BatchRestart* rs) {
     if (count < 1 || !ops) return fail(TSK_EINVAL, "empty batch");
     if (k < 1 || m < k || m > kMaxKrylov) return fail(TSK_EINVAL, "need 1 <= k <= m <= 96");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TSK_EINVAL, "tol must be finite and >= 0");
@@ -684,11 +832,11 @@ tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double t
     }
     switch (ops[0]->kind) {
         case StateKind::Complex64x2:
-            return arnoldi_t<double2>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
+            return arnoldi_t<double2>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd, rs);
         case StateKind::Real64:
-            return arnoldi_t<double>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
+            return arnoldi_t<double>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd, rs);
         case StateKind::Real32:
-            return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd);
+            return arnoldi_t<float>(ops, count, m, k, tol, v0s, seeds, mu_ri, lam_ri, resid, ritz, infos, svd, rs);
     }
     return fail(TSK_EINVAL, "unknown state kind");
 }

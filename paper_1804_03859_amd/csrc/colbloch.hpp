@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch(ColInst<real> one, cons
     constexpr int S = L == 128 ? 2 : 1;  // modes per lane
     stepper_wave_priority();
     const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
-    if (I.active && *I.active == 0) return;
+    if ((I.active && *I.active == 0) || jstep >= I.jmax) return;
     const int lane = threadIdx.x;
     const real* __restrict__ xin = I.xbase + jstep * I.xstride;
     real* __restrict__ yout = I.y;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_bloch_split(ColInst<real> one
     constexpr int M = G::M, P = 4;
     stepper_wave_priority();
     const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
-    if (I.active && *I.active == 0) return;
+    if ((I.active && *I.active == 0) || jstep >= I.jmax) return;
     const int lane = threadIdx.x;
     const real* __restrict__ xin = I.xbase + jstep * I.xstride;
     real* __restrict__ yout = I.y;

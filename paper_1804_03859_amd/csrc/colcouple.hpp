@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_couple(ColInst<real> one, con
     using C = cplx<real>;
     stepper_wave_priority();
     const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
-    if (I.active && *I.active == 0) return;
+    if ((I.active && *I.active == 0) || jstep >= I.jmax) return;
     const int M = I.M, nh = I.nh;
     if (int(blockIdx.x) >= couple_blocks(M, nh)) return;
     const int lane = threadIdx.x;

@@ -45,6 +45,9 @@ template <typename real> struct ColInst {
     // and phase; unused by the other steppers
     int M, nh;
     double amp, y0;
+    // batched restart phase: the instance's input is xbase + jstep xstride while
+    // jstep < jmax, later steps skip it (INT_MAX in ordinary runs)
+    int jmax;
 };
 struct ColTask {
     int inst;  // index into the instance table
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(kWave) void k_colstep(ColInst<real> one, const ColI
     stepper_wave_priority();
     const ColTask tk = tasks[blockIdx.x];
     const ColInst<real>& I = insts ? insts[tk.inst] : one;
-    if (I.active && *I.active == 0) return;
+    if ((I.active && *I.active == 0) || jstep >= I.jmax) return;
     const real* __restrict__ xin = I.xbase + jstep * I.xstride;
     real* __restrict__ yout = I.y;
     const real* __restrict__ negU = I.negU;

@@ -1591,7 +1591,7 @@ tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double
     return tridiag_ritz_launch_steps(one, 1, count, p, k, tol, s);
 }
 
-tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s) {
+tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s, int count) {
     if (m < 2 || m > kMaxKrylov) return fail(TSK_EINVAL, "Krylov-Schur order must be in [2, 96]");
     static bool attr_set = false;
     if (!attr_set) {
@@ -1599,7 +1599,7 @@ tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int co
                                     int(2 * kMaxKrylov * kMaxKrylov * sizeof(double))));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_ks_contract, dim3(1), dim3(kHT), size_t(2) * m * m * sizeof(double), s, D, m, k, tol,
+    hipLaunchKernelGGL(k_ks_contract, dim3(count), dim3(kHT), size_t(2) * m * m * sizeof(double), s, D, m, k, tol,
                        contract);
     TSK_HIP(hipGetLastError());
     return TSK_OK;

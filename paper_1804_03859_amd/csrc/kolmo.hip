@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <limits>
 #include <mutex>
 #include <tuple>
 
@@ -465,6 +466,7 @@ struct KolmoOp final : Operator {
         c.nh = nh;
         c.amp = amp;
         c.y0 = y0;
+        c.jmax = std::numeric_limits<int>::max();
         return c;
     }
     bool use_couple() const { return !gen && couple && force_cols == 0; }
@@ -846,6 +848,7 @@ int kolmo_cutoff(const Operator* op) {
 struct KolmoBatch {
     bool fp32 = false;
     DevBuf insts;
+    std::vector<char> host_insts;  // the instance table as uploaded (restart offsets rewrite it)
     struct Group {
         int N;
         bool prop;
@@ -899,6 +902,7 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     }
     TSK_TRY(b->insts.ensure(host.size()));
     TSK_HIP(hipMemcpy(b->insts.ptr, host.data(), host.size(), hipMemcpyHostToDevice));
+    b->host_insts = host;
     std::vector<std::vector<int>> gids;
     for (int i = 0; i < count; ++i) {
         const bool kc = kolmo_couple(ko[i]);
@@ -1017,6 +1021,27 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
         if (q > 0) TSK_HIP(hipEventRecord(b->done[q - 1], st));
     }
     for (size_t q = 1; q < G; ++q) TSK_HIP(hipStreamWaitEvent(s, b->done[q - 1], 0));
+    return TSK_OK;
+}
+
+tsk_status kolmo_batch_set_inputs(KolmoBatch* b, const void* const* xbase, const int* jmax, hipStream_t s) {
+    const size_t isz = b->fp32 ? sizeof(ColInst<float>) : sizeof(ColInst<double>);
+    const size_t count = b->host_insts.size() / isz;
+    for (size_t i = 0; i < count; ++i) {
+        char* e = b->host_insts.data() + isz * i;
+        if (b->fp32) {
+            auto* c = reinterpret_cast<ColInst<float>*>(e);
+            c->xbase = static_cast<const float*>(xbase[i]);
+            c->jmax = jmax[i];
+        } else {
+            auto* c = reinterpret_cast<ColInst<double>*>(e);
+            c->xbase = static_cast<const double*>(xbase[i]);
+            c->jmax = jmax[i];
+        }
+    }
+    TSK_HIP(hipMemcpyAsync(b->insts.ptr, b->host_insts.data(), b->host_insts.size(), hipMemcpyHostToDevice, s));
+    // the host copy may be rewritten by the next call before this copy runs
+    TSK_HIP(hipStreamSynchronize(s));
     return TSK_OK;
 }
 

@@ -167,6 +167,10 @@ __global__ __launch_bounds__(kBT) void k_dot(const KryDesc* __restrict__ Dv, int
     using A = typename ET<TS>::A;
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active || int(blockIdx.x) >= d.nblk) return;
+    if (!from_x0) {
+        p += d.poff;  // the instance's own order (batched restart phase)
+        if (p > d.ldh - 1) return;
+    }
     __shared__ A wl[kChunk];
     __shared__ double red[kBT / kWave];
     const TS* w = static_cast<const TS*>(from_x0 ? d.x0 : d.w);
@@ -294,6 +298,9 @@ template <typename TS>
 __global__ __launch_bounds__(kBT) void k_reduce_coefs(const KryDesc* __restrict__ Dv, int p, int j, int pass) {
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active) return;
+    p += d.poff;
+    j += d.poff;
+    if (j >= d.ldh - 1) return;
     constexpr int NW = kBT / kWave;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     // block b, wave w: coefficients b * NW * kDotU + w + NW u
@@ -315,6 +322,9 @@ __global__ __launch_bounds__(kBT) void k_cgs_pass(const KryDesc* __restrict__ Dv
     using A = typename ET<TS>::A;
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active || int(blockIdx.x) >= d.nblk) return;
+    p += d.poff;
+    j += d.poff;
+    if (j >= d.ldh - 1) return;
     __shared__ A wl[kChunk];
     __shared__ double2 hl[kMaxKrylov + 1];
     __shared__ double red[kBT / kWave];
@@ -376,6 +386,8 @@ template <typename TS>
 __global__ __launch_bounds__(kBT) void k_scale_final(const KryDesc* __restrict__ Dv, int j) {
     const KryDesc& d = Dv[blockIdx.y];
     if (!d.active) return;
+    j += d.poff;
+    if (j >= d.ldh - 1) return;
     finalize_scale<TS>(d, j, int(blockIdx.x), int(gridDim.x));
 }
 
@@ -506,12 +518,13 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s) {
 
 template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
-                     hipStream_t s) {
+                     hipStream_t s, int pextra) {
     const bool pre = nblk_max > kFuseFinalMaxBlocks;  // long states: one reduction launch first
     if (pre) {
+        // pextra: the largest step offset of the batch (its instances reduce up to p + pextra coefficients)
         constexpr int per_block = (kBT / kWave) * kDotU;
-        hipLaunchKernelGGL(k_reduce_coefs<TS>, dim3((p + per_block - 1) / per_block, count), dim3(kBT), 0, s, D, p,
-                           j, pass);
+        hipLaunchKernelGGL(k_reduce_coefs<TS>, dim3((p + pextra + per_block - 1) / per_block, count), dim3(kBT), 0,
+                           s, D, p, j, pass);
     }
     hipLaunchKernelGGL(k_cgs_pass<TS>, dim3(nblk_max, count), dim3(kBT), 0, s, D, p, j, pass, fuse_final ? 1 : 0,
                        pre ? 1 : 0);
@@ -548,7 +561,7 @@ template void launch_rotate<float>(const void*, void*, const double*, int64_t, i
     template void launch_check_finite<TS>(const KryDesc*, int, int64_t, hipStream_t);               \
     template void launch_dot<TS>(const KryDesc*, int, int, int, bool, hipStream_t);                  \
     template void launch_scale<TS>(const KryDesc*, int, int64_t, int, hipStream_t);                  \
-    template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, bool, hipStream_t);    \
+    template void launch_cgs_pass<TS>(const KryDesc*, int, int, int, int, int, bool, hipStream_t, int); \
     template void launch_scale_final<TS>(const KryDesc*, int, int64_t, int, hipStream_t);             \
     template void launch_ritz_vectors<TS>(const KryDesc*, int, int64_t, int, hipStream_t);
 TSK_INST(double)

@@ -67,7 +67,10 @@ struct KryDesc {
     double* ksW;        // m x p orthonormal rotation of the basis, column-major (ld m)
     double ks_delta;    // wanted when |mu| >= 1 - ks_delta
     int ks_pmax;        // largest order kept
-    int ks_pad;
+    // step offset of the batched restart phase: an instance at order p_i expands
+    // in lockstep with the others, its own step being the batch step + poff
+    // (0 in ordinary runs); steps at or beyond order m = ldh - 1 are skipped
+    int poff;
 };
 
 __host__ __device__ inline int* cgs_counter(const KryDesc& d) { return reinterpret_cast<int*>(d.scal + 34); }
@@ -89,7 +92,7 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s);
 constexpr int kFuseFinalMaxBlocks = 64;
 template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
-                     hipStream_t s);
+                     hipStream_t s, int pextra = 0);
 template <typename TS>
 void launch_scale_final(const KryDesc* D, int count, int64_t nmax, int j, hipStream_t s);
 // V_{j+1} = w64 / beta (j >= 0), or V_0 = x0 / ||x0|| (j < 0).

@@ -65,6 +65,7 @@ struct ArnoldiWork {
     DevBuf tmp;       // Lanczos on M^dagger M: the forward integration's output
     DevBuf V2;        // Krylov-Schur: second basis buffer (truncation writes here)
     DevBuf ksW;       // Krylov-Schur: m x p basis rotation (FP64)
+    DevBuf ks_desc;   // batched restart phase: descriptor table of the restarting instances
     void* Vcur = nullptr;  // basis of the last run (V or V2)
     int m = 0, steps = 0;
     int64_t ldv = 0;
@@ -180,6 +181,9 @@ using KolmoBatchPtr = std::unique_ptr<KolmoBatch, KolmoBatchDeleter>;
 tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* D_host, const KryDesc* D_dev,
                             KolmoBatchPtr* out);
 tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s);
+// Batched restart phase: instance i's matvec input becomes xbase[i] + j ldv, and
+// steps j >= jmax[i] skip it.
+tsk_status kolmo_batch_set_inputs(KolmoBatch* b, const void* const* xbase, const int* jmax, hipStream_t s);
 
 // Ginzburg-Landau batches of one node count: the integrations of all instances
 // (propagators or resolvents; with svd, the forward then the adjoint pass) in
@@ -201,9 +205,17 @@ tsk_status cgle_batch_matvec(CgleBatch* b, int j, hipStream_t s);
 // global failure; per-instance outcomes are in infos[i].status.
 // svd = true: Lanczos on M^dagger M instead (every operator needs an adjoint);
 // mu_ri then receives (sigma^2, 0).
+// Batched restart phase (tsk_batch_krylov_schur): instances not converged at
+// order m contract (Krylov-Schur, real states) and expand again in lockstep.
+struct BatchRestart {
+    double delta;      // wanted when |mu| >= 1 - delta
+    int pmax;          // largest order kept
+    int max_restarts;  // contractions per instance
+    tsk_ks_info* infos;  // per instance (n_matvec, n_restarts, kept_last, ...)
+};
 tsk_status arnoldi_batch(Operator* const* ops, int count, int m, int k, double tol, const void* const* v0s,
                          const uint64_t* seeds, double* mu_ri, double* lam_ri, double* resid, void* const* ritz,
-                         tsk_arnoldi_info* infos, bool svd = false);
+                         tsk_arnoldi_info* infos, bool svd = false, const BatchRestart* rs = nullptr);
 
 // Krylov-Schur driver (arnoldi.hip): one real operator; arguments as tsk_krylov_schur.
 tsk_status krylov_schur(Operator* op, int m, int k, double tol, double delta, int pmax, int max_restarts,
@@ -242,10 +254,12 @@ tsk_status ritz_steps_launch(const StepSet& ss, int n, int count, int k, double 
 tsk_status tridiag_ritz_launch(const KryDesc* D, int count, int p, int k, double tol, hipStream_t s);
 tsk_status tridiag_ritz_launch_steps(const StepSet& ss, int n, int count, int pmax, int k, double tol,
                                      hipStream_t s);
-// Krylov-Schur analysis and contraction of the order-m factorisation of the
-// single instance D[0] (real H): contract = 0 analysis only, 1 unless the stop
-// test is met, 2 always.  Results in D[0].rr (kept, beta), H and ksW.
-tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s);
+// Krylov-Schur analysis and contraction of the order-m factorisations of the
+// `count` instances D[0..count) (real H), one wavefront each: contract = 0
+// analysis only, 1 unless the stop test is met, 2 always.  Results in D[i].rr
+// (kept, beta), H and ksW.
+tsk_status ks_contract_launch(const KryDesc* D, int m, int k, double tol, int contract, hipStream_t s,
+                              int count = 1);
 // Unit Ritz coordinates of the wanted pairs (inverse iteration on H_p): Y[s*p + r].
 // Needs the attribute set by a prior hess_ritz_launch.
 tsk_status ritz_coords_launch(const KryDesc* D, int count, int pmax, int k, hipStream_t s);  // p = steps

@@ -87,6 +87,8 @@ def load():
         "tsk_boostconv": [vp, vp, i32, f64, i32, P(f64), P(FpInfo)],
         "tsk_optimal_perturbation": [vp, i32, i32, f64, vp, u64, P(f64), P(f64), vp, P(ArnoldiInfo)],
         "tsk_krylov_schur": [vp, i32, i32, f64, f64, i32, i32, vp, u64, P(f64), P(f64), P(f64), vp, P(KsInfo)],
+        "tsk_batch_krylov_schur": [P(vp), i32, i32, i32, f64, f64, i32, i32, P(vp), P(u64), P(f64), P(f64), P(f64),
+                                   P(vp), P(KsInfo)],
         "tsk_ks_contract": [vp, i32, i32, f64, i32, f64, i32, vp, vp, vp, vp, P(i32), P(f64), vp],
         "tsk_last_hessenberg": [vp, P(f64), P(i32), P(i32)],
         "tsk_last_basis": [vp, P(vp), P(i64)],
@@ -127,7 +129,7 @@ def exported_symbols():
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
             "tsk_get_tuning", "tsk_set_stop_rule", "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
-            "tsk_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
+            "tsk_krylov_schur", "tsk_batch_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
             "tsk_set_resolvent", "tsk_batch_optimal_perturbation",
             "tsk_set_nonlinear", "tsk_laminar_state", "tsk_nonlinear_step", "tsk_set_base_from_state", "tsk_sfd",
             "tsk_rpm", "tsk_boostconv",
@@ -505,6 +507,48 @@ def krylov_schur(op, m, k, tol, delta=0.1, p_max=0, max_restarts=50, v0=None, se
                ms_apply=info.ms_apply)
     if X is not None:
         out["X"] = X[:nr]
+    return out
+
+
+def batch_krylov_schur(ops, m, k, tol, delta=0.1, p_max=0, max_restarts=50, v0s=None, seeds=None,
+                       want_vectors=False):
+    """Run tsk_batch_krylov_schur on a list of real operators (same state type
+    and stream).  Returns a list of dicts like ``krylov_schur`` (X when
+    want_vectors)."""
+    import numpy as np
+    count = len(ops)
+    if v0s is not None:
+        for op, v in zip(ops, v0s):
+            if v is not None:
+                _need(v, op.n, op.state_dtype, "v0")
+    hs = (C.c_void_p * count)(*[op.h for op in ops])
+    v0p = None
+    if v0s is not None:
+        v0p = (C.c_void_p * count)(*[(v.data_ptr() if v is not None else None) for v in v0s])
+    sp = None
+    if seeds is not None:
+        sp = (C.c_uint64 * count)(*[int(x) for x in seeds])
+    mu = np.zeros(2 * k * count)
+    lam = np.zeros(2 * k * count)
+    res = np.zeros(k * count)
+    Xs = [torch.zeros((k, op.n), dtype=torch.complex128, device="cuda") for op in ops] if want_vectors else None
+    rp = (C.c_void_p * count)(*[x.data_ptr() for x in Xs]) if Xs else None
+    infos = (KsInfo * count)()
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    _check(load().tsk_batch_krylov_schur(hs, count, m, k, tol, delta, p_max, max_restarts, v0p, sp, pd(mu), pd(lam),
+                                         pd(res), rp, infos))
+    out = []
+    for i in range(count):
+        f = infos[i]
+        nr = f.n_ritz
+        o = dict(mu=(mu[2 * k * i:2 * k * (i + 1):2] + 1j * mu[2 * k * i + 1:2 * k * (i + 1):2])[:nr],
+                 lam=(lam[2 * k * i:2 * k * (i + 1):2] + 1j * lam[2 * k * i + 1:2 * k * (i + 1):2])[:nr],
+                 res=res[k * i:k * (i + 1)][:nr], status=f.status, n_matvec=f.n_matvec, n_restarts=f.n_restarts,
+                 kept_last=f.kept_last, n_ritz=nr, n_converged=f.n_converged, beta=f.beta, ms_total=f.ms_total,
+                 ms_apply=f.ms_apply)
+        if Xs:
+            o["X"] = Xs[i][:nr]
+        out.append(o)
     return out
 
 

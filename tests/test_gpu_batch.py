@@ -135,17 +135,73 @@ def test_batch_rejects_mixed_precision_and_duplicates(tsk):
     assert e.value.status == tsk.TSK_EINVAL
 
 
+def _galerkin_top(N, alpha, Re, count):
+    """The `count` leading distinct eigenvalues (by real part) of the dense
+    Galerkin blocks of the linearized Kolmogorov operator."""
+    blocks = galerkin_sinusoidal_blocks(N, alpha, Re)
+    ev = np.concatenate([np.linalg.eigvals(A) for _, A in blocks.values()])
+    ev = ev[np.argsort(-ev.real)]
+    out = []
+    for z in ev:
+        if all(abs(z - w) > 1e-9 for w in out):
+            out.append(z)
+        if len(out) == count:
+            break
+    return np.array(out)
+
+
 def test_neutral_curve_sweep_full_size(tsk):
-    # 64 instances (24 x 128^2, 20 x 256^2, 20 x 384^2), FP32, m = 64, k = 4.
-    print("batch sweep 64 instances", flush=True)
+    # 64 instances (24 x 128^2, 20 x 256^2, 20 x 384^2), FP32, m = 64, k = 4, all
+    # converged: the instances not converged at order m restart (Krylov-Schur)
+    print("batch sweep 64 instances, batched Krylov-Schur", flush=True)
     sweep = W.batch_sweep(64, 0)
     ops = [_kolmo(tsk, c["N"], c["Re"], c["alpha"], 1) for c in sweep]
-    rb = tsk.batch_arnoldi(ops, 64, 4, 1e-8, seeds=list(range(64)))
-    assert all(b["status"] >= 0 for b in rb)
-    # leading eigenvalue of a sample of instances against dense Galerkin blocks
-    for i in (0, 1, 5, 10, 30, 63):
-        c = sweep[i]
-        blocks = galerkin_sinusoidal_blocks(c["N"], c["alpha"], c["Re"])
-        lead = max(np.max(np.linalg.eigvals(A).real) for _, A in blocks.values())
-        got = np.max(rb[i]["lam"].real)
-        assert abs(got - lead) <= 2e-5, (i, got, lead)
+    rb = tsk.batch_krylov_schur(ops, 64, 4, 1e-8, delta=0.1, seeds=list(range(64)))
+    assert [b["status"] for b in rb] == [0] * 64
+    assert any(b["n_restarts"] > 0 for b in rb)
+    # the leading Galerkin eigenvalues are converged in the grid: at 384^2 they equal
+    # the 128^2 ones to rounding, so every instance is checked against its 128^2 blocks
+    c9 = sweep[9]
+    assert np.max(np.abs(_galerkin_top(384, c9["alpha"], c9["Re"], 6) -
+                         _galerkin_top(128, c9["alpha"], c9["Re"], 6))) <= 1e-10
+    for i, (c, b) in enumerate(zip(sweep, rb)):
+        top = _galerkin_top(128, c["alpha"], c["Re"], 8)
+        assert b["n_ritz"] == 4
+        # every returned value is an eigenvalue, and the four are the leading four
+        # (FP32 form, stated bound 2e-5) whenever the fourth is separated from the fifth
+        for lam in b["lam"]:
+            assert np.min(np.abs(top - lam)) <= 2e-5, (i, lam)
+        if top[3].real - top[4].real > 1e-4:
+            assert match_sets(b["lam"], top[:4]) <= 2e-5, (i, b["lam"], top[:4])
+        if b["n_restarts"] > 0:
+            assert b["n_matvec"] > 64
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_krylov_schur_restarts_small(tsk, prec):
+    # m small enough that most instances restart: FP64 every returned value is a
+    # Galerkin eigenvalue to 1e-8 with residual <= tol; instances that converge
+    # before order m equal the plain batched Arnoldi run bitwise
+    print(f"batched krylov-schur small prec={prec}", flush=True)
+    cfg = [(32, 20.0, 0.5), (48, 12.0, 0.75), (48, 30.0, 0.25), (64, 25.0, 1.0), (32, 8.0, 0.25)]
+    m, k = 14, 4
+    ops = [_kolmo(tsk, N, Re, a, prec) for N, Re, a in cfg]
+    v0s = [_start(tsk, op, N, 30 + i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
+    rk = tsk.batch_krylov_schur(ops, m, k, 1e-8, delta=0.1, v0s=v0s, want_vectors=True)
+    ra = tsk.batch_arnoldi(ops, m, k, 1e-8, v0s=v0s, want_vectors=True)
+    bar = 1e-8 if prec == 0 else 2e-5
+    assert any(b["n_restarts"] > 0 for b in rk)
+    for (N, Re, a), b, a_ in zip(cfg, rk, ra):
+        assert b["status"] == 0
+        assert np.all(b["res"] <= (1e-8 if prec == 0 else max(1e-8, 32 * 2.0 ** -24 * 2.0)))
+        top = _galerkin_top(N, a, Re, 12)
+        for lam in b["lam"]:
+            assert np.min(np.abs(top - lam)) <= bar, (N, Re, a, lam)
+        if a_["status"] == 0:
+            assert b["n_restarts"] == 0 and b["n_matvec"] == a_["n_matvec"]
+            assert np.array_equal(b["lam"], a_["lam"]) and torch.equal(b["X"], a_["X"])
+        else:
+            assert b["n_restarts"] >= 1 and b["n_matvec"] > m
+            # Ritz vectors of the restarted instances: unit norm
+            nrm = torch.linalg.norm(b["X"], dim=1).cpu().numpy()
+            assert np.all(np.abs(nrm - 1.0) <= 1e-6)

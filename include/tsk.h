@@ -138,6 +138,17 @@ tsk_status tsk_set_base_flow(tsk_op op, const double* U, const double* V,
 tsk_status tsk_set_tuning(tsk_op op, int columns_per_wave);
 tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave);
 
+/* Launch shape of the spectral-coupling stepper: 64-lane wavefronts per
+ * workgroup (1, 2 or 4; one chain per wavefront in every shape, so the results
+ * are the same bits).  0 (the default) lets the library time the three shapes
+ * on the first launch of a given precision, chain layout and launch size (a
+ * single matvec, or a batch's shared launch) and keep the fastest for the
+ * process.  tsk_get_stepper_waves reports the forced shape, else the shape of
+ * the operator's last single matvec (0 before the first).  Navier-Stokes
+ * operators only; TSK_EINVAL for other values. */
+tsk_status tsk_set_stepper_waves(tsk_op op, int waves_per_group);
+tsk_status tsk_get_stepper_waves(tsk_op op, int* waves_per_group);
+
 /* Stop rule of the Arnoldi stop test (Sec. 3.2.2, eq. "Krylov convergence":
  * a Ritz pair is converged when |beta e_m^T y| <= tol), per operator, for
  * tsk_arnoldi, tsk_batch_arnoldi and tsk_krylov_schur:

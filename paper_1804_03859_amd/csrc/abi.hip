@@ -147,6 +147,21 @@ tsk_status tsk_get_tuning(tsk_op op, int* columns_per_wave) {
     })
 }
 
+tsk_status tsk_set_stepper_waves(tsk_op op, int waves_per_group) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        return kolmo_set_stepper_waves(op->op.get(), waves_per_group);
+    })
+}
+
+tsk_status tsk_get_stepper_waves(tsk_op op, int* waves_per_group) {
+    TSK_GUARD({
+        TSK_NEED(op);
+        if (!waves_per_group) return fail(TSK_EINVAL, "null argument");
+        return kolmo_get_stepper_waves(op->op.get(), waves_per_group);
+    })
+}
+
 tsk_status tsk_set_stop_rule(tsk_op op, double res_floor_rel, double dup_rel) {
     TSK_GUARD({
         TSK_NEED(op);

@@ -598,21 +598,50 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             TSK_HIP(hipMemcpyAsync(DRd, DR.data(), nr2 * sizeof(KryDesc), hipMemcpyHostToDevice, s));
             if (kb) TSK_TRY(kolmo_batch_set_inputs(kb.get(), xb.data(), jm.data(), s));
             const int G = m - pmin;
-            for (int g = 0; g < G; ++g) {
-                TSK_HIP(hipEventRecord(L.ev_apply[2 * g], s));
-                if (kb) {
-                    TSK_TRY(kolmo_batch_matvec(kb.get(), g, s));
-                } else {
-                    for (int q = 0; q < nr2; ++q) {
-                        const int i = R[q];
-                        if (g < jm[i]) TSK_TRY(ops[i]->apply(static_cast<const TS*>(xb[i]) + size_t(g) * ops[i]->aw.ldv,
-                                                             DR[q].w));
+            // the whole expansion of the cycle (G lockstep steps of matvec and
+            // Gram-Schmidt, the offsets fixed for the cycle) of a batch with one
+            // matvec launch per step is one graph, captured on the idle worker
+            // stream 0 and launched once on the operator's stream; other batches
+            // (matvec groups forked to worker streams, or the operators' own matvecs
+            // on their streams) launch directly
+            auto expand = [&](hipStream_t es) -> tsk_status {
+                for (int g = 0; g < G; ++g) {
+                    TSK_HIP(hipEventRecord(L.ev_apply[2 * g], es));
+                    if (kb) {
+                        TSK_TRY(kolmo_batch_matvec(kb.get(), g, es));
+                    } else {
+                        for (int q = 0; q < nr2; ++q) {
+                            const int i = R[q];
+                            if (g < jm[i])
+                                TSK_TRY(ops[i]->apply(static_cast<const TS*>(xb[i]) + size_t(g) * ops[i]->aw.ldv,
+                                                      DR[q].w));
+                        }
                     }
+                    TSK_HIP(hipEventRecord(L.ev_apply[2 * g + 1], es));
+                    cgs2_step<TS>(DRd, nr2, nblk_max_r, nmax_r, g, es, pext);
                 }
-                TSK_HIP(hipEventRecord(L.ev_apply[2 * g + 1], s));
-                cgs2_step<TS>(DRd, nr2, nblk_max_r, nmax_r, g, s, pext);
+                return TSK_OK;
+            };
+            if (kb && kolmo_batch_groups(kb.get()) <= 1) {
+                const hipStream_t cs = L.side[0];
+                TSK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                const tsk_status est = expand(cs);
+                hipGraph_t graph = nullptr;
+                const hipError_t ce = hipStreamEndCapture(cs, &graph);
+                TSK_TRY(est);
+                TSK_HIP(ce);
+                hipGraphExec_t exec = nullptr;
+                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                const hipError_t le = ie == hipSuccess ? hipGraphLaunch(exec, s) : ie;
+                const hipError_t se = hipStreamSynchronize(s);
+                if (exec) (void)hipGraphExecDestroy(exec);
+                (void)hipGraphDestroy(graph);
+                TSK_HIP(le);
+                TSK_HIP(se);
+            } else {
+                TSK_TRY(expand(s));
+                TSK_HIP(hipStreamSynchronize(s));
             }
-            TSK_HIP(hipStreamSynchronize(s));
             for (int g = 0; g < G; ++g) {
                 float ms = 0.0f;
                 TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * g], L.ev_apply[2 * g + 1]));

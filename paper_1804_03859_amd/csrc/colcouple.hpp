@@ -49,28 +49,33 @@ template <int CTRL> __device__ inline double wave_move(double v) {
 // nh chains of every column kx = 1..M.
 __host__ __device__ inline int couple_blocks(int M, int nh) { return 1 + nh * M; }
 
-// Grid x: at least couple_blocks(M, nh) of the largest instance (blocks beyond an
-// instance's own count return at once).  Grid y: the instance, insts[ids[y]] of a
-// batch (input of Arnoldi step jstep: xbase + jstep xstride; finished instances
-// skip), or `one` when insts is null.  S: positions per lane (chains of up to
-// 64 S modes).  Lawson RK4 as the other column steppers.
-template <typename real, int S>
-__global__ __launch_bounds__(kWave) void k_colstep_couple(ColInst<real> one, const ColInst<real>* __restrict__ insts,
-                                                          const int* __restrict__ ids, int jstep) {
+// Wavefront w of the grid (w = blockIdx.x WPW + wave in the workgroup) takes
+// chain slot w: at least couple_blocks(M, nh) of the largest instance (slots
+// beyond an instance's own count return at once).  WPW: wavefronts per
+// workgroup (the launch shape the library tunes; every wavefront computes its
+// chain alone, so the results do not depend on it).  Grid y: the instance,
+// insts[ids[y]] of a batch (input of Arnoldi step jstep: xbase + jstep xstride;
+// finished instances skip), or `one` when insts is null.  S: positions per lane
+// (chains of up to 64 S modes).  Lawson RK4 as the other column steppers.
+template <typename real, int S, int WPW>
+__global__ __launch_bounds__(kWave * WPW) void k_colstep_couple(ColInst<real> one,
+                                                                const ColInst<real>* __restrict__ insts,
+                                                                const int* __restrict__ ids, int jstep) {
     static_assert(S == 1 || S == 2, "positions per lane");
     using C = cplx<real>;
     stepper_wave_priority();
     const ColInst<real>& I = insts ? insts[ids[blockIdx.y]] : one;
     if ((I.active && *I.active == 0) || jstep >= I.jmax) return;
     const int M = I.M, nh = I.nh;
-    if (int(blockIdx.x) >= couple_blocks(M, nh)) return;
-    const int lane = threadIdx.x;
+    const int slot = int(blockIdx.x) * WPW + (WPW == 1 ? 0 : int(threadIdx.x) / kWave);
+    if (slot >= couple_blocks(M, nh)) return;
+    const int lane = int(threadIdx.x) % kWave;
     const real* __restrict__ xin = I.xbase + jstep * I.xstride;
     real* __restrict__ yout = I.y;
     const double alpha = I.alpha, Re = I.Re, dt = I.dt, cprop = I.cprop;
     const int nsteps = I.nsteps;
     const int NM = 2 * M + 1;
-    if (blockIdx.x == 0) {
+    if (slot == 0) {
         // kx = 0: the advection term vanishes (d/dx of a y-only field)
         for (int q = lane; q < M; q += kWave) {
             const double jy = q + 1;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kWave) void k_colstep_couple(ColInst<real> one, con
         }
         return;
     }
-    const int b = int(blockIdx.x) - 1;
+    const int b = slot - 1;
     const int kx = 1 + b / nh, c = b % nh;
     const double kxv = alpha * kx;
     // first kept ky of the chain (ky = c mod nh) and its length

@@ -366,13 +366,81 @@ void launch_bloch_stepper(int N, const ColInst<real>& one, const ColInst<real>* 
 // Spectral-coupling stepper launch (colcouple.hpp): `n` instances (grid y),
 // insts[ids[.]] of a batch at Arnoldi step jstep, or `one` (insts null, n = 1);
 // blocks = couple_blocks of the largest instance, S positions per lane.
+template <typename real, int S>
+void launch_couple_shape(const ColInst<real>& one, const ColInst<real>* insts, const int* ids, int n, int jstep,
+                         int blocks, int wpw, hipStream_t s) {
+    const dim3 grid((blocks + wpw - 1) / wpw, n);
+    if (wpw == 1)
+        hipLaunchKernelGGL((k_colstep_couple<real, S, 1>), grid, dim3(kWave), 0, s, one, insts, ids, jstep);
+    else if (wpw == 2)
+        hipLaunchKernelGGL((k_colstep_couple<real, S, 2>), grid, dim3(2 * kWave), 0, s, one, insts, ids, jstep);
+    else
+        hipLaunchKernelGGL((k_colstep_couple<real, S, 4>), grid, dim3(4 * kWave), 0, s, one, insts, ids, jstep);
+}
 template <typename real>
 void launch_couple_stepper(const ColInst<real>& one, const ColInst<real>* insts, const int* ids, int n, int jstep,
-                           int blocks, int S, hipStream_t s) {
+                           int blocks, int S, int wpw, hipStream_t s) {
     if (S == 1)
-        hipLaunchKernelGGL((k_colstep_couple<real, 1>), dim3(blocks, n), dim3(kWave), 0, s, one, insts, ids, jstep);
+        launch_couple_shape<real, 1>(one, insts, ids, n, jstep, blocks, wpw, s);
     else
-        hipLaunchKernelGGL((k_colstep_couple<real, 2>), dim3(blocks, n), dim3(kWave), 0, s, one, insts, ids, jstep);
+        launch_couple_shape<real, 2>(one, insts, ids, n, jstep, blocks, wpw, s);
+}
+
+// Launch shape of the coupling stepper (wavefronts per workgroup: 1, 2 or 4),
+// timed once per (precision, positions per lane, launch size) and process on
+// the first real launch, like the column variants; the shapes compute the same
+// bits, so the choice never changes results.
+struct CoupleKey {
+    bool fp32;
+    int S, size;
+    bool operator<(const CoupleKey& o) const {
+        return std::tie(fp32, S, size) < std::tie(o.fp32, o.S, o.size);
+    }
+};
+std::mutex g_couple_mu;
+std::map<CoupleKey, int> g_couple;
+
+int wave_bucket(int waves) {
+    int b = 1;
+    while (b < waves) b *= 2;
+    return b;
+}
+
+template <typename F>
+tsk_status couple_choice(const CoupleKey& key, hipStream_t s, F&& launch, int* out) {
+    {
+        std::lock_guard<std::mutex> lk(g_couple_mu);
+        auto it = g_couple.find(key);
+        if (it != g_couple.end()) {
+            *out = it->second;
+            return TSK_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    TSK_HIP(hipEventCreate(&e0));
+    TSK_HIP(hipEventCreate(&e1));
+    float best = 0.0f;
+    int bw = 1;
+    for (int w : {1, 2, 4}) {
+        launch(w);
+        TSK_HIP(hipEventRecord(e0, s));
+        launch(w);
+        TSK_HIP(hipEventRecord(e1, s));
+        TSK_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        TSK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (w == 1 || ms < best) {
+            best = ms;
+            bw = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TSK_HIP(hipGetLastError());
+    *out = bw;
+    std::lock_guard<std::mutex> lk(g_couple_mu);
+    g_couple[key] = bw;
+    return TSK_OK;
 }
 
 // Positions per lane of the coupling stepper for cutoff M and harmonic nh: the
@@ -395,6 +463,8 @@ struct KolmoOp final : Operator {
     DevBuf tasks[3];   // single-instance task lists for 1 and 2 columns per wavefront
     int ntasks[3] = {0, 0, 0};
     int force_cols = 0;  // 0: automatic choice; 1, 2: column stepper; 3: Bloch-sector stepper
+    int force_wpw = 0;   // coupling stepper's wavefronts per workgroup: 0 tuned, else 1, 2 or 4
+    int tuned_wpw = 0;   // the tuned (or forced) shape of the last launch
     Gen2D* gen = nullptr;  // general two-dimensional base flow (kolmo2d.hip), else parallel
     // nonlinear forced equation (fixed-point solvers): pipeline workspace, packed
     // forcing and laminar state, drift, and the inputs the forcing is made from
@@ -482,11 +552,18 @@ struct KolmoOp final : Operator {
         if (gen) return gen2d_apply(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
         if (use_couple()) {
             const int S = couple_slots(M, nh), blocks = couple_blocks(M, nh);
-            if (prec == TSK_FP32)
-                launch_couple_stepper<float>(inst<float>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S, stream);
-            else
-                launch_couple_stepper<double>(inst<double>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S,
-                                              stream);
+            auto launch = [&](int w) {
+                if (prec == TSK_FP32)
+                    launch_couple_stepper<float>(inst<float>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S, w,
+                                                 stream);
+                else
+                    launch_couple_stepper<double>(inst<double>(x, 0, y, nullptr), nullptr, nullptr, 1, 0, blocks, S, w,
+                                                  stream);
+            };
+            int w = force_wpw;
+            if (w == 0) TSK_TRY(couple_choice(CoupleKey{prec == TSK_FP32, S, wave_bucket(blocks)}, stream, launch, &w));
+            tuned_wpw = w;
+            launch(w);
             TSK_HIP(hipGetLastError());
             return TSK_OK;
         }
@@ -818,6 +895,22 @@ tsk_status kolmo_get_tuning(const Operator* op, int* cols) {
     return TSK_OK;
 }
 
+tsk_status kolmo_set_stepper_waves(Operator* op, int w) {
+    auto* k = dynamic_cast<KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    if (w != 0 && w != 1 && w != 2 && w != 4)
+        return fail(TSK_EINVAL, "wavefronts per workgroup must be 0 (tuned), 1, 2 or 4");
+    k->force_wpw = w;
+    return TSK_OK;
+}
+
+tsk_status kolmo_get_stepper_waves(const Operator* op, int* w) {
+    const auto* k = dynamic_cast<const KolmoOp*>(op);
+    if (!k) return fail(TSK_EINVAL, "not a Navier-Stokes operator");
+    *w = k->force_wpw ? k->force_wpw : k->tuned_wpw;
+    return TSK_OK;
+}
+
 bool kolmo_parallel(const Operator* op) {
     const auto* k = dynamic_cast<const KolmoOp*>(op);
     return k && !k->gen;
@@ -855,6 +948,7 @@ struct KolmoBatch {
         bool bloch = false;
         bool couple = false;  // spectral-coupling stepper: instances of every N in one launch
         int cblocks = 0, cslots = 1;  // its grid x (largest instance) and positions per lane
+        int cwpw = 1;                 // its launch shape (wavefronts per workgroup, tuned)
         DevBuf ids;  // Bloch and coupling groups: instance indices
         int nids = 0;
         const void* tw;
@@ -931,6 +1025,8 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
         if (kc) {
             g->cblocks = std::max(g->cblocks, couple_blocks(ko[i]->M, ko[i]->nh));
             g->cslots = std::max(g->cslots, couple_slots(ko[i]->M, ko[i]->nh));
+            if (ko[i]->force_wpw) g->cwpw = ko[i]->force_wpw;
+            g->force = g->force ? g->force : ko[i]->force_wpw;
         }
     }
     for (size_t q = 0; q < b->groups.size(); ++q) {
@@ -957,7 +1053,25 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
     if (b->groups.size() > 1) TSK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     const hipStream_t s = ops[0]->stream;
     for (auto& g : b->groups) {
-        if (g->bloch || g->couple) continue;  // no column tasks, nothing to tune
+        if (g->couple) {
+            // the launch shape: forced by an instance of the group, else timed on the
+            // step-0 inputs (the outputs are overwritten by the first real matvec)
+            if (g->force) continue;
+            KolmoBatch::Group* gp = g.get();
+            KolmoBatch* bp = b.get();
+            auto launch = [&](int w) {
+                if (bp->fp32)
+                    launch_couple_stepper<float>(ColInst<float>{}, bp->insts.as<ColInst<float>>(), gp->ids.as<int>(),
+                                                 gp->nids, 0, gp->cblocks, gp->cslots, w, s);
+                else
+                    launch_couple_stepper<double>(ColInst<double>{}, bp->insts.as<ColInst<double>>(),
+                                                  gp->ids.as<int>(), gp->nids, 0, gp->cblocks, gp->cslots, w, s);
+            };
+            TSK_TRY(couple_choice(CoupleKey{b->fp32, g->cslots, wave_bucket(g->cblocks * g->nids)}, s, launch,
+                                  &g->cwpw));
+            continue;
+        }
+        if (g->bloch) continue;  // no column tasks, nothing to tune
         for (int c = 1; c <= max_cols(g->N); ++c) {
             std::vector<ColTask> tk;
             for (int i = 0; i < count; ++i)
@@ -1000,10 +1114,10 @@ tsk_status kolmo_batch_matvec(KolmoBatch* b, int j, hipStream_t s) {
         if (g->couple) {
             if (b->fp32)
                 launch_couple_stepper<float>(ColInst<float>{}, b->insts.as<ColInst<float>>(), g->ids.as<int>(),
-                                             g->nids, j, g->cblocks, g->cslots, st);
+                                             g->nids, j, g->cblocks, g->cslots, g->cwpw, st);
             else
                 launch_couple_stepper<double>(ColInst<double>{}, b->insts.as<ColInst<double>>(), g->ids.as<int>(),
-                                              g->nids, j, g->cblocks, g->cslots, st);
+                                              g->nids, j, g->cblocks, g->cslots, g->cwpw, st);
         } else if (g->bloch) {
             if (b->fp32)
                 launch_bloch_stepper<float>(g->N, ColInst<float>{}, b->insts.as<ColInst<float>>(), g->ids.as<int>(),

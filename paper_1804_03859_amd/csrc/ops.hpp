@@ -151,6 +151,10 @@ int kolmo_nsteps(const Operator* op);
 // get reports the forced or tuned value (0 = not tuned yet).
 tsk_status kolmo_set_tuning(Operator* op, int cols);
 tsk_status kolmo_get_tuning(const Operator* op, int* cols);
+// Launch shape of the spectral-coupling stepper: wavefronts per workgroup, 0 =
+// tuned (get: the shape of the last launch, 0 before the first).
+tsk_status kolmo_set_stepper_waves(Operator* op, int w);
+tsk_status kolmo_get_stepper_waves(const Operator* op, int* w);
 // A Navier-Stokes operator whose base flow is parallel (column stepper; batchable).
 bool kolmo_parallel(const Operator* op);
 // The operator's own matvec runs the Bloch-sector stepper (colbloch.hpp).

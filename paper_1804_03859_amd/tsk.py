@@ -68,6 +68,8 @@ def load():
         "tsk_set_tuning": [vp, i32],
         "tsk_get_tuning": [vp, P(i32)],
         "tsk_set_stop_rule": [vp, f64, f64],
+        "tsk_set_stepper_waves": [vp, i32],
+        "tsk_get_stepper_waves": [vp, P(i32)],
         "tsk_from_physical": [vp, vp, vp],
         "tsk_to_physical": [vp, vp, vp],
         "tsk_apply": [vp, vp, vp],
@@ -127,7 +129,8 @@ def exported_symbols():
     """Names the binding expects the library to export (all of include/tsk.h)."""
     return ["tsk_create_cgle1d", "tsk_set_params_cgle", "tsk_create_kolmo2d", "tsk_set_params_kolmo",
             "tsk_set_base_parallel", "tsk_set_base_kolmogorov", "tsk_set_base_flow", "tsk_set_tuning",
-            "tsk_get_tuning", "tsk_set_stop_rule", "tsk_state_dim",
+            "tsk_get_tuning", "tsk_set_stop_rule", "tsk_set_stepper_waves", "tsk_get_stepper_waves",
+            "tsk_state_dim",
             "tsk_from_physical", "tsk_to_physical", "tsk_apply", "tsk_arnoldi", "tsk_batch_arnoldi",
             "tsk_krylov_schur", "tsk_batch_krylov_schur", "tsk_ks_contract", "tsk_apply_adjoint", "tsk_optimal_perturbation",
             "tsk_set_resolvent", "tsk_batch_optimal_perturbation",
@@ -248,6 +251,16 @@ def get_tuning(op):
     c = C.c_int()
     _check(load().tsk_get_tuning(op.h, C.byref(c)))
     return c.value
+
+
+def set_stepper_waves(op, waves_per_group):
+    _check(load().tsk_set_stepper_waves(op.h, int(waves_per_group)))
+
+
+def get_stepper_waves(op):
+    w = C.c_int()
+    _check(load().tsk_get_stepper_waves(op.h, C.byref(w)))
+    return w.value
 
 
 def set_stop_rule(op, res_floor_rel=-1.0, dup_rel=-1.0):

@@ -95,6 +95,39 @@ def test_coupling_stepper_batch_of_mixed_sizes_equals_single_runs_bitwise(tsk, p
         assert torch.equal(b["X"], r["X"])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coupling_stepper_launch_shapes_agree_bitwise(tsk, prec):
+    # 1, 2 or 4 wavefronts per workgroup (the tuned launch shape): the same bits,
+    # alone and in a batch; the tuned choice is one of them
+    print(f"coupling launch shapes prec={prec}", flush=True)
+    cfg = [(128, 20.0, 0.5), (384, 12.0, 0.75), (512, 30.0, 1.0)]
+    ops = [_kolmo(tsk, N, Re, a, prec) for N, Re, a in cfg]
+    for op, (N, _, _) in zip(ops, cfg):
+        x = _start(tsk, op, N, 7)
+        outs = []
+        for w in (1, 2, 4):
+            tsk.set_stepper_waves(op, w)
+            assert tsk.get_stepper_waves(op) == w
+            y = op.new_state()
+            tsk.apply(op, x, y)
+            outs.append(y)
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+        tsk.set_stepper_waves(op, 0)
+        y = op.new_state()
+        tsk.apply(op, x, y)
+        assert torch.equal(y, outs[0]) and tsk.get_stepper_waves(op) in (1, 2, 4)
+    with pytest.raises(tsk.TskError):
+        tsk.set_stepper_waves(ops[0], 3)
+    v0s = [_start(tsk, op, N, 40 + i) for i, (op, (N, _, _)) in enumerate(zip(ops, cfg))]
+    res = []
+    for w in (1, 4):
+        for op in ops:
+            tsk.set_stepper_waves(op, w)
+        res.append(tsk.batch_arnoldi(ops, 20, 2, 1e-8, v0s=v0s))
+    for a, b in zip(*res):
+        assert a["n_matvec"] == b["n_matvec"] and np.array_equal(a["lam"], b["lam"])
+
+
 def test_batch_member_matches_oracle(tsk):
     print("batch member vs oracle", flush=True)
     cfg = [(48, 20.0, 0.5), (32, 10.0, 1.0)]

@@ -331,7 +331,9 @@ tsk_status tsk_krylov_schur(tsk_op op, int m, int k, double tol, double delta, i
  * lambda_ri + 2k i, resid + k i, ritz_devs[i]) and tsk_krylov_schur (delta,
  * p_max: 0 = max(k, m/2), max_restarts); infos[i] (host array or NULL): the
  * instance's matvecs (m + (m - p) per contraction when it restarted), its
- * contractions and status.  Returns TSK_OK when every instance ended without
+ * contractions and status; ms_apply times the matvecs of the lockstep phase
+ * (the expansion of a restart cycle of one shared matvec launch per step runs as
+ * one captured HIP graph and is not timed per matvec).  Returns TSK_OK when every instance ended without
  * error (see infos[i].status), or a negative status for an argument or runtime
  * failure of the whole batch. */
 tsk_status tsk_batch_krylov_schur(const tsk_op* ops, int count, int m, int k, double tol, double delta, int p_max,

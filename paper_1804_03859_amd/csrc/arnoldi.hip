@@ -596,7 +596,21 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             DR = keepD;
             const int nr2 = int(R.size());
             TSK_HIP(hipMemcpyAsync(DRd, DR.data(), nr2 * sizeof(KryDesc), hipMemcpyHostToDevice, s));
-            if (kb) TSK_TRY(kolmo_batch_set_inputs(kb.get(), xb.data(), jm.data(), s));
+            // the matvecs of the restarting instances only: a batch plan of their own
+            // (instance q of the plan is R[q], its flags in the restart table)
+            KolmoBatchPtr kbr;
+            if (kb) {
+                std::vector<Operator*> opsR;
+                std::vector<const void*> xbr;
+                std::vector<int> jmr;
+                for (int i : R) {
+                    opsR.push_back(ops[i]);
+                    xbr.push_back(xb[i]);
+                    jmr.push_back(jm[i]);
+                }
+                TSK_TRY(kolmo_batch_plan(opsR.data(), nr2, DR.data(), DRd, &kbr));
+                TSK_TRY(kolmo_batch_set_inputs(kbr.get(), xbr.data(), jmr.data(), s));
+            }
             const int G = m - pmin;
             // the whole expansion of the cycle (G lockstep steps of matvec and
             // Gram-Schmidt, the offsets fixed for the cycle) of a batch with one
@@ -604,11 +618,13 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             // stream 0 and launched once on the operator's stream; other batches
             // (matvec groups forked to worker streams, or the operators' own matvecs
             // on their streams) launch directly
-            auto expand = [&](hipStream_t es) -> tsk_status {
+            // timed: HIP events around every matvec (direct launches only: event
+            // nodes of a captured graph do not bracket its kernel nodes)
+            auto expand = [&](hipStream_t es, bool timed) -> tsk_status {
                 for (int g = 0; g < G; ++g) {
-                    TSK_HIP(hipEventRecord(L.ev_apply[2 * g], es));
-                    if (kb) {
-                        TSK_TRY(kolmo_batch_matvec(kb.get(), g, es));
+                    if (timed) TSK_HIP(hipEventRecord(L.ev_apply[2 * g], es));
+                    if (kbr) {
+                        TSK_TRY(kolmo_batch_matvec(kbr.get(), g, es));
                     } else {
                         for (int q = 0; q < nr2; ++q) {
                             const int i = R[q];
@@ -617,15 +633,16 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
                                                       DR[q].w));
                         }
                     }
-                    TSK_HIP(hipEventRecord(L.ev_apply[2 * g + 1], es));
+                    if (timed) TSK_HIP(hipEventRecord(L.ev_apply[2 * g + 1], es));
                     cgs2_step<TS>(DRd, nr2, nblk_max_r, nmax_r, g, es, pext);
                 }
                 return TSK_OK;
             };
-            if (kb && kolmo_batch_groups(kb.get()) <= 1) {
+            const bool graphed = kbr && kolmo_batch_groups(kbr.get()) <= 1;
+            if (graphed) {
                 const hipStream_t cs = L.side[0];
                 TSK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-                const tsk_status est = expand(cs);
+                const tsk_status est = expand(cs, false);
                 hipGraph_t graph = nullptr;
                 const hipError_t ce = hipStreamEndCapture(cs, &graph);
                 TSK_TRY(est);
@@ -639,13 +656,13 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
                 TSK_HIP(le);
                 TSK_HIP(se);
             } else {
-                TSK_TRY(expand(s));
+                TSK_TRY(expand(s, true));
                 TSK_HIP(hipStreamSynchronize(s));
-            }
-            for (int g = 0; g < G; ++g) {
-                float ms = 0.0f;
-                TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * g], L.ev_apply[2 * g + 1]));
-                ms_apply += ms;
+                for (int g = 0; g < G; ++g) {
+                    float ms = 0.0f;
+                    TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * g], L.ev_apply[2 * g + 1]));
+                    ms_apply += ms;
+                }
             }
             for (KryDesc& d : DR) d.poff = 0;  // order m again: the contraction reads H_m
             ++cycle;

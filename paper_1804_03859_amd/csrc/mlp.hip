@@ -18,7 +18,9 @@
 //
 // Parameter vector layout (flat, FP32): W1 [2][W], b1 [W], W2 [W][W], b2 [W],
 // W3 [W][2048], b3 [2048], weights row-major [in][out].
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "ops.hpp"
@@ -64,41 +66,110 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64, GK = 32, GLD = GK + 8;
 
+// Split K: for products with a long K and few 64 x 64 tiles (the back-products of
+// the output layer, K = 2048, eight tiles), grid z splits K into equal slabs;
+// each workgroup stores its FP32 partial tile in a workspace and a second kernel
+// sums the slabs in a fixed order and applies the epilogue, so the result does
+// not depend on scheduling.
+struct GemmSplit {
+    float* part;  // [splits][M][N] partial products (null: no split)
+    int kslab;    // K per slab (a multiple of GK)
+};
+
+template <int EPI>
+__device__ inline void gemm_epilogue(const GemmArgs& g, int row, int col, float v) {
+    const size_t o = size_t(row) * g.ldc + col;
+    if constexpr (EPI == EPI_BIAS) v += g.bias[col];
+    if constexpr (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[col]);
+    if constexpr (EPI == EPI_DTANH) {
+        const float a = g.act[o];
+        v = v * (1.0f - a * a);
+    }
+    g.C[o] = v;
+    if constexpr (EPI == EPI_BIAS_TANH || EPI == EPI_DTANH)
+        if (g.Ch) g.Ch[o] = f2bf(v);
+}
+
+// Operands whose k index is contiguous (A with TA = false, B with TB = true) are
+// read as 16-byte vectors of 8 bfloat16 (one per thread per K slice); the others
+// element by element.  The next slice's global loads are issued before the
+// current slice's products, so they overlap.
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, GemmSplit sp) {
     __shared__ __align__(16) uint16_t As[GT * GLD];
     __shared__ __align__(16) uint16_t Bs[GT * GLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kbeg = sp.part ? int(blockIdx.z) * sp.kslab : 0;
+    const int kend = sp.part ? min(g.K, kbeg + sp.kslab) : g.K;
+    // 16-byte loads need 16-byte aligned rows (k0 is a multiple of 8)
+    const bool avec = ((reinterpret_cast<uintptr_t>(g.A) | (uintptr_t(g.lda) * 2)) & 15) == 0;
+    const bool bvec = ((reinterpret_cast<uintptr_t>(g.B) | (uintptr_t(g.ldb) * 2)) & 15) == 0;
     v4f acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
+    // staging registers of one K slice
+    typedef unsigned short v8u __attribute__((ext_vector_type(8)));
+    v8u av{}, bv{};
+    uint16_t as8[8], bs8[8];
+    auto load = [&](int k0) {
+        if constexpr (!TA) {
+            // A[m][k]: thread -> row tid/4, k chunk 8 (tid % 4)
+            const int m = m0 + (tid >> 2), k = k0 + 8 * (tid & 3);
+            if (m < g.M && k + 8 <= g.K && avec) {
+                av = *reinterpret_cast<const v8u*>(g.A + size_t(m) * g.lda + k);
+            } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            int mm, kk;
-            if constexpr (!TA) { kk = tid & 31; mm = (tid >> 5) + 8 * i; }
-            else { mm = tid & 63; kk = (tid >> 6) + 4 * i; }
-            const int m = m0 + mm, k = k0 + kk;
-            uint16_t v = 0;
-            if (m < g.M && k < g.K) v = TA ? g.A[size_t(k) * g.lda + m] : g.A[size_t(m) * g.lda + k];
-            As[mm * GLD + kk] = v;
-        }
+                for (int e = 0; e < 8; ++e) av[e] = (m < g.M && k + e < g.K) ? g.A[size_t(m) * g.lda + k + e] : 0;
+            }
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            int nn, kk;
-            if constexpr (TB) { kk = tid & 31; nn = (tid >> 5) + 8 * i; }
-            else { nn = tid & 63; kk = (tid >> 6) + 4 * i; }
-            const int n = n0 + nn, k = k0 + kk;
-            uint16_t v = 0;
-            if (n < g.N && k < g.K) v = TB ? g.B[size_t(n) * g.ldb + k] : g.B[size_t(k) * g.ldb + n];
-            Bs[nn * GLD + kk] = v;
+            for (int i = 0; i < 8; ++i) {
+                const int mm = tid & 63, kk = (tid >> 6) + 4 * i;
+                const int m = m0 + mm, k = k0 + kk;
+                as8[i] = (m < g.M && k < g.K) ? g.A[size_t(k) * g.lda + m] : 0;
+            }
         }
+        if constexpr (TB) {
+            const int n = n0 + (tid >> 2), k = k0 + 8 * (tid & 3);
+            if (n < g.N && k + 8 <= g.K && bvec) {
+                bv = *reinterpret_cast<const v8u*>(g.B + size_t(n) * g.ldb + k);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = (n < g.N && k + e < g.K) ? g.B[size_t(n) * g.ldb + k + e] : 0;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int nn = tid & 63, kk = (tid >> 6) + 4 * i;
+                const int n = n0 + nn, k = k0 + kk;
+                bs8[i] = (n < g.N && k < g.K) ? g.B[size_t(k) * g.ldb + n] : 0;
+            }
+        }
+    };
+    auto stage = [&]() {
+        if constexpr (!TA) {
+            *reinterpret_cast<v8u*>(&As[(tid >> 2) * GLD + 8 * (tid & 3)]) = av;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[(tid & 63) * GLD + (tid >> 6) + 4 * i] = as8[i];
+        }
+        if constexpr (TB) {
+            *reinterpret_cast<v8u*>(&Bs[(tid >> 2) * GLD + 8 * (tid & 3)]) = bv;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(tid & 63) * GLD + (tid >> 6) + 4 * i] = bs8[i];
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        stage();
         __syncthreads();
+        if (k0 + GK < kend) load(k0 + GK);  // in flight during the products below
 #pragma unroll
         for (int ks = 0; ks < GK; ks += 16) {
             v4s a[2], b[2];
@@ -125,24 +196,47 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
                 const int col = n0 + wn + 16 * j + (lane & 15);
                 if (row >= g.M || col >= g.N) continue;
-                const size_t o = size_t(row) * g.ldc + col;
-                float v = acc[i][j][r];
-                if constexpr (EPI == EPI_BIAS) v += g.bias[col];
-                if constexpr (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[col]);
-                if constexpr (EPI == EPI_DTANH) {
-                    const float a = g.act[o];
-                    v = v * (1.0f - a * a);
-                }
-                g.C[o] = v;
-                if constexpr (EPI == EPI_BIAS_TANH || EPI == EPI_DTANH)
-                    if (g.Ch) g.Ch[o] = f2bf(v);
+                if (sp.part)
+                    sp.part[(size_t(blockIdx.z) * g.M + row) * g.N + col] = acc[i][j][r];
+                else
+                    gemm_epilogue<EPI>(g, row, col, acc[i][j][r]);
             }
 }
 
+// Sum of the split-K slabs in slab order, then the epilogue.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, const float* __restrict__ part, int splits) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(g.M) * g.N) return;
+    float v = 0.0f;
+    for (int z = 0; z < splits; ++z) v += part[size_t(z) * g.M * g.N + e];
+    gemm_epilogue<EPI>(g, int(e / g.N), int(e % g.N), v);
+}
+
+// Split K when the tile grid is small (< 64 workgroups) and K long: slabs of at
+// least 128, as many as bring the grid to about 128 workgroups.
+inline int gemm_splits(int M, int N, int K) {
+    const int tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    if (tiles >= 64 || K < 512) return 1;
+    int s = 1;
+    while (tiles * s * 2 <= 128 && K / (s * 2) >= 128) s *= 2;
+    return s;
+}
+
 template <bool TA, bool TB, int EPI>
-void gemm(const GemmArgs& g, hipStream_t s) {
-    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
-    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+void gemm(const GemmArgs& g, float* work, hipStream_t s) {
+    const int splits = work ? gemm_splits(g.M, g.N, g.K) : 1;
+    GemmSplit sp{nullptr, g.K};
+    if (splits > 1) {
+        sp.part = work;
+        sp.kslab = ((g.K + splits - 1) / splits + GK - 1) / GK * GK;
+    }
+    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, splits);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g, sp);
+    if (splits > 1) {
+        const int64_t ne = int64_t(g.M) * g.N;
+        hipLaunchKernelGGL(k_gemm_reduce<EPI>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, g, work, splits);
+    }
 }
 
 // ---- vector kernels -------------------------------------------------------------------
@@ -198,22 +292,49 @@ __global__ void k_loss_final(const double* __restrict__ partial, int nb, double 
     }
 }
 
-// g[n] = sum_b D[b][n] (FP64 accumulation, rows in order).
+// g[n] = sum_b D[b][n] (FP64 accumulation, rows in order).  Rows are loaded
+// eight at a time ahead of the additions (the sum stays in row order), so the
+// loads overlap instead of each waiting for the previous addition.
 __global__ void k_colsum(const float* __restrict__ D, int B, int N, float* __restrict__ g) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     double s = 0.0;
-    for (int b = 0; b < B; ++b) s += D[size_t(b) * N + n];
+    int b = 0;
+    for (; b + 8 <= B; b += 8) {
+        float d[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d[i] = D[size_t(b + i) * N + n];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += d[i];
+    }
+    for (; b < B; ++b) s += D[size_t(b) * N + n];
     g[n] = float(s);
 }
 
-// gW1[i][n] = sum_b X[b][i] dZ1[b][n], gb1[n] = sum_b dZ1[b][n].
+// gW1[i][n] = sum_b X[b][i] dZ1[b][n], gb1[n] = sum_b dZ1[b][n] (rows in order,
+// loaded eight at a time as in k_colsum).
 __global__ void k_l1_grad(const float* __restrict__ X, const float* __restrict__ dZ1, int B, int W,
                           float* __restrict__ grad) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= W) return;
     double s0 = 0.0, s1 = 0.0, sb = 0.0;
-    for (int b = 0; b < B; ++b) {
+    int b = 0;
+    for (; b + 8 <= B; b += 8) {
+        float d[8], x0[8], x1[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            d[i] = dZ1[size_t(b + i) * W + n];
+            x0[i] = X[2 * (b + i)];
+            x1[i] = X[2 * (b + i) + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            s0 += double(x0[i]) * double(d[i]);
+            s1 += double(x1[i]) * double(d[i]);
+            sb += double(d[i]);
+        }
+    }
+    for (; b < B; ++b) {
         const double d = dZ1[size_t(b) * W + n];
         s0 += double(X[2 * b]) * d;
         s1 += double(X[2 * b + 1]) * d;
@@ -479,6 +600,7 @@ struct Mlp {
     int64_t o_W1 = 0, o_b1 = 0, o_W2 = 0, o_b2 = 0, o_W3 = 0, o_b3 = 0;
     DevBuf w, wh, g, m, v;
     DevBuf in1, X, A1, A1h, A2, A2h, Y, dY, dYh, dZ2, dZ2h, dZ1, partial, loss, nrm;
+    DevBuf gwork;  // split-K partial products
     int cap = 0;
     int64_t t = 0;
     bool has_params = false;
@@ -516,6 +638,15 @@ struct Mlp {
             TSK_TRY(dZ1.ensure(size_t(B) * W * 4));
             cap = B;
         }
+        // the largest split-K workspace of the six products at this batch (not
+        // monotone in B: a larger batch may take fewer slabs)
+        size_t wf = 0;
+        const int shapes[6][3] = {{B, W, W}, {B, kOut, W}, {W, kOut, B}, {B, W, kOut}, {W, W, B}, {B, W, W}};
+        for (const auto& sh : shapes) {
+            const int sp = gemm_splits(sh[0], sh[1], sh[2]);
+            if (sp > 1) wf = std::max(wf, size_t(sp) * sh[0] * sh[1]);
+        }
+        TSK_TRY(gwork.ensure(std::max<size_t>(wf, 1) * 4));
         TSK_TRY(loss.ensure(size_t(loss_slots < 1 ? 1 : loss_slots) * 8));
         return TSK_OK;
     }
@@ -530,11 +661,11 @@ struct Mlp {
         GemmArgs a{};
         a.A = A1h.as<uint16_t>(); a.B = whp(o_W2); a.M = B; a.N = W; a.K = W;
         a.lda = W; a.ldb = W; a.ldc = W; a.C = A2.as<float>(); a.Ch = A2h.as<uint16_t>(); a.bias = wf() + o_b2;
-        gemm<false, false, EPI_BIAS_TANH>(a, s);
+        gemm<false, false, EPI_BIAS_TANH>(a, gwork.as<float>(), s);
         GemmArgs b{};
         b.A = A2h.as<uint16_t>(); b.B = whp(o_W3); b.M = B; b.N = kOut; b.K = W;
         b.lda = W; b.ldb = kOut; b.ldc = kOut; b.C = out; b.bias = wf() + o_b3;
-        gemm<false, false, EPI_BIAS>(b, s);
+        gemm<false, false, EPI_BIAS>(b, gwork.as<float>(), s);
     }
 
     // Loss into loss[slot] and the full gradient into g.
@@ -548,23 +679,23 @@ struct Mlp {
         GemmArgs g3{};  // gW3 = A2h^T dYh
         g3.A = A2h.as<uint16_t>(); g3.B = dYh.as<uint16_t>(); g3.M = W; g3.N = kOut; g3.K = B;
         g3.lda = W; g3.ldb = kOut; g3.ldc = kOut; g3.C = G + o_W3;
-        gemm<true, false, EPI_STORE>(g3, s);
-        hipLaunchKernelGGL(k_colsum, dim3((kOut + 255) / 256), dim3(256), 0, s, dY.as<float>(), B, kOut, G + o_b3);
+        gemm<true, false, EPI_STORE>(g3, gwork.as<float>(), s);
+        hipLaunchKernelGGL(k_colsum, dim3((kOut + 63) / 64), dim3(64), 0, s, dY.as<float>(), B, kOut, G + o_b3);
         GemmArgs d2{};  // dZ2 = (dYh W3h^T) * (1 - A2^2)
         d2.A = dYh.as<uint16_t>(); d2.B = whp(o_W3); d2.M = B; d2.N = W; d2.K = kOut;
         d2.lda = kOut; d2.ldb = kOut; d2.ldc = W; d2.C = dZ2.as<float>(); d2.Ch = dZ2h.as<uint16_t>();
         d2.act = A2.as<float>();
-        gemm<false, true, EPI_DTANH>(d2, s);
+        gemm<false, true, EPI_DTANH>(d2, gwork.as<float>(), s);
         GemmArgs g2{};  // gW2 = A1h^T dZ2h
         g2.A = A1h.as<uint16_t>(); g2.B = dZ2h.as<uint16_t>(); g2.M = W; g2.N = W; g2.K = B;
         g2.lda = W; g2.ldb = W; g2.ldc = W; g2.C = G + o_W2;
-        gemm<true, false, EPI_STORE>(g2, s);
-        hipLaunchKernelGGL(k_colsum, dim3((W + 255) / 256), dim3(256), 0, s, dZ2.as<float>(), B, W, G + o_b2);
+        gemm<true, false, EPI_STORE>(g2, gwork.as<float>(), s);
+        hipLaunchKernelGGL(k_colsum, dim3((W + 63) / 64), dim3(64), 0, s, dZ2.as<float>(), B, W, G + o_b2);
         GemmArgs d1{};  // dZ1 = (dZ2h W2h^T) * (1 - A1^2)
         d1.A = dZ2h.as<uint16_t>(); d1.B = whp(o_W2); d1.M = B; d1.N = W; d1.K = W;
         d1.lda = W; d1.ldb = W; d1.ldc = W; d1.C = dZ1.as<float>(); d1.act = A1.as<float>();
-        gemm<false, true, EPI_DTANH>(d1, s);
-        hipLaunchKernelGGL(k_l1_grad, dim3((W + 255) / 256), dim3(256), 0, s, X.as<float>(), dZ1.as<float>(), B, W,
+        gemm<false, true, EPI_DTANH>(d1, gwork.as<float>(), s);
+        hipLaunchKernelGGL(k_l1_grad, dim3((W + 63) / 64), dim3(64), 0, s, X.as<float>(), dZ1.as<float>(), B, W,
                            G + o_W1);
     }
 

@@ -38,6 +38,7 @@
 // eigenvalue into a cluster of about that width), and a pair counts as
 // converged below max(tol, res_floor |mu|), the FP32 floor of the estimate.
 #include <cstring>
+#include <type_traits>
 
 #include "krylov.hpp"
 #include "ops.hpp"
@@ -406,10 +407,14 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(StepSet ss, int kreq, double 
 // subdiagonal entries, and every converged 2x2 block with real eigenvalues split
 // by one rotation, so T ends quasi upper triangular with 2x2 blocks only for
 // complex conjugate pairs.  The similarity P T P of one bulge step touches three
-// rows and three columns whose only overlap is a 3x3 block: nine lanes form the
-// block, the others the rest of the rows and columns, in one phase.  Only the
-// last row of Z (H = Z T Z^T) is tracked, as in the complex solver; the
-// eigenvector of each Ritz value follows by back substitution through the
+// rows and three columns whose only overlap is a 3x3 block.  A single wavefront
+// issues one instruction every four cycles, so the sweep is bound by the
+// instructions per bulge step: the Ritz analysis (only the last row of Z
+// tracked) keeps the block and the entries near the bulge in registers and
+// runs each step as straight-line code (sweep_window); the solvers that
+// accumulate all of Z go through LDS, nine lanes forming the block and the
+// others the rest of the rows and columns in one phase (bulge_step).  H = Z T
+// Z^T; the eigenvector of each Ritz value follows by back substitution through the
 // quasi-triangular T (one lane per eigenvalue, complex arithmetic for pairs).
 
 // Householder vector for (x, y, z): v = (1, v1, v2), tau, with
@@ -678,6 +683,213 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
     return fwd;
 }
 
+// One double-shift sweep over the active window l..ihi (ihi - l >= 2) with the
+// state near the bulge in registers; only the last row of Z (zl) is tracked.
+// The sweep applies T <- P_k T P_k for k = l..ihi-1 (3-element reflectors, then
+// a 2-element one at k = ihi - 1).  Left and right products commute, so every
+// entry outside the moving 3 x 3 block meets its updates in a fixed order: row
+// r's entries in columns k..k+2 (r < k) get the right factor of step k, column
+// c's entries in rows k..k+2 (c >= k + 3) the left factor.  Lane i (and i + 64
+// when p > 64) holds a window of three such entries, T[i][k..k+2] while i < k
+// and T[k..k+2][i] while i >= k + 3; both updates are w <- w - tau (v.w) v, so
+// every lane runs the same instructions.  The block, the bulge (x, y, z), row
+// k + 3 of the window (0, 0, T[k+3][k+2] before step k) and the window of zl are
+// computed by every lane alike.  After step k an entry that no later step of the
+// sweep changes in the same way goes to LDS (T[i][k] of a row window, T[k][i] of
+// a column window, T[k][k], zl[k], the annihilated column k - 1); the next step
+// takes column k + 3 (rows k..k+2) into the block and row k's new window entry
+// from lane k + 3 by readlane, and every other entry it needs from LDS, where
+// it is either untouched so far in this sweep or was stored at least one step
+// earlier.  Per step: one reflector, one 3 x 3 two-sided update and one window
+// update per lane, with no wait on LDS in the chain from one reflector to the
+// next.
+template <bool B> using bool_c = std::integral_constant<bool, B>;
+
+template <int S>
+__device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ihi, double x, double y, double z,
+                                    int lane) {
+    // sink[0] takes the stores of lanes with no window entry to store; sink[1]
+    // stays 0 and is what those lanes load, so no lane branches on its role
+    __shared__ double sink[2];
+    if (lane == 0) sink[1] = 0.0;
+    double B[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) B[a][b] = Tr[(l + a) * p + l + b];
+    double Z0 = zl[l], Z1 = zl[l + 1], Z2 = zl[l + 2];
+    double E2 = (l + 3 <= ihi) ? Tr[(l + 3) * p + l + 2] : 0.0;
+    // lane window i: rp = &T[i][k] (row role, i < k), cp = &T[k][i] (column role,
+    // i >= k + 3), both advanced with k
+    double W[S][3];
+    double* rp[S];
+    double* cp[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int i = lane + kHT * s;
+        rp[s] = Tr + i * p + l;
+        cp[s] = Tr + l * p + i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double* src = i < l ? rp[s] + a : (i >= l + 3 && i < p ? cp[s] + a * p : sink + 1);
+            W[s][a] = *src;
+        }
+    }
+    double* dg = Tr + l * p + l;  // &T[k][k]
+    double* zp = zl + l;          // &zl[k]
+    wave_lds_sync();
+    // step k; THREE: a 3-element reflector (else the final 2-element one at
+    // k = ihi - 1); NEXT3: step k + 1 has a 3-element reflector too
+    auto step = [&](auto three_c, auto next3_c, int k) {
+        constexpr bool THREE = decltype(three_c)::value;
+        constexpr bool NEXT3 = decltype(next3_c)::value;
+        // reflector P = I - tau v v^T, v = (1, v1, v2), P (x, y, z)^T = (alpha, 0, 0)^T.
+        // With y = z = 0 and x != 0 the formulas give tau = 2 (P flips the sign of
+        // row and column k), a valid reflector; only sums of squares outside the
+        // safe range, x = y = z = 0 included, take the careful path.
+        double v1, v2, tau, alpha;
+        {
+            const double zz = THREE ? z : 0.0;
+            const double s2 = fma(x, x, fma(y, y, zz * zz));
+            if (__builtin_amdgcn_readfirstlane((s2 > 1e-280 && s2 < 1e280) ? 1 : 0)) {
+                const double r = rsqrt_full(s2);  // 1 / rho
+                const double rho = s2 * r;
+                alpha = x >= 0.0 ? -rho : rho;
+                const double u0 = x - alpha;
+                const double iu = rcp_full(u0);
+                v1 = y * iu;
+                v2 = zz * iu;
+                tau = fabs(u0) * r;
+            } else {
+                house3(x, y, zz, v1, v2, tau, alpha);
+            }
+        }
+        // block: B <- P B P = B - v a^T - b v^T, a = tau (B^T v - tau g v), b = tau B v, g = v^T B v
+        {
+            const double vv[3] = {1.0, v1, v2};
+            double u[3], w[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u[a] = fma(v2, B[a][2], fma(v1, B[a][1], B[a][0]));
+                w[a] = fma(v2, B[2][a], fma(v1, B[1][a], B[0][a]));
+            }
+            const double tg = tau * fma(v2, u[2], fma(v1, u[1], u[0]));
+            double av[3], bv[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                av[a] = tau * fma(-tg, vv[a], w[a]);
+                bv[a] = tau * u[a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) B[a][b] = fma(-bv[a], vv[b], fma(-vv[a], av[b], B[a][b]));
+        }
+        // row k + 3 (right factor; (0, 0, E2) before the step), zl, the lanes' windows
+        const double te = tau * (v2 * E2);
+        const double E0 = -te, E1 = -te * v1;
+        E2 = fma(-te, v2, E2);
+        const double tz = tau * fma(v2, Z2, fma(v1, Z1, Z0));
+        Z0 -= tz;
+        Z1 = fma(-tz, v1, Z1);
+        Z2 = fma(-tz, v2, Z2);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double tw = tau * fma(v2, W[s][2], fma(v1, W[s][1], W[s][0]));
+            W[s][0] -= tw;
+            W[s][1] = fma(-tw, v1, W[s][1]);
+            W[s][2] = fma(-tw, v2, W[s][2]);
+        }
+        if (lane == 0) {
+            if (k > l) {  // the reflector turned column k - 1 into (alpha, 0, 0)
+                dg[-1] = alpha;
+                dg[p - 1] = 0.0;
+                if (THREE) dg[2 * p - 1] = 0.0;
+            }
+            dg[0] = B[0][0];
+            zp[0] = Z0;
+            if (!THREE) {
+                dg[1] = B[0][1];
+                dg[p] = B[1][0];
+                dg[p + 1] = B[1][1];
+                zp[1] = Z1;
+            }
+        }
+        constexpr int NB = THREE ? 3 : 2;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = lane + kHT * s;
+            const bool row = i < k, col = i >= k + NB && i < p;
+            double* d0 = row ? rp[s] : (col ? cp[s] : sink);
+            *d0 = W[s][0];
+            if (!THREE) *(row ? d0 + 1 : (col ? d0 + p : sink)) = W[s][1];
+        }
+        if constexpr (THREE) {
+            // keeps the LDS reads below after the stores above (other lanes read them)
+            wave_lds_sync();
+            const double xn = B[1][0], yn = B[2][0];
+            double cB = 0.0, cC = 0.0, d33 = 0.0, e2n = 0.0, z2n = 0.0;
+            if constexpr (NEXT3) {  // column k + 3 (k + 3 <= ihi) enters the block
+                const int src = k + 3;
+                double a1 = W[0][1], a2 = W[0][2];
+                if constexpr (S > 1) {
+                    if (src >= kHT) {
+                        a1 = W[1][1];
+                        a2 = W[1][2];
+                    }
+                }
+                cB = readlane_d(a1, src % kHT);
+                cC = readlane_d(a2, src % kHT);
+                d33 = dg[3 * p + 3];
+                e2n = *(k + 4 <= ihi ? dg + 4 * p + 3 : sink + 1);
+                z2n = zp[3];
+            }
+            const double b01 = B[0][1], b02 = B[0][2];
+            B[0][0] = B[1][1];
+            B[0][1] = B[1][2];
+            B[0][2] = cB;
+            B[1][0] = B[2][1];
+            B[1][1] = B[2][2];
+            B[1][2] = cC;
+            B[2][0] = NEXT3 ? E1 : 0.0;
+            B[2][1] = NEXT3 ? E2 : 0.0;
+            B[2][2] = d33;
+            // every lane shifts its window (the values of a lane without one are
+            // never used); row k takes the block's row and T[k][k+3], which lane
+            // k + 3 has just stored; the other rows and the columns load their new entry
+            const int cfirst = k + 1 + (NEXT3 ? 3 : 2);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = lane + kHT * s;
+                double nw = 0.0;
+                if constexpr (NEXT3) {
+                    const bool row = i <= k, col = i >= cfirst && i < p;
+                    nw = *(row ? rp[s] + 3 : (col ? cp[s] + 3 * p : sink + 1));
+                }
+                const bool nr = i == k;
+                W[s][0] = nr ? b01 : W[s][1];
+                W[s][1] = nr ? b02 : W[s][2];
+                W[s][2] = nw;
+                rp[s] += 1;
+                cp[s] += p;
+            }
+            dg += p + 1;
+            zp += 1;
+            E2 = e2n;
+            Z0 = Z1;
+            Z1 = Z2;
+            Z2 = z2n;
+            x = xn;
+            y = yn;
+            z = NEXT3 ? E0 : 0.0;
+        }
+    };
+    int k = l;
+    for (; k <= ihi - 3; ++k) step(bool_c<true>{}, bool_c<true>{}, __builtin_amdgcn_readfirstlane(k));
+    step(bool_c<true>{}, bool_c<false>{}, ihi - 2);
+    step(bool_c<false>{}, bool_c<false>{}, ihi - 1);
+}
+
 // Francis double-shift QR of the p x p real Hessenberg matrix in Tr (row-major,
 // LDS) to quasi upper-triangular form; blk marks the 2x2 blocks (1 = first, 2 =
 // second row).  zl: last row of Z (FZ = false) or all of Z (FZ = true), updated
@@ -784,6 +996,12 @@ __device__ __attribute__((always_inline)) inline void francis_real(double* Tr, d
             x = t00 * t00 + t01 * t10 - ss * t00 + tt;
             y = t10 * (t00 + t11 - ss);
             z = t10 * t21;
+        }
+        if constexpr (!FZ) {
+            if (p > kHT) sweep_window<2>(Tr, zl, p, l, ihi, x, y, z, lane);
+            else sweep_window<1>(Tr, zl, p, l, ihi, x, y, z, lane);
+            wave_lds_sync();
+            continue;
         }
         // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
         for (int kk = l; kk <= ihi - 2; ++kk) {

@@ -13,7 +13,7 @@ The line also carries the 64-instance sweep's throughput, the accuracy of every
 form (true residuals by an FP64 matvec, |dlambda| against FP64), the roofline
 of the dominant kernel and the CPU oracle's time on the same operator.
 
-Other workloads: kolmo128 (128^2 FP64), kolmo512-fp32, sweep, cgle, general,
+Other workloads: kolmo128 (128^2 FP64), kolmo256-fp32, kolmo512-fp32, sweep, cgle, general,
 krylov-schur, optimal, fixed-point, resolvent, copy.
 
 Prints ONE JSON line (rank 0).  Other output goes to stderr.
@@ -224,8 +224,12 @@ def run_single(args, tsk, W, np, torch, cfg, prec, dtype_name):
     launch_ms = ms_apply / nmv
     stepper = tsk.get_tuning(op)  # -2 spectral coupling, -1 Bloch sectors, else columns per wavefront
     flops, kernel = stepper_flops(tsk, op, N, nsteps)
-    traffic = (measured_traffic("k_colstep_couple_kolmo128_fp64_hbm_traffic.md")
-               if prec == tsk.TSK_FP64 and N == 128 and stepper == -2 else None)
+    traffic = None
+    wkey = f"traffic_bytes_per_launch_w{tsk.get_stepper_waves(op)}"  # the launch shape the library kept
+    if stepper == -2 and prec == tsk.TSK_FP64 and N == 128:
+        traffic = measured_traffic("k_colstep_couple_kolmo128_fp64_hbm_traffic.md", key=wkey)
+    elif stepper == -2 and prec == tsk.TSK_FP32 and N == 256:
+        traffic = measured_traffic("k_colstep_couple_kolmo256_fp32_hbm_traffic.md", key=wkey)
     achieved = flops / (launch_ms / 1e3) / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if prec == tsk.TSK_FP64 else FP32_VECTOR_PEAK_TFLOPS
     return {
@@ -737,7 +741,8 @@ def run_learned(args, tsk, W, np, torch):
     launch_ms = stats["fp32_learned"]["ms_per_matvec"]
     flops, kname = stepper_flops(tsk, o32[0], N, nsteps)
     achieved = flops / (launch_ms / 1e3) / 1e12
-    traffic = measured_traffic("k_colstep_couple_kolmo256_fp32_hbm_traffic.md")
+    traffic = measured_traffic("k_colstep_couple_kolmo256_fp32_hbm_traffic.md",
+                               key=f"traffic_bytes_per_launch_w{tsk.get_stepper_waves(o32[0])}")
     sweep_stats = run_sweep_tsgp(tsk, W, torch)
     for name in forms:
         stats[name]["tsgp_per_s"] = stats[name]["mean_matvecs"] * nsteps * N * N / (stats[name]["ms_per_solve"] / 1e3)
@@ -949,7 +954,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="learned",
-                    choices=["learned", "kolmo128", "kolmo512-fp32", "sweep", "cgle", "general", "krylov-schur",
+                    choices=["learned", "kolmo128", "kolmo256-fp32", "kolmo512-fp32", "sweep", "cgle", "general", "krylov-schur",
                              "optimal", "fixed-point", "resolvent", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -988,6 +993,8 @@ def main():
         el = time.perf_counter() - t0
         out = {"metric": "copy calibration", "value": 2 * nbytes * args.steps / el / 1e9, "unit": "GB/s",
                "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes, "steps": args.steps}
+    elif args.workload == "kolmo256-fp32":
+        out = run_single(args, tsk, W, np, torch, dict(W.KOLMO_512_FP32, N=256), tsk.TSK_FP32, "f32")
     elif args.workload == "kolmo512-fp32":
         out = run_single(args, tsk, W, np, torch, W.KOLMO_512_FP32, tsk.TSK_FP32, "f32")
     elif args.workload == "learned":

@@ -12,11 +12,11 @@
 //     RHS on the kept modes, RK4 update, then the four derived spectral fields
 //     i kx s, i ky s, i ky s/K^2, -i kx s/K^2 of the next stage input s, one
 //     per wavefront, and their inverse y-transforms into G[f][kx][y];
-//   row kernel (one workgroup of four wavefronts per pair of grid rows):
-//     the four fields of the two rows by four concurrent complex inverse
+//   row kernel (one workgroup of 2 R wavefronts per R = 2 grid rows):
+//     the four fields of each row by two concurrent complex inverse
 //     x-transforms (two Hermitian half-spectra packed as a + i b per
 //     transform), the products P = U d_x w + V d_y w + u Omega_x + v Omega_y
-//     with the base fields, and one complex forward x-transform of both rows
+//     with the base fields, and one complex forward x-transform per row pair
 //     (P0 + i P1), unpacked to the kx = 0..M half spectra Q[kx][y].
 // G and Q are the only fields in HBM between the two kernels: each kernel
 // reads and writes them once per stage (4 + 1 complex N x (M+1) arrays) and
@@ -49,7 +49,7 @@ template <int N> struct Geo2 {
     }
 };
 
-constexpr int kGT = 4 * kWave;  // both kernels: four wavefronts per workgroup
+constexpr int kGT = 4 * kWave;  // column kernel: four wavefronts per workgroup
 
 enum GenMode { GEN_FIRST = 0, GEN_STAGE = 1, GEN_LAST = 2 };
 
@@ -85,23 +85,39 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
         }
         __syncthreads();
     } else {
+        // the thread's modes e = tid + kGT r: W, Acc (and the forcing) are loaded
+        // first, so their latency overlaps the load and transform of Q
+        constexpr int R = (NM + kGT - 1) / kGT;
+        real wv[R][2], av[R][2], fv[R][2];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + kGT * r;
+            const int64_t o = base + 2 * (e < nq ? e : 0);
+            wv[r][0] = W[o];
+            wv[r][1] = W[o + 1];
+            av[r][0] = q == 0 ? real(0) : Acc[o];
+            av[r][1] = q == 0 ? real(0) : Acc[o + 1];
+            fv[r][0] = fvec ? fvec[o] : real(0);
+            fv[r][1] = fvec ? fvec[o + 1] : real(0);
+        }
         for (int t = tid; t < N; t += kGT) sA[0][t] = Q[size_t(kx) * N + t];
         __syncthreads();
         const C* X = fft_lds<N, -1, kGT>(sA[0], sB[0], sT, tid);
         const double h = dt, h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
         const double scl = -1.0 / (double(N) * N);
-        for (int e = tid; e < nq; e += kGT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + kGT * r;
+            if (e >= nq) continue;
             const int jy = kx == 0 ? e + 1 : e - M;
             const C xr = X[jy < 0 ? jy + N : jy];
-            double nx = scl * double(xr.x), ny = scl * double(xr.y);
-            if (fvec) {  // steady forcing (packed units), nonlinear equation
-                nx += double(fvec[base + 2 * e]);
-                ny += double(fvec[base + 2 * e + 1]);
-            }
+            // steady forcing (packed units) of the nonlinear equation, else 0
+            const double nx = scl * double(xr.x) + double(fv[r][0]), ny = scl * double(xr.y) + double(fv[r][1]);
             const double K2 = kxv * kxv + double(jy) * jy;
             const double e1 = exp(-K2 * dt / Re), eh = exp(-K2 * (0.5 * dt) / Re);
             const int64_t o = base + 2 * e;
-            const double wx = W[o], wy = W[o + 1];
+            const double wx = wv[r][0], wy = wv[r][1];
+            const double ax = av[r][0], ay = av[r][1];
             double sx, sy;
             if (q == 0) {
                 Acc[o] = real(e1 * (wx + h6 * nx));
@@ -109,17 +125,17 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
                 sx = eh * (wx + h2 * nx);
                 sy = eh * (wy + h2 * ny);
             } else if (q == 1) {
-                Acc[o] = real(double(Acc[o]) + h3 * eh * nx);
-                Acc[o + 1] = real(double(Acc[o + 1]) + h3 * eh * ny);
+                Acc[o] = real(ax + h3 * eh * nx);
+                Acc[o + 1] = real(ay + h3 * eh * ny);
                 sx = eh * wx + h2 * nx;
                 sy = eh * wy + h2 * ny;
             } else if (q == 2) {
-                Acc[o] = real(double(Acc[o]) + h3 * eh * nx);
-                Acc[o + 1] = real(double(Acc[o + 1]) + h3 * eh * ny);
+                Acc[o] = real(ax + h3 * eh * nx);
+                Acc[o + 1] = real(ay + h3 * eh * ny);
                 sx = e1 * wx + h * eh * nx;
                 sy = e1 * wy + h * eh * ny;
             } else {
-                const real nwx = real(double(Acc[o]) + h6 * nx), nwy = real(double(Acc[o + 1]) + h6 * ny);
+                const real nwx = real(ax + h6 * nx), nwy = real(ay + h6 * ny);
                 if (mode == GEN_LAST) {
                     yout[o] = nwx;
                     yout[o + 1] = nwy;
@@ -156,10 +172,12 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
     for (int t = lane; t < N; t += kWave) out[t] = X[t];
 }
 
-// Row kernel, one workgroup per pair of grid rows (y0, y0 + 1).  Wavefront
-// 2r + pr inverse-transforms field pair pr ((d_x w, d_y w) or (u, v), packed as
-// a + i b) of row y0 + r; the workgroup then forms the products of both rows
-// and transforms them forward as one complex sequence P0 + i P1.
+// Row kernel, one workgroup per RPW consecutive grid rows y0 .. y0 + RPW - 1
+// (gen_rows_per_group).  Wavefront 2r + pr
+// inverse-transforms field pair pr ((d_x w, d_y w) or (u, v), packed as a + i b)
+// of row y0 + r; the workgroup then forms the products of all its rows and
+// transforms them forward two rows at a time (P_2a + i P_2a+1, 256 threads per
+// transform, the RPW/2 transforms concurrently).
 //   ROW_LIN:    P = U d_x w + V d_y w + u Omega_x + v Omega_y (base fields U..Oy);
 //   ROW_NL:     P = (u + U0) d_x w + v d_y w of the state itself (nonlinear
 //               advection; the derived fields carry the packing factor sqrt(2),
@@ -167,19 +185,47 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
 //   ROW_FIELDS: no product: the physical grid fields (u + U0, v, d_x w, d_y w)
 //               of the state go to U, V, Ox, Oy (the state as a base flow).
 enum RowMode { ROW_LIN = 0, ROW_NL = 1, ROW_FIELDS = 2 };
-template <typename real, int N, int RM>
-__global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ Gf, real* __restrict__ U,
-                                                 real* __restrict__ V, real* __restrict__ Ox, real* __restrict__ Oy,
-                                                 cplx<real>* __restrict__ Q, const cplx<real>* __restrict__ twg,
-                                                 double U0) {
+// Rows per workgroup: 2.  With 8 rows (16 wavefronts) the reads of G and the
+// writes of Q cover whole 128-byte lines and the kernel fetches half the bytes,
+// but its 16 workgroups of 1024 threads take 9.6 instead of 5.4 us per launch
+// at 128^2 (4 rows: 6.8 us); the stage is latency-bound, so the wider grid of
+// small workgroups wins.
+template <typename real, int N> constexpr int gen_rows_per_group() {
+    return 2;
+}
+template <typename real, int N, int RM, int RPW>
+__global__ __launch_bounds__(2 * RPW * kWave) void k_gen_row(const cplx<real>* __restrict__ Gf, real* __restrict__ U,
+                                                             real* __restrict__ V, real* __restrict__ Ox,
+                                                             real* __restrict__ Oy, cplx<real>* __restrict__ Q,
+                                                             const cplx<real>* __restrict__ twg, double U0) {
     using C = cplx<real>;
     using G = Geo2<N>;
     constexpr int M = G::M, MC = G::MC;
+    constexpr int NT = 2 * RPW * kWave;  // threads
+    constexpr int NP = RPW / 2;          // row pairs, one forward transform each
+    constexpr int GT = NT / NP;          // threads per forward transform
+    constexpr int NE = RPW * N;          // grid points of the workgroup
+    constexpr int RX = (NE + NT - 1) / NT;
+    static_assert(N % RPW == 0 && GT == 4 * kWave, "row grouping");
     __shared__ C sT[N];
-    __shared__ C sA[4][N], sB[4][N];
+    __shared__ C sA[2 * RPW][N], sB[2 * RPW][N];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int y0 = 2 * blockIdx.x, r = wv >> 1, pr = wv & 1, y = y0 + r;
-    for (int t = tid; t < N; t += kGT) sT[t] = twg[t];
+    const int y0 = RPW * blockIdx.x, r = wv >> 1, pr = wv & 1, y = y0 + r;
+    // the base fields of the thread's grid points (ROW_LIN), loaded first so that
+    // their latency overlaps the transforms; point e = rr N + x of the workgroup
+    real bU[RX], bV[RX], bOx[RX], bOy[RX];
+    if constexpr (RM == ROW_LIN) {
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+            const int e = tid + NT * i;
+            const size_t o = size_t(y0) * N + (e < NE ? e : 0);
+            bU[i] = U[o];
+            bV[i] = V[o];
+            bOx[i] = Ox[o];
+            bOy[i] = Oy[o];
+        }
+    }
+    for (int t = tid; t < N; t += NT) sT[t] = twg[t];
     C* a = sA[wv];
     C* b = sB[wv];
     for (int t = lane; t < N; t += kWave) a[t] = cmk<C>(real(0), real(0));
@@ -198,49 +244,48 @@ __global__ __launch_bounds__(kGT) void k_gen_row(const cplx<real>* __restrict__ 
     __syncthreads();
     fft_lds<N, +1, kWave>(a, b, sT, lane);
     __syncthreads();
-    // the inverse results sit in sA[w] after an even number of passes, else in
-    // sB[w]; the products of both rows, packed as P0 + i P1, go to a free buffer
+    // the inverse results of row rr sit in sA[2 rr + pr] after an even number of
+    // passes, else in sB; the other set is free for the products
     constexpr bool in_a = fft_num_passes(N) % 2 == 0;
-    C* z = in_a ? sB[0] : sA[0];
-    C* scratch = in_a ? sB[1] : sA[1];
-    const C* R00 = in_a ? sA[0] : sB[0];  // row 0, (d_x w, d_y w)
-    const C* R01 = in_a ? sA[1] : sB[1];  // row 0, (u, v)
-    const C* R10 = in_a ? sA[2] : sB[2];  // row 1, (d_x w, d_y w)
-    const C* R11 = in_a ? sA[3] : sB[3];  // row 1, (u, v)
+    C(*res)[N] = in_a ? sA : sB;
+    C(*freeb)[N] = in_a ? sB : sA;
     if constexpr (RM == ROW_FIELDS) {
         const real is2 = real(0.70710678118654752440);  // packing factor sqrt(2) removed
-        for (int x = tid; x < N; x += kGT) {
-            const size_t o0 = size_t(y0) * N + x, o1 = o0 + N;
-            U[o0] = is2 * R01[x].x + real(U0);
-            V[o0] = is2 * R01[x].y;
-            Ox[o0] = is2 * R00[x].x;
-            Oy[o0] = is2 * R00[x].y;
-            U[o1] = is2 * R11[x].x + real(U0);
-            V[o1] = is2 * R11[x].y;
-            Ox[o1] = is2 * R10[x].x;
-            Oy[o1] = is2 * R10[x].y;
+        for (int e = tid; e < NE; e += NT) {
+            const int rr = e / N, x = e % N;
+            const size_t o = size_t(y0) * N + e;
+            const C d = res[2 * rr][x], uv = res[2 * rr + 1][x];
+            U[o] = is2 * uv.x + real(U0);
+            V[o] = is2 * uv.y;
+            Ox[o] = is2 * d.x;
+            Oy[o] = is2 * d.y;
         }
         return;
     }
-    for (int x = tid; x < N; x += kGT) {
-        const size_t o0 = size_t(y0) * N + x, o1 = o0 + N;
-        real p0, p1;
+#pragma unroll
+    for (int i = 0; i < RX; ++i) {
+        const int e = tid + NT * i;
+        if (e >= NE) continue;
+        const int rr = e / N, x = e % N;
+        const C d = res[2 * rr][x], uv = res[2 * rr + 1][x];  // (d_x w, d_y w), (u, v)
+        real pv;
         if constexpr (RM == ROW_NL) {
             const real is2 = real(0.70710678118654752440), u0 = real(U0);
-            p0 = is2 * (R01[x].x * R00[x].x + R01[x].y * R00[x].y) + u0 * R00[x].x;
-            p1 = is2 * (R11[x].x * R10[x].x + R11[x].y * R10[x].y) + u0 * R10[x].x;
+            pv = is2 * (uv.x * d.x + uv.y * d.y) + u0 * d.x;
         } else {
-            p0 = U[o0] * R00[x].x + V[o0] * R00[x].y + Ox[o0] * R01[x].x + Oy[o0] * R01[x].y;
-            p1 = U[o1] * R10[x].x + V[o1] * R10[x].y + Ox[o1] * R11[x].x + Oy[o1] * R11[x].y;
+            pv = bU[i] * d.x + bV[i] * d.y + bOx[i] * uv.x + bOy[i] * uv.y;
         }
-        z[x] = cmk<C>(p0, p1);
+        C* z = freeb[2 * (rr >> 1)];
+        if (rr & 1) z[x].y = pv;
+        else z[x].x = pv;
     }
     __syncthreads();
-    const C* Z = fft_lds<N, -1, kGT>(z, scratch, sT, tid);
-    for (int k = tid; k <= M; k += kGT) {
+    const int g = tid / GT, gt = tid % GT;  // transform g: rows 2g, 2g + 1
+    const C* Z = fft_lds<N, -1, GT>(freeb[2 * g], freeb[2 * g + 1], sT, gt);
+    for (int k = gt; k <= M; k += GT) {
         const C za = Z[k], zb = cconj(Z[k == 0 ? 0 : N - k]);
-        Q[size_t(k) * N + y0] = cmk<C>(real(0.5) * (za.x + zb.x), real(0.5) * (za.y + zb.y));
-        Q[size_t(k) * N + y0 + 1] = cmk<C>(real(0.5) * (za.y - zb.y), real(-0.5) * (za.x - zb.x));
+        Q[size_t(k) * N + y0 + 2 * g] = cmk<C>(real(0.5) * (za.x + zb.x), real(0.5) * (za.y + zb.y));
+        Q[size_t(k) * N + y0 + 2 * g + 1] = cmk<C>(real(0.5) * (za.y - zb.y), real(-0.5) * (za.x - zb.x));
     }
 }
 
@@ -253,17 +298,19 @@ void gen_run(const void* x, void* y, real* W, real* Acc, cplx<real>* Q, cplx<rea
              hipStream_t s) {
     using C = cplx<real>;
     constexpr int MC = Geo2<N>::MC;
-    static_assert(N % 2 == 0, "row pairs");
+    constexpr int RPW = gen_rows_per_group<real, N>();
     const C* twc = static_cast<const C*>(tw);
     hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc, Q, Gf,
                        static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST), fvec);
     if constexpr (RM == ROW_FIELDS) {
-        hipLaunchKernelGGL((k_gen_row<real, N, RM>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc, U0);
+        hipLaunchKernelGGL((k_gen_row<real, N, RM, RPW>), dim3(N / RPW), dim3(2 * RPW * kWave), 0, s, Gf, U, V, Ox,
+                           Oy, Q, twc, U0);
         return;
     }
     for (int st = 0; st < nsteps; ++st)
         for (int q = 0; q < 4; ++q) {
-            hipLaunchKernelGGL((k_gen_row<real, N, RM>), dim3(N / 2), dim3(kGT), 0, s, Gf, U, V, Ox, Oy, Q, twc, U0);
+            hipLaunchKernelGGL((k_gen_row<real, N, RM, RPW>), dim3(N / RPW), dim3(2 * RPW * kWave), 0, s, Gf, U, V,
+                               Ox, Oy, Q, twc, U0);
             const int mode = (st == nsteps - 1 && q == 3) ? GEN_LAST : GEN_STAGE;
             hipLaunchKernelGGL((k_gen_col<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc,
                                Q, Gf, static_cast<real*>(y), twc, alpha, Re, dt, q, mode, fvec);

@@ -355,7 +355,11 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // as soon as the operator stream has finished the matvec before the last
     // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
-    constexpr int kQueueAhead = 1;
+    // Matvec timing: an event pair around every kTimeEvery-th matvec (the first
+    // included); ms_apply is their mean duration times the matvecs run.  An
+    // event record costs about 5 us of operator-stream time on this device, as
+    // much as a sixth of a 128^2 step, while the matvec's duration hardly varies.
+    constexpr int kTimeEvery = 8;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     // a batch of grid-size groups runs its extra groups on worker streams 1 and 2;
     // its analyses then use stream 0 only, so the operator's stream and the three
@@ -371,9 +375,10 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
         cgs2_step<TS>(table(t), count, nblk_max, nmax, j, s);
         TSK_HIP(hipEventRecord(L.ev_cgs[t], s));
         if (j + 1 < m) {
-            TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
+            const bool timed = (j + 1) % kTimeEvery == 0;
+            if (timed) TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1)], s));
             TSK_TRY(matvec(j + 1));
-            TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1) + 1], s));
+            if (timed) TSK_HIP(hipEventRecord(L.ev_apply[2 * (j + 1) + 1], s));
         }
         ready.push_back(j);
         return TSK_OK;
@@ -458,14 +463,12 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
             if (q != hipErrorNotReady) TSK_HIP(q);
         }
         if (next < m && int(pend.size() + ready.size()) < NS) {
-            // kQueueAhead steps queued ahead: step `next` goes behind its own matvec
-            // as soon as the matvec kQueueAhead steps before it has finished, so the
-            // operator stream never waits for the host.  The gaps left between the
-            // kernels of a step (5-10 us each on this device) are dependent-launch
-            // latency, not host delay: queueing three steps ahead did not shorten
-            // them, so one step ahead keeps the fewest discarded matvecs.
-            const hipError_t qm = next < kQueueAhead ? hipSuccess
-                                                     : hipEventQuery(L.ev_apply[2 * (next - kQueueAhead) + 1]);
+            // one step queued ahead: step `next` (its Gram-Schmidt and the matvec
+            // after it) goes behind its own matvec as soon as that matvec can start,
+            // i.e. once the Gram-Schmidt of step next - 1 has finished, so the
+            // operator stream never waits for the host.  Queueing three steps ahead
+            // did not help; one step ahead keeps the fewest discarded matvecs.
+            const hipError_t qm = next < 1 ? hipSuccess : hipEventQuery(L.ev_cgs[(next - 1) % NS]);
             if (qm == hipSuccess) {
                 TSK_TRY(enqueue(next++));
                 continue;
@@ -479,10 +482,15 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // ---- outputs --------------------------------------------------------------------------------
     TSK_HIP(hipStreamSynchronize(s));  // drains discarded speculative matvecs
     double ms_apply = 0.0;
-    for (int j = 0; j < steps_run; ++j) {
-        float ms = 0.0f;
-        TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * j], L.ev_apply[2 * j + 1]));
-        ms_apply += ms;
+    {
+        int nt = 0;
+        for (int j = 0; j < steps_run; j += kTimeEvery) {
+            float ms = 0.0f;
+            TSK_HIP(hipEventElapsedTime(&ms, L.ev_apply[2 * j], L.ev_apply[2 * j + 1]));
+            ms_apply += ms;
+            ++nt;
+        }
+        if (nt > 0) ms_apply = ms_apply / nt * steps_run;
     }
     int pmax = 1;
     for (int i = 0; i < count; ++i) {

@@ -253,8 +253,19 @@ template <typename TS> __device__ inline void finalize_scale(const KryDesc& d, i
     const double inv = (b > 0.0 && isfinite(b)) ? 1.0 / b : 0.0;
     TS* v = static_cast<TS*>(d.V) + (j + 1) * d.ldv;
     const A* w64 = static_cast<const A*>(d.w64);
-    for (int64_t g = int64_t(blk) * blockDim.x + threadIdx.x; g < d.n; g += int64_t(nb) * blockDim.x)
-        v[g] = ET<TS>::store(scale_by(w64[g], inv));
+    // eight loads in flight before their stores (one block scales a whole short
+    // state when the normalisation is fused into pass 2)
+    constexpr int U = 8;
+    const int64_t st = int64_t(nb) * blockDim.x;
+    int64_t g = int64_t(blk) * blockDim.x + threadIdx.x;
+    for (; g + (U - 1) * st < d.n; g += U * st) {
+        A x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = w64[g + u * st];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[g + u * st] = ET<TS>::store(scale_by(x[u], inv));
+    }
+    for (; g < d.n; g += st) v[g] = ET<TS>::store(scale_by(w64[g], inv));
 }
 
 // The coefficients of a Gram-Schmidt pass from the partial dots of the kernel

@@ -37,6 +37,7 @@
 
 #include "colbloch.hpp"
 #include "colcouple.hpp"
+#include "colcouple_adj.hpp"
 #include "colstep.hpp"
 #include "kolmo2d.hpp"
 #include "krylov.hpp"
@@ -386,6 +387,25 @@ void launch_couple_stepper(const ColInst<real>& one, const ColInst<real>* insts,
         launch_couple_shape<real, 2>(one, insts, ids, n, jstep, blocks, wpw, s);
 }
 
+// Transposed coupling stepper (colcouple_adj.hpp), one instance.
+template <typename real, int S>
+void launch_couple_adj_shape(const ColInst<real>& one, int blocks, int wpw, hipStream_t s) {
+    const dim3 grid((blocks + wpw - 1) / wpw);
+    if (wpw == 1)
+        hipLaunchKernelGGL((k_colstep_couple_adj<real, S, 1>), grid, dim3(kWave), 0, s, one);
+    else if (wpw == 2)
+        hipLaunchKernelGGL((k_colstep_couple_adj<real, S, 2>), grid, dim3(2 * kWave), 0, s, one);
+    else
+        hipLaunchKernelGGL((k_colstep_couple_adj<real, S, 4>), grid, dim3(4 * kWave), 0, s, one);
+}
+template <typename real>
+void launch_couple_adj(const ColInst<real>& one, int blocks, int S, int wpw, hipStream_t s) {
+    if (S == 1)
+        launch_couple_adj_shape<real, 1>(one, blocks, wpw, s);
+    else
+        launch_couple_adj_shape<real, 2>(one, blocks, wpw, s);
+}
+
 // Launch shape of the coupling stepper (wavefronts per workgroup: 1, 2 or 4),
 // timed once per (precision, positions per lane, launch size) and process on
 // the first real launch, like the column variants; the shapes compute the same
@@ -591,12 +611,24 @@ struct KolmoOp final : Operator {
         return TSK_OK;
     }
     bool has_adjoint() const override { return gen == nullptr; }
-    // Transposed propagator (k_colstep_adj): parallel base flows, one column per
-    // wavefront (task list of 1-column tasks).
+    // Transposed propagator: for a one-harmonic base the transposed coupling
+    // stepper (k_colstep_couple_adj, in the launch shape the forward stepper
+    // kept, else one wavefront per workgroup); other parallel bases the
+    // transposed column stepper (k_colstep_adj, task list of 1-column tasks).
     tsk_status apply_adjoint(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply_adjoint: input and output must not alias");
         if (gen) return fail(TSK_EINVAL, "the adjoint propagator needs a parallel base flow");
+        if (use_couple()) {
+            const int S = couple_slots(M, nh), blocks = couple_blocks(M, nh);
+            const int w = force_wpw ? force_wpw : (tuned_wpw ? tuned_wpw : 1);
+            if (prec == TSK_FP32)
+                launch_couple_adj<float>(inst<float>(x, 0, y, nullptr), blocks, S, w, stream);
+            else
+                launch_couple_adj<double>(inst<double>(x, 0, y, nullptr), blocks, S, w, stream);
+            TSK_HIP(hipGetLastError());
+            return TSK_OK;
+        }
         if (prec == TSK_FP32)
             dispatch_colstep_adj<float>(N, inst<float>(x, 0, y, nullptr), tasks[1].as<ColTask>(), ntasks[1], prop,
                                         tw.ptr, stream);

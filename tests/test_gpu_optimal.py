@@ -16,12 +16,18 @@ pytestmark = pytest.mark.gpu
 def _op(tsk, N, alpha=0.5, Re=20.0, dt=0.005, T=1.0, prec=0, base="kolmogorov"):
     op = tsk.create_kolmo2d(N, prec)
     tsk.set_params_kolmo(op, Re, alpha, dt, T)
-    if base == "kolmogorov":
+    if base in ("kolmogorov", "kolmogorov-columns"):
         tsk.set_base_kolmogorov(op, 4)
+        if base == "kolmogorov-columns":  # the transposed column stepper instead of the coupling one
+            tsk.set_tuning(op, 1)
         return op, Kolmogorov.kolmogorov(N, alpha, Re, dt, T, 4)
     y = 2 * np.pi * np.arange(N) / N
-    U = np.sin(y) + 0.5 * np.cos(2 * y)
-    dO = np.sin(y) + 2.0 * np.cos(2 * y)  # -U''
+    if base == "shifted":  # one harmonic with a phase: the coupling steppers with y0 != 0
+        U = 0.8 * np.sin(4 * (y - 0.3))
+        dO = 16.0 * U  # -U''
+    else:
+        U = np.sin(y) + 0.5 * np.cos(2 * y)
+        dO = np.sin(y) + 2.0 * np.cos(2 * y)  # -U''
     tsk.set_base_parallel(op, U, dO)
     Ug = np.repeat(U[:, None], N, axis=1)
     Og = np.repeat(dO[:, None], N, axis=1)
@@ -43,13 +49,19 @@ def _phys(tsk, op, s):
 
 
 @pytest.mark.parametrize("N,T,base,prec", [(16, 1.0, "kolmogorov", 0), (48, 0.5, "kolmogorov", 0),
-                                           (48, 0.5, "parallel", 0), (128, 0.1, "kolmogorov", 0),
-                                           (128, 0.1, "parallel", 0), (384, 0.01, "kolmogorov", 0),
-                                           (512, 0.01, "parallel", 0), (128, 0.1, "kolmogorov", 1),
+                                           (48, 0.5, "parallel", 0), (128, 1.0, "kolmogorov", 0),
+                                           (128, 0.1, "parallel", 0), (128, 0.1, "kolmogorov-columns", 0),
+                                           (128, 0.5, "shifted", 0), (384, 0.01, "kolmogorov", 0),
+                                           (512, 0.01, "parallel", 0), (512, 0.1, "kolmogorov", 0),
+                                           (128, 0.1, "kolmogorov", 1), (256, 0.1, "shifted", 1),
                                            (512, 0.01, "kolmogorov", 1)])
 def test_adjoint_matvec_matches_oracle(tsk, N, T, base, prec):
+    # kolmogorov and shifted: the transposed spectral-coupling stepper (512: two
+    # modes per lane); parallel and kolmogorov-columns: the transposed column stepper
     print(f"adjoint matvec N={N} T={T} base={base} prec={prec}", flush=True)
     op, ref = _op(tsk, N, T=T, prec=prec, base=base)
+    assert tsk.get_tuning(op) == (-2 if base in ("kolmogorov", "shifted") else 1 if base == "kolmogorov-columns"
+                                  else tsk.get_tuning(op))
     z = ref.project(W.kolmo_start_physical(N, 5))
     x = _state(tsk, op, z)
     y = op.new_state()
@@ -60,9 +72,8 @@ def test_adjoint_matvec_matches_oracle(tsk, N, T, base, prec):
     assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(want))
 
 
-@pytest.mark.parametrize("base", ["kolmogorov", "parallel"])
-def test_device_adjoint_satisfies_the_dot_product_identity(tsk, base):
-    N = 128
+@pytest.mark.parametrize("N,base", [(128, "kolmogorov"), (128, "parallel"), (128, "shifted"), (512, "kolmogorov")])
+def test_device_adjoint_satisfies_the_dot_product_identity(tsk, N, base):
     print(f"adjoint dot product N={N} base={base}", flush=True)
     op, ref = _op(tsk, N, base=base)
     x = _state(tsk, op, W.kolmo_start_physical(N, 1))

@@ -191,9 +191,11 @@ tsk_status tsk_apply(tsk_op op, const void* x_dev, void* y_dev);
  * Euclidean inner product (Sec. 2.2: for the Euclidean inner product the
  * adjoint is the conjugate transpose; Sec. 3.3.2: M^dagger is one backward
  * integration of the adjoint system).  Navier-Stokes operators: each IF-RK4
- * step transposed stage by stage; parallel base flows only (TSK_EINVAL after
- * tsk_set_base_flow).  Ginzburg-Landau: Crank-Nicolson on L_h^H.  Same
- * layout, stream and aliasing rule as tsk_apply. */
+ * step transposed stage by stage, for parallel base flows (the transposed
+ * steppers) and for a general 2-D base flow after tsk_set_base_flow (the
+ * transposed two-dimensional pipeline: one inverse and four forward transforms
+ * per stage).  Ginzburg-Landau: Crank-Nicolson on L_h^H.  Same layout, stream
+ * and aliasing rule as tsk_apply. */
 tsk_status tsk_apply_adjoint(tsk_op op, const void* x_dev, void* y_dev);
 
 /* Resolvent mode (Sec. 2.3.2; Sec. 3.3.2, the resolvent by forced time

@@ -610,15 +610,16 @@ struct KolmoOp final : Operator {
         TSK_HIP(hipGetLastError());
         return TSK_OK;
     }
-    bool has_adjoint() const override { return gen == nullptr; }
+    bool has_adjoint() const override { return true; }
     // Transposed propagator: for a one-harmonic base the transposed coupling
     // stepper (k_colstep_couple_adj, in the launch shape the forward stepper
     // kept, else one wavefront per workgroup); other parallel bases the
-    // transposed column stepper (k_colstep_adj, task list of 1-column tasks).
+    // transposed column stepper (k_colstep_adj, task list of 1-column tasks);
+    // a general 2-D base the transposed pipeline of kolmo2d.hip.
     tsk_status apply_adjoint(const void* x, void* y) override {
         if (!ready()) return fail(TSK_ESTATE, "Navier-Stokes parameters or base flow not set");
         if (x == y) return fail(TSK_EINVAL, "apply_adjoint: input and output must not alias");
-        if (gen) return fail(TSK_EINVAL, "the adjoint propagator needs a parallel base flow");
+        if (gen) return gen2d_apply_adjoint(gen, alpha, Re, dt, nsteps, x, y, tw.ptr, stream);
         if (use_couple()) {
             const int S = couple_slots(M, nh), blocks = couple_blocks(M, nh);
             const int w = force_wpw ? force_wpw : (tuned_wpw ? tuned_wpw : 1);

@@ -289,6 +289,256 @@ __global__ __launch_bounds__(2 * RPW * kWave) void k_gen_row(const cplx<real>* _
     }
 }
 
+// ---- the transposed pipeline (discrete adjoint) ------------------------------------
+// The advection operator of a stage is N s = -R sum_f B_f P(D_f s): D_f the four
+// derived fields i c_f s (c = kx, ky, ky/K^2, -kx/K^2), P packed state -> grid
+// field, B_f the base fields (U, V, Omega_x, Omega_y), R grid field -> packed
+// state on the kept modes.  The packed Euclidean norm is the RMS of the field,
+// so P^T = N^2 R; D_f^T = -D_f; B_f is symmetric.  Hence
+//     N^T v = sum_f D_f R(B_f P v) = (1/N^2) sum_f i c_f F(B_f F^-1 v)
+// with the pipeline's unnormalised transforms (the sqrt(2) of the packing
+// cancels): one inverse 2-D transform of v, four products, four forward
+// transforms.  The Lawson step transposes stage by stage in reverse order, as
+// for the column steppers (z the adjoint state, so the stage output):
+//     so3 = N^T(h/6 z),                acc = E1 z + E1 so3
+//     so2 = N^T(h/3 Eh z + h Eh so3),  acc += Eh so2
+//     so1 = N^T(h/3 Eh z + h/2 so2),   acc += Eh so1
+//     so0 = N^T(h/6 E1 z + h/2 Eh so1), z+ = acc + so0.
+// A stage is one row kernel (the inverse x-transform of two rows of v packed as
+// a + i b, the products, four forward x-transforms) and one column kernel (four
+// forward y-transforms, the stage output and the RK bookkeeping, the next
+// stage input and its inverse y-transform).  The exchanged arrays swap roles:
+// G1 [kx][y] (one field, the Q buffer) and Q4 [f][kx][y] (four, the G buffer).
+
+// Column kernel of the transposed pipeline, one workgroup per kept kx column.
+// FIRST: z = x, next input h/6 z.  STAGE q: so from Q4, RK bookkeeping of stage
+// q (W holds z, Acc acc), the next stage input.  LAST (stage 3 of the last
+// step): y = new z.
+template <typename real, int N>
+__global__ __launch_bounds__(kGT) void k_gen_col_adj(const real* __restrict__ xin, real* __restrict__ W,
+                                                     real* __restrict__ Acc, const cplx<real>* __restrict__ Q4,
+                                                     cplx<real>* __restrict__ G1, real* __restrict__ yout,
+                                                     const cplx<real>* __restrict__ twg, double alpha, double Re,
+                                                     double dt, int q, int mode) {
+    using C = cplx<real>;
+    using G = Geo2<N>;
+    constexpr int M = G::M, MC = G::MC, NM = G::NM;
+    __shared__ C sA[4][N], sB[4][N], sT[N];
+    __shared__ C sS[NM];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave, kx = blockIdx.x;
+    const int nq = kx == 0 ? M : NM;  // packed complex entries of the column
+    const int64_t base = G::seg(kx);
+    for (int t = tid; t < N; t += kGT) sT[t] = twg[t];
+    const double kxv = alpha * kx;
+    const double h = dt, h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
+
+    if (mode == GEN_FIRST) {
+        for (int e = tid; e < nq; e += kGT) {
+            const real re = xin[base + 2 * e], im = xin[base + 2 * e + 1];
+            W[base + 2 * e] = re;
+            W[base + 2 * e + 1] = im;
+            sS[e] = cmk<C>(real(h6 * double(re)), real(h6 * double(im)));
+        }
+        __syncthreads();
+    } else {
+        constexpr int R = (NM + kGT - 1) / kGT;
+        real zv[R][2], av[R][2];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + kGT * r;
+            const int64_t o = base + 2 * (e < nq ? e : 0);
+            zv[r][0] = W[o];
+            zv[r][1] = W[o + 1];
+            av[r][0] = q == 0 ? real(0) : Acc[o];
+            av[r][1] = q == 0 ? real(0) : Acc[o + 1];
+        }
+        // wavefront f: forward y-transform of field f's column
+        for (int t = lane; t < N; t += kWave) sA[wv][t] = Q4[(size_t(wv) * MC + kx) * N + t];
+        __syncthreads();
+        fft_lds<N, -1, kWave>(sA[wv], sB[wv], sT, lane);
+        __syncthreads();
+        constexpr bool in_a = fft_num_passes(N) % 2 == 0;
+        const double scl = 1.0 / (double(N) * N);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + kGT * r;
+            if (e >= nq) continue;
+            const int jy = kx == 0 ? e + 1 : e - M;
+            const int ix = jy < 0 ? jy + N : jy;
+            const double K2 = kxv * kxv + double(jy) * jy;
+            const double cf[4] = {kxv, double(jy), double(jy) / K2, -kxv / K2};
+            double sx = 0.0, sy = 0.0;  // so = (1/N^2) sum_f i c_f X_f
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const C xf = in_a ? sA[f][ix] : sB[f][ix];
+                sx -= cf[f] * double(xf.y);
+                sy += cf[f] * double(xf.x);
+            }
+            sx *= scl;
+            sy *= scl;
+            const double e1 = exp(-K2 * dt / Re), eh = exp(-K2 * (0.5 * dt) / Re);
+            const int64_t o = base + 2 * e;
+            const double zx = zv[r][0], zy = zv[r][1];
+            double vx, vy;  // the next stage's input
+            if (q == 0) {
+                Acc[o] = real(e1 * (zx + sx));
+                Acc[o + 1] = real(e1 * (zy + sy));
+                vx = eh * (h3 * zx + h * sx);
+                vy = eh * (h3 * zy + h * sy);
+            } else if (q == 1) {
+                Acc[o] = real(double(av[r][0]) + eh * sx);
+                Acc[o + 1] = real(double(av[r][1]) + eh * sy);
+                vx = h3 * eh * zx + h2 * sx;
+                vy = h3 * eh * zy + h2 * sy;
+            } else if (q == 2) {
+                Acc[o] = real(double(av[r][0]) + eh * sx);
+                Acc[o + 1] = real(double(av[r][1]) + eh * sy);
+                vx = h6 * e1 * zx + h2 * eh * sx;
+                vy = h6 * e1 * zy + h2 * eh * sy;
+            } else {
+                const real nzx = real(double(av[r][0]) + sx), nzy = real(double(av[r][1]) + sy);
+                if (mode == GEN_LAST) {
+                    yout[o] = nzx;
+                    yout[o + 1] = nzy;
+                } else {
+                    W[o] = nzx;
+                    W[o + 1] = nzy;
+                }
+                vx = h6 * double(nzx);
+                vy = h6 * double(nzy);
+            }
+            sS[e] = cmk<C>(real(vx), real(vy));
+        }
+        __syncthreads();
+        if (mode == GEN_LAST) return;
+    }
+    // the next stage input v of the column and its inverse y-transform (all four wavefronts)
+    C* a = sA[0];
+    for (int t = tid; t < N; t += kGT) a[t] = cmk<C>(real(0), real(0));
+    __syncthreads();
+    for (int e = tid; e < nq; e += kGT) {
+        const int jy = kx == 0 ? e + 1 : e - M;
+        const C v = sS[e];
+        a[jy < 0 ? jy + N : jy] = v;
+        if (kx == 0) a[N - jy] = cconj(v);  // the kx = 0 column of a real field
+    }
+    __syncthreads();
+    const C* X = fft_lds<N, +1, kGT>(a, sB[0], sT, tid);
+    C* out = G1 + size_t(kx) * N;
+    for (int t = tid; t < N; t += kGT) out[t] = X[t];
+}
+
+// Row kernel of the transposed pipeline, one workgroup per pair of grid rows
+// (y0, y0 + 1): the inverse x-transform of both rows of v (packed as a + i b),
+// the four products with the base fields, and wavefront f's forward
+// x-transform of field f of both rows (P_f,0 + i P_f,1), unpacked to the
+// kx = 0..M half spectra Q4[f][kx][y].
+template <typename real, int N>
+__global__ __launch_bounds__(kGT) void k_gen_row_adj(const cplx<real>* __restrict__ G1, const real* __restrict__ U,
+                                                     const real* __restrict__ V, const real* __restrict__ Ox,
+                                                     const real* __restrict__ Oy, cplx<real>* __restrict__ Q4,
+                                                     const cplx<real>* __restrict__ twg) {
+    using C = cplx<real>;
+    using G = Geo2<N>;
+    constexpr int M = G::M, MC = G::MC;
+    constexpr int RX = (N + kGT - 1) / kGT;
+    __shared__ C sT[N];
+    __shared__ C sA[4][N], sB[4][N];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int y0 = 2 * blockIdx.x;
+    // base fields of the thread's points of both rows, loaded first
+    real bf[RX][4][2];
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+        const int x = tid + kGT * r < N ? tid + kGT * r : 0;
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const size_t o = size_t(y0 + rr) * N + x;
+            bf[r][0][rr] = U[o];
+            bf[r][1][rr] = V[o];
+            bf[r][2][rr] = Ox[o];
+            bf[r][3][rr] = Oy[o];
+        }
+    }
+    for (int t = tid; t < N; t += kGT) sT[t] = twg[t];
+    C* a = sA[0];
+    for (int t = tid; t < N; t += kGT) a[t] = cmk<C>(real(0), real(0));
+    __syncthreads();
+    for (int k = tid; k <= M; k += kGT) {
+        C g0 = G1[size_t(k) * N + y0], g1 = G1[size_t(k) * N + y0 + 1];
+        if (k == 0) {  // the kx = 0 column of a real field is real
+            g0.y = real(0);
+            g1.y = real(0);
+        }
+        a[k] = cmk<C>(g0.x - g1.y, g0.y + g1.x);                 // g0 + i g1
+        if (k > 0) a[N - k] = cmk<C>(g0.x + g1.y, g1.x - g0.y);  // conj(g0) + i conj(g1)
+    }
+    __syncthreads();
+    const C* Fv = fft_lds<N, +1, kGT>(a, sB[0], sT, tid);  // v of row y0 + i v of row y0 + 1
+    // the products of field f go to a buffer not holding Fv: sA[1..3] and sB[1..3]
+    // are free, and the fourth is whichever of sA[0] / sB[0] Fv is not in
+    C* zf[4];
+    C* sc[4];
+    zf[0] = (Fv == sA[0]) ? sB[0] : sA[0];
+    sc[0] = sA[1];
+    zf[1] = sB[1];
+    sc[1] = sA[2];
+    zf[2] = sB[2];
+    sc[2] = sA[3];
+    zf[3] = sB[3];
+    __shared__ C sExtra[N];
+    sc[3] = sExtra;
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+        const int x = tid + kGT * r;
+        if (x >= N) continue;
+        const C v = Fv[x];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) zf[f][x] = cmk<C>(bf[r][f][0] * v.x, bf[r][f][1] * v.y);
+    }
+    __syncthreads();
+    const C* Z = fft_lds<N, -1, kWave>(zf[wv], sc[wv], sT, lane);
+    C* Qf = Q4 + size_t(wv) * MC * N;
+    for (int k = lane; k <= M; k += kWave) {
+        const C za = Z[k], zb = cconj(Z[k == 0 ? 0 : N - k]);
+        Qf[size_t(k) * N + y0] = cmk<C>(real(0.5) * (za.x + zb.x), real(0.5) * (za.y + zb.y));
+        Qf[size_t(k) * N + y0 + 1] = cmk<C>(real(0.5) * (za.y - zb.y), real(-0.5) * (za.x - zb.x));
+    }
+}
+
+// nsteps transposed Lawson steps from x into y (G1 in the Q buffer, Q4 in G).
+template <typename real, int N>
+void gen_run_adj(const void* x, void* y, real* W, real* Acc, cplx<real>* G1, cplx<real>* Q4, const real* U,
+                 const real* V, const real* Ox, const real* Oy, const void* tw, double alpha, double Re, double dt,
+                 int nsteps, hipStream_t s) {
+    using C = cplx<real>;
+    constexpr int MC = Geo2<N>::MC;
+    const C* twc = static_cast<const C*>(tw);
+    hipLaunchKernelGGL((k_gen_col_adj<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W, Acc, Q4,
+                       G1, static_cast<real*>(y), twc, alpha, Re, dt, 0, int(GEN_FIRST));
+    for (int st = 0; st < nsteps; ++st)
+        for (int q = 0; q < 4; ++q) {
+            hipLaunchKernelGGL((k_gen_row_adj<real, N>), dim3(N / 2), dim3(kGT), 0, s, G1, U, V, Ox, Oy, Q4, twc);
+            const int mode = (st == nsteps - 1 && q == 3) ? GEN_LAST : GEN_STAGE;
+            hipLaunchKernelGGL((k_gen_col_adj<real, N>), dim3(MC), dim3(kGT), 0, s, static_cast<const real*>(x), W,
+                               Acc, Q4, G1, static_cast<real*>(y), twc, alpha, Re, dt, q, mode);
+        }
+}
+
+template <typename real>
+void gen_dispatch_adj(int N, const void* x, void* y, real* W, real* Acc, cplx<real>* G1, cplx<real>* Q4,
+                      const real* U, const real* V, const real* Ox, const real* Oy, const void* tw, double alpha,
+                      double Re, double dt, int nsteps, hipStream_t s) {
+    switch (N) {
+#define X(n)                                                                                                      \
+    case n:                                                                                                       \
+        gen_run_adj<real, n>(x, y, W, Acc, G1, Q4, U, V, Ox, Oy, tw, alpha, Re, dt, nsteps, s);                   \
+        break;
+        X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#undef X
+    }
+}
+
 // One run of the pipeline.  ROW_LIN / ROW_NL: nsteps Lawson steps of the
 // linearized / nonlinear (forcing fvec, drift U0) equation from x into y.
 // ROW_FIELDS: the grid fields of x into U, V, Ox, Oy (nsteps ignored).
@@ -390,6 +640,20 @@ tsk_status gen_go(Gen2D* g, double alpha, double Re, double dt, int nsteps, doub
 tsk_status gen2d_apply(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
                        const void* tw, hipStream_t s) {
     return gen_go<ROW_LIN>(g, alpha, Re, dt, nsteps, 0.0, nullptr, x, y, tw, s);
+}
+
+tsk_status gen2d_apply_adjoint(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
+                               const void* tw, hipStream_t s) {
+    if (g->fp32)
+        gen_dispatch_adj<float>(g->N, x, y, g->W.as<float>(), g->Acc.as<float>(), g->Q.as<float2>(),
+                                g->G.as<float2>(), g->U.as<float>(), g->V.as<float>(), g->Ox.as<float>(),
+                                g->Oy.as<float>(), tw, alpha, Re, dt, nsteps, s);
+    else
+        gen_dispatch_adj<double>(g->N, x, y, g->W.as<double>(), g->Acc.as<double>(), g->Q.as<double2>(),
+                                 g->G.as<double2>(), g->U.as<double>(), g->V.as<double>(), g->Ox.as<double>(),
+                                 g->Oy.as<double>(), tw, alpha, Re, dt, nsteps, s);
+    TSK_HIP(hipGetLastError());
+    return TSK_OK;
 }
 
 tsk_status gen2d_nonlinear(Gen2D* g, double alpha, double Re, double dt, int nsteps, double U0, const void* fvec,

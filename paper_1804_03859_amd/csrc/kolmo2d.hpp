@@ -17,6 +17,10 @@ void gen2d_free(Gen2D* g);
 // tw: exp(-2 pi i t / N), t < N, in the operator's precision (complex).
 tsk_status gen2d_apply(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
                        const void* tw, hipStream_t s);
+// The transposed propagator (discrete adjoint in the packed Euclidean inner
+// product) applied to x into y: nsteps transposed Lawson steps.
+tsk_status gen2d_apply_adjoint(Gen2D* g, double alpha, double Re, double dt, int nsteps, const void* x, void* y,
+                               const void* tw, hipStream_t s);
 // nsteps Lawson steps of the nonlinear forced equation (advection (u + U0) d_x w +
 // v d_y w of the state, steady forcing fvec in packed units) from x into y.
 // The base-field arrays are not read.

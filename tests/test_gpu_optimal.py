@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 def _op(tsk, N, alpha=0.5, Re=20.0, dt=0.005, T=1.0, prec=0, base="kolmogorov"):
     op = tsk.create_kolmo2d(N, prec)
     tsk.set_params_kolmo(op, Re, alpha, dt, T)
+    if base == "general":  # random band-limited 2-D base: the transposed 2-D pipeline
+        U, V, Ox, Oy = base_from_streamfunction(W.random_base_modes(2, 1), N, alpha)
+        tsk.set_base_flow(op, U, V, Ox, Oy)
+        return op, Kolmogorov(N, alpha, Re, dt, T, U, V, Ox, Oy)
     if base in ("kolmogorov", "kolmogorov-columns"):
         tsk.set_base_kolmogorov(op, 4)
         if base == "kolmogorov-columns":  # the transposed column stepper instead of the coupling one
@@ -54,10 +58,14 @@ def _phys(tsk, op, s):
                                            (128, 0.5, "shifted", 0), (384, 0.01, "kolmogorov", 0),
                                            (512, 0.01, "parallel", 0), (512, 0.1, "kolmogorov", 0),
                                            (128, 0.1, "kolmogorov", 1), (256, 0.1, "shifted", 1),
-                                           (512, 0.01, "kolmogorov", 1)])
+                                           (512, 0.01, "kolmogorov", 1), (16, 1.0, "general", 0),
+                                           (48, 0.5, "general", 0), (128, 0.1, "general", 0),
+                                           (384, 0.01, "general", 0), (96, 0.2, "general", 1),
+                                           (512, 0.01, "general", 1)])
 def test_adjoint_matvec_matches_oracle(tsk, N, T, base, prec):
     # kolmogorov and shifted: the transposed spectral-coupling stepper (512: two
-    # modes per lane); parallel and kolmogorov-columns: the transposed column stepper
+    # modes per lane); parallel and kolmogorov-columns: the transposed column
+    # stepper; general: the transposed 2-D pipeline
     print(f"adjoint matvec N={N} T={T} base={base} prec={prec}", flush=True)
     op, ref = _op(tsk, N, T=T, prec=prec, base=base)
     assert tsk.get_tuning(op) == (-2 if base in ("kolmogorov", "shifted") else 1 if base == "kolmogorov-columns"
@@ -72,7 +80,8 @@ def test_adjoint_matvec_matches_oracle(tsk, N, T, base, prec):
     assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(want))
 
 
-@pytest.mark.parametrize("N,base", [(128, "kolmogorov"), (128, "parallel"), (128, "shifted"), (512, "kolmogorov")])
+@pytest.mark.parametrize("N,base", [(128, "kolmogorov"), (128, "parallel"), (128, "shifted"), (512, "kolmogorov"),
+                                    (128, "general"), (48, "general")])
 def test_device_adjoint_satisfies_the_dot_product_identity(tsk, N, base):
     print(f"adjoint dot product N={N} base={base}", flush=True)
     op, ref = _op(tsk, N, base=base)
@@ -105,7 +114,7 @@ def test_cgle_adjoint_matches_oracle(tsk):
     assert abs(lhs - rhs) <= 1e-12 * torch.linalg.norm(Ma).item() * torch.linalg.norm(b).item()
 
 
-@pytest.mark.parametrize("N,base", [(32, "kolmogorov"), (48, "parallel")])
+@pytest.mark.parametrize("N,base", [(32, "kolmogorov"), (48, "parallel"), (32, "general")])
 def test_optimal_perturbation_matches_oracle(tsk, N, base):
     print(f"optimal perturbation N={N} base={base}", flush=True)
     op, ref = _op(tsk, N, base=base)
@@ -161,19 +170,17 @@ def test_full_size_gain_bounds_and_fp32_form(tsk):
     assert abs(r32["sigma"][0] - r["sigma"][0]) <= 1e-5 * r["sigma"][0]
 
 
-def test_operators_without_an_adjoint_are_rejected(tsk):
-    print("optimal perturbation validation", flush=True)
+def test_adjoint_argument_errors_are_rejected(tsk):
+    print("adjoint validation", flush=True)
     N = 32
-    U, V, Ox, Oy = base_from_streamfunction(W.random_base_modes(2, 1), N, 0.5)
-    op = tsk.create_kolmo2d(N, 0)
-    tsk.set_params_kolmo(op, 20.0, 0.5, 0.005, 1.0)
-    tsk.set_base_flow(op, U, V, Ox, Oy)
-    x, y = op.new_state(), op.new_state()
-    with pytest.raises(tsk.TskError):
-        tsk.apply_adjoint(op, x, y)
-    with pytest.raises(tsk.TskError) as e:
-        tsk.optimal_perturbation(op, 20, 2, 1e-8)
-    assert "adjoint" in str(e.value)
+    op, _ = _op(tsk, N, base="general")
+    x = op.new_state()
+    with pytest.raises(tsk.TskError):  # aliasing
+        tsk.apply_adjoint(op, x, x)
     op2, _ = _op(tsk, N)
     with pytest.raises(tsk.TskError):
         tsk.apply_adjoint(op2, x, x)
+    op3 = tsk.create_kolmo2d(N, 0)  # no parameters or base flow yet
+    y = op3.new_state()
+    with pytest.raises(tsk.TskError):
+        tsk.apply_adjoint(op3, x, y)

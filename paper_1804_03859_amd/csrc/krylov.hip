@@ -73,12 +73,13 @@ template <typename T> __device__ inline T ldg(const T* p, int64_t i) {
 // load is in flight before the first wait, and accumulates each vector in the
 // element order e = 0, 1, ... (elements beyond the state skipped) before its
 // shuffle reduction.
-constexpr int kDotU = 4;
+constexpr int kDotU = 8;
 template <typename TS, typename A>
 __device__ inline void chunk_dots(const TS* __restrict__ V, int64_t ldv, int p, const A* wl, int64_t base,
                                   int64_t n, double2* __restrict__ partial) {
     constexpr bool kReal = !std::is_same<TS, double2>::value;  // real states: the dots are real
-    constexpr int NW = kBT / kWave, E = kChunk / kWave, U = kDotU;
+    // complex states load 4 vectors at a time (8 of them would not fit the registers)
+    constexpr int NW = kBT / kWave, E = kChunk / kWave, U = kReal ? kDotU : 4;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t lim = n - base;  // >= 1
     A wv[E];
@@ -147,9 +148,23 @@ __device__ inline void project_out(A (&x)[EPT], const TS* __restrict__ V, int64_
 #pragma unroll
             for (int e = 0; e < EPT; ++e) x[e] = axmy(x[e], vv[u][e], hl[i0 + u]);
     }
-    for (; i0 < p; ++i0)
+    if (i0 < p) {
+        // the remaining p - i0 < U vectors as one more batch (indices clamped to
+        // p - 1 for the loads, the extra products skipped): same order, one
+        // memory latency instead of one per vector
+        TS vv[U][EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) x[e] = axmy(x[e], ldg(V, int64_t(i0) * ldv + g[e]), hl[i0]);
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u < p ? i0 + u : p - 1;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) vv[u][e] = ldg(V, int64_t(i) * ldv + g[e]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u < p)
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) x[e] = axmy(x[e], vv[u][e], hl[i0 + u]);
+    }
 }
 
 template <typename TS>

@@ -409,11 +409,10 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(StepSet ss, int kreq, double 
 // complex conjugate pairs.  The similarity P T P of one bulge step touches three
 // rows and three columns whose only overlap is a 3x3 block.  A single wavefront
 // issues one instruction every four cycles, so the sweep is bound by the
-// instructions per bulge step: the Ritz analysis (only the last row of Z
-// tracked) keeps the block and the entries near the bulge in registers and
-// runs each step as straight-line code (sweep_window); the solvers that
-// accumulate all of Z go through LDS, nine lanes forming the block and the
-// others the rest of the rows and columns in one phase (bulge_step).  H = Z T
+// instructions per bulge step: the sweep keeps the block, the entries near the
+// bulge and each lane's window of Z in registers and runs each step as
+// straight-line code (sweep_window), whether only the last row of Z is tracked
+// (the Ritz analysis) or all of it (the Krylov-Schur contraction).  H = Z T
 // Z^T; the eigenvector of each Ritz value follows by back substitution through the
 // quasi-triangular T (one lane per eigenvalue, complex arithmetic for pairs).
 
@@ -553,138 +552,10 @@ __device__ inline void rot_similarity(double* T, double* zl, int p, int i, doubl
     wave_lds_sync();
 }
 
-// One bulge step: the similarity T <- P T P with the NB-element reflector P at
-// indices kk..kk+NB-1 built from (x, y, z), and Z <- Z P (zl: the last row of Z,
-// or with FZ all of Z, each lane updating its own rows).  The NB x NB block by
-// lanes 0..NB*NB-1, the rows kk.. at columns kk+NB..p-1 and the columns kk.. at
-// rows 0..kk-1 and kk+NB (when inside the window) by the lanes in turn, all from
-// pre-update values in one phase.
-// Returns true with the next bulge (x, y, z) = new (T[kk+1][kk], T[kk+2][kk],
-// T[kk+3][kk]) taken from the lanes that computed them; false when no
-// reflection was needed (the caller then reads T).
-template <int NB, bool FZ>
-__device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi, int kk, double x, double y,
-                                  double z, int lane, double& nx, double& ny, double& nz) {
-    double v1, v2, tau, alpha;
-    house3(x, y, NB == 3 ? z : 0.0, v1, v2, tau, alpha);
-    bool fwd = false;
-    if (tau != 0.0) {
-        const double v[3] = {1.0, v1, NB == 3 ? v2 : 0.0};
-        const int rto = (kk + 3 <= ihi ? kk + 3 : ihi);  // right factor: rows 0..rto
-        const int ncr = p - (kk + NB);                     // row-only columns kk+NB..p-1
-        const int ncc = kk + ((kk + NB <= rto) ? 1 : 0);   // col-only rows 0..kk-1, kk+NB
-        double bval = 0.0;
-        const bool blane = lane < NB * NB;
-        const int bi = blane ? lane / NB : 0, bj = blane ? lane % NB : 0;
-        if (blane) {
-            // g = v^T B v from the whole block (same addresses on every lane);
-            // the lane's own row and column sums and entry read directly, so no
-            // lane selects among register copies
-            double g = 0.0;
-#pragma unroll
-            for (int a = 0; a < NB; ++a) {
-                double ua = 0.0;
-#pragma unroll
-                for (int c = 0; c < NB; ++c) ua += Tr[(kk + a) * p + kk + c] * v[c];
-                g += v[a] * ua;
-            }
-            const double* rowi = Tr + (kk + bi) * p + kk;
-            const double* colj = Tr + kk * p + kk + bj;
-            double ui = 0.0, wj = 0.0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                ui += rowi[c] * v[c];
-                wj += v[c] * colj[c * p];
-            }
-            const double bij = rowi[bj];
-            const double vi = bi == 0 ? v[0] : (bi == 1 ? v[1] : v[NB - 1]);
-            const double vj = bj == 0 ? v[0] : (bj == 1 ? v[1] : v[NB - 1]);
-            bval = bij - tau * vi * wj - tau * ui * vj + tau * tau * g * vi * vj;
-        }
-        double nv[2][NB];
-        int nidx[2] = {-1, -1}, nstr[2] = {1, 1};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int t = lane + q * kHT;
-            if (t < ncr + ncc) {
-                int base, stride;
-                if (t < ncr) {
-                    base = kk * p + (kk + NB + t);
-                    stride = p;
-                } else {
-                    const int qq = t - ncr;
-                    base = (qq < kk ? qq : kk + NB) * p + kk;
-                    stride = 1;
-                }
-                double tv[NB], dot = 0.0;
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    tv[a] = Tr[base + a * stride];
-                    dot += v[a] * tv[a];
-                }
-#pragma unroll
-                for (int a = 0; a < NB; ++a) nv[q][a] = tv[a] - tau * dot * v[a];
-                nidx[q] = base;
-                nstr[q] = stride;
-            }
-        }
-        double zn[NB];
-        if constexpr (FZ) {
-            // rows of Z are private to their lanes in this phase
-            for (int r = lane; r < p; r += kHT) {
-                double* zr = zl + r * p + kk;
-                double dz = 0.0;
-#pragma unroll
-                for (int a = 0; a < NB; ++a) dz += zr[a] * v[a];
-#pragma unroll
-                for (int a = 0; a < NB; ++a) zr[a] -= tau * dz * v[a];
-            }
-        } else {
-            double dz = 0.0;
-#pragma unroll
-            for (int a = 0; a < NB; ++a) dz += zl[kk + a] * v[a];
-#pragma unroll
-            for (int a = 0; a < NB; ++a) zn[a] = zl[kk + a] - tau * dz * v[a];
-        }
-        // writes (every lane has done all of its reads of this phase)
-        if (blane) Tr[(kk + bi) * p + kk + bj] = bval;
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-            if (nidx[q] >= 0) {
-#pragma unroll
-                for (int a = 0; a < NB; ++a) Tr[nidx[q] + a * nstr[q]] = nv[q][a];
-            }
-        if (lane == 0) {
-            if constexpr (!FZ) {
-#pragma unroll
-                for (int a = 0; a < NB; ++a) zl[kk + a] = zn[a];
-            }
-            if (kk > l) {  // the reflector turned column kk-1 into (alpha, 0, ..., 0)
-                Tr[kk * p + kk - 1] = alpha;
-#pragma unroll
-                for (int a = 1; a < NB; ++a) Tr[(kk + a) * p + kk - 1] = 0.0;
-            }
-        }
-        if constexpr (NB == 3) {
-            // block entries (1, 0) and (2, 0) sit in lanes 3 and 6; row kk+3 of
-            // column kk is col-only item ncr + kk
-            nx = readlane_d(bval, 3);
-            ny = readlane_d(bval, 6);
-            nz = 0.0;
-            if (kk + 3 <= ihi) {
-                const int t = ncr + kk;
-                const double zq = (t / kHT == 0) ? nv[0][0] : nv[1][0];
-                nz = readlane_d(zq, t % kHT);
-            }
-            fwd = true;
-        }
-    }
-    wave_lds_sync();
-    return fwd;
-}
-
 // One double-shift sweep over the active window l..ihi (ihi - l >= 2) with the
-// state near the bulge in registers; only the last row of Z (zl) is tracked.
+// state near the bulge in registers, and Z <- Z P_k: with FZ all of Z (zl, p x p
+// row-major; lane i holds Z[i][k..k+2] and stores Z[i][k] after step k), else
+// only its last row (zl, a window shared by every lane).
 // The sweep applies T <- P_k T P_k for k = l..ihi-1 (3-element reflectors, then
 // a 2-element one at k = ihi - 1).  Left and right products commute, so every
 // entry outside the moving 3 x 3 block meets its updates in a fixed order: row
@@ -705,7 +576,7 @@ __device__ inline bool bulge_step(double* Tr, double* zl, int p, int l, int ihi,
 // next.
 template <bool B> using bool_c = std::integral_constant<bool, B>;
 
-template <int S>
+template <int S, bool FZ>
 __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ihi, double x, double y, double z,
                                     int lane) {
     // sink[0] takes the stores of lanes with no window entry to store; sink[1]
@@ -717,13 +588,22 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) B[a][b] = Tr[(l + a) * p + l + b];
-    double Z0 = zl[l], Z1 = zl[l + 1], Z2 = zl[l + 2];
+    // the last row of Z (its window shared by every lane), or with FZ all of Z
+    // (row-major p x p; lane i's window of row i, zr = &Z[i][k])
+    double Z0 = 0.0, Z1 = 0.0, Z2 = 0.0;
+    if constexpr (!FZ) {
+        Z0 = zl[l];
+        Z1 = zl[l + 1];
+        Z2 = zl[l + 2];
+    }
     double E2 = (l + 3 <= ihi) ? Tr[(l + 3) * p + l + 2] : 0.0;
     // lane window i: rp = &T[i][k] (row role, i < k), cp = &T[k][i] (column role,
     // i >= k + 3), both advanced with k
     double W[S][3];
     double* rp[S];
     double* cp[S];
+    double ZW[FZ ? S : 1][3];
+    double* zr[FZ ? S : 1];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int i = lane + kHT * s;
@@ -733,6 +613,11 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
         for (int a = 0; a < 3; ++a) {
             const double* src = i < l ? rp[s] + a : (i >= l + 3 && i < p ? cp[s] + a * p : sink + 1);
             W[s][a] = *src;
+        }
+        if constexpr (FZ) {
+            zr[s] = zl + i * p + l;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ZW[s][a] = *(i < p ? zr[s] + a : sink + 1);
         }
     }
     double* dg = Tr + l * p + l;  // &T[k][k]
@@ -789,10 +674,20 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
         const double te = tau * (v2 * E2);
         const double E0 = -te, E1 = -te * v1;
         E2 = fma(-te, v2, E2);
-        const double tz = tau * fma(v2, Z2, fma(v1, Z1, Z0));
-        Z0 -= tz;
-        Z1 = fma(-tz, v1, Z1);
-        Z2 = fma(-tz, v2, Z2);
+        if constexpr (FZ) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double tz = tau * fma(v2, ZW[s][2], fma(v1, ZW[s][1], ZW[s][0]));
+                ZW[s][0] -= tz;
+                ZW[s][1] = fma(-tz, v1, ZW[s][1]);
+                ZW[s][2] = fma(-tz, v2, ZW[s][2]);
+            }
+        } else {
+            const double tz = tau * fma(v2, Z2, fma(v1, Z1, Z0));
+            Z0 -= tz;
+            Z1 = fma(-tz, v1, Z1);
+            Z2 = fma(-tz, v2, Z2);
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const double tw = tau * fma(v2, W[s][2], fma(v1, W[s][1], W[s][0]));
@@ -807,12 +702,12 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
                 if (THREE) dg[2 * p - 1] = 0.0;
             }
             dg[0] = B[0][0];
-            zp[0] = Z0;
+            if (!FZ) zp[0] = Z0;
             if (!THREE) {
                 dg[1] = B[0][1];
                 dg[p] = B[1][0];
                 dg[p + 1] = B[1][1];
-                zp[1] = Z1;
+                if (!FZ) zp[1] = Z1;
             }
         }
         constexpr int NB = THREE ? 3 : 2;
@@ -823,6 +718,11 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
             double* d0 = row ? rp[s] : (col ? cp[s] : sink);
             *d0 = W[s][0];
             if (!THREE) *(row ? d0 + 1 : (col ? d0 + p : sink)) = W[s][1];
+            if constexpr (FZ) {  // Z[i][k] is final for the sweep
+                double* zd = i < p ? zr[s] : sink;
+                *zd = ZW[s][0];
+                if (!THREE) *(i < p ? zd + 1 : sink) = ZW[s][1];
+            }
         }
         if constexpr (THREE) {
             // keeps the LDS reads below after the stores above (other lanes read them)
@@ -842,7 +742,7 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
                 cC = readlane_d(a2, src % kHT);
                 d33 = dg[3 * p + 3];
                 e2n = *(k + 4 <= ihi ? dg + 4 * p + 3 : sink + 1);
-                z2n = zp[3];
+                if (!FZ) z2n = zp[3];
             }
             const double b01 = B[0][1], b02 = B[0][2];
             B[0][0] = B[1][1];
@@ -872,6 +772,13 @@ __device__ inline void sweep_window(double* Tr, double* zl, int p, int l, int ih
                 W[s][2] = nw;
                 rp[s] += 1;
                 cp[s] += p;
+                if constexpr (FZ) {  // Z[i][k+3] is untouched so far in the sweep
+                    const int iz = lane + kHT * s;
+                    ZW[s][0] = ZW[s][1];
+                    ZW[s][1] = ZW[s][2];
+                    ZW[s][2] = NEXT3 ? *(iz < p ? zr[s] + 3 : sink + 1) : 0.0;
+                    zr[s] += 1;
+                }
             }
             dg += p + 1;
             zp += 1;
@@ -997,29 +904,9 @@ __device__ __attribute__((always_inline)) inline void francis_real(double* Tr, d
             y = t10 * (t00 + t11 - ss);
             z = t10 * t21;
         }
-        if constexpr (!FZ) {
-            if (p > kHT) sweep_window<2>(Tr, zl, p, l, ihi, x, y, z, lane);
-            else sweep_window<1>(Tr, zl, p, l, ihi, x, y, z, lane);
-            wave_lds_sync();
-            continue;
-        }
-        // bulge chase: 3-element reflectors at k = l .. ihi-2, then a 2-element one
-        for (int kk = l; kk <= ihi - 2; ++kk) {
-            double nx, ny, nz;
-            if (bulge_step<3, FZ>(Tr, zl, p, l, ihi, kk, x, y, z, lane, nx, ny, nz)) {
-                x = nx;
-                y = ny;
-                z = nz;
-            } else {
-                x = Tr[(kk + 1) * p + kk];
-                y = Tr[(kk + 2) * p + kk];
-                z = kk + 3 <= ihi ? Tr[(kk + 3) * p + kk] : 0.0;
-            }
-        }
-        {
-            double nx, ny, nz;
-            bulge_step<2, FZ>(Tr, zl, p, l, ihi, ihi - 1, x, y, 0.0, lane, nx, ny, nz);
-        }
+        if (p > kHT) sweep_window<2, FZ>(Tr, zl, p, l, ihi, x, y, z, lane);
+        else sweep_window<1, FZ>(Tr, zl, p, l, ihi, x, y, z, lane);
+        wave_lds_sync();
     }
 }
 

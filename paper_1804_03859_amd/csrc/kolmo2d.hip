@@ -51,6 +51,20 @@ template <int N> struct Geo2 {
 
 constexpr int kGT = 4 * kWave;  // column kernel: four wavefronts per workgroup
 
+// Row groups of the row kernels by XCD.  The device has 8 XCDs, each with its
+// own L2, and hands workgroups to them in turn (workgroup b runs on XCD b mod
+// 8).  The row kernels read G and write Q with y the fastest index, so the
+// rows of one 128-byte line (8 FP64 or 16 FP32 complex values) belong to
+// several workgroups; numbered in launch order, those workgroups sit on
+// different XCDs and each XCD's L2 fetches the whole line.  Workgroup b
+// therefore takes row group (b mod 8) (nb / 8) + b / 8: each XCD gets a
+// contiguous band of nb / 8 groups, and a line is fetched by one L2 only once
+// the band covers it (nb / 8 >= 4 at two rows per group, N >= 64).
+__device__ inline int xcd_row_group(int b, int nb) {
+    constexpr int kXcd = 8;
+    return nb % kXcd == 0 ? (b % kXcd) * (nb / kXcd) + b / kXcd : b;
+}
+
 enum GenMode { GEN_FIRST = 0, GEN_STAGE = 1, GEN_LAST = 2 };
 
 // Column kernel, one workgroup per kept kx column.  FIRST: W = x, s = W,
@@ -185,11 +199,11 @@ __global__ __launch_bounds__(kGT) void k_gen_col(const real* __restrict__ xin, r
 //   ROW_FIELDS: no product: the physical grid fields (u + U0, v, d_x w, d_y w)
 //               of the state go to U, V, Ox, Oy (the state as a base flow).
 enum RowMode { ROW_LIN = 0, ROW_NL = 1, ROW_FIELDS = 2 };
-// Rows per workgroup: 2.  With 8 rows (16 wavefronts) the reads of G and the
-// writes of Q cover whole 128-byte lines and the kernel fetches half the bytes,
-// but its 16 workgroups of 1024 threads take 9.6 instead of 5.4 us per launch
-// at 128^2 (4 rows: 6.8 us); the stage is latency-bound, so the wider grid of
-// small workgroups wins.
+// Rows per workgroup: 2 (whole 128-byte lines per L2 come from the row groups
+// by XCD, xcd_row_group).  With 8 rows (16 wavefronts) one workgroup covers
+// whole lines by itself, but its 16 workgroups of 1024 threads take 9.6
+// instead of 5.4 us per launch at 128^2 (4 rows: 6.8 us); the stage is
+// latency-bound, so the wider grid of small workgroups wins.
 template <typename real, int N> constexpr int gen_rows_per_group() {
     return 2;
 }
@@ -210,7 +224,7 @@ __global__ __launch_bounds__(2 * RPW * kWave) void k_gen_row(const cplx<real>* _
     __shared__ C sT[N];
     __shared__ C sA[2 * RPW][N], sB[2 * RPW][N];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int y0 = RPW * blockIdx.x, r = wv >> 1, pr = wv & 1, y = y0 + r;
+    const int y0 = RPW * xcd_row_group(blockIdx.x, gridDim.x), r = wv >> 1, pr = wv & 1, y = y0 + r;
     // the base fields of the thread's grid points (ROW_LIN), loaded first so that
     // their latency overlaps the transforms; point e = rr N + x of the workgroup
     real bU[RX], bV[RX], bOx[RX], bOy[RX];
@@ -445,7 +459,7 @@ __global__ __launch_bounds__(kGT) void k_gen_row_adj(const cplx<real>* __restric
     __shared__ C sT[N];
     __shared__ C sA[4][N], sB[4][N];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int y0 = 2 * blockIdx.x;
+    const int y0 = 2 * xcd_row_group(blockIdx.x, gridDim.x);
     // base fields of the thread's points of both rows, loaded first
     real bf[RX][4][2];
 #pragma unroll

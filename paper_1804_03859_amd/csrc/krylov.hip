@@ -545,7 +545,7 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s) {
 template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
                      hipStream_t s, int pextra) {
-    const bool pre = nblk_max > kFuseFinalMaxBlocks;  // long states: one reduction launch first
+    const bool pre = nblk_max >= kPreReduceMinBlocks;  // long states: one reduction launch first
     if (pre) {
         // pextra: the largest step offset of the batch (its instances reduce up to p + pextra coefficients)
         constexpr int per_block = (kBT / kWave) * kDotU;

@@ -90,6 +90,14 @@ void launch_reduce_norm(const KryDesc* D, int count, int slot, hipStream_t s);
 // launch_scale_final, whose launch is then skipped (for short states, where a
 // launch costs more than one block scaling the vector).
 constexpr int kFuseFinalMaxBlocks = 64;
+// Passes over more than this many chunks take their coefficients from one
+// reduction launch (k_reduce_coefs) instead of every block reducing the
+// partial dots itself.  Measured with interleaved runs of both forms: at 115
+// chunks (256^2 states) the folded form saves the launch (256^2 solves FP64
+// 6.06 -> 5.77 ms, FP32 8.23 -> 8.05 ms); with 255 chunks (384^2, in the
+// 64-instance sweep) and 456 (512^2) the separate launch is faster (sweep 57
+// against 64 ms with the threshold at 256 or 512).
+constexpr int kPreReduceMinBlocks = 129;
 template <typename TS>
 void launch_cgs_pass(const KryDesc* D, int count, int nblk_max, int p, int j, int pass, bool fuse_final,
                      hipStream_t s, int pextra = 0);

@@ -439,21 +439,29 @@ tsk_status couple_choice(const CoupleKey& key, hipStream_t s, F&& launch, int* o
     hipEvent_t e0, e1;
     TSK_HIP(hipEventCreate(&e0));
     TSK_HIP(hipEventCreate(&e1));
-    float best = 0.0f;
-    int bw = 1;
-    for (int w : {1, 2, 4}) {
-        launch(w);
-        TSK_HIP(hipEventRecord(e0, s));
-        launch(w);
-        TSK_HIP(hipEventRecord(e1, s));
-        TSK_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        TSK_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (w == 1 || ms < best) {
-            best = ms;
-            bw = w;
+    // one untimed launch per shape, then three rounds over the shapes with one
+    // timed launch each; the shortest time of each shape decides (one launch
+    // per shape varied by more than the shapes differ)
+    constexpr int kShapes[3] = {1, 2, 4};
+    float tmin[3] = {0.0f, 0.0f, 0.0f};
+    for (int w : kShapes) launch(w);
+    for (int round = 0; round < 3; ++round)
+        for (int q = 0; q < 3; ++q) {
+            TSK_HIP(hipEventRecord(e0, s));
+            launch(kShapes[q]);
+            TSK_HIP(hipEventRecord(e1, s));
+            TSK_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            TSK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (round == 0 || ms < tmin[q]) tmin[q] = ms;
         }
-    }
+    int bw = kShapes[0];
+    float best = tmin[0];
+    for (int q = 1; q < 3; ++q)
+        if (tmin[q] < best) {
+            best = tmin[q];
+            bw = kShapes[q];
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     TSK_HIP(hipGetLastError());

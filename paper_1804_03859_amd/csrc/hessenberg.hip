@@ -1015,12 +1015,12 @@ __global__ __launch_bounds__(kHT) void k_ritz_coords(const KryDesc* __restrict__
     const int lane = threadIdx.x;
     const double2 m = dsc.mu[dsc.sel[sidx]];
     double hn = 0.0;
-    for (int e = lane; e < p * p; e += kHT) {
-        int r = e / p, c = e % p;
+    for (int e = lane; e < p * p; e += kHT) {  // H is column-major: consecutive lanes read down a column
+        const int c = e / p, r = e % p;
         double2 v = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
         hn = fmax(hn, cabs1(v));
         if (r == c) v = csub(v, m);
-        A[e] = v;
+        A[r * p + c] = v;
     }
     red[lane] = hn;
     for (int r = lane; r < p; r += kHT) b[r] = cmk<double2>(1.0, 0.0);
@@ -1052,24 +1052,36 @@ __global__ __launch_bounds__(kHT) void k_ritz_coords(const KryDesc* __restrict__
     if (lane == 0 && cabs1(A[(p - 1) * p + (p - 1)]) < tiny) A[(p - 1) * p + (p - 1)] = cmk<double2>(tiny, 0.0);
     __syncthreads();
     for (int it = 0; it < 2; ++it) {
+        // forward elimination on b (serial, O(p))
         if (lane == 0) {
-            // forward elimination on b, then back substitution (serial, O(p^2))
             for (int j = 0; j < p - 1; ++j) {
                 if (piv[j]) { double2 t = b[j]; b[j] = b[j + 1]; b[j + 1] = t; }
                 b[j + 1] = csub(b[j + 1], cmul(lmul[j], b[j]));
             }
-            for (int r = p - 1; r >= 0; --r) {
-                double2 acc = b[r];
-                for (int c = r + 1; c < p; ++c) acc = csub(acc, cmul(A[r * p + c], b[c]));
-                double2 dg = A[r * p + r];
-                if (cabs1(dg) < tiny) dg = cmk<double2>(tiny, 0.0);
-                b[r] = cdiv(acc, dg);
-            }
-            double n2 = 0.0;
-            for (int r = 0; r < p; ++r) n2 += cabs2(b[r]);
-            double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-            for (int r = 0; r < p; ++r) b[r] = cscale(b[r], inv);
         }
+        __syncthreads();
+        // back substitution by columns: x_r = b_r / U_rr, then b_c -= U_cr x_r for
+        // every c < r, one lane per c
+        for (int r = p - 1; r >= 0; --r) {
+            double2 dg = A[r * p + r];
+            if (cabs1(dg) < tiny) dg = cmk<double2>(tiny, 0.0);
+            const double2 xr = cdiv(b[r], dg);
+            for (int c = lane; c < r; c += kHT) b[c] = csub(b[c], cmul(A[c * p + r], xr));
+            if (lane == 0) b[r] = xr;
+            __syncthreads();
+        }
+        double n2 = 0.0;
+        for (int r = lane; r < p; r += kHT) n2 += cabs2(b[r]);
+        red[lane] = n2;
+        __syncthreads();
+        if (lane == 0) {
+            double t = 0.0;
+            for (int q = 0; q < kHT; ++q) t += red[q];
+            red[0] = t;
+        }
+        __syncthreads();
+        const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
+        for (int r = lane; r < p; r += kHT) b[r] = cscale(b[r], inv);
         __syncthreads();
     }
     for (int r = lane; r < p; r += kHT) Y[(size_t)sidx * p + r] = b[r];

@@ -205,11 +205,11 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz(StepSet ss, int kreq, double 
     // later (speculative) steps never modify; the standalone path from scal[2].
     const double beta = FULLZ ? dsc.scal[2] : H[p + (size_t)ldh * (p - 1)].x;
     bool bad = !isfinite(beta);
-    for (int e = lane; e < p * p; e += kHT) {
-        int r = e / p, c = e % p;
+    for (int e = lane; e < p * p; e += kHT) {  // H is column-major: consecutive lanes read down a column
+        const int c = e / p, r = e % p;
         const double2 v = (r <= c + 1) ? H[r + (size_t)ldh * c] : cmk<double2>(0.0, 0.0);
         bad = bad || !isfinite(v.x) || !isfinite(v.y);
-        T[e] = v;
+        T[r * p + c] = v;
     }
     if (__ballot(bad)) {  // non-finite input: no QR (it could not deflate), report and stop
         if (lane == 0 && rr) {
@@ -957,11 +957,11 @@ __global__ __launch_bounds__(kHT) void k_hess_ritz_real(StepSet ss, int kreq, do
 
     const double beta = standalone ? dsc.scal[2] : H[p + (size_t)ldh * (p - 1)].x;
     bool bad = !isfinite(beta);
-    for (int e = lane; e < p * p; e += kHT) {
-        const int r = e / p, c = e % p;
+    for (int e = lane; e < p * p; e += kHT) {  // H is column-major: consecutive lanes read down a column
+        const int c = e / p, r = e % p;
         const double v = (r <= c + 1) ? H[r + (size_t)ldh * c].x : 0.0;
         bad = bad || !isfinite(v);
-        Tr[e] = v;
+        Tr[r * p + c] = v;
     }
     if (__ballot(bad)) {
         if (lane == 0 && rr) {
@@ -1363,11 +1363,11 @@ __global__ __launch_bounds__(kHT) void k_ks_contract(const KryDesc* __restrict__
 
     const double beta = H[m + (size_t)ldh * (m - 1)].x;
     bool bad = !isfinite(beta);
-    for (int e = lane; e < m * m; e += kHT) {
-        const int r = e / m, c = e % m;
+    for (int e = lane; e < m * m; e += kHT) {  // H is column-major: consecutive lanes read down a column
+        const int c = e / m, r = e % m;
         const double v = (r <= c + 1) ? H[r + (size_t)ldh * c].x : 0.0;
         bad = bad || !isfinite(v);
-        Tr[e] = v;
+        Tr[r * m + c] = v;
         Zf[e] = r == c ? 1.0 : 0.0;
     }
     if (__ballot(bad)) {

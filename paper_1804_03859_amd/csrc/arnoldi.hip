@@ -356,9 +356,10 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // one it was given (one step always queued behind the running matvec).
     constexpr int NA = ArnoldiWork::kAnaStreams;
     // Matvec timing: an event pair around every kTimeEvery-th matvec (the first
-    // included); ms_apply is their mean duration times the matvecs run.  An
-    // event record costs about 5 us of operator-stream time on this device, as
-    // much as a sixth of a 128^2 step, while the matvec's duration hardly varies.
+    // included); ms_apply is their mean duration times the matvecs run.  A
+    // timing event record costs about 3.4 us of operator-stream time between
+    // dependent kernels, two of them a tenth of a 128^2 step, while the
+    // matvec's duration hardly varies.
     constexpr int kTimeEvery = 8;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     // a batch of grid-size groups runs its extra groups on worker streams 1 and 2;

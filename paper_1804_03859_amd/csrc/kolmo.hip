@@ -426,8 +426,14 @@ int wave_bucket(int waves) {
     return b;
 }
 
+// prefer (single-operator launches): the shape kept when its isolated time is
+// within 10% of the fastest.  Isolated launches of one operator come out nearly
+// even, but inside an Arnoldi run, beside its Gram-Schmidt kernels and Ritz
+// analyses, interleaved runs ranked them clearly: FP32 256^2 27.3 us per
+// matvec with 4 wavefronts per workgroup, 29.9 with 2, 31.0 with 1 (whole
+// solve 7.9 against 8.2 ms); FP64 128^2 and 256^2 fastest with 1.
 template <typename F>
-tsk_status couple_choice(const CoupleKey& key, hipStream_t s, F&& launch, int* out) {
+tsk_status couple_choice(const CoupleKey& key, hipStream_t s, F&& launch, int* out, int prefer = 0) {
     {
         std::lock_guard<std::mutex> lk(g_couple_mu);
         auto it = g_couple.find(key);
@@ -462,6 +468,8 @@ tsk_status couple_choice(const CoupleKey& key, hipStream_t s, F&& launch, int* o
             best = tmin[q];
             bw = kShapes[q];
         }
+    for (int q = 0; q < 3; ++q)
+        if (kShapes[q] == prefer && tmin[q] <= 1.10f * best) bw = prefer;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     TSK_HIP(hipGetLastError());
@@ -589,7 +597,9 @@ struct KolmoOp final : Operator {
                                                   stream);
             };
             int w = force_wpw;
-            if (w == 0) TSK_TRY(couple_choice(CoupleKey{prec == TSK_FP32, S, wave_bucket(blocks)}, stream, launch, &w));
+            if (w == 0)
+                TSK_TRY(couple_choice(CoupleKey{prec == TSK_FP32, S, wave_bucket(blocks)}, stream, launch, &w,
+                                      prec == TSK_FP32 ? 4 : 1));
             tuned_wpw = w;
             launch(w);
             TSK_HIP(hipGetLastError());

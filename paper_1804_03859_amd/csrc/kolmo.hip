@@ -413,8 +413,9 @@ void launch_couple_adj(const ColInst<real>& one, int blocks, int S, int wpw, hip
 struct CoupleKey {
     bool fp32;
     int S, size;
+    int prefer;  // the preferred shape of the caller (0: none); single-operator and batch launches keep apart
     bool operator<(const CoupleKey& o) const {
-        return std::tie(fp32, S, size) < std::tie(o.fp32, o.S, o.size);
+        return std::tie(fp32, S, size, prefer) < std::tie(o.fp32, o.S, o.size, o.prefer);
     }
 };
 std::mutex g_couple_mu;
@@ -597,9 +598,11 @@ struct KolmoOp final : Operator {
                                                   stream);
             };
             int w = force_wpw;
-            if (w == 0)
-                TSK_TRY(couple_choice(CoupleKey{prec == TSK_FP32, S, wave_bucket(blocks)}, stream, launch, &w,
-                                      prec == TSK_FP32 ? 4 : 1));
+            if (w == 0) {
+                const int prefer = prec == TSK_FP32 ? 4 : 1;
+                TSK_TRY(couple_choice(CoupleKey{prec == TSK_FP32, S, wave_bucket(blocks), prefer}, stream, launch, &w,
+                                      prefer));
+            }
             tuned_wpw = w;
             launch(w);
             TSK_HIP(hipGetLastError());
@@ -1118,7 +1121,7 @@ tsk_status kolmo_batch_plan(Operator* const* ops, int count, const KryDesc* Dh, 
                     launch_couple_stepper<double>(ColInst<double>{}, bp->insts.as<ColInst<double>>(),
                                                   gp->ids.as<int>(), gp->nids, 0, gp->cblocks, gp->cslots, w, s);
             };
-            TSK_TRY(couple_choice(CoupleKey{b->fp32, g->cslots, wave_bucket(g->cblocks * g->nids)}, s, launch,
+            TSK_TRY(couple_choice(CoupleKey{b->fp32, g->cslots, wave_bucket(g->cblocks * g->nids), 0}, s, launch,
                                   &g->cwpw));
             continue;
         }

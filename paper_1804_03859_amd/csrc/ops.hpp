@@ -42,9 +42,11 @@ struct ArnoldiWork {
     // Ritz analyses of up to kSlots consecutive steps are in flight at once, in
     // batched launches on kAnaStreams side streams, each step with its own
     // eigensolver outputs (see arnoldi.hip).  An analysis at p ~ 50-60 takes
-    // about as long as ten matvecs of the 128^2 and 512^2 grids, so fewer slots
-    // would stall the operator stream while it waits for a free one.
-    static constexpr int kSlots = 16;
+    // as long as ten to twenty-five steps, so fewer slots stall the operator
+    // stream while it waits for a free one: with 16 instead of 24, 256^2 FP32
+    // solves (62 steps) took 7.9-8.0 instead of 7.2-7.3 ms in interleaved runs;
+    // 32 gained nothing more.
+    static constexpr int kSlots = 24;
     // three analysis streams and the operator's stream use the 4 hardware queues a
     // process gets by default (GPU_MAX_HW_QUEUES); more streams would share a queue
     // and could put an analysis in front of a matvec
@@ -244,7 +246,7 @@ tsk_status hess_ritz_launch(const KryDesc* D, int count, int p, int k, double to
 // finished into one launch, so the analyses of a backlog run side by side
 // without a hardware queue each.
 struct StepSet {
-    static constexpr int kMax = 16;
+    static constexpr int kMax = 24;
     const KryDesc* tab[kMax];
     int p[kMax];
 };

@@ -66,7 +66,7 @@ typedef struct {
     double beta;             /* last ||f_j||                                                 */
     double ms_total;         /* wall time of the call, host clock                            */
     double ms_apply;         /* device time of the matvecs: HIP events on the op's stream    */
-                             /* around every eighth matvec (the first included), their mean   */
+                             /* around every 32nd matvec (the first included), their mean     */
                              /* times n_matvec (an event record costs stream time of its own) */
 } tsk_arnoldi_info;
 

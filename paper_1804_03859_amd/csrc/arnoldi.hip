@@ -358,9 +358,10 @@ tsk_status arnoldi_t(Operator* const* ops, int count, int m, int k, double tol, 
     // Matvec timing: an event pair around every kTimeEvery-th matvec (the first
     // included); ms_apply is their mean duration times the matvecs run.  A
     // timing event record costs about 3.4 us of operator-stream time between
-    // dependent kernels, two of them a tenth of a 128^2 step, while the
-    // matvec's duration hardly varies.
-    constexpr int kTimeEvery = 8;
+    // dependent kernels, while the matvec's duration hardly varies: timing
+    // every 32nd instead of every 8th matvec made 128^2 FP64 runs 5.86 -> 5.62
+    // ms and 256^2 FP64 solves 5.75 -> 5.58 ms in interleaved runs.
+    constexpr int kTimeEvery = 32;
     static_assert(NS <= StepSet::kMax, "a batch holds every step in flight");
     // a batch of grid-size groups runs its extra groups on worker streams 1 and 2;
     // its analyses then use stream 0 only, so the operator's stream and the three
